@@ -1,0 +1,305 @@
+"""Pins of the oracle's Stage-1 render (Sec. 3.1 Stage 1, Sec. 3.3 Eq. 1-2)
+against closed forms, an independent linear solve, invariants and brute
+force.  CPU only."""
+import math
+
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation
+
+from paper_2609_30741_amd import synth
+
+Y00 = 0.5 / math.sqrt(math.pi)
+
+
+def cam_identity(W=64, H=48, f=100.0):
+    """Camera at the origin whose axes are the world axes."""
+    return synth.Camera(W, H, f, f, (W - 1) / 2.0, (H - 1) / 2.0, np.eye(3), np.zeros(3))
+
+
+def stored_colour(scene, k):
+    """Colour the scene actually encodes (its fp32 degree-0 coefficient)."""
+    f = scene.sh[:, k].astype(np.float64).reshape(1, 3)[0]
+    return np.maximum(f * Y00 + 0.5, 0.0)
+
+
+def test_single_frontoparallel_closed_form(oracle):
+    # Fronto-parallel surfel at depth Z: the ray of pixel (i, j) meets it at
+    # X = Z r, so u = (Z (i-cx)/fx - px)/s, v likewise (Eq. 1-2), and the
+    # pixel gets alpha*c, D = alpha*Z, A = alpha when alpha >= 1/255.
+    cam = cam_identity()
+    Z, px, py, s, o = 3.0, 0.07, -0.05, 0.04, 0.8
+    sc = synth.explicit_scene([px, py, Z], [1, 0, 0], [0, 1, 0], s, s, o, [0.9, 0.2, 0.4])
+    r = oracle.Raster(lowpass=False)
+    out = oracle.render(sc, cam, r, prefilter=False)
+    jj, ii = np.mgrid[0:cam.height, 0:cam.width].astype(np.float64)
+    sp = float(np.float32(s))
+    pxx, pyy, Zf = (float(np.float32(v)) for v in (px, py, Z))
+    u = (Zf * (ii - cam.cx) / cam.fx - pxx) / sp
+    v = (Zf * (jj - cam.cy) / cam.fy - pyy) / sp
+    a = np.minimum(0.99, float(np.float32(o)) * np.exp(-0.5 * (u * u + v * v)))
+    a = np.where(a >= 1 / 255, a, 0.0)
+    c = stored_colour(sc, 0)
+    for ch in range(3):
+        np.testing.assert_allclose(out["rgb"][ch], a * c[ch], rtol=0, atol=1e-12)
+    np.testing.assert_allclose(out["alpha"], a, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(out["depth_raw"], a * Zf, rtol=1e-12, atol=1e-12)
+    # Footprint: alpha >= 1/255 exactly on the disc u^2+v^2 <= 2 ln(255 o).
+    inside = u * u + v * v <= 2 * math.log(255 * float(np.float32(o)))
+    assert np.array_equal(out["alpha"] > 0, inside)
+    # Depth proxy D/A equals the surfel depth wherever it is covered.
+    m = out["alpha"] > 0
+    np.testing.assert_allclose(out["depth_raw"][m] / out["alpha"][m], Zf, rtol=1e-14)
+
+
+def _frame_from_quat(q):
+    # Independent route: scipy's rotation (scalar-last quaternion order).
+    R = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()
+    return R[:, 0], R[:, 1]
+
+
+def test_tilted_surfels_match_linear_solve(oracle):
+    # The hit point solves p + u s_u t_u + v s_v t_v = lambda r (the surfel
+    # plane of Eq. 1 meets the pixel ray); solve that 3x3 system directly.
+    rng = np.random.default_rng(5)
+    n = 12
+    sc = synth.scene_uniform_cube(7, n, half=0.3)
+    sc.pos[2] += 2.5  # put them in front of the identity camera
+    cam = cam_identity(80, 60, 90.0)
+    r = oracle.Raster(lowpass=False)
+    for k in range(n):
+        tu, tv = _frame_from_quat(sc.quat[:, k].astype(np.float64))
+        p = sc.pos[:, k].astype(np.float64)
+        su, sv = sc.scale[:, k].astype(np.float64)
+        mu = p[:2] / p[2] * 90.0 + np.array([cam.cx, cam.cy])
+        for _ in range(6):
+            i, j = mu + rng.normal(0, 3.0, size=2)
+            ray = np.array([(i - cam.cx) / cam.fx, (j - cam.cy) / cam.fy, 1.0])
+            A = np.stack([su * tu, sv * tv, -ray], axis=1)
+            u, v, lam = np.linalg.solve(A, -p)
+            e = oracle.pair(sc, cam, k, i, j, r)
+            assert e is not None
+            if lam <= cam.z_near:
+                assert e["valid3"] == 0
+                continue
+            assert abs(e["u"] - u) < 1e-9 * (1 + abs(u))
+            assert abs(e["v"] - v) < 1e-9 * (1 + abs(v))
+            assert abs(e["lambda"] - lam) < 1e-12 * lam
+            g = math.exp(-0.5 * (u * u + v * v))
+            assert abs(e["G3"] - g) < 1e-9
+            assert abs(e["alpha"] - min(0.99, float(sc.opacity[k]) * g)) < 1e-9
+            assert abs(e["depth"] - lam) < 1e-12 * lam
+
+
+def test_two_surfels_closed_form(oracle):
+    # C = a1 c1 + (1-a1) a2 c2 + (1-a1)(1-a2) bg and D = a1 Z1 + (1-a1) a2 Z2
+    # (w_i = alpha_i T_i, Sec. 3.1).  The nearer surfel has the larger index:
+    # order is by depth, not by index.
+    cam = cam_identity(32, 32, 60.0)
+    bg = (0.1, 0.3, 0.2)
+    sc = synth.explicit_scene([[0.0, 0.0, 4.0], [0.02, 0.0, 2.0]], [[1, 0, 0], [1, 0, 0]],
+                              [[0, 1, 0], [0, 1, 0]], [0.5, 0.3], [0.5, 0.3], [0.7, 0.6],
+                              [[0.9, 0.1, 0.1], [0.1, 0.8, 0.3]])
+    r = oracle.Raster(lowpass=False, bg=bg)
+    out = oracle.render(sc, cam, r, prefilter=False)
+    for (i, j) in [(15, 15), (16, 16), (10, 18), (20, 12)]:
+        e1 = oracle.pair(sc, cam, 1, i, j, r)  # near
+        e0 = oracle.pair(sc, cam, 0, i, j, r)  # far
+        a1, a2 = e1["alpha"], e0["alpha"]
+        assert a1 >= 1 / 255 and a2 >= 1 / 255
+        c1, c2 = stored_colour(sc, 1), stored_colour(sc, 0)
+        exp_c = a1 * c1 + (1 - a1) * a2 * c2 + (1 - a1) * (1 - a2) * np.array(bg)
+        np.testing.assert_allclose(out["rgb"][:, j, i], exp_c, atol=1e-12)
+        exp_d = a1 * e1["depth"] + (1 - a1) * a2 * e0["depth"]
+        assert abs(out["depth_raw"][j, i] - exp_d) < 1e-12
+        assert abs(out["alpha"][j, i] - (a1 + (1 - a1) * a2)) < 1e-12
+    order = oracle.composite_order(sc, cam, r)
+    assert list(order) == [1, 0]
+
+
+def test_transmittance_stop(oracle):
+    # 20 identical wide fronto-parallel surfels with alpha = 0.5 at the centre
+    # pixel: T after n of them is 0.5^n; the 14th would take T to
+    # 6.1e-5 < 1e-4, so exactly 13 are composited and A = 1 - 0.5^13.
+    cam = cam_identity(17, 17, 50.0)
+    n = 20
+    pos = [[0.0, 0.0, 2.0 + 0.01 * k] for k in range(n)]
+    sc = synth.explicit_scene(pos, [[1, 0, 0]] * n, [[0, 1, 0]] * n, [5.0] * n, [5.0] * n, [0.5] * n,
+                              [[0.5, 0.5, 0.5]] * n)
+    out = oracle.render(sc, cam, oracle.Raster(lowpass=False), prefilter=False)
+    assert out["alpha"][8, 8] == pytest.approx(1 - 0.5 ** 13, abs=1e-15)
+    Zs = np.array([float(np.float32(2.0 + 0.01 * k)) for k in range(13)])
+    w = 0.5 * 0.5 ** np.arange(13)
+    assert out["depth_raw"][8, 8] == pytest.approx(float((w * Zs).sum()), abs=1e-12)
+
+
+def test_alpha_threshold_and_cull(oracle):
+    cam = cam_identity(16, 16, 40.0)
+    # Opacity below 1/255 never contributes; a surfel behind the near plane
+    # is culled by its centre depth.
+    sc = synth.explicit_scene([[0, 0, 2.0], [0, 0, 0.1]], [[1, 0, 0]] * 2, [[0, 1, 0]] * 2, [1.0, 1.0],
+                              [1.0, 1.0], [0.0035, 0.9], [[1, 1, 1]] * 2)
+    out = oracle.render(sc, cam, oracle.Raster(lowpass=False), prefilter=False)
+    assert np.all(out["alpha"] == 0)
+    assert list(oracle.composite_order(sc, cam)) == [0]
+
+
+def test_lowpass_term(oracle):
+    # A surfel far smaller than a pixel: its own Gaussian vanishes one pixel
+    # away and the screen-space term exp(-|x-mu|^2) takes over, with the
+    # centre depth as d.
+    cam = cam_identity(21, 21, 50.0)
+    Z = 3.0
+    sc = synth.explicit_scene([[0.0, 0.0, Z]], [[1, 0, 0]], [[0, 1, 0]], [1e-4], [1e-4], [0.9], [[1, 0, 0]])
+    out = oracle.render(sc, cam, oracle.Raster(lowpass=True), prefilter=False)
+    o = float(np.float32(0.9))
+    for (i, j) in [(11, 10), (10, 12), (12, 12)]:
+        d2 = (i - 10.0) ** 2 + (j - 10.0) ** 2
+        a = min(0.99, o * math.exp(-d2))
+        a = a if a >= 1 / 255 else 0.0
+        assert out["alpha"][j, i] == pytest.approx(a, abs=1e-12)
+        assert out["depth_raw"][j, i] == pytest.approx(a * Z, rel=1e-12, abs=1e-15)
+    assert out["alpha"][12, 12] == 0.0 and out["alpha"][10, 11] > 0.3
+
+
+def test_sh_orthonormal_by_quadrature(oracle):
+    # Gauss-Legendre in cos(theta) x uniform phi integrates products of
+    # degree <= 6 exactly: int Y_i Y_j = delta_ij.
+    xg, wg = np.polynomial.legendre.leggauss(12)
+    nphi = 24
+    phi = 2 * np.pi * np.arange(nphi) / nphi
+    ct, ph = np.meshgrid(xg, phi, indexing="ij")
+    st = np.sqrt(1 - ct * ct)
+    dirs = np.stack([st * np.cos(ph), st * np.sin(ph), ct], axis=-1).reshape(-1, 3)
+    w = (wg[:, None] * np.full(nphi, 2 * np.pi / nphi)[None, :]).reshape(-1)
+    Y = oracle.sh_basis(3, dirs)
+    G = (Y * w[:, None]).T @ Y
+    np.testing.assert_allclose(G, np.eye(16), atol=1e-12)
+
+
+def test_sh_textbook_values(oracle):
+    # Real SH with the Condon-Shortley phase, in Cartesian form (unit x,y,z).
+    rng = np.random.default_rng(3)
+    d = rng.normal(size=(20, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    x, y, z = d.T
+    Y = oracle.sh_basis(2, d)
+    pi = math.pi
+    exp = np.stack([
+        np.full_like(x, 0.5 / math.sqrt(pi)),
+        -math.sqrt(3 / (4 * pi)) * y,
+        math.sqrt(3 / (4 * pi)) * z,
+        -math.sqrt(3 / (4 * pi)) * x,
+        0.5 * math.sqrt(15 / pi) * x * y,
+        -0.5 * math.sqrt(15 / pi) * y * z,
+        0.25 * math.sqrt(5 / pi) * (3 * z * z - 1),
+        -0.5 * math.sqrt(15 / pi) * x * z,
+        0.25 * math.sqrt(15 / pi) * (x * x - y * y),
+    ], axis=1)
+    np.testing.assert_allclose(Y, exp, atol=1e-13)
+    # Degree 3 through the addition theorem: sum_m Y_3m(a) Y_3m(b) =
+    # 7/(4 pi) P_3(a.b).
+    a, b = d[:10], d[10:]
+    Y3a, Y3b = oracle.sh_basis(3, a)[:, 9:16], oracle.sh_basis(3, b)[:, 9:16]
+    c = (a * b).sum(1)
+    P3 = 0.5 * (5 * c ** 3 - 3 * c)
+    np.testing.assert_allclose((Y3a * Y3b).sum(1), 7 / (4 * pi) * P3, atol=1e-13)
+
+
+def test_sh_colour_direction(oracle):
+    # Colour = max(0, sum_lm Y_lm(dir) f_lm + 0.5) with dir from the camera
+    # centre to the surfel (per eye).
+    sc = synth.scene_sphere_shell(2, 40, sh_degree=3)
+    cam = synth.look_at((0, -3, 0.5), (0, 0, 0), (0, 0, 1), 64, 64, 80.0)
+    for k in range(0, 40, 7):
+        e = oracle.pair(sc, cam, k, 32.0, 32.0)
+        if e is None:
+            continue
+        d = sc.pos[:, k].astype(np.float64) - cam.t
+        Y = oracle.sh_basis(3, d / np.linalg.norm(d))[0]
+        f = sc.sh[:, k].astype(np.float64).reshape(16, 3)
+        np.testing.assert_allclose(e["color"], np.maximum(Y @ f + 0.5, 0), atol=1e-12)
+
+
+def test_prefilter_bit_identical(oracle):
+    for seed in range(3):
+        sc = synth.scene_uniform_cube(seed, 200)
+        cam = synth.look_at((0.3, -3.0, 0.2), (0, 0, 0), (0, 0, 1), 32, 32, 40.0)
+        a = oracle.render(sc, cam, prefilter=False)
+        b = oracle.render(sc, cam, prefilter=True)
+        for k in ("rgb", "depth_raw", "alpha", "amb"):
+            assert np.array_equal(a[k], b[k]), k
+
+
+def test_composite_order_is_fp32_centre_depth(oracle):
+    sc = synth.scene_uniform_cube(1, 500)
+    cam = synth.look_at((0.5, -4.0, 0.3), (0, 0, 0), (0, 0, 1), 64, 64, 60.0)
+    z = oracle.center_zkeys(sc, cam)
+    pc = cam.R.T @ (sc.pos.astype(np.float64) - cam.t[:, None])
+    np.testing.assert_allclose(z, pc[2], rtol=1e-6)
+    order = oracle.composite_order(sc, cam)
+    bits = z.view(np.uint32)[order]
+    assert np.all((bits[1:] > bits[:-1]) | ((bits[1:] == bits[:-1]) & (order[1:] > order[:-1])))
+    assert set(order.tolist()) == set(np.nonzero(z > cam.z_near)[0].tolist())
+
+
+def _brute_python(sc, cam, lowpass):
+    """Pure-Python compositing on tiny inputs: hit points by a 3x3 solve,
+    SH0 colours from the stored coefficients, order by the fp32 key."""
+    H, W = cam.height, cam.width
+    z = (np.float32(cam.R[0, 2]) * sc.pos[0] + np.float32(cam.R[1, 2]) * sc.pos[1]) \
+        + np.float32(cam.R[2, 2]) * sc.pos[2] \
+        + np.float32(-((cam.R[0, 2] * cam.t[0] + cam.R[1, 2] * cam.t[1]) + cam.R[2, 2] * cam.t[2]))
+    keys = sorted([(int(z.view(np.uint32)[k]), k) for k in range(sc.n) if z[k] > cam.z_near])
+    rgb = np.zeros((3, H, W))
+    D = np.zeros((H, W))
+    A = np.zeros((H, W))
+    for j in range(H):
+        for i in range(W):
+            ray_c = np.array([(i - cam.cx) / cam.fx, (j - cam.cy) / cam.fy, 1.0])
+            ray_w = cam.R @ ray_c
+            T = 1.0
+            for _, k in keys:
+                tu, tv = _frame_from_quat(sc.quat[:, k].astype(np.float64))
+                p = sc.pos[:, k].astype(np.float64)
+                su, sv = sc.scale[:, k].astype(np.float64)
+                M = np.stack([su * tu, sv * tv, -ray_w], axis=1)
+                g3, lam = 0.0, None
+                try:
+                    u, v, lam = np.linalg.solve(M, cam.t - p)
+                    if lam > cam.z_near:
+                        g3 = math.exp(-0.5 * (u * u + v * v))
+                    else:
+                        lam = None
+                except np.linalg.LinAlgError:
+                    lam = None
+                pc = cam.R.T @ (p - cam.t)
+                g2 = 0.0
+                if lowpass:
+                    mu = (cam.fx * pc[0] / pc[2] + cam.cx, cam.fy * pc[1] / pc[2] + cam.cy)
+                    g2 = math.exp(-((i - mu[0]) ** 2 + (j - mu[1]) ** 2))
+                g = max(g3, g2)
+                a = min(0.99, float(sc.opacity[k]) * g)
+                if a < 1 / 255:
+                    continue
+                Tn = T * (1 - a)
+                if Tn < 1e-4:
+                    break
+                d = lam if (lam is not None and g3 >= g2) else pc[2]
+                w = a * T
+                rgb[:, j, i] += w * stored_colour(sc, k)
+                D[j, i] += w * d
+                A[j, i] += w
+                T = Tn
+    return rgb, D, A
+
+
+@pytest.mark.parametrize("lowpass", [False, True])
+def test_brute_force_tiny_scene(oracle, lowpass):
+    sc = synth.scene_uniform_cube(11, 40, half=0.6, log_scale=(-1.8, 0.3))
+    cam = synth.look_at((0.2, -2.5, 0.4), (0, 0, 0), (0, 0, 1), 12, 10, 9.0)
+    rgb, D, A = _brute_python(sc, cam, lowpass)
+    out = oracle.render(sc, cam, oracle.Raster(lowpass=lowpass), prefilter=False)
+    np.testing.assert_allclose(out["rgb"], rgb, atol=1e-9)
+    np.testing.assert_allclose(out["depth_raw"], D, atol=1e-9)
+    np.testing.assert_allclose(out["alpha"], A, atol=1e-9)

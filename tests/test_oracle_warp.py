@@ -1,0 +1,280 @@
+"""Pins of the oracle's Stages 2-4: reprojection (Eq. 3-5), edge ROIs
+(Eq. 6-8), gap interpolation, connected center holes and boxes, ROI
+re-rendering, and the composed stereo frame.  CPU only."""
+import math
+
+import numpy as np
+import pytest
+from scipy import ndimage
+
+from paper_2609_30741_amd import synth
+
+
+def plane_images(W, H, Z, seed=0):
+    rng = np.random.default_rng(seed)
+    rgb = rng.uniform(0, 1, size=(3, H, W)).astype(np.float32)
+    alpha = np.ones((H, W), np.float32)
+    depth_raw = np.full((H, W), Z, np.float32)
+    return rgb, depth_raw, alpha
+
+
+def rig(W=96, H=64, f=120.0, b=0.064):
+    dom = synth.look_at((0.0, -4.0, 0.0), (0, 0, 0), (0, 0, 1), W, H, f)
+    return dom, synth.affiliated(dom, b)
+
+
+def test_zero_baseline_is_identity(oracle):
+    dom, _ = rig()
+    rgb, dr, a = synth.stage_images(dom.width, dom.height, 4)
+    out = oracle.reproject(dom, dom, rgb, dr, a)
+    assert out["hole"].sum() == 0
+    assert np.array_equal(out["rgb"], rgb)
+    assert np.array_equal(out["alpha"], a)
+    fg = a >= 0.5
+    assert np.array_equal(out["z"][fg], (dr[fg] / a[fg]).astype(np.float32))
+    assert np.all(np.isinf(out["z"][~fg]))
+
+
+@pytest.mark.parametrize("Z", [2.0, 3.3, 5.0])
+def test_plane_shift_closed_form(oracle, Z):
+    # A fronto-parallel plane at depth Z seen by an eye moved b along x
+    # shifts by s = fx b / Z pixels: source column i lands on
+    # floor(i - s + 0.5); the columns after floor(W-1-s+0.5) are holes.
+    dom, aff = rig()
+    W, H = dom.width, dom.height
+    rgb, dr, a = plane_images(W, H, Z)
+    out = oracle.reproject(dom, aff, rgb, dr, a)
+    s = dom.fx * 0.064 / float(np.float32(Z))
+    last = math.floor(W - 1 - s + 0.5)
+    exp_hole = np.zeros((H, W), np.uint8)
+    exp_hole[:, last + 1:] = 1
+    assert np.array_equal(out["hole"], exp_hole)
+    for i in range(W):
+        t = math.floor(i - s + 0.5)
+        if 0 <= t < W:
+            assert np.array_equal(out["rgb"][:, :, t], rgb[:, :, i])
+    np.testing.assert_array_equal(out["depth_range"], np.float32([Z, Z]))
+    # Eq. 7-8 closed form: only the right border is uncovered.
+    roi = oracle.Roi()
+    widths, boxes = oracle.edge_rois(dom, aff, roi, out["depth_range"])
+    rw = min(max((W - 1) - math.floor(W - 1 - s) + roi.margin, 0), W // 2)
+    assert list(widths) == [0, rw, 0, 0]
+    assert boxes.tolist() == [[(W - rw) // 16 * 16, 0, W, H, oracle.BOX_RIGHT, -1]]
+
+
+def test_edge_rois_cube_workload_example(oracle):
+    # 256x256, fx = 300, b = 0.064, plane at Z = 4: s = 4.8, right width =
+    # 255 - floor(250.2) + 32 = 37, so the strip starts at floor16(219) = 208.
+    dom = synth.look_at((0.0, -4.0, 0.0), (0, 0, 0), (0, 0, 1), 256, 256, 300.0)
+    aff = synth.affiliated(dom, 0.064)
+    widths, boxes = oracle.edge_rois(dom, aff, oracle.Roi(), np.array([4.0, 4.0], np.float32))
+    assert list(widths) == [0, 37, 0, 0]
+    assert boxes.tolist() == [[208, 0, 256, 256, oracle.BOX_RIGHT, -1]]
+    # Zero baseline: nothing uncovered.
+    widths, boxes = oracle.edge_rois(dom, dom, oracle.Roi(), np.array([1.0, 9.0], np.float32))
+    assert list(widths) == [0, 0, 0, 0] and len(boxes) == 0
+    # Widths are clamped to half the image (Eq. 7-8).
+    far = synth.affiliated(dom, 4.0)
+    widths, _ = oracle.edge_rois(dom, far, oracle.Roi(), np.array([4.0, 4.0], np.float32))
+    assert widths[1] == 128
+
+
+def test_ztest_nearest_and_index_tiebreak(oracle):
+    # Two source pixels of one row aimed at the same destination column: the
+    # nearer one wins; with equal depth the smaller source index wins.
+    dom, aff = rig(W=64, H=8)
+    W, H = 64, 8
+    rgb, dr, a = plane_images(W, H, 4.0, seed=1)
+    s4 = dom.fx * 0.064 / 4.0
+    i0 = 30
+    t = math.floor(i0 - s4 + 0.5)
+    # Pixel i0+3 at a depth that sends it to column t as well.
+    Zn = dom.fx * 0.064 / (i0 + 3 - t)
+    dr[:, i0 + 3] = np.float32(Zn)
+    out = oracle.reproject(dom, aff, rgb, dr, a)
+    src = out["zbuf"][:, t] & np.uint64(0xFFFFFFFF)
+    assert np.all(src % W == i0 + 3)
+    # Equal keys are impossible (distinct sources), so the smaller index wins
+    # when depths tie: make two source pixels of equal depth collide.
+    dr2 = np.full((H, W), 4.0, np.float32)
+    dom2 = dom.copy()
+    out2 = oracle.reproject(dom2, dom2, rgb, dr2, a)
+    assert np.all((out2["zbuf"] & np.uint64(0xFFFFFFFF)) == np.arange(H * W).reshape(H, W))
+
+
+def test_background_moves_with_rotation_only(oracle):
+    dom, aff = rig(W=48, H=32)
+    rgb, dr, a = plane_images(48, 32, 3.0)
+    a[:] = 0.0
+    dr[:] = 0.0
+    out = oracle.reproject(dom, aff, rgb, dr, a)
+    assert out["hole"].sum() == 0
+    assert np.all(np.isinf(out["z"]))
+    assert np.array_equal(out["rgb"], rgb)
+    np.testing.assert_array_equal(out["depth_range"], np.float32([dom.z_near, dom.z_far]))
+
+
+def _classify(oracle, rgb, z, a, hole, center=True, passes=2, margin=32, W=None, H=None):
+    dom, _ = rig(W=W or rgb.shape[2], H=H or rgb.shape[1])
+    roi = oracle.Roi(center_roi=center, gap_passes=passes, margin=margin)
+    # Zero baseline and a single depth: no edge ROIs, only the given holes.
+    return oracle.classify(dom, dom, roi, np.array([4.0, 4.0], np.float32), rgb, z, a, hole)
+
+
+def test_gap_isolated_hole_is_neighbour_mean(oracle):
+    W, H = 40, 30
+    rng = np.random.default_rng(2)
+    rgb = rng.uniform(0, 1, size=(3, H, W)).astype(np.float32)
+    z = rng.uniform(1, 5, size=(H, W)).astype(np.float32)
+    a = rng.uniform(0.5, 1, size=(H, W)).astype(np.float32)
+    hole = np.zeros((H, W), np.uint8)
+    hole[10, 20] = 1
+    out = _classify(oracle, rgb, z, a, hole)
+    nb = [(-1, -1), (0, -1), (1, -1), (-1, 0), (1, 0), (-1, 1), (0, 1), (1, 1)]
+    for c in range(3):
+        acc = np.float32(0)
+        for dx, dy in nb:
+            acc = np.float32(acc + rgb[c, 10 + dy, 20 + dx])
+        assert out["rgb"][c, 10, 20] == np.float32(acc / np.float32(8))
+    assert out["z"][10, 20] == max(z[10 + dy, 20 + dx] for dx, dy in nb)
+    assert out["cls"][10, 20] == oracle.CLS_GAP
+    assert out["n_boxes"] == 0 and out["tile_mask"].sum() == 0
+
+
+@pytest.mark.parametrize("w", [1, 2, 3, 4, 5, 7])
+def test_gap_run_filled_iff_short(oracle, w):
+    # k Jacobi passes fill exactly the holes whose chessboard distance to a
+    # non-hole pixel is <= k; a tall run of width w is closed iff w <= 2k.
+    W, H = 48, 40
+    rgb = np.full((3, H, W), 0.5, np.float32)
+    z = np.full((H, W), 2.0, np.float32)
+    a = np.ones((H, W), np.float32)
+    hole = np.zeros((H, W), np.uint8)
+    hole[8:30, 10:10 + w] = 1
+    hole[33, 5:5 + w] = 1
+    for k in (1, 2, 3):
+        out = _classify(oracle, rgb, z, a, hole, passes=k, center=True)
+        dist = ndimage.distance_transform_cdt(hole, metric="chessboard")
+        exp = (hole == 1) & (dist <= k)
+        assert np.array_equal(out["cls"] == oracle.CLS_GAP, exp)
+        assert (out["cls"][8:30, 10:10 + w] == oracle.CLS_GAP).all() == (w <= 2 * k)
+
+
+def test_center_hole_box(oracle):
+    W, H = 160, 128
+    rgb = np.full((3, H, W), 0.3, np.float32)
+    z = np.full((H, W), 2.0, np.float32)
+    a = np.ones((H, W), np.float32)
+    hole = np.zeros((H, W), np.uint8)
+    hole[50:70, 60:75] = 1   # 20x15 block, too wide for 2 passes
+    out = _classify(oracle, rgb, z, a, hole)
+    lab = out["labels"]
+    rem = out["cls"] == oracle.CLS_HOLE
+    assert rem.sum() > 0 and np.all(lab[rem] == lab[rem].min())
+    first = np.flatnonzero(rem.ravel())[0]
+    assert lab.ravel()[first] == first
+    ys, xs = np.nonzero(rem)
+    x0, y0, x1, y1 = xs.min() - 32, ys.min() - 32, xs.max() + 1 + 32, ys.max() + 1 + 32
+    x0, y0 = max(x0, 0) // 16 * 16, max(y0, 0) // 16 * 16
+    x1, y1 = min(-(-min(x1, W) // 16) * 16, W), min(-(-min(y1, H) // 16) * 16, H)
+    assert out["boxes"].tolist() == [[x0, y0, x1, y1, oracle.BOX_CENTER, first]]
+    tm = np.zeros_like(out["tile_mask"])
+    tm[y0 // 16:-(-y1 // 16), x0 // 16:-(-x1 // 16)] = 1
+    assert np.array_equal(out["tile_mask"], tm)
+
+
+def test_row_fill_takes_farther_side(oracle):
+    W, H = 64, 32
+    rgb = np.zeros((3, H, W), np.float32)
+    rgb[0, :, :20] = 1.0   # near side on the left
+    rgb[1, :, 40:] = 1.0   # far side on the right
+    z = np.full((H, W), 1.0, np.float32)
+    z[:, 40:] = 5.0
+    a = np.ones((H, W), np.float32)
+    hole = np.zeros((H, W), np.uint8)
+    hole[:, 20:40] = 1
+    out = _classify(oracle, rgb, z, a, hole, center=False)
+    mid = out["cls"][:, 25:35]
+    assert np.all(mid == oracle.CLS_ROWFILL)
+    assert np.all(out["rgb"][1, :, 25:35] == 1.0) and np.all(out["z"][:, 25:35] == 5.0)
+    assert out["n_boxes"] == 0
+
+
+def _partition_equal(lab, ref_lab):
+    # Same partition as scipy, and each label is the smallest linear index.
+    m = ref_lab > 0
+    assert np.array_equal(lab >= 0, m)
+    flat = lab.ravel()
+    for comp in range(1, ref_lab.max() + 1):
+        idx = np.flatnonzero(ref_lab.ravel() == comp)
+        assert np.all(flat[idx] == idx.min())
+
+
+@pytest.mark.parametrize("case", ["rand05", "rand30", "rand70", "checker", "serpentine", "single", "empty", "full"])
+def test_label_components_vs_scipy(oracle, case):
+    W, H = 67, 45
+    if case.startswith("rand"):
+        mask = synth.random_mask(W, H, 9, int(case[4:]) / 100)
+    elif case == "checker":
+        mask = synth.checkerboard_mask(W, H)
+    elif case == "serpentine":
+        mask = synth.serpentine_mask(W, H)
+    elif case == "single":
+        mask = np.zeros((H, W), np.uint8)
+        mask[20, 30] = 1
+    elif case == "empty":
+        mask = np.zeros((H, W), np.uint8)
+    else:
+        mask = np.ones((H, W), np.uint8)
+    lab = oracle.label_components(mask, 8)
+    ref, _ = ndimage.label(mask, structure=np.ones((3, 3)))
+    _partition_equal(lab, ref)
+    lab4 = oracle.label_components(mask, 4)
+    ref4, _ = ndimage.label(mask)
+    _partition_equal(lab4, ref4)
+
+
+def test_patch_all_tiles_equals_full_render(oracle):
+    sc = synth.scene_uniform_cube(3, 600)
+    dom = synth.look_at((0.0, -4.0, 0.0), (0, 0, 0), (0, 0, 1), 64, 48, 70.0)
+    full = oracle.render(sc, dom)
+    H, W = 48, 64
+    tm = np.ones((3, 4), np.uint8)
+    z0 = np.zeros((H, W), np.float32)
+    out = oracle.patch(sc, dom, tm, np.zeros((3, H, W), np.float32), z0, z0, np.zeros((H, W), np.uint8))
+    assert np.array_equal(out["rgb"], full["rgb"].astype(np.float32))
+    assert np.array_equal(out["alpha"], full["alpha"].astype(np.float32))
+    fg = full["alpha"] >= 0.5
+    assert np.array_equal(out["z"][fg], (full["depth_raw"][fg] / full["alpha"][fg]).astype(np.float32))
+    assert np.all(np.isinf(out["z"][~fg]))
+    assert np.all(out["cls"] == oracle.CLS_ROI)
+    # Empty mask: nothing changes.
+    rgb = np.random.default_rng(0).uniform(size=(3, H, W)).astype(np.float32)
+    out2 = oracle.patch(sc, dom, np.zeros((3, 4), np.uint8), rgb, z0, z0, np.zeros((H, W), np.uint8))
+    assert np.array_equal(out2["rgb"], rgb) and np.all(out2["cls"] == 0)
+
+
+def test_stereo_zero_baseline(oracle):
+    sc = synth.scene_uniform_cube(4, 800)
+    dom = synth.look_at((0.0, -4.0, 0.0), (0, 0, 0), (0, 0, 1), 64, 64, 75.0)
+    out = oracle.render_stereo(sc, dom, dom.copy())
+    assert out["rep"]["hole"].sum() == 0
+    assert out["cls"]["n_boxes"] == 0
+    assert np.array_equal(out["aff"]["rgb"], out["dom"]["rgb"].astype(np.float32))
+
+
+def test_stereo_cube_workload_small(oracle):
+    # The composed frame: every pixel ends warped, gap-filled or in an ROI,
+    # and the ROI pixels equal the full affiliated render.
+    sc = synth.scene_uniform_cube(0, 3000)
+    dom = synth.look_at((0.0, -4.0, 0.0), (0, 0, 0), (0, 0, 1), 96, 96, 112.0)
+    aff = synth.affiliated(dom, 0.064)
+    out = oracle.render_stereo(sc, dom, aff)
+    cls = out["aff"]["cls"]
+    assert not np.any(cls == oracle.CLS_HOLE)
+    full = oracle.render(sc, aff)
+    roi = cls == oracle.CLS_ROI
+    assert roi.sum() > 0
+    assert np.array_equal(out["aff"]["rgb"][:, roi], full["rgb"][:, roi].astype(np.float32))
+    # Edge ROI on the right for a rightward baseline.
+    assert out["cls"]["boxes"][0][4] == oracle.BOX_RIGHT
