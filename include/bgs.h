@@ -137,6 +137,9 @@ typedef struct bgs_stats {
     int32_t n_holes, n_gap, n_center, n_rowfill, n_boxes, n_roi_tiles;
     int32_t overflow;
     int32_t reserved;
+    /* Only with bgs_ctx_set_count_pairs(ctx, 1): (pixel, surfel) pairs the
+     * blend evaluated, and those that contributed to a pixel. */
+    int64_t pairs_eval_dom, pairs_used_dom, pairs_eval_roi, pairs_used_roi;
 } bgs_stats;
 
 typedef struct bgs_ctx bgs_ctx;
@@ -150,6 +153,24 @@ BGS_API int32_t bgs_ctx_set_stream(bgs_ctx* ctx, void* hip_stream);
  * count and capacity overflow; sync = 0: nothing waits. */
 BGS_API int32_t bgs_ctx_set_sync(bgs_ctx* ctx, int32_t sync);
 BGS_API const char* bgs_last_error(const bgs_ctx* ctx);
+/* count = 1: the blend kernels also count evaluated and contributing
+ * (pixel, surfel) pairs into bgs_stats (slower; for measurement only). */
+BGS_API int32_t bgs_ctx_set_count_pairs(bgs_ctx* ctx, int32_t count);
+
+/* Per-stage GPU timing with HIP events recorded on the context's stream
+ * around each stage's launches.  on = 1 enables it and clears the totals.
+ * After the caller has waited for the stream, bgs_timing_collect() adds the
+ * elapsed times of the stages recorded since the last collect to the
+ * totals and copies totals (ms) and counts for the BGS_NUM_STAGES stages,
+ * in the order of enum bgs_stage. */
+enum bgs_stage {
+    BGS_STAGE_PREPROCESS_DOM = 0, BGS_STAGE_DEPTH_SORT_DOM, BGS_STAGE_EMIT_DOM, BGS_STAGE_TILE_SORT_DOM,
+    BGS_STAGE_RANGES_DOM, BGS_STAGE_BLEND_DOM, BGS_STAGE_REPROJECT, BGS_STAGE_CLASSIFY,
+    BGS_STAGE_PREPROCESS_ROI, BGS_STAGE_DEPTH_SORT_ROI, BGS_STAGE_EMIT_ROI, BGS_STAGE_TILE_SORT_ROI,
+    BGS_STAGE_RANGES_ROI, BGS_STAGE_BLEND_ROI, BGS_NUM_STAGES
+};
+BGS_API int32_t bgs_ctx_set_timing(bgs_ctx* ctx, int32_t on);
+BGS_API int32_t bgs_timing_collect(bgs_ctx* ctx, double* total_ms, int64_t* counts);
 
 /* Workspace bytes for scenes of up to n surfels, images of up to
  * width x height, and up to key_capacity (surfel, tile) keys per render.

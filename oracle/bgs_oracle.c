@@ -343,11 +343,14 @@ static int may_touch(const osurf* s, const orc_camera* cam, double i, double j) 
     return 0;
 }
 
-/* Ambiguity flags: decisions that fp32 arithmetic may take differently. */
-#define AMB_ALPHA 1 /* alpha within 2e-4 (relative) of alpha_min */
-#define AMB_TSTOP 2 /* transmittance within 1e-3 (relative) of T_min */
-#define AMB_DEPTH 4 /* G3 and G2 within 1e-4 (relative): depth choice */
-#define AMB_GRAZE 8 /* contributing pair with a grazing ray or lambda near z_near */
+/* Ambiguity flags: threshold decisions that an fp32 evaluation of the same
+ * pixel may take differently.  The bands are a few times the relative error
+ * of fp32 arithmetic on fp32 inputs: alpha ~1e-6 (up to ~2e-5 for surfels
+ * seen nearly edge-on), a transmittance product of ~100 factors ~1e-5. */
+#define AMB_ALPHA 1 /* alpha within 5e-5 (relative) of alpha_min */
+#define AMB_TSTOP 2 /* transmittance within 1e-4 (relative) of T_min */
+#define AMB_DEPTH 4 /* G3 and G2 within 1e-5 (relative): depth choice */
+#define AMB_GRAZE 8 /* contributing pair with a ray within 1e-3 of the surfel plane, or lambda near z_near */
 
 static void render_pixel(const osurf* L, int64_t m, const orc_camera* cam, const orc_raster* rp, double i,
                          double j, int prefilter, double out[5], uint8_t* amb) {
@@ -359,15 +362,15 @@ static void render_pixel(const osurf* L, int64_t m, const orc_camera* cam, const
         opair e;
         eval_pair(s, cam, rp, i, j, &e);
         double og = s->o * e.G;
-        if (fabs(og - rp->alpha_min) <= 2e-4 * rp->alpha_min) flags |= AMB_ALPHA;
+        if (fabs(og - rp->alpha_min) <= 5e-5 * rp->alpha_min) flags |= AMB_ALPHA;
         double alpha = og < rp->alpha_max ? og : rp->alpha_max;
         if (alpha < rp->alpha_min) continue;
-        if (e.G2 > 0.0 && fabs(e.G3 - e.G2) <= 1e-4 * e.G) flags |= AMB_DEPTH;
+        if (e.G2 > 0.0 && fabs(e.G3 - e.G2) <= 1e-5 * e.G) flags |= AMB_DEPTH;
         if (e.valid3 && e.G3 >= e.G2 && alpha > 1e-3 &&
-            (e.cosang < 2e-2 || fabs(e.lambda - cam->z_near) <= 1e-5 * cam->z_near))
+            (e.cosang < 1e-3 || fabs(e.lambda - cam->z_near) <= 1e-5 * cam->z_near))
             flags |= AMB_GRAZE;
         double Tn = T * (1.0 - alpha);
-        if (fabs(Tn - rp->t_min) <= 1e-3 * rp->t_min) flags |= AMB_TSTOP;
+        if (fabs(Tn - rp->t_min) <= 1e-4 * rp->t_min) flags |= AMB_TSTOP;
         if (Tn < rp->t_min) break;
         double w = alpha * T;
         C[0] += w * s->col[0];
@@ -589,7 +592,7 @@ ORC_API void orc_reproject(const orc_camera* src, const orc_camera* dst, double 
         double xn = ((double)i - src->cx) / src->fx;
         double yn = ((double)j - src->cy) / src->fy;
         double Xp[3];
-        int fg = (double)alpha[s] >= a_min;
+        int fg = alpha[s] >= (float)a_min; /* the threshold is an fp32 parameter */
         float zf;
         if (fg) {
             float df = depth_raw[s] / alpha[s];

@@ -1,0 +1,721 @@
+// C ABI of the binocular 2DGS frame path: argument validation, workspace
+// layout and the order of the stages on the context's stream.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "bgs_internal.h"
+
+struct bgs_ctx {
+    hipStream_t stream = nullptr;
+    int sync = 1;
+    int count_pairs = 0;
+    int timing = 0;
+    hipEvent_t ev[BGS_NUM_STAGES][2] = {};
+    bool pending[BGS_NUM_STAGES] = {};
+    double total_ms[BGS_NUM_STAGES] = {};
+    int64_t count[BGS_NUM_STAGES] = {};
+    std::string err;
+};
+
+namespace bgs {
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+// Workspace layout.  Regions that depend only on the image size come first
+// so that stage calls, which do not know the scene size, find them at the
+// same offsets; the surfel region follows, then the tile keys, whose count
+// is whatever the remaining bytes hold.
+struct Layout {
+    size_t status;
+    size_t zbuf, rgb2, z2, a2, hole, hole2, flags, bbox, pix_scan;
+    size_t ranges, mask32, mprefix, tlist, tile_scan, torder;
+    size_t recs, zkeys, rects, counts, dkeys_b, dvals_a, dvals_b, offs, surf_scan;
+    size_t tkeys_a, tkeys_b, tvals_a, tvals_b;
+    size_t radix;
+    size_t total;
+};
+
+Layout make_layout(int64_t n, int64_t W, int64_t H, int64_t kc) {
+    Layout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o += up(bytes);
+        return at;
+    };
+    const int64_t np = W * H;
+    const int64_t nt = ((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile);
+    L.status = take(sizeof(DevStatus));
+    L.zbuf = take(8 * np);
+    L.rgb2 = take(12 * np);
+    L.z2 = take(4 * np);
+    L.a2 = take(4 * np);
+    L.hole = take(np);
+    L.hole2 = take(np);
+    L.flags = take(4 * (np + 1));
+    L.bbox = take(16 * np);
+    L.pix_scan = take(4 * scan_tmp_elems(np));
+    L.ranges = take(8 * nt);
+    L.mask32 = take(4 * nt);
+    L.mprefix = take(4 * (nt + 1));
+    L.tlist = take(4 * nt);
+    L.tile_scan = take(4 * scan_tmp_elems(nt));
+    L.torder = take(4 * nt);
+    L.recs = take(sizeof(SurfelRec) * n);
+    L.zkeys = take(4 * n);
+    L.rects = take(8 * n);
+    L.counts = take(4 * n);
+    L.dkeys_b = take(4 * n);
+    L.dvals_a = take(4 * n);
+    L.dvals_b = take(4 * n);
+    L.offs = take(4 * (n + 1));
+    L.surf_scan = take(4 * scan_tmp_elems(n));
+    L.tkeys_a = take(4 * kc);
+    L.tkeys_b = take(4 * kc);
+    L.tvals_a = take(4 * kc);
+    L.tvals_b = take(4 * kc);
+    L.radix = take(radix_tmp_bytes(kc > n ? kc : n));
+    L.total = o;
+    return L;
+}
+
+// Largest key capacity whose layout fits in `bytes` (-1 if none does).
+int64_t key_capacity_for(int64_t n, int64_t W, int64_t H, size_t bytes) {
+    if (make_layout(n, W, H, 0).total > bytes) return -1;
+    int64_t lo = 0, hi = 1;
+    while (hi < (int64_t)0xFFFFFFF0 && make_layout(n, W, H, hi).total <= bytes) hi *= 2;
+    if (hi > (int64_t)0xFFFFFFF0) hi = 0xFFFFFFF0;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo + 1) / 2;
+        if (make_layout(n, W, H, mid).total <= bytes) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <class T>
+T* at(void* ws, size_t off) {
+    return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+int fail(bgs_ctx* ctx, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+int fail(bgs_ctx* ctx, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    return code;
+}
+
+int hip_fail(bgs_ctx* ctx, hipError_t e, const char* where) {
+    return fail(ctx, BGS_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define HIP_CHECK(expr, where)                        \
+    do {                                              \
+        hipError_t e_ = (expr);                       \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, where); \
+    } while (0)
+
+int check_camera(bgs_ctx* ctx, const bgs_camera* c, const char* name) {
+    if (!c) return fail(ctx, BGS_ERR_INVALID_ARG, "%s: null camera", name);
+    if (c->width < 1 || c->width > 16384 || c->height < 1 || c->height > 16384)
+        return fail(ctx, BGS_ERR_INVALID_ARG, "%s: image size %dx%d outside [1, 16384]", name, c->width, c->height);
+    if (!(c->fx > 0.0) || !(c->fy > 0.0) || !std::isfinite(c->fx) || !std::isfinite(c->fy))
+        return fail(ctx, BGS_ERR_INVALID_ARG, "%s: focal lengths must be positive", name);
+    if (!std::isfinite(c->cx) || !std::isfinite(c->cy))
+        return fail(ctx, BGS_ERR_INVALID_ARG, "%s: principal point must be finite", name);
+    if (!(c->z_near > 0.0) || !(c->z_far > c->z_near))
+        return fail(ctx, BGS_ERR_INVALID_ARG, "%s: need 0 < z_near < z_far", name);
+    for (int i = 0; i < 3; ++i) {
+        if (!std::isfinite(c->t[i])) return fail(ctx, BGS_ERR_INVALID_ARG, "%s: camera centre not finite", name);
+        for (int j = 0; j < 3; ++j) {
+            double d = 0.0;
+            for (int k = 0; k < 3; ++k) d += c->R[k * 3 + i] * c->R[k * 3 + j];
+            if (!(std::fabs(d - (i == j ? 1.0 : 0.0)) <= 1e-6))
+                return fail(ctx, BGS_ERR_INVALID_ARG, "%s: R is not orthonormal", name);
+        }
+    }
+    return BGS_OK;
+}
+
+int check_scene(bgs_ctx* ctx, const bgs_scene* s) {
+    if (!s) return fail(ctx, BGS_ERR_INVALID_ARG, "null scene");
+    if (s->n < 0 || s->n >= ((int64_t)1 << 31)) return fail(ctx, BGS_ERR_INVALID_ARG, "scene size %lld out of range", (long long)s->n);
+    if (s->sh_degree < 0 || s->sh_degree > 3)
+        return fail(ctx, BGS_ERR_INVALID_ARG, "sh_degree %d outside 0..3", s->sh_degree);
+    if (s->n > 0 && (!s->pos || !s->quat || !s->scale || !s->opacity || !s->sh))
+        return fail(ctx, BGS_ERR_INVALID_ARG, "null scene array");
+    return BGS_OK;
+}
+
+int check_raster(bgs_ctx* ctx, const bgs_raster_params* r) {
+    if (!r) return fail(ctx, BGS_ERR_INVALID_ARG, "null raster params");
+    if (!(r->alpha_min > 0.f && r->alpha_min < 1.f) || !(r->alpha_max > r->alpha_min && r->alpha_max <= 1.f) ||
+        !(r->t_min > 0.f && r->t_min < 1.f))
+        return fail(ctx, BGS_ERR_INVALID_ARG, "raster thresholds out of range");
+    return BGS_OK;
+}
+
+int check_roi(bgs_ctx* ctx, const bgs_roi_params* r) {
+    if (!r) return fail(ctx, BGS_ERR_INVALID_ARG, "null roi params");
+    if (r->tile != kTile) return fail(ctx, BGS_ERR_UNSUPPORTED, "tile %d unsupported (only 16)", r->tile);
+    if (r->margin < 0 || r->margin > 16384) return fail(ctx, BGS_ERR_INVALID_ARG, "margin %d out of range", r->margin);
+    if (r->edge_samples < 1 || r->edge_samples > 65536)
+        return fail(ctx, BGS_ERR_INVALID_ARG, "edge_samples %d out of range", r->edge_samples);
+    if (r->gap_passes < 0 || r->gap_passes > 64)
+        return fail(ctx, BGS_ERR_INVALID_ARG, "gap_passes %d out of range", r->gap_passes);
+    if (!(r->a_min > 0.f && r->a_min <= 1.f)) return fail(ctx, BGS_ERR_INVALID_ARG, "a_min out of (0, 1]");
+    return BGS_OK;
+}
+
+PreCam make_precam(const bgs_camera& c) {
+    PreCam p{};
+    for (int r = 0; r < 3; ++r)
+        for (int q = 0; q < 3; ++q) p.Rt[r * 3 + q] = c.R[q * 3 + r];
+    for (int i = 0; i < 3; ++i) p.t[i] = c.t[i];
+    p.fx = c.fx;
+    p.fy = c.fy;
+    p.cx = c.cx;
+    p.cy = c.cy;
+    p.z_near = c.z_near;
+    // Centre-depth key coefficients: row 2 of R^T and -(R^T t)_2, in fp64
+    // with a fixed summation order, then rounded to fp32.
+    const double r20 = c.R[0 * 3 + 2], r21 = c.R[1 * 3 + 2], r22 = c.R[2 * 3 + 2];
+    const double tz = -(((r20 * c.t[0]) + (r21 * c.t[1])) + (r22 * c.t[2]));
+    p.zc[0] = (float)r20;
+    p.zc[1] = (float)r21;
+    p.zc[2] = (float)r22;
+    p.zc[3] = (float)tz;
+    p.W = c.width;
+    p.H = c.height;
+    p.tiles_x = (c.width + kTile - 1) / kTile;
+    p.tiles_y = (c.height + kTile - 1) / kTile;
+    return p;
+}
+
+WarpCam make_warpcam(const bgs_camera& c) {
+    WarpCam w;
+    w.W = c.width;
+    w.H = c.height;
+    w.fx = c.fx;
+    w.fy = c.fy;
+    w.cx = c.cx;
+    w.cy = c.cy;
+    w.z_near = c.z_near;
+    w.z_far = c.z_far;
+    return w;
+}
+
+int tile_bits(int64_t n_tiles) {
+    int b = 1;
+    while (((int64_t)1 << b) < n_tiles) ++b;
+    return b;
+}
+
+// Records the start (end = 0) or end (end = 1) of a stage when timing is on.
+void mark(bgs_ctx* ctx, int stage, int end) {
+    if (!ctx->timing) return;
+    hipEventRecord(ctx->ev[stage][end], ctx->stream);
+    if (end) ctx->pending[stage] = true;
+}
+
+void fill_stats(const DevStatus& h, bgs_stats* s) {
+    s->n_keys_dom = h.n_keys_dom;
+    s->n_keys_roi = h.n_keys_roi;
+    s->n_holes = (int32_t)h.n_holes;
+    s->n_gap = (int32_t)h.n_gap;
+    s->n_center = (int32_t)h.n_center;
+    s->n_rowfill = (int32_t)h.n_rowfill;
+    s->n_boxes = (int32_t)h.n_boxes;
+    s->n_roi_tiles = (int32_t)h.n_roi_tiles;
+    s->overflow = (int32_t)h.overflow;
+    s->reserved = 0;
+    s->pairs_eval_dom = (int64_t)h.pairs[0];
+    s->pairs_used_dom = (int64_t)h.pairs[1];
+    s->pairs_eval_roi = (int64_t)h.pairs[2];
+    s->pairs_used_roi = (int64_t)h.pairs[3];
+}
+
+struct RasterOut {
+    float* rgb;
+    float* dz;
+    float* alpha;
+    uint8_t* cls;
+};
+
+// Stage 1 for one camera, optionally restricted to the tiles of tile_mask.
+int raster_pass(bgs_ctx* ctx, const Layout& L, void* ws, int64_t kc, const bgs_scene& scene, const bgs_camera& cam,
+                const bgs_raster_params& rp, const uint8_t* tile_mask, float a_min, const RasterOut& out, int which) {
+    hipStream_t s = ctx->stream;
+    const int n = (int)scene.n;
+    const PreCam pc = make_precam(cam);
+    const int n_tiles = pc.tiles_x * pc.tiles_y;
+    DevStatus* st = at<DevStatus>(ws, L.status);
+    const int sb = which ? BGS_STAGE_PREPROCESS_ROI : BGS_STAGE_PREPROCESS_DOM;
+    mark(ctx, sb + 0, 0);
+    MaskArgs mask{nullptr, 0};
+    if (tile_mask) {
+        HIP_CHECK(launch_mask_prefix(tile_mask, n_tiles, at<uint32_t>(ws, L.mask32), at<uint32_t>(ws, L.mprefix),
+                                     at<uint32_t>(ws, L.tlist), at<uint32_t>(ws, L.tile_scan), st, s),
+                  "mask prefix");
+        mask.prefix = at<uint32_t>(ws, L.mprefix);
+        mask.enabled = 1;
+    }
+    SurfelRec* recs = at<SurfelRec>(ws, L.recs);
+    uint32_t* zkeys = at<uint32_t>(ws, L.zkeys);
+    uint2* rects = at<uint2>(ws, L.rects);
+    uint32_t* counts = at<uint32_t>(ws, L.counts);
+    uint32_t* offs = at<uint32_t>(ws, L.offs);
+    const SceneArgs sa{scene.pos, scene.quat, scene.scale, scene.opacity, scene.sh, n, scene.sh_degree};
+    HIP_CHECK(launch_preprocess(sa, pc, rp.alpha_min, rp.lowpass, mask, recs, zkeys, rects, counts, s), "preprocess");
+    mark(ctx, sb + 0, 1);
+    // Compositing order: surfels sorted by (fp32 centre-depth bits, index).
+    mark(ctx, sb + 1, 0);
+    bool in_b = false;
+    uint32_t* dva = at<uint32_t>(ws, L.dvals_a);
+    uint32_t* dvb = at<uint32_t>(ws, L.dvals_b);
+    HIP_CHECK(radix_sort(zkeys, dva, at<uint32_t>(ws, L.dkeys_b), dvb, nullptr, n, 32, true, at<void>(ws, L.radix), s,
+                         &in_b),
+              "depth sort");
+    const uint32_t* order = in_b ? dvb : dva;
+    mark(ctx, sb + 1, 1);
+    mark(ctx, sb + 2, 0);
+    HIP_CHECK(exclusive_scan(counts, order, offs, nullptr, n, at<uint32_t>(ws, L.surf_scan), s), "count scan");
+    HIP_CHECK(launch_status_keys(offs, n, st, (uint32_t)kc, which, s), "key count");
+    uint32_t* tka = at<uint32_t>(ws, L.tkeys_a);
+    uint32_t* tva = at<uint32_t>(ws, L.tvals_a);
+    uint32_t* tkb = at<uint32_t>(ws, L.tkeys_b);
+    uint32_t* tvb = at<uint32_t>(ws, L.tvals_b);
+    HIP_CHECK(launch_emit(order, offs, rects, n, pc.tiles_x, mask, (uint32_t)kc, tka, tva, s), "emit");
+    mark(ctx, sb + 2, 1);
+    // Stable sort by tile: within a tile the emission (= compositing) order stays.
+    mark(ctx, sb + 3, 0);
+    HIP_CHECK(radix_sort(tka, tva, tkb, tvb, &st->n_sort, kc, tile_bits(n_tiles), false, at<void>(ws, L.radix), s,
+                         &in_b),
+              "tile sort");
+    const uint32_t* skeys = in_b ? tkb : tka;
+    const uint32_t* svals = in_b ? tvb : tva;
+    mark(ctx, sb + 3, 1);
+    uint2* ranges = at<uint2>(ws, L.ranges);
+    mark(ctx, sb + 4, 0);
+    HIP_CHECK(launch_ranges(skeys, &st->n_sort, kc, ranges, n_tiles, s), "ranges");
+    uint32_t* torder = at<uint32_t>(ws, L.torder);
+    HIP_CHECK(launch_tile_order(ranges, tile_mask ? &st->n_masked : nullptr, n_tiles, torder, s), "tile order");
+    mark(ctx, sb + 4, 1);
+    BlendArgs ba{};
+    ba.W = cam.width;
+    ba.H = cam.height;
+    ba.tiles_x = pc.tiles_x;
+    ba.alpha_min = rp.alpha_min;
+    ba.alpha_max = rp.alpha_max;
+    ba.t_min = rp.t_min;
+    ba.lowpass = rp.lowpass;
+    ba.bg0 = rp.bg[0];
+    ba.bg1 = rp.bg[1];
+    ba.bg2 = rp.bg[2];
+    ba.a_min = a_min;
+    ba.z_near = (float)cam.z_near;
+    ba.patch = tile_mask ? 1 : 0;
+    mark(ctx, sb + 5, 0);
+    HIP_CHECK(launch_blend(recs, svals, ranges, tile_mask ? at<uint32_t>(ws, L.tlist) : nullptr, torder,
+                           tile_mask ? &st->n_masked : nullptr, n_tiles, ba, out.rgb, out.dz, out.alpha, out.cls,
+                           ctx->count_pairs ? &st->pairs[2 * which] : nullptr, s),
+              "blend");
+    mark(ctx, sb + 5, 1);
+    return BGS_OK;
+}
+
+int finish(bgs_ctx* ctx, void* ws, const Layout& L, DevStatus* host) {
+    HIP_CHECK(hipMemcpyAsync(host, at<DevStatus>(ws, L.status), sizeof(DevStatus), hipMemcpyDeviceToHost, ctx->stream),
+              "status readback");
+    HIP_CHECK(hipStreamSynchronize(ctx->stream), "stream sync");
+    return BGS_OK;
+}
+
+}  // namespace
+}  // namespace bgs
+
+using namespace bgs;
+
+extern "C" {
+
+int32_t bgs_ctx_create(bgs_ctx** out, void* stream) {
+    if (!out) return BGS_ERR_INVALID_ARG;
+    bgs_ctx* c = new (std::nothrow) bgs_ctx();
+    if (!c) return BGS_ERR_INVALID_ARG;
+    c->stream = (hipStream_t)stream;
+    *out = c;
+    return BGS_OK;
+}
+
+int32_t bgs_ctx_destroy(bgs_ctx* ctx) {
+    if (!ctx) return BGS_OK;
+    for (int i = 0; i < BGS_NUM_STAGES; ++i)
+        for (int j = 0; j < 2; ++j)
+            if (ctx->ev[i][j]) hipEventDestroy(ctx->ev[i][j]);
+    delete ctx;
+    return BGS_OK;
+}
+
+int32_t bgs_ctx_set_stream(bgs_ctx* ctx, void* stream) {
+    if (!ctx) return BGS_ERR_INVALID_ARG;
+    ctx->stream = (hipStream_t)stream;
+    return BGS_OK;
+}
+
+int32_t bgs_ctx_set_sync(bgs_ctx* ctx, int32_t sync) {
+    if (!ctx) return BGS_ERR_INVALID_ARG;
+    ctx->sync = sync ? 1 : 0;
+    return BGS_OK;
+}
+
+const char* bgs_last_error(const bgs_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int32_t bgs_ctx_set_count_pairs(bgs_ctx* ctx, int32_t count) {
+    if (!ctx) return BGS_ERR_INVALID_ARG;
+    ctx->count_pairs = count ? 1 : 0;
+    return BGS_OK;
+}
+
+int32_t bgs_ctx_set_timing(bgs_ctx* ctx, int32_t on) {
+    if (!ctx) return BGS_ERR_INVALID_ARG;
+    if (on) {
+        for (int i = 0; i < BGS_NUM_STAGES; ++i)
+            for (int j = 0; j < 2; ++j)
+                if (!ctx->ev[i][j]) {
+                    hipError_t e = hipEventCreate(&ctx->ev[i][j]);
+                    if (e != hipSuccess) return hip_fail(ctx, e, "event create");
+                }
+    }
+    ctx->timing = on ? 1 : 0;
+    for (int i = 0; i < BGS_NUM_STAGES; ++i) {
+        ctx->pending[i] = false;
+        ctx->total_ms[i] = 0.0;
+        ctx->count[i] = 0;
+    }
+    return BGS_OK;
+}
+
+int32_t bgs_timing_collect(bgs_ctx* ctx, double* total_ms, int64_t* counts) {
+    if (!ctx) return BGS_ERR_INVALID_ARG;
+    for (int i = 0; i < BGS_NUM_STAGES; ++i) {
+        if (!ctx->pending[i]) continue;
+        float ms = 0.f;
+        hipError_t e = hipEventElapsedTime(&ms, ctx->ev[i][0], ctx->ev[i][1]);
+        if (e != hipSuccess) return hip_fail(ctx, e, "event elapsed time (wait for the stream first)");
+        ctx->total_ms[i] += ms;
+        ctx->count[i] += 1;
+        ctx->pending[i] = false;
+    }
+    for (int i = 0; i < BGS_NUM_STAGES; ++i) {
+        if (total_ms) total_ms[i] = ctx->total_ms[i];
+        if (counts) counts[i] = ctx->count[i];
+    }
+    return BGS_OK;
+}
+
+int32_t bgs_workspace_size(int64_t n, int32_t width, int32_t height, int64_t key_capacity, size_t* bytes) {
+    if (!bytes || n < 0 || n >= ((int64_t)1 << 31) || width < 1 || height < 1 || width > 16384 || height > 16384 ||
+        key_capacity < 0 || key_capacity > (int64_t)0xFFFFFFF0)
+        return BGS_ERR_INVALID_ARG;
+    *bytes = make_layout(n, width, height, key_capacity).total;
+    return BGS_OK;
+}
+
+int32_t bgs_poll_status(bgs_ctx* ctx, void* ws, size_t ws_bytes, bgs_stats* stats) {
+    if (!ctx || !ws || !stats) return fail(ctx, BGS_ERR_INVALID_ARG, "null argument");
+    if (ws_bytes < sizeof(DevStatus)) return fail(ctx, BGS_ERR_WORKSPACE, "workspace too small");
+    Layout L{};
+    L.status = 0;
+    DevStatus h{};
+    int rc = finish(ctx, ws, L, &h);
+    if (rc) return rc;
+    fill_stats(h, stats);
+    return BGS_OK;
+}
+
+int32_t bgs_render_dominant(bgs_ctx* ctx, const bgs_scene* scene, const bgs_camera* cam,
+                            const bgs_raster_params* raster, void* ws, size_t ws_bytes, float* rgb, float* depth_raw,
+                            float* alpha, int64_t* n_keys) {
+    if (!ctx) return BGS_ERR_INVALID_ARG;
+    int rc;
+    if ((rc = check_scene(ctx, scene)) || (rc = check_camera(ctx, cam, "camera")) || (rc = check_raster(ctx, raster)))
+        return rc;
+    if (!ws || !rgb || !depth_raw || !alpha) return fail(ctx, BGS_ERR_INVALID_ARG, "null buffer");
+    const int64_t kc = key_capacity_for(scene->n, cam->width, cam->height, ws_bytes);
+    if (kc < 0) return fail(ctx, BGS_ERR_WORKSPACE, "workspace of %zu bytes is too small", ws_bytes);
+    const Layout L = make_layout(scene->n, cam->width, cam->height, kc);
+    DevStatus* st = at<DevStatus>(ws, L.status);
+    HIP_CHECK(hipMemsetAsync(st, 0, sizeof(DevStatus), ctx->stream), "status reset");
+    rc = raster_pass(ctx, L, ws, kc, *scene, *cam, *raster, nullptr, 0.f, RasterOut{rgb, depth_raw, alpha, nullptr}, 0);
+    if (rc) return rc;
+    if (!ctx->sync) return BGS_OK;
+    DevStatus h{};
+    if ((rc = finish(ctx, ws, L, &h))) return rc;
+    if (n_keys) *n_keys = h.n_keys_dom;
+    if (h.overflow & 1u)
+        return fail(ctx, BGS_ERR_CAPACITY, "%u tile keys exceed the workspace capacity of %lld", h.n_keys_dom,
+                    (long long)kc);
+    return BGS_OK;
+}
+
+int32_t bgs_reproject(bgs_ctx* ctx, const bgs_camera* src, const bgs_camera* dst, const bgs_roi_params* roi,
+                      const float* rgb_src, const float* depth_raw_src, const float* alpha_src, void* ws,
+                      size_t ws_bytes, float* rgb_dst, float* z_dst, float* alpha_dst, uint8_t* hole_mask,
+                      float* depth_range) {
+    if (!ctx) return BGS_ERR_INVALID_ARG;
+    int rc;
+    if ((rc = check_camera(ctx, src, "src")) || (rc = check_camera(ctx, dst, "dst")) || (rc = check_roi(ctx, roi)))
+        return rc;
+    if (!rgb_src || !depth_raw_src || !alpha_src || !ws || !rgb_dst || !z_dst || !alpha_dst || !hole_mask ||
+        !depth_range)
+        return fail(ctx, BGS_ERR_INVALID_ARG, "null buffer");
+    if ((int64_t)src->width * src->height > ((int64_t)1 << 32))
+        return fail(ctx, BGS_ERR_INVALID_ARG, "source image too large");
+    const Layout L = make_layout(0, dst->width, dst->height, 0);
+    if (L.total > ws_bytes) return fail(ctx, BGS_ERR_WORKSPACE, "workspace of %zu bytes is too small", ws_bytes);
+    DevStatus* st = at<DevStatus>(ws, L.status);
+    HIP_CHECK(launch_reproject(make_warpcam(*src), make_warpcam(*dst), rel_pose(*src, *dst), roi->a_min, rgb_src,
+                               depth_raw_src, alpha_src, at<unsigned long long>(ws, L.zbuf), rgb_dst, z_dst, alpha_dst,
+                               hole_mask, depth_range, st, ctx->stream),
+              "reproject");
+    return BGS_OK;
+}
+
+int32_t bgs_classify_holes(bgs_ctx* ctx, const bgs_camera* src, const bgs_camera* dst, const bgs_roi_params* roi,
+                           const bgs_raster_params* raster, const float* depth_range, void* ws, size_t ws_bytes,
+                           float* rgb_dst, float* z_dst, float* alpha_dst, uint8_t* cls, int32_t* labels,
+                           bgs_box* boxes, int32_t box_capacity, int32_t* n_boxes, uint8_t* tile_mask) {
+    if (!ctx) return BGS_ERR_INVALID_ARG;
+    int rc;
+    if ((rc = check_camera(ctx, src, "src")) || (rc = check_camera(ctx, dst, "dst")) || (rc = check_roi(ctx, roi)) ||
+        (rc = check_raster(ctx, raster)))
+        return rc;
+    if (!depth_range || !ws || !rgb_dst || !z_dst || !alpha_dst || !cls || !labels || !n_boxes || !tile_mask ||
+        (box_capacity > 0 && !boxes) || box_capacity < 0)
+        return fail(ctx, BGS_ERR_INVALID_ARG, "null buffer or negative box capacity");
+    const Layout L = make_layout(0, dst->width, dst->height, 0);
+    if (L.total > ws_bytes) return fail(ctx, BGS_ERR_WORKSPACE, "workspace of %zu bytes is too small", ws_bytes);
+    ClassifyBufs b{at<float>(ws, L.rgb2), at<float>(ws, L.z2), at<float>(ws, L.a2), at<uint8_t>(ws, L.hole),
+                   at<uint8_t>(ws, L.hole2), at<uint32_t>(ws, L.flags), at<int32_t>(ws, L.bbox),
+                   at<uint32_t>(ws, L.pix_scan)};
+    HIP_CHECK(launch_classify(make_warpcam(*src), make_warpcam(*dst), rel_pose(*src, *dst), *roi, raster->bg,
+                              depth_range, rgb_dst, z_dst, alpha_dst, cls, labels, boxes, box_capacity, n_boxes,
+                              tile_mask, b, at<DevStatus>(ws, L.status), ctx->stream),
+              "classify");
+    return BGS_OK;
+}
+
+int32_t bgs_patch_rois(bgs_ctx* ctx, const bgs_scene* scene, const bgs_camera* dst, const bgs_raster_params* raster,
+                       const bgs_roi_params* roi, const uint8_t* tile_mask, void* ws, size_t ws_bytes, float* rgb_dst,
+                       float* z_dst, float* alpha_dst, uint8_t* cls, int64_t* n_keys) {
+    if (!ctx) return BGS_ERR_INVALID_ARG;
+    int rc;
+    if ((rc = check_scene(ctx, scene)) || (rc = check_camera(ctx, dst, "dst")) || (rc = check_raster(ctx, raster)) ||
+        (rc = check_roi(ctx, roi)))
+        return rc;
+    if (!tile_mask || !ws || !rgb_dst || !z_dst || !alpha_dst || !cls) return fail(ctx, BGS_ERR_INVALID_ARG, "null buffer");
+    const int64_t kc = key_capacity_for(scene->n, dst->width, dst->height, ws_bytes);
+    if (kc < 0) return fail(ctx, BGS_ERR_WORKSPACE, "workspace of %zu bytes is too small", ws_bytes);
+    const Layout L = make_layout(scene->n, dst->width, dst->height, kc);
+    DevStatus* st = at<DevStatus>(ws, L.status);
+    HIP_CHECK(hipMemsetAsync(st, 0, sizeof(DevStatus), ctx->stream), "status reset");
+    rc = raster_pass(ctx, L, ws, kc, *scene, *dst, *raster, tile_mask, roi->a_min, RasterOut{rgb_dst, z_dst, alpha_dst, cls},
+                     1);
+    if (rc) return rc;
+    if (!ctx->sync) return BGS_OK;
+    DevStatus h{};
+    if ((rc = finish(ctx, ws, L, &h))) return rc;
+    if (n_keys) *n_keys = h.n_keys_roi;
+    if (h.overflow & 1u)
+        return fail(ctx, BGS_ERR_CAPACITY, "%u ROI keys exceed the workspace capacity of %lld", h.n_keys_roi,
+                    (long long)kc);
+    return BGS_OK;
+}
+
+int32_t bgs_render_stereo(bgs_ctx* ctx, const bgs_scene* scene, const bgs_camera* cam_dom, const bgs_camera* cam_aff,
+                          const bgs_raster_params* raster, const bgs_roi_params* roi, void* ws, size_t ws_bytes,
+                          float* rgb_dom, float* depth_raw_dom, float* alpha_dom, float* rgb_aff, float* z_aff,
+                          float* alpha_aff, uint8_t* cls_aff, int32_t* labels, bgs_box* boxes, int32_t box_capacity,
+                          int32_t* n_boxes, uint8_t* tile_mask, bgs_stats* stats) {
+    if (!ctx) return BGS_ERR_INVALID_ARG;
+    int rc;
+    if ((rc = check_scene(ctx, scene)) || (rc = check_camera(ctx, cam_dom, "dominant camera")) ||
+        (rc = check_camera(ctx, cam_aff, "affiliated camera")) || (rc = check_raster(ctx, raster)) ||
+        (rc = check_roi(ctx, roi)))
+        return rc;
+    if (!ws || !rgb_dom || !depth_raw_dom || !alpha_dom || !rgb_aff || !z_aff || !alpha_aff || !cls_aff || !labels ||
+        !n_boxes || !tile_mask || box_capacity < 0 || (box_capacity > 0 && !boxes))
+        return fail(ctx, BGS_ERR_INVALID_ARG, "null buffer or negative box capacity");
+    const int W = cam_dom->width > cam_aff->width ? cam_dom->width : cam_aff->width;
+    const int H = cam_dom->height > cam_aff->height ? cam_dom->height : cam_aff->height;
+    const int64_t kc = key_capacity_for(scene->n, W, H, ws_bytes);
+    if (kc < 0) return fail(ctx, BGS_ERR_WORKSPACE, "workspace of %zu bytes is too small", ws_bytes);
+    const Layout L = make_layout(scene->n, W, H, kc);
+    hipStream_t s = ctx->stream;
+    DevStatus* st = at<DevStatus>(ws, L.status);
+    HIP_CHECK(hipMemsetAsync(st, 0, sizeof(DevStatus), s), "status reset");
+    // Stage 1: dominant eye with the depth proxy.
+    rc = raster_pass(ctx, L, ws, kc, *scene, *cam_dom, *raster, nullptr, 0.f,
+                     RasterOut{rgb_dom, depth_raw_dom, alpha_dom, nullptr}, 0);
+    if (rc) return rc;
+    // Stage 2: reprojection.  The hole mask is written straight into cls.
+    const WarpCam wd = make_warpcam(*cam_dom), wa = make_warpcam(*cam_aff);
+    const RelPose P = rel_pose(*cam_dom, *cam_aff);
+    float* depth_range = reinterpret_cast<float*>(&st->pad2[0]);
+    mark(ctx, BGS_STAGE_REPROJECT, 0);
+    HIP_CHECK(launch_reproject(wd, wa, P, roi->a_min, rgb_dom, depth_raw_dom, alpha_dom,
+                               at<unsigned long long>(ws, L.zbuf), rgb_aff, z_aff, alpha_aff, cls_aff, depth_range, st, s),
+              "reproject");
+    mark(ctx, BGS_STAGE_REPROJECT, 1);
+    // Stage 3: hole classification and interpolation.
+    ClassifyBufs b{at<float>(ws, L.rgb2), at<float>(ws, L.z2), at<float>(ws, L.a2), at<uint8_t>(ws, L.hole),
+                   at<uint8_t>(ws, L.hole2), at<uint32_t>(ws, L.flags), at<int32_t>(ws, L.bbox),
+                   at<uint32_t>(ws, L.pix_scan)};
+    mark(ctx, BGS_STAGE_CLASSIFY, 0);
+    HIP_CHECK(launch_classify(wd, wa, P, *roi, raster->bg, depth_range, rgb_aff, z_aff, alpha_aff, cls_aff, labels, boxes,
+                              box_capacity, n_boxes, tile_mask, b, st, s),
+              "classify");
+    mark(ctx, BGS_STAGE_CLASSIFY, 1);
+    // Stage 4: ROI re-rasterisation of the affiliated eye.
+    rc = raster_pass(ctx, L, ws, kc, *scene, *cam_aff, *raster, tile_mask, roi->a_min,
+                     RasterOut{rgb_aff, z_aff, alpha_aff, cls_aff}, 1);
+    if (rc) return rc;
+    if (!ctx->sync && !stats) return BGS_OK;
+    DevStatus h{};
+    if ((rc = finish(ctx, ws, L, &h))) return rc;
+    if (stats) fill_stats(h, stats);
+    if (h.overflow & 1u)
+        return fail(ctx, BGS_ERR_CAPACITY, "tile keys (%u dominant, %u ROI) exceed the capacity of %lld", h.n_keys_dom,
+                    h.n_keys_roi, (long long)kc);
+    return BGS_OK;
+}
+
+int32_t bgs_sort_workspace_size(int64_t n, size_t* bytes) {
+    if (!bytes || n < 0 || n > (int64_t)0xFFFFFFF0) return BGS_ERR_INVALID_ARG;
+    *bytes = up(sizeof(DevStatus)) + 2 * up(4 * (size_t)n) + up(radix_tmp_bytes(n));
+    return BGS_OK;
+}
+
+int32_t bgs_sort_pairs(bgs_ctx* ctx, uint32_t* keys, uint32_t* values, int64_t n, int32_t key_bits, void* ws,
+                       size_t ws_bytes) {
+    if (!ctx) return BGS_ERR_INVALID_ARG;
+    if (n < 0 || n > (int64_t)0xFFFFFFF0) return fail(ctx, BGS_ERR_INVALID_ARG, "n out of range");
+    if (key_bits < 1 || key_bits > 32) return fail(ctx, BGS_ERR_INVALID_ARG, "key_bits %d outside 1..32", key_bits);
+    if (n == 0) return BGS_OK;
+    if (!keys || !values || !ws) return fail(ctx, BGS_ERR_INVALID_ARG, "null buffer");
+    size_t need = 0;
+    bgs_sort_workspace_size(n, &need);
+    if (ws_bytes < need) return fail(ctx, BGS_ERR_WORKSPACE, "sort workspace needs %zu bytes", need);
+    uint32_t* kb = at<uint32_t>(ws, up(sizeof(DevStatus)));
+    uint32_t* vb = at<uint32_t>(ws, up(sizeof(DevStatus)) + up(4 * (size_t)n));
+    void* tmp = at<void>(ws, up(sizeof(DevStatus)) + 2 * up(4 * (size_t)n));
+    bool in_b = false;
+    HIP_CHECK(radix_sort(keys, values, kb, vb, nullptr, n, key_bits, false, tmp, ctx->stream, &in_b), "sort");
+    if (in_b) {
+        HIP_CHECK(hipMemcpyAsync(keys, kb, 4 * (size_t)n, hipMemcpyDeviceToDevice, ctx->stream), "copy");
+        HIP_CHECK(hipMemcpyAsync(values, vb, 4 * (size_t)n, hipMemcpyDeviceToDevice, ctx->stream), "copy");
+    }
+    return BGS_OK;
+}
+
+int32_t bgs_label_components(bgs_ctx* ctx, const uint8_t* mask, int32_t width, int32_t height, int32_t conn,
+                             int32_t* labels) {
+    if (!ctx) return BGS_ERR_INVALID_ARG;
+    if (width < 1 || height < 1 || width > 16384 || height > 16384)
+        return fail(ctx, BGS_ERR_INVALID_ARG, "image size out of range");
+    if (conn != 4 && conn != 8) return fail(ctx, BGS_ERR_INVALID_ARG, "conn must be 4 or 8");
+    if (!mask || !labels) return fail(ctx, BGS_ERR_INVALID_ARG, "null buffer");
+    HIP_CHECK(launch_label_components(mask, width, height, conn, labels, ctx->stream), "label components");
+    return BGS_OK;
+}
+
+int32_t bgs_preprocess_debug(bgs_ctx* ctx, const bgs_scene* scene, const bgs_camera* cam,
+                             const bgs_raster_params* raster, void* ws, size_t ws_bytes, uint32_t* zkey, int32_t* rects,
+                             uint32_t* counts) {
+    if (!ctx) return BGS_ERR_INVALID_ARG;
+    int rc;
+    if ((rc = check_scene(ctx, scene)) || (rc = check_camera(ctx, cam, "camera")) || (rc = check_raster(ctx, raster)))
+        return rc;
+    if (!ws || !zkey || !rects || !counts) return fail(ctx, BGS_ERR_INVALID_ARG, "null buffer");
+    const int64_t kc = key_capacity_for(scene->n, cam->width, cam->height, ws_bytes);
+    if (kc < 0) return fail(ctx, BGS_ERR_WORKSPACE, "workspace too small");
+    const Layout L = make_layout(scene->n, cam->width, cam->height, kc);
+    const PreCam pc = make_precam(*cam);
+    const SceneArgs sa{scene->pos, scene->quat, scene->scale, scene->opacity, scene->sh, (int)scene->n,
+                       scene->sh_degree};
+    const int n = (int)scene->n;
+    HIP_CHECK(launch_preprocess(sa, pc, raster->alpha_min, raster->lowpass, MaskArgs{nullptr, 0}, at<SurfelRec>(ws, L.recs),
+                                zkey, at<uint2>(ws, L.rects), counts, ctx->stream),
+              "preprocess");
+    // Unpack the tile rectangles for the caller.
+    if (n > 0) {
+        std::vector<uint2> hr(n);
+        HIP_CHECK(hipMemcpyAsync(hr.data(), at<uint2>(ws, L.rects), 8 * (size_t)n, hipMemcpyDeviceToHost, ctx->stream),
+                  "rect readback");
+        HIP_CHECK(hipStreamSynchronize(ctx->stream), "sync");
+        std::vector<int32_t> out(4 * (size_t)n);
+        for (int k = 0; k < n; ++k) {
+            if (hr[k].x == 0xFFFFFFFFu) {
+                out[4 * k] = out[4 * k + 1] = out[4 * k + 2] = out[4 * k + 3] = -1;
+            } else {
+                out[4 * k] = (int32_t)(hr[k].x & 0xFFFF);
+                out[4 * k + 1] = (int32_t)(hr[k].x >> 16);
+                out[4 * k + 2] = (int32_t)(hr[k].y & 0xFFFF);
+                out[4 * k + 3] = (int32_t)(hr[k].y >> 16);
+            }
+        }
+        HIP_CHECK(hipMemcpyAsync(rects, out.data(), 16 * (size_t)n, hipMemcpyHostToDevice, ctx->stream), "rect copy");
+        HIP_CHECK(hipStreamSynchronize(ctx->stream), "sync");
+    }
+    return BGS_OK;
+}
+
+int32_t bgs_tile_lists_debug(bgs_ctx* ctx, const bgs_scene* scene, const bgs_camera* cam,
+                             const bgs_raster_params* raster, void* ws, size_t ws_bytes, uint32_t* ranges,
+                             uint32_t* values, int64_t values_capacity, int64_t* n_keys) {
+    if (!ctx) return BGS_ERR_INVALID_ARG;
+    int rc;
+    if ((rc = check_scene(ctx, scene)) || (rc = check_camera(ctx, cam, "camera")) || (rc = check_raster(ctx, raster)))
+        return rc;
+    if (!ws || !ranges || !values || !n_keys) return fail(ctx, BGS_ERR_INVALID_ARG, "null buffer");
+    const int64_t kc = key_capacity_for(scene->n, cam->width, cam->height, ws_bytes);
+    if (kc < 0) return fail(ctx, BGS_ERR_WORKSPACE, "workspace too small");
+    const Layout L = make_layout(scene->n, cam->width, cam->height, kc);
+    DevStatus* st = at<DevStatus>(ws, L.status);
+    HIP_CHECK(hipMemsetAsync(st, 0, sizeof(DevStatus), ctx->stream), "status reset");
+    // A render whose outputs go to scratch pixel buffers; the binning it
+    // leaves in the workspace is what is copied out.
+    const int64_t np = (int64_t)cam->width * cam->height;
+    float* scratch = at<float>(ws, L.rgb2);
+    rc = raster_pass(ctx, L, ws, kc, *scene, *cam, *raster, nullptr, 0.f,
+                     RasterOut{scratch, at<float>(ws, L.zbuf), at<float>(ws, L.zbuf) + np, nullptr}, 0);
+    if (rc) return rc;
+    DevStatus h{};
+    if ((rc = finish(ctx, ws, L, &h))) return rc;
+    *n_keys = h.n_keys_dom;
+    if (h.overflow & 1u) return fail(ctx, BGS_ERR_CAPACITY, "key capacity exceeded");
+    if ((int64_t)h.n_sort > values_capacity) return fail(ctx, BGS_ERR_CAPACITY, "values_capacity too small");
+    const PreCam pc = make_precam(*cam);
+    const int n_tiles = pc.tiles_x * pc.tiles_y;
+    const int passes = (tile_bits(n_tiles) + 7) / 8;
+    const uint32_t* svals = (passes % 2) ? at<uint32_t>(ws, L.tvals_b) : at<uint32_t>(ws, L.tvals_a);
+    HIP_CHECK(hipMemcpyAsync(ranges, at<uint2>(ws, L.ranges), 8 * (size_t)n_tiles, hipMemcpyDeviceToDevice, ctx->stream),
+              "copy");
+    if (h.n_sort)
+        HIP_CHECK(hipMemcpyAsync(values, svals, 4 * (size_t)h.n_sort, hipMemcpyDeviceToDevice, ctx->stream), "copy");
+    HIP_CHECK(hipStreamSynchronize(ctx->stream), "sync");
+    return BGS_OK;
+}
+
+}  // extern "C"

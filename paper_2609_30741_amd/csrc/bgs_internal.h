@@ -1,0 +1,165 @@
+// Internal declarations of the HIP library behind include/bgs.h.
+// gfx950 (CDNA4): wave64, 160 KiB LDS per CU, 256 CUs in 8 XCDs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "bgs.h"
+
+namespace bgs {
+
+constexpr int kTile = 16;            // rasteriser tile edge (pixels)
+constexpr int kRadixItems = 16;      // keys per thread in a radix block
+constexpr int kRadixBlock = 256 * kRadixItems;  // 4096 keys per block
+constexpr int kScanItems = 8;        // elements per thread in a scan block
+constexpr int kScanBlock = 256 * kScanItems;    // 2048 elements per block
+
+// Per-surfel record written by the preprocess and read (one record per
+// wave-uniform scalar load) by the blend kernel.  64 bytes.
+//   a = (mu_x, mu_y, C1, C2)    projected centre; u numerator coefficients
+//   b = (D1, D2, N1, N2)        v numerator; common denominator
+//   c = (lam_num, z_c, opacity, pixbox_lo)
+//   d = (r, g, b, pixbox_hi)
+// With dx = i - mu_x, dy = j - mu_y and den = 1 + N1 dx + N2 dy the
+// surfel-plane coordinates of pixel (i, j) are u = (C1 dx + C2 dy)/den,
+// v = (D1 dx + D2 dy)/den and the ray meets the plane at depth
+// lam_num/den (lam_num < 0 marks a surfel seen exactly edge-on).  The
+// pixel box (x0 | y0 << 16, x1 | y1 << 16) bounds every pixel the surfel
+// can reach.
+struct alignas(16) SurfelRec {
+    float4 a, b, c, d;
+};
+
+// Camera constants for the preprocess (fp64 geometry).
+struct PreCam {
+    double Rt[9];  // world-to-camera rotation R^T, row-major
+    double t[3];   // camera centre
+    double fx, fy, cx, cy;
+    double z_near;
+    float zc[4];   // fp32 centre-depth key coefficients (r20, r21, r22, tz)
+    int W, H, tiles_x, tiles_y;
+};
+
+struct SceneArgs {
+    const float* pos;
+    const float* quat;
+    const float* scale;
+    const float* opacity;
+    const float* sh;
+    int n;
+    int sh_degree;
+};
+
+// Optional ROI restriction of the binning: only tiles with mask = 1 are
+// emitted, under compact ids (row-major rank among masked tiles).
+// prefix[t] = number of masked tiles before tile t in row-major order
+// (n_tiles + 1 entries), so a tile's compact id is prefix[t] and the masked
+// tiles of row ty in columns [a, b] number prefix[ty*tx+b+1] - prefix[ty*tx+a].
+struct MaskArgs {
+    const uint32_t* prefix;
+    int enabled;
+};
+
+struct BlendArgs {
+    int W, H, tiles_x;
+    float alpha_min, alpha_max, t_min;
+    int lowpass;
+    float bg0, bg1, bg2;
+    float a_min;     // patch mode: depth proxy written only when A >= a_min
+    float z_near;
+    int patch;       // 0: write rgb/depth_raw/alpha; 1: write rgb/z/alpha/cls
+};
+
+// Device status block kept in the workspace.
+struct DevStatus {
+    uint32_t n_keys;       // keys of the last binning (may exceed capacity)
+    uint32_t n_sort;       // min(n_keys, capacity): keys actually sorted
+    uint32_t n_masked;     // masked tiles of the last ROI patch
+    uint32_t n_keys_dom;
+    uint32_t n_keys_roi;
+    uint32_t overflow;     // bit 0 key capacity, bit 1 box capacity
+    uint32_t n_holes, n_gap, n_center, n_rowfill, n_boxes, n_roi_tiles, n_edge, pad;
+    uint32_t dmin_bits, dmax_bits;  // depth-range reduction (positive fp32 bits)
+    uint32_t pad2[2];
+    unsigned long long pairs[4];  // evaluated, contributing (dominant), then ROI; counting mode only
+    int32_t edge_boxes[4 * 6];
+    int32_t widths[4];
+};
+
+// ---- scan / sort (sort.hip) -------------------------------------------------
+size_t scan_tmp_elems(int64_t n);
+// out[i] = sum_{j < i} in[idx ? idx[j] : j] for i = 0..n, with n = *n_dev when
+// n_dev is given (at most n_cap), else n_cap.  Elements past n count as 0.
+hipError_t exclusive_scan(const uint32_t* in, const uint32_t* idx, uint32_t* out, const uint32_t* n_dev,
+                          int64_t n_cap, uint32_t* tmp, hipStream_t s);
+size_t radix_tmp_bytes(int64_t n_cap);
+// Stable LSD radix sort of (keys, values) by bits [0, key_bits) with 8-bit
+// digits.  (ka, va) is the input, (kb, vb) the ping-pong buffer (all four
+// are real buffers); iota = true ignores the input values and uses the
+// input positions instead.  The element count is *n_dev (<= n_cap), or
+// n_cap when n_dev is null.
+// Returns in *in_b whether the result is in (kb, vb).
+hipError_t radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, const uint32_t* n_dev,
+                      int64_t n_cap, int key_bits, bool iota, void* tmp, hipStream_t s, bool* in_b);
+
+// ---- rasteriser (raster.hip) --------------------------------------------------
+hipError_t launch_preprocess(const SceneArgs& sc, const PreCam& cam, float alpha_min, int lowpass,
+                             const MaskArgs& mask, SurfelRec* recs, uint32_t* zkeys, uint2* rects,
+                             uint32_t* counts, hipStream_t s);
+hipError_t launch_emit(const uint32_t* order, const uint32_t* offs, const uint2* rects, int n, int tiles_x,
+                       const MaskArgs& mask, uint32_t cap, uint32_t* tkeys, uint32_t* tvals, hipStream_t s);
+hipError_t launch_ranges(const uint32_t* tkeys, const uint32_t* n_dev, int64_t cap, uint2* ranges,
+                         int n_tiles, hipStream_t s);
+// Dispatch order of the (compact) tiles for the blend, heaviest first.
+hipError_t launch_tile_order(const uint2* ranges, const uint32_t* n_live, int n_tiles, uint32_t* order,
+                             hipStream_t s);
+// One block per (compact) tile, in `order`; n_live (device, optional) limits
+// the blocks that do work when the tile count is only known on the device.
+// pair_counts (optional): {evaluated, contributing} pair counters.
+hipError_t launch_blend(const SurfelRec* recs, const uint32_t* vals, const uint2* ranges,
+                        const uint32_t* tile_list, const uint32_t* order, const uint32_t* n_live, int n_blocks,
+                        const BlendArgs& a, float* rgb, float* d_or_z, float* alpha, uint8_t* cls,
+                        unsigned long long* pair_counts, hipStream_t s);
+// prefix[n_tiles + 1] and the compact list of masked tile ids; tmp32 holds
+// n_tiles words, scan_tmp scan_tmp_elems(n_tiles) words.
+hipError_t launch_mask_prefix(const uint8_t* tile_mask, int n_tiles, uint32_t* tmp32, uint32_t* prefix,
+                              uint32_t* tile_list, uint32_t* scan_tmp, DevStatus* st, hipStream_t s);
+// Record the key count offs[n] of a binning (which: 0 dominant, 1 ROI).
+hipError_t launch_status_keys(const uint32_t* offs, int n, DevStatus* st, uint32_t cap, int which,
+                              hipStream_t s);
+
+// ---- reprojection and classification (warp.hip, no fp contraction) -------
+struct WarpCam {
+    int W, H;
+    double fx, fy, cx, cy, z_near, z_far;
+};
+struct RelPose {
+    double M[9], c[3];
+};
+RelPose rel_pose(const bgs_camera& src, const bgs_camera& dst);
+
+hipError_t launch_reproject(const WarpCam& src, const WarpCam& dst, const RelPose& P, float a_min,
+                            const float* rgb, const float* draw, const float* alpha, unsigned long long* zbuf,
+                            float* rgb_dst, float* z_dst, float* alpha_dst, uint8_t* hole, float* depth_range,
+                            DevStatus* st, hipStream_t s);
+struct ClassifyBufs {
+    float* rgb2;
+    float* z2;
+    float* a2;
+    uint8_t* hole;
+    uint8_t* hole2;
+    uint32_t* flags;   // root flags -> slots (exclusive scan), n + 1
+    int32_t* bbox;     // 4 per component
+    uint32_t* scan_tmp;
+};
+hipError_t launch_classify(const WarpCam& src, const WarpCam& dst, const RelPose& P, const bgs_roi_params& roi,
+                           const float bg[3], const float* depth_range, float* rgb, float* z, float* alpha,
+                           uint8_t* cls, int32_t* labels, bgs_box* boxes, int32_t box_cap, int32_t* n_boxes,
+                           uint8_t* tile_mask, const ClassifyBufs& b, DevStatus* st, hipStream_t s);
+hipError_t launch_label_components(const uint8_t* mask, int W, int H, int conn, int32_t* labels,
+                                   hipStream_t s);
+
+}  // namespace bgs

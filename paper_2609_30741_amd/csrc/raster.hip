@@ -1,0 +1,546 @@
+// 2DGS tile rasteriser for gfx950: per-surfel preprocess, load-balanced
+// (surfel, tile) key emission, tile ranges and front-to-back blending with
+// the joint depth proxy (Sec. 3.1 Stage 1, Sec. 3.3 Eq. 1-2).
+#include <cmath>
+
+#include "bgs_internal.h"
+
+namespace bgs {
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Preprocess: one thread per surfel.
+// ---------------------------------------------------------------------------
+
+// Compositing-order key: fp32 centre depth with one fixed operation order,
+// ((r20*px + r21*py) + r22*pz) + tz, every operation rounded separately.
+__device__ inline float centre_depth_key(const float zc[4], float px, float py, float pz) {
+#pragma clang fp contract(off)
+    float a = zc[0] * px;
+    float b = zc[1] * py;
+    float s = a + b;
+    float c = zc[2] * pz;
+    s = s + c;
+    return s + zc[3];
+}
+
+// Real spherical harmonics (Condon-Shortley phase) in Cartesian form for a
+// unit direction; the constants are sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!)
+// (times sqrt(2) for m != 0) folded with the polynomial normalisation.
+__device__ inline void sh_basis(int deg, float x, float y, float z, float* Y) {
+    Y[0] = 0.28209479177387814f;
+    if (deg < 1) return;
+    const float c1 = 0.4886025119029199f;
+    Y[1] = -c1 * y;
+    Y[2] = c1 * z;
+    Y[3] = -c1 * x;
+    if (deg < 2) return;
+    const float xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = 1.0925484305920792f * x * y;
+    Y[5] = -1.0925484305920792f * y * z;
+    Y[6] = 0.31539156525252005f * (2.f * zz - xx - yy);
+    Y[7] = -1.0925484305920792f * x * z;
+    Y[8] = 0.5462742152960396f * (xx - yy);
+    if (deg < 3) return;
+    Y[9] = -0.5900435899266435f * y * (3.f * xx - yy);
+    Y[10] = 2.890611442640554f * x * y * z;
+    Y[11] = -0.4570457994644658f * y * (4.f * zz - xx - yy);
+    Y[12] = 0.3731763325901154f * z * (2.f * zz - 3.f * xx - 3.f * yy);
+    Y[13] = -0.4570457994644658f * x * (4.f * zz - xx - yy);
+    Y[14] = 1.445305721320277f * z * (xx - yy);
+    Y[15] = -0.5900435899266435f * x * (xx - 3.f * yy);
+}
+
+__device__ inline uint32_t masked_count(const MaskArgs& m, int tiles_x, int tx0, int ty0, int tx1, int ty1) {
+    uint32_t c = 0;
+    for (int ty = ty0; ty <= ty1; ++ty) {
+        const uint32_t* row = m.prefix + (int64_t)ty * tiles_x;
+        c += row[tx1 + 1] - row[tx0];
+    }
+    return c;
+}
+
+__global__ __launch_bounds__(256) void k_preprocess(SceneArgs sc, PreCam cam, float alpha_min, int lowpass,
+                                                    MaskArgs mask, SurfelRec* __restrict__ recs,
+                                                    uint32_t* __restrict__ zkeys, uint2* __restrict__ rects,
+                                                    uint32_t* __restrict__ counts) {
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= sc.n) return;
+    const int n = sc.n;
+    const float px = sc.pos[k], py = sc.pos[n + k], pz = sc.pos[2 * n + k];
+    const float zf = centre_depth_key(cam.zc, px, py, pz);
+    const float op = sc.opacity[k];
+    const uint2 empty = make_uint2(0xFFFFFFFFu, 0u);
+    if (!((double)zf > cam.z_near)) {
+        zkeys[k] = 0xFFFFFFFFu;
+        counts[k] = 0;
+        rects[k] = empty;
+        return;
+    }
+    zkeys[k] = __float_as_uint(zf);
+    if (!(op >= alpha_min)) {  // alpha = min(0.99, o G) <= o can never reach alpha_min
+        counts[k] = 0;
+        rects[k] = empty;
+        return;
+    }
+    // ---- geometry in fp64 ----
+    const double d0 = (double)px - cam.t[0], d1 = (double)py - cam.t[1], d2 = (double)pz - cam.t[2];
+    double pc[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) pc[r] = cam.Rt[r * 3 + 0] * d0 + cam.Rt[r * 3 + 1] * d1 + cam.Rt[r * 3 + 2] * d2;
+    double qw = sc.quat[k], qx = sc.quat[n + k], qy = sc.quat[2 * n + k], qz = sc.quat[3 * n + k];
+    const double qn = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+    qw *= qn; qx *= qn; qy *= qn; qz *= qn;
+    // Columns t_u, t_v of the quaternion's rotation matrix (Sec. 3.3).
+    const double tu[3] = {1.0 - 2.0 * (qy * qy + qz * qz), 2.0 * (qx * qy + qw * qz), 2.0 * (qx * qz - qw * qy)};
+    const double tv[3] = {2.0 * (qx * qy - qw * qz), 1.0 - 2.0 * (qx * qx + qz * qz), 2.0 * (qy * qz + qw * qx)};
+    double a[3], b[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        a[r] = cam.Rt[r * 3 + 0] * tu[0] + cam.Rt[r * 3 + 1] * tu[1] + cam.Rt[r * 3 + 2] * tu[2];
+        b[r] = cam.Rt[r * 3 + 0] * tv[0] + cam.Rt[r * 3 + 1] * tv[1] + cam.Rt[r * 3 + 2] * tv[2];
+    }
+    const double nv[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+    const double su = sc.scale[k], sv = sc.scale[n + k];
+    const double pzc = pc[2];
+    const double mux = cam.fx * pc[0] / pzc + cam.cx;
+    const double muy = cam.fy * pc[1] / pzc + cam.cy;
+
+    // ---- conservative pixel bounds of {alpha >= alpha_min} ----
+    // Surfel term: the disc u^2+v^2 <= 2 ln(o/alpha_min) of the surfel plane;
+    // its outline E(t) = p + cos t A + sin t B projects to a conic whose
+    // dual is A A^T + B B^T - p p^T, giving the extreme tangent lines
+    // directly.  If the disc reaches z <= 0 the bound is the whole screen.
+    const double lr = log((double)op / (double)alpha_min);
+    const double rho = sqrt(2.0 * lr) * (1.0 + 1e-5);
+    double xmin = INFINITY, xmax = -INFINITY, ymin = INFINITY, ymax = -INFINITY;
+    {
+        const double A[3] = {rho * su * a[0], rho * su * a[1], rho * su * a[2]};
+        const double B[3] = {rho * sv * b[0], rho * sv * b[1], rho * sv * b[2]};
+        const double zr2 = A[2] * A[2] + B[2] * B[2];
+        if (pzc > 0.0 && pzc * pzc > zr2 * (1.0 + 1e-6) + 1e-12) {
+            const double c22 = zr2 - pzc * pzc;
+            const double c00 = A[0] * A[0] + B[0] * B[0] - pc[0] * pc[0];
+            const double c02 = A[0] * A[2] + B[0] * B[2] - pc[0] * pzc;
+            const double c11 = A[1] * A[1] + B[1] * B[1] - pc[1] * pc[1];
+            const double c12 = A[1] * A[2] + B[1] * B[2] - pc[1] * pzc;
+            const double dx = sqrt(fmax(c02 * c02 - c00 * c22, 0.0));
+            const double dy = sqrt(fmax(c12 * c12 - c11 * c22, 0.0));
+            const double kx0 = (c02 - dx) / c22, kx1 = (c02 + dx) / c22;
+            const double ky0 = (c12 - dy) / c22, ky1 = (c12 + dy) / c22;
+            xmin = cam.fx * fmin(kx0, kx1) + cam.cx;
+            xmax = cam.fx * fmax(kx0, kx1) + cam.cx;
+            ymin = cam.fy * fmin(ky0, ky1) + cam.cy;
+            ymax = cam.fy * fmax(ky0, ky1) + cam.cy;
+        } else {
+            xmin = -INFINITY;
+            xmax = INFINITY;
+            ymin = -INFINITY;
+            ymax = INFINITY;
+        }
+    }
+    // Low-pass term: exp(-|x - mu|^2) >= alpha_min / o on a disc around mu.
+    if (lowpass) {
+        const double r2 = sqrt(lr) * (1.0 + 1e-5);
+        xmin = fmin(xmin, mux - r2);
+        xmax = fmax(xmax, mux + r2);
+        ymin = fmin(ymin, muy - r2);
+        ymax = fmax(ymax, muy + r2);
+    }
+    const double padx = 0.02 + 1e-7 * (fabs(xmin) + fabs(xmax));
+    const double pady = 0.02 + 1e-7 * (fabs(ymin) + fabs(ymax));
+    const double fx0 = fmax(ceil(xmin - padx), 0.0), fx1 = fmin(floor(xmax + padx), (double)(cam.W - 1));
+    const double fy0 = fmax(ceil(ymin - pady), 0.0), fy1 = fmin(floor(ymax + pady), (double)(cam.H - 1));
+    if (!(fx0 <= fx1 && fy0 <= fy1)) {
+        counts[k] = 0;
+        rects[k] = empty;
+        return;
+    }
+    const int x0 = (int)fx0, x1 = (int)fx1, y0 = (int)fy0, y1 = (int)fy1;
+    const int tx0 = x0 / kTile, tx1 = x1 / kTile, ty0 = y0 / kTile, ty1 = y1 / kTile;
+    const uint32_t cnt = mask.enabled ? masked_count(mask, cam.tiles_x, tx0, ty0, tx1, ty1)
+                                      : (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
+    counts[k] = cnt;
+    rects[k] = make_uint2((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tx1 | ((uint32_t)ty1 << 16));
+    if (cnt == 0) return;
+
+    // ---- colour: SH towards the surfel from this camera's centre ----
+    float col[3];
+    {
+        float dirx = (float)((double)px - cam.t[0]), diry = (float)((double)py - cam.t[1]),
+              dirz = (float)((double)pz - cam.t[2]);
+        const float inv = rsqrtf(dirx * dirx + diry * diry + dirz * dirz);
+        dirx *= inv; diry *= inv; dirz *= inv;
+        float Y[16];
+        sh_basis(sc.sh_degree, dirx, diry, dirz, Y);
+        const int nc = (sc.sh_degree + 1) * (sc.sh_degree + 1);
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            float acc = 0.f;
+            for (int c = 0; c < nc; ++c) acc += Y[c] * sc.sh[(int64_t)(c * 3 + ch) * n + k];
+            col[ch] = fmaxf(acc + 0.5f, 0.f);
+        }
+    }
+
+    // ---- plane-to-screen homography centred at the projected centre ----
+    // With r_c = p/p_z and delta = ((i-mu_x)/fx, (j-mu_y)/fy, 0) the pixel
+    // ray is r = r_c + delta; the plane n.X = n.p meets it at
+    // lambda = p_z / (1 + n.delta / n.r_c), and the in-plane coordinates
+    // u = (lambda r - p).t_u / s_u, v likewise, reduce to ratios of linear
+    // forms in (dx, dy): the form stays well conditioned near the centre.
+    float C1 = 0.f, C2 = 0.f, D1 = 0.f, D2 = 0.f, N1 = 0.f, N2 = 0.f, lam_num = -1.f;
+    {
+        const double np = nv[0] * pc[0] + nv[1] * pc[1] + nv[2] * pc[2];
+        const double nn = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+        const double pn = sqrt(pc[0] * pc[0] + pc[1] * pc[1] + pc[2] * pc[2]);
+        if (fabs(np) > 1e-12 * nn * pn) {
+            const double nrc = np / pzc;
+            const double as[3] = {a[0] / su, a[1] / su, a[2] / su};
+            const double bs[3] = {b[0] / sv, b[1] / sv, b[2] / sv};
+            const double pa = pc[0] * as[0] + pc[1] * as[1] + pc[2] * as[2];
+            const double pb = pc[0] * bs[0] + pc[1] * bs[1] + pc[2] * bs[2];
+            const double n1 = nv[0] / (cam.fx * nrc), n2 = nv[1] / (cam.fy * nrc);
+            C1 = (float)(pzc * as[0] / cam.fx - n1 * pa);
+            C2 = (float)(pzc * as[1] / cam.fy - n2 * pa);
+            D1 = (float)(pzc * bs[0] / cam.fx - n1 * pb);
+            D2 = (float)(pzc * bs[1] / cam.fy - n2 * pb);
+            N1 = (float)n1;
+            N2 = (float)n2;
+            lam_num = (float)pzc;
+        }
+    }
+    SurfelRec rec;
+    rec.a = make_float4((float)mux, (float)muy, C1, C2);
+    rec.b = make_float4(D1, D2, N1, N2);
+    rec.c = make_float4(lam_num, (float)pzc, op, __uint_as_float((uint32_t)x0 | ((uint32_t)y0 << 16)));
+    rec.d = make_float4(col[0], col[1], col[2], __uint_as_float((uint32_t)x1 | ((uint32_t)y1 << 16)));
+    recs[k] = rec;
+}
+
+// ---------------------------------------------------------------------------
+// Key emission: one block per 256 consecutive surfels in compositing order;
+// output positions are spread evenly over the block's threads (each finds
+// its surfel by binary search over the block's offsets), so a surfel that
+// covers the whole screen does not serialise one thread.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order, const uint32_t* __restrict__ offs,
+                                              const uint2* __restrict__ rects, int n, int tiles_x, MaskArgs mask,
+                                              uint32_t cap, uint32_t* __restrict__ tkeys,
+                                              uint32_t* __restrict__ tvals) {
+    __shared__ uint32_t loc[257];
+    __shared__ uint32_t sk[256];
+    __shared__ uint2 srect[256];
+    const int r0 = blockIdx.x * 256;
+    const int m = min(256, n - r0);
+    const uint32_t base = offs[r0];
+    if ((int)threadIdx.x < m) {
+        const uint32_t k = order[r0 + threadIdx.x];
+        sk[threadIdx.x] = k;
+        srect[threadIdx.x] = rects[k];
+        loc[threadIdx.x] = offs[r0 + threadIdx.x] - base;
+    }
+    if (threadIdx.x == 0) loc[m] = offs[r0 + m] - base;
+    __syncthreads();
+    const uint32_t total = loc[m];
+    for (uint32_t p = threadIdx.x; p < total; p += 256) {
+        // Last l with loc[l] <= p (that surfel has a non-empty range).
+        int lo = 0, hi = m - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (loc[mid] <= p) lo = mid;
+            else hi = mid - 1;
+        }
+        uint32_t local = p - loc[lo];
+        const uint2 rc = srect[lo];
+        const int tx0 = rc.x & 0xFFFF, ty0 = rc.x >> 16, tx1 = rc.y & 0xFFFF, ty1 = rc.y >> 16;
+        uint32_t tile;
+        if (!mask.enabled) {
+            const uint32_t w = (uint32_t)(tx1 - tx0 + 1);
+            tile = (uint32_t)(ty0 + (int)(local / w)) * (uint32_t)tiles_x + (uint32_t)tx0 + local % w;
+        } else {
+            tile = 0xFFFFFFFFu;
+            for (int ty = ty0; ty <= ty1; ++ty) {
+                const uint32_t* row = mask.prefix + (int64_t)ty * tiles_x;
+                const uint32_t first = row[tx0];
+                const uint32_t c = row[tx1 + 1] - first;
+                if (local < c) {
+                    tile = first + local;  // compact id: masked tiles before it
+                    break;
+                }
+                local -= c;
+            }
+        }
+        const uint32_t g = base + p;
+        if (g < cap) {
+            tkeys[g] = tile;
+            tvals[g] = sk[lo];
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_dev,
+                                                uint2* __restrict__ ranges, uint32_t n_tiles) {
+    const uint32_t n = *n_dev;
+    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t t = keys[i];
+    if (t >= n_tiles) return;
+    if (i == 0 || keys[i - 1] != t) ranges[t].x = i;
+    if (i == n - 1 || keys[i + 1] != t) ranges[t].y = i + 1;
+}
+
+__global__ void k_status_keys(const uint32_t* __restrict__ offs, int n, DevStatus* st, uint32_t cap, int which) {
+    const uint32_t K = offs[n];
+    st->n_keys = K;
+    st->n_sort = K < cap ? K : cap;
+    if (K > cap) st->overflow |= 1u;
+    if (which == 0) st->n_keys_dom = K;
+    else st->n_keys_roi = K;
+}
+
+__global__ __launch_bounds__(256) void k_mask_u32(const uint8_t* __restrict__ m, int n, uint32_t* __restrict__ o) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) o[i] = m[i] ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(256) void k_mask_list(const uint8_t* __restrict__ m, int n,
+                                                   const uint32_t* __restrict__ prefix, uint32_t* __restrict__ list,
+                                                   DevStatus* st) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n && m[i]) list[prefix[i]] = (uint32_t)i;
+    if (i == 0) {
+        st->n_masked = prefix[n];
+        st->n_roi_tiles = prefix[n];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tile order for the blend: tiles by decreasing key count in log2 buckets,
+// so that the heaviest tiles are dispatched first and spread over all CUs.
+// The order only decides which block renders which tile; every tile's
+// pixels are computed the same way whatever the order.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_tile_order(const uint2* __restrict__ ranges, const uint32_t* n_live,
+                                                     uint32_t n_tiles, uint32_t* __restrict__ order) {
+    __shared__ uint32_t hist[33];
+    const uint32_t n = n_live ? min(*n_live, n_tiles) : n_tiles;
+    if (threadIdx.x < 33) hist[threadIdx.x] = 0;
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < n; t += 1024) {
+        const uint2 r = ranges[t];
+        const uint32_t key = (uint32_t)__clz((int)(r.y - r.x));  // 32 for an empty tile; small = heavy
+        atomicAdd(&hist[key], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int b = 0; b < 33; ++b) {
+            uint32_t c = hist[b];
+            hist[b] = acc;
+            acc += c;
+        }
+    }
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < n; t += 1024) {
+        const uint2 r = ranges[t];
+        const uint32_t key = (uint32_t)__clz((int)(r.y - r.x));
+        order[atomicAdd(&hist[key], 1u)] = t;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Blend: one 256-thread block per 16x16 tile; wave w owns the 16x4 strip of
+// rows 4w..4w+3.  The tile's sorted list is consumed in batches of 256
+// records: every thread fetches one record with vector loads (the next
+// batch is fetched while the current one is composited), the batch is put
+// in LDS, and each wave walks it with broadcast LDS reads, skipping records
+// whose pixel box misses its strip.  A wave stops compositing once all its
+// pixels are done; the block stops at the first batch boundary where all
+// 256 pixels are done.
+// ---------------------------------------------------------------------------
+template <bool kCount>
+__global__ __launch_bounds__(256) void k_blend(const SurfelRec* __restrict__ recs, const uint32_t* __restrict__ vals,
+                                               const uint2* __restrict__ ranges, const uint32_t* __restrict__ tile_list,
+                                               const uint32_t* __restrict__ order,
+                                               const uint32_t* __restrict__ n_live, BlendArgs a,
+                                               float* __restrict__ rgb, float* __restrict__ dz,
+                                               float* __restrict__ alpha, uint8_t* __restrict__ cls,
+                                               unsigned long long* __restrict__ pair_counts) {
+    __shared__ float4 s_rec[256 * 4];
+    const uint32_t blk = blockIdx.x;
+    if (n_live && blk >= *n_live) return;
+    const uint32_t cid = order ? order[blk] : blk;
+    const uint32_t tile = tile_list ? tile_list[cid] : cid;
+    const int tx = (int)(tile % (uint32_t)a.tiles_x), ty = (int)(tile / (uint32_t)a.tiles_x);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int px = tx * kTile + (lane & 15);
+    const int py = ty * kTile + wave * 4 + (lane >> 4);
+    const bool inside = px < a.W && py < a.H;
+    const float fpx = (float)px, fpy = (float)py;
+    const int sx0 = tx * kTile, sx1 = sx0 + kTile - 1, sy0 = ty * kTile + wave * 4, sy1 = sy0 + 3;
+    const uint2 rg = ranges[cid];
+    float T = 1.f, c0 = 0.f, c1 = 0.f, c2 = 0.f, D = 0.f, A = 0.f;
+    bool live = inside;
+    uint32_t n_eval = 0, n_used = 0;
+
+    float4 q0, q1, q2, q3;
+    {
+        const uint32_t pos = rg.x + tid;
+        if (pos < rg.y) {
+            const SurfelRec* r = recs + vals[pos];
+            q0 = r->a; q1 = r->b; q2 = r->c; q3 = r->d;
+        }
+    }
+    for (uint32_t base = rg.x; base < rg.y; base += 256) {
+        const uint32_t nb = min(256u, rg.y - base);
+        __syncthreads();
+        if ((uint32_t)tid < nb) {
+            s_rec[4 * tid + 0] = q0;
+            s_rec[4 * tid + 1] = q1;
+            s_rec[4 * tid + 2] = q2;
+            s_rec[4 * tid + 3] = q3;
+        }
+        __syncthreads();
+        {
+            const uint32_t pos = base + 256 + tid;
+            if (pos < rg.y) {
+                const SurfelRec* r = recs + vals[pos];
+                q0 = r->a; q1 = r->b; q2 = r->c; q3 = r->d;
+            }
+        }
+        for (uint32_t j = 0; j < nb; ++j) {
+            if (__ballot(live) == 0ull) break;
+            const float4 ra = s_rec[4 * j + 2];
+            const uint32_t lo = __builtin_amdgcn_readfirstlane(__float_as_uint(ra.w));
+            const float4 rd = s_rec[4 * j + 3];
+            const uint32_t hi = __builtin_amdgcn_readfirstlane(__float_as_uint(rd.w));
+            if ((int)(hi & 0xFFFF) < sx0 || (int)(lo & 0xFFFF) > sx1 || (int)(hi >> 16) < sy0 ||
+                (int)(lo >> 16) > sy1)
+                continue;
+            const float4 r0 = s_rec[4 * j + 0];
+            const float4 r1 = s_rec[4 * j + 1];
+            if (live) {
+                if (kCount) ++n_eval;
+                const float dx = fpx - r0.x, dy = fpy - r0.y;
+                const float den = fmaf(r1.z, dx, fmaf(r1.w, dy, 1.f));
+                const float w = __builtin_amdgcn_rcpf(den);
+                const float u = fmaf(r0.z, dx, r0.w * dy) * w;
+                const float v = fmaf(r1.x, dx, r1.y * dy) * w;
+                const float lam = ra.x * w;
+                const bool ok3 = lam > a.z_near && lam < 3.0e38f;
+                const float e3 = ok3 ? -0.5f * fmaf(u, u, v * v) : -INFINITY;
+                const float e2 = a.lowpass ? -fmaf(dx, dx, dy * dy) : -INFINITY;
+                const float e = fmaxf(e3, e2);
+                const float al = fminf(a.alpha_max, ra.z * __expf(e));
+                if (al >= a.alpha_min) {
+                    const float Tn = T * (1.f - al);
+                    if (Tn < a.t_min) {
+                        live = false;
+                    } else {
+                        const float wt = al * T;
+                        if (kCount) ++n_used;
+                        c0 = fmaf(wt, rd.x, c0);
+                        c1 = fmaf(wt, rd.y, c1);
+                        c2 = fmaf(wt, rd.z, c2);
+                        D = fmaf(wt, (e3 >= e2) ? lam : ra.y, D);
+                        A += wt;
+                        T = Tn;
+                    }
+                }
+            }
+        }
+        if (__syncthreads_count(live) == 0) break;
+    }
+    if (kCount) {
+        unsigned long long e = n_eval, u = n_used;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            e += __shfl_xor(e, off, 64);
+            u += __shfl_xor(u, off, 64);
+        }
+        if (lane == 0) {
+            atomicAdd(&pair_counts[0], e);
+            atomicAdd(&pair_counts[1], u);
+        }
+    }
+    if (!inside) return;
+    const int64_t hw = (int64_t)a.W * a.H;
+    const int64_t p = (int64_t)py * a.W + px;
+    rgb[p] = fmaf(T, a.bg0, c0);
+    rgb[hw + p] = fmaf(T, a.bg1, c1);
+    rgb[2 * hw + p] = fmaf(T, a.bg2, c2);
+    alpha[p] = A;
+    if (!a.patch) {
+        dz[p] = D;
+    } else {
+        dz[p] = A >= a.a_min ? D / A : INFINITY;
+        cls[p] = (uint8_t)BGS_CLS_ROI;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_preprocess(const SceneArgs& sc, const PreCam& cam, float alpha_min, int lowpass,
+                             const MaskArgs& mask, SurfelRec* recs, uint32_t* zkeys, uint2* rects,
+                             uint32_t* counts, hipStream_t s) {
+    if (sc.n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_preprocess, dim3((sc.n + 255) / 256), dim3(256), 0, s, sc, cam, alpha_min, lowpass, mask,
+                       recs, zkeys, rects, counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_emit(const uint32_t* order, const uint32_t* offs, const uint2* rects, int n, int tiles_x,
+                       const MaskArgs& mask, uint32_t cap, uint32_t* tkeys, uint32_t* tvals, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_emit, dim3((n + 255) / 256), dim3(256), 0, s, order, offs, rects, n, tiles_x, mask, cap,
+                       tkeys, tvals);
+    return hipGetLastError();
+}
+
+hipError_t launch_ranges(const uint32_t* tkeys, const uint32_t* n_dev, int64_t cap, uint2* ranges, int n_tiles,
+                         hipStream_t s) {
+    hipError_t e = hipMemsetAsync(ranges, 0, sizeof(uint2) * (size_t)n_tiles, s);
+    if (e != hipSuccess) return e;
+    if (cap <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ranges, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, tkeys, n_dev, ranges,
+                       (uint32_t)n_tiles);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_order(const uint2* ranges, const uint32_t* n_live, int n_tiles, uint32_t* order,
+                             hipStream_t s) {
+    if (n_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tile_order, dim3(1), dim3(1024), 0, s, ranges, n_live, (uint32_t)n_tiles, order);
+    return hipGetLastError();
+}
+
+hipError_t launch_blend(const SurfelRec* recs, const uint32_t* vals, const uint2* ranges, const uint32_t* tile_list,
+                        const uint32_t* order, const uint32_t* n_live, int n_blocks, const BlendArgs& a, float* rgb,
+                        float* d_or_z, float* alpha, uint8_t* cls, unsigned long long* pair_counts, hipStream_t s) {
+    if (n_blocks <= 0) return hipSuccess;
+    if (pair_counts)
+        hipLaunchKernelGGL(k_blend<true>, dim3(n_blocks), dim3(256), 0, s, recs, vals, ranges, tile_list, order, n_live,
+                           a, rgb, d_or_z, alpha, cls, pair_counts);
+    else
+        hipLaunchKernelGGL(k_blend<false>, dim3(n_blocks), dim3(256), 0, s, recs, vals, ranges, tile_list, order,
+                           n_live, a, rgb, d_or_z, alpha, cls, pair_counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_mask_prefix(const uint8_t* tile_mask, int n_tiles, uint32_t* tmp32, uint32_t* prefix,
+                              uint32_t* tile_list, uint32_t* scan_tmp, DevStatus* st, hipStream_t s) {
+    const unsigned g = (unsigned)((n_tiles + 255) / 256);
+    hipLaunchKernelGGL(k_mask_u32, dim3(g), dim3(256), 0, s, tile_mask, n_tiles, tmp32);
+    hipError_t e = exclusive_scan(tmp32, nullptr, prefix, nullptr, n_tiles, scan_tmp, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mask_list, dim3(g), dim3(256), 0, s, tile_mask, n_tiles, prefix, tile_list, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_status_keys(const uint32_t* offs, int n, DevStatus* st, uint32_t cap, int which, hipStream_t s) {
+    hipLaunchKernelGGL(k_status_keys, dim3(1), dim3(1), 0, s, offs, n, st, cap, which);
+    return hipGetLastError();
+}
+
+}  // namespace bgs

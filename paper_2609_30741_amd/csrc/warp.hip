@@ -1,0 +1,752 @@
+// Reprojection (Sec. 3.4, Eq. 3-5) and hole classification (Sec. 3.1
+// Stage 3, Sec. 3.5 Steps 1-2) for gfx950.
+//
+// This file is compiled without floating-point contraction: the fp64
+// reprojection, the Eq. 6-8 extrema and the fp32 interpolation sums are
+// evaluated operation by operation in a fixed order, so that their integer
+// outcomes (target pixels, hole masks, widths, labels, boxes) are exactly
+// reproducible.
+#include <cfloat>
+#include <climits>
+
+#include "bgs_internal.h"
+
+namespace bgs {
+
+RelPose rel_pose(const bgs_camera& src, const bgs_camera& dst) {
+    RelPose P;
+    for (int r = 0; r < 3; ++r)
+        for (int q = 0; q < 3; ++q) {
+            double p0 = dst.R[0 * 3 + r] * src.R[0 * 3 + q];
+            double p1 = dst.R[1 * 3 + r] * src.R[1 * 3 + q];
+            double p2 = dst.R[2 * 3 + r] * src.R[2 * 3 + q];
+            P.M[r * 3 + q] = (p0 + p1) + p2;
+        }
+    double d0 = src.t[0] - dst.t[0], d1 = src.t[1] - dst.t[1], d2 = src.t[2] - dst.t[2];
+    for (int r = 0; r < 3; ++r) {
+        double p0 = dst.R[0 * 3 + r] * d0;
+        double p1 = dst.R[1 * 3 + r] * d1;
+        double p2 = dst.R[2 * 3 + r] * d2;
+        P.c[r] = (p0 + p1) + p2;
+    }
+    return P;
+}
+
+namespace {
+
+// X' = M X (+ c): a source-frame point in the destination frame.
+__device__ inline void map_point(const RelPose& P, bool with_t, double X, double Y, double Z, double out[3]) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        double p0 = P.M[r * 3 + 0] * X;
+        double p1 = P.M[r * 3 + 1] * Y;
+        double p2 = P.M[r * 3 + 2] * Z;
+        double s = (p0 + p1) + p2;
+        out[r] = with_t ? s + P.c[r] : s;
+    }
+}
+
+// Pinhole projection (Eq. 3) in pixels, unrounded.
+__device__ inline void project(const WarpCam& c, const double X[3], double* u, double* v) {
+    double qx = X[0] / X[2];
+    double qy = X[1] / X[2];
+    double sx = c.fx * qx;
+    double sy = c.fy * qy;
+    *u = sx + c.cx;
+    *v = sy + c.cy;
+}
+
+__device__ inline uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, off, 64));
+    return v;
+}
+__device__ inline uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off, 64));
+    return v;
+}
+__device__ inline uint32_t wave_sum_u32(uint32_t v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += (uint32_t)__shfl_xor((int)v, off, 64);
+    return v;
+}
+
+__global__ void k_warp_reset(DevStatus* st) {
+    st->n_holes = 0;
+    st->n_gap = 0;
+    st->n_center = 0;
+    st->n_rowfill = 0;
+    st->n_boxes = 0;
+    st->n_edge = 0;
+    st->dmin_bits = 0xFFFFFFFFu;
+    st->dmax_bits = 0u;
+    st->overflow &= ~2u;
+}
+
+__global__ __launch_bounds__(256) void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// Forward splat of every source pixel into the destination z-buffer.
+__global__ __launch_bounds__(256) void k_reproject_scatter(WarpCam src, WarpCam dst, RelPose P, float a_min,
+                                                           const float* __restrict__ draw,
+                                                           const float* __restrict__ alpha,
+                                                           unsigned long long* __restrict__ zbuf, DevStatus* st) {
+    const int64_t ns = (int64_t)src.W * src.H;
+    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    uint32_t dmin = 0xFFFFFFFFu, dmax = 0u;
+    if (s < ns) {
+        const int64_t i = s % src.W, j = s / src.W;
+        const double xn = ((double)i - src.cx) / src.fx;
+        const double yn = ((double)j - src.cy) / src.fy;
+        const float A = alpha[s];
+        double Xp[3];
+        bool ok;
+        float zf;
+        if (A >= a_min) {
+            const float df = draw[s] / A;
+            dmin = __float_as_uint(df);
+            dmax = dmin;
+            const double d = (double)df;
+            map_point(P, true, d * xn, d * yn, d, Xp);
+            ok = Xp[2] > dst.z_near;
+            zf = (float)Xp[2];
+        } else {
+            map_point(P, false, xn, yn, 1.0, Xp);
+            ok = Xp[2] > 0.0;
+            zf = INFINITY;
+        }
+        if (ok) {
+            double u, v;
+            project(dst, Xp, &u, &v);
+            const double fu = floor(u + 0.5), fv = floor(v + 0.5);
+            if (fu >= 0.0 && fu <= (double)(dst.W - 1) && fv >= 0.0 && fv <= (double)(dst.H - 1)) {
+                const int64_t t = (int64_t)fv * dst.W + (int64_t)fu;
+                const unsigned long long key =
+                    ((unsigned long long)__float_as_uint(zf) << 32) | (unsigned long long)(uint32_t)s;
+                atomicMin(&zbuf[t], key);
+            }
+        }
+    }
+    dmin = wave_min_u32(dmin);
+    dmax = wave_max_u32(dmax);
+    if ((threadIdx.x & 63) == 0) {
+        if (dmin != 0xFFFFFFFFu) atomicMin(&st->dmin_bits, dmin);
+        if (dmax != 0u) atomicMax(&st->dmax_bits, dmax);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_reproject_resolve(int64_t nd, int64_t ns,
+                                                           const unsigned long long* __restrict__ zbuf,
+                                                           const float* __restrict__ rgb,
+                                                           const float* __restrict__ alpha,
+                                                           float* __restrict__ rgb_dst, float* __restrict__ z_dst,
+                                                           float* __restrict__ a_dst, uint8_t* __restrict__ hole,
+                                                           DevStatus* st) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    uint32_t h = 0;
+    if (t < nd) {
+        const unsigned long long key = zbuf[t];
+        if (key == ~0ull) {
+            h = 1;
+            rgb_dst[t] = 0.f;
+            rgb_dst[nd + t] = 0.f;
+            rgb_dst[2 * nd + t] = 0.f;
+            z_dst[t] = INFINITY;
+            a_dst[t] = 0.f;
+        } else {
+            const uint32_t s = (uint32_t)(key & 0xFFFFFFFFull);
+            rgb_dst[t] = rgb[s];
+            rgb_dst[nd + t] = rgb[ns + s];
+            rgb_dst[2 * nd + t] = rgb[2 * ns + s];
+            z_dst[t] = __uint_as_float((uint32_t)(key >> 32));
+            a_dst[t] = alpha[s];
+        }
+        hole[t] = (uint8_t)h;
+    }
+    h = wave_sum_u32(h);
+    if ((threadIdx.x & 63) == 0 && h) atomicAdd(&st->n_holes, h);
+}
+
+__global__ void k_depth_range(const DevStatus* st, float z_near, float z_far, float* range) {
+    if (st->dmin_bits == 0xFFFFFFFFu) {
+        range[0] = z_near;
+        range[1] = z_far;
+    } else {
+        range[0] = __uint_as_float(st->dmin_bits);
+        range[1] = __uint_as_float(st->dmax_bits);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Step 1: edge ROIs (Eq. 6-8).  One block.
+// ---------------------------------------------------------------------------
+__device__ inline int64_t edge_pos(int64_t k, int64_t N, int64_t L) {
+    if (N <= 1) return 0;
+    return (2 * k * (L - 1) + (N - 1)) / (2 * (N - 1));
+}
+__device__ inline double snap(double x) {
+    double r = rint(x);
+    return fabs(x - r) <= 1e-6 ? r : x;
+}
+__device__ inline double clampd(double x, double a, double b) { return x < a ? a : (x > b ? b : x); }
+__device__ inline int64_t align_down(int64_t x, int64_t T) { return (x / T) * T; }
+__device__ inline int64_t align_up(int64_t x, int64_t T) { return ((x + T - 1) / T) * T; }
+
+__global__ __launch_bounds__(256) void k_edge_rois(WarpCam src, WarpCam dst, RelPose P, int N, int margin, int T,
+                                                   const float* __restrict__ depth_range, DevStatus* st,
+                                                   bgs_box* boxes, int box_cap) {
+    __shared__ double red[4][256];
+    const double hyp0 = (double)depth_range[0], hyp1 = (double)depth_range[1];
+    double xmin = INFINITY, xmax = -INFINITY, ymin = INFINITY, ymax = -INFINITY;
+    const int64_t total = 4LL * N;
+    for (int64_t q = threadIdx.x; q < total; q += 256) {
+        const int edge = (int)(q / N);
+        const int64_t k = q % N;
+        int64_t i, j;
+        if (edge == 0) { i = edge_pos(k, N, src.W); j = 0; }
+        else if (edge == 1) { i = edge_pos(k, N, src.W); j = src.H - 1; }
+        else if (edge == 2) { i = 0; j = edge_pos(k, N, src.H); }
+        else { i = src.W - 1; j = edge_pos(k, N, src.H); }
+        const double xn = ((double)i - src.cx) / src.fx;
+        const double yn = ((double)j - src.cy) / src.fy;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const double d = h ? hyp1 : hyp0;
+            double Xp[3];
+            map_point(P, true, d * xn, d * yn, d, Xp);
+            if (!(Xp[2] > dst.z_near)) continue;
+            double u, v;
+            project(dst, Xp, &u, &v);
+            xmin = fmin(xmin, u);
+            xmax = fmax(xmax, u);
+            ymin = fmin(ymin, v);
+            ymax = fmax(ymax, v);
+        }
+    }
+    red[0][threadIdx.x] = xmin;
+    red[1][threadIdx.x] = xmax;
+    red[2][threadIdx.x] = ymin;
+    red[3][threadIdx.x] = ymax;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            red[0][threadIdx.x] = fmin(red[0][threadIdx.x], red[0][threadIdx.x + s]);
+            red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + s]);
+            red[2][threadIdx.x] = fmin(red[2][threadIdx.x], red[2][threadIdx.x + s]);
+            red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double W = dst.W, H = dst.H, m = margin;
+    const double hw = floor(W / 2.0), hh = floor(H / 2.0);
+    const double umin = snap(red[0][0]), umax = snap(red[1][0]), vmin = snap(red[2][0]), vmax = snap(red[3][0]);
+    const double lw = umin > 0.0 ? clampd(ceil(umin) + m, 0.0, hw) : 0.0;
+    const double rw = umax < W - 1.0 ? clampd((W - 1.0) - floor(umax) + m, 0.0, hw) : 0.0;
+    const double th = vmin > 0.0 ? clampd(ceil(vmin) + m, 0.0, hh) : 0.0;
+    const double bh = vmax < H - 1.0 ? clampd((H - 1.0) - floor(vmax) + m, 0.0, hh) : 0.0;
+    const int w4[4] = {(int)lw, (int)rw, (int)th, (int)bh};
+    const int64_t Wi = dst.W, Hi = dst.H;
+    int nb = 0;
+    int32_t bx[4][6];
+    if (w4[0] > 0) {
+        int64_t x1 = align_up(w4[0], T);
+        int32_t b[6] = {0, 0, (int32_t)(x1 < Wi ? x1 : Wi), (int32_t)Hi, BGS_BOX_LEFT, -1};
+        for (int q = 0; q < 6; ++q) bx[nb][q] = b[q];
+        ++nb;
+    }
+    if (w4[1] > 0) {
+        int32_t b[6] = {(int32_t)align_down(Wi - w4[1], T), 0, (int32_t)Wi, (int32_t)Hi, BGS_BOX_RIGHT, -1};
+        for (int q = 0; q < 6; ++q) bx[nb][q] = b[q];
+        ++nb;
+    }
+    if (w4[2] > 0) {
+        int64_t y1 = align_up(w4[2], T);
+        int32_t b[6] = {0, 0, (int32_t)Wi, (int32_t)(y1 < Hi ? y1 : Hi), BGS_BOX_TOP, -1};
+        for (int q = 0; q < 6; ++q) bx[nb][q] = b[q];
+        ++nb;
+    }
+    if (w4[3] > 0) {
+        int32_t b[6] = {0, (int32_t)align_down(Hi - w4[3], T), (int32_t)Wi, (int32_t)Hi, BGS_BOX_BOTTOM, -1};
+        for (int q = 0; q < 6; ++q) bx[nb][q] = b[q];
+        ++nb;
+    }
+    for (int q = 0; q < 4; ++q) st->widths[q] = w4[q];
+    st->n_edge = (uint32_t)nb;
+    for (int b = 0; b < nb; ++b) {
+        for (int q = 0; q < 6; ++q) st->edge_boxes[b * 6 + q] = bx[b][q];
+        if (b < box_cap) {
+            boxes[b].x0 = bx[b][0];
+            boxes[b].y0 = bx[b][1];
+            boxes[b].x1 = bx[b][2];
+            boxes[b].y1 = bx[b][3];
+            boxes[b].kind = bx[b][4];
+            boxes[b].label = bx[b][5];
+        }
+    }
+}
+
+__device__ inline bool in_edge(const DevStatus* st, int x, int y) {
+    const int ne = (int)st->n_edge;
+    for (int b = 0; b < ne; ++b) {
+        const int32_t* e = st->edge_boxes + b * 6;
+        if (x >= e[0] && x < e[2] && y >= e[1] && y < e[3]) return true;
+    }
+    return false;
+}
+
+// ---------------------------------------------------------------------------
+// Gap interpolation: one Jacobi pass.  Unfilled pixels are copied through.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gap_pass(int W, int H, const float* __restrict__ rgb_in,
+                                                  const float* __restrict__ z_in, const float* __restrict__ a_in,
+                                                  const uint8_t* __restrict__ hole_in, float* __restrict__ rgb_out,
+                                                  float* __restrict__ z_out, float* __restrict__ a_out,
+                                                  uint8_t* __restrict__ hole_out, uint8_t* __restrict__ cls,
+                                                  DevStatus* st) {
+    const int64_t n = (int64_t)W * H;
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    uint32_t filled = 0;
+    if (p < n) {
+        const int x = (int)(p % W), y = (int)(p / W);
+        float r0 = rgb_in[p], r1 = rgb_in[n + p], r2 = rgb_in[2 * n + p], zz = z_in[p], aa = a_in[p];
+        uint8_t h = hole_in[p];
+        if (h && !in_edge(st, x, y)) {
+            const int NX[8] = {-1, 0, 1, -1, 1, -1, 0, 1};
+            const int NY[8] = {-1, -1, -1, 0, 0, 1, 1, 1};
+            int cnt = 0;
+            float s0 = 0.f, s1 = 0.f, s2 = 0.f, sa = 0.f, zm = -INFINITY;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int xx = x + NX[q], yy = y + NY[q];
+                if (xx < 0 || yy < 0 || xx >= W || yy >= H) continue;
+                const int64_t r = (int64_t)yy * W + xx;
+                if (hole_in[r]) continue;
+                s0 = s0 + rgb_in[r];
+                s1 = s1 + rgb_in[n + r];
+                s2 = s2 + rgb_in[2 * n + r];
+                sa = sa + a_in[r];
+                const float zr = z_in[r];
+                if (zr > zm) zm = zr;
+                ++cnt;
+            }
+            if (cnt > 0) {
+                const float fc = (float)cnt;
+                r0 = s0 / fc;
+                r1 = s1 / fc;
+                r2 = s2 / fc;
+                aa = sa / fc;
+                zz = zm;
+                h = 0;
+                cls[p] = (uint8_t)BGS_CLS_GAP;
+                filled = 1;
+            }
+        }
+        rgb_out[p] = r0;
+        rgb_out[n + p] = r1;
+        rgb_out[2 * n + p] = r2;
+        z_out[p] = zz;
+        a_out[p] = aa;
+        hole_out[p] = h;
+    }
+    filled = wave_sum_u32(filled);
+    if ((threadIdx.x & 63) == 0 && filled) atomicAdd(&st->n_gap, filled);
+}
+
+__global__ __launch_bounds__(256) void k_copy_state(int64_t n, const float* __restrict__ rgb_in,
+                                                    const float* __restrict__ z_in, const float* __restrict__ a_in,
+                                                    float* __restrict__ rgb_out, float* __restrict__ z_out,
+                                                    float* __restrict__ a_out) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    rgb_out[p] = rgb_in[p];
+    rgb_out[n + p] = rgb_in[n + p];
+    rgb_out[2 * n + p] = rgb_in[2 * n + p];
+    z_out[p] = z_in[p];
+    a_out[p] = a_in[p];
+}
+
+__global__ __launch_bounds__(256) void k_hole_init(int64_t n, const uint8_t* __restrict__ cls,
+                                                   uint8_t* __restrict__ hole) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p < n) hole[p] = cls[p] ? 1 : 0;
+}
+
+// Holes left after interpolation and outside the edge ROIs.
+__global__ __launch_bounds__(256) void k_center_mask(int W, int H, const uint8_t* __restrict__ hole,
+                                                     uint8_t* __restrict__ center, DevStatus* st) {
+    const int64_t n = (int64_t)W * H;
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    uint32_t c = 0;
+    if (p < n) {
+        c = (hole[p] && !in_edge(st, (int)(p % W), (int)(p / W))) ? 1u : 0u;
+        center[p] = (uint8_t)c;
+    }
+    c = wave_sum_u32(c);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(&st->n_center, c);
+}
+
+// ---------------------------------------------------------------------------
+// Row fill (center step off): nearest non-hole pixel left and right on the
+// row via block max/min scans; the farther candidate wins.  One block/row.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_row_fill(int W, int H, const uint8_t* __restrict__ hole,
+                                                  const uint8_t* __restrict__ center, float bg0, float bg1, float bg2,
+                                                  float* __restrict__ rgb, float* __restrict__ z,
+                                                  float* __restrict__ alpha, uint8_t* __restrict__ cls,
+                                                  DevStatus* st) {
+    __shared__ int s_left[256], s_right[256];
+    const int y = blockIdx.x;
+    const int64_t n = (int64_t)W * H;
+    const int64_t row = (int64_t)y * W;
+    const int chunk = (W + 255) / 256;
+    const int xa = threadIdx.x * chunk, xb = min(xa + chunk, W);
+    int last = -1, first = INT_MAX;
+    for (int x = xa; x < xb; ++x)
+        if (!hole[row + x]) {
+            last = x;
+            if (first == INT_MAX) first = x;
+        }
+    s_left[threadIdx.x] = last;
+    s_right[threadIdx.x] = first;
+    __syncthreads();
+    // Inclusive scans: max from the left, min from the right.
+    for (int off = 1; off < 256; off <<= 1) {
+        int l = (int)threadIdx.x >= off ? s_left[threadIdx.x - off] : -1;
+        int r = (int)threadIdx.x + off < 256 ? s_right[threadIdx.x + off] : INT_MAX;
+        __syncthreads();
+        s_left[threadIdx.x] = max(s_left[threadIdx.x], l);
+        s_right[threadIdx.x] = min(s_right[threadIdx.x], r);
+        __syncthreads();
+    }
+    int left = threadIdx.x > 0 ? s_left[threadIdx.x - 1] : -1;
+    const int right_after = threadIdx.x < 255 ? s_right[threadIdx.x + 1] : INT_MAX;
+    uint32_t filled = 0;
+    // Nearest valid to the right of x inside the chunk, else right_after.
+    for (int x = xa; x < xb; ++x) {
+        const int64_t p = row + x;
+        if (center[p]) {
+            int right = right_after;
+            for (int xx = x + 1; xx < xb; ++xx)
+                if (!hole[row + xx]) {
+                    right = xx;
+                    break;
+                }
+            int pick = -1;
+            if (left >= 0 && right != INT_MAX) pick = z[row + right] > z[row + left] ? right : left;
+            else if (left >= 0) pick = left;
+            else if (right != INT_MAX) pick = right;
+            if (pick >= 0) {
+                const int64_t r = row + pick;
+                rgb[p] = rgb[r];
+                rgb[n + p] = rgb[n + r];
+                rgb[2 * n + p] = rgb[2 * n + r];
+                z[p] = z[r];
+                alpha[p] = alpha[r];
+            } else {
+                rgb[p] = bg0;
+                rgb[n + p] = bg1;
+                rgb[2 * n + p] = bg2;
+                z[p] = INFINITY;
+                alpha[p] = 0.f;
+            }
+            cls[p] = (uint8_t)BGS_CLS_ROWFILL;
+            ++filled;
+        }
+        if (!hole[p]) left = x;
+    }
+    filled = wave_sum_u32(filled);
+    if ((threadIdx.x & 63) == 0 && filled) atomicAdd(&st->n_rowfill, filled);
+}
+
+// ---------------------------------------------------------------------------
+// Connected components: block-local union-find in LDS over 16x16 pixel
+// blocks, then unions across block borders with global atomicMin, then
+// flattening.  Links always go from the larger to the smaller index, so the
+// root of every component is its smallest linear index.
+// ---------------------------------------------------------------------------
+__device__ inline int find_root_lds(int* L, int x) {
+    int p = __atomic_load_n(&L[x], __ATOMIC_RELAXED);
+    while (p != x) {
+        x = p;
+        p = __atomic_load_n(&L[x], __ATOMIC_RELAXED);
+    }
+    return x;
+}
+
+__device__ inline int find_root_g(int* L, int x) {
+    int p = __atomic_load_n(&L[x], __ATOMIC_RELAXED);
+    while (p != x) {
+        x = p;
+        p = __atomic_load_n(&L[x], __ATOMIC_RELAXED);
+    }
+    return x;
+}
+
+__device__ inline void unite_g(int* L, int a, int b) {
+    while (true) {
+        a = find_root_g(L, a);
+        b = find_root_g(L, b);
+        if (a == b) return;
+        if (a < b) {
+            int t = a;
+            a = b;
+            b = t;
+        }
+        const int old = atomicMin(&L[a], b);
+        if (old == a) return;
+        a = old;  // a had gained a parent meanwhile; unite that one with b
+    }
+}
+
+__device__ inline void unite_lds(int* L, int a, int b) {
+    while (true) {
+        a = find_root_lds(L, a);
+        b = find_root_lds(L, b);
+        if (a == b) return;
+        if (a < b) {
+            int t = a;
+            a = b;
+            b = t;
+        }
+        const int old = atomicMin(&L[a], b);
+        if (old == a) return;
+        a = old;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ccl_local(int W, int H, int conn, const uint8_t* __restrict__ mask,
+                                                   int* __restrict__ labels) {
+    __shared__ int L[256];
+    __shared__ uint8_t m[256];
+    const int lx = threadIdx.x & 15, ly = threadIdx.x >> 4;
+    const int x = blockIdx.x * 16 + lx, y = blockIdx.y * 16 + ly;
+    const bool in = x < W && y < H;
+    const int li = threadIdx.x;
+    const bool set = in && mask[(int64_t)y * W + x];
+    m[li] = set ? 1 : 0;
+    L[li] = li;
+    __syncthreads();
+    if (set) {
+        // Backward neighbours inside the block: left, up-left, up, up-right.
+        if (lx > 0 && m[li - 1]) unite_lds(L, li, li - 1);
+        if (ly > 0) {
+            if (m[li - 16]) unite_lds(L, li, li - 16);
+            if (conn == 8) {
+                if (lx > 0 && m[li - 17]) unite_lds(L, li, li - 17);
+                if (lx < 15 && m[li - 15]) unite_lds(L, li, li - 15);
+            }
+        }
+    }
+    __syncthreads();
+    if (!in) return;
+    if (set) {
+        const int r = find_root_lds(L, li);
+        const int rx = blockIdx.x * 16 + (r & 15), ry = blockIdx.y * 16 + (r >> 4);
+        labels[(int64_t)y * W + x] = ry * W + rx;
+    } else {
+        labels[(int64_t)y * W + x] = -1;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ccl_border(int W, int H, int conn, const uint8_t* __restrict__ mask,
+                                                    int* labels) {
+    const int lx = threadIdx.x & 15, ly = threadIdx.x >> 4;
+    const int x = blockIdx.x * 16 + lx, y = blockIdx.y * 16 + ly;
+    if (x >= W || y >= H) return;
+    if (!(lx == 0 || ly == 0 || lx == 15)) return;
+    const int64_t p = (int64_t)y * W + x;
+    if (!mask[p]) return;
+    const int me = (int)p;
+    // Neighbours in another block (the rest were joined in LDS).
+    if (lx == 0 && x > 0 && mask[p - 1]) unite_g(labels, me, me - 1);
+    if (y > 0) {
+        if (ly == 0 && mask[p - W]) unite_g(labels, me, me - W);
+        if (conn == 8) {
+            if (x > 0 && (lx == 0 || ly == 0) && mask[p - W - 1]) unite_g(labels, me, me - W - 1);
+            if (x + 1 < W && (lx == 15 || ly == 0) && mask[p - W + 1]) unite_g(labels, me, me - W + 1);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ccl_flatten(int64_t n, int* labels) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    const int l = labels[p];
+    if (l < 0) return;
+    labels[p] = find_root_g(labels, l);
+}
+
+// ---------------------------------------------------------------------------
+// Center boxes.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_root_flags(int64_t n, const int* __restrict__ labels,
+                                                    uint32_t* __restrict__ flags) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p < n) flags[p] = (labels[p] == (int)p) ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(256) void k_bbox_init(int64_t n, const int* __restrict__ labels,
+                                                   const uint32_t* __restrict__ slots, int32_t* __restrict__ bbox) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n || labels[p] != (int)p) return;
+    const uint32_t s = slots[p];
+    bbox[4 * s + 0] = INT_MAX;
+    bbox[4 * s + 1] = INT_MAX;
+    bbox[4 * s + 2] = -1;
+    bbox[4 * s + 3] = -1;
+}
+
+__global__ __launch_bounds__(256) void k_bbox_acc(int W, int64_t n, const int* __restrict__ labels,
+                                                  const uint32_t* __restrict__ slots, int32_t* bbox) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    const int l = labels[p];
+    if (l < 0) return;
+    const uint32_t s = slots[l];
+    const int x = (int)(p % W), y = (int)(p / W);
+    atomicMin(&bbox[4 * s + 0], x);
+    atomicMin(&bbox[4 * s + 1], y);
+    atomicMax(&bbox[4 * s + 2], x + 1);
+    atomicMax(&bbox[4 * s + 3], y + 1);
+}
+
+__global__ __launch_bounds__(256) void k_tile_mask_edges(int tiles_x, int tiles_y, int T, const DevStatus* st,
+                                                         uint8_t* __restrict__ tm) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= tiles_x * tiles_y) return;
+    const int x0 = (t % tiles_x) * T, y0 = (t / tiles_x) * T, x1 = x0 + T, y1 = y0 + T;
+    uint8_t hit = 0;
+    for (int b = 0; b < (int)st->n_edge; ++b) {
+        const int32_t* e = st->edge_boxes + b * 6;
+        if (x0 < e[2] && e[0] < x1 && y0 < e[3] && e[1] < y1) hit = 1;
+    }
+    tm[t] = hit;
+}
+
+__global__ __launch_bounds__(256) void k_center_boxes(int W, int H, int64_t n, int margin, int T, int tiles_x,
+                                                      const int* __restrict__ labels,
+                                                      const uint32_t* __restrict__ slots,
+                                                      const int32_t* __restrict__ bbox, bgs_box* __restrict__ boxes,
+                                                      int box_cap, uint8_t* tm, DevStatus* st) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n || labels[p] != (int)p) return;
+    const uint32_t s = slots[p];
+    int64_t x0 = bbox[4 * s + 0] - margin, y0 = bbox[4 * s + 1] - margin;
+    int64_t x1 = bbox[4 * s + 2] + margin, y1 = bbox[4 * s + 3] + margin;
+    if (x0 < 0) x0 = 0;
+    if (y0 < 0) y0 = 0;
+    if (x1 > W) x1 = W;
+    if (y1 > H) y1 = H;
+    x0 = align_down(x0, T);
+    y0 = align_down(y0, T);
+    x1 = align_up(x1, T);
+    y1 = align_up(y1, T);
+    if (x1 > W) x1 = W;
+    if (y1 > H) y1 = H;
+    const int64_t slot = (int64_t)st->n_edge + s;
+    if (slot < box_cap) {
+        boxes[slot].x0 = (int32_t)x0;
+        boxes[slot].y0 = (int32_t)y0;
+        boxes[slot].x1 = (int32_t)x1;
+        boxes[slot].y1 = (int32_t)y1;
+        boxes[slot].kind = BGS_BOX_CENTER;
+        boxes[slot].label = (int32_t)p;
+    }
+    for (int64_t ty = y0 / T; ty < (y1 + T - 1) / T; ++ty)
+        for (int64_t tx = x0 / T; tx < (x1 + T - 1) / T; ++tx) tm[ty * tiles_x + tx] = 1;
+}
+
+__global__ void k_box_count(int64_t n, const uint32_t* __restrict__ slots, int box_cap, int32_t* n_boxes,
+                            DevStatus* st, int center) {
+    const uint32_t nc = center ? slots[n] : 0u;
+    const uint32_t tot = st->n_edge + nc;
+    st->n_boxes = tot;
+    if ((int64_t)tot > box_cap) st->overflow |= 2u;
+    *n_boxes = (int32_t)tot;
+}
+
+__global__ __launch_bounds__(256) void k_fill_i32(int64_t n, int32_t* p, int32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+inline unsigned grid(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+hipError_t launch_reproject(const WarpCam& src, const WarpCam& dst, const RelPose& P, float a_min, const float* rgb,
+                            const float* draw, const float* alpha, unsigned long long* zbuf, float* rgb_dst,
+                            float* z_dst, float* alpha_dst, uint8_t* hole, float* depth_range, DevStatus* st,
+                            hipStream_t s) {
+    const int64_t ns = (int64_t)src.W * src.H, nd = (int64_t)dst.W * dst.H;
+    hipLaunchKernelGGL(k_warp_reset, dim3(1), dim3(1), 0, s, st);
+    hipLaunchKernelGGL(k_fill_u64, dim3(grid(nd)), dim3(256), 0, s, zbuf, nd, ~0ull);
+    hipLaunchKernelGGL(k_reproject_scatter, dim3(grid(ns)), dim3(256), 0, s, src, dst, P, a_min, draw, alpha, zbuf, st);
+    hipLaunchKernelGGL(k_reproject_resolve, dim3(grid(nd)), dim3(256), 0, s, nd, ns, zbuf, rgb, alpha, rgb_dst, z_dst,
+                       alpha_dst, hole, st);
+    hipLaunchKernelGGL(k_depth_range, dim3(1), dim3(1), 0, s, st, (float)src.z_near, (float)src.z_far, depth_range);
+    return hipGetLastError();
+}
+
+hipError_t launch_label_components(const uint8_t* mask, int W, int H, int conn, int32_t* labels, hipStream_t s) {
+    const int64_t n = (int64_t)W * H;
+    if (n == 0) return hipSuccess;
+    dim3 g((W + 15) / 16, (H + 15) / 16);
+    hipLaunchKernelGGL(k_ccl_local, g, dim3(256), 0, s, W, H, conn, mask, labels);
+    hipLaunchKernelGGL(k_ccl_border, g, dim3(256), 0, s, W, H, conn, mask, labels);
+    hipLaunchKernelGGL(k_ccl_flatten, dim3(grid(n)), dim3(256), 0, s, n, labels);
+    return hipGetLastError();
+}
+
+hipError_t launch_classify(const WarpCam& src, const WarpCam& dst, const RelPose& P, const bgs_roi_params& roi,
+                           const float bg[3], const float* depth_range, float* rgb, float* z, float* alpha,
+                           uint8_t* cls, int32_t* labels, bgs_box* boxes, int32_t box_cap, int32_t* n_boxes,
+                           uint8_t* tile_mask, const ClassifyBufs& b, DevStatus* st, hipStream_t s) {
+    const int W = dst.W, H = dst.H, T = roi.tile;
+    const int64_t n = (int64_t)W * H;
+    const int tiles_x = (W + T - 1) / T, tiles_y = (H + T - 1) / T;
+    hipLaunchKernelGGL(k_edge_rois, dim3(1), dim3(256), 0, s, src, dst, P, roi.edge_samples, roi.margin, T,
+                       depth_range, st, boxes, box_cap);
+    hipLaunchKernelGGL(k_hole_init, dim3(grid(n)), dim3(256), 0, s, n, cls, b.hole);
+    // Jacobi passes ping-pong between the caller's image and the scratch copy.
+    float *ri = rgb, *zi = z, *ai = alpha, *ro = b.rgb2, *zo = b.z2, *ao = b.a2;
+    uint8_t *hi = b.hole, *ho = b.hole2;
+    for (int pass = 0; pass < roi.gap_passes; ++pass) {
+        hipLaunchKernelGGL(k_gap_pass, dim3(grid(n)), dim3(256), 0, s, W, H, ri, zi, ai, hi, ro, zo, ao, ho, cls, st);
+        float* t;
+        t = ri; ri = ro; ro = t;
+        t = zi; zi = zo; zo = t;
+        t = ai; ai = ao; ao = t;
+        uint8_t* th = hi; hi = ho; ho = th;
+    }
+    if (ri != rgb)
+        hipLaunchKernelGGL(k_copy_state, dim3(grid(n)), dim3(256), 0, s, n, ri, zi, ai, rgb, z, alpha);
+    // hi now holds the hole state after interpolation; ho is free scratch.
+    uint8_t* center = ho;
+    hipLaunchKernelGGL(k_center_mask, dim3(grid(n)), dim3(256), 0, s, W, H, hi, center, st);
+    hipLaunchKernelGGL(k_tile_mask_edges, dim3(grid((int64_t)tiles_x * tiles_y)), dim3(256), 0, s, tiles_x, tiles_y, T,
+                       st, tile_mask);
+    if (roi.center_roi) {
+        hipError_t e = launch_label_components(center, W, H, 8, labels, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_root_flags, dim3(grid(n)), dim3(256), 0, s, n, labels, b.flags);
+        e = exclusive_scan(b.flags, nullptr, b.flags, nullptr, n, b.scan_tmp, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_bbox_init, dim3(grid(n)), dim3(256), 0, s, n, labels, b.flags, b.bbox);
+        hipLaunchKernelGGL(k_bbox_acc, dim3(grid(n)), dim3(256), 0, s, W, n, labels, b.flags, b.bbox);
+        hipLaunchKernelGGL(k_center_boxes, dim3(grid(n)), dim3(256), 0, s, W, H, n, roi.margin, T, tiles_x, labels,
+                           b.flags, b.bbox, boxes, box_cap, tile_mask, st);
+    } else {
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid(n)), dim3(256), 0, s, n, labels, -1);
+        hipLaunchKernelGGL(k_row_fill, dim3(H), dim3(256), 0, s, W, H, hi, center, bg[0], bg[1], bg[2], rgb, z, alpha,
+                           cls, st);
+    }
+    hipLaunchKernelGGL(k_box_count, dim3(1), dim3(1), 0, s, n, b.flags, box_cap, n_boxes, st, roi.center_roi);
+    return hipGetLastError();
+}
+
+}  // namespace bgs

@@ -1,0 +1,331 @@
+"""GPU parity of every stage of the frame path against the CPU oracle on the
+same seeded inputs, through the C ABI.
+
+Tolerances: RGB and the accumulated weight A: |GPU - oracle| <= 1e-4 per
+channel after clamping RGB to [0, 1]; depth 1e-4 relative to the depth
+scale: |D_raw(GPU) - D_raw| <= 1e-4 * (D/A) + 1e-7 for the accumulated
+D = sum d w, and the depth proxy D/A within 1e-4 relative wherever
+A >= 0.5 (where reprojection uses it); sort orders, hole masks, labels,
+boxes and tile masks bit-exact.  Pixels where the oracle flags a threshold
+decision that fp32 may take differently (alpha within 5e-5 of alpha_min,
+transmittance within 1e-4 of T_min, the G3/G2 depth choice, rays grazing
+a surfel plane) are counted, must stay below 0.5% of the pixels, and are
+held to a loose bound of 1e-2 instead: one such flip moves a pixel by at
+most about alpha_min.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2609_30741_amd import api, synth
+
+pytestmark = pytest.mark.gpu
+
+RGB_TOL = 1e-4
+DEPTH_RTOL = 1e-4
+MAX_AMBIGUOUS_FRAC = 0.005
+AMBIGUOUS_TOL = 1e-2
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "the gpu tests need an MI355X"
+    return api.Context()
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+def check_image(gpu_rgb, gpu_d, gpu_a, ref, where=""):
+    """gpu_* are (3, ...) / (...) arrays over the same pixels as ref."""
+    amb = ref["amb"] > 0
+    A_ref, D_ref = ref["alpha"], ref["depth_raw"]
+    zhat = np.where(A_ref > 0, D_ref / np.maximum(A_ref, 1e-30), 0.0)
+    e_rgb = np.abs(np.clip(gpu_rgb, 0, 1) - np.clip(ref["rgb"], 0, 1)).max(axis=0)
+    e_a = np.abs(gpu_a - A_ref)
+    e_d = np.abs(gpu_d - D_ref) / (np.abs(zhat) + 1e-3)
+    fg = A_ref >= 0.5
+    e_p = np.zeros_like(e_a)
+    e_p[fg] = np.abs(gpu_d[fg] / gpu_a[fg] - zhat[fg]) / zhat[fg]
+    bad = ((e_rgb > RGB_TOL) | (e_a > RGB_TOL) | (e_d > DEPTH_RTOL + 1e-7) | (e_p > DEPTH_RTOL)) & ~amb
+    loose = (e_rgb > AMBIGUOUS_TOL) | (e_a > AMBIGUOUS_TOL) | (e_p > AMBIGUOUS_TOL)
+    log(f"[{where}] px={amb.size} ambiguous={int(amb.sum())} max_rgb_err(non-amb)="
+        f"{float(e_rgb[~amb].max()) if (~amb).any() else 0:.2e} max_depth_err(non-amb)="
+        f"{float(np.maximum(e_d, e_p)[~amb].max()) if (~amb).any() else 0:.2e} bad={int(bad.sum())}")
+    assert amb.mean() <= MAX_AMBIGUOUS_FRAC, f"{where}: too many ambiguous pixels {amb.mean():.4f}"
+    assert not bad.any(), f"{where}: {int(bad.sum())} pixels outside tolerance; first at {np.argwhere(bad)[:5]}"
+    assert not loose.any(), f"{where}: ambiguous pixels beyond {AMBIGUOUS_TOL}: {np.argwhere(loose)[:5]}"
+
+
+# ---------------------------------------------------------------------------
+# Sort and connected components (bit-exact)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,bits", [(0, 8), (1, 8), (4095, 8), (4096, 13), (4097, 13), (100_003, 11),
+                                    (1_000_001, 32), (250_000, 1), (70_000, 20)])
+def test_sort_pairs_bit_exact(ctx, n, bits):
+    log(f"sort n={n} bits={bits}")
+    keys, vals = synth.random_sort_keys(n, seed=n + bits, key_bits=32)
+    kt = torch.from_numpy(keys.view(np.int32).copy()).cuda()
+    vt = torch.from_numpy(vals.view(np.int32).copy()).cuda()
+    ctx.sort_pairs(kt, vt, bits)
+    torch.cuda.synchronize()
+    mask = np.uint32((1 << bits) - 1) if bits < 32 else np.uint32(0xFFFFFFFF)
+    order = np.argsort(keys & mask, kind="stable")
+    assert np.array_equal(to_np(kt).view(np.uint32), keys[order])
+    assert np.array_equal(to_np(vt).view(np.uint32), vals[order])
+
+
+@pytest.mark.parametrize("shape", [(45, 67), (200, 301), (1, 1), (17, 1)])
+@pytest.mark.parametrize("case", ["rand05", "rand30", "rand60", "checker", "serpentine", "empty", "full"])
+@pytest.mark.parametrize("conn", [4, 8])
+def test_label_components_bit_exact(ctx, oracle, shape, case, conn):
+    H, W = shape
+    if case.startswith("rand"):
+        mask = synth.random_mask(W, H, 13, int(case[4:]) / 100)
+    elif case == "checker":
+        mask = synth.checkerboard_mask(W, H)
+    elif case == "serpentine":
+        mask = synth.serpentine_mask(W, H)
+    elif case == "empty":
+        mask = np.zeros((H, W), np.uint8)
+    else:
+        mask = np.ones((H, W), np.uint8)
+    lab = to_np(ctx.label_components(torch.from_numpy(mask).cuda(), conn))
+    ref = oracle.label_components(mask, conn)
+    assert np.array_equal(lab, ref)
+
+
+# ---------------------------------------------------------------------------
+# Stage 1: preprocess, binning and blending
+# ---------------------------------------------------------------------------
+
+def cube_workload(n=10_000, W=256, H=256, f=300.0, seed=0):
+    sc = synth.scene_uniform_cube(seed, n)
+    cam = synth.look_at((0.0, -4.0, 0.0), (0, 0, 0), (0, 0, 1), W, H, f)
+    return sc, cam
+
+
+def test_preprocess_keys_and_conservative_bins(ctx, oracle):
+    sc, cam = cube_workload(3000, 96, 80, 110.0)
+    ds = api.DeviceScene(sc)
+    zkey, rects, counts = ctx.preprocess_debug(ds, cam)
+    zkey, rects, counts = to_np(zkey).view(np.uint32), to_np(rects), to_np(counts)
+    zo = oracle.center_zkeys(sc, cam)
+    live = zo > cam.z_near
+    assert np.array_equal(zkey[live], zo.view(np.uint32)[live])
+    assert np.all(zkey[~live] == 0xFFFFFFFF)
+    cov = oracle.coverage_boxes(sc, cam)
+    has = cov[:, 0] >= 0
+    assert has.sum() > 100
+    # Every pixel where alpha >= alpha_min lies in a binned tile.
+    assert np.all(rects[has, 0] >= 0)
+    assert np.all(rects[has, 0] <= cov[has, 0] // 16) and np.all(rects[has, 1] <= cov[has, 1] // 16)
+    assert np.all(rects[has, 2] >= cov[has, 2] // 16) and np.all(rects[has, 3] >= cov[has, 3] // 16)
+    exp_counts = np.where(rects[:, 0] >= 0, (rects[:, 2] - rects[:, 0] + 1) * (rects[:, 3] - rects[:, 1] + 1), 0)
+    assert np.array_equal(counts, exp_counts)
+
+
+def test_tile_lists_are_sorted_and_complete(ctx, oracle):
+    sc, cam = cube_workload(4000, 128, 96, 140.0, seed=3)
+    ds = api.DeviceScene(sc)
+    zkey, rects, _ = ctx.preprocess_debug(ds, cam)
+    zkey, rects = to_np(zkey).view(np.uint32), to_np(rects)
+    ranges, vals, nk = ctx.tile_lists_debug(ds, cam)
+    ranges, vals = to_np(ranges), to_np(vals)
+    tx_n = (cam.width + 15) // 16
+    for t in range(ranges.shape[0]):
+        tx, ty = t % tx_n, t // tx_n
+        got = vals[ranges[t, 0]:ranges[t, 1]]
+        inr = np.nonzero((rects[:, 0] >= 0) & (rects[:, 0] <= tx) & (rects[:, 2] >= tx) & (rects[:, 1] <= ty)
+                         & (rects[:, 3] >= ty))[0]
+        exp = inr[np.lexsort((inr, zkey[inr]))]
+        assert np.array_equal(got, exp), f"tile {t}"
+    assert ranges[:, 1].max() == nk
+
+
+@pytest.mark.parametrize("W,H", [(256, 256), (37, 23), (129, 65)])
+def test_render_dominant_cube(ctx, oracle, W, H):
+    sc, cam = cube_workload(10_000, W, H, 300.0 * W / 256)
+    log(f"render cube {W}x{H}")
+    out = ctx.render_dominant(api.DeviceScene(sc), cam)
+    ref = oracle.render(sc, cam)
+    check_image(to_np(out["rgb"]), to_np(out["depth_raw"]), to_np(out["alpha"]), ref, f"cube {W}x{H}")
+
+
+def test_render_edge_cases(ctx, oracle):
+    # Empty scene -> background; one opaque surfel -> depth proxy = its depth;
+    # surfels behind the camera are culled.
+    bg = (0.2, 0.4, 0.6)
+    cam = synth.look_at((0.0, -3.0, 0.0), (0, 0, 0), (0, 0, 1), 40, 30, 50.0)
+    r = api.Raster(bg=bg)
+    out = ctx.render_dominant(api.DeviceScene(synth.empty_scene()), cam, r)
+    assert np.allclose(to_np(out["rgb"]), np.array(bg)[:, None, None]) and np.all(to_np(out["alpha"]) == 0)
+    sc = synth.explicit_scene([[0.0, 0.0, 0.0]], [[1, 0, 0]], [[0, 0, 1]], [0.3], [0.3], [0.99], [[0.8, 0.1, 0.3]])
+    out = ctx.render_dominant(api.DeviceScene(sc), cam, api.Raster(lowpass=False))
+    a, d = to_np(out["alpha"]), to_np(out["depth_raw"])
+    m = a > 0
+    assert m.sum() > 50
+    np.testing.assert_allclose(d[m] / a[m], 3.0, rtol=2e-6)
+    ref = oracle.render(sc, cam, oracle.Raster(lowpass=False))
+    check_image(to_np(out["rgb"]), d, a, ref, "one surfel")
+    behind = synth.explicit_scene([[0.0, -3.5, 0.0]], [[1, 0, 0]], [[0, 0, 1]], [0.3], [0.3], [0.99], [[1, 1, 1]])
+    out = ctx.render_dominant(api.DeviceScene(behind), cam)
+    assert np.all(to_np(out["alpha"]) == 0)
+
+
+@pytest.mark.parametrize("name,n_px", [("sphere800", 1500), ("unbounded1600", 600)])
+def test_render_dominant_full_size_sampled(ctx, oracle, name, n_px):
+    """The full-size workloads in the bench's launch configuration, checked on
+    sampled pixels the oracle computes one by one."""
+    log(f"full-size {name}")
+    sc, cams, _ = synth.WORKLOADS[name](0)
+    cam = cams[3]
+    out = ctx.render_dominant(api.DeviceScene(sc), cam)
+    rng = np.random.default_rng(7)
+    pix = np.stack([rng.integers(0, cam.width, n_px), rng.integers(0, cam.height, n_px)], axis=1).astype(np.int32)
+    ref = oracle.render(sc, cam, pixels=pix)
+    rgb, d, a = to_np(out["rgb"]), to_np(out["depth_raw"]), to_np(out["alpha"])
+    check_image(rgb[:, pix[:, 1], pix[:, 0]], d[pix[:, 1], pix[:, 0]], a[pix[:, 1], pix[:, 0]], ref, name)
+    log(f"{name}: keys={out['n_keys']}")
+
+
+# ---------------------------------------------------------------------------
+# Stages 2-3: bit-exact given identical inputs
+# ---------------------------------------------------------------------------
+
+def stage_rig(W, H, f, b=0.064):
+    dom = synth.look_at((0.0, -4.0, 0.0), (0, 0, 0), (0, 0, 1), W, H, f)
+    return dom, synth.affiliated(dom, b)
+
+
+@pytest.mark.parametrize("W,H,seed,b", [(256, 256, 0, 0.064), (800, 600, 1, 0.064), (203, 117, 2, 0.3),
+                                        (160, 120, 3, 0.0), (96, 64, 4, -0.2)])
+def test_reproject_bit_exact(ctx, oracle, W, H, seed, b):
+    dom, aff = stage_rig(W, H, 1.2 * W, b)
+    rgb, dr, a = synth.stage_images(W, H, seed)
+    out = ctx.reproject(dom, aff, torch.from_numpy(rgb).cuda(), torch.from_numpy(dr).cuda(), torch.from_numpy(a).cuda())
+    ref = oracle.reproject(dom, aff, rgb, dr, a)
+    assert np.array_equal(to_np(out["hole"]), ref["hole"])
+    assert np.array_equal(to_np(out["rgb"]), ref["rgb"])
+    assert np.array_equal(to_np(out["z"]), ref["z"])
+    assert np.array_equal(to_np(out["alpha"]), ref["alpha"])
+    assert np.array_equal(to_np(out["depth_range"]), ref["depth_range"])
+
+
+@pytest.mark.parametrize("center", [True, False])
+@pytest.mark.parametrize("W,H,seed,b", [(256, 256, 5, 0.064), (800, 600, 6, 0.15), (203, 117, 7, 0.3),
+                                        (1600, 1064, 8, 0.064)])
+def test_classify_bit_exact(ctx, oracle, center, W, H, seed, b):
+    dom, aff = stage_rig(W, H, 1.2 * W, b)
+    rgb, dr, a = synth.stage_images(W, H, seed, n_occluders=10)
+    rep = oracle.reproject(dom, aff, rgb, dr, a)
+    roi = api.Roi(center_roi=center)
+    ref = oracle.classify(dom, aff, oracle.Roi(center_roi=center), rep["depth_range"], rep["rgb"], rep["z"],
+                          rep["alpha"], rep["hole"], box_cap=4096)
+    g_rgb = torch.from_numpy(rep["rgb"]).cuda()
+    g_z = torch.from_numpy(rep["z"]).cuda()
+    g_a = torch.from_numpy(rep["alpha"]).cuda()
+    g_cls = torch.from_numpy(rep["hole"]).cuda()
+    out = ctx.classify_holes(dom, aff, torch.from_numpy(rep["depth_range"]).cuda(), g_rgb, g_z, g_a, g_cls, roi,
+                             box_capacity=4096)
+    torch.cuda.synchronize()
+    log(f"classify {W}x{H} center={center}: boxes={ref['n_boxes']} stats={ref['stats']}")
+    assert np.array_equal(to_np(g_cls), ref["cls"])
+    assert np.array_equal(to_np(out["labels"]), ref["labels"])
+    nb = int(to_np(out["n_boxes"])[0])
+    assert nb == ref["n_boxes"]
+    assert np.array_equal(to_np(out["boxes"])[:nb], ref["boxes"])
+    assert np.array_equal(to_np(out["tile_mask"]), ref["tile_mask"])
+    assert np.array_equal(to_np(g_rgb), ref["rgb"])
+    assert np.array_equal(to_np(g_z), ref["z"])
+    assert np.array_equal(to_np(g_a), ref["alpha"])
+
+
+def test_box_capacity_overflow_keeps_tile_mask(ctx, oracle):
+    W, H = 256, 192
+    dom, aff = stage_rig(W, H, 300.0, 0.0)
+    rgb = np.full((3, H, W), 0.5, np.float32)
+    z = np.full((H, W), 2.0, np.float32)
+    a = np.ones((H, W), np.float32)
+    hole = np.zeros((H, W), np.uint8)
+    for k in range(12):
+        hole[10 + 15 * k:16 + 15 * k, 20 + 17 * k:28 + 17 * k] = 1
+    ref = oracle.classify(dom, aff, oracle.Roi(), np.float32([4, 4]), rgb, z, a, hole, box_cap=3)
+    g = [torch.from_numpy(x).cuda() for x in (rgb, z, a, hole)]
+    out = ctx.classify_holes(dom, aff, torch.from_numpy(np.float32([4, 4])).cuda(), *g, box_capacity=3)
+    torch.cuda.synchronize()
+    assert int(to_np(out["n_boxes"])[0]) == ref["n_boxes"] == 12
+    assert np.array_equal(to_np(out["boxes"])[:3], ref["boxes"][:3])
+    assert np.array_equal(to_np(out["tile_mask"]), ref["tile_mask"])
+
+
+# ---------------------------------------------------------------------------
+# Stage 4 and the whole frame
+# ---------------------------------------------------------------------------
+
+def test_patch_matches_oracle_and_all_tiles_equal_full_render(ctx, oracle):
+    sc, cam = cube_workload(10_000, 256, 256, 300.0, seed=1)
+    aff = synth.affiliated(cam, 0.064)
+    ds = api.DeviceScene(sc)
+    H, W = 256, 256
+    rng = np.random.default_rng(0)
+    tm = (rng.uniform(size=(16, 16)) < 0.3).astype(np.uint8)
+    base = rng.uniform(size=(3, H, W)).astype(np.float32)
+    g_rgb, g_z = torch.from_numpy(base.copy()).cuda(), torch.zeros((H, W), device="cuda")
+    g_a, g_cls = torch.zeros((H, W), device="cuda"), torch.zeros((H, W), dtype=torch.uint8, device="cuda")
+    ctx.patch_rois(ds, aff, torch.from_numpy(tm).cuda(), g_rgb, g_z, g_a, g_cls)
+    ref = oracle.patch(sc, aff, tm, base, np.zeros((H, W), np.float32), np.zeros((H, W), np.float32),
+                       np.zeros((H, W), np.uint8))
+    pm = np.kron(tm, np.ones((16, 16), np.uint8)).astype(bool)
+    rgb = to_np(g_rgb)
+    assert np.array_equal(rgb[:, ~pm], base[:, ~pm])
+    assert np.array_equal(to_np(g_cls), ref["cls"])
+    amb = ref["amb"] > 0
+    err = np.abs(np.clip(rgb, 0, 1) - np.clip(ref["rgb"], 0, 1)).max(0)
+    assert not np.any((err > RGB_TOL) & pm & ~amb)
+    # An all-ones mask re-renders the whole image: bit-identical to the full
+    # render of the same camera.
+    full = ctx.render_dominant(ds, aff)
+    ones = torch.ones((16, 16), dtype=torch.uint8, device="cuda")
+    ctx.patch_rois(ds, aff, ones, g_rgb, g_z, g_a, g_cls)
+    assert torch.equal(g_rgb, full["rgb"]) and torch.equal(g_a, full["alpha"])
+
+
+def test_render_stereo_zero_baseline(ctx):
+    sc, cam = cube_workload(10_000, 256, 256, 300.0, seed=2)
+    out = ctx.render_stereo(api.DeviceScene(sc), cam, cam.copy())
+    assert out["stats"]["n_holes"] == 0 and out["stats"]["n_boxes"] == 0
+    assert torch.equal(out["rgb_aff"], out["rgb_dom"])
+
+
+@pytest.mark.parametrize("center", [False, True])
+def test_render_stereo_cube_end_to_end(ctx, oracle, center):
+    sc, cam = cube_workload(10_000, 256, 256, 300.0)
+    aff = synth.affiliated(cam, 0.064)
+    roi = api.Roi(center_roi=center)
+    out = ctx.render_stereo(api.DeviceScene(sc), cam, aff, roi=roi)
+    ref = oracle.render_stereo(sc, cam, aff, roi=oracle.Roi(center_roi=center))
+    check_image(to_np(out["rgb_dom"]), to_np(out["depth_raw_dom"]), to_np(out["alpha_dom"]), ref["dom"], "stereo dom")
+    cls_g, cls_o = to_np(out["cls_aff"]), ref["aff"]["cls"]
+    mism = (cls_g != cls_o).mean()
+    log(f"stereo center={center}: class mismatch {mism:.5f}; stats {out['stats']}")
+    assert mism < 2e-3
+    same = cls_g == cls_o
+    rgb_g = np.clip(to_np(out["rgb_aff"]), 0, 1)
+    rgb_o = np.clip(ref["aff"]["rgb"], 0, 1)
+    amb = ref["aff"]["amb"] > 0
+    roi_px = same & (cls_g == api.CLS_ROI) & ~amb
+    assert np.abs(rgb_g - rgb_o).max(0)[roi_px].max() <= RGB_TOL
+    # End to end the warped pixels inherit fp32 depth differences of the
+    # dominant render: they agree except where a target pixel flips.
+    warp_px = same & (cls_g == api.CLS_WARPED)
+    frac = (np.abs(rgb_g - rgb_o).max(0)[warp_px] > RGB_TOL).mean()
+    assert frac < 2e-3
