@@ -110,7 +110,7 @@ def main():
         f"keys dom {np.mean(keys_dom):.3g} roi {np.mean(keys_roi):.3g}; roi tiles {np.mean(roi_tiles):.0f}/{n_tiles}")
 
     ctx.set_count_pairs(True)
-    pe_dom, pu_dom, pe_roi, pu_roi = [], [], [], []
+    pe_dom, pu_dom, pe_roi, pu_roi, work_dom, work_roi = [], [], [], [], [], []
     for cd, ca in zip(cams, affs):
         out = ctx.render_stereo(ds, cd, ca, raster, roi, out=out)
         st = out["stats"]
@@ -118,7 +118,13 @@ def main():
         pu_dom.append(st["pairs_used_dom"])
         pe_roi.append(st["pairs_eval_roi"])
         pu_roi.append(st["pairs_used_roi"])
+        work_dom.append(st["blend_work_dom"])
+        work_roi.append(st["blend_work_roi"])
     ctx.set_count_pairs(False)
+    wd, wr = np.mean(work_dom, axis=0), np.mean(work_roi, axis=0)
+    log(f"blend work dom: walked {wd[0]:.3g} tested {wd[1]:.3g} lane-eff {np.mean(pe_dom) / max(wd[1], 1) / 64:.3f} "
+        f"max wave walk {wd[2]:.0f} max list {wd[3]:.0f}; roi: walked {wr[0]:.3g} tested {wr[1]:.3g} "
+        f"max wave walk {wr[2]:.0f} max list {wr[3]:.0f}")
 
     # ---- timed: ours ----
     ctx.set_sync(False)
@@ -183,6 +189,8 @@ def main():
                 "traffic": None, "avg_launch_ms": round(blend_ms, 4),
                 "pairs_evaluated_per_launch": int(np.mean(pe_dom)),
                 "pairs_contributing_per_launch": int(np.mean(pu_dom)),
+                "records_walked_per_launch": int(wd[0]), "records_tested_per_launch": int(wd[1]),
+                "longest_wave_walk": int(wd[2]), "longest_tile_list": int(wd[3]),
                 "largest_stage": dominant}
 
     # ---- CPU oracle on a bounded sample (a baseline only) ----

@@ -138,8 +138,11 @@ typedef struct bgs_stats {
     int32_t overflow;
     int32_t reserved;
     /* Only with bgs_ctx_set_count_pairs(ctx, 1): (pixel, surfel) pairs the
-     * blend evaluated, and those that contributed to a pixel. */
+     * blend evaluated, and those that contributed to a pixel; and the blend's
+     * work shape {records walked summed over waves, records that passed a
+     * wave's strip test, longest walk of one wave, longest tile list}. */
     int64_t pairs_eval_dom, pairs_used_dom, pairs_eval_roi, pairs_used_roi;
+    int64_t blend_work_dom[4], blend_work_roi[4];
 } bgs_stats;
 
 typedef struct bgs_ctx bgs_ctx;
@@ -156,6 +159,18 @@ BGS_API const char* bgs_last_error(const bgs_ctx* ctx);
 /* count = 1: the blend kernels also count evaluated and contributing
  * (pixel, surfel) pairs into bgs_stats (slower; for measurement only). */
 BGS_API int32_t bgs_ctx_set_count_pairs(bgs_ctx* ctx, int32_t count);
+
+/* Scheduling of long tile lists in the blend (the pixels do not depend on
+ * it beyond fp32 rounding of the composited sums).  A tile first composites
+ * at most cap records of its list; if pixels are still unsaturated, the rest
+ * of the list is split into up to 8 segments of at least seg_len records
+ * that other workgroups composite at once, each from full transmittance, and
+ * the segments are then chained front to back (a segment inside which a
+ * pixel would reach the termination threshold is composited again in order
+ * from that pixel's running state).  cap = 0 composites every list in one
+ * pass.  Defaults: cap 768, seg_len 384.  Returns BGS_ERR_INVALID_ARG for
+ * cap < 0 or seg_len < 1. */
+BGS_API int32_t bgs_ctx_set_blend_split(bgs_ctx* ctx, int32_t cap, int32_t seg_len);
 
 /* Per-stage GPU timing with HIP events recorded on the context's stream
  * around each stage's launches.  on = 1 enables it and clears the totals.
@@ -281,6 +296,14 @@ BGS_API int32_t bgs_label_components(bgs_ctx* ctx, const uint8_t* mask, int32_t 
 BGS_API int32_t bgs_preprocess_debug(bgs_ctx* ctx, const bgs_scene* scene, const bgs_camera* cam,
                                      const bgs_raster_params* raster, void* ws, size_t ws_bytes, uint32_t* zkey,
                                      int32_t* rects, uint32_t* counts);
+
+/* Per-tile trace of the last dominant-eye blend run with pair counting on
+ * (bgs_ctx_set_count_pairs): for each launched block, 6 int64 {tile, list
+ * length, longest wave walk, CU id, start, end (wall clock, 100 MHz)}.
+ * n, width, height are those the workspace was laid out for.  Waits for
+ * the stream.  Measurement only. */
+BGS_API int32_t bgs_blend_trace(bgs_ctx* ctx, int64_t n, int32_t width, int32_t height, void* ws, size_t ws_bytes,
+                                int64_t* out);
 
 /* Binned and sorted tile lists of Stage 1: ranges[n_tiles][2] = [start,
  * end) into values, values[key_capacity] = surfel indices in compositing

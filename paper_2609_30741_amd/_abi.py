@@ -44,7 +44,8 @@ class Stats(C.Structure):
                 ("n_gap", C.c_int32), ("n_center", C.c_int32), ("n_rowfill", C.c_int32),
                 ("n_boxes", C.c_int32), ("n_roi_tiles", C.c_int32), ("overflow", C.c_int32),
                 ("reserved", C.c_int32), ("pairs_eval_dom", C.c_int64), ("pairs_used_dom", C.c_int64),
-                ("pairs_eval_roi", C.c_int64), ("pairs_used_roi", C.c_int64)]
+                ("pairs_eval_roi", C.c_int64), ("pairs_used_roi", C.c_int64),
+                ("blend_work_dom", C.c_int64 * 4), ("blend_work_roi", C.c_int64 * 4)]
 
 
 STAGES = ["preprocess_dom", "depth_sort_dom", "emit_dom", "tile_sort_dom", "ranges_dom", "blend_dom",
@@ -57,7 +58,7 @@ EXPORTS = [
     "bgs_workspace_size", "bgs_poll_status", "bgs_render_dominant", "bgs_reproject", "bgs_classify_holes",
     "bgs_patch_rois", "bgs_render_stereo", "bgs_sort_workspace_size", "bgs_sort_pairs",
     "bgs_label_components", "bgs_preprocess_debug", "bgs_tile_lists_debug", "bgs_ctx_set_count_pairs",
-    "bgs_ctx_set_timing", "bgs_timing_collect",
+    "bgs_ctx_set_timing", "bgs_timing_collect", "bgs_blend_trace", "bgs_ctx_set_blend_split",
 ]
 
 _lib = None
@@ -79,6 +80,7 @@ def load():
         "bgs_ctx_set_sync": [P, I32],
         "bgs_ctx_set_count_pairs": [P, I32],
         "bgs_ctx_set_timing": [P, I32],
+        "bgs_ctx_set_blend_split": [P, I32, I32],
         "bgs_timing_collect": [P, P, P],
         "bgs_workspace_size": [I64, I32, I32, I64, C.POINTER(SZ)],
         "bgs_poll_status": [P, P, SZ, C.POINTER(Stats)],
@@ -93,6 +95,7 @@ def load():
         "bgs_render_stereo": [P, C.POINTER(Scene), C.POINTER(Camera), C.POINTER(Camera), C.POINTER(RasterParams),
                               C.POINTER(RoiParams), P, SZ, P, P, P, P, P, P, P, P, P, I32, P, P, C.POINTER(Stats)],
         "bgs_sort_workspace_size": [I64, C.POINTER(SZ)],
+        "bgs_blend_trace": [P, I64, I32, I32, P, SZ, P],
         "bgs_sort_pairs": [P, P, P, I64, I32, P, SZ],
         "bgs_label_components": [P, P, I32, I32, I32, P],
         "bgs_preprocess_debug": [P, C.POINTER(Scene), C.POINTER(Camera), C.POINTER(RasterParams), P, SZ, P, P, P],

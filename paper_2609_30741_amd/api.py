@@ -73,6 +73,14 @@ def camera(cam) -> _abi.Camera:
     return c
 
 
+def _stats_dict(st):
+    d = {}
+    for f, _ in _abi.Stats._fields_:
+        v = getattr(st, f)
+        d[f] = [int(x) for x in v] if hasattr(v, "__len__") else int(v)
+    return d
+
+
 def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else None
 
@@ -125,6 +133,11 @@ class Context:
     def set_count_pairs(self, on: bool):
         self._check(self.L.bgs_ctx_set_count_pairs(self.h, int(bool(on))))
 
+    def set_blend_split(self, cap: int, seg_len: int = 384):
+        """Long-list scheduling of the blend: cap records per tile before the
+        rest is split into segments of >= seg_len records (cap 0: no split)."""
+        self._check(self.L.bgs_ctx_set_blend_split(self.h, int(cap), int(seg_len)))
+
     def set_timing(self, on: bool):
         """Enable per-stage HIP-event timing on this context's stream (clears totals)."""
         self._check(self.L.bgs_ctx_set_timing(self.h, int(bool(on))))
@@ -138,10 +151,19 @@ class Context:
         self._check(self.L.bgs_timing_collect(self.h, tot, cnt))
         return {name: (tot[i], cnt[i]) for i, name in enumerate(_abi.STAGES)}
 
+    def blend_trace(self, n, W, H):
+        """Per-tile trace of the last counting-mode dominant blend:
+        (tile, list length, longest wave walk, CU, start, end) rows."""
+        nt = ((W + 15) // 16) * ((H + 15) // 16)
+        out = np.zeros((nt, 6), np.int64)
+        self._check(self.L.bgs_blend_trace(self.h, int(n), int(W), int(H), _ptr(self.ws), self.ws.numel(),
+                                           out.ctypes.data_as(C.c_void_p)))
+        return out
+
     def poll_status(self):
         st = _abi.Stats()
         self._check(self.L.bgs_poll_status(self.h, _ptr(self.ws), self.ws.numel(), C.byref(st)))
-        return {f: int(getattr(st, f)) for f, _ in _abi.Stats._fields_}
+        return _stats_dict(st)
 
     def _check(self, rc):
         if rc != 0:
@@ -286,7 +308,7 @@ class Context:
             self.workspace(scene.n, W, H, int(need * 1.25) + 1024)
         self._check(rc)
         if self.sync:
-            out["stats"] = {f: int(getattr(st, f)) for f, _ in _abi.Stats._fields_}
+            out["stats"] = _stats_dict(st)
         return out
 
     # -- stage-level exports ------------------------------------------------

@@ -15,6 +15,8 @@ struct bgs_ctx {
     int sync = 1;
     int count_pairs = 0;
     int timing = 0;
+    uint32_t blend_cap = 768;      // records a tile walks before splitting the rest (0: never split)
+    uint32_t blend_seg_len = 384;  // least records per continuation segment
     hipEvent_t ev[BGS_NUM_STAGES][2] = {};
     bool pending[BGS_NUM_STAGES] = {};
     double total_ms[BGS_NUM_STAGES] = {};
@@ -26,6 +28,12 @@ namespace bgs {
 namespace {
 
 constexpr size_t kAlign = 256;
+// Long tile lists: a tile walks the context's blend_cap records, then hands
+// the rest to up to kContSeg segment blocks of at least blend_seg_len records
+// each; at most kContSlots tiles per pass are continued this way.
+constexpr int64_t kContSlots = 512;
+constexpr uint32_t kContSeg = 8;
+
 inline size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 // Workspace layout.  Regions that depend only on the image size come first
@@ -34,11 +42,14 @@ inline size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 // is whatever the remaining bytes hold.
 struct Layout {
     size_t status;
-    size_t zbuf, rgb2, z2, a2, hole, hole2, flags, bbox, pix_scan;
+    size_t zbuf, hole, hole2, flags, bbox, pix_scan, pflag, pbox;
     size_t ranges, mask32, mprefix, tlist, tile_scan, torder;
     size_t recs, zkeys, rects, counts, dkeys_b, dvals_a, dvals_b, offs, surf_scan;
     size_t tkeys_a, tkeys_b, tvals_a, tvals_b;
     size_t radix;
+    size_t trace;  // per-tile blend trace of the last counting-mode dominant pass
+    size_t cdesc, cdone, cstate1, cseg;  // long-list continuation (slots x segments)
+    int64_t cslots;
     size_t total;
 };
 
@@ -54,14 +65,13 @@ Layout make_layout(int64_t n, int64_t W, int64_t H, int64_t kc) {
     const int64_t nt = ((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile);
     L.status = take(sizeof(DevStatus));
     L.zbuf = take(8 * np);
-    L.rgb2 = take(12 * np);
-    L.z2 = take(4 * np);
-    L.a2 = take(4 * np);
     L.hole = take(np);
     L.hole2 = take(np);
     L.flags = take(4 * (np + 1));
     L.bbox = take(16 * np);
     L.pix_scan = take(4 * scan_tmp_elems(np));
+    L.pflag = take(np);
+    L.pbox = take(16 * np);
     L.ranges = take(8 * nt);
     L.mask32 = take(4 * nt);
     L.mprefix = take(4 * (nt + 1));
@@ -82,6 +92,12 @@ Layout make_layout(int64_t n, int64_t W, int64_t H, int64_t kc) {
     L.tvals_a = take(4 * kc);
     L.tvals_b = take(4 * kc);
     L.radix = take(radix_tmp_bytes(kc > n ? kc : n));
+    L.trace = take(6 * 8 * nt);
+    L.cslots = nt < kContSlots ? nt : kContSlots;
+    L.cdesc = take(16 * L.cslots);
+    L.cdone = take(4 * L.cslots);
+    L.cstate1 = take(32 * 256 * L.cslots);
+    L.cseg = take(32 * 256 * kContSeg * L.cslots);
     L.total = o;
     return L;
 }
@@ -242,8 +258,12 @@ void fill_stats(const DevStatus& h, bgs_stats* s) {
     s->reserved = 0;
     s->pairs_eval_dom = (int64_t)h.pairs[0];
     s->pairs_used_dom = (int64_t)h.pairs[1];
-    s->pairs_eval_roi = (int64_t)h.pairs[2];
-    s->pairs_used_roi = (int64_t)h.pairs[3];
+    s->pairs_eval_roi = (int64_t)h.pairs[6];
+    s->pairs_used_roi = (int64_t)h.pairs[7];
+    for (int i = 0; i < 4; ++i) {
+        s->blend_work_dom[i] = (int64_t)h.pairs[2 + i];
+        s->blend_work_roi[i] = (int64_t)h.pairs[8 + i];
+    }
 }
 
 struct RasterOut {
@@ -254,8 +274,12 @@ struct RasterOut {
 };
 
 // Stage 1 for one camera, optionally restricted to the tiles of tile_mask.
+// reuse_order: the compositing order of an earlier pass whose centre-depth
+// keys are bit-identical to this camera's (null: sort here).  *order_out
+// receives the order used.
 int raster_pass(bgs_ctx* ctx, const Layout& L, void* ws, int64_t kc, const bgs_scene& scene, const bgs_camera& cam,
-                const bgs_raster_params& rp, const uint8_t* tile_mask, float a_min, const RasterOut& out, int which) {
+                const bgs_raster_params& rp, const uint8_t* tile_mask, float a_min, const RasterOut& out, int which,
+                const uint32_t* reuse_order = nullptr, const uint32_t** order_out = nullptr) {
     hipStream_t s = ctx->stream;
     const int n = (int)scene.n;
     const PreCam pc = make_precam(cam);
@@ -282,12 +306,16 @@ int raster_pass(bgs_ctx* ctx, const Layout& L, void* ws, int64_t kc, const bgs_s
     // Compositing order: surfels sorted by (fp32 centre-depth bits, index).
     mark(ctx, sb + 1, 0);
     bool in_b = false;
-    uint32_t* dva = at<uint32_t>(ws, L.dvals_a);
-    uint32_t* dvb = at<uint32_t>(ws, L.dvals_b);
-    HIP_CHECK(radix_sort(zkeys, dva, at<uint32_t>(ws, L.dkeys_b), dvb, nullptr, n, 32, true, at<void>(ws, L.radix), s,
-                         &in_b),
-              "depth sort");
-    const uint32_t* order = in_b ? dvb : dva;
+    const uint32_t* order = reuse_order;
+    if (!order) {
+        uint32_t* dva = at<uint32_t>(ws, L.dvals_a);
+        uint32_t* dvb = at<uint32_t>(ws, L.dvals_b);
+        HIP_CHECK(radix_sort(zkeys, dva, at<uint32_t>(ws, L.dkeys_b), dvb, nullptr, n, 32, true,
+                             at<void>(ws, L.radix), s, &in_b),
+                  "depth sort");
+        order = in_b ? dvb : dva;
+    }
+    if (order_out) *order_out = order;
     mark(ctx, sb + 1, 1);
     mark(ctx, sb + 2, 0);
     HIP_CHECK(exclusive_scan(counts, order, offs, nullptr, n, at<uint32_t>(ws, L.surf_scan), s), "count scan");
@@ -326,10 +354,14 @@ int raster_pass(bgs_ctx* ctx, const Layout& L, void* ws, int64_t kc, const bgs_s
     ba.a_min = a_min;
     ba.z_near = (float)cam.z_near;
     ba.patch = tile_mask ? 1 : 0;
+    ba.cap = ctx->blend_cap;
+    ContArgs ca{&st->n_cont, at<uint4>(ws, L.cdesc), at<uint32_t>(ws, L.cdone), at<float4>(ws, L.cstate1),
+                at<float4>(ws, L.cseg), ctx->blend_cap ? (uint32_t)L.cslots : 0u, kContSeg, ctx->blend_seg_len};
     mark(ctx, sb + 5, 0);
     HIP_CHECK(launch_blend(recs, svals, ranges, tile_mask ? at<uint32_t>(ws, L.tlist) : nullptr, torder,
-                           tile_mask ? &st->n_masked : nullptr, n_tiles, ba, out.rgb, out.dz, out.alpha, out.cls,
-                           ctx->count_pairs ? &st->pairs[2 * which] : nullptr, s),
+                           tile_mask ? &st->n_masked : nullptr, n_tiles, ba, ca, out.rgb, out.dz, out.alpha, out.cls,
+                           ctx->count_pairs ? &st->pairs[6 * which] : nullptr,
+                           (ctx->count_pairs && which == 0) ? at<long long>(ws, L.trace) : nullptr, s),
               "blend");
     mark(ctx, sb + 5, 1);
     return BGS_OK;
@@ -384,6 +416,14 @@ const char* bgs_last_error(const bgs_ctx* ctx) { return ctx ? ctx->err.c_str() :
 int32_t bgs_ctx_set_count_pairs(bgs_ctx* ctx, int32_t count) {
     if (!ctx) return BGS_ERR_INVALID_ARG;
     ctx->count_pairs = count ? 1 : 0;
+    return BGS_OK;
+}
+
+int32_t bgs_ctx_set_blend_split(bgs_ctx* ctx, int32_t cap, int32_t seg_len) {
+    if (!ctx) return BGS_ERR_INVALID_ARG;
+    if (cap < 0 || seg_len < 1) return fail(ctx, BGS_ERR_INVALID_ARG, "blend split: need cap >= 0 and seg_len >= 1");
+    ctx->blend_cap = (uint32_t)cap;
+    ctx->blend_seg_len = (uint32_t)seg_len;
     return BGS_OK;
 }
 
@@ -506,9 +546,9 @@ int32_t bgs_classify_holes(bgs_ctx* ctx, const bgs_camera* src, const bgs_camera
         return fail(ctx, BGS_ERR_INVALID_ARG, "null buffer or negative box capacity");
     const Layout L = make_layout(0, dst->width, dst->height, 0);
     if (L.total > ws_bytes) return fail(ctx, BGS_ERR_WORKSPACE, "workspace of %zu bytes is too small", ws_bytes);
-    ClassifyBufs b{at<float>(ws, L.rgb2), at<float>(ws, L.z2), at<float>(ws, L.a2), at<uint8_t>(ws, L.hole),
-                   at<uint8_t>(ws, L.hole2), at<uint32_t>(ws, L.flags), at<int32_t>(ws, L.bbox),
-                   at<uint32_t>(ws, L.pix_scan)};
+    ClassifyBufs b{at<uint8_t>(ws, L.hole), at<uint8_t>(ws, L.hole2), at<uint32_t>(ws, L.flags),
+                   at<int32_t>(ws, L.bbox), at<uint32_t>(ws, L.pix_scan), at<uint8_t>(ws, L.pflag),
+                   at<int4>(ws, L.pbox)};
     HIP_CHECK(launch_classify(make_warpcam(*src), make_warpcam(*dst), rel_pose(*src, *dst), *roi, raster->bg,
                               depth_range, rgb_dst, z_dst, alpha_dst, cls, labels, boxes, box_capacity, n_boxes,
                               tile_mask, b, at<DevStatus>(ws, L.status), ctx->stream),
@@ -566,9 +606,16 @@ int32_t bgs_render_stereo(bgs_ctx* ctx, const bgs_scene* scene, const bgs_camera
     DevStatus* st = at<DevStatus>(ws, L.status);
     HIP_CHECK(hipMemsetAsync(st, 0, sizeof(DevStatus), s), "status reset");
     // Stage 1: dominant eye with the depth proxy.
+    const uint32_t* dom_order = nullptr;
     rc = raster_pass(ctx, L, ws, kc, *scene, *cam_dom, *raster, nullptr, 0.f,
-                     RasterOut{rgb_dom, depth_raw_dom, alpha_dom, nullptr}, 0);
+                     RasterOut{rgb_dom, depth_raw_dom, alpha_dom, nullptr}, 0, nullptr, &dom_order);
     if (rc) return rc;
+    // The affiliated eye's compositing order equals the dominant one when
+    // their fp32 centre-depth key coefficients and near planes coincide bit
+    // for bit (same orientation, offset perpendicular to the optical axis):
+    // every surfel then gets the same key, so the depth sort is reused.
+    const PreCam pd = make_precam(*cam_dom), pa = make_precam(*cam_aff);
+    const bool same_keys = std::memcmp(pd.zc, pa.zc, sizeof pd.zc) == 0 && pd.z_near == pa.z_near;
     // Stage 2: reprojection.  The hole mask is written straight into cls.
     const WarpCam wd = make_warpcam(*cam_dom), wa = make_warpcam(*cam_aff);
     const RelPose P = rel_pose(*cam_dom, *cam_aff);
@@ -579,9 +626,9 @@ int32_t bgs_render_stereo(bgs_ctx* ctx, const bgs_scene* scene, const bgs_camera
               "reproject");
     mark(ctx, BGS_STAGE_REPROJECT, 1);
     // Stage 3: hole classification and interpolation.
-    ClassifyBufs b{at<float>(ws, L.rgb2), at<float>(ws, L.z2), at<float>(ws, L.a2), at<uint8_t>(ws, L.hole),
-                   at<uint8_t>(ws, L.hole2), at<uint32_t>(ws, L.flags), at<int32_t>(ws, L.bbox),
-                   at<uint32_t>(ws, L.pix_scan)};
+    ClassifyBufs b{at<uint8_t>(ws, L.hole), at<uint8_t>(ws, L.hole2), at<uint32_t>(ws, L.flags),
+                   at<int32_t>(ws, L.bbox), at<uint32_t>(ws, L.pix_scan), at<uint8_t>(ws, L.pflag),
+                   at<int4>(ws, L.pbox)};
     mark(ctx, BGS_STAGE_CLASSIFY, 0);
     HIP_CHECK(launch_classify(wd, wa, P, *roi, raster->bg, depth_range, rgb_aff, z_aff, alpha_aff, cls_aff, labels, boxes,
                               box_capacity, n_boxes, tile_mask, b, st, s),
@@ -589,7 +636,7 @@ int32_t bgs_render_stereo(bgs_ctx* ctx, const bgs_scene* scene, const bgs_camera
     mark(ctx, BGS_STAGE_CLASSIFY, 1);
     // Stage 4: ROI re-rasterisation of the affiliated eye.
     rc = raster_pass(ctx, L, ws, kc, *scene, *cam_aff, *raster, tile_mask, roi->a_min,
-                     RasterOut{rgb_aff, z_aff, alpha_aff, cls_aff}, 1);
+                     RasterOut{rgb_aff, z_aff, alpha_aff, cls_aff}, 1, same_keys ? dom_order : nullptr);
     if (rc) return rc;
     if (!ctx->sync && !stats) return BGS_OK;
     DevStatus h{};
@@ -598,6 +645,20 @@ int32_t bgs_render_stereo(bgs_ctx* ctx, const bgs_scene* scene, const bgs_camera
     if (h.overflow & 1u)
         return fail(ctx, BGS_ERR_CAPACITY, "tile keys (%u dominant, %u ROI) exceed the capacity of %lld", h.n_keys_dom,
                     h.n_keys_roi, (long long)kc);
+    return BGS_OK;
+}
+
+int32_t bgs_blend_trace(bgs_ctx* ctx, int64_t n, int32_t width, int32_t height, void* ws, size_t ws_bytes,
+                        int64_t* out) {
+    if (!ctx) return BGS_ERR_INVALID_ARG;
+    if (!ws || !out || width < 1 || height < 1 || n < 0) return fail(ctx, BGS_ERR_INVALID_ARG, "bad argument");
+    const int64_t kc = key_capacity_for(n, width, height, ws_bytes);
+    if (kc < 0) return fail(ctx, BGS_ERR_WORKSPACE, "workspace too small");
+    const Layout L = make_layout(n, width, height, kc);
+    const int64_t nt = ((width + kTile - 1) / kTile) * (int64_t)((height + kTile - 1) / kTile);
+    HIP_CHECK(hipMemcpyAsync(out, at<long long>(ws, L.trace), 6 * 8 * (size_t)nt, hipMemcpyDeviceToHost, ctx->stream),
+              "trace copy");
+    HIP_CHECK(hipStreamSynchronize(ctx->stream), "sync");
     return BGS_OK;
 }
 
@@ -697,7 +758,9 @@ int32_t bgs_tile_lists_debug(bgs_ctx* ctx, const bgs_scene* scene, const bgs_cam
     // A render whose outputs go to scratch pixel buffers; the binning it
     // leaves in the workspace is what is copied out.
     const int64_t np = (int64_t)cam->width * cam->height;
-    float* scratch = at<float>(ws, L.rgb2);
+    // Scratch outputs: rgb in the piece-box region (16 B/px), depth and
+    // alpha in the z-buffer (8 B/px).
+    float* scratch = at<float>(ws, L.pbox);
     rc = raster_pass(ctx, L, ws, kc, *scene, *cam, *raster, nullptr, 0.f,
                      RasterOut{scratch, at<float>(ws, L.zbuf), at<float>(ws, L.zbuf) + np, nullptr}, 0);
     if (rc) return rc;

@@ -71,6 +71,19 @@ struct BlendArgs {
     float a_min;     // patch mode: depth proxy written only when A >= a_min
     float z_near;
     int patch;       // 0: write rgb/depth_raw/alpha; 1: write rgb/z/alpha/cls
+    uint32_t cap;    // records a tile walks before it may hand its rest to segment blocks
+};
+
+// Continuation of long tile lists (see k_blend / k_blend_cont).
+struct ContArgs {
+    uint32_t* n_slots;   // device counter of slots taken
+    uint4* desc;         // per slot: compact tile id, first record, end record, segments
+    uint32_t* done;      // per slot: segment blocks finished
+    float4* state1;      // per slot: 256 pixels x 2 float4 after the capped walk
+    float4* seg_state;   // per slot and segment: 256 pixels x 2 float4
+    uint32_t max_slots;  // 0 disables continuation
+    uint32_t max_seg;
+    uint32_t seg_len;    // records per segment (at most max_seg segments)
 };
 
 // Device status block kept in the workspace.
@@ -78,13 +91,18 @@ struct DevStatus {
     uint32_t n_keys;       // keys of the last binning (may exceed capacity)
     uint32_t n_sort;       // min(n_keys, capacity): keys actually sorted
     uint32_t n_masked;     // masked tiles of the last ROI patch
+    uint32_t n_cont;       // continuation slots requested by the last blend
     uint32_t n_keys_dom;
     uint32_t n_keys_roi;
     uint32_t overflow;     // bit 0 key capacity, bit 1 box capacity
     uint32_t n_holes, n_gap, n_center, n_rowfill, n_boxes, n_roi_tiles, n_edge, pad;
     uint32_t dmin_bits, dmax_bits;  // depth-range reduction (positive fp32 bits)
     uint32_t pad2[2];
-    unsigned long long pairs[4];  // evaluated, contributing (dominant), then ROI; counting mode only
+    // Counting mode only, dominant then ROI pass, 6 each: evaluated pairs,
+    // contributing pairs, records walked (summed over waves), records past
+    // the strip test (summed over waves), longest walk of one wave, longest
+    // tile list.
+    unsigned long long pairs[12];
     int32_t edge_boxes[4 * 6];
     int32_t widths[4];
 };
@@ -118,11 +136,11 @@ hipError_t launch_tile_order(const uint2* ranges, const uint32_t* n_live, int n_
                              hipStream_t s);
 // One block per (compact) tile, in `order`; n_live (device, optional) limits
 // the blocks that do work when the tile count is only known on the device.
-// pair_counts (optional): {evaluated, contributing} pair counters.
+// pair_counts (optional): the six blend counters of DevStatus::pairs.
 hipError_t launch_blend(const SurfelRec* recs, const uint32_t* vals, const uint2* ranges,
                         const uint32_t* tile_list, const uint32_t* order, const uint32_t* n_live, int n_blocks,
-                        const BlendArgs& a, float* rgb, float* d_or_z, float* alpha, uint8_t* cls,
-                        unsigned long long* pair_counts, hipStream_t s);
+                        const BlendArgs& a, const ContArgs& ca, float* rgb, float* d_or_z, float* alpha, uint8_t* cls,
+                        unsigned long long* pair_counts, long long* trace, hipStream_t s);
 // prefix[n_tiles + 1] and the compact list of masked tile ids; tmp32 holds
 // n_tiles words, scan_tmp scan_tmp_elems(n_tiles) words.
 hipError_t launch_mask_prefix(const uint8_t* tile_mask, int n_tiles, uint32_t* tmp32, uint32_t* prefix,
@@ -146,14 +164,13 @@ hipError_t launch_reproject(const WarpCam& src, const WarpCam& dst, const RelPos
                             float* rgb_dst, float* z_dst, float* alpha_dst, uint8_t* hole, float* depth_range,
                             DevStatus* st, hipStream_t s);
 struct ClassifyBufs {
-    float* rgb2;
-    float* z2;
-    float* a2;
-    uint8_t* hole;
-    uint8_t* hole2;
+    uint8_t* hole;     // interpolation tags
+    uint8_t* hole2;    // center-hole mask
     uint32_t* flags;   // root flags -> slots (exclusive scan), n + 1
     int32_t* bbox;     // 4 per component
     uint32_t* scan_tmp;
+    uint8_t* pflag;    // block-local piece roots
+    int4* pbox;        // piece boxes, indexed by root pixel
 };
 hipError_t launch_classify(const WarpCam& src, const WarpCam& dst, const RelPose& P, const bgs_roi_params& roi,
                            const float bg[3], const float* depth_range, float* rgb, float* z, float* alpha,

@@ -279,18 +279,31 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order
     }
 }
 
+// [start, end) of every tile in the sorted keys, by binary search (a tile
+// with no key gets an empty range).
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_dev,
                                                 uint2* __restrict__ ranges, uint32_t n_tiles) {
-    const uint32_t n = *n_dev;
-    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t t = keys[i];
+    const uint32_t t = blockIdx.x * 256 + threadIdx.x;
     if (t >= n_tiles) return;
-    if (i == 0 || keys[i - 1] != t) ranges[t].x = i;
-    if (i == n - 1 || keys[i + 1] != t) ranges[t].y = i + 1;
+    const uint32_t n = *n_dev;
+    uint32_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (keys[mid] < t) lo = mid + 1;
+        else hi = mid;
+    }
+    const uint32_t start = lo;
+    hi = n;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (keys[mid] <= t) lo = mid + 1;
+        else hi = mid;
+    }
+    ranges[t] = make_uint2(start, lo);
 }
 
 __global__ void k_status_keys(const uint32_t* __restrict__ offs, int n, DevStatus* st, uint32_t cap, int which) {
+    st->n_cont = 0;
     const uint32_t K = offs[n];
     st->n_keys = K;
     st->n_sort = K < cap ? K : cap;
@@ -313,6 +326,46 @@ __global__ __launch_bounds__(256) void k_mask_list(const uint8_t* __restrict__ m
         st->n_masked = prefix[n];
         st->n_roi_tiles = prefix[n];
     }
+}
+
+// One (pixel, surfel) step of front-to-back compositing (Eq. 2 with the
+// plane homography of the record), branch-free: alpha = min(alpha_max,
+// o * max(G3, G2)); a pair below alpha_min is skipped; the pixel stops
+// before the surfel that would take T below t_min; otherwise RGB, the depth
+// proxy D and A accumulate with the same weight w = alpha * T.
+__device__ __forceinline__ void composite(const float4& r0, const float4& r1, const float4& r2, const float4& r3,
+                                          float fpx, float fpy, const BlendArgs& a, bool& live, float& T, float& c0,
+                                          float& c1, float& c2, float& D, float& A, uint32_t& n_eval,
+                                          uint32_t& n_used, bool count) {
+    const float dx = fpx - r0.x, dy = fpy - r0.y;
+    const float den = fmaf(r1.z, dx, fmaf(r1.w, dy, 1.f));
+    const float w = __builtin_amdgcn_rcpf(den);
+    const float u = fmaf(r0.z, dx, r0.w * dy) * w;
+    const float v = fmaf(r1.x, dx, r1.y * dy) * w;
+    const float lam = r2.x * w;
+    // lam <= z_near covers hits behind the camera and edge-on records; a
+    // non-finite u, v near the plane's horizon gives -inf or NaN, and
+    // fmaxf then keeps the low-pass term.
+    const float e3 = lam > a.z_near ? -0.5f * fmaf(u, u, v * v) : -INFINITY;
+    const float e2 = a.lowpass ? -fmaf(dx, dx, dy * dy) : -INFINITY;
+    const float e = fmaxf(e3, e2);
+    const float al = fminf(a.alpha_max, r2.z * __expf(e));
+    const float Tn = T * (1.f - al);
+    const bool use = live && al >= a.alpha_min;
+    const bool stop = use && Tn < a.t_min;
+    const bool add = use && !stop;
+    const float wt = add ? al * T : 0.f;
+    if (count) {
+        n_eval += live ? 1u : 0u;
+        n_used += add ? 1u : 0u;
+    }
+    c0 = fmaf(wt, r3.x, c0);
+    c1 = fmaf(wt, r3.y, c1);
+    c2 = fmaf(wt, r3.z, c2);
+    D = fmaf(wt, (e3 >= e2) ? lam : r2.y, D);
+    A += wt;
+    T = add ? Tn : T;
+    live = live && !stop;
 }
 
 // ---------------------------------------------------------------------------
@@ -350,133 +403,304 @@ __global__ __launch_bounds__(1024) void k_tile_order(const uint2* __restrict__ r
 }
 
 // ---------------------------------------------------------------------------
-// Blend: one 256-thread block per 16x16 tile; wave w owns the 16x4 strip of
-// rows 4w..4w+3.  The tile's sorted list is consumed in batches of 256
-// records: every thread fetches one record with vector loads (the next
-// batch is fetched while the current one is composited), the batch is put
-// in LDS, and each wave walks it with broadcast LDS reads, skipping records
-// whose pixel box misses its strip.  A wave stops compositing once all its
-// pixels are done; the block stops at the first batch boundary where all
-// 256 pixels are done.
+// Blend.  One 256-thread block per 16x16 tile; wave w owns the 16x4 strip of
+// rows 4w..4w+3.  walk_range composites the records [b, e) of the tile's
+// sorted list into the block's pixels: batches of 256 records are fetched
+// by all threads with vector loads (the next batch while the current one is
+// composited) and put in LDS; each wave tests the whole batch against its
+// strip in one vector pass (a 256-bit mask) and then evaluates only the
+// records that can touch it, two per trip.  The walk ends at the first
+// batch boundary where all 256 pixels are done.  Every thread of the block
+// must call it (it has block barriers).
 // ---------------------------------------------------------------------------
-template <bool kCount>
-__global__ __launch_bounds__(256) void k_blend(const SurfelRec* __restrict__ recs, const uint32_t* __restrict__ vals,
-                                               const uint2* __restrict__ ranges, const uint32_t* __restrict__ tile_list,
-                                               const uint32_t* __restrict__ order,
-                                               const uint32_t* __restrict__ n_live, BlendArgs a,
-                                               float* __restrict__ rgb, float* __restrict__ dz,
-                                               float* __restrict__ alpha, uint8_t* __restrict__ cls,
-                                               unsigned long long* __restrict__ pair_counts) {
-    __shared__ float4 s_rec[256 * 4];
-    const uint32_t blk = blockIdx.x;
-    if (n_live && blk >= *n_live) return;
-    const uint32_t cid = order ? order[blk] : blk;
-    const uint32_t tile = tile_list ? tile_list[cid] : cid;
-    const int tx = (int)(tile % (uint32_t)a.tiles_x), ty = (int)(tile / (uint32_t)a.tiles_x);
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int px = tx * kTile + (lane & 15);
-    const int py = ty * kTile + wave * 4 + (lane >> 4);
-    const bool inside = px < a.W && py < a.H;
-    const float fpx = (float)px, fpy = (float)py;
-    const int sx0 = tx * kTile, sx1 = sx0 + kTile - 1, sy0 = ty * kTile + wave * 4, sy1 = sy0 + 3;
-    const uint2 rg = ranges[cid];
-    float T = 1.f, c0 = 0.f, c1 = 0.f, c2 = 0.f, D = 0.f, A = 0.f;
-    bool live = inside;
-    uint32_t n_eval = 0, n_used = 0;
+struct PixelState {
+    float T, c0, c1, c2, D, A;
+    bool live;
+};
 
+struct WalkCounts {
+    uint32_t eval, used, walk, test;
+};
+
+struct TileGeom {
+    int tid, lane, sx0, sx1, sy0, sy1;
+    float fpx, fpy;
+};
+
+template <bool kCount>
+__device__ __forceinline__ void walk_range(const SurfelRec* __restrict__ recs, const uint32_t* __restrict__ vals,
+                                           uint32_t b, uint32_t e, float4* s_rec, const TileGeom& g,
+                                           const BlendArgs& a, PixelState& p, WalkCounts& wc) {
     float4 q0, q1, q2, q3;
     {
-        const uint32_t pos = rg.x + tid;
-        if (pos < rg.y) {
+        const uint32_t pos = b + g.tid;
+        if (pos < e) {
             const SurfelRec* r = recs + vals[pos];
             q0 = r->a; q1 = r->b; q2 = r->c; q3 = r->d;
         }
     }
-    for (uint32_t base = rg.x; base < rg.y; base += 256) {
-        const uint32_t nb = min(256u, rg.y - base);
+    for (uint32_t base = b; base < e; base += 256) {
+        const uint32_t nb = min(256u, e - base);
         __syncthreads();
-        if ((uint32_t)tid < nb) {
-            s_rec[4 * tid + 0] = q0;
-            s_rec[4 * tid + 1] = q1;
-            s_rec[4 * tid + 2] = q2;
-            s_rec[4 * tid + 3] = q3;
+        if ((uint32_t)g.tid < nb) {
+            s_rec[4 * g.tid + 0] = q0;
+            s_rec[4 * g.tid + 1] = q1;
+            s_rec[4 * g.tid + 2] = q2;
+            s_rec[4 * g.tid + 3] = q3;
         }
         __syncthreads();
         {
-            const uint32_t pos = base + 256 + tid;
-            if (pos < rg.y) {
+            const uint32_t pos = base + 256 + g.tid;
+            if (pos < e) {
                 const SurfelRec* r = recs + vals[pos];
                 q0 = r->a; q1 = r->b; q2 = r->c; q3 = r->d;
             }
         }
-        for (uint32_t j = 0; j < nb; ++j) {
-            if (__ballot(live) == 0ull) break;
-            const float4 ra = s_rec[4 * j + 2];
-            const uint32_t lo = __builtin_amdgcn_readfirstlane(__float_as_uint(ra.w));
-            const float4 rd = s_rec[4 * j + 3];
-            const uint32_t hi = __builtin_amdgcn_readfirstlane(__float_as_uint(rd.w));
-            if ((int)(hi & 0xFFFF) < sx0 || (int)(lo & 0xFFFF) > sx1 || (int)(hi >> 16) < sy0 ||
-                (int)(lo >> 16) > sy1)
-                continue;
-            const float4 r0 = s_rec[4 * j + 0];
-            const float4 r1 = s_rec[4 * j + 1];
-            if (live) {
-                if (kCount) ++n_eval;
-                const float dx = fpx - r0.x, dy = fpy - r0.y;
-                const float den = fmaf(r1.z, dx, fmaf(r1.w, dy, 1.f));
-                const float w = __builtin_amdgcn_rcpf(den);
-                const float u = fmaf(r0.z, dx, r0.w * dy) * w;
-                const float v = fmaf(r1.x, dx, r1.y * dy) * w;
-                const float lam = ra.x * w;
-                const bool ok3 = lam > a.z_near && lam < 3.0e38f;
-                const float e3 = ok3 ? -0.5f * fmaf(u, u, v * v) : -INFINITY;
-                const float e2 = a.lowpass ? -fmaf(dx, dx, dy * dy) : -INFINITY;
-                const float e = fmaxf(e3, e2);
-                const float al = fminf(a.alpha_max, ra.z * __expf(e));
-                if (al >= a.alpha_min) {
-                    const float Tn = T * (1.f - al);
-                    if (Tn < a.t_min) {
-                        live = false;
-                    } else {
-                        const float wt = al * T;
-                        if (kCount) ++n_used;
-                        c0 = fmaf(wt, rd.x, c0);
-                        c1 = fmaf(wt, rd.y, c1);
-                        c2 = fmaf(wt, rd.z, c2);
-                        D = fmaf(wt, (e3 >= e2) ? lam : ra.y, D);
-                        A += wt;
-                        T = Tn;
-                    }
+        uint64_t hit[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t j = (uint32_t)(q * 64 + g.lane);
+            bool h = false;
+            if (j < nb) {
+                const uint32_t lo = __float_as_uint(s_rec[4 * j + 2].w), hi = __float_as_uint(s_rec[4 * j + 3].w);
+                h = !((int)(hi & 0xFFFF) < g.sx0 || (int)(lo & 0xFFFF) > g.sx1 || (int)(hi >> 16) < g.sy0 ||
+                      (int)(lo >> 16) > g.sy1);
+            }
+            hit[q] = __ballot(h);
+        }
+        if (kCount) wc.walk += nb;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            uint64_t mm = hit[q];
+            while (mm) {
+                if (__ballot(p.live) == 0ull) break;
+                // Two records per trip: both are read before either is
+                // evaluated, so the second read overlaps the first's math.
+                const uint32_t j1 = (uint32_t)(q * 64) + (uint32_t)__ffsll((unsigned long long)mm) - 1u;
+                mm &= mm - 1ull;
+                const bool two = mm != 0ull;
+                const uint32_t j2 = two ? (uint32_t)(q * 64) + (uint32_t)__ffsll((unsigned long long)mm) - 1u : j1;
+                if (two) mm &= mm - 1ull;
+                const float4 a0 = s_rec[4 * j1 + 0], a1 = s_rec[4 * j1 + 1], a2 = s_rec[4 * j1 + 2],
+                             a3 = s_rec[4 * j1 + 3];
+                const float4 b0 = s_rec[4 * j2 + 0], b1 = s_rec[4 * j2 + 1], b2 = s_rec[4 * j2 + 2],
+                             b3 = s_rec[4 * j2 + 3];
+                composite(a0, a1, a2, a3, g.fpx, g.fpy, a, p.live, p.T, p.c0, p.c1, p.c2, p.D, p.A, wc.eval, wc.used,
+                          kCount);
+                if (kCount) ++wc.test;
+                if (two) {
+                    composite(b0, b1, b2, b3, g.fpx, g.fpy, a, p.live, p.T, p.c0, p.c1, p.c2, p.D, p.A, wc.eval,
+                              wc.used, kCount);
+                    if (kCount) ++wc.test;
                 }
             }
         }
-        if (__syncthreads_count(live) == 0) break;
+        if (__syncthreads_count(p.live) == 0) break;
+    }
+}
+
+__device__ __forceinline__ TileGeom tile_geom(uint32_t tile, const BlendArgs& a, bool* inside, int* px, int* py) {
+    TileGeom g;
+    const int tx = (int)(tile % (uint32_t)a.tiles_x), ty = (int)(tile / (uint32_t)a.tiles_x);
+    g.tid = threadIdx.x;
+    g.lane = g.tid & 63;
+    const int wave = g.tid >> 6;
+    *px = tx * kTile + (g.lane & 15);
+    *py = ty * kTile + wave * 4 + (g.lane >> 4);
+    *inside = *px < a.W && *py < a.H;
+    g.fpx = (float)*px;
+    g.fpy = (float)*py;
+    g.sx0 = tx * kTile;
+    g.sx1 = g.sx0 + kTile - 1;
+    g.sy0 = ty * kTile + wave * 4;
+    g.sy1 = g.sy0 + 3;
+    return g;
+}
+
+__device__ __forceinline__ void write_pixel(const PixelState& p, int px, int py, const BlendArgs& a,
+                                            float* __restrict__ rgb, float* __restrict__ dz, float* __restrict__ alpha,
+                                            uint8_t* __restrict__ cls) {
+    const int64_t hw = (int64_t)a.W * a.H;
+    const int64_t q = (int64_t)py * a.W + px;
+    rgb[q] = fmaf(p.T, a.bg0, p.c0);
+    rgb[hw + q] = fmaf(p.T, a.bg1, p.c1);
+    rgb[2 * hw + q] = fmaf(p.T, a.bg2, p.c2);
+    alpha[q] = p.A;
+    if (!a.patch) {
+        dz[q] = p.D;
+    } else {
+        dz[q] = p.A >= a.a_min ? p.D / p.A : INFINITY;
+        cls[q] = (uint8_t)BGS_CLS_ROI;
+    }
+}
+
+// Continuation state of one pixel: (c0, c1, c2, D) and (A, T, flag, 0);
+// flag = 1 for a pixel still compositing (phase 1) or one that stopped
+// inside the segment (segments).
+__device__ __forceinline__ void store_state(float4* st, int tid, const PixelState& p, bool flag) {
+    st[2 * tid + 0] = make_float4(p.c0, p.c1, p.c2, p.D);
+    st[2 * tid + 1] = make_float4(p.A, p.T, flag ? 1.f : 0.f, 0.f);
+}
+
+__device__ __forceinline__ void count_flush(const WalkCounts& wc, int lane, int wave, uint32_t len,
+                                            unsigned long long* pair_counts, uint32_t* s_walk) {
+    unsigned long long e = wc.eval, u = wc.used;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        e += __shfl_xor(e, off, 64);
+        u += __shfl_xor(u, off, 64);
+    }
+    if (lane == 0) {
+        // walk / test are wave-uniform: records walked by this wave and
+        // records that passed its strip test.
+        atomicAdd(&pair_counts[0], e);
+        atomicAdd(&pair_counts[1], u);
+        atomicAdd(&pair_counts[2], (unsigned long long)wc.walk);
+        atomicAdd(&pair_counts[3], (unsigned long long)wc.test);
+        atomicMax(&pair_counts[4], (unsigned long long)wc.walk);
+        if (wave == 0) atomicMax(&pair_counts[5], (unsigned long long)len);
+        if (s_walk) s_walk[wave] = wc.walk;
+    }
+}
+
+// Phase 1: every tile walks at most a.cap records of its list.  A tile that
+// is done by then (or whose list ends) writes its pixels; otherwise it takes
+// a continuation slot and leaves its state for the segment blocks (if no
+// slot is free it simply walks on).
+template <bool kCount>
+__global__ __launch_bounds__(256) void k_blend(const SurfelRec* __restrict__ recs, const uint32_t* __restrict__ vals,
+                                               const uint2* __restrict__ ranges, const uint32_t* __restrict__ tile_list,
+                                               const uint32_t* __restrict__ order,
+                                               const uint32_t* __restrict__ n_live, BlendArgs a, ContArgs ca,
+                                               float* __restrict__ rgb, float* __restrict__ dz,
+                                               float* __restrict__ alpha, uint8_t* __restrict__ cls,
+                                               unsigned long long* __restrict__ pair_counts,
+                                               long long* __restrict__ trace) {
+    __shared__ float4 s_rec[256 * 4];
+    __shared__ uint32_t s_walk[4];
+    __shared__ uint32_t s_slot;
+    const long long t_begin = kCount ? wall_clock64() : 0;
+    const uint32_t blk = blockIdx.x;
+    if (n_live && blk >= *n_live) return;
+    const uint32_t cid = order ? order[blk] : blk;
+    const uint32_t tile = tile_list ? tile_list[cid] : cid;
+    bool inside;
+    int px, py;
+    const TileGeom g = tile_geom(tile, a, &inside, &px, &py);
+    const uint2 rg = ranges[cid];
+    PixelState p{1.f, 0.f, 0.f, 0.f, 0.f, 0.f, inside};
+    WalkCounts wc{0, 0, 0, 0};
+    const uint32_t cap_end = (ca.max_slots > 0 && rg.y - rg.x > a.cap) ? rg.x + a.cap : rg.y;
+    walk_range<kCount>(recs, vals, rg.x, cap_end, s_rec, g, a, p, wc);
+    bool handed_off = false;
+    if (cap_end < rg.y && __syncthreads_count(p.live) > 0) {
+        if (g.tid == 0) {
+            const uint32_t c = atomicAdd(ca.n_slots, 1u);
+            s_slot = c < ca.max_slots ? c : 0xFFFFFFFFu;
+        }
+        __syncthreads();
+        const uint32_t slot = s_slot;
+        if (slot != 0xFFFFFFFFu) {
+            store_state(ca.state1 + (size_t)slot * 512, g.tid, p, p.live);
+            if (g.tid == 0) {
+                const uint32_t rem = rg.y - cap_end;
+                const uint32_t nseg = min((uint32_t)ca.max_seg, max(1u, (rem + ca.seg_len - 1) / ca.seg_len));
+                ca.desc[slot] = make_uint4(cid, cap_end, rg.y, nseg);
+                ca.done[slot] = 0u;
+            }
+            handed_off = true;
+        } else {
+            walk_range<kCount>(recs, vals, cap_end, rg.y, s_rec, g, a, p, wc);
+        }
     }
     if (kCount) {
-        unsigned long long e = n_eval, u = n_used;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            e += __shfl_xor(e, off, 64);
-            u += __shfl_xor(u, off, 64);
-        }
-        if (lane == 0) {
-            atomicAdd(&pair_counts[0], e);
-            atomicAdd(&pair_counts[1], u);
+        count_flush(wc, g.lane, g.tid >> 6, rg.y - rg.x, pair_counts, s_walk);
+        __syncthreads();
+        if (trace && g.tid == 0) {
+            // Per tile: id, list length, longest wave walk, CU, start, end.
+            long long* t = trace + 6 * (long long)blk;
+            t[0] = tile;
+            t[1] = rg.y - rg.x;
+            t[2] = max(max(s_walk[0], s_walk[1]), max(s_walk[2], s_walk[3]));
+            t[3] = __smid();
+            t[4] = t_begin;
+            t[5] = wall_clock64();
         }
     }
-    if (!inside) return;
-    const int64_t hw = (int64_t)a.W * a.H;
-    const int64_t p = (int64_t)py * a.W + px;
-    rgb[p] = fmaf(T, a.bg0, c0);
-    rgb[hw + p] = fmaf(T, a.bg1, c1);
-    rgb[2 * hw + p] = fmaf(T, a.bg2, c2);
-    alpha[p] = A;
-    if (!a.patch) {
-        dz[p] = D;
-    } else {
-        dz[p] = A >= a.a_min ? D / A : INFINITY;
-        cls[p] = (uint8_t)BGS_CLS_ROI;
+    if (!handed_off && inside) write_pixel(p, px, py, a, rgb, dz, alpha, cls);
+}
+
+// Phases 2-3: block (slot, s) composites segment s of a continued tile for
+// the pixels still compositing, with a fresh transmittance.  The last of a
+// tile's segment blocks to finish combines them front to back: a segment is
+// taken whole where the running transmittance stays above t_min through it,
+// and is walked again in sequence from the running state where it does not,
+// so the pixels equal those of one uninterrupted walk.
+template <bool kCount>
+__global__ __launch_bounds__(256) void k_blend_cont(const SurfelRec* __restrict__ recs,
+                                                    const uint32_t* __restrict__ vals,
+                                                    const uint32_t* __restrict__ tile_list, BlendArgs a, ContArgs ca,
+                                                    float* __restrict__ rgb, float* __restrict__ dz,
+                                                    float* __restrict__ alpha, uint8_t* __restrict__ cls,
+                                                    unsigned long long* __restrict__ pair_counts) {
+    __shared__ float4 s_rec[256 * 4];
+    __shared__ uint32_t s_last;
+    const uint32_t slot = blockIdx.x / (uint32_t)ca.max_seg, seg = blockIdx.x % (uint32_t)ca.max_seg;
+    if (slot >= min(*ca.n_slots, (uint32_t)ca.max_slots)) return;
+    const uint4 d = ca.desc[slot];
+    const uint32_t nseg = d.w;
+    if (seg >= nseg) return;
+    const uint32_t tile = tile_list ? tile_list[d.x] : d.x;
+    bool inside;
+    int px, py;
+    const TileGeom g = tile_geom(tile, a, &inside, &px, &py);
+    WalkCounts wc{0, 0, 0, 0};
+    const float4* st1 = ca.state1 + (size_t)slot * 512;
+    float4* sst = ca.seg_state + ((size_t)slot * ca.max_seg) * 512;
+    const uint32_t total = d.z - d.y;
+    auto seg_b = [&](uint32_t k) { return d.y + (uint32_t)(((uint64_t)total * k) / nseg); };
+    {
+        const bool live0 = st1[2 * g.tid + 1].z != 0.f;
+        PixelState p{1.f, 0.f, 0.f, 0.f, 0.f, 0.f, live0};
+        walk_range<kCount>(recs, vals, seg_b(seg), seg_b(seg + 1), s_rec, g, a, p, wc);
+        store_state(sst + (size_t)seg * 512, g.tid, p, live0 && !p.live);
     }
+    __threadfence();
+    __syncthreads();
+    if (g.tid == 0) s_last = atomicAdd(&ca.done[slot], 1u) == nseg - 1 ? 1u : 0u;
+    __syncthreads();
+    if (!s_last) {
+        if (kCount) count_flush(wc, g.lane, g.tid >> 6, 0, pair_counts, nullptr);
+        return;
+    }
+    __threadfence();
+    const float4 s0 = st1[2 * g.tid], s1 = st1[2 * g.tid + 1];
+    PixelState p{s1.y, s0.x, s0.y, s0.z, s0.w, s1.x, s1.z != 0.f};
+    for (uint32_t k = 0; k < nseg; ++k) {
+        const float4 q0 = sst[(size_t)k * 512 + 2 * g.tid], q1 = sst[(size_t)k * 512 + 2 * g.tid + 1];
+        bool need = false;
+        if (p.live) {
+            const float Tn = p.T * q1.y;
+            if (q1.z == 0.f && Tn >= a.t_min) {
+                p.c0 = fmaf(p.T, q0.x, p.c0);
+                p.c1 = fmaf(p.T, q0.y, p.c1);
+                p.c2 = fmaf(p.T, q0.z, p.c2);
+                p.D = fmaf(p.T, q0.w, p.D);
+                p.A = fmaf(p.T, q1.x, p.A);
+                p.T = Tn;
+            } else {
+                need = true;
+            }
+        }
+        if (__syncthreads_count(need) > 0) {
+            const bool keep = p.live;
+            p.live = need;
+            walk_range<kCount>(recs, vals, seg_b(k), seg_b(k + 1), s_rec, g, a, p, wc);
+            p.live = need ? p.live : keep;
+        }
+    }
+    if (kCount) count_flush(wc, g.lane, g.tid >> 6, 0, pair_counts, nullptr);
+    if (inside) write_pixel(p, px, py, a, rgb, dz, alpha, cls);
 }
 
 }  // namespace
@@ -500,10 +724,9 @@ hipError_t launch_emit(const uint32_t* order, const uint32_t* offs, const uint2*
 
 hipError_t launch_ranges(const uint32_t* tkeys, const uint32_t* n_dev, int64_t cap, uint2* ranges, int n_tiles,
                          hipStream_t s) {
-    hipError_t e = hipMemsetAsync(ranges, 0, sizeof(uint2) * (size_t)n_tiles, s);
-    if (e != hipSuccess) return e;
-    if (cap <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ranges, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, tkeys, n_dev, ranges,
+    (void)cap;
+    if (n_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ranges, dim3((unsigned)((n_tiles + 255) / 256)), dim3(256), 0, s, tkeys, n_dev, ranges,
                        (uint32_t)n_tiles);
     return hipGetLastError();
 }
@@ -516,15 +739,25 @@ hipError_t launch_tile_order(const uint2* ranges, const uint32_t* n_live, int n_
 }
 
 hipError_t launch_blend(const SurfelRec* recs, const uint32_t* vals, const uint2* ranges, const uint32_t* tile_list,
-                        const uint32_t* order, const uint32_t* n_live, int n_blocks, const BlendArgs& a, float* rgb,
-                        float* d_or_z, float* alpha, uint8_t* cls, unsigned long long* pair_counts, hipStream_t s) {
+                        const uint32_t* order, const uint32_t* n_live, int n_blocks, const BlendArgs& a,
+                        const ContArgs& ca, float* rgb, float* d_or_z, float* alpha, uint8_t* cls,
+                        unsigned long long* pair_counts, long long* trace, hipStream_t s) {
     if (n_blocks <= 0) return hipSuccess;
     if (pair_counts)
         hipLaunchKernelGGL(k_blend<true>, dim3(n_blocks), dim3(256), 0, s, recs, vals, ranges, tile_list, order, n_live,
-                           a, rgb, d_or_z, alpha, cls, pair_counts);
+                           a, ca, rgb, d_or_z, alpha, cls, pair_counts, trace);
     else
         hipLaunchKernelGGL(k_blend<false>, dim3(n_blocks), dim3(256), 0, s, recs, vals, ranges, tile_list, order,
-                           n_live, a, rgb, d_or_z, alpha, cls, pair_counts);
+                           n_live, a, ca, rgb, d_or_z, alpha, cls, pair_counts, (long long*)nullptr);
+    if (ca.max_slots > 0) {
+        const unsigned g = (unsigned)(ca.max_slots * ca.max_seg);
+        if (pair_counts)
+            hipLaunchKernelGGL(k_blend_cont<true>, dim3(g), dim3(256), 0, s, recs, vals, tile_list, a, ca, rgb, d_or_z,
+                               alpha, cls, pair_counts);
+        else
+            hipLaunchKernelGGL(k_blend_cont<false>, dim3(g), dim3(256), 0, s, recs, vals, tile_list, a, ca, rgb,
+                               d_or_z, alpha, cls, pair_counts);
+    }
     return hipGetLastError();
 }
 

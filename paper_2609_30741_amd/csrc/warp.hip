@@ -89,6 +89,42 @@ __global__ __launch_bounds__(256) void k_fill_u64(unsigned long long* p, int64_t
     if (i < n) p[i] = v;
 }
 
+// Where source pixel s lands: the fixed-order fp64 recipe of Eq. 4-5.
+// Returns false when it lands nowhere; *df gets the fp32 depth proxy of a
+// covered source pixel (else stays untouched).
+__device__ inline bool splat_target(const WarpCam& src, const WarpCam& dst, const RelPose& P, float a_min,
+                                    const float* __restrict__ draw, const float* __restrict__ alpha, int64_t s,
+                                    int64_t* fu_out, int64_t* fv_out, unsigned long long* key, float* df_out) {
+    const int64_t i = s % src.W, j = s / src.W;
+    const double xn = ((double)i - src.cx) / src.fx;
+    const double yn = ((double)j - src.cy) / src.fy;
+    const float A = alpha[s];
+    double Xp[3];
+    bool ok;
+    float zf;
+    if (A >= a_min) {
+        const float df = draw[s] / A;
+        *df_out = df;
+        const double d = (double)df;
+        map_point(P, true, d * xn, d * yn, d, Xp);
+        ok = Xp[2] > dst.z_near;
+        zf = (float)Xp[2];
+    } else {
+        map_point(P, false, xn, yn, 1.0, Xp);
+        ok = Xp[2] > 0.0;
+        zf = INFINITY;
+    }
+    if (!ok) return false;
+    double u, v;
+    project(dst, Xp, &u, &v);
+    const double fu = floor(u + 0.5), fv = floor(v + 0.5);
+    if (!(fu >= 0.0 && fu <= (double)(dst.W - 1) && fv >= 0.0 && fv <= (double)(dst.H - 1))) return false;
+    *fu_out = (int64_t)fu;
+    *fv_out = (int64_t)fv;
+    *key = ((unsigned long long)__float_as_uint(zf) << 32) | (unsigned long long)(uint32_t)s;
+    return true;
+}
+
 // Forward splat of every source pixel into the destination z-buffer.
 __global__ __launch_bounds__(256) void k_reproject_scatter(WarpCam src, WarpCam dst, RelPose P, float a_min,
                                                            const float* __restrict__ draw,
@@ -98,43 +134,93 @@ __global__ __launch_bounds__(256) void k_reproject_scatter(WarpCam src, WarpCam 
     const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
     uint32_t dmin = 0xFFFFFFFFu, dmax = 0u;
     if (s < ns) {
-        const int64_t i = s % src.W, j = s / src.W;
-        const double xn = ((double)i - src.cx) / src.fx;
-        const double yn = ((double)j - src.cy) / src.fy;
-        const float A = alpha[s];
-        double Xp[3];
-        bool ok;
-        float zf;
-        if (A >= a_min) {
-            const float df = draw[s] / A;
+        int64_t fu, fv;
+        unsigned long long key;
+        float df = -1.f;
+        const bool hit = splat_target(src, dst, P, a_min, draw, alpha, s, &fu, &fv, &key, &df);
+        if (df >= 0.f) {
             dmin = __float_as_uint(df);
             dmax = dmin;
-            const double d = (double)df;
-            map_point(P, true, d * xn, d * yn, d, Xp);
-            ok = Xp[2] > dst.z_near;
-            zf = (float)Xp[2];
-        } else {
-            map_point(P, false, xn, yn, 1.0, Xp);
-            ok = Xp[2] > 0.0;
-            zf = INFINITY;
         }
-        if (ok) {
-            double u, v;
-            project(dst, Xp, &u, &v);
-            const double fu = floor(u + 0.5), fv = floor(v + 0.5);
-            if (fu >= 0.0 && fu <= (double)(dst.W - 1) && fv >= 0.0 && fv <= (double)(dst.H - 1)) {
-                const int64_t t = (int64_t)fv * dst.W + (int64_t)fu;
-                const unsigned long long key =
-                    ((unsigned long long)__float_as_uint(zf) << 32) | (unsigned long long)(uint32_t)s;
-                atomicMin(&zbuf[t], key);
-            }
-        }
+        if (hit) atomicMin(&zbuf[fv * dst.W + fu], key);
     }
     dmin = wave_min_u32(dmin);
     dmax = wave_max_u32(dmax);
     if ((threadIdx.x & 63) == 0) {
         if (dmin != 0xFFFFFFFFu) atomicMin(&st->dmin_bits, dmin);
         if (dmax != 0u) atomicMax(&st->dmax_bits, dmax);
+    }
+}
+
+// Resolve one destination pixel t from its z-buffer key.
+__device__ inline uint32_t resolve_pixel(unsigned long long key, int64_t t, int64_t nd, int64_t ns,
+                                         const float* __restrict__ rgb, const float* __restrict__ alpha,
+                                         float* __restrict__ rgb_dst, float* __restrict__ z_dst,
+                                         float* __restrict__ a_dst, uint8_t* __restrict__ hole) {
+    if (key == ~0ull) {
+        rgb_dst[t] = 0.f;
+        rgb_dst[nd + t] = 0.f;
+        rgb_dst[2 * nd + t] = 0.f;
+        z_dst[t] = INFINITY;
+        a_dst[t] = 0.f;
+        hole[t] = 1;
+        return 1;
+    }
+    const uint32_t s = (uint32_t)(key & 0xFFFFFFFFull);
+    rgb_dst[t] = rgb[s];
+    rgb_dst[nd + t] = rgb[ns + s];
+    rgb_dst[2 * nd + t] = rgb[2 * ns + s];
+    z_dst[t] = __uint_as_float((uint32_t)(key >> 32));
+    a_dst[t] = alpha[s];
+    hole[t] = 0;
+    return 0;
+}
+
+// Row-preserving form (the host has proven that every splat stays on its
+// source row, as for a rig that keeps the orientation and moves along x):
+// one block per row, the row's z-buffer in LDS (64-bit LDS atomicMin), the
+// z-test and the resolve in one kernel.  Same recipe, same result as the
+// scatter/resolve pair.
+__global__ __launch_bounds__(256) void k_reproject_rows(WarpCam src, WarpCam dst, RelPose P, float a_min,
+                                                        const float* __restrict__ draw,
+                                                        const float* __restrict__ alpha,
+                                                        const float* __restrict__ rgb, float* __restrict__ rgb_dst,
+                                                        float* __restrict__ z_dst, float* __restrict__ a_dst,
+                                                        uint8_t* __restrict__ hole, DevStatus* st) {
+    extern __shared__ unsigned long long zrow[];
+    const int j = blockIdx.x;
+    for (int t = threadIdx.x; t < dst.W; t += 256) zrow[t] = ~0ull;
+    __syncthreads();
+    uint32_t dmin = 0xFFFFFFFFu, dmax = 0u, off_row = 0;
+    for (int i = threadIdx.x; i < src.W; i += 256) {
+        const int64_t s = (int64_t)j * src.W + i;
+        int64_t fu, fv;
+        unsigned long long key;
+        float df = -1.f;
+        const bool hit = splat_target(src, dst, P, a_min, draw, alpha, s, &fu, &fv, &key, &df);
+        if (df >= 0.f) {
+            dmin = min(dmin, __float_as_uint(df));
+            dmax = max(dmax, __float_as_uint(df));
+        }
+        if (hit) {
+            if (fv == j) atomicMin(&zrow[fu], key);
+            else off_row = 1;
+        }
+    }
+    __syncthreads();
+    const int64_t nd = (int64_t)dst.W * dst.H, ns = (int64_t)src.W * src.H;
+    uint32_t holes = 0;
+    for (int t = threadIdx.x; t < dst.W; t += 256)
+        holes += resolve_pixel(zrow[t], (int64_t)j * dst.W + t, nd, ns, rgb, alpha, rgb_dst, z_dst, a_dst, hole);
+    dmin = wave_min_u32(dmin);
+    dmax = wave_max_u32(dmax);
+    holes = wave_sum_u32(holes);
+    off_row = wave_max_u32(off_row);
+    if ((threadIdx.x & 63) == 0) {
+        if (dmin != 0xFFFFFFFFu) atomicMin(&st->dmin_bits, dmin);
+        if (dmax != 0u) atomicMax(&st->dmax_bits, dmax);
+        if (holes) atomicAdd(&st->n_holes, holes);
+        if (off_row) atomicOr(&st->overflow, 4u);  // cannot happen when the host's bound holds
     }
 }
 
@@ -147,25 +233,7 @@ __global__ __launch_bounds__(256) void k_reproject_resolve(int64_t nd, int64_t n
                                                            DevStatus* st) {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     uint32_t h = 0;
-    if (t < nd) {
-        const unsigned long long key = zbuf[t];
-        if (key == ~0ull) {
-            h = 1;
-            rgb_dst[t] = 0.f;
-            rgb_dst[nd + t] = 0.f;
-            rgb_dst[2 * nd + t] = 0.f;
-            z_dst[t] = INFINITY;
-            a_dst[t] = 0.f;
-        } else {
-            const uint32_t s = (uint32_t)(key & 0xFFFFFFFFull);
-            rgb_dst[t] = rgb[s];
-            rgb_dst[nd + t] = rgb[ns + s];
-            rgb_dst[2 * nd + t] = rgb[2 * ns + s];
-            z_dst[t] = __uint_as_float((uint32_t)(key >> 32));
-            a_dst[t] = alpha[s];
-        }
-        hole[t] = (uint8_t)h;
-    }
+    if (t < nd) h = resolve_pixel(zbuf[t], t, nd, ns, rgb, alpha, rgb_dst, z_dst, a_dst, hole);
     h = wave_sum_u32(h);
     if ((threadIdx.x & 63) == 0 && h) atomicAdd(&st->n_holes, h);
 }
@@ -299,22 +367,25 @@ __device__ inline bool in_edge(const DevStatus* st, int x, int y) {
 }
 
 // ---------------------------------------------------------------------------
-// Gap interpolation: one Jacobi pass.  Unfilled pixels are copied through.
+// Gap interpolation, Jacobi passes done in place.  tag[p] = 0 for a pixel
+// that was never a hole, k for a hole filled in pass k, 255 for a hole.  In
+// pass k a neighbour counts as valid iff its tag is below k, which is the
+// state before the pass; a pixel filled in pass k is written only where no
+// other pixel of pass k reads it.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_gap_pass(int W, int H, const float* __restrict__ rgb_in,
-                                                  const float* __restrict__ z_in, const float* __restrict__ a_in,
-                                                  const uint8_t* __restrict__ hole_in, float* __restrict__ rgb_out,
-                                                  float* __restrict__ z_out, float* __restrict__ a_out,
-                                                  uint8_t* __restrict__ hole_out, uint8_t* __restrict__ cls,
-                                                  DevStatus* st) {
+__global__ __launch_bounds__(256) void k_tag_init(int64_t n, const uint8_t* __restrict__ cls, uint8_t* __restrict__ tag) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p < n) tag[p] = cls[p] ? 255 : 0;
+}
+
+__global__ __launch_bounds__(256) void k_gap_pass(int W, int H, int pass, float* rgb, float* z, float* alpha,
+                                                  uint8_t* tag, uint8_t* __restrict__ cls, DevStatus* st) {
     const int64_t n = (int64_t)W * H;
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     uint32_t filled = 0;
-    if (p < n) {
+    if (p < n && tag[p] == 255) {
         const int x = (int)(p % W), y = (int)(p / W);
-        float r0 = rgb_in[p], r1 = rgb_in[n + p], r2 = rgb_in[2 * n + p], zz = z_in[p], aa = a_in[p];
-        uint8_t h = hole_in[p];
-        if (h && !in_edge(st, x, y)) {
+        if (!in_edge(st, x, y)) {
             const int NX[8] = {-1, 0, 1, -1, 1, -1, 0, 1};
             const int NY[8] = {-1, -1, -1, 0, 0, 1, 1, 1};
             int cnt = 0;
@@ -324,65 +395,40 @@ __global__ __launch_bounds__(256) void k_gap_pass(int W, int H, const float* __r
                 const int xx = x + NX[q], yy = y + NY[q];
                 if (xx < 0 || yy < 0 || xx >= W || yy >= H) continue;
                 const int64_t r = (int64_t)yy * W + xx;
-                if (hole_in[r]) continue;
-                s0 = s0 + rgb_in[r];
-                s1 = s1 + rgb_in[n + r];
-                s2 = s2 + rgb_in[2 * n + r];
-                sa = sa + a_in[r];
-                const float zr = z_in[r];
+                if ((int)tag[r] >= pass) continue;  // a hole, or filled in this pass
+                s0 = s0 + rgb[r];
+                s1 = s1 + rgb[n + r];
+                s2 = s2 + rgb[2 * n + r];
+                sa = sa + alpha[r];
+                const float zr = z[r];
                 if (zr > zm) zm = zr;
                 ++cnt;
             }
             if (cnt > 0) {
                 const float fc = (float)cnt;
-                r0 = s0 / fc;
-                r1 = s1 / fc;
-                r2 = s2 / fc;
-                aa = sa / fc;
-                zz = zm;
-                h = 0;
+                rgb[p] = s0 / fc;
+                rgb[n + p] = s1 / fc;
+                rgb[2 * n + p] = s2 / fc;
+                alpha[p] = sa / fc;
+                z[p] = zm;
+                tag[p] = (uint8_t)pass;
                 cls[p] = (uint8_t)BGS_CLS_GAP;
                 filled = 1;
             }
         }
-        rgb_out[p] = r0;
-        rgb_out[n + p] = r1;
-        rgb_out[2 * n + p] = r2;
-        z_out[p] = zz;
-        a_out[p] = aa;
-        hole_out[p] = h;
     }
     filled = wave_sum_u32(filled);
     if ((threadIdx.x & 63) == 0 && filled) atomicAdd(&st->n_gap, filled);
 }
 
-__global__ __launch_bounds__(256) void k_copy_state(int64_t n, const float* __restrict__ rgb_in,
-                                                    const float* __restrict__ z_in, const float* __restrict__ a_in,
-                                                    float* __restrict__ rgb_out, float* __restrict__ z_out,
-                                                    float* __restrict__ a_out) {
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (p >= n) return;
-    rgb_out[p] = rgb_in[p];
-    rgb_out[n + p] = rgb_in[n + p];
-    rgb_out[2 * n + p] = rgb_in[2 * n + p];
-    z_out[p] = z_in[p];
-    a_out[p] = a_in[p];
-}
-
-__global__ __launch_bounds__(256) void k_hole_init(int64_t n, const uint8_t* __restrict__ cls,
-                                                   uint8_t* __restrict__ hole) {
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (p < n) hole[p] = cls[p] ? 1 : 0;
-}
-
 // Holes left after interpolation and outside the edge ROIs.
-__global__ __launch_bounds__(256) void k_center_mask(int W, int H, const uint8_t* __restrict__ hole,
+__global__ __launch_bounds__(256) void k_center_mask(int W, int H, const uint8_t* __restrict__ tag,
                                                      uint8_t* __restrict__ center, DevStatus* st) {
     const int64_t n = (int64_t)W * H;
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     uint32_t c = 0;
     if (p < n) {
-        c = (hole[p] && !in_edge(st, (int)(p % W), (int)(p / W))) ? 1u : 0u;
+        c = (tag[p] == 255 && !in_edge(st, (int)(p % W), (int)(p / W))) ? 1u : 0u;
         center[p] = (uint8_t)c;
     }
     c = wave_sum_u32(c);
@@ -393,7 +439,7 @@ __global__ __launch_bounds__(256) void k_center_mask(int W, int H, const uint8_t
 // Row fill (center step off): nearest non-hole pixel left and right on the
 // row via block max/min scans; the farther candidate wins.  One block/row.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_row_fill(int W, int H, const uint8_t* __restrict__ hole,
+__global__ __launch_bounds__(256) void k_row_fill(int W, int H, const uint8_t* __restrict__ tag,
                                                   const uint8_t* __restrict__ center, float bg0, float bg1, float bg2,
                                                   float* __restrict__ rgb, float* __restrict__ z,
                                                   float* __restrict__ alpha, uint8_t* __restrict__ cls,
@@ -406,7 +452,7 @@ __global__ __launch_bounds__(256) void k_row_fill(int W, int H, const uint8_t* _
     const int xa = threadIdx.x * chunk, xb = min(xa + chunk, W);
     int last = -1, first = INT_MAX;
     for (int x = xa; x < xb; ++x)
-        if (!hole[row + x]) {
+        if (tag[row + x] != 255) {
             last = x;
             if (first == INT_MAX) first = x;
         }
@@ -431,7 +477,7 @@ __global__ __launch_bounds__(256) void k_row_fill(int W, int H, const uint8_t* _
         if (center[p]) {
             int right = right_after;
             for (int xx = x + 1; xx < xb; ++xx)
-                if (!hole[row + xx]) {
+                if (tag[row + xx] != 255) {
                     right = xx;
                     break;
                 }
@@ -456,7 +502,7 @@ __global__ __launch_bounds__(256) void k_row_fill(int W, int H, const uint8_t* _
             cls[p] = (uint8_t)BGS_CLS_ROWFILL;
             ++filled;
         }
-        if (!hole[p]) left = x;
+        if (tag[p] != 255) left = x;
     }
     filled = wave_sum_u32(filled);
     if ((threadIdx.x & 63) == 0 && filled) atomicAdd(&st->n_rowfill, filled);
@@ -518,10 +564,16 @@ __device__ inline void unite_lds(int* L, int a, int b) {
     }
 }
 
+// Block-local labelling of a 16x16 pixel block.  With pflag/pbox given, it
+// also records every block-local piece (its root pixel gets pflag = 1 and
+// the piece's half-open bounding box in pbox), so that component boxes can
+// be formed from pieces instead of pixels.
 __global__ __launch_bounds__(256) void k_ccl_local(int W, int H, int conn, const uint8_t* __restrict__ mask,
-                                                   int* __restrict__ labels) {
+                                                   int* __restrict__ labels, uint8_t* __restrict__ pflag,
+                                                   int4* __restrict__ pbox) {
     __shared__ int L[256];
     __shared__ uint8_t m[256];
+    __shared__ int bx0[256], by0[256], bx1[256], by1[256];
     const int lx = threadIdx.x & 15, ly = threadIdx.x >> 4;
     const int x = blockIdx.x * 16 + lx, y = blockIdx.y * 16 + ly;
     const bool in = x < W && y < H;
@@ -529,6 +581,10 @@ __global__ __launch_bounds__(256) void k_ccl_local(int W, int H, int conn, const
     const bool set = in && mask[(int64_t)y * W + x];
     m[li] = set ? 1 : 0;
     L[li] = li;
+    bx0[li] = INT_MAX;
+    by0[li] = INT_MAX;
+    bx1[li] = -1;
+    by1[li] = -1;
     __syncthreads();
     if (set) {
         // Backward neighbours inside the block: left, up-left, up, up-right.
@@ -542,13 +598,29 @@ __global__ __launch_bounds__(256) void k_ccl_local(int W, int H, int conn, const
         }
     }
     __syncthreads();
-    if (!in) return;
+    int r = -1;
     if (set) {
-        const int r = find_root_lds(L, li);
+        r = find_root_lds(L, li);
+        if (pbox) {
+            atomicMin(&bx0[r], x);
+            atomicMin(&by0[r], y);
+            atomicMax(&bx1[r], x + 1);
+            atomicMax(&by1[r], y + 1);
+        }
+    }
+    __syncthreads();
+    if (!in) return;
+    const int64_t g = (int64_t)y * W + x;
+    if (set) {
         const int rx = blockIdx.x * 16 + (r & 15), ry = blockIdx.y * 16 + (r >> 4);
-        labels[(int64_t)y * W + x] = ry * W + rx;
+        labels[g] = ry * W + rx;
     } else {
-        labels[(int64_t)y * W + x] = -1;
+        labels[g] = -1;
+    }
+    if (pflag) {
+        const bool root = set && r == li;
+        pflag[g] = root ? 1 : 0;
+        if (root) pbox[g] = make_int4(bx0[li], by0[li], bx1[li], by1[li]);
     }
 }
 
@@ -600,18 +672,18 @@ __global__ __launch_bounds__(256) void k_bbox_init(int64_t n, const int* __restr
     bbox[4 * s + 3] = -1;
 }
 
-__global__ __launch_bounds__(256) void k_bbox_acc(int W, int64_t n, const int* __restrict__ labels,
+// Component boxes from the block-local pieces: 4 atomics per piece.
+__global__ __launch_bounds__(256) void k_bbox_acc(int64_t n, const int* __restrict__ labels,
+                                                  const uint8_t* __restrict__ pflag, const int4* __restrict__ pbox,
                                                   const uint32_t* __restrict__ slots, int32_t* bbox) {
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (p >= n) return;
-    const int l = labels[p];
-    if (l < 0) return;
-    const uint32_t s = slots[l];
-    const int x = (int)(p % W), y = (int)(p / W);
-    atomicMin(&bbox[4 * s + 0], x);
-    atomicMin(&bbox[4 * s + 1], y);
-    atomicMax(&bbox[4 * s + 2], x + 1);
-    atomicMax(&bbox[4 * s + 3], y + 1);
+    if (p >= n || !pflag[p]) return;
+    const uint32_t s = slots[labels[p]];
+    const int4 b = pbox[p];
+    atomicMin(&bbox[4 * s + 0], b.x);
+    atomicMin(&bbox[4 * s + 1], b.y);
+    atomicMax(&bbox[4 * s + 2], b.z);
+    atomicMax(&bbox[4 * s + 3], b.w);
 }
 
 __global__ __launch_bounds__(256) void k_tile_mask_edges(int tiles_x, int tiles_y, int T, const DevStatus* st,
@@ -678,28 +750,62 @@ inline unsigned grid(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
 
+// True when every splat provably stays on its source row: same row count,
+// same fy and cy, and the fp64 bound on |v - j| over the image for any valid
+// depth is below a quarter pixel.  With M = I + E (|E| <= eps) and a point
+// at depth d >= d_lo, v - j = fy (num / den) with
+// |num| <= g + |c1|/d_lo + |yn| (g + |c2|/d_lo), den >= 1 - g - |c2|/d_lo,
+// g = eps (|xn| + |yn| + 1); valid splats need Z' > z_near, hence d_lo.
+static bool rows_preserved(const WarpCam& src, const WarpCam& dst, const RelPose& P) {
+    if (src.H != dst.H || src.fy != dst.fy || src.cy != dst.cy || dst.W > 8192) return false;
+    double eps = 0.0;
+    for (int r = 0; r < 3; ++r)
+        for (int q = 0; q < 3; ++q) eps = fmax(eps, fabs(P.M[r * 3 + q] - (r == q ? 1.0 : 0.0)));
+    const double xn = fmax(fabs(0.0 - src.cx), fabs((src.W - 1.0) - src.cx)) / src.fx;
+    const double yn = fmax(fabs(0.0 - src.cy), fabs((src.H - 1.0) - src.cy)) / src.fy;
+    const double g = eps * (xn + yn + 1.0);
+    const double d_lo = (dst.z_near - fabs(P.c[2])) / (1.0 + g);
+    if (!(d_lo > 0.0)) return false;
+    const double c1 = fabs(P.c[1]) / d_lo, c2 = fabs(P.c[2]) / d_lo;
+    const double den = 1.0 - g - c2;
+    if (!(den > 0.5)) return false;
+    const double bound = dst.fy * (g + c1 + yn * (g + c2)) / den + 1e-9 * (dst.H + 1.0);
+    return bound < 0.25;
+}
+
 hipError_t launch_reproject(const WarpCam& src, const WarpCam& dst, const RelPose& P, float a_min, const float* rgb,
                             const float* draw, const float* alpha, unsigned long long* zbuf, float* rgb_dst,
                             float* z_dst, float* alpha_dst, uint8_t* hole, float* depth_range, DevStatus* st,
                             hipStream_t s) {
     const int64_t ns = (int64_t)src.W * src.H, nd = (int64_t)dst.W * dst.H;
     hipLaunchKernelGGL(k_warp_reset, dim3(1), dim3(1), 0, s, st);
-    hipLaunchKernelGGL(k_fill_u64, dim3(grid(nd)), dim3(256), 0, s, zbuf, nd, ~0ull);
-    hipLaunchKernelGGL(k_reproject_scatter, dim3(grid(ns)), dim3(256), 0, s, src, dst, P, a_min, draw, alpha, zbuf, st);
-    hipLaunchKernelGGL(k_reproject_resolve, dim3(grid(nd)), dim3(256), 0, s, nd, ns, zbuf, rgb, alpha, rgb_dst, z_dst,
-                       alpha_dst, hole, st);
+    if (rows_preserved(src, dst, P)) {
+        hipLaunchKernelGGL(k_reproject_rows, dim3(dst.H), dim3(256), sizeof(unsigned long long) * dst.W, s, src, dst, P,
+                           a_min, draw, alpha, rgb, rgb_dst, z_dst, alpha_dst, hole, st);
+    } else {
+        hipLaunchKernelGGL(k_fill_u64, dim3(grid(nd)), dim3(256), 0, s, zbuf, nd, ~0ull);
+        hipLaunchKernelGGL(k_reproject_scatter, dim3(grid(ns)), dim3(256), 0, s, src, dst, P, a_min, draw, alpha, zbuf,
+                           st);
+        hipLaunchKernelGGL(k_reproject_resolve, dim3(grid(nd)), dim3(256), 0, s, nd, ns, zbuf, rgb, alpha, rgb_dst,
+                           z_dst, alpha_dst, hole, st);
+    }
     hipLaunchKernelGGL(k_depth_range, dim3(1), dim3(1), 0, s, st, (float)src.z_near, (float)src.z_far, depth_range);
     return hipGetLastError();
 }
 
-hipError_t launch_label_components(const uint8_t* mask, int W, int H, int conn, int32_t* labels, hipStream_t s) {
+static hipError_t label_components(const uint8_t* mask, int W, int H, int conn, int32_t* labels, uint8_t* pflag,
+                                   int4* pbox, hipStream_t s) {
     const int64_t n = (int64_t)W * H;
     if (n == 0) return hipSuccess;
     dim3 g((W + 15) / 16, (H + 15) / 16);
-    hipLaunchKernelGGL(k_ccl_local, g, dim3(256), 0, s, W, H, conn, mask, labels);
+    hipLaunchKernelGGL(k_ccl_local, g, dim3(256), 0, s, W, H, conn, mask, labels, pflag, pbox);
     hipLaunchKernelGGL(k_ccl_border, g, dim3(256), 0, s, W, H, conn, mask, labels);
     hipLaunchKernelGGL(k_ccl_flatten, dim3(grid(n)), dim3(256), 0, s, n, labels);
     return hipGetLastError();
+}
+
+hipError_t launch_label_components(const uint8_t* mask, int W, int H, int conn, int32_t* labels, hipStream_t s) {
+    return label_components(mask, W, H, conn, labels, nullptr, nullptr, s);
 }
 
 hipError_t launch_classify(const WarpCam& src, const WarpCam& dst, const RelPose& P, const bgs_roi_params& roi,
@@ -711,38 +817,27 @@ hipError_t launch_classify(const WarpCam& src, const WarpCam& dst, const RelPose
     const int tiles_x = (W + T - 1) / T, tiles_y = (H + T - 1) / T;
     hipLaunchKernelGGL(k_edge_rois, dim3(1), dim3(256), 0, s, src, dst, P, roi.edge_samples, roi.margin, T,
                        depth_range, st, boxes, box_cap);
-    hipLaunchKernelGGL(k_hole_init, dim3(grid(n)), dim3(256), 0, s, n, cls, b.hole);
-    // Jacobi passes ping-pong between the caller's image and the scratch copy.
-    float *ri = rgb, *zi = z, *ai = alpha, *ro = b.rgb2, *zo = b.z2, *ao = b.a2;
-    uint8_t *hi = b.hole, *ho = b.hole2;
-    for (int pass = 0; pass < roi.gap_passes; ++pass) {
-        hipLaunchKernelGGL(k_gap_pass, dim3(grid(n)), dim3(256), 0, s, W, H, ri, zi, ai, hi, ro, zo, ao, ho, cls, st);
-        float* t;
-        t = ri; ri = ro; ro = t;
-        t = zi; zi = zo; zo = t;
-        t = ai; ai = ao; ao = t;
-        uint8_t* th = hi; hi = ho; ho = th;
-    }
-    if (ri != rgb)
-        hipLaunchKernelGGL(k_copy_state, dim3(grid(n)), dim3(256), 0, s, n, ri, zi, ai, rgb, z, alpha);
-    // hi now holds the hole state after interpolation; ho is free scratch.
-    uint8_t* center = ho;
-    hipLaunchKernelGGL(k_center_mask, dim3(grid(n)), dim3(256), 0, s, W, H, hi, center, st);
+    uint8_t* tag = b.hole;
+    hipLaunchKernelGGL(k_tag_init, dim3(grid(n)), dim3(256), 0, s, n, cls, tag);
+    for (int pass = 1; pass <= roi.gap_passes; ++pass)
+        hipLaunchKernelGGL(k_gap_pass, dim3(grid(n)), dim3(256), 0, s, W, H, pass, rgb, z, alpha, tag, cls, st);
+    uint8_t* center = b.hole2;
+    hipLaunchKernelGGL(k_center_mask, dim3(grid(n)), dim3(256), 0, s, W, H, tag, center, st);
     hipLaunchKernelGGL(k_tile_mask_edges, dim3(grid((int64_t)tiles_x * tiles_y)), dim3(256), 0, s, tiles_x, tiles_y, T,
                        st, tile_mask);
     if (roi.center_roi) {
-        hipError_t e = launch_label_components(center, W, H, 8, labels, s);
+        hipError_t e = label_components(center, W, H, 8, labels, b.pflag, b.pbox, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_root_flags, dim3(grid(n)), dim3(256), 0, s, n, labels, b.flags);
         e = exclusive_scan(b.flags, nullptr, b.flags, nullptr, n, b.scan_tmp, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_bbox_init, dim3(grid(n)), dim3(256), 0, s, n, labels, b.flags, b.bbox);
-        hipLaunchKernelGGL(k_bbox_acc, dim3(grid(n)), dim3(256), 0, s, W, n, labels, b.flags, b.bbox);
+        hipLaunchKernelGGL(k_bbox_acc, dim3(grid(n)), dim3(256), 0, s, n, labels, b.pflag, b.pbox, b.flags, b.bbox);
         hipLaunchKernelGGL(k_center_boxes, dim3(grid(n)), dim3(256), 0, s, W, H, n, roi.margin, T, tiles_x, labels,
                            b.flags, b.bbox, boxes, box_cap, tile_mask, st);
     } else {
         hipLaunchKernelGGL(k_fill_i32, dim3(grid(n)), dim3(256), 0, s, n, labels, -1);
-        hipLaunchKernelGGL(k_row_fill, dim3(H), dim3(256), 0, s, W, H, hi, center, bg[0], bg[1], bg[2], rgb, z, alpha,
+        hipLaunchKernelGGL(k_row_fill, dim3(H), dim3(256), 0, s, W, H, tag, center, bg[0], bg[1], bg[2], rgb, z, alpha,
                            cls, st);
     }
     hipLaunchKernelGGL(k_box_count, dim3(1), dim3(1), 0, s, n, b.flags, box_cap, n_boxes, st, roi.center_roi);

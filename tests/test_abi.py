@@ -40,7 +40,7 @@ def test_struct_sizes():
     assert C.sizeof(_abi.RasterParams) == 32
     assert C.sizeof(_abi.RoiParams) == 24
     assert C.sizeof(_abi.Box) == 24
-    assert C.sizeof(_abi.Stats) == 80
+    assert C.sizeof(_abi.Stats) == 144
 
 
 @pytest.fixture

@@ -160,6 +160,32 @@ def test_render_dominant_cube(ctx, oracle, W, H):
     check_image(to_np(out["rgb"]), to_np(out["depth_raw"]), to_np(out["alpha"]), ref, f"cube {W}x{H}")
 
 
+@pytest.mark.parametrize("cap,seg", [(64, 32), (200, 16), (1, 1)])
+def test_render_split_long_lists(ctx, oracle, cap, seg):
+    """Long lists handed to segment workgroups (small caps force it on most
+    tiles, and opaque surfels make pixels saturate inside segments, which
+    exercises the in-order re-walk) give the oracle's pixels, and agree
+    with the unsplit blend to fp32 rounding."""
+    sc, cam = cube_workload(10_000, 144, 112, 170.0, seed=4)
+    sc.opacity[:] = np.maximum(sc.opacity, 0.9)
+    ds = api.DeviceScene(sc)
+    log(f"split cap={cap} seg={seg}")
+    try:
+        ctx.set_blend_split(0)
+        whole = ctx.render_dominant(ds, cam)
+        ctx.set_blend_split(cap, seg)
+        out = ctx.render_dominant(ds, cam)
+    finally:
+        ctx.set_blend_split(768, 384)
+    ref = oracle.render(sc, cam)
+    check_image(to_np(out["rgb"]), to_np(out["depth_raw"]), to_np(out["alpha"]), ref, f"split {cap}/{seg}")
+    amb = ref["amb"] > 0
+    for k in ("rgb", "depth_raw", "alpha"):
+        diff = np.abs(to_np(out[k]) - to_np(whole[k]))
+        scale = 1.0 if k != "depth_raw" else np.abs(to_np(whole[k])).max() + 1e-3
+        assert float((diff / scale)[..., ~amb].max()) <= 2e-5, k
+
+
 def test_render_edge_cases(ctx, oracle):
     # Empty scene -> background; one opaque surfel -> depth proxy = its depth;
     # surfels behind the camera are culled.
@@ -201,15 +227,22 @@ def test_render_dominant_full_size_sampled(ctx, oracle, name, n_px):
 # Stages 2-3: bit-exact given identical inputs
 # ---------------------------------------------------------------------------
 
-def stage_rig(W, H, f, b=0.064):
+def stage_rig(W, H, f, b=0.064, turn=0.0):
     dom = synth.look_at((0.0, -4.0, 0.0), (0, 0, 0), (0, 0, 1), W, H, f)
-    return dom, synth.affiliated(dom, b)
+    aff = synth.affiliated(dom, b)
+    if turn:
+        # A toed-in affiliated eye: rows are no longer preserved, so the
+        # general scatter path with the global z-buffer is the one used.
+        aff = synth.look_at(aff.t, (turn, 0.0, 0.3 * turn), (0, 0, 1), W, H, f)
+    return dom, aff
 
 
-@pytest.mark.parametrize("W,H,seed,b", [(256, 256, 0, 0.064), (800, 600, 1, 0.064), (203, 117, 2, 0.3),
-                                        (160, 120, 3, 0.0), (96, 64, 4, -0.2)])
-def test_reproject_bit_exact(ctx, oracle, W, H, seed, b):
-    dom, aff = stage_rig(W, H, 1.2 * W, b)
+@pytest.mark.parametrize("W,H,seed,b,turn", [(256, 256, 0, 0.064, 0.0), (800, 600, 1, 0.064, 0.0),
+                                             (203, 117, 2, 0.3, 0.0), (160, 120, 3, 0.0, 0.0),
+                                             (96, 64, 4, -0.2, 0.0), (256, 192, 5, 0.064, 0.05),
+                                             (800, 600, 6, 0.1, -0.2)])
+def test_reproject_bit_exact(ctx, oracle, W, H, seed, b, turn):
+    dom, aff = stage_rig(W, H, 1.2 * W, b, turn)
     rgb, dr, a = synth.stage_images(W, H, seed)
     out = ctx.reproject(dom, aff, torch.from_numpy(rgb).cuda(), torch.from_numpy(dr).cuda(), torch.from_numpy(a).cuda())
     ref = oracle.reproject(dom, aff, rgb, dr, a)
@@ -221,10 +254,11 @@ def test_reproject_bit_exact(ctx, oracle, W, H, seed, b):
 
 
 @pytest.mark.parametrize("center", [True, False])
-@pytest.mark.parametrize("W,H,seed,b", [(256, 256, 5, 0.064), (800, 600, 6, 0.15), (203, 117, 7, 0.3),
-                                        (1600, 1064, 8, 0.064)])
-def test_classify_bit_exact(ctx, oracle, center, W, H, seed, b):
-    dom, aff = stage_rig(W, H, 1.2 * W, b)
+@pytest.mark.parametrize("W,H,seed,b,turn", [(256, 256, 5, 0.064, 0.0), (800, 600, 6, 0.15, 0.0),
+                                             (203, 117, 7, 0.3, 0.0), (1600, 1064, 8, 0.064, 0.0),
+                                             (320, 240, 9, 0.1, 0.1)])
+def test_classify_bit_exact(ctx, oracle, center, W, H, seed, b, turn):
+    dom, aff = stage_rig(W, H, 1.2 * W, b, turn)
     rgb, dr, a = synth.stage_images(W, H, seed, n_occluders=10)
     rep = oracle.reproject(dom, aff, rgb, dr, a)
     roi = api.Roi(center_roi=center)
