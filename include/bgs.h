@@ -160,18 +160,6 @@ BGS_API const char* bgs_last_error(const bgs_ctx* ctx);
  * (pixel, surfel) pairs into bgs_stats (slower; for measurement only). */
 BGS_API int32_t bgs_ctx_set_count_pairs(bgs_ctx* ctx, int32_t count);
 
-/* Scheduling of long tile lists in the blend (the pixels do not depend on
- * it beyond fp32 rounding of the composited sums).  A tile first composites
- * at most cap records of its list; if pixels are still unsaturated, the rest
- * of the list is split into up to 8 segments of at least seg_len records
- * that other workgroups composite at once, each from full transmittance, and
- * the segments are then chained front to back (a segment inside which a
- * pixel would reach the termination threshold is composited again in order
- * from that pixel's running state).  cap = 0 composites every list in one
- * pass.  Defaults: cap 768, seg_len 384.  Returns BGS_ERR_INVALID_ARG for
- * cap < 0 or seg_len < 1. */
-BGS_API int32_t bgs_ctx_set_blend_split(bgs_ctx* ctx, int32_t cap, int32_t seg_len);
-
 /* Per-stage GPU timing with HIP events recorded on the context's stream
  * around each stage's launches.  on = 1 enables it and clears the totals.
  * After the caller has waited for the stream, bgs_timing_collect() adds the
@@ -299,7 +287,8 @@ BGS_API int32_t bgs_preprocess_debug(bgs_ctx* ctx, const bgs_scene* scene, const
 
 /* Per-tile trace of the last dominant-eye blend run with pair counting on
  * (bgs_ctx_set_count_pairs): for each launched block, 6 int64 {tile, list
- * length, longest wave walk, CU id, start, end (wall clock, 100 MHz)}.
+ * length, most records one wave evaluated, CU id, start, end (wall
+ * clock, 100 MHz)}.
  * n, width, height are those the workspace was laid out for.  Waits for
  * the stream.  Measurement only. */
 BGS_API int32_t bgs_blend_trace(bgs_ctx* ctx, int64_t n, int32_t width, int32_t height, void* ws, size_t ws_bytes,

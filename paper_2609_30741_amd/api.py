@@ -133,11 +133,6 @@ class Context:
     def set_count_pairs(self, on: bool):
         self._check(self.L.bgs_ctx_set_count_pairs(self.h, int(bool(on))))
 
-    def set_blend_split(self, cap: int, seg_len: int = 384):
-        """Long-list scheduling of the blend: cap records per tile before the
-        rest is split into segments of >= seg_len records (cap 0: no split)."""
-        self._check(self.L.bgs_ctx_set_blend_split(self.h, int(cap), int(seg_len)))
-
     def set_timing(self, on: bool):
         """Enable per-stage HIP-event timing on this context's stream (clears totals)."""
         self._check(self.L.bgs_ctx_set_timing(self.h, int(bool(on))))

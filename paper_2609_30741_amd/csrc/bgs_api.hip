@@ -15,8 +15,6 @@ struct bgs_ctx {
     int sync = 1;
     int count_pairs = 0;
     int timing = 0;
-    uint32_t blend_cap = 768;      // records a tile walks before splitting the rest (0: never split)
-    uint32_t blend_seg_len = 384;  // least records per continuation segment
     hipEvent_t ev[BGS_NUM_STAGES][2] = {};
     bool pending[BGS_NUM_STAGES] = {};
     double total_ms[BGS_NUM_STAGES] = {};
@@ -28,11 +26,6 @@ namespace bgs {
 namespace {
 
 constexpr size_t kAlign = 256;
-// Long tile lists: a tile walks the context's blend_cap records, then hands
-// the rest to up to kContSeg segment blocks of at least blend_seg_len records
-// each; at most kContSlots tiles per pass are continued this way.
-constexpr int64_t kContSlots = 512;
-constexpr uint32_t kContSeg = 8;
 
 inline size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -48,8 +41,6 @@ struct Layout {
     size_t tkeys_a, tkeys_b, tvals_a, tvals_b;
     size_t radix;
     size_t trace;  // per-tile blend trace of the last counting-mode dominant pass
-    size_t cdesc, cdone, cstate1, cseg;  // long-list continuation (slots x segments)
-    int64_t cslots;
     size_t total;
 };
 
@@ -93,11 +84,6 @@ Layout make_layout(int64_t n, int64_t W, int64_t H, int64_t kc) {
     L.tvals_b = take(4 * kc);
     L.radix = take(radix_tmp_bytes(kc > n ? kc : n));
     L.trace = take(6 * 8 * nt);
-    L.cslots = nt < kContSlots ? nt : kContSlots;
-    L.cdesc = take(16 * L.cslots);
-    L.cdone = take(4 * L.cslots);
-    L.cstate1 = take(32 * 256 * L.cslots);
-    L.cseg = take(32 * 256 * kContSeg * L.cslots);
     L.total = o;
     return L;
 }
@@ -354,12 +340,9 @@ int raster_pass(bgs_ctx* ctx, const Layout& L, void* ws, int64_t kc, const bgs_s
     ba.a_min = a_min;
     ba.z_near = (float)cam.z_near;
     ba.patch = tile_mask ? 1 : 0;
-    ba.cap = ctx->blend_cap;
-    ContArgs ca{&st->n_cont, at<uint4>(ws, L.cdesc), at<uint32_t>(ws, L.cdone), at<float4>(ws, L.cstate1),
-                at<float4>(ws, L.cseg), ctx->blend_cap ? (uint32_t)L.cslots : 0u, kContSeg, ctx->blend_seg_len};
     mark(ctx, sb + 5, 0);
     HIP_CHECK(launch_blend(recs, svals, ranges, tile_mask ? at<uint32_t>(ws, L.tlist) : nullptr, torder,
-                           tile_mask ? &st->n_masked : nullptr, n_tiles, ba, ca, out.rgb, out.dz, out.alpha, out.cls,
+                           tile_mask ? &st->n_masked : nullptr, n_tiles, ba, out.rgb, out.dz, out.alpha, out.cls,
                            ctx->count_pairs ? &st->pairs[6 * which] : nullptr,
                            (ctx->count_pairs && which == 0) ? at<long long>(ws, L.trace) : nullptr, s),
               "blend");
@@ -416,14 +399,6 @@ const char* bgs_last_error(const bgs_ctx* ctx) { return ctx ? ctx->err.c_str() :
 int32_t bgs_ctx_set_count_pairs(bgs_ctx* ctx, int32_t count) {
     if (!ctx) return BGS_ERR_INVALID_ARG;
     ctx->count_pairs = count ? 1 : 0;
-    return BGS_OK;
-}
-
-int32_t bgs_ctx_set_blend_split(bgs_ctx* ctx, int32_t cap, int32_t seg_len) {
-    if (!ctx) return BGS_ERR_INVALID_ARG;
-    if (cap < 0 || seg_len < 1) return fail(ctx, BGS_ERR_INVALID_ARG, "blend split: need cap >= 0 and seg_len >= 1");
-    ctx->blend_cap = (uint32_t)cap;
-    ctx->blend_seg_len = (uint32_t)seg_len;
     return BGS_OK;
 }
 

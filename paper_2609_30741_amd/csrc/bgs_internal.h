@@ -17,18 +17,19 @@ constexpr int kRadixBlock = 256 * kRadixItems;  // 4096 keys per block
 constexpr int kScanItems = 8;        // elements per thread in a scan block
 constexpr int kScanBlock = 256 * kScanItems;    // 2048 elements per block
 
-// Per-surfel record written by the preprocess and read (one record per
-// wave-uniform scalar load) by the blend kernel.  64 bytes.
+// Per-surfel record written by the preprocess and staged through LDS by the
+// blend kernel.  64 bytes.
 //   a = (mu_x, mu_y, C1, C2)    projected centre; u numerator coefficients
 //   b = (D1, D2, N1, N2)        v numerator; common denominator
-//   c = (lam_num, z_c, opacity, pixbox_lo)
-//   d = (r, g, b, pixbox_hi)
+//   c = (lam_num, z_c, opacity, band direction)
+//   d = (r, g, b, band interval)
 // With dx = i - mu_x, dy = j - mu_y and den = 1 + N1 dx + N2 dy the
 // surfel-plane coordinates of pixel (i, j) are u = (C1 dx + C2 dy)/den,
 // v = (D1 dx + D2 dy)/den and the ray meets the plane at depth
 // lam_num/den (lam_num < 0 marks a surfel seen exactly edge-on).  The
-// pixel box (x0 | y0 << 16, x1 | y1 << 16) bounds every pixel the surfel
-// can reach.
+// strip band bounds every pixel x the surfel can reach by
+// |n.(x - mu) - c| <= w, with n a pair of snorm16 (x low, y high) and c, w
+// a pair of fp16 (c low, w high).
 struct alignas(16) SurfelRec {
     float4 a, b, c, d;
 };
@@ -71,27 +72,14 @@ struct BlendArgs {
     float a_min;     // patch mode: depth proxy written only when A >= a_min
     float z_near;
     int patch;       // 0: write rgb/depth_raw/alpha; 1: write rgb/z/alpha/cls
-    uint32_t cap;    // records a tile walks before it may hand its rest to segment blocks
 };
 
-// Continuation of long tile lists (see k_blend / k_blend_cont).
-struct ContArgs {
-    uint32_t* n_slots;   // device counter of slots taken
-    uint4* desc;         // per slot: compact tile id, first record, end record, segments
-    uint32_t* done;      // per slot: segment blocks finished
-    float4* state1;      // per slot: 256 pixels x 2 float4 after the capped walk
-    float4* seg_state;   // per slot and segment: 256 pixels x 2 float4
-    uint32_t max_slots;  // 0 disables continuation
-    uint32_t max_seg;
-    uint32_t seg_len;    // records per segment (at most max_seg segments)
-};
 
 // Device status block kept in the workspace.
 struct DevStatus {
     uint32_t n_keys;       // keys of the last binning (may exceed capacity)
     uint32_t n_sort;       // min(n_keys, capacity): keys actually sorted
     uint32_t n_masked;     // masked tiles of the last ROI patch
-    uint32_t n_cont;       // continuation slots requested by the last blend
     uint32_t n_keys_dom;
     uint32_t n_keys_roi;
     uint32_t overflow;     // bit 0 key capacity, bit 1 box capacity
@@ -139,7 +127,7 @@ hipError_t launch_tile_order(const uint2* ranges, const uint32_t* n_live, int n_
 // pair_counts (optional): the six blend counters of DevStatus::pairs.
 hipError_t launch_blend(const SurfelRec* recs, const uint32_t* vals, const uint2* ranges,
                         const uint32_t* tile_list, const uint32_t* order, const uint32_t* n_live, int n_blocks,
-                        const BlendArgs& a, const ContArgs& ca, float* rgb, float* d_or_z, float* alpha, uint8_t* cls,
+                        const BlendArgs& a, float* rgb, float* d_or_z, float* alpha, uint8_t* cls,
                         unsigned long long* pair_counts, long long* trace, hipStream_t s);
 // prefix[n_tiles + 1] and the compact list of masked tile ids; tmp32 holds
 // n_tiles words, scan_tmp scan_tmp_elems(n_tiles) words.

@@ -61,6 +61,119 @@ __device__ inline uint32_t masked_count(const MaskArgs& m, int tiles_x, int tx0,
     return c;
 }
 
+// ---------------------------------------------------------------------------
+// Strip band of a surfel: a direction n (snorm16 pair) and an interval
+// [n.mu + c - w, n.mu + c + w] (fp16 c, w) of n.x that holds every pixel x
+// the surfel can reach with alpha >= alpha_min.  The blend skips a record
+// for a 16x4 strip that lies outside the band, which is exact: such a
+// record is a no-op on every pixel of the strip.  Tile binning already
+// guarantees overlap in x, so the band only has to separate strips in y;
+// n is the footprint's narrowest direction when that confines the strips of
+// a tile column better than the y extent, else the y axis.  The band is
+// computed for the quantised n the blend decodes, and padded for the fp16
+// rounding and for the blend's fp32 arithmetic.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float snorm16_value(int q) { return (float)q * (1.0f / 32767.0f); }
+
+__device__ __forceinline__ uint32_t half_bits(float x) {
+    return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)x);
+}
+
+__device__ __forceinline__ float half_value(uint32_t bits) {
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(bits & 0xFFFFu));
+}
+
+// Smallest fp16 value >= x (x >= 0), +inf beyond the fp16 range.
+__device__ __forceinline__ uint32_t half_bits_up(double x) {
+    if (!(x <= 65504.0)) return 0x7C00u;
+    uint32_t h = half_bits((float)x);
+    while ((double)half_value(h) < x) ++h;
+    return h;
+}
+
+// Interval of n.x over the conic's outline (dual conic C in normalised
+// camera coordinates) for a pixel-space direction n: the tangent lines
+// n.x = s solve m^T C2 m - 2 s' m.c3 + s'^2 c22 = 0 with m = (fx nx, fy ny)
+// and s = s' + n.(cx, cy).
+__device__ __forceinline__ void conic_extent(double nx, double ny, double c00, double c01, double c02, double c11,
+                                             double c12, double c22, const PreCam& cam, double& lo, double& hi) {
+    const double mx = cam.fx * nx, my = cam.fy * ny;
+    const double mc = mx * c02 + my * c12;
+    const double mm = mx * mx * c00 + 2.0 * mx * my * c01 + my * my * c11;
+    const double d = sqrt(fmax(mc * mc - c22 * mm, 0.0));
+    const double s0 = (mc - d) / c22, s1 = (mc + d) / c22;
+    const double off = nx * cam.cx + ny * cam.cy;
+    lo = fmin(s0, s1) + off;
+    hi = fmax(s0, s1) + off;
+}
+
+__device__ uint2 strip_band(bool bounded, double c00, double c01, double c02, double c11, double c12, double c22,
+                            const PreCam& cam, double mux, double muy, double r_lowpass, double xmin, double xmax,
+                            double ymin, double ymax) {
+    int qx = 0, qy = 32767;
+    if (bounded) {
+        // Narrowest direction: smallest eigenvector of F (c3 c3^T - c22 C2) F.
+        const double s00 = cam.fx * cam.fx * (c02 * c02 - c22 * c00);
+        const double s11 = cam.fy * cam.fy * (c12 * c12 - c22 * c11);
+        const double s01 = cam.fx * cam.fy * (c02 * c12 - c22 * c01);
+        const double h = 0.5 * (s00 - s11);
+        const double lmin = 0.5 * (s00 + s11) - sqrt(h * h + s01 * s01);
+        double ex = s01, ey = lmin - s00;
+        const double fx2 = lmin - s11, fy2 = s01;
+        if (fx2 * fx2 + fy2 * fy2 > ex * ex + ey * ey) {
+            ex = fx2;
+            ey = fy2;
+        }
+        const double en = sqrt(ex * ex + ey * ey);
+        if (en > 0.0 && isfinite(en)) {
+            ex /= en;
+            ey /= en;
+            if (ey < 0.0) {
+                ex = -ex;
+                ey = -ey;
+            }
+            const int cx = (int)rint(ex * 32767.0), cy = (int)rint(ey * 32767.0);
+            const double nx = snorm16_value(cx), ny = snorm16_value(cy);
+            double lo, hi;
+            conic_extent(nx, ny, c00, c01, c02, c11, c12, c22, cam, lo, hi);
+            const double nmu = nx * mux + ny * muy, rn = r_lowpass * sqrt(nx * nx + ny * ny);
+            lo = fmin(lo, nmu - rn);
+            hi = fmax(hi, nmu + rn);
+            // Length of the strip-centre rows of one tile column that pass.
+            const double pass_n = ny > 1e-6 ? (0.5 * (hi - lo) + 7.5 * fabs(nx) + 1.5 * ny) / ny : INFINITY;
+            const double pass_y = 0.5 * (ymax - ymin) + 1.5;
+            if (pass_n < pass_y) {
+                qx = cx;
+                qy = cy;
+            }
+        }
+    }
+    const double nx = snorm16_value(qx), ny = snorm16_value(qy);
+    double lo, hi;
+    if (!bounded) {
+        lo = -INFINITY;
+        hi = INFINITY;
+    } else if (qx == 0 && qy == 32767) {
+        lo = ny * ymin;  // ymin/ymax already hold the low-pass disc
+        hi = ny * ymax;
+    } else {
+        conic_extent(nx, ny, c00, c01, c02, c11, c12, c22, cam, lo, hi);
+        const double nmu = nx * mux + ny * muy, rn = r_lowpass * sqrt(nx * nx + ny * ny);
+        lo = fmin(lo, nmu - rn);
+        hi = fmax(hi, nmu + rn);
+    }
+    const uint32_t nbits = ((uint32_t)qx & 0xFFFFu) | ((uint32_t)qy << 16);
+    if (!(isfinite(lo) && isfinite(hi))) return make_uint2(nbits, 0u | (0x7C00u << 16));
+    const double nmu = nx * (double)(float)mux + ny * (double)(float)muy;
+    const double c = 0.5 * (lo + hi) - nmu;
+    const uint32_t cb = half_bits((float)c);
+    const double rx = fmax(fabs(xmin - mux), fabs(xmax - mux)), ry = fmax(fabs(ymin - muy), fabs(ymax - muy));
+    const double pad = 0.05 + 1e-6 * (fabs(mux) + fabs(muy) + sqrt(rx * rx + ry * ry) + cam.W + cam.H) +
+                       fabs(nmu - (nx * mux + ny * muy));
+    const double w = 0.5 * (hi - lo) + fabs(c - (double)half_value(cb)) + pad;
+    return make_uint2(nbits, cb | (half_bits_up(w) << 16));
+}
+
 __global__ __launch_bounds__(256) void k_preprocess(SceneArgs sc, PreCam cam, float alpha_min, int lowpass,
                                                     MaskArgs mask, SurfelRec* __restrict__ recs,
                                                     uint32_t* __restrict__ zkeys, uint2* __restrict__ rects,
@@ -115,16 +228,20 @@ __global__ __launch_bounds__(256) void k_preprocess(SceneArgs sc, PreCam cam, fl
     const double lr = log((double)op / (double)alpha_min);
     const double rho = sqrt(2.0 * lr) * (1.0 + 1e-5);
     double xmin = INFINITY, xmax = -INFINITY, ymin = INFINITY, ymax = -INFINITY;
+    bool bounded = false;
+    double c00 = 0, c01 = 0, c02 = 0, c11 = 0, c12 = 0, c22 = -1;
     {
         const double A[3] = {rho * su * a[0], rho * su * a[1], rho * su * a[2]};
         const double B[3] = {rho * sv * b[0], rho * sv * b[1], rho * sv * b[2]};
         const double zr2 = A[2] * A[2] + B[2] * B[2];
         if (pzc > 0.0 && pzc * pzc > zr2 * (1.0 + 1e-6) + 1e-12) {
-            const double c22 = zr2 - pzc * pzc;
-            const double c00 = A[0] * A[0] + B[0] * B[0] - pc[0] * pc[0];
-            const double c02 = A[0] * A[2] + B[0] * B[2] - pc[0] * pzc;
-            const double c11 = A[1] * A[1] + B[1] * B[1] - pc[1] * pc[1];
-            const double c12 = A[1] * A[2] + B[1] * B[2] - pc[1] * pzc;
+            bounded = true;
+            c22 = zr2 - pzc * pzc;
+            c00 = A[0] * A[0] + B[0] * B[0] - pc[0] * pc[0];
+            c01 = A[0] * A[1] + B[0] * B[1] - pc[0] * pc[1];
+            c02 = A[0] * A[2] + B[0] * B[2] - pc[0] * pzc;
+            c11 = A[1] * A[1] + B[1] * B[1] - pc[1] * pc[1];
+            c12 = A[1] * A[2] + B[1] * B[2] - pc[1] * pzc;
             const double dx = sqrt(fmax(c02 * c02 - c00 * c22, 0.0));
             const double dy = sqrt(fmax(c12 * c12 - c11 * c22, 0.0));
             const double kx0 = (c02 - dx) / c22, kx1 = (c02 + dx) / c22;
@@ -158,6 +275,8 @@ __global__ __launch_bounds__(256) void k_preprocess(SceneArgs sc, PreCam cam, fl
         return;
     }
     const int x0 = (int)fx0, x1 = (int)fx1, y0 = (int)fy0, y1 = (int)fy1;
+    const uint2 band = strip_band(bounded, c00, c01, c02, c11, c12, c22, cam, mux, muy,
+                                  lowpass ? sqrt(lr) * (1.0 + 1e-5) : 0.0, xmin, xmax, ymin, ymax);
     const int tx0 = x0 / kTile, tx1 = x1 / kTile, ty0 = y0 / kTile, ty1 = y1 / kTile;
     const uint32_t cnt = mask.enabled ? masked_count(mask, cam.tiles_x, tx0, ty0, tx1, ty1)
                                       : (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
@@ -213,8 +332,8 @@ __global__ __launch_bounds__(256) void k_preprocess(SceneArgs sc, PreCam cam, fl
     SurfelRec rec;
     rec.a = make_float4((float)mux, (float)muy, C1, C2);
     rec.b = make_float4(D1, D2, N1, N2);
-    rec.c = make_float4(lam_num, (float)pzc, op, __uint_as_float((uint32_t)x0 | ((uint32_t)y0 << 16)));
-    rec.d = make_float4(col[0], col[1], col[2], __uint_as_float((uint32_t)x1 | ((uint32_t)y1 << 16)));
+    rec.c = make_float4(lam_num, (float)pzc, op, __uint_as_float(band.x));
+    rec.d = make_float4(col[0], col[1], col[2], __uint_as_float(band.y));
     recs[k] = rec;
 }
 
@@ -303,7 +422,6 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key
 }
 
 __global__ void k_status_keys(const uint32_t* __restrict__ offs, int n, DevStatus* st, uint32_t cap, int which) {
-    st->n_cont = 0;
     const uint32_t K = offs[n];
     st->n_keys = K;
     st->n_sort = K < cap ? K : cap;
@@ -328,15 +446,94 @@ __global__ __launch_bounds__(256) void k_mask_list(const uint8_t* __restrict__ m
     }
 }
 
-// One (pixel, surfel) step of front-to-back compositing (Eq. 2 with the
-// plane homography of the record), branch-free: alpha = min(alpha_max,
-// o * max(G3, G2)); a pair below alpha_min is skipped; the pixel stops
-// before the surfel that would take T below t_min; otherwise RGB, the depth
-// proxy D and A accumulate with the same weight w = alpha * T.
-__device__ __forceinline__ void composite(const float4& r0, const float4& r1, const float4& r2, const float4& r3,
-                                          float fpx, float fpy, const BlendArgs& a, bool& live, float& T, float& c0,
-                                          float& c1, float& c2, float& D, float& A, uint32_t& n_eval,
-                                          uint32_t& n_used, bool count) {
+// ---------------------------------------------------------------------------
+// Tile order for the blend: tiles by decreasing key count, bucketed by the
+// leading bit and the next four bits of the count (about 6% resolution), so
+// that the heaviest tiles are dispatched first and spread over all CUs.
+// The order only decides which block renders which tile; every tile's
+// pixels are computed the same way whatever the order.
+// ---------------------------------------------------------------------------
+constexpr int kOrderBuckets = 32 * 16 + 1;  // (octave, 4 mantissa bits), then empty tiles
+
+__device__ __forceinline__ uint32_t order_bucket(uint32_t len) {
+    if (len == 0) return kOrderBuckets - 1;
+    const uint32_t e = 31u - (uint32_t)__clz((int)len);
+    const uint32_t m = e >= 4 ? (len >> (e - 4)) & 15u : (len << (4 - e)) & 15u;
+    return (31u - e) * 16u + (15u - m);
+}
+
+__global__ __launch_bounds__(1024) void k_tile_order(const uint2* __restrict__ ranges, const uint32_t* n_live,
+                                                     uint32_t n_tiles, uint32_t* __restrict__ order) {
+    __shared__ uint32_t hist[kOrderBuckets];
+    __shared__ uint32_t wsum[16];
+    const uint32_t n = n_live ? min(*n_live, n_tiles) : n_tiles;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int i = tid; i < kOrderBuckets; i += 1024) hist[i] = 0;
+    __syncthreads();
+    for (uint32_t t = tid; t < n; t += 1024) {
+        const uint2 r = ranges[t];
+        atomicAdd(&hist[order_bucket(r.y - r.x)], 1u);
+    }
+    __syncthreads();
+    // Exclusive scan of the buckets (one per thread).
+    uint32_t v = tid < kOrderBuckets ? hist[tid] : 0u, x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    uint32_t wbase = 0;
+    for (int w = 0; w < wave; ++w) wbase += wsum[w];
+    if (tid < kOrderBuckets) hist[tid] = wbase + x - v;
+    __syncthreads();
+    for (uint32_t t = tid; t < n; t += 1024) {
+        const uint2 r = ranges[t];
+        order[atomicAdd(&hist[order_bucket(r.y - r.x)], 1u)] = t;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Blend.  One 256-thread block per 16x16 tile; wave w owns the 16x4 strip of
+// rows 4w..4w+3.  walk_range composites the records [b, e) of the tile's
+// sorted list into the block's pixels: batches of 256 records are fetched
+// by all threads with vector loads (the next batch while the current one is
+// composited) and put in LDS; each wave tests the whole batch against its
+// strip (the record's strip band) in one vector pass and writes the byte offsets of the records that
+// can touch it, in list order, to its own LDS list, padded with an all-zero
+// record that never contributes.  It then takes kTrip records per trip: their
+// alphas are independent and computed together, and only the short
+// transmittance chain runs in sequence.  The walk ends at the first batch
+// boundary where all 256 pixels are done.  Every thread of the block must
+// call it (it has block barriers).
+// ---------------------------------------------------------------------------
+constexpr int kBatch = 256;
+constexpr int kTrip = 4;                // records per trip of the walk
+constexpr int kDummy = kBatch;          // LDS record index of the zero record
+constexpr int kListLen = kBatch + 4;    // per-wave hit list, with padding
+
+struct PixelState {
+    float T, c0, c1, c2, D, A;
+    bool live;
+};
+
+struct WalkCounts {
+    uint32_t eval, used, walk, test;
+};
+
+struct TileGeom {
+    int tid, lane;
+    float fpx, fpy;
+    float scx, scy;  // centre of the wave's 16x4 strip
+};
+
+// Alpha of one (pixel, surfel) pair (Eq. 2 with the plane homography of the
+// record): alpha = min(alpha_max, o * max(G3, G2)), and the depth the pair
+// adds to the proxy (the ray-plane depth where G3 wins, else the centre
+// depth).
+__device__ __forceinline__ void pair_alpha(const float4& r0, const float4& r1, const float4& r2, float fpx, float fpy,
+                                           const BlendArgs& a, float& al, float& dsel) {
     const float dx = fpx - r0.x, dy = fpy - r0.y;
     const float den = fmaf(r1.z, dx, fmaf(r1.w, dy, 1.f));
     const float w = __builtin_amdgcn_rcpf(den);
@@ -348,89 +545,39 @@ __device__ __forceinline__ void composite(const float4& r0, const float4& r1, co
     // fmaxf then keeps the low-pass term.
     const float e3 = lam > a.z_near ? -0.5f * fmaf(u, u, v * v) : -INFINITY;
     const float e2 = a.lowpass ? -fmaf(dx, dx, dy * dy) : -INFINITY;
-    const float e = fmaxf(e3, e2);
-    const float al = fminf(a.alpha_max, r2.z * __expf(e));
-    const float Tn = T * (1.f - al);
-    const bool use = live && al >= a.alpha_min;
+    al = fminf(a.alpha_max, r2.z * __expf(fmaxf(e3, e2)));
+    dsel = (e3 >= e2) ? lam : r2.y;
+}
+
+// One front-to-back compositing step: a pair below alpha_min is skipped;
+// the pixel stops before the surfel that would take T below t_min;
+// otherwise RGB, the depth proxy D and A accumulate with the same weight
+// w = alpha * T.
+__device__ __forceinline__ void accumulate(float al, float dsel, const float4& r3, const BlendArgs& a, PixelState& p,
+                                           WalkCounts& wc, bool count, bool valid) {
+    const float Tn = p.T * (1.f - al);
+    const bool use = p.live && al >= a.alpha_min;
     const bool stop = use && Tn < a.t_min;
     const bool add = use && !stop;
-    const float wt = add ? al * T : 0.f;
-    if (count) {
-        n_eval += live ? 1u : 0u;
-        n_used += add ? 1u : 0u;
+    const float wt = add ? al * p.T : 0.f;
+    if (count && valid) {
+        wc.eval += p.live ? 1u : 0u;
+        wc.used += add ? 1u : 0u;
     }
-    c0 = fmaf(wt, r3.x, c0);
-    c1 = fmaf(wt, r3.y, c1);
-    c2 = fmaf(wt, r3.z, c2);
-    D = fmaf(wt, (e3 >= e2) ? lam : r2.y, D);
-    A += wt;
-    T = add ? Tn : T;
-    live = live && !stop;
+    p.c0 = fmaf(wt, r3.x, p.c0);
+    p.c1 = fmaf(wt, r3.y, p.c1);
+    p.c2 = fmaf(wt, r3.z, p.c2);
+    p.D = fmaf(wt, dsel, p.D);
+    p.A += wt;
+    p.T = add ? Tn : p.T;
+    p.live = p.live && !stop;
 }
-
-// ---------------------------------------------------------------------------
-// Tile order for the blend: tiles by decreasing key count in log2 buckets,
-// so that the heaviest tiles are dispatched first and spread over all CUs.
-// The order only decides which block renders which tile; every tile's
-// pixels are computed the same way whatever the order.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_tile_order(const uint2* __restrict__ ranges, const uint32_t* n_live,
-                                                     uint32_t n_tiles, uint32_t* __restrict__ order) {
-    __shared__ uint32_t hist[33];
-    const uint32_t n = n_live ? min(*n_live, n_tiles) : n_tiles;
-    if (threadIdx.x < 33) hist[threadIdx.x] = 0;
-    __syncthreads();
-    for (uint32_t t = threadIdx.x; t < n; t += 1024) {
-        const uint2 r = ranges[t];
-        const uint32_t key = (uint32_t)__clz((int)(r.y - r.x));  // 32 for an empty tile; small = heavy
-        atomicAdd(&hist[key], 1u);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t acc = 0;
-        for (int b = 0; b < 33; ++b) {
-            uint32_t c = hist[b];
-            hist[b] = acc;
-            acc += c;
-        }
-    }
-    __syncthreads();
-    for (uint32_t t = threadIdx.x; t < n; t += 1024) {
-        const uint2 r = ranges[t];
-        const uint32_t key = (uint32_t)__clz((int)(r.y - r.x));
-        order[atomicAdd(&hist[key], 1u)] = t;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Blend.  One 256-thread block per 16x16 tile; wave w owns the 16x4 strip of
-// rows 4w..4w+3.  walk_range composites the records [b, e) of the tile's
-// sorted list into the block's pixels: batches of 256 records are fetched
-// by all threads with vector loads (the next batch while the current one is
-// composited) and put in LDS; each wave tests the whole batch against its
-// strip in one vector pass (a 256-bit mask) and then evaluates only the
-// records that can touch it, two per trip.  The walk ends at the first
-// batch boundary where all 256 pixels are done.  Every thread of the block
-// must call it (it has block barriers).
-// ---------------------------------------------------------------------------
-struct PixelState {
-    float T, c0, c1, c2, D, A;
-    bool live;
-};
-
-struct WalkCounts {
-    uint32_t eval, used, walk, test;
-};
-
-struct TileGeom {
-    int tid, lane, sx0, sx1, sy0, sy1;
-    float fpx, fpy;
-};
 
 template <bool kCount>
 __device__ __forceinline__ void walk_range(const SurfelRec* __restrict__ recs, const uint32_t* __restrict__ vals,
-                                           uint32_t b, uint32_t e, float4* s_rec, const TileGeom& g,
-                                           const BlendArgs& a, PixelState& p, WalkCounts& wc) {
+                                           uint32_t b, uint32_t e, float4* s_rec, uint16_t* s_list,
+                                           const TileGeom& g, const BlendArgs& a, PixelState& p, WalkCounts& wc) {
+    const char* s_bytes = reinterpret_cast<const char*>(s_rec);
     float4 q0, q1, q2, q3;
     {
         const uint32_t pos = b + g.tid;
@@ -439,8 +586,8 @@ __device__ __forceinline__ void walk_range(const SurfelRec* __restrict__ recs, c
             q0 = r->a; q1 = r->b; q2 = r->c; q3 = r->d;
         }
     }
-    for (uint32_t base = b; base < e; base += 256) {
-        const uint32_t nb = min(256u, e - base);
+    for (uint32_t base = b; base < e; base += kBatch) {
+        const uint32_t nb = min((uint32_t)kBatch, e - base);
         __syncthreads();
         if ((uint32_t)g.tid < nb) {
             s_rec[4 * g.tid + 0] = q0;
@@ -450,49 +597,66 @@ __device__ __forceinline__ void walk_range(const SurfelRec* __restrict__ recs, c
         }
         __syncthreads();
         {
-            const uint32_t pos = base + 256 + g.tid;
+            const uint32_t pos = base + kBatch + g.tid;
             if (pos < e) {
                 const SurfelRec* r = recs + vals[pos];
                 q0 = r->a; q1 = r->b; q2 = r->c; q3 = r->d;
             }
         }
-        uint64_t hit[4];
+        // Strip test and compaction of this wave's hits.
+        uint32_t nhit = 0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < kBatch / 64; ++q) {
             const uint32_t j = (uint32_t)(q * 64 + g.lane);
             bool h = false;
             if (j < nb) {
-                const uint32_t lo = __float_as_uint(s_rec[4 * j + 2].w), hi = __float_as_uint(s_rec[4 * j + 3].w);
-                h = !((int)(hi & 0xFFFF) < g.sx0 || (int)(lo & 0xFFFF) > g.sx1 || (int)(hi >> 16) < g.sy0 ||
-                      (int)(lo >> 16) > g.sy1);
+                const uint32_t nq = __float_as_uint(s_rec[4 * j + 2].w), bq = __float_as_uint(s_rec[4 * j + 3].w);
+                const float nx = snorm16_value((int)(int16_t)(nq & 0xFFFFu));
+                const float ny = snorm16_value((int)(int16_t)(nq >> 16));
+                const float4 r0 = s_rec[4 * j];
+                const float pr = fmaf(nx, g.scx - r0.x, ny * (g.scy - r0.y)) - half_value(bq);
+                h = fabsf(pr) <= half_value(bq >> 16) + fmaf(fabsf(nx), 7.5f, fabsf(ny) * 1.5f);
             }
-            hit[q] = __ballot(h);
+            const uint64_t m = __ballot(h);
+            if (h) {
+                const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                s_list[nhit + below] = (uint16_t)(j * 64u);
+            }
+            nhit += (uint32_t)__popcll(m);
         }
-        if (kCount) wc.walk += nb;
+        if (g.lane < kTrip) s_list[nhit + g.lane] = (uint16_t)(kDummy * 64);
+        // The list is written and read by this wave only.
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (kCount) {
+            wc.walk += nb;
+            wc.test += nhit;
+        }
+        for (uint32_t k = 0; k < nhit; k += kTrip) {
+            if (__ballot(p.live) == 0ull) break;
+            uint32_t off[kTrip];
+            if (kTrip == 4) {
+                const uint2 o = *reinterpret_cast<const uint2*>(s_list + k);
+                off[0] = o.x & 0xFFFFu;
+                off[1] = o.x >> 16;
+                off[2 % kTrip] = o.y & 0xFFFFu;
+                off[3 % kTrip] = o.y >> 16;
+            } else {
+                const uint32_t o = *reinterpret_cast<const uint32_t*>(s_list + k);
+                off[0] = o & 0xFFFFu;
+                off[1 % kTrip] = o >> 16;
+            }
+            float al[kTrip], ds[kTrip];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            uint64_t mm = hit[q];
-            while (mm) {
-                if (__ballot(p.live) == 0ull) break;
-                // Two records per trip: both are read before either is
-                // evaluated, so the second read overlaps the first's math.
-                const uint32_t j1 = (uint32_t)(q * 64) + (uint32_t)__ffsll((unsigned long long)mm) - 1u;
-                mm &= mm - 1ull;
-                const bool two = mm != 0ull;
-                const uint32_t j2 = two ? (uint32_t)(q * 64) + (uint32_t)__ffsll((unsigned long long)mm) - 1u : j1;
-                if (two) mm &= mm - 1ull;
-                const float4 a0 = s_rec[4 * j1 + 0], a1 = s_rec[4 * j1 + 1], a2 = s_rec[4 * j1 + 2],
-                             a3 = s_rec[4 * j1 + 3];
-                const float4 b0 = s_rec[4 * j2 + 0], b1 = s_rec[4 * j2 + 1], b2 = s_rec[4 * j2 + 2],
-                             b3 = s_rec[4 * j2 + 3];
-                composite(a0, a1, a2, a3, g.fpx, g.fpy, a, p.live, p.T, p.c0, p.c1, p.c2, p.D, p.A, wc.eval, wc.used,
-                          kCount);
-                if (kCount) ++wc.test;
-                if (two) {
-                    composite(b0, b1, b2, b3, g.fpx, g.fpy, a, p.live, p.T, p.c0, p.c1, p.c2, p.D, p.A, wc.eval,
-                              wc.used, kCount);
-                    if (kCount) ++wc.test;
-                }
+            for (int i = 0; i < kTrip; ++i) {
+                const float4* r = reinterpret_cast<const float4*>(s_bytes + off[i]);
+                pair_alpha(r[0], r[1], r[2], g.fpx, g.fpy, a, al[i], ds[i]);
+            }
+#pragma unroll
+            for (int i = 0; i < kTrip; ++i) {
+                const float4* r = reinterpret_cast<const float4*>(s_bytes + off[i]);
+                accumulate(al[i], ds[i], r[3], a, p, wc, kCount, k + i < nhit);
             }
         }
         if (__syncthreads_count(p.live) == 0) break;
@@ -510,10 +674,8 @@ __device__ __forceinline__ TileGeom tile_geom(uint32_t tile, const BlendArgs& a,
     *inside = *px < a.W && *py < a.H;
     g.fpx = (float)*px;
     g.fpy = (float)*py;
-    g.sx0 = tx * kTile;
-    g.sx1 = g.sx0 + kTile - 1;
-    g.sy0 = ty * kTile + wave * 4;
-    g.sy1 = g.sy0 + 3;
+    g.scx = (float)(tx * kTile) + 7.5f;
+    g.scy = (float)(ty * kTile + wave * 4) + 1.5f;
     return g;
 }
 
@@ -534,14 +696,6 @@ __device__ __forceinline__ void write_pixel(const PixelState& p, int px, int py,
     }
 }
 
-// Continuation state of one pixel: (c0, c1, c2, D) and (A, T, flag, 0);
-// flag = 1 for a pixel still compositing (phase 1) or one that stopped
-// inside the segment (segments).
-__device__ __forceinline__ void store_state(float4* st, int tid, const PixelState& p, bool flag) {
-    st[2 * tid + 0] = make_float4(p.c0, p.c1, p.c2, p.D);
-    st[2 * tid + 1] = make_float4(p.A, p.T, flag ? 1.f : 0.f, 0.f);
-}
-
 __device__ __forceinline__ void count_flush(const WalkCounts& wc, int lane, int wave, uint32_t len,
                                             unsigned long long* pair_counts, uint32_t* s_walk) {
     unsigned long long e = wc.eval, u = wc.used;
@@ -559,26 +713,24 @@ __device__ __forceinline__ void count_flush(const WalkCounts& wc, int lane, int 
         atomicAdd(&pair_counts[3], (unsigned long long)wc.test);
         atomicMax(&pair_counts[4], (unsigned long long)wc.walk);
         if (wave == 0) atomicMax(&pair_counts[5], (unsigned long long)len);
-        if (s_walk) s_walk[wave] = wc.walk;
+        if (s_walk) s_walk[wave] = wc.test;
     }
 }
 
-// Phase 1: every tile walks at most a.cap records of its list.  A tile that
-// is done by then (or whose list ends) writes its pixels; otherwise it takes
-// a continuation slot and leaves its state for the segment blocks (if no
-// slot is free it simply walks on).
+// One block per tile (compact id blk, taken in the order given, heaviest
+// lists first): composite the whole list, then write the pixels.
 template <bool kCount>
 __global__ __launch_bounds__(256) void k_blend(const SurfelRec* __restrict__ recs, const uint32_t* __restrict__ vals,
                                                const uint2* __restrict__ ranges, const uint32_t* __restrict__ tile_list,
                                                const uint32_t* __restrict__ order,
-                                               const uint32_t* __restrict__ n_live, BlendArgs a, ContArgs ca,
+                                               const uint32_t* __restrict__ n_live, BlendArgs a,
                                                float* __restrict__ rgb, float* __restrict__ dz,
                                                float* __restrict__ alpha, uint8_t* __restrict__ cls,
                                                unsigned long long* __restrict__ pair_counts,
                                                long long* __restrict__ trace) {
-    __shared__ float4 s_rec[256 * 4];
+    __shared__ float4 s_rec[(kBatch + 1) * 4];
+    __shared__ __align__(8) uint16_t s_list[4 * kListLen];
     __shared__ uint32_t s_walk[4];
-    __shared__ uint32_t s_slot;
     const long long t_begin = kCount ? wall_clock64() : 0;
     const uint32_t blk = blockIdx.x;
     if (n_live && blk >= *n_live) return;
@@ -590,34 +742,14 @@ __global__ __launch_bounds__(256) void k_blend(const SurfelRec* __restrict__ rec
     const uint2 rg = ranges[cid];
     PixelState p{1.f, 0.f, 0.f, 0.f, 0.f, 0.f, inside};
     WalkCounts wc{0, 0, 0, 0};
-    const uint32_t cap_end = (ca.max_slots > 0 && rg.y - rg.x > a.cap) ? rg.x + a.cap : rg.y;
-    walk_range<kCount>(recs, vals, rg.x, cap_end, s_rec, g, a, p, wc);
-    bool handed_off = false;
-    if (cap_end < rg.y && __syncthreads_count(p.live) > 0) {
-        if (g.tid == 0) {
-            const uint32_t c = atomicAdd(ca.n_slots, 1u);
-            s_slot = c < ca.max_slots ? c : 0xFFFFFFFFu;
-        }
-        __syncthreads();
-        const uint32_t slot = s_slot;
-        if (slot != 0xFFFFFFFFu) {
-            store_state(ca.state1 + (size_t)slot * 512, g.tid, p, p.live);
-            if (g.tid == 0) {
-                const uint32_t rem = rg.y - cap_end;
-                const uint32_t nseg = min((uint32_t)ca.max_seg, max(1u, (rem + ca.seg_len - 1) / ca.seg_len));
-                ca.desc[slot] = make_uint4(cid, cap_end, rg.y, nseg);
-                ca.done[slot] = 0u;
-            }
-            handed_off = true;
-        } else {
-            walk_range<kCount>(recs, vals, cap_end, rg.y, s_rec, g, a, p, wc);
-        }
-    }
+    if (g.tid < 4) s_rec[4 * kDummy + g.tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+    walk_range<kCount>(recs, vals, rg.x, rg.y, s_rec, s_list + (g.tid >> 6) * kListLen, g, a, p, wc);
     if (kCount) {
         count_flush(wc, g.lane, g.tid >> 6, rg.y - rg.x, pair_counts, s_walk);
         __syncthreads();
         if (trace && g.tid == 0) {
-            // Per tile: id, list length, longest wave walk, CU, start, end.
+            // Per tile: id, list length, most records one wave evaluated, CU,
+            // start, end.
             long long* t = trace + 6 * (long long)blk;
             t[0] = tile;
             t[1] = rg.y - rg.x;
@@ -627,79 +759,6 @@ __global__ __launch_bounds__(256) void k_blend(const SurfelRec* __restrict__ rec
             t[5] = wall_clock64();
         }
     }
-    if (!handed_off && inside) write_pixel(p, px, py, a, rgb, dz, alpha, cls);
-}
-
-// Phases 2-3: block (slot, s) composites segment s of a continued tile for
-// the pixels still compositing, with a fresh transmittance.  The last of a
-// tile's segment blocks to finish combines them front to back: a segment is
-// taken whole where the running transmittance stays above t_min through it,
-// and is walked again in sequence from the running state where it does not,
-// so the pixels equal those of one uninterrupted walk.
-template <bool kCount>
-__global__ __launch_bounds__(256) void k_blend_cont(const SurfelRec* __restrict__ recs,
-                                                    const uint32_t* __restrict__ vals,
-                                                    const uint32_t* __restrict__ tile_list, BlendArgs a, ContArgs ca,
-                                                    float* __restrict__ rgb, float* __restrict__ dz,
-                                                    float* __restrict__ alpha, uint8_t* __restrict__ cls,
-                                                    unsigned long long* __restrict__ pair_counts) {
-    __shared__ float4 s_rec[256 * 4];
-    __shared__ uint32_t s_last;
-    const uint32_t slot = blockIdx.x / (uint32_t)ca.max_seg, seg = blockIdx.x % (uint32_t)ca.max_seg;
-    if (slot >= min(*ca.n_slots, (uint32_t)ca.max_slots)) return;
-    const uint4 d = ca.desc[slot];
-    const uint32_t nseg = d.w;
-    if (seg >= nseg) return;
-    const uint32_t tile = tile_list ? tile_list[d.x] : d.x;
-    bool inside;
-    int px, py;
-    const TileGeom g = tile_geom(tile, a, &inside, &px, &py);
-    WalkCounts wc{0, 0, 0, 0};
-    const float4* st1 = ca.state1 + (size_t)slot * 512;
-    float4* sst = ca.seg_state + ((size_t)slot * ca.max_seg) * 512;
-    const uint32_t total = d.z - d.y;
-    auto seg_b = [&](uint32_t k) { return d.y + (uint32_t)(((uint64_t)total * k) / nseg); };
-    {
-        const bool live0 = st1[2 * g.tid + 1].z != 0.f;
-        PixelState p{1.f, 0.f, 0.f, 0.f, 0.f, 0.f, live0};
-        walk_range<kCount>(recs, vals, seg_b(seg), seg_b(seg + 1), s_rec, g, a, p, wc);
-        store_state(sst + (size_t)seg * 512, g.tid, p, live0 && !p.live);
-    }
-    __threadfence();
-    __syncthreads();
-    if (g.tid == 0) s_last = atomicAdd(&ca.done[slot], 1u) == nseg - 1 ? 1u : 0u;
-    __syncthreads();
-    if (!s_last) {
-        if (kCount) count_flush(wc, g.lane, g.tid >> 6, 0, pair_counts, nullptr);
-        return;
-    }
-    __threadfence();
-    const float4 s0 = st1[2 * g.tid], s1 = st1[2 * g.tid + 1];
-    PixelState p{s1.y, s0.x, s0.y, s0.z, s0.w, s1.x, s1.z != 0.f};
-    for (uint32_t k = 0; k < nseg; ++k) {
-        const float4 q0 = sst[(size_t)k * 512 + 2 * g.tid], q1 = sst[(size_t)k * 512 + 2 * g.tid + 1];
-        bool need = false;
-        if (p.live) {
-            const float Tn = p.T * q1.y;
-            if (q1.z == 0.f && Tn >= a.t_min) {
-                p.c0 = fmaf(p.T, q0.x, p.c0);
-                p.c1 = fmaf(p.T, q0.y, p.c1);
-                p.c2 = fmaf(p.T, q0.z, p.c2);
-                p.D = fmaf(p.T, q0.w, p.D);
-                p.A = fmaf(p.T, q1.x, p.A);
-                p.T = Tn;
-            } else {
-                need = true;
-            }
-        }
-        if (__syncthreads_count(need) > 0) {
-            const bool keep = p.live;
-            p.live = need;
-            walk_range<kCount>(recs, vals, seg_b(k), seg_b(k + 1), s_rec, g, a, p, wc);
-            p.live = need ? p.live : keep;
-        }
-    }
-    if (kCount) count_flush(wc, g.lane, g.tid >> 6, 0, pair_counts, nullptr);
     if (inside) write_pixel(p, px, py, a, rgb, dz, alpha, cls);
 }
 
@@ -739,25 +798,16 @@ hipError_t launch_tile_order(const uint2* ranges, const uint32_t* n_live, int n_
 }
 
 hipError_t launch_blend(const SurfelRec* recs, const uint32_t* vals, const uint2* ranges, const uint32_t* tile_list,
-                        const uint32_t* order, const uint32_t* n_live, int n_blocks, const BlendArgs& a,
-                        const ContArgs& ca, float* rgb, float* d_or_z, float* alpha, uint8_t* cls,
-                        unsigned long long* pair_counts, long long* trace, hipStream_t s) {
+                        const uint32_t* order, const uint32_t* n_live, int n_blocks, const BlendArgs& a, float* rgb,
+                        float* d_or_z, float* alpha, uint8_t* cls, unsigned long long* pair_counts, long long* trace,
+                        hipStream_t s) {
     if (n_blocks <= 0) return hipSuccess;
     if (pair_counts)
         hipLaunchKernelGGL(k_blend<true>, dim3(n_blocks), dim3(256), 0, s, recs, vals, ranges, tile_list, order, n_live,
-                           a, ca, rgb, d_or_z, alpha, cls, pair_counts, trace);
+                           a, rgb, d_or_z, alpha, cls, pair_counts, trace);
     else
         hipLaunchKernelGGL(k_blend<false>, dim3(n_blocks), dim3(256), 0, s, recs, vals, ranges, tile_list, order,
-                           n_live, a, ca, rgb, d_or_z, alpha, cls, pair_counts, (long long*)nullptr);
-    if (ca.max_slots > 0) {
-        const unsigned g = (unsigned)(ca.max_slots * ca.max_seg);
-        if (pair_counts)
-            hipLaunchKernelGGL(k_blend_cont<true>, dim3(g), dim3(256), 0, s, recs, vals, tile_list, a, ca, rgb, d_or_z,
-                               alpha, cls, pair_counts);
-        else
-            hipLaunchKernelGGL(k_blend_cont<false>, dim3(g), dim3(256), 0, s, recs, vals, tile_list, a, ca, rgb,
-                               d_or_z, alpha, cls, pair_counts);
-    }
+                           n_live, a, rgb, d_or_z, alpha, cls, pair_counts, (long long*)nullptr);
     return hipGetLastError();
 }
 

@@ -160,32 +160,6 @@ def test_render_dominant_cube(ctx, oracle, W, H):
     check_image(to_np(out["rgb"]), to_np(out["depth_raw"]), to_np(out["alpha"]), ref, f"cube {W}x{H}")
 
 
-@pytest.mark.parametrize("cap,seg", [(64, 32), (200, 16), (1, 1)])
-def test_render_split_long_lists(ctx, oracle, cap, seg):
-    """Long lists handed to segment workgroups (small caps force it on most
-    tiles, and opaque surfels make pixels saturate inside segments, which
-    exercises the in-order re-walk) give the oracle's pixels, and agree
-    with the unsplit blend to fp32 rounding."""
-    sc, cam = cube_workload(10_000, 144, 112, 170.0, seed=4)
-    sc.opacity[:] = np.maximum(sc.opacity, 0.9)
-    ds = api.DeviceScene(sc)
-    log(f"split cap={cap} seg={seg}")
-    try:
-        ctx.set_blend_split(0)
-        whole = ctx.render_dominant(ds, cam)
-        ctx.set_blend_split(cap, seg)
-        out = ctx.render_dominant(ds, cam)
-    finally:
-        ctx.set_blend_split(768, 384)
-    ref = oracle.render(sc, cam)
-    check_image(to_np(out["rgb"]), to_np(out["depth_raw"]), to_np(out["alpha"]), ref, f"split {cap}/{seg}")
-    amb = ref["amb"] > 0
-    for k in ("rgb", "depth_raw", "alpha"):
-        diff = np.abs(to_np(out[k]) - to_np(whole[k]))
-        scale = 1.0 if k != "depth_raw" else np.abs(to_np(whole[k])).max() + 1e-3
-        assert float((diff / scale)[..., ~amb].max()) <= 2e-5, k
-
-
 def test_render_edge_cases(ctx, oracle):
     # Empty scene -> background; one opaque surfel -> depth proxy = its depth;
     # surfels behind the camera are culled.
