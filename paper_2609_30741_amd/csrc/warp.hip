@@ -72,6 +72,38 @@ __device__ inline uint32_t wave_sum_u32(uint32_t v) {
     return v;
 }
 
+// Block-wide reductions for 256-thread blocks; every thread gets the result.
+// s4 is a 4-entry LDS scratch that the caller does not touch in between.
+__device__ inline uint32_t block_sum_u32(uint32_t v, uint32_t* s4) {
+    v = wave_sum_u32(v);
+    if ((threadIdx.x & 63) == 0) s4[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const uint32_t r = s4[0] + s4[1] + s4[2] + s4[3];
+    __syncthreads();
+    return r;
+}
+__device__ inline uint32_t block_min_u32(uint32_t v, uint32_t* s4) {
+    v = wave_min_u32(v);
+    if ((threadIdx.x & 63) == 0) s4[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const uint32_t r = min(min(s4[0], s4[1]), min(s4[2], s4[3]));
+    __syncthreads();
+    return r;
+}
+__device__ inline uint32_t block_max_u32(uint32_t v, uint32_t* s4) {
+    v = wave_max_u32(v);
+    if ((threadIdx.x & 63) == 0) s4[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const uint32_t r = max(max(s4[0], s4[1]), max(s4[2], s4[3]));
+    __syncthreads();
+    return r;
+}
+
+// Image kernels in 2D: a 256-thread block covers 64 columns x kBandRows
+// rows, a wave per row at a time (coalesced), so no pixel index is divided.
+constexpr int kBandRows = 16;
+inline dim3 band_grid(int W, int H) { return dim3((unsigned)((W + 63) / 64), (unsigned)((H + kBandRows - 1) / kBandRows)); }
+
 __global__ void k_warp_reset(DevStatus* st) {
     st->n_holes = 0;
     st->n_gap = 0;
@@ -93,9 +125,9 @@ __global__ __launch_bounds__(256) void k_fill_u64(unsigned long long* p, int64_t
 // Returns false when it lands nowhere; *df gets the fp32 depth proxy of a
 // covered source pixel (else stays untouched).
 __device__ inline bool splat_target(const WarpCam& src, const WarpCam& dst, const RelPose& P, float a_min,
-                                    const float* __restrict__ draw, const float* __restrict__ alpha, int64_t s,
+                                    const float* __restrict__ draw, const float* __restrict__ alpha, int i, int j,
                                     int64_t* fu_out, int64_t* fv_out, unsigned long long* key, float* df_out) {
-    const int64_t i = s % src.W, j = s / src.W;
+    const int64_t s = (int64_t)j * src.W + i;
     const double xn = ((double)i - src.cx) / src.fx;
     const double yn = ((double)j - src.cy) / src.fy;
     const float A = alpha[s];
@@ -130,23 +162,25 @@ __global__ __launch_bounds__(256) void k_reproject_scatter(WarpCam src, WarpCam 
                                                            const float* __restrict__ draw,
                                                            const float* __restrict__ alpha,
                                                            unsigned long long* __restrict__ zbuf, DevStatus* st) {
-    const int64_t ns = (int64_t)src.W * src.H;
-    const int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    __shared__ uint32_t s4[4];
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
     uint32_t dmin = 0xFFFFFFFFu, dmax = 0u;
-    if (s < ns) {
+    for (int r = threadIdx.x >> 6; r < kBandRows; r += 4) {
+        const int j = blockIdx.y * kBandRows + r;
+        if (i >= src.W || j >= src.H) continue;
         int64_t fu, fv;
         unsigned long long key;
         float df = -1.f;
-        const bool hit = splat_target(src, dst, P, a_min, draw, alpha, s, &fu, &fv, &key, &df);
+        const bool hit = splat_target(src, dst, P, a_min, draw, alpha, i, j, &fu, &fv, &key, &df);
         if (df >= 0.f) {
-            dmin = __float_as_uint(df);
-            dmax = dmin;
+            dmin = min(dmin, __float_as_uint(df));
+            dmax = max(dmax, __float_as_uint(df));
         }
         if (hit) atomicMin(&zbuf[fv * dst.W + fu], key);
     }
-    dmin = wave_min_u32(dmin);
-    dmax = wave_max_u32(dmax);
-    if ((threadIdx.x & 63) == 0) {
+    dmin = block_min_u32(dmin, s4);
+    dmax = block_max_u32(dmax, s4);
+    if (threadIdx.x == 0) {
         if (dmin != 0xFFFFFFFFu) atomicMin(&st->dmin_bits, dmin);
         if (dmax != 0u) atomicMax(&st->dmax_bits, dmax);
     }
@@ -193,11 +227,10 @@ __global__ __launch_bounds__(256) void k_reproject_rows(WarpCam src, WarpCam dst
     __syncthreads();
     uint32_t dmin = 0xFFFFFFFFu, dmax = 0u, off_row = 0;
     for (int i = threadIdx.x; i < src.W; i += 256) {
-        const int64_t s = (int64_t)j * src.W + i;
         int64_t fu, fv;
         unsigned long long key;
         float df = -1.f;
-        const bool hit = splat_target(src, dst, P, a_min, draw, alpha, s, &fu, &fv, &key, &df);
+        const bool hit = splat_target(src, dst, P, a_min, draw, alpha, i, j, &fu, &fv, &key, &df);
         if (df >= 0.f) {
             dmin = min(dmin, __float_as_uint(df));
             dmax = max(dmax, __float_as_uint(df));
@@ -212,11 +245,12 @@ __global__ __launch_bounds__(256) void k_reproject_rows(WarpCam src, WarpCam dst
     uint32_t holes = 0;
     for (int t = threadIdx.x; t < dst.W; t += 256)
         holes += resolve_pixel(zrow[t], (int64_t)j * dst.W + t, nd, ns, rgb, alpha, rgb_dst, z_dst, a_dst, hole);
-    dmin = wave_min_u32(dmin);
-    dmax = wave_max_u32(dmax);
-    holes = wave_sum_u32(holes);
-    off_row = wave_max_u32(off_row);
-    if ((threadIdx.x & 63) == 0) {
+    __shared__ uint32_t s4[4];
+    dmin = block_min_u32(dmin, s4);
+    dmax = block_max_u32(dmax, s4);
+    holes = block_sum_u32(holes, s4);
+    off_row = block_max_u32(off_row, s4);
+    if (threadIdx.x == 0) {
         if (dmin != 0xFFFFFFFFu) atomicMin(&st->dmin_bits, dmin);
         if (dmax != 0u) atomicMax(&st->dmax_bits, dmax);
         if (holes) atomicAdd(&st->n_holes, holes);
@@ -231,11 +265,13 @@ __global__ __launch_bounds__(256) void k_reproject_resolve(int64_t nd, int64_t n
                                                            float* __restrict__ rgb_dst, float* __restrict__ z_dst,
                                                            float* __restrict__ a_dst, uint8_t* __restrict__ hole,
                                                            DevStatus* st) {
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    __shared__ uint32_t s4[4];
     uint32_t h = 0;
-    if (t < nd) h = resolve_pixel(zbuf[t], t, nd, ns, rgb, alpha, rgb_dst, z_dst, a_dst, hole);
-    h = wave_sum_u32(h);
-    if ((threadIdx.x & 63) == 0 && h) atomicAdd(&st->n_holes, h);
+    for (int64_t t = (int64_t)blockIdx.x * 1024 + threadIdx.x, e = min(nd, (int64_t)blockIdx.x * 1024 + 1024); t < e;
+         t += 256)
+        h += resolve_pixel(zbuf[t], t, nd, ns, rgb, alpha, rgb_dst, z_dst, a_dst, hole);
+    h = block_sum_u32(h, s4);
+    if (threadIdx.x == 0 && h) atomicAdd(&st->n_holes, h);
 }
 
 __global__ void k_depth_range(const DevStatus* st, float z_near, float z_far, float* range) {
@@ -380,12 +416,16 @@ __global__ __launch_bounds__(256) void k_tag_init(int64_t n, const uint8_t* __re
 
 __global__ __launch_bounds__(256) void k_gap_pass(int W, int H, int pass, float* rgb, float* z, float* alpha,
                                                   uint8_t* tag, uint8_t* __restrict__ cls, DevStatus* st) {
+    __shared__ uint32_t s4[4];
     const int64_t n = (int64_t)W * H;
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
     uint32_t filled = 0;
-    if (p < n && tag[p] == 255) {
-        const int x = (int)(p % W), y = (int)(p / W);
-        if (!in_edge(st, x, y)) {
+    for (int r = threadIdx.x >> 6; r < kBandRows; r += 4) {
+        const int y = blockIdx.y * kBandRows + r;
+        if (x >= W || y >= H) continue;
+        const int64_t p = (int64_t)y * W + x;
+        if (tag[p] != 255 || in_edge(st, x, y)) continue;
+        {
             const int NX[8] = {-1, 0, 1, -1, 1, -1, 0, 1};
             const int NY[8] = {-1, -1, -1, 0, 0, 1, 1, 1};
             int cnt = 0;
@@ -413,26 +453,30 @@ __global__ __launch_bounds__(256) void k_gap_pass(int W, int H, int pass, float*
                 z[p] = zm;
                 tag[p] = (uint8_t)pass;
                 cls[p] = (uint8_t)BGS_CLS_GAP;
-                filled = 1;
+                ++filled;
             }
         }
     }
-    filled = wave_sum_u32(filled);
-    if ((threadIdx.x & 63) == 0 && filled) atomicAdd(&st->n_gap, filled);
+    filled = block_sum_u32(filled, s4);
+    if (threadIdx.x == 0 && filled) atomicAdd(&st->n_gap, filled);
 }
 
 // Holes left after interpolation and outside the edge ROIs.
 __global__ __launch_bounds__(256) void k_center_mask(int W, int H, const uint8_t* __restrict__ tag,
                                                      uint8_t* __restrict__ center, DevStatus* st) {
-    const int64_t n = (int64_t)W * H;
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    uint32_t c = 0;
-    if (p < n) {
-        c = (tag[p] == 255 && !in_edge(st, (int)(p % W), (int)(p / W))) ? 1u : 0u;
+    __shared__ uint32_t s4[4];
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    uint32_t count = 0;
+    for (int r = threadIdx.x >> 6; r < kBandRows; r += 4) {
+        const int y = blockIdx.y * kBandRows + r;
+        if (x >= W || y >= H) continue;
+        const int64_t p = (int64_t)y * W + x;
+        const uint32_t c = (tag[p] == 255 && !in_edge(st, x, y)) ? 1u : 0u;
         center[p] = (uint8_t)c;
+        count += c;
     }
-    c = wave_sum_u32(c);
-    if ((threadIdx.x & 63) == 0 && c) atomicAdd(&st->n_center, c);
+    count = block_sum_u32(count, s4);
+    if (threadIdx.x == 0 && count) atomicAdd(&st->n_center, count);
 }
 
 // ---------------------------------------------------------------------------
@@ -504,8 +548,9 @@ __global__ __launch_bounds__(256) void k_row_fill(int W, int H, const uint8_t* _
         }
         if (tag[p] != 255) left = x;
     }
-    filled = wave_sum_u32(filled);
-    if ((threadIdx.x & 63) == 0 && filled) atomicAdd(&st->n_rowfill, filled);
+    __shared__ uint32_t s4[4];
+    filled = block_sum_u32(filled, s4);
+    if (threadIdx.x == 0 && filled) atomicAdd(&st->n_rowfill, filled);
 }
 
 // ---------------------------------------------------------------------------
@@ -784,10 +829,10 @@ hipError_t launch_reproject(const WarpCam& src, const WarpCam& dst, const RelPos
                            a_min, draw, alpha, rgb, rgb_dst, z_dst, alpha_dst, hole, st);
     } else {
         hipLaunchKernelGGL(k_fill_u64, dim3(grid(nd)), dim3(256), 0, s, zbuf, nd, ~0ull);
-        hipLaunchKernelGGL(k_reproject_scatter, dim3(grid(ns)), dim3(256), 0, s, src, dst, P, a_min, draw, alpha, zbuf,
-                           st);
-        hipLaunchKernelGGL(k_reproject_resolve, dim3(grid(nd)), dim3(256), 0, s, nd, ns, zbuf, rgb, alpha, rgb_dst,
-                           z_dst, alpha_dst, hole, st);
+        hipLaunchKernelGGL(k_reproject_scatter, band_grid(src.W, src.H), dim3(256), 0, s, src, dst, P, a_min, draw,
+                           alpha, zbuf, st);
+        hipLaunchKernelGGL(k_reproject_resolve, dim3((unsigned)((nd + 1023) / 1024)), dim3(256), 0, s, nd, ns, zbuf, rgb,
+                           alpha, rgb_dst, z_dst, alpha_dst, hole, st);
     }
     hipLaunchKernelGGL(k_depth_range, dim3(1), dim3(1), 0, s, st, (float)src.z_near, (float)src.z_far, depth_range);
     return hipGetLastError();
@@ -820,9 +865,9 @@ hipError_t launch_classify(const WarpCam& src, const WarpCam& dst, const RelPose
     uint8_t* tag = b.hole;
     hipLaunchKernelGGL(k_tag_init, dim3(grid(n)), dim3(256), 0, s, n, cls, tag);
     for (int pass = 1; pass <= roi.gap_passes; ++pass)
-        hipLaunchKernelGGL(k_gap_pass, dim3(grid(n)), dim3(256), 0, s, W, H, pass, rgb, z, alpha, tag, cls, st);
+        hipLaunchKernelGGL(k_gap_pass, band_grid(W, H), dim3(256), 0, s, W, H, pass, rgb, z, alpha, tag, cls, st);
     uint8_t* center = b.hole2;
-    hipLaunchKernelGGL(k_center_mask, dim3(grid(n)), dim3(256), 0, s, W, H, tag, center, st);
+    hipLaunchKernelGGL(k_center_mask, band_grid(W, H), dim3(256), 0, s, W, H, tag, center, st);
     hipLaunchKernelGGL(k_tile_mask_edges, dim3(grid((int64_t)tiles_x * tiles_y)), dim3(256), 0, s, tiles_x, tiles_y, T,
                        st, tile_mask);
     if (roi.center_roi) {
