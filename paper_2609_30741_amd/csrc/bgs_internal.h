@@ -12,8 +12,6 @@
 namespace bgs {
 
 constexpr int kTile = 16;            // rasteriser tile edge (pixels)
-constexpr int kRadixItems = 16;      // keys per thread in a radix block
-constexpr int kRadixBlock = 256 * kRadixItems;  // 4096 keys per block
 constexpr int kScanItems = 8;        // elements per thread in a scan block
 constexpr int kScanBlock = 256 * kScanItems;    // 2048 elements per block
 
@@ -102,8 +100,8 @@ size_t scan_tmp_elems(int64_t n);
 hipError_t exclusive_scan(const uint32_t* in, const uint32_t* idx, uint32_t* out, const uint32_t* n_dev,
                           int64_t n_cap, uint32_t* tmp, hipStream_t s);
 size_t radix_tmp_bytes(int64_t n_cap);
-// Stable LSD radix sort of (keys, values) by bits [0, key_bits) with 8-bit
-// digits.  (ka, va) is the input, (kb, vb) the ping-pong buffer (all four
+// Stable LSD radix sort of (keys, values) by bits [0, key_bits) with digits
+// of up to 8 bits.  (ka, va) is the input, (kb, vb) the ping-pong buffer (all four
 // are real buffers); iota = true ignores the input values and uses the
 // input positions instead.  The element count is *n_dev (<= n_cap), or
 // n_cap when n_dev is null.

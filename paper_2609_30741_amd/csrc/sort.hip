@@ -1,11 +1,7 @@
 // Device-wide exclusive scan and stable LSD radix sort for gfx950.
 //
-// Radix sort: reduce-then-scan per 8-bit digit.  Each pass is three steps:
-// per-block digit histograms (LDS), an exclusive scan of the digit-major
-// histogram matrix, and a scatter in which every block ranks its 4096 keys
-// stably with wave64 ballots (match-any on the digit), reorders them in LDS
-// and writes digit runs out contiguously.  No inter-block waiting: blocks
-// never spin on each other.
+// Radix sort: stable LSD with up to 8-bit digits over a fixed grid of
+// blocks (described below).
 #include "bgs_internal.h"
 
 namespace bgs {
@@ -127,152 +123,225 @@ hipError_t exclusive_scan(const uint32_t* in, const uint32_t* idx, uint32_t* out
 }
 
 // ---------------------------------------------------------------------------
-// Radix sort
+// Radix sort.  Stable LSD with digits of up to 8 bits (a 32-bit key takes four
+// passes, an 11-bit tile id two of 6 and 5 bits).  The grid is fixed by the
+// capacity (at most kRsGrid blocks); block b owns the contiguous chunk
+// [b C, b C + C) of the *n_dev keys, C = n / grid rounded up to 256.  A pass
+// is three launches:
+//   1. k_rs_hist: per-block digit counts (LDS, match-any aggregated), stored
+//      digit-major: counts[d * grid + b].
+//   2. k_rs_scan: one block per digit scans its row over the blocks and
+//      writes the digit total.
+//   3. k_rs_scatter: every block scans the digit totals, then walks its chunk
+//      in sub-chunks of 4096 keys: each wave ranks its 1024 keys in 16 steps
+//      of 64 with match-any ballots and a per-wave LDS count per digit, the
+//      sub-chunk is reordered by digit in LDS, and each digit's run (16 keys
+//      on average at 8 bits) is written out contiguously.
+// Blocks never wait on each other.
 // ---------------------------------------------------------------------------
 namespace {
 
-// Lanes of the wave whose 8-bit digit equals this lane's (among `valid`).
-__device__ inline uint64_t match_digit(uint32_t d, uint64_t valid) {
+constexpr int kRsMaxBits = 8;
+constexpr int kRsBins = 1 << kRsMaxBits;
+constexpr int kRsGrid = 1024;
+constexpr int kRsItems = 16;                 // keys per thread per sub-chunk
+constexpr int kRsSub = 256 * kRsItems;       // 4096
+
+__device__ inline uint64_t match_digit(uint32_t d, uint64_t valid, int bits) {
     uint64_t peers = valid;
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-        uint64_t bal = __ballot((d >> b) & 1u);
-        peers &= ((d >> b) & 1u) ? bal : ~bal;
+    for (int b = 0; b < kRsMaxBits; ++b) {
+        if (b < bits) {
+            const uint64_t bal = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? bal : ~bal;
+        }
     }
     return peers;
 }
 
-__global__ __launch_bounds__(256) void k_radix_hist(const uint32_t* __restrict__ keys,
-                                                    const uint32_t* __restrict__ n_dev, uint32_t n_host, int shift,
-                                                    uint32_t mask, uint32_t* __restrict__ hist, uint32_t nb) {
-    __shared__ uint32_t h[256];
-    const uint32_t n = n_dev ? *n_dev : n_host;
+__device__ inline void chunk_of(uint32_t n, uint32_t grid, uint32_t b, uint32_t* lo, uint32_t* hi) {
+    const uint32_t per = (uint32_t)(((uint64_t)n + grid - 1) / grid);
+    const uint64_t c = ((uint64_t)per + 255u) & ~255ull;
+    const uint64_t l = min<uint64_t>((uint64_t)b * c, n);
+    *lo = (uint32_t)l;
+    *hi = (uint32_t)min<uint64_t>(l + c, n);
+}
+
+__global__ __launch_bounds__(256) void k_rs_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_dev,
+                                                 uint32_t n_host, int shift, int bits,
+                                                 uint32_t* __restrict__ counts) {
+    __shared__ uint32_t h[kRsBins];
+    const uint32_t n = n_dev ? *n_dev : n_host, bins = 1u << bits, mask = bins - 1u;
     h[threadIdx.x] = 0;
     __syncthreads();
-    const uint64_t base = (uint64_t)blockIdx.x * kRadixBlock;
-    if (base < n) {
-        const uint32_t lane = lane_id();
-        const uint64_t lt = (1ull << lane) - 1ull;
-#pragma unroll 4
-        for (int j = 0; j < kRadixItems; ++j) {
-            uint64_t i = base + (uint64_t)j * 256 + threadIdx.x;
-            bool ok = i < n;
-            uint32_t d = ok ? (keys[i] >> shift) & mask : 0u;
-            uint64_t peers = match_digit(d, __ballot(ok));
+    uint32_t lo, hi;
+    chunk_of(n, gridDim.x, blockIdx.x, &lo, &hi);
+    const uint64_t lt = (1ull << lane_id()) - 1ull;
+    for (uint64_t sub = lo; sub < hi; sub += kRsSub) {
+        uint32_t k[kRsItems];
+#pragma unroll
+        for (int it = 0; it < kRsItems; ++it) {
+            const uint64_t i = sub + it * 256 + threadIdx.x;
+            k[it] = i < hi ? keys[i] : 0u;
+        }
+#pragma unroll
+        for (int it = 0; it < kRsItems; ++it) {
+            const bool ok = sub + it * 256 + threadIdx.x < hi;
+            const uint32_t d = (k[it] >> shift) & mask;
+            const uint64_t peers = match_digit(d, __ballot(ok), bits);
             if (ok && (peers & lt) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
         }
     }
     __syncthreads();
-    hist[(uint64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+    if (threadIdx.x < bins) counts[(uint64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
 }
 
-__global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t* __restrict__ kin,
-                                                       const uint32_t* __restrict__ vin,
-                                                       uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                       const uint32_t* __restrict__ n_dev, uint32_t n_host,
-                                                       int shift, uint32_t mask,
-                                                       const uint32_t* __restrict__ offs, uint32_t nb) {
-    __shared__ uint32_t s_keys[kRadixBlock];
-    __shared__ uint32_t s_vals[kRadixBlock];
-    __shared__ uint32_t cnt[4][256];
-    __shared__ uint32_t dstart[256];
-    __shared__ uint32_t gbase[256];
+// One block per digit: exclusive scan of counts[d * grid .. + grid) in place;
+// totals[d] = the row's sum.
+__global__ __launch_bounds__(256) void k_rs_scan(uint32_t* __restrict__ counts, uint32_t grid,
+                                                 uint32_t* __restrict__ totals) {
     __shared__ uint32_t lds[4];
-    const uint32_t n = n_dev ? *n_dev : n_host;
-    const uint64_t base = (uint64_t)blockIdx.x * kRadixBlock;
-    if (base >= n) return;
+    uint32_t* row = counts + (uint64_t)blockIdx.x * grid;
+    const uint32_t per = (grid + 255) / 256, b0 = threadIdx.x * per;
+    uint32_t v[kRsGrid / 256];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int j = 0; j < kRsGrid / 256; ++j) {
+        v[j] = ((uint32_t)j < per && b0 + j < grid) ? row[b0 + j] : 0u;
+        sum += v[j];
+    }
+    uint32_t tot;
+    uint32_t run = block_excl_scan(sum, lds, &tot);
+#pragma unroll
+    for (int j = 0; j < kRsGrid / 256; ++j) {
+        if ((uint32_t)j < per && b0 + j < grid) row[b0 + j] = run;
+        run += v[j];
+    }
+    if (threadIdx.x == 0) totals[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_rs_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                    const uint32_t* __restrict__ n_dev, uint32_t n_host, int shift,
+                                                    int bits, const uint32_t* __restrict__ counts,
+                                                    const uint32_t* __restrict__ totals) {
+    __shared__ uint32_t s_keys[kRsSub];
+    __shared__ uint32_t s_vals[kRsSub];
+    __shared__ uint32_t cnt[4][kRsBins];
+    __shared__ uint32_t dstart[kRsBins];
+    __shared__ uint32_t gbase[kRsBins];
+    __shared__ uint32_t run[kRsBins];
+    __shared__ uint32_t lds[4];
+    const uint32_t n = n_dev ? *n_dev : n_host, bins = 1u << bits, mask = bins - 1u;
+    uint32_t lo, hi;
+    chunk_of(n, gridDim.x, blockIdx.x, &lo, &hi);
+    if (lo >= hi) return;
     const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
     const uint64_t lt = (1ull << lane) - 1ull;
-#pragma unroll
-    for (int w = 0; w < 4; ++w) cnt[w][threadIdx.x] = 0;
-    __syncthreads();
-
-    // Stable rank of every key within its wave's 1024-key segment: the
-    // segment is walked in 16 steps of 64 consecutive keys; lanes with the
-    // same digit are found with ballots and the wave's running per-digit
-    // count lives in LDS.
-    uint32_t k[kRadixItems], v[kRadixItems], r[kRadixItems];
-#pragma unroll
-    for (int it = 0; it < kRadixItems; ++it) {
-        uint64_t i = base + (uint64_t)wave * (64 * kRadixItems) + (uint64_t)it * 64 + lane;
-        bool ok = i < n;
-        k[it] = ok ? kin[i] : 0xFFFFFFFFu;
-        v[it] = ok ? (vin ? vin[i] : (uint32_t)i) : 0u;
-        uint32_t d = (k[it] >> shift) & mask;
-        uint64_t valid = __ballot(ok);
-        uint64_t peers = match_digit(d, valid);
-        uint32_t c = ok ? cnt[wave][d] : 0u;
-        r[it] = c + (uint32_t)__popcll(peers & lt);
-        __builtin_amdgcn_wave_barrier();
-        if (ok && (peers & lt) == 0) cnt[wave][d] = c + (uint32_t)__popcll(peers);
-        __builtin_amdgcn_wave_barrier();
-        if (!ok) r[it] = 0xFFFFFFFFu;
-    }
-    __syncthreads();
+    const uint32_t dt = threadIdx.x;  // the digit this thread looks after
     {
-        const uint32_t d = threadIdx.x;
-        uint32_t c0 = cnt[0][d], c1 = cnt[1][d], c2 = cnt[2][d], c3 = cnt[3][d];
-        uint32_t tot = c0 + c1 + c2 + c3;
-        uint32_t st = block_excl_scan(tot, lds, nullptr);
-        cnt[0][d] = st;
-        cnt[1][d] = st + c0;
-        cnt[2][d] = st + c0 + c1;
-        cnt[3][d] = st + c0 + c1 + c2;
-        dstart[d] = st;
-        gbase[d] = offs[(uint64_t)d * nb + blockIdx.x];
-    }
-    __syncthreads();
+        // run[d] = (keys of smaller digits) + (keys of digit d in earlier blocks).
+        const uint32_t t = dt < bins ? totals[dt] : 0u;
+        const uint32_t acc = block_excl_scan(t, lds, nullptr);
+        if (dt < bins) run[dt] = acc + counts[(uint64_t)dt * gridDim.x + blockIdx.x];
 #pragma unroll
-    for (int it = 0; it < kRadixItems; ++it) {
-        if (r[it] != 0xFFFFFFFFu) {
-            uint32_t d = (k[it] >> shift) & mask;
-            uint32_t pos = cnt[wave][d] + r[it];
-            s_keys[pos] = k[it];
-            s_vals[pos] = v[it];
-        }
+        for (int w = 0; w < 4; ++w) cnt[w][dt] = 0;
     }
     __syncthreads();
-    const uint32_t m = (uint32_t)min<uint64_t>((uint64_t)kRadixBlock, (uint64_t)n - base);
-    for (uint32_t p = threadIdx.x; p < m; p += 256) {
-        uint32_t kk = s_keys[p];
-        uint32_t d = (kk >> shift) & mask;
-        uint32_t o = gbase[d] + (p - dstart[d]);
-        if (o < n) {
-            kout[o] = kk;
-            vout[o] = s_vals[p];
+    for (uint64_t sub = lo; sub < hi; sub += kRsSub) {
+        uint32_t k[kRsItems], v[kRsItems], r[kRsItems];
+#pragma unroll
+        for (int it = 0; it < kRsItems; ++it) {
+            const uint64_t i = sub + wave * (64 * kRsItems) + it * 64 + lane;
+            const bool ok = i < hi;
+            k[it] = ok ? kin[i] : 0u;
+            v[it] = ok ? (vin ? vin[i] : (uint32_t)i) : 0u;
         }
+#pragma unroll
+        for (int it = 0; it < kRsItems; ++it) {
+            const uint64_t i = sub + wave * (64 * kRsItems) + it * 64 + lane;
+            const bool ok = i < hi;
+            const uint32_t d = (k[it] >> shift) & mask;
+            const uint64_t peers = match_digit(d, __ballot(ok), bits);
+            const uint32_t c = ok ? cnt[wave][d] : 0u;
+            r[it] = ok ? c + (uint32_t)__popcll(peers & lt) : 0xFFFFFFFFu;
+            __builtin_amdgcn_wave_barrier();
+            if (ok && (peers & lt) == 0) cnt[wave][d] = c + (uint32_t)__popcll(peers);
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+        {
+            const uint32_t c0 = cnt[0][dt], c1 = cnt[1][dt], c2 = cnt[2][dt], c3 = cnt[3][dt];
+            const uint32_t tot = c0 + c1 + c2 + c3;
+            const uint32_t st = block_excl_scan(tot, lds, nullptr);
+            cnt[0][dt] = st;
+            cnt[1][dt] = st + c0;
+            cnt[2][dt] = st + c0 + c1;
+            cnt[3][dt] = st + c0 + c1 + c2;
+            dstart[dt] = st;
+            if (dt < bins) {
+                gbase[dt] = run[dt];
+                run[dt] += tot;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < kRsItems; ++it) {
+            if (r[it] != 0xFFFFFFFFu) {
+                const uint32_t lp = cnt[wave][(k[it] >> shift) & mask] + r[it];
+                s_keys[lp] = k[it];
+                s_vals[lp] = v[it];
+            }
+        }
+        __syncthreads();
+        const uint32_t m = (uint32_t)min<uint64_t>((uint64_t)kRsSub, hi - sub);
+        for (uint32_t p = threadIdx.x; p < m; p += 256) {
+            const uint32_t kk = s_keys[p];
+            const uint32_t d = (kk >> shift) & mask;
+            const uint32_t o = gbase[d] + (p - dstart[d]);
+            if (o < n) {  // always true for consistent counts; keeps every write in bounds
+                kout[o] = kk;
+                vout[o] = s_vals[p];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < 4; ++w) cnt[w][dt] = 0;
+        __syncthreads();
     }
+}
+
+uint32_t rs_grid(int64_t n_cap) {
+    const int64_t g = ceil_div(n_cap > 0 ? n_cap : 1, kRsSub);
+    return (uint32_t)(g < kRsGrid ? g : kRsGrid);
 }
 
 }  // namespace
 
 size_t radix_tmp_bytes(int64_t n_cap) {
-    int64_t nb = ceil_div(n_cap > 0 ? n_cap : 1, kRadixBlock);
-    size_t hist = (size_t)256 * nb;
-    size_t tmp = scan_tmp_elems((int64_t)hist);
-    return (hist + 64 + tmp) * sizeof(uint32_t) + 256;
+    return ((size_t)kRsBins * rs_grid(n_cap) + kRsBins + 64) * sizeof(uint32_t) + 256;
 }
 
 hipError_t radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, const uint32_t* n_dev,
                       int64_t n_cap, int key_bits, bool iota, void* tmp, hipStream_t s, bool* in_b) {
     *in_b = false;
     if (n_cap <= 0 || key_bits <= 0) return hipSuccess;
-    const int64_t nb = ceil_div(n_cap, kRadixBlock);
-    uint32_t* hist = (uint32_t*)tmp;
-    uint32_t* stmp = hist + 256 * nb + 64;
+    if (n_cap > 0xFFFFFFFFll) return hipErrorInvalidValue;
+    const uint32_t grid = rs_grid(n_cap);
+    uint32_t* counts = (uint32_t*)tmp;
+    uint32_t* totals = counts + (size_t)kRsBins * grid;
+    const int passes = (key_bits + kRsMaxBits - 1) / kRsMaxBits;
+    const int per = (key_bits + passes - 1) / passes;
     uint32_t *ki = ka, *ko = kb, *vo = vb;
     const uint32_t* vi = iota ? nullptr : va;
     bool cur_b = false;
-    for (int shift = 0; shift < key_bits; shift += 8) {
-        int bits = key_bits - shift < 8 ? key_bits - shift : 8;
-        uint32_t mask = (1u << bits) - 1u;
-        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(256), 0, s, ki, n_dev, (uint32_t)n_cap, shift,
-                           mask, hist, (uint32_t)nb);
-        hipError_t e = exclusive_scan(hist, nullptr, hist, nullptr, 256 * nb, stmp, s);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(256), 0, s, ki, vi, ko, vo, n_dev,
-                           (uint32_t)n_cap, shift, mask, hist, (uint32_t)nb);
-        e = hipGetLastError();
+    for (int shift = 0; shift < key_bits; shift += per) {
+        const int bits = key_bits - shift < per ? key_bits - shift : per;
+        hipLaunchKernelGGL(k_rs_hist, dim3(grid), dim3(256), 0, s, ki, n_dev, (uint32_t)n_cap, shift, bits, counts);
+        hipLaunchKernelGGL(k_rs_scan, dim3(1u << bits), dim3(256), 0, s, counts, grid, totals);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(grid), dim3(256), 0, s, ki, vi, ko, vo, n_dev, (uint32_t)n_cap, shift,
+                           bits, counts, totals);
+        const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         cur_b = !cur_b;
         if (cur_b) {
