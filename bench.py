@@ -193,6 +193,19 @@ def main():
                 "longest_wave_walk": int(wd[2]), "longest_tile_list": int(wd[3]),
                 "largest_stage": dominant}
 
+    # ---- HBM efficiency of the sort and reprojection stages (algorithmic
+    # bytes: one read and one write of every key and value for a sort, the
+    # 20 B read + 17 B written per pixel of a forward warp) ----
+    def hbm(stage, nbytes):
+        ms = stage_ms[stage]
+        gbs = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        return {"stage": stage, "bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(gbs / PEAK_HBM_GBS, 4), "bytes_per_launch": int(nbytes), "avg_ms": round(ms, 4)}
+
+    npx = cams[0].width * cams[0].height
+    hbm_stages = [hbm("tile_sort_dom", 16.0 * np.mean(keys_dom)), hbm("depth_sort_dom", 16.0 * scene.n),
+                  hbm("tile_sort_roi", 16.0 * np.mean(keys_roi)), hbm("reproject", 37.0 * npx)]
+
     # ---- CPU oracle on a bounded sample (a baseline only) ----
     cpu = None
     if not args.no_cpu_baseline:
@@ -227,6 +240,7 @@ def main():
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "stage_ms_two_pass": {k: round(v[0] / v[1], 4) for k, v in stages2.items() if v[1]},
         "roofline": roofline,
+        "hbm_stages": hbm_stages,
         "cpu_baseline": cpu,
     }
     print(json.dumps(result), flush=True)

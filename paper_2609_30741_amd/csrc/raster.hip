@@ -679,6 +679,7 @@ __device__ __forceinline__ TileGeom tile_geom(uint32_t tile, const BlendArgs& a,
     return g;
 }
 
+template <bool kPatch>
 __device__ __forceinline__ void write_pixel(const PixelState& p, int px, int py, const BlendArgs& a,
                                             float* __restrict__ rgb, float* __restrict__ dz, float* __restrict__ alpha,
                                             uint8_t* __restrict__ cls) {
@@ -688,7 +689,7 @@ __device__ __forceinline__ void write_pixel(const PixelState& p, int px, int py,
     rgb[hw + q] = fmaf(p.T, a.bg1, p.c1);
     rgb[2 * hw + q] = fmaf(p.T, a.bg2, p.c2);
     alpha[q] = p.A;
-    if (!a.patch) {
+    if (!kPatch) {
         dz[q] = p.D;
     } else {
         dz[q] = p.A >= a.a_min ? p.D / p.A : INFINITY;
@@ -718,8 +719,9 @@ __device__ __forceinline__ void count_flush(const WalkCounts& wc, int lane, int 
 }
 
 // One block per tile (compact id blk, taken in the order given, heaviest
-// lists first): composite the whole list, then write the pixels.
-template <bool kCount>
+// lists first): composite the whole list, then write the pixels.  kPatch:
+// ROI patch of the affiliated eye (writes the depth proxy and the class).
+template <bool kCount, bool kPatch>
 __global__ __launch_bounds__(256) void k_blend(const SurfelRec* __restrict__ recs, const uint32_t* __restrict__ vals,
                                                const uint2* __restrict__ ranges, const uint32_t* __restrict__ tile_list,
                                                const uint32_t* __restrict__ order,
@@ -759,7 +761,7 @@ __global__ __launch_bounds__(256) void k_blend(const SurfelRec* __restrict__ rec
             t[5] = wall_clock64();
         }
     }
-    if (inside) write_pixel(p, px, py, a, rgb, dz, alpha, cls);
+    if (inside) write_pixel<kPatch>(p, px, py, a, rgb, dz, alpha, cls);
 }
 
 }  // namespace
@@ -802,12 +804,22 @@ hipError_t launch_blend(const SurfelRec* recs, const uint32_t* vals, const uint2
                         float* d_or_z, float* alpha, uint8_t* cls, unsigned long long* pair_counts, long long* trace,
                         hipStream_t s) {
     if (n_blocks <= 0) return hipSuccess;
-    if (pair_counts)
-        hipLaunchKernelGGL(k_blend<true>, dim3(n_blocks), dim3(256), 0, s, recs, vals, ranges, tile_list, order, n_live,
-                           a, rgb, d_or_z, alpha, cls, pair_counts, trace);
-    else
-        hipLaunchKernelGGL(k_blend<false>, dim3(n_blocks), dim3(256), 0, s, recs, vals, ranges, tile_list, order,
-                           n_live, a, rgb, d_or_z, alpha, cls, pair_counts, (long long*)nullptr);
+    const dim3 g(n_blocks), b(256);
+    if (a.patch) {
+        if (pair_counts)
+            hipLaunchKernelGGL((k_blend<true, true>), g, b, 0, s, recs, vals, ranges, tile_list, order, n_live, a, rgb,
+                               d_or_z, alpha, cls, pair_counts, trace);
+        else
+            hipLaunchKernelGGL((k_blend<false, true>), g, b, 0, s, recs, vals, ranges, tile_list, order, n_live, a,
+                               rgb, d_or_z, alpha, cls, pair_counts, (long long*)nullptr);
+    } else {
+        if (pair_counts)
+            hipLaunchKernelGGL((k_blend<true, false>), g, b, 0, s, recs, vals, ranges, tile_list, order, n_live, a,
+                               rgb, d_or_z, alpha, cls, pair_counts, trace);
+        else
+            hipLaunchKernelGGL((k_blend<false, false>), g, b, 0, s, recs, vals, ranges, tile_list, order, n_live, a,
+                               rgb, d_or_z, alpha, cls, pair_counts, (long long*)nullptr);
+    }
     return hipGetLastError();
 }
 
