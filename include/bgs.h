@@ -160,6 +160,22 @@ BGS_API const char* bgs_last_error(const bgs_ctx* ctx);
  * (pixel, surfel) pairs into bgs_stats (slower; for measurement only). */
 BGS_API int32_t bgs_ctx_set_count_pairs(bgs_ctx* ctx, int32_t count);
 
+/* Scheduling of long tile lists in the blend; the pixels agree with a
+ * single front-to-back walk to fp32 rounding.  A tile composites at most
+ * `cap` records of its list in its own workgroup (cap_dom for the dominant
+ * eye and full renders, cap_roi for the ROI patch; 0 = the whole list).
+ * Where pixels are still compositing after that, at least 2 seg_len records
+ * remain, and some pixel, extrapolating the decay of its transmittance
+ * over the second half of the capped walk, is expected to composite at
+ * least `far` more records (far_dom, far_roi), the rest of the list is
+ * split into up to 16 segments of about seg_len records that other
+ * workgroups composite speculatively; the segments are chained front to
+ * back, and a pixel that stops inside a segment is composited again over
+ * that segment, in order, from its exact state.  Defaults 1024, 128, 192,
+ * 0, 768.  BGS_ERR_INVALID_ARG for a negative cap or far, or seg_len < 1. */
+BGS_API int32_t bgs_ctx_set_blend_split(bgs_ctx* ctx, int32_t cap_dom, int32_t cap_roi, int32_t seg_len,
+                                        int32_t far_dom, int32_t far_roi);
+
 /* Per-stage GPU timing with HIP events recorded on the context's stream
  * around each stage's launches.  on = 1 enables it and clears the totals.
  * After the caller has waited for the stream, bgs_timing_collect() adds the

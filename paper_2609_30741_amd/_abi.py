@@ -58,7 +58,7 @@ EXPORTS = [
     "bgs_workspace_size", "bgs_poll_status", "bgs_render_dominant", "bgs_reproject", "bgs_classify_holes",
     "bgs_patch_rois", "bgs_render_stereo", "bgs_sort_workspace_size", "bgs_sort_pairs",
     "bgs_label_components", "bgs_preprocess_debug", "bgs_tile_lists_debug", "bgs_ctx_set_count_pairs",
-    "bgs_ctx_set_timing", "bgs_timing_collect", "bgs_blend_trace",
+    "bgs_ctx_set_timing", "bgs_timing_collect", "bgs_blend_trace", "bgs_ctx_set_blend_split",
 ]
 
 _lib = None
@@ -80,6 +80,7 @@ def load():
         "bgs_ctx_set_sync": [P, I32],
         "bgs_ctx_set_count_pairs": [P, I32],
         "bgs_ctx_set_timing": [P, I32],
+        "bgs_ctx_set_blend_split": [P, I32, I32, I32, I32, I32],
         "bgs_timing_collect": [P, P, P],
         "bgs_workspace_size": [I64, I32, I32, I64, C.POINTER(SZ)],
         "bgs_poll_status": [P, P, SZ, C.POINTER(Stats)],

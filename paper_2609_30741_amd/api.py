@@ -133,6 +133,15 @@ class Context:
     def set_count_pairs(self, on: bool):
         self._check(self.L.bgs_ctx_set_count_pairs(self.h, int(bool(on))))
 
+    def set_blend_split(self, cap_dom: int = 1024, cap_roi: int = 128, seg_len: int = 192, far_dom: int = 0,
+                        far_roi: int = 768):
+        """Records a tile composites before the rest of its list may be split
+        into segments (dominant / full renders, ROI patch; 0 = never), the
+        segment length, and the extrapolated walk a pixel must still have for
+        its tile to be split (dominant, ROI)."""
+        self._check(self.L.bgs_ctx_set_blend_split(self.h, int(cap_dom), int(cap_roi), int(seg_len), int(far_dom),
+                                                   int(far_roi)))
+
     def set_timing(self, on: bool):
         """Enable per-stage HIP-event timing on this context's stream (clears totals)."""
         self._check(self.L.bgs_ctx_set_timing(self.h, int(bool(on))))

@@ -15,6 +15,9 @@ struct bgs_ctx {
     int sync = 1;
     int count_pairs = 0;
     int timing = 0;
+    // Blend continuation: records a tile composites before the rest of its
+    // list is split into segments (0: never), per pass, and the segment length.
+    uint32_t cap_dom = 1024, cap_roi = 128, seg_len = 192, far_dom = 0, far_roi = 768;
     hipEvent_t ev[BGS_NUM_STAGES][2] = {};
     bool pending[BGS_NUM_STAGES] = {};
     double total_ms[BGS_NUM_STAGES] = {};
@@ -26,6 +29,8 @@ namespace bgs {
 namespace {
 
 constexpr size_t kAlign = 256;
+// Tiles per pass whose list tail may be continued by segment workgroups.
+constexpr int64_t kContSlots = 512;
 
 inline size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -41,6 +46,8 @@ struct Layout {
     size_t tkeys_a, tkeys_b, tvals_a, tvals_b;
     size_t radix;
     size_t trace;  // per-tile blend trace of the last counting-mode dominant pass
+    size_t cdesc, citem, cst1, cpart;  // blend continuation
+    uint32_t cslots;
     size_t total;
 };
 
@@ -84,6 +91,11 @@ Layout make_layout(int64_t n, int64_t W, int64_t H, int64_t kc) {
     L.tvals_b = take(4 * kc);
     L.radix = take(radix_tmp_bytes(kc > n ? kc : n));
     L.trace = take(6 * 8 * nt);
+    L.cslots = (uint32_t)(nt < kContSlots ? nt : kContSlots);
+    L.cdesc = take(16 * (size_t)L.cslots);
+    L.citem = take(4 * (size_t)L.cslots * kContMaxSeg);
+    L.cst1 = take(8192 * (size_t)L.cslots);
+    L.cpart = take(8192 * (size_t)L.cslots * kContMaxSeg);
     L.total = o;
     return L;
 }
@@ -340,9 +352,14 @@ int raster_pass(bgs_ctx* ctx, const Layout& L, void* ws, int64_t kc, const bgs_s
     ba.a_min = a_min;
     ba.z_near = (float)cam.z_near;
     ba.patch = tile_mask ? 1 : 0;
+    const ContArgs ca{which ? ctx->cap_roi : ctx->cap_dom, ctx->seg_len, L.cslots,
+                      which ? ctx->far_roi : ctx->far_dom, &st->n_slots,
+                      &st->n_items,
+                      at<uint4>(ws, L.cdesc), at<uint32_t>(ws, L.citem), at<float4>(ws, L.cst1),
+                      at<float4>(ws, L.cpart)};
     mark(ctx, sb + 5, 0);
     HIP_CHECK(launch_blend(recs, svals, ranges, tile_mask ? at<uint32_t>(ws, L.tlist) : nullptr, torder,
-                           tile_mask ? &st->n_masked : nullptr, n_tiles, ba, out.rgb, out.dz, out.alpha, out.cls,
+                           tile_mask ? &st->n_masked : nullptr, n_tiles, ba, ca, out.rgb, out.dz, out.alpha, out.cls,
                            ctx->count_pairs ? &st->pairs[6 * which] : nullptr,
                            (ctx->count_pairs && which == 0) ? at<long long>(ws, L.trace) : nullptr, s),
               "blend");
@@ -399,6 +416,19 @@ const char* bgs_last_error(const bgs_ctx* ctx) { return ctx ? ctx->err.c_str() :
 int32_t bgs_ctx_set_count_pairs(bgs_ctx* ctx, int32_t count) {
     if (!ctx) return BGS_ERR_INVALID_ARG;
     ctx->count_pairs = count ? 1 : 0;
+    return BGS_OK;
+}
+
+int32_t bgs_ctx_set_blend_split(bgs_ctx* ctx, int32_t cap_dom, int32_t cap_roi, int32_t seg_len, int32_t far_dom,
+                                int32_t far_roi) {
+    if (!ctx) return BGS_ERR_INVALID_ARG;
+    if (cap_dom < 0 || cap_roi < 0 || seg_len < 1 || far_dom < 0 || far_roi < 0)
+        return fail(ctx, BGS_ERR_INVALID_ARG, "blend split: need caps >= 0, seg_len >= 1 and far_* >= 0");
+    ctx->cap_dom = (uint32_t)cap_dom;
+    ctx->cap_roi = (uint32_t)cap_roi;
+    ctx->seg_len = (uint32_t)seg_len;
+    ctx->far_dom = (uint32_t)far_dom;
+    ctx->far_roi = (uint32_t)far_roi;
     return BGS_OK;
 }
 

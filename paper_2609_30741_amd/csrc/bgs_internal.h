@@ -72,6 +72,22 @@ struct BlendArgs {
     int patch;       // 0: write rgb/depth_raw/alpha; 1: write rgb/z/alpha/cls
 };
 
+// Continuation of long tile lists in the blend (k_blend, k_blend_seg,
+// k_blend_fix in raster.hip).  All arrays live in the workspace.
+struct ContArgs {
+    uint32_t cap;          // records a tile composites before its rest is continued; 0: never
+    uint32_t seg_len;      // records per continuation segment (at most kContMaxSeg segments)
+    uint32_t max_slots;    // tiles that may be continued per pass
+    uint32_t min_far;      // continue a tile only if some pixel is expected to composite this many more records
+    uint32_t* n_slots;     // counters (DevStatus), cleared before each pass
+    uint32_t* n_items;
+    uint4* slot_desc;      // per slot: compact tile id, first continued record, end record, item base | nseg << 27
+    uint32_t* item_slot;   // per item: its slot
+    float4* st1;           // per slot: 256 pixels x 2 float4 after the capped walk
+    float4* part;          // per item: 256 pixels x 2 float4, the segment's walk from the slot's transmittance
+};
+constexpr uint32_t kContMaxSeg = 16;
+
 
 // Device status block kept in the workspace.
 struct DevStatus {
@@ -84,6 +100,7 @@ struct DevStatus {
     uint32_t n_holes, n_gap, n_center, n_rowfill, n_boxes, n_roi_tiles, n_edge, pad;
     uint32_t dmin_bits, dmax_bits;  // depth-range reduction (positive fp32 bits)
     uint32_t pad2[2];
+    uint32_t n_slots, n_items;  // blend continuation of the current pass
     // Counting mode only, dominant then ROI pass, 6 each: evaluated pairs,
     // contributing pairs, records walked (summed over waves), records past
     // the strip test (summed over waves), longest walk of one wave, longest
@@ -125,7 +142,7 @@ hipError_t launch_tile_order(const uint2* ranges, const uint32_t* n_live, int n_
 // pair_counts (optional): the six blend counters of DevStatus::pairs.
 hipError_t launch_blend(const SurfelRec* recs, const uint32_t* vals, const uint2* ranges,
                         const uint32_t* tile_list, const uint32_t* order, const uint32_t* n_live, int n_blocks,
-                        const BlendArgs& a, float* rgb, float* d_or_z, float* alpha, uint8_t* cls,
+                        const BlendArgs& a, const ContArgs& ca, float* rgb, float* d_or_z, float* alpha, uint8_t* cls,
                         unsigned long long* pair_counts, long long* trace, hipStream_t s);
 // prefix[n_tiles + 1] and the compact list of masked tile ids; tmp32 holds
 // n_tiles words, scan_tmp scan_tmp_elems(n_tiles) words.

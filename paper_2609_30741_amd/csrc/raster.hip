@@ -422,6 +422,8 @@ __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key
 }
 
 __global__ void k_status_keys(const uint32_t* __restrict__ offs, int n, DevStatus* st, uint32_t cap, int which) {
+    st->n_slots = 0;
+    st->n_items = 0;
     const uint32_t K = offs[n];
     st->n_keys = K;
     st->n_sort = K < cap ? K : cap;
@@ -512,6 +514,8 @@ constexpr int kBatch = 256;
 constexpr int kTrip = 4;                // records per trip of the walk
 constexpr int kDummy = kBatch;          // LDS record index of the zero record
 constexpr int kListLen = kBatch + 4;    // per-wave hit list, with padding
+constexpr uint32_t kRoundSeg = 4;       // continuation segments walked in the first round
+
 
 struct PixelState {
     float T, c0, c1, c2, D, A;
@@ -573,100 +577,108 @@ __device__ __forceinline__ void accumulate(float al, float dsel, const float4& r
     p.live = p.live && !stop;
 }
 
+// Strip test, compaction and compositing of one staged batch of nb records
+// by one wave (no block barriers).
+template <bool kCount>
+__device__ __forceinline__ void walk_batch(const float4* s_rec, uint32_t nb, uint16_t* s_list, const TileGeom& g,
+                                           const BlendArgs& a, PixelState& p, WalkCounts& wc) {
+    const char* s_bytes = reinterpret_cast<const char*>(s_rec);
+    uint32_t nhit = 0;
+#pragma unroll
+    for (int q = 0; q < kBatch / 64; ++q) {
+        const uint32_t j = (uint32_t)(q * 64 + g.lane);
+        bool h = false;
+        if (j < nb) {
+            const uint32_t nq = __float_as_uint(s_rec[4 * j + 2].w), bq = __float_as_uint(s_rec[4 * j + 3].w);
+            const float nx = snorm16_value((int)(int16_t)(nq & 0xFFFFu));
+            const float ny = snorm16_value((int)(int16_t)(nq >> 16));
+            const float4 r0 = s_rec[4 * j];
+            const float pr = fmaf(nx, g.scx - r0.x, ny * (g.scy - r0.y)) - half_value(bq);
+            h = fabsf(pr) <= half_value(bq >> 16) + fmaf(fabsf(nx), 7.5f, fabsf(ny) * 1.5f);
+        }
+        const uint64_t m = __ballot(h);
+        if (h) {
+            const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            s_list[nhit + below] = (uint16_t)(j * 64u);
+        }
+        nhit += (uint32_t)__popcll(m);
+    }
+    if (g.lane < kTrip) s_list[nhit + g.lane] = (uint16_t)(kDummy * 64);
+    // The list is written and read by this wave only.
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (kCount) {
+        wc.walk += nb;
+        wc.test += nhit;
+    }
+    for (uint32_t k = 0; k < nhit; k += kTrip) {
+        if (__ballot(p.live) == 0ull) break;
+        uint32_t off[kTrip];
+        if (kTrip == 4) {
+            const uint2 o = *reinterpret_cast<const uint2*>(s_list + k);
+            off[0] = o.x & 0xFFFFu;
+            off[1] = o.x >> 16;
+            off[2 % kTrip] = o.y & 0xFFFFu;
+            off[3 % kTrip] = o.y >> 16;
+        } else {
+            const uint32_t o = *reinterpret_cast<const uint32_t*>(s_list + k);
+            off[0] = o & 0xFFFFu;
+            off[1 % kTrip] = o >> 16;
+        }
+        float al[kTrip], ds[kTrip];
+#pragma unroll
+        for (int i = 0; i < kTrip; ++i) {
+            const float4* r = reinterpret_cast<const float4*>(s_bytes + off[i]);
+            pair_alpha(r[0], r[1], r[2], g.fpx, g.fpy, a, al[i], ds[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < kTrip; ++i) {
+            const float4* r = reinterpret_cast<const float4*>(s_bytes + off[i]);
+            accumulate(al[i], ds[i], r[3], a, p, wc, kCount, k + i < nhit);
+        }
+    }
+}
+
+__device__ __forceinline__ void load_rec(const SurfelRec* __restrict__ recs, const uint32_t* __restrict__ vals,
+                                         uint32_t pos, float4& q0, float4& q1, float4& q2, float4& q3) {
+    const SurfelRec* r = recs + vals[pos];
+    q0 = r->a;
+    q1 = r->b;
+    q2 = r->c;
+    q3 = r->d;
+}
+
+__device__ __forceinline__ void stage_rec(float4* s_rec, int t, const float4& q0, const float4& q1, const float4& q2,
+                                          const float4& q3) {
+    s_rec[4 * t + 0] = q0;
+    s_rec[4 * t + 1] = q1;
+    s_rec[4 * t + 2] = q2;
+    s_rec[4 * t + 3] = q3;
+}
+
 template <bool kCount>
 __device__ __forceinline__ void walk_range(const SurfelRec* __restrict__ recs, const uint32_t* __restrict__ vals,
                                            uint32_t b, uint32_t e, float4* s_rec, uint16_t* s_list,
                                            const TileGeom& g, const BlendArgs& a, PixelState& p, WalkCounts& wc) {
-    const char* s_bytes = reinterpret_cast<const char*>(s_rec);
     float4 q0, q1, q2, q3;
-    {
-        const uint32_t pos = b + g.tid;
-        if (pos < e) {
-            const SurfelRec* r = recs + vals[pos];
-            q0 = r->a; q1 = r->b; q2 = r->c; q3 = r->d;
-        }
-    }
+    if (b + g.tid < e) load_rec(recs, vals, b + g.tid, q0, q1, q2, q3);
     for (uint32_t base = b; base < e; base += kBatch) {
         const uint32_t nb = min((uint32_t)kBatch, e - base);
         __syncthreads();
-        if ((uint32_t)g.tid < nb) {
-            s_rec[4 * g.tid + 0] = q0;
-            s_rec[4 * g.tid + 1] = q1;
-            s_rec[4 * g.tid + 2] = q2;
-            s_rec[4 * g.tid + 3] = q3;
-        }
+        if ((uint32_t)g.tid < nb) stage_rec(s_rec, g.tid, q0, q1, q2, q3);
         __syncthreads();
-        {
-            const uint32_t pos = base + kBatch + g.tid;
-            if (pos < e) {
-                const SurfelRec* r = recs + vals[pos];
-                q0 = r->a; q1 = r->b; q2 = r->c; q3 = r->d;
-            }
-        }
-        // Strip test and compaction of this wave's hits.
-        uint32_t nhit = 0;
-#pragma unroll
-        for (int q = 0; q < kBatch / 64; ++q) {
-            const uint32_t j = (uint32_t)(q * 64 + g.lane);
-            bool h = false;
-            if (j < nb) {
-                const uint32_t nq = __float_as_uint(s_rec[4 * j + 2].w), bq = __float_as_uint(s_rec[4 * j + 3].w);
-                const float nx = snorm16_value((int)(int16_t)(nq & 0xFFFFu));
-                const float ny = snorm16_value((int)(int16_t)(nq >> 16));
-                const float4 r0 = s_rec[4 * j];
-                const float pr = fmaf(nx, g.scx - r0.x, ny * (g.scy - r0.y)) - half_value(bq);
-                h = fabsf(pr) <= half_value(bq >> 16) + fmaf(fabsf(nx), 7.5f, fabsf(ny) * 1.5f);
-            }
-            const uint64_t m = __ballot(h);
-            if (h) {
-                const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                s_list[nhit + below] = (uint16_t)(j * 64u);
-            }
-            nhit += (uint32_t)__popcll(m);
-        }
-        if (g.lane < kTrip) s_list[nhit + g.lane] = (uint16_t)(kDummy * 64);
-        // The list is written and read by this wave only.
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        if (kCount) {
-            wc.walk += nb;
-            wc.test += nhit;
-        }
-        for (uint32_t k = 0; k < nhit; k += kTrip) {
-            if (__ballot(p.live) == 0ull) break;
-            uint32_t off[kTrip];
-            if (kTrip == 4) {
-                const uint2 o = *reinterpret_cast<const uint2*>(s_list + k);
-                off[0] = o.x & 0xFFFFu;
-                off[1] = o.x >> 16;
-                off[2 % kTrip] = o.y & 0xFFFFu;
-                off[3 % kTrip] = o.y >> 16;
-            } else {
-                const uint32_t o = *reinterpret_cast<const uint32_t*>(s_list + k);
-                off[0] = o & 0xFFFFu;
-                off[1 % kTrip] = o >> 16;
-            }
-            float al[kTrip], ds[kTrip];
-#pragma unroll
-            for (int i = 0; i < kTrip; ++i) {
-                const float4* r = reinterpret_cast<const float4*>(s_bytes + off[i]);
-                pair_alpha(r[0], r[1], r[2], g.fpx, g.fpy, a, al[i], ds[i]);
-            }
-#pragma unroll
-            for (int i = 0; i < kTrip; ++i) {
-                const float4* r = reinterpret_cast<const float4*>(s_bytes + off[i]);
-                accumulate(al[i], ds[i], r[3], a, p, wc, kCount, k + i < nhit);
-            }
-        }
+        if (base + kBatch + g.tid < e) load_rec(recs, vals, base + kBatch + g.tid, q0, q1, q2, q3);
+        walk_batch<kCount>(s_rec, nb, s_list, g, a, p, wc);
         if (__syncthreads_count(p.live) == 0) break;
     }
 }
 
-__device__ __forceinline__ TileGeom tile_geom(uint32_t tile, const BlendArgs& a, bool* inside, int* px, int* py) {
+__device__ __forceinline__ TileGeom tile_geom(uint32_t tile, int tid, const BlendArgs& a, bool* inside, int* px,
+                                              int* py) {
     TileGeom g;
     const int tx = (int)(tile % (uint32_t)a.tiles_x), ty = (int)(tile / (uint32_t)a.tiles_x);
-    g.tid = threadIdx.x;
+    g.tid = tid;
     g.lane = g.tid & 63;
     const int wave = g.tid >> 6;
     *px = tx * kTile + (g.lane & 15);
@@ -725,7 +737,7 @@ template <bool kCount, bool kPatch>
 __global__ __launch_bounds__(256) void k_blend(const SurfelRec* __restrict__ recs, const uint32_t* __restrict__ vals,
                                                const uint2* __restrict__ ranges, const uint32_t* __restrict__ tile_list,
                                                const uint32_t* __restrict__ order,
-                                               const uint32_t* __restrict__ n_live, BlendArgs a,
+                                               const uint32_t* __restrict__ n_live, BlendArgs a, ContArgs ca,
                                                float* __restrict__ rgb, float* __restrict__ dz,
                                                float* __restrict__ alpha, uint8_t* __restrict__ cls,
                                                unsigned long long* __restrict__ pair_counts,
@@ -733,6 +745,8 @@ __global__ __launch_bounds__(256) void k_blend(const SurfelRec* __restrict__ rec
     __shared__ float4 s_rec[(kBatch + 1) * 4];
     __shared__ __align__(8) uint16_t s_list[4 * kListLen];
     __shared__ uint32_t s_walk[4];
+    __shared__ uint32_t s_slot, s_ibase, s_nseg;
+    __shared__ float s_far[4];
     const long long t_begin = kCount ? wall_clock64() : 0;
     const uint32_t blk = blockIdx.x;
     if (n_live && blk >= *n_live) return;
@@ -740,12 +754,85 @@ __global__ __launch_bounds__(256) void k_blend(const SurfelRec* __restrict__ rec
     const uint32_t tile = tile_list ? tile_list[cid] : cid;
     bool inside;
     int px, py;
-    const TileGeom g = tile_geom(tile, a, &inside, &px, &py);
+    const TileGeom g = tile_geom(tile, (int)threadIdx.x, a, &inside, &px, &py);
     const uint2 rg = ranges[cid];
     PixelState p{1.f, 0.f, 0.f, 0.f, 0.f, 0.f, inside};
     WalkCounts wc{0, 0, 0, 0};
     if (g.tid < 4) s_rec[4 * kDummy + g.tid] = make_float4(0.f, 0.f, 0.f, 0.f);
-    walk_range<kCount>(recs, vals, rg.x, rg.y, s_rec, s_list + (g.tid >> 6) * kListLen, g, a, p, wc);
+    uint16_t* my_list = s_list + (g.tid >> 6) * kListLen;
+    const uint32_t cap_end = (ca.cap && ca.max_slots && rg.y - rg.x > ca.cap) ? rg.x + ca.cap : rg.y;
+    // A capped walk also breaks its batches at its midpoint, where the
+    // transmittance is sampled for the hand-over decision.
+    const uint32_t mid = cap_end < rg.y ? rg.x + (cap_end - rg.x) / 2 : rg.y;
+    float t_half = 1.f;
+    uint32_t at_half = rg.x;  // records walked when t_half was taken
+    bool half_taken = false, handed = false;
+    // One batch loop over the whole list; batches stop at the cap, where the
+    // tile decides once whether to hand the rest over (then it leaves the
+    // loop) or to walk on.
+    float4 q0, q1, q2, q3;
+    if (rg.x + g.tid < rg.y) load_rec(recs, vals, rg.x + g.tid, q0, q1, q2, q3);
+    for (uint32_t base = rg.x; base < rg.y;) {
+        const uint32_t lim = base < mid ? mid : base < cap_end ? cap_end : rg.y;
+        const uint32_t nb = min((uint32_t)kBatch, lim - base);
+        __syncthreads();
+        if ((uint32_t)g.tid < nb) stage_rec(s_rec, g.tid, q0, q1, q2, q3);
+        __syncthreads();
+        if (base + nb + g.tid < rg.y) load_rec(recs, vals, base + nb + g.tid, q0, q1, q2, q3);
+        walk_batch<kCount>(s_rec, nb, my_list, g, a, p, wc);
+        base += nb;
+        if (!half_taken && base >= mid) {
+            half_taken = true;
+            t_half = p.T;
+            at_half = base;
+        }
+        const int n_live_px = __syncthreads_count(p.live);
+        if (n_live_px == 0) break;
+        if (base != cap_end || cap_end == rg.y) continue;
+        // Pixels still compositing past the cap: hand the rest of the list
+        // to continuation segments if a slot is free and the split pays,
+        // else walk on.  It pays when some pixel is expected to walk far:
+        // extrapolating the transmittance's decay over the second half of
+        // the capped walk, a pixel needs about ln(T / t_min) / (decay per
+        // record) more records.  Segments started for pixels that will stop
+        // soon would mostly be walked in vain.
+        float far = 0.f;
+        if (p.live) {
+            const float drop = t_half > p.T ? __logf(t_half / p.T) : 0.f;
+            const float need = __logf(p.T / a.t_min) * (float)(cap_end - at_half);
+            far = need >= 1e30f * drop ? 1e30f : need / drop;
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) far = fmaxf(far, __shfl_xor(far, off, 64));
+        if (g.lane == 0) s_far[g.tid >> 6] = far;
+        __syncthreads();
+        const float far_max = fmaxf(fmaxf(s_far[0], s_far[1]), fmaxf(s_far[2], s_far[3]));
+        const uint32_t rem = rg.y - cap_end;
+        if (g.tid == 0) {
+            s_slot = 0xFFFFFFFFu;
+            if (far_max >= (float)ca.min_far && rem >= 2 * ca.seg_len) {
+                const uint32_t slot = atomicAdd(ca.n_slots, 1u);
+                if (slot < ca.max_slots) {
+                    const uint32_t nseg = min(kContMaxSeg, max(1u, (rem + ca.seg_len - 1) / ca.seg_len));
+                    const uint32_t ibase = atomicAdd(ca.n_items, nseg);
+                    ca.slot_desc[slot] = make_uint4(cid, cap_end, rg.y, ibase | (nseg << 27));
+                    s_slot = slot;
+                    s_ibase = ibase;
+                    s_nseg = nseg;
+                }
+            }
+        }
+        __syncthreads();
+        const uint32_t slot = s_slot;
+        if (slot != 0xFFFFFFFFu) {
+            if ((uint32_t)g.tid < s_nseg) ca.item_slot[s_ibase + g.tid] = slot;
+            float4* st = ca.st1 + (size_t)slot * 512;
+            st[2 * g.tid] = make_float4(p.c0, p.c1, p.c2, p.D);
+            st[2 * g.tid + 1] = make_float4(p.A, p.T, p.live ? 1.f : 0.f, 0.f);
+            handed = p.live;  // pixels already done are final now
+            break;
+        }
+    }
     if (kCount) {
         count_flush(wc, g.lane, g.tid >> 6, rg.y - rg.x, pair_counts, s_walk);
         __syncthreads();
@@ -761,7 +848,146 @@ __global__ __launch_bounds__(256) void k_blend(const SurfelRec* __restrict__ rec
             t[5] = wall_clock64();
         }
     }
-    if (inside) write_pixel<kPatch>(p, px, py, a, rgb, dz, alpha, cls);
+    if (inside && !handed) write_pixel<kPatch>(p, px, py, a, rgb, dz, alpha, cls);
+}
+
+// ---------------------------------------------------------------------------
+// Continuation of the lists handed over by k_blend.  Segment k of a slot's
+// remaining records is walked by k_blend_seg from an upper bound of the
+// true transmittance at the segment's start: its sums divided by that bound
+// are the segment's contribution per unit of incoming transmittance, which
+// chains exactly while no pixel would stop inside the segment, and a pixel
+// that stops in this walk stops at or before the same record in the true
+// one.
+// k_blend_fix chains the segments before its own for every pixel; a pixel
+// whose transmittance would cross t_min inside its segment (or that stopped
+// in the speculative walk) is composited again over the segment, in order,
+// from its exact state, and written; the last segment also writes the
+// pixels that never stop.  k_blend writes the pixels already done when it
+// hands a tile over, so every pixel is written once.
+// ---------------------------------------------------------------------------
+struct Chain {
+    float T, c0, c1, c2, D, A;
+};
+
+// One segment of the chain.  Returns false where the pixel stops inside the
+// segment (nothing is added then).
+// One segment of the chain; the segment's sums are stored per unit of the
+// transmittance its walk started from.  Returns false where the pixel stops
+// inside the segment, or the segment was not walked for it (nothing is added
+// then).
+__device__ __forceinline__ bool chain_step(const float4& x0, const float4& x1, float t_min, Chain& c) {
+    if (x1.z != 0.f || c.T * x1.y < t_min) return false;
+    c.c0 = fmaf(c.T, x0.x, c.c0);
+    c.c1 = fmaf(c.T, x0.y, c.c1);
+    c.c2 = fmaf(c.T, x0.z, c.c2);
+    c.D = fmaf(c.T, x0.w, c.D);
+    c.A = fmaf(c.T, x1.x, c.A);
+    c.T *= x1.y;
+    return true;
+}
+
+__device__ __forceinline__ void item_segment(const uint4& d, uint32_t k, uint32_t* sb, uint32_t* se) {
+    const uint32_t nseg = d.w >> 27;
+    const uint64_t rem = d.z - d.y;
+    *sb = d.y + (uint32_t)(rem * k / nseg);
+    *se = d.y + (uint32_t)(rem * (k + 1) / nseg);
+}
+
+// Round 0 walks the first kRoundSeg segments of every continued tile from
+// the transmittance T1 after the capped walk.  Round 1 walks the others,
+// each pixel from its exact transmittance after the round-0 segments (a
+// tighter bound than T1), and only for the pixels that get through round 0:
+// for tiles whose pixels stop soon after the cap, round 1 has no work.
+template <bool kCount>
+__global__ __launch_bounds__(256) void k_blend_seg(const SurfelRec* __restrict__ recs,
+                                                   const uint32_t* __restrict__ vals,
+                                                   const uint32_t* __restrict__ tile_list, BlendArgs a, ContArgs ca,
+                                                   int round, unsigned long long* __restrict__ pair_counts) {
+    __shared__ float4 s_rec[(kBatch + 1) * 4];
+    __shared__ __align__(8) uint16_t s_list[4 * kListLen];
+    const uint32_t n_items = min(*ca.n_items, ca.max_slots * kContMaxSeg);
+    if (blockIdx.x >= n_items) return;
+    const int tid = (int)threadIdx.x;
+    if (tid < 4) s_rec[4 * kDummy + tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+    WalkCounts wc{0, 0, 0, 0};
+    for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+        const uint32_t slot = ca.item_slot[item];
+        const uint4 d = ca.slot_desc[slot];
+        const uint32_t ibase = d.w & 0x07FFFFFFu, nseg = d.w >> 27, k = item - ibase;
+        const uint32_t m = min(nseg, kRoundSeg);
+        if ((k < m) != (round == 0)) continue;
+        uint32_t sb, se;
+        item_segment(d, k, &sb, &se);
+        bool inside;
+        int px, py;
+        const TileGeom g = tile_geom(tile_list ? tile_list[d.x] : d.x, tid, a, &inside, &px, &py);
+        const float4 s1 = ca.st1[(size_t)slot * 512 + 2 * tid + 1];
+        Chain c{s1.y, 0.f, 0.f, 0.f, 0.f, 0.f};
+        bool live = s1.z != 0.f;
+        if (round != 0) {
+            for (uint32_t j = 0; j < m && live; ++j) {
+                const float4* x = ca.part + (size_t)(ibase + j) * 512 + 2 * tid;
+                live = chain_step(x[0], x[1], a.t_min, c);
+            }
+        }
+        const float ts = c.T;
+        PixelState p{ts, 0.f, 0.f, 0.f, 0.f, 0.f, live};
+        if (__syncthreads_or(live))
+            walk_range<kCount>(recs, vals, sb, se, s_rec, s_list + (tid >> 6) * kListLen, g, a, p, wc);
+        const float inv = live ? 1.f / ts : 0.f;
+        float4* o = ca.part + (size_t)item * 512;
+        o[2 * tid] = make_float4(p.c0 * inv, p.c1 * inv, p.c2 * inv, p.D * inv);
+        o[2 * tid + 1] = make_float4(p.A * inv, p.T * inv, live ? (p.live ? 0.f : 1.f) : 3.f, 0.f);
+    }
+    if (kCount) count_flush(wc, tid & 63, tid >> 6, 0, pair_counts, nullptr);
+}
+
+template <bool kCount, bool kPatch>
+__global__ __launch_bounds__(256) void k_blend_fix(const SurfelRec* __restrict__ recs,
+                                                   const uint32_t* __restrict__ vals,
+                                                   const uint32_t* __restrict__ tile_list, BlendArgs a, ContArgs ca,
+                                                   float* __restrict__ rgb, float* __restrict__ dz,
+                                                   float* __restrict__ alpha, uint8_t* __restrict__ cls,
+                                                   unsigned long long* __restrict__ pair_counts) {
+    __shared__ float4 s_rec[(kBatch + 1) * 4];
+    __shared__ __align__(8) uint16_t s_list[4 * kListLen];
+    const uint32_t n_items = min(*ca.n_items, ca.max_slots * kContMaxSeg);
+    if (blockIdx.x >= n_items) return;
+    const int tid = (int)threadIdx.x;
+    if (tid < 4) s_rec[4 * kDummy + tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+    WalkCounts wc{0, 0, 0, 0};
+    for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+        const uint32_t slot = ca.item_slot[item];
+        const uint4 d = ca.slot_desc[slot];
+        const uint32_t ibase = d.w & 0x07FFFFFFu, nseg = d.w >> 27, k = item - ibase;
+        uint32_t sb, se;
+        item_segment(d, k, &sb, &se);
+        bool inside;
+        int px, py;
+        const TileGeom g = tile_geom(tile_list ? tile_list[d.x] : d.x, tid, a, &inside, &px, &py);
+        const float4 s0 = ca.st1[(size_t)slot * 512 + 2 * tid], s1 = ca.st1[(size_t)slot * 512 + 2 * tid + 1];
+        Chain c{s1.y, s0.x, s0.y, s0.z, s0.w, s1.x};
+        bool reach = s1.z != 0.f;  // the pixel is still compositing when this segment starts
+        for (uint32_t j = 0; j < k && reach; ++j) {
+            const float4* x = ca.part + (size_t)(ibase + j) * 512 + 2 * tid;
+            reach = chain_step(x[0], x[1], a.t_min, c);
+        }
+        bool need = false, done_here = false;
+        if (reach) {
+            const float4* x = ca.part + (size_t)item * 512 + 2 * tid;
+            need = !chain_step(x[0], x[1], a.t_min, c);
+            done_here = !need && k + 1 == nseg;  // never stops: the last segment writes it
+        }
+        PixelState q{c.T, c.c0, c.c1, c.c2, c.D, c.A, false};
+        if (__syncthreads_or(need)) {
+            // c was left at the segment's start for the pixels that stop in it.
+            q.live = need;
+            walk_range<kCount>(recs, vals, sb, se, s_rec, s_list + (tid >> 6) * kListLen, g, a, q, wc);
+        }
+        if (inside && (need || done_here)) write_pixel<kPatch>(q, px, py, a, rgb, dz, alpha, cls);
+    }
+    if (kCount) count_flush(wc, tid & 63, tid >> 6, 0, pair_counts, nullptr);
 }
 
 }  // namespace
@@ -800,25 +1026,57 @@ hipError_t launch_tile_order(const uint2* ranges, const uint32_t* n_live, int n_
 }
 
 hipError_t launch_blend(const SurfelRec* recs, const uint32_t* vals, const uint2* ranges, const uint32_t* tile_list,
-                        const uint32_t* order, const uint32_t* n_live, int n_blocks, const BlendArgs& a, float* rgb,
-                        float* d_or_z, float* alpha, uint8_t* cls, unsigned long long* pair_counts, long long* trace,
-                        hipStream_t s) {
+                        const uint32_t* order, const uint32_t* n_live, int n_blocks, const BlendArgs& a,
+                        const ContArgs& ca, float* rgb, float* d_or_z, float* alpha, uint8_t* cls,
+                        unsigned long long* pair_counts, long long* trace, hipStream_t s) {
     if (n_blocks <= 0) return hipSuccess;
     const dim3 g(n_blocks), b(256);
+    const bool cont = ca.cap != 0 && ca.max_slots != 0;
+    const dim3 gc(min(ca.max_slots * kContMaxSeg, 4096u));
     if (a.patch) {
-        if (pair_counts)
-            hipLaunchKernelGGL((k_blend<true, true>), g, b, 0, s, recs, vals, ranges, tile_list, order, n_live, a, rgb,
-                               d_or_z, alpha, cls, pair_counts, trace);
-        else
-            hipLaunchKernelGGL((k_blend<false, true>), g, b, 0, s, recs, vals, ranges, tile_list, order, n_live, a,
-                               rgb, d_or_z, alpha, cls, pair_counts, (long long*)nullptr);
-    } else {
-        if (pair_counts)
-            hipLaunchKernelGGL((k_blend<true, false>), g, b, 0, s, recs, vals, ranges, tile_list, order, n_live, a,
+        if (pair_counts) {
+            hipLaunchKernelGGL((k_blend<true, true>), g, b, 0, s, recs, vals, ranges, tile_list, order, n_live, a, ca,
                                rgb, d_or_z, alpha, cls, pair_counts, trace);
-        else
-            hipLaunchKernelGGL((k_blend<false, false>), g, b, 0, s, recs, vals, ranges, tile_list, order, n_live, a,
+            if (cont) {
+                for (int round = 0; round < 2; ++round)
+                    hipLaunchKernelGGL((k_blend_seg<true>), gc, b, 0, s, recs, vals, tile_list, a, ca, round,
+                                       pair_counts);
+                hipLaunchKernelGGL((k_blend_fix<true, true>), gc, b, 0, s, recs, vals, tile_list, a, ca, rgb, d_or_z,
+                                   alpha, cls, pair_counts);
+            }
+        } else {
+            hipLaunchKernelGGL((k_blend<false, true>), g, b, 0, s, recs, vals, ranges, tile_list, order, n_live, a, ca,
                                rgb, d_or_z, alpha, cls, pair_counts, (long long*)nullptr);
+            if (cont) {
+                for (int round = 0; round < 2; ++round)
+                    hipLaunchKernelGGL((k_blend_seg<false>), gc, b, 0, s, recs, vals, tile_list, a, ca, round,
+                                       pair_counts);
+                hipLaunchKernelGGL((k_blend_fix<false, true>), gc, b, 0, s, recs, vals, tile_list, a, ca, rgb, d_or_z,
+                                   alpha, cls, pair_counts);
+            }
+        }
+    } else {
+        if (pair_counts) {
+            hipLaunchKernelGGL((k_blend<true, false>), g, b, 0, s, recs, vals, ranges, tile_list, order, n_live, a, ca,
+                               rgb, d_or_z, alpha, cls, pair_counts, trace);
+            if (cont) {
+                for (int round = 0; round < 2; ++round)
+                    hipLaunchKernelGGL((k_blend_seg<true>), gc, b, 0, s, recs, vals, tile_list, a, ca, round,
+                                       pair_counts);
+                hipLaunchKernelGGL((k_blend_fix<true, false>), gc, b, 0, s, recs, vals, tile_list, a, ca, rgb, d_or_z,
+                                   alpha, cls, pair_counts);
+            }
+        } else {
+            hipLaunchKernelGGL((k_blend<false, false>), g, b, 0, s, recs, vals, ranges, tile_list, order, n_live, a,
+                               ca, rgb, d_or_z, alpha, cls, pair_counts, (long long*)nullptr);
+            if (cont) {
+                for (int round = 0; round < 2; ++round)
+                    hipLaunchKernelGGL((k_blend_seg<false>), gc, b, 0, s, recs, vals, tile_list, a, ca, round,
+                                       pair_counts);
+                hipLaunchKernelGGL((k_blend_fix<false, false>), gc, b, 0, s, recs, vals, tile_list, a, ca, rgb,
+                                   d_or_z, alpha, cls, pair_counts);
+            }
+        }
     }
     return hipGetLastError();
 }

@@ -160,6 +160,42 @@ def test_render_dominant_cube(ctx, oracle, W, H):
     check_image(to_np(out["rgb"]), to_np(out["depth_raw"]), to_np(out["alpha"]), ref, f"cube {W}x{H}")
 
 
+@pytest.mark.parametrize("W,H,f,caps", [(144, 112, 170.0, (32, 16, 16)), (144, 112, 170.0, (1, 1, 1)),
+                                          (144, 112, 170.0, (200, 100, 7)), (640, 480, 740.0, (64, 64, 32))])
+def test_render_continued_lists(ctx, oracle, W, H, f, caps):
+    """Long lists continued by segment workgroups (small caps force it on most
+    tiles; opaque surfels make pixels stop inside segments, which exercises
+    the in-order recompositing; 640x480 has more tiles than continuation
+    slots, so some tiles walk on in their own workgroup) give the oracle's
+    pixels, the ROI patch included, and agree with the single walk to fp32
+    rounding."""
+    sc, cam = cube_workload(10_000 if W < 400 else 30_000, W, H, f, seed=4)
+    sc.opacity[:] = np.maximum(sc.opacity, 0.9)
+    ds = api.DeviceScene(sc)
+    log(f"continued lists {W}x{H} caps={caps}")
+    try:
+        ctx.set_blend_split(0, 0, 256)
+        whole = ctx.render_dominant(ds, cam)
+        ctx.set_blend_split(*caps, 0, 0)
+        out = ctx.render_dominant(ds, cam)
+        tm = (np.random.default_rng(3).uniform(size=((H + 15) // 16, (W + 15) // 16)) < 0.5).astype(np.uint8)
+        g_rgb, g_z = torch.zeros((3, H, W), device="cuda"), torch.zeros((H, W), device="cuda")
+        g_a, g_cls = torch.zeros((H, W), device="cuda"), torch.zeros((H, W), dtype=torch.uint8, device="cuda")
+        ctx.patch_rois(ds, cam, torch.from_numpy(tm).cuda(), g_rgb, g_z, g_a, g_cls)
+    finally:
+        ctx.set_blend_split()
+    ref = oracle.render(sc, cam)
+    check_image(to_np(out["rgb"]), to_np(out["depth_raw"]), to_np(out["alpha"]), ref, f"continued {caps}")
+    amb = ref["amb"] > 0
+    for k in ("rgb", "depth_raw", "alpha"):
+        diff = np.abs(to_np(out[k]) - to_np(whole[k]))
+        scale = 1.0 if k != "depth_raw" else float(np.abs(to_np(whole[k])).max()) + 1e-3
+        assert float((diff / scale)[..., ~amb].max()) <= 2e-5, k
+    pm = np.kron(tm, np.ones((16, 16), np.uint8)).astype(bool)[:H, :W]
+    err = np.abs(np.clip(to_np(g_rgb), 0, 1) - np.clip(ref["rgb"], 0, 1)).max(0)
+    assert not np.any((err > RGB_TOL) & pm & ~amb), "ROI patch with continued lists"
+
+
 def test_render_edge_cases(ctx, oracle):
     # Empty scene -> background; one opaque surfel -> depth proxy = its depth;
     # surfels behind the camera are culled.
@@ -300,10 +336,15 @@ def test_patch_matches_oracle_and_all_tiles_equal_full_render(ctx, oracle):
     err = np.abs(np.clip(rgb, 0, 1) - np.clip(ref["rgb"], 0, 1)).max(0)
     assert not np.any((err > RGB_TOL) & pm & ~amb)
     # An all-ones mask re-renders the whole image: bit-identical to the full
-    # render of the same camera.
-    full = ctx.render_dominant(ds, aff)
-    ones = torch.ones((16, 16), dtype=torch.uint8, device="cuda")
-    ctx.patch_rois(ds, aff, ones, g_rgb, g_z, g_a, g_cls)
+    # render of the same camera when both passes schedule long lists alike
+    # (the same continuation caps).
+    try:
+        ctx.set_blend_split(256, 256, 256, 0, 0)
+        full = ctx.render_dominant(ds, aff)
+        ones = torch.ones((16, 16), dtype=torch.uint8, device="cuda")
+        ctx.patch_rois(ds, aff, ones, g_rgb, g_z, g_a, g_cls)
+    finally:
+        ctx.set_blend_split()
     assert torch.equal(g_rgb, full["rgb"]) and torch.equal(g_a, full["alpha"])
 
 
