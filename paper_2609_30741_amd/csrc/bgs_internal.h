@@ -22,8 +22,9 @@ constexpr int kScanBlock = 256 * kScanItems;    // 2048 elements per block
 //   c = (lam_num, z_c, opacity, band direction)
 //   d = (r, g, b, band interval)
 // With dx = i - mu_x, dy = j - mu_y and den = 1 + N1 dx + N2 dy the
-// surfel-plane coordinates of pixel (i, j) are u = (C1 dx + C2 dy)/den,
-// v = (D1 dx + D2 dy)/den and the ray meets the plane at depth
+// surfel-plane coordinates of pixel (i, j), times sqrt(1/2), are
+// u = (C1 dx + C2 dy)/den, v = (D1 dx + D2 dy)/den and the ray meets the
+// plane at depth
 // lam_num/den (lam_num < 0 marks a surfel seen exactly edge-on).  The
 // strip band bounds every pixel x the surfel can reach by
 // |n.(x - mu) - c| <= w, with n a pair of snorm16 (x low, y high) and c, w

@@ -320,10 +320,13 @@ __global__ __launch_bounds__(256) void k_preprocess(SceneArgs sc, PreCam cam, fl
             const double pa = pc[0] * as[0] + pc[1] * as[1] + pc[2] * as[2];
             const double pb = pc[0] * bs[0] + pc[1] * bs[1] + pc[2] * bs[2];
             const double n1 = nv[0] / (cam.fx * nrc), n2 = nv[1] / (cam.fy * nrc);
-            C1 = (float)(pzc * as[0] / cam.fx - n1 * pa);
-            C2 = (float)(pzc * as[1] / cam.fy - n2 * pa);
-            D1 = (float)(pzc * bs[0] / cam.fx - n1 * pb);
-            D2 = (float)(pzc * bs[1] / cam.fy - n2 * pb);
+            // u and v are stored scaled by sqrt(1/2): the blend then takes
+            // -(u^2 + v^2) as the exponent of G3 = exp(-(u^2 + v^2) / 2).
+            constexpr double kRootHalf = 0.70710678118654752440;
+            C1 = (float)(kRootHalf * (pzc * as[0] / cam.fx - n1 * pa));
+            C2 = (float)(kRootHalf * (pzc * as[1] / cam.fy - n2 * pa));
+            D1 = (float)(kRootHalf * (pzc * bs[0] / cam.fx - n1 * pb));
+            D2 = (float)(kRootHalf * (pzc * bs[1] / cam.fy - n2 * pb));
             N1 = (float)n1;
             N2 = (float)n2;
             lam_num = (float)pzc;
@@ -517,10 +520,16 @@ constexpr int kListLen = kBatch + 4;    // per-wave hit list, with padding
 constexpr uint32_t kRoundSeg = 4;       // continuation segments walked in the first round
 
 
+// A pixel's compositing state.  A pixel that has stopped, or that takes no
+// part in a walk, has T = 0: every later pair then adds nothing, so no
+// separate flag is needed.  The background weight of a stopped pixel is its
+// transmittance at the stop, which equals 1 - A (A is the sum of the
+// weights alpha * T, and each step lowers T by exactly its weight).
 struct PixelState {
     float T, c0, c1, c2, D, A;
-    bool live;
 };
+
+__device__ __forceinline__ bool live(const PixelState& p) { return p.T > 0.f; }
 
 struct WalkCounts {
     uint32_t eval, used, walk, test;
@@ -547,7 +556,9 @@ __device__ __forceinline__ void pair_alpha(const float4& r0, const float4& r1, c
     // lam <= z_near covers hits behind the camera and edge-on records; a
     // non-finite u, v near the plane's horizon gives -inf or NaN, and
     // fmaxf then keeps the low-pass term.
-    const float e3 = lam > a.z_near ? -0.5f * fmaf(u, u, v * v) : -INFINITY;
+    // The record's u and v coefficients carry a factor sqrt(1/2), so
+    // -(u^2 + v^2) here is the G3 exponent -(u^2 + v^2) / 2 of the plane.
+    const float e3 = lam > a.z_near ? -fmaf(u, u, v * v) : -INFINITY;
     const float e2 = a.lowpass ? -fmaf(dx, dx, dy * dy) : -INFINITY;
     al = fminf(a.alpha_max, r2.z * __expf(fmaxf(e3, e2)));
     dsel = (e3 >= e2) ? lam : r2.y;
@@ -556,25 +567,23 @@ __device__ __forceinline__ void pair_alpha(const float4& r0, const float4& r1, c
 // One front-to-back compositing step: a pair below alpha_min is skipped;
 // the pixel stops before the surfel that would take T below t_min;
 // otherwise RGB, the depth proxy D and A accumulate with the same weight
-// w = alpha * T.
+// w = alpha * T, and T drops by w.
 __device__ __forceinline__ void accumulate(float al, float dsel, const float4& r3, const BlendArgs& a, PixelState& p,
                                            WalkCounts& wc, bool count, bool valid) {
-    const float Tn = p.T * (1.f - al);
-    const bool use = p.live && al >= a.alpha_min;
-    const bool stop = use && Tn < a.t_min;
-    const bool add = use && !stop;
-    const float wt = add ? al * p.T : 0.f;
+    float wt = (al >= a.alpha_min ? al : 0.f) * p.T;
+    const float Tn = p.T - wt;
+    const bool stop = Tn < a.t_min;  // also for a pixel already stopped (T = 0)
+    wt = stop ? 0.f : wt;
     if (count && valid) {
-        wc.eval += p.live ? 1u : 0u;
-        wc.used += add ? 1u : 0u;
+        wc.eval += p.T > 0.f ? 1u : 0u;
+        wc.used += wt > 0.f ? 1u : 0u;
     }
     p.c0 = fmaf(wt, r3.x, p.c0);
     p.c1 = fmaf(wt, r3.y, p.c1);
     p.c2 = fmaf(wt, r3.z, p.c2);
     p.D = fmaf(wt, dsel, p.D);
     p.A += wt;
-    p.T = add ? Tn : p.T;
-    p.live = p.live && !stop;
+    p.T = stop ? 0.f : Tn;
 }
 
 // Strip test, compaction and compositing of one staged batch of nb records
@@ -613,7 +622,7 @@ __device__ __forceinline__ void walk_batch(const float4* s_rec, uint32_t nb, uin
         wc.test += nhit;
     }
     for (uint32_t k = 0; k < nhit; k += kTrip) {
-        if (__ballot(p.live) == 0ull) break;
+        if (__ballot(live(p)) == 0ull) break;
         uint32_t off[kTrip];
         if (kTrip == 4) {
             const uint2 o = *reinterpret_cast<const uint2*>(s_list + k);
@@ -670,7 +679,7 @@ __device__ __forceinline__ void walk_range(const SurfelRec* __restrict__ recs, c
         __syncthreads();
         if (base + kBatch + g.tid < e) load_rec(recs, vals, base + kBatch + g.tid, q0, q1, q2, q3);
         walk_batch<kCount>(s_rec, nb, s_list, g, a, p, wc);
-        if (__syncthreads_count(p.live) == 0) break;
+        if (__syncthreads_count(live(p)) == 0) break;
     }
 }
 
@@ -697,9 +706,10 @@ __device__ __forceinline__ void write_pixel(const PixelState& p, int px, int py,
                                             uint8_t* __restrict__ cls) {
     const int64_t hw = (int64_t)a.W * a.H;
     const int64_t q = (int64_t)py * a.W + px;
-    rgb[q] = fmaf(p.T, a.bg0, p.c0);
-    rgb[hw + q] = fmaf(p.T, a.bg1, p.c1);
-    rgb[2 * hw + q] = fmaf(p.T, a.bg2, p.c2);
+    const float tb = p.T > 0.f ? p.T : 1.f - p.A;  // background weight
+    rgb[q] = fmaf(tb, a.bg0, p.c0);
+    rgb[hw + q] = fmaf(tb, a.bg1, p.c1);
+    rgb[2 * hw + q] = fmaf(tb, a.bg2, p.c2);
     alpha[q] = p.A;
     if (!kPatch) {
         dz[q] = p.D;
@@ -756,7 +766,7 @@ __global__ __launch_bounds__(256) void k_blend(const SurfelRec* __restrict__ rec
     int px, py;
     const TileGeom g = tile_geom(tile, (int)threadIdx.x, a, &inside, &px, &py);
     const uint2 rg = ranges[cid];
-    PixelState p{1.f, 0.f, 0.f, 0.f, 0.f, 0.f, inside};
+    PixelState p{inside ? 1.f : 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     WalkCounts wc{0, 0, 0, 0};
     if (g.tid < 4) s_rec[4 * kDummy + g.tid] = make_float4(0.f, 0.f, 0.f, 0.f);
     uint16_t* my_list = s_list + (g.tid >> 6) * kListLen;
@@ -786,7 +796,7 @@ __global__ __launch_bounds__(256) void k_blend(const SurfelRec* __restrict__ rec
             t_half = p.T;
             at_half = base;
         }
-        const int n_live_px = __syncthreads_count(p.live);
+        const int n_live_px = __syncthreads_count(live(p));
         if (n_live_px == 0) break;
         if (base != cap_end || cap_end == rg.y) continue;
         // Pixels still compositing past the cap: hand the rest of the list
@@ -797,7 +807,7 @@ __global__ __launch_bounds__(256) void k_blend(const SurfelRec* __restrict__ rec
         // record) more records.  Segments started for pixels that will stop
         // soon would mostly be walked in vain.
         float far = 0.f;
-        if (p.live) {
+        if (live(p)) {
             const float drop = t_half > p.T ? __logf(t_half / p.T) : 0.f;
             const float need = __logf(p.T / a.t_min) * (float)(cap_end - at_half);
             far = need >= 1e30f * drop ? 1e30f : need / drop;
@@ -828,8 +838,8 @@ __global__ __launch_bounds__(256) void k_blend(const SurfelRec* __restrict__ rec
             if ((uint32_t)g.tid < s_nseg) ca.item_slot[s_ibase + g.tid] = slot;
             float4* st = ca.st1 + (size_t)slot * 512;
             st[2 * g.tid] = make_float4(p.c0, p.c1, p.c2, p.D);
-            st[2 * g.tid + 1] = make_float4(p.A, p.T, p.live ? 1.f : 0.f, 0.f);
-            handed = p.live;  // pixels already done are final now
+            st[2 * g.tid + 1] = make_float4(p.A, p.T, live(p) ? 1.f : 0.f, 0.f);
+            handed = live(p);  // pixels already done are final now
             break;
         }
     }
@@ -932,13 +942,13 @@ __global__ __launch_bounds__(256) void k_blend_seg(const SurfelRec* __restrict__
             }
         }
         const float ts = c.T;
-        PixelState p{ts, 0.f, 0.f, 0.f, 0.f, 0.f, live};
+        PixelState p{live ? ts : 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         if (__syncthreads_or(live))
             walk_range<kCount>(recs, vals, sb, se, s_rec, s_list + (tid >> 6) * kListLen, g, a, p, wc);
         const float inv = live ? 1.f / ts : 0.f;
         float4* o = ca.part + (size_t)item * 512;
         o[2 * tid] = make_float4(p.c0 * inv, p.c1 * inv, p.c2 * inv, p.D * inv);
-        o[2 * tid + 1] = make_float4(p.A * inv, p.T * inv, live ? (p.live ? 0.f : 1.f) : 3.f, 0.f);
+        o[2 * tid + 1] = make_float4(p.A * inv, p.T * inv, live ? (p.T > 0.f ? 0.f : 1.f) : 3.f, 0.f);
     }
     if (kCount) count_flush(wc, tid & 63, tid >> 6, 0, pair_counts, nullptr);
 }
@@ -979,13 +989,15 @@ __global__ __launch_bounds__(256) void k_blend_fix(const SurfelRec* __restrict__
             need = !chain_step(x[0], x[1], a.t_min, c);
             done_here = !need && k + 1 == nseg;  // never stops: the last segment writes it
         }
-        PixelState q{c.T, c.c0, c.c1, c.c2, c.D, c.A, false};
+        // c was left at the segment's start for the pixels that stop in it;
+        // the others take no part in the walk.
+        PixelState q{need ? c.T : 0.f, c.c0, c.c1, c.c2, c.D, c.A};
         if (__syncthreads_or(need)) {
-            // c was left at the segment's start for the pixels that stop in it.
-            q.live = need;
             walk_range<kCount>(recs, vals, sb, se, s_rec, s_list + (tid >> 6) * kListLen, g, a, q, wc);
         }
-        if (inside && (need || done_here)) write_pixel<kPatch>(q, px, py, a, rgb, dz, alpha, cls);
+        if (inside && need) write_pixel<kPatch>(q, px, py, a, rgb, dz, alpha, cls);
+        if (inside && done_here)
+            write_pixel<kPatch>(PixelState{c.T, c.c0, c.c1, c.c2, c.D, c.A}, px, py, a, rgb, dz, alpha, cls);
     }
     if (kCount) count_flush(wc, tid & 63, tid >> 6, 0, pair_counts, nullptr);
 }
