@@ -178,10 +178,11 @@ BGS_API int32_t bgs_ctx_set_blend_split(bgs_ctx* ctx, int32_t cap_dom, int32_t c
 
 /* Per-stage GPU timing with HIP events recorded on the context's stream
  * around each stage's launches.  on = 1 enables it and clears the totals.
- * After the caller has waited for the stream, bgs_timing_collect() adds the
- * elapsed times of the stages recorded since the last collect to the
- * totals and copies totals (ms) and counts for the BGS_NUM_STAGES stages,
- * in the order of enum bgs_stage. */
+ * Frames may be issued back to back: the events of the last 64 frames are
+ * kept, and older ones are folded into the totals as new frames start (a
+ * frame 64 frames old has long finished).  bgs_timing_collect() waits for
+ * the recorded stages, adds them to the totals and copies totals (ms) and
+ * counts for the BGS_NUM_STAGES stages, in the order of enum bgs_stage. */
 enum bgs_stage {
     BGS_STAGE_PREPROCESS_DOM = 0, BGS_STAGE_DEPTH_SORT_DOM, BGS_STAGE_EMIT_DOM, BGS_STAGE_TILE_SORT_DOM,
     BGS_STAGE_RANGES_DOM, BGS_STAGE_BLEND_DOM, BGS_STAGE_REPROJECT, BGS_STAGE_CLASSIFY,

@@ -18,8 +18,13 @@ struct bgs_ctx {
     // Blend continuation: records a tile composites before the rest of its
     // list is split into segments (0: never), per pass, and the segment length.
     uint32_t cap_dom = 1024, cap_roi = 128, seg_len = 192, far_dom = 0, far_roi = 768;
-    hipEvent_t ev[BGS_NUM_STAGES][2] = {};
-    bool pending[BGS_NUM_STAGES] = {};
+    // Stage timing: a ring of event pairs, one set per frame, so frames can
+    // be issued back to back; a set is folded into the totals when the ring
+    // comes round to it again (its frame is long done by then) or on collect.
+    static constexpr int kRing = 64;
+    hipEvent_t ev[kRing][BGS_NUM_STAGES][2] = {};
+    bool pending[kRing][BGS_NUM_STAGES] = {};
+    int slot = 0;
     double total_ms[BGS_NUM_STAGES] = {};
     int64_t count[BGS_NUM_STAGES] = {};
     std::string err;
@@ -237,10 +242,31 @@ int tile_bits(int64_t n_tiles) {
 }
 
 // Records the start (end = 0) or end (end = 1) of a stage when timing is on.
+// Fold one ring slot's finished stages into the totals.
+hipError_t drain_slot(bgs_ctx* ctx, int r) {
+    for (int i = 0; i < BGS_NUM_STAGES; ++i) {
+        if (!ctx->pending[r][i]) continue;
+        hipError_t e = hipEventSynchronize(ctx->ev[r][i][1]);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ctx->ev[r][i][0], ctx->ev[r][i][1]);
+        if (e != hipSuccess) return e;
+        ctx->total_ms[i] += ms;
+        ctx->count[i] += 1;
+        ctx->pending[r][i] = false;
+    }
+    return hipSuccess;
+}
+
+// Record a stage boundary.  A stage started again in the same slot begins
+// a new frame: move to the next slot, folding in what it still holds.
 void mark(bgs_ctx* ctx, int stage, int end) {
     if (!ctx->timing) return;
-    hipEventRecord(ctx->ev[stage][end], ctx->stream);
-    if (end) ctx->pending[stage] = true;
+    if (!end && ctx->pending[ctx->slot][stage]) {
+        ctx->slot = (ctx->slot + 1) % bgs_ctx::kRing;
+        drain_slot(ctx, ctx->slot);
+    }
+    hipEventRecord(ctx->ev[ctx->slot][stage][end], ctx->stream);
+    if (end) ctx->pending[ctx->slot][stage] = true;
 }
 
 void fill_stats(const DevStatus& h, bgs_stats* s) {
@@ -392,9 +418,10 @@ int32_t bgs_ctx_create(bgs_ctx** out, void* stream) {
 
 int32_t bgs_ctx_destroy(bgs_ctx* ctx) {
     if (!ctx) return BGS_OK;
-    for (int i = 0; i < BGS_NUM_STAGES; ++i)
-        for (int j = 0; j < 2; ++j)
-            if (ctx->ev[i][j]) hipEventDestroy(ctx->ev[i][j]);
+    for (int r = 0; r < bgs_ctx::kRing; ++r)
+        for (int i = 0; i < BGS_NUM_STAGES; ++i)
+            for (int j = 0; j < 2; ++j)
+                if (ctx->ev[r][i][j]) hipEventDestroy(ctx->ev[r][i][j]);
     delete ctx;
     return BGS_OK;
 }
@@ -435,16 +462,18 @@ int32_t bgs_ctx_set_blend_split(bgs_ctx* ctx, int32_t cap_dom, int32_t cap_roi, 
 int32_t bgs_ctx_set_timing(bgs_ctx* ctx, int32_t on) {
     if (!ctx) return BGS_ERR_INVALID_ARG;
     if (on) {
-        for (int i = 0; i < BGS_NUM_STAGES; ++i)
-            for (int j = 0; j < 2; ++j)
-                if (!ctx->ev[i][j]) {
-                    hipError_t e = hipEventCreate(&ctx->ev[i][j]);
-                    if (e != hipSuccess) return hip_fail(ctx, e, "event create");
-                }
+        for (int r = 0; r < bgs_ctx::kRing; ++r)
+            for (int i = 0; i < BGS_NUM_STAGES; ++i)
+                for (int j = 0; j < 2; ++j)
+                    if (!ctx->ev[r][i][j]) {
+                        hipError_t e = hipEventCreate(&ctx->ev[r][i][j]);
+                        if (e != hipSuccess) return hip_fail(ctx, e, "event create");
+                    }
     }
     ctx->timing = on ? 1 : 0;
+    ctx->slot = 0;
     for (int i = 0; i < BGS_NUM_STAGES; ++i) {
-        ctx->pending[i] = false;
+        for (int r = 0; r < bgs_ctx::kRing; ++r) ctx->pending[r][i] = false;
         ctx->total_ms[i] = 0.0;
         ctx->count[i] = 0;
     }
@@ -453,14 +482,9 @@ int32_t bgs_ctx_set_timing(bgs_ctx* ctx, int32_t on) {
 
 int32_t bgs_timing_collect(bgs_ctx* ctx, double* total_ms, int64_t* counts) {
     if (!ctx) return BGS_ERR_INVALID_ARG;
-    for (int i = 0; i < BGS_NUM_STAGES; ++i) {
-        if (!ctx->pending[i]) continue;
-        float ms = 0.f;
-        hipError_t e = hipEventElapsedTime(&ms, ctx->ev[i][0], ctx->ev[i][1]);
-        if (e != hipSuccess) return hip_fail(ctx, e, "event elapsed time (wait for the stream first)");
-        ctx->total_ms[i] += ms;
-        ctx->count[i] += 1;
-        ctx->pending[i] = false;
+    for (int k = 1; k <= bgs_ctx::kRing; ++k) {
+        const hipError_t e = drain_slot(ctx, (ctx->slot + k) % bgs_ctx::kRing);
+        if (e != hipSuccess) return hip_fail(ctx, e, "stage timing");
     }
     for (int i = 0; i < BGS_NUM_STAGES; ++i) {
         if (total_ms) total_ms[i] = ctx->total_ms[i];
