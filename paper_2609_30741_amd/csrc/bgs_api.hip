@@ -46,7 +46,7 @@ inline size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
     size_t status;
     size_t zbuf, hole, hole2, flags, bbox, pix_scan, pflag, pbox;
-    size_t ranges, mask32, mprefix, tlist, tile_scan, torder;
+    size_t ranges, colcum, mprefix, tlist, torder;
     size_t recs, zkeys, rects, counts, dkeys_b, dvals_a, dvals_b, offs, surf_scan;
     size_t tkeys_a, tkeys_b, tvals_a, tvals_b;
     size_t radix;
@@ -76,10 +76,9 @@ Layout make_layout(int64_t n, int64_t W, int64_t H, int64_t kc) {
     L.pflag = take(np);
     L.pbox = take(16 * np);
     L.ranges = take(8 * nt);
-    L.mask32 = take(4 * nt);
+    L.colcum = take(4 * (nt + (H + kTile - 1) / kTile));
     L.mprefix = take(4 * (nt + 1));
     L.tlist = take(4 * nt);
-    L.tile_scan = take(4 * scan_tmp_elems(nt));
     L.torder = take(4 * nt);
     L.recs = take(sizeof(SurfelRec) * n);
     L.zkeys = take(4 * n);
@@ -311,12 +310,13 @@ int raster_pass(bgs_ctx* ctx, const Layout& L, void* ws, int64_t kc, const bgs_s
     DevStatus* st = at<DevStatus>(ws, L.status);
     const int sb = which ? BGS_STAGE_PREPROCESS_ROI : BGS_STAGE_PREPROCESS_DOM;
     mark(ctx, sb + 0, 0);
-    MaskArgs mask{nullptr, 0};
+    MaskArgs mask{nullptr, nullptr, pc.tiles_x, 0};
     if (tile_mask) {
-        HIP_CHECK(launch_mask_prefix(tile_mask, n_tiles, at<uint32_t>(ws, L.mask32), at<uint32_t>(ws, L.mprefix),
-                                     at<uint32_t>(ws, L.tlist), at<uint32_t>(ws, L.tile_scan), st, s),
-                  "mask prefix");
+        HIP_CHECK(launch_mask_tables(tile_mask, n_tiles, pc.tiles_x, at<uint32_t>(ws, L.mprefix),
+                                     at<uint32_t>(ws, L.tlist), at<uint32_t>(ws, L.colcum), st, s),
+                  "mask tables");
         mask.prefix = at<uint32_t>(ws, L.mprefix);
+        mask.colcum = at<uint32_t>(ws, L.colcum);
         mask.enabled = 1;
     }
     SurfelRec* recs = at<SurfelRec>(ws, L.recs);

@@ -59,7 +59,9 @@ struct SceneArgs {
 // (n_tiles + 1 entries), so a tile's compact id is prefix[t] and the masked
 // tiles of row ty in columns [a, b] number prefix[ty*tx+b+1] - prefix[ty*tx+a].
 struct MaskArgs {
-    const uint32_t* prefix;
+    const uint32_t* prefix;  // masked tiles before each tile (n_tiles + 1)
+    const uint32_t* colcum;  // column sums of prefix over rows (tiles_y x (tiles_x + 1))
+    int tiles_x;
     int enabled;
 };
 
@@ -145,10 +147,11 @@ hipError_t launch_blend(const SurfelRec* recs, const uint32_t* vals, const uint2
                         const uint32_t* tile_list, const uint32_t* order, const uint32_t* n_live, int n_blocks,
                         const BlendArgs& a, const ContArgs& ca, float* rgb, float* d_or_z, float* alpha, uint8_t* cls,
                         unsigned long long* pair_counts, long long* trace, hipStream_t s);
-// prefix[n_tiles + 1] and the compact list of masked tile ids; tmp32 holds
-// n_tiles words, scan_tmp scan_tmp_elems(n_tiles) words.
-hipError_t launch_mask_prefix(const uint8_t* tile_mask, int n_tiles, uint32_t* tmp32, uint32_t* prefix,
-                              uint32_t* tile_list, uint32_t* scan_tmp, DevStatus* st, hipStream_t s);
+// Tables of an ROI tile mask (n_tiles = tiles_x * tiles_y): prefix[n_tiles +
+// 1], the compact list of masked tile ids, the masked count in DevStatus, and
+// colcum[tiles_y][tiles_x + 1], the column sums of prefix over rows.
+hipError_t launch_mask_tables(const uint8_t* tile_mask, int n_tiles, int tiles_x, uint32_t* prefix,
+                              uint32_t* tile_list, uint32_t* colcum, DevStatus* st, hipStream_t s);
 // Record the key count offs[n] of a binning (which: 0 dominant, 1 ROI).
 hipError_t launch_status_keys(const uint32_t* offs, int n, DevStatus* st, uint32_t cap, int which,
                               hipStream_t s);

@@ -52,13 +52,19 @@ __device__ inline void sh_basis(int deg, float x, float y, float z, float* Y) {
     Y[15] = -0.5900435899266435f * x * (xx - 3.f * yy);
 }
 
-__device__ inline uint32_t masked_count(const MaskArgs& m, int tiles_x, int tx0, int ty0, int tx1, int ty1) {
-    uint32_t c = 0;
-    for (int ty = ty0; ty <= ty1; ++ty) {
-        const uint32_t* row = m.prefix + (int64_t)ty * tiles_x;
-        c += row[tx1 + 1] - row[tx0];
-    }
-    return c;
+// Masked tiles of the rect's rows ty0..ty of columns tx0..tx1, from the
+// column sums of the mask prefix: colcum[ty][x] = sum over rows <= ty of
+// prefix[row * tiles_x + x].
+__device__ inline uint32_t masked_rows(const MaskArgs& m, int tx0, int ty0, int tx1, int ty) {
+    const int w = m.tiles_x + 1;
+    const uint32_t* c = m.colcum;
+    uint32_t s = c[(int64_t)ty * w + tx1 + 1] - c[(int64_t)ty * w + tx0];
+    if (ty0 > 0) s -= c[(int64_t)(ty0 - 1) * w + tx1 + 1] - c[(int64_t)(ty0 - 1) * w + tx0];
+    return s;
+}
+
+__device__ inline uint32_t masked_count(const MaskArgs& m, int tx0, int ty0, int tx1, int ty1) {
+    return masked_rows(m, tx0, ty0, tx1, ty1);
 }
 
 // ---------------------------------------------------------------------------
@@ -278,7 +284,7 @@ __global__ __launch_bounds__(256) void k_preprocess(SceneArgs sc, PreCam cam, fl
     const uint2 band = strip_band(bounded, c00, c01, c02, c11, c12, c22, cam, mux, muy,
                                   lowpass ? sqrt(lr) * (1.0 + 1e-5) : 0.0, xmin, xmax, ymin, ymax);
     const int tx0 = x0 / kTile, tx1 = x1 / kTile, ty0 = y0 / kTile, ty1 = y1 / kTile;
-    const uint32_t cnt = mask.enabled ? masked_count(mask, cam.tiles_x, tx0, ty0, tx1, ty1)
+    const uint32_t cnt = mask.enabled ? masked_count(mask, tx0, ty0, tx1, ty1)
                                       : (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
     counts[k] = cnt;
     rects[k] = make_uint2((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tx1 | ((uint32_t)ty1 << 16));
@@ -381,17 +387,17 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order
             const uint32_t w = (uint32_t)(tx1 - tx0 + 1);
             tile = (uint32_t)(ty0 + (int)(local / w)) * (uint32_t)tiles_x + (uint32_t)tx0 + local % w;
         } else {
-            tile = 0xFFFFFFFFu;
-            for (int ty = ty0; ty <= ty1; ++ty) {
-                const uint32_t* row = mask.prefix + (int64_t)ty * tiles_x;
-                const uint32_t first = row[tx0];
-                const uint32_t c = row[tx1 + 1] - first;
-                if (local < c) {
-                    tile = first + local;  // compact id: masked tiles before it
-                    break;
-                }
-                local -= c;
+            // The row holding the local-th masked tile of the rect: the first
+            // row whose cumulative masked count exceeds local.
+            int lo = ty0, hi = ty1;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (masked_rows(mask, tx0, ty0, tx1, mid) > local) hi = mid;
+                else lo = mid + 1;
             }
+            const uint32_t before = lo > ty0 ? masked_rows(mask, tx0, ty0, tx1, lo - 1) : 0u;
+            // Compact id: the masked tiles before it in row-major order.
+            tile = mask.prefix[(int64_t)lo * tiles_x + tx0] + (local - before);
         }
         const uint32_t g = base + p;
         if (g < cap) {
@@ -435,19 +441,63 @@ __global__ void k_status_keys(const uint32_t* __restrict__ offs, int n, DevStatu
     else st->n_keys_roi = K;
 }
 
-__global__ __launch_bounds__(256) void k_mask_u32(const uint8_t* __restrict__ m, int n, uint32_t* __restrict__ o) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i < n) o[i] = m[i] ? 1u : 0u;
-}
-
-__global__ __launch_bounds__(256) void k_mask_list(const uint8_t* __restrict__ m, int n,
-                                                   const uint32_t* __restrict__ prefix, uint32_t* __restrict__ list,
-                                                   DevStatus* st) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i < n && m[i]) list[prefix[i]] = (uint32_t)i;
-    if (i == 0) {
-        st->n_masked = prefix[n];
-        st->n_roi_tiles = prefix[n];
+// Tables of an ROI tile mask, one workgroup: prefix[t] = masked tiles before
+// tile t (t = 0..n_tiles), the compact list of masked tile ids, their count,
+// and colcum[ty][x] = sum over rows <= ty of prefix[row * tiles_x + x] for
+// x = 0..tiles_x, from which any rect's masked count takes four loads.
+__global__ __launch_bounds__(1024) void k_mask_tables(const uint8_t* __restrict__ m, int n_tiles, int tiles_x,
+                                                      uint32_t* __restrict__ prefix, uint32_t* __restrict__ list,
+                                                      uint32_t* __restrict__ colcum, DevStatus* st) {
+    __shared__ uint32_t wsum[16];
+    __shared__ uint32_t s_run;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) s_run = 0;
+    __syncthreads();
+    for (int base = 0; base < n_tiles; base += 1024 * 4) {
+        uint32_t v[4], sum = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int t = base + tid * 4 + j;
+            v[j] = (t < n_tiles && m[t]) ? 1u : 0u;
+            sum += v[j];
+        }
+        uint32_t x = sum;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wsum[wave] = x;
+        __syncthreads();
+        uint32_t acc = s_run;
+        for (int w = 0; w < wave; ++w) acc += wsum[w];
+        acc += x - sum;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int t = base + tid * 4 + j;
+            if (t < n_tiles) {
+                prefix[t] = acc;
+                if (v[j]) list[acc] = (uint32_t)t;
+            }
+            acc += v[j];
+        }
+        __syncthreads();
+        if (tid == 1023) s_run = acc;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        prefix[n_tiles] = s_run;
+        st->n_masked = s_run;
+        st->n_roi_tiles = s_run;
+    }
+    __syncthreads();  // prefix is read back below by other threads of this block
+    const int tiles_y = n_tiles / tiles_x;
+    for (int xc = tid; xc <= tiles_x; xc += 1024) {
+        uint32_t acc = 0;
+        for (int ty = 0; ty < tiles_y; ++ty) {
+            acc += prefix[ty * tiles_x + xc];
+            colcum[(int64_t)ty * (tiles_x + 1) + xc] = acc;
+        }
     }
 }
 
@@ -1093,13 +1143,10 @@ hipError_t launch_blend(const SurfelRec* recs, const uint32_t* vals, const uint2
     return hipGetLastError();
 }
 
-hipError_t launch_mask_prefix(const uint8_t* tile_mask, int n_tiles, uint32_t* tmp32, uint32_t* prefix,
-                              uint32_t* tile_list, uint32_t* scan_tmp, DevStatus* st, hipStream_t s) {
-    const unsigned g = (unsigned)((n_tiles + 255) / 256);
-    hipLaunchKernelGGL(k_mask_u32, dim3(g), dim3(256), 0, s, tile_mask, n_tiles, tmp32);
-    hipError_t e = exclusive_scan(tmp32, nullptr, prefix, nullptr, n_tiles, scan_tmp, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_mask_list, dim3(g), dim3(256), 0, s, tile_mask, n_tiles, prefix, tile_list, st);
+hipError_t launch_mask_tables(const uint8_t* tile_mask, int n_tiles, int tiles_x, uint32_t* prefix,
+                              uint32_t* tile_list, uint32_t* colcum, DevStatus* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_mask_tables, dim3(1), dim3(1024), 0, s, tile_mask, n_tiles, tiles_x, prefix, tile_list,
+                       colcum, st);
     return hipGetLastError();
 }
 
