@@ -441,6 +441,8 @@ __global__ void k_status_keys(const uint32_t* __restrict__ offs, int n, DevStatu
     else st->n_keys_roi = K;
 }
 
+constexpr int kMaskLds = 15360;  // tile-mask prefix words staged in LDS (60 KiB)
+
 // Tables of an ROI tile mask, one workgroup: prefix[t] = masked tiles before
 // tile t (t = 0..n_tiles), the compact list of masked tile ids, their count,
 // and colcum[ty][x] = sum over rows <= ty of prefix[row * tiles_x + x] for
@@ -450,6 +452,7 @@ __global__ __launch_bounds__(1024) void k_mask_tables(const uint8_t* __restrict_
                                                       uint32_t* __restrict__ colcum, DevStatus* st) {
     __shared__ uint32_t wsum[16];
     __shared__ uint32_t s_run;
+    __shared__ uint32_t s_pre[kMaskLds];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (tid == 0) s_run = 0;
     __syncthreads();
@@ -491,11 +494,18 @@ __global__ __launch_bounds__(1024) void k_mask_tables(const uint8_t* __restrict_
         st->n_roi_tiles = s_run;
     }
     __syncthreads();  // prefix is read back below by other threads of this block
+    // Column sums, a column per thread; the prefix is staged in LDS when it
+    // fits so that the walk down a column reads LDS.
     const int tiles_y = n_tiles / tiles_x;
+    const bool staged = n_tiles + 1 <= kMaskLds;
+    if (staged) {
+        for (int t = tid; t <= n_tiles; t += 1024) s_pre[t] = prefix[t];
+        __syncthreads();
+    }
     for (int xc = tid; xc <= tiles_x; xc += 1024) {
         uint32_t acc = 0;
         for (int ty = 0; ty < tiles_y; ++ty) {
-            acc += prefix[ty * tiles_x + xc];
+            acc += staged ? s_pre[ty * tiles_x + xc] : prefix[ty * tiles_x + xc];
             colcum[(int64_t)ty * (tiles_x + 1) + xc] = acc;
         }
     }

@@ -461,6 +461,111 @@ __global__ __launch_bounds__(256) void k_gap_pass(int W, int H, int pass, float*
     if (threadIdx.x == 0 && filled) atomicAdd(&st->n_gap, filled);
 }
 
+// The same gap passes and the center mask in one kernel: a block loads its
+// 64 x kBandRows tile plus a halo of `passes` pixels into LDS, runs the
+// passes there (pass j is final for pixels at least j from the halo's
+// edge, which after all passes is the tile), and writes the tile's filled
+// pixels, tags and center mask.  Per pixel it computes exactly what
+// k_tag_init, k_gap_pass and k_center_mask compute.
+constexpr int kGapMaxHalo = 4;
+constexpr int kGapRW = 64 + 2 * kGapMaxHalo, kGapRH = kBandRows + 2 * kGapMaxHalo;
+
+__global__ __launch_bounds__(256) void k_gap_fill(int W, int H, int passes, float* __restrict__ rgb,
+                                                  float* __restrict__ z, float* __restrict__ alpha,
+                                                  uint8_t* __restrict__ tag_out, uint8_t* __restrict__ cls,
+                                                  uint8_t* __restrict__ center, DevStatus* st) {
+    __shared__ float s_c[3][kGapRH * kGapRW];
+    __shared__ float s_a[kGapRH * kGapRW], s_z[kGapRH * kGapRW];
+    __shared__ uint8_t s_tag[kGapRH * kGapRW];
+    __shared__ uint8_t s_fix[kGapRH * kGapRW];  // 1: outside the image, 2: hole inside an edge ROI
+    __shared__ uint32_t s4[4];
+    const int64_t n = (int64_t)W * H;
+    const int h = passes;
+    const int rw = 64 + 2 * h, rh = kBandRows + 2 * h;
+    const int x0 = blockIdx.x * 64 - h, y0 = blockIdx.y * kBandRows - h;
+    for (int i = threadIdx.x; i < rw * rh; i += 256) {
+        const int lx = i % rw, ly = i / rw, x = x0 + lx, y = y0 + ly;
+        const int li = ly * kGapRW + lx;
+        if (x < 0 || y < 0 || x >= W || y >= H) {
+            s_tag[li] = 255;
+            s_fix[li] = 1;
+            continue;
+        }
+        const int64_t p = (int64_t)y * W + x;
+        const bool hole = cls[p] != 0;
+        s_tag[li] = hole ? 255 : 0;
+        s_fix[li] = (hole && in_edge(st, x, y)) ? 2 : 0;
+        s_c[0][li] = rgb[p];
+        s_c[1][li] = rgb[n + p];
+        s_c[2][li] = rgb[2 * n + p];
+        s_a[li] = alpha[p];
+        s_z[li] = z[p];
+    }
+    __syncthreads();
+    for (int pass = 1; pass <= passes; ++pass) {
+        const int m = pass;  // pixels at least `pass` from the region's edge
+        const int cw = rw - 2 * m, ch = rh - 2 * m;
+        for (int i = threadIdx.x; i < cw * ch; i += 256) {
+            const int lx = m + i % cw, ly = m + i / cw;
+            const int li = ly * kGapRW + lx;
+            if (s_tag[li] != 255 || s_fix[li] != 0) continue;
+            const int NX[8] = {-1, 0, 1, -1, 1, -1, 0, 1};
+            const int NY[8] = {-1, -1, -1, 0, 0, 1, 1, 1};
+            int cnt = 0;
+            float s0 = 0.f, s1 = 0.f, s2 = 0.f, sa = 0.f, zm = -INFINITY;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int r = (ly + NY[q]) * kGapRW + lx + NX[q];
+                if (s_fix[r] == 1 || (int)s_tag[r] >= pass) continue;  // outside, a hole, or filled in this pass
+                s0 = s0 + s_c[0][r];
+                s1 = s1 + s_c[1][r];
+                s2 = s2 + s_c[2][r];
+                sa = sa + s_a[r];
+                const float zr = s_z[r];
+                if (zr > zm) zm = zr;
+                ++cnt;
+            }
+            if (cnt > 0) {
+                const float fc = (float)cnt;
+                s_c[0][li] = s0 / fc;
+                s_c[1][li] = s1 / fc;
+                s_c[2][li] = s2 / fc;
+                s_a[li] = sa / fc;
+                s_z[li] = zm;
+                s_tag[li] = (uint8_t)pass;
+            }
+        }
+        __syncthreads();
+    }
+    uint32_t filled = 0, centers = 0;
+    for (int i = threadIdx.x; i < 64 * kBandRows; i += 256) {
+        const int lx = h + (i & 63), ly = h + (i >> 6), x = x0 + lx, y = y0 + ly;
+        if (x >= W || y >= H) continue;
+        const int li = ly * kGapRW + lx;
+        const int64_t p = (int64_t)y * W + x;
+        const uint8_t t = s_tag[li];
+        tag_out[p] = t;
+        if (t != 0 && t != 255) {
+            rgb[p] = s_c[0][li];
+            rgb[n + p] = s_c[1][li];
+            rgb[2 * n + p] = s_c[2][li];
+            alpha[p] = s_a[li];
+            z[p] = s_z[li];
+            cls[p] = (uint8_t)BGS_CLS_GAP;
+            ++filled;
+        }
+        const uint32_t c = (t == 255 && s_fix[li] == 0) ? 1u : 0u;
+        center[p] = (uint8_t)c;
+        centers += c;
+    }
+    filled = block_sum_u32(filled, s4);
+    centers = block_sum_u32(centers, s4);
+    if (threadIdx.x == 0) {
+        if (filled) atomicAdd(&st->n_gap, filled);
+        if (centers) atomicAdd(&st->n_center, centers);
+    }
+}
+
 // Holes left after interpolation and outside the edge ROIs.
 __global__ __launch_bounds__(256) void k_center_mask(int W, int H, const uint8_t* __restrict__ tag,
                                                      uint8_t* __restrict__ center, DevStatus* st) {
@@ -863,11 +968,16 @@ hipError_t launch_classify(const WarpCam& src, const WarpCam& dst, const RelPose
     hipLaunchKernelGGL(k_edge_rois, dim3(1), dim3(256), 0, s, src, dst, P, roi.edge_samples, roi.margin, T,
                        depth_range, st, boxes, box_cap);
     uint8_t* tag = b.hole;
-    hipLaunchKernelGGL(k_tag_init, dim3(grid(n)), dim3(256), 0, s, n, cls, tag);
-    for (int pass = 1; pass <= roi.gap_passes; ++pass)
-        hipLaunchKernelGGL(k_gap_pass, band_grid(W, H), dim3(256), 0, s, W, H, pass, rgb, z, alpha, tag, cls, st);
     uint8_t* center = b.hole2;
-    hipLaunchKernelGGL(k_center_mask, band_grid(W, H), dim3(256), 0, s, W, H, tag, center, st);
+    if (roi.gap_passes <= kGapMaxHalo) {
+        hipLaunchKernelGGL(k_gap_fill, band_grid(W, H), dim3(256), 0, s, W, H, roi.gap_passes, rgb, z, alpha, tag, cls,
+                           center, st);
+    } else {
+        hipLaunchKernelGGL(k_tag_init, dim3(grid(n)), dim3(256), 0, s, n, cls, tag);
+        for (int pass = 1; pass <= roi.gap_passes; ++pass)
+            hipLaunchKernelGGL(k_gap_pass, band_grid(W, H), dim3(256), 0, s, W, H, pass, rgb, z, alpha, tag, cls, st);
+        hipLaunchKernelGGL(k_center_mask, band_grid(W, H), dim3(256), 0, s, W, H, tag, center, st);
+    }
     hipLaunchKernelGGL(k_tile_mask_edges, dim3(grid((int64_t)tiles_x * tiles_y)), dim3(256), 0, s, tiles_x, tiles_y, T,
                        st, tile_mask);
     if (roi.center_roi) {
