@@ -40,6 +40,10 @@ WORKLOAD_TEXT = {
 # Published MI355X peaks.
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
+# HBM bytes of one sphere800 dominant-eye blend stage (capped walk, two
+# segment rounds, fix-up), FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (factors from a
+# 512 MiB copy), valid for the blend source with this sha1.
+BLEND_TRAFFIC = {"raster_sha1": "a139c6420217b734b94efd42d30475393c738da9", "bytes": 187.7e6}
 # fp32 operations of one evaluated (pixel, surfel) pair in the blend and the
 # extra ones of a contributing pair (an FMA counts as two).
 FLOPS_EVAL = 31
@@ -64,6 +68,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="budget of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="no timing: a 512 MiB copy (counter calibration), then 12 dominant-eye renders of the "
+                         "workload, for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -79,6 +86,10 @@ def main():
         sys.exit(3)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+
+    if args.traffic_probe:
+        traffic_probe(args)
+        return
 
     t0 = time.time()
     scene, cams, baseline = synth.WORKLOADS[args.workload](args.seed)
@@ -192,7 +203,7 @@ def main():
     dominant = max(stage_ms, key=lambda k: stage_ms[k])
     roofline = {"kernel": "k_blend (dominant eye)", "bound": "alu", "achieved": round(achieved, 3),
                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                "traffic": None, "avg_launch_ms": round(blend_ms, 4),
+                "traffic": blend_traffic() if args.workload == "sphere800" else None, "avg_launch_ms": round(blend_ms, 4),
                 "pairs_evaluated_per_launch": int(np.mean(pe_dom)),
                 "pairs_contributing_per_launch": int(np.mean(pu_dom)),
                 "records_walked_per_launch": int(wd[0]), "records_tested_per_launch": int(wd[1]),
@@ -250,6 +261,45 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(result), flush=True)
+
+
+def traffic_probe(args):
+    """Kernels for HBM counter runs: three copies of a 512 MiB fp32 tensor
+    (reads and writes of known size, to calibrate FETCH_SIZE/WRITE_SIZE), then
+    12 dominant-eye renders of the workload with the library's default blend
+    schedule."""
+    import torch
+    from paper_2609_30741_amd import api, synth
+
+    a = torch.empty(128 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    scene, cams, _ = synth.WORKLOADS[args.workload](args.seed)
+    ds = api.DeviceScene(scene)
+    ctx = api.Context(sync=True)
+    for c in cams[:4]:
+        ctx.render_dominant(ds, c)
+    ctx.set_sync(False)
+    for c in cams[:8]:
+        ctx.render_dominant(ds, c)
+    torch.cuda.synchronize()
+    log("traffic probe done")
+
+
+def blend_traffic():
+    """HBM bytes per dominant-eye blend stage (all its launches) of the bench
+    workload, from calibrated FETCH_SIZE and WRITE_SIZE counter runs of
+    `bench.py --traffic-probe`; None when the blend source has changed since
+    the counters were taken."""
+    import hashlib
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2609_30741_amd", "csrc", "raster.hip")
+    with open(src, "rb") as f:
+        h = hashlib.sha1(f.read()).hexdigest()
+    return BLEND_TRAFFIC["bytes"] if h == BLEND_TRAFFIC["raster_sha1"] else None
 
 
 def cpu_baseline(args, scene, cam_dom, cam_aff, roi_px):
