@@ -177,7 +177,10 @@ BGS_API int32_t bgs_ctx_set_blend_split(bgs_ctx* ctx, int32_t cap_dom, int32_t c
                                         int32_t far_dom, int32_t far_roi);
 
 /* Per-stage GPU timing with HIP events recorded on the context's stream
- * around each stage's launches.  on = 1 enables it and clears the totals.
+ * around each stage's launches.  stages is a bit mask over enum bgs_stage
+ * (bit i times stage i; -1 times every stage; 0 turns timing off); every
+ * call clears the totals.  Each timed stage adds two event records to the
+ * stream, so time only the stages you need where the frame rate matters.
  * Frames may be issued back to back: the events of the last 64 frames are
  * kept, and older ones are folded into the totals as new frames start (a
  * frame 64 frames old has long finished).  bgs_timing_collect() waits for
@@ -189,7 +192,7 @@ enum bgs_stage {
     BGS_STAGE_PREPROCESS_ROI, BGS_STAGE_DEPTH_SORT_ROI, BGS_STAGE_EMIT_ROI, BGS_STAGE_TILE_SORT_ROI,
     BGS_STAGE_RANGES_ROI, BGS_STAGE_BLEND_ROI, BGS_NUM_STAGES
 };
-BGS_API int32_t bgs_ctx_set_timing(bgs_ctx* ctx, int32_t on);
+BGS_API int32_t bgs_ctx_set_timing(bgs_ctx* ctx, int32_t stages);
 BGS_API int32_t bgs_timing_collect(bgs_ctx* ctx, double* total_ms, int64_t* counts);
 
 /* Workspace bytes for scenes of up to n surfels, images of up to

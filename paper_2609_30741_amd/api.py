@@ -142,9 +142,14 @@ class Context:
         self._check(self.L.bgs_ctx_set_blend_split(self.h, int(cap_dom), int(cap_roi), int(seg_len), int(far_dom),
                                                    int(far_roi)))
 
-    def set_timing(self, on: bool):
-        """Enable per-stage HIP-event timing on this context's stream (clears totals)."""
-        self._check(self.L.bgs_ctx_set_timing(self.h, int(bool(on))))
+    def set_timing(self, on, stages=None):
+        """Per-stage HIP-event timing on this context's stream (clears the
+        totals).  on: True times every stage, False none; stages: names from
+        _abi.STAGES to time instead of all of them."""
+        mask = 0
+        if on:
+            mask = -1 if stages is None else sum(1 << _abi.STAGES.index(n) for n in stages)
+        self._check(self.L.bgs_ctx_set_timing(self.h, mask))
 
     def timing_collect(self):
         """Accumulate the stages recorded since the last call (the stream must

@@ -14,7 +14,7 @@ struct bgs_ctx {
     hipStream_t stream = nullptr;
     int sync = 1;
     int count_pairs = 0;
-    int timing = 0;
+    uint32_t timing = 0;  // bit i: time stage i
     // Blend continuation: records a tile composites before the rest of its
     // list is split into segments (0: never), per pass, and the segment length.
     uint32_t cap_dom = 1024, cap_roi = 128, seg_len = 192, far_dom = 0, far_roi = 768;
@@ -45,7 +45,7 @@ inline size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 // is whatever the remaining bytes hold.
 struct Layout {
     size_t status;
-    size_t zbuf, hole, hole2, flags, bbox, pix_scan, pflag, pbox;
+    size_t zbuf, hole, hole2, bcount, rmask, bbox, pflag, pbox, wpart, gpart;
     size_t ranges, colcum, mprefix, tlist, torder;
     size_t recs, zkeys, rects, counts, dkeys_b, dvals_a, dvals_b, offs, surf_scan;
     size_t tkeys_a, tkeys_b, tvals_a, tvals_b;
@@ -70,11 +70,14 @@ Layout make_layout(int64_t n, int64_t W, int64_t H, int64_t kc) {
     L.zbuf = take(8 * np);
     L.hole = take(np);
     L.hole2 = take(np);
-    L.flags = take(4 * (np + 1));
-    L.bbox = take(16 * np);
-    L.pix_scan = take(4 * scan_tmp_elems(np));
+    const int64_t nb = (np + 255) / 256;  // 256-pixel blocks of the component labelling
+    L.bcount = take(4 * (nb + 1));
+    L.rmask = take(32 * nb);
+    L.bbox = take(16 * np);  // 8 words per component; at most np / 2 components
     L.pflag = take(np);
     L.pbox = take(16 * np);
+    L.wpart = take(16 * H);                                   // one per row
+    L.gpart = take(8 * ((W + 63) / 64) * ((H + 15) / 16));   // one per gap-fill block
     L.ranges = take(8 * nt);
     L.colcum = take(4 * (nt + (H + kTile - 1) / kTile));
     L.mprefix = take(4 * (nt + 1));
@@ -259,7 +262,7 @@ hipError_t drain_slot(bgs_ctx* ctx, int r) {
 // Record a stage boundary.  A stage started again in the same slot begins
 // a new frame: move to the next slot, folding in what it still holds.
 void mark(bgs_ctx* ctx, int stage, int end) {
-    if (!ctx->timing) return;
+    if (!((ctx->timing >> stage) & 1u)) return;
     if (!end && ctx->pending[ctx->slot][stage]) {
         ctx->slot = (ctx->slot + 1) % bgs_ctx::kRing;
         drain_slot(ctx, ctx->slot);
@@ -470,7 +473,7 @@ int32_t bgs_ctx_set_timing(bgs_ctx* ctx, int32_t on) {
                         if (e != hipSuccess) return hip_fail(ctx, e, "event create");
                     }
     }
-    ctx->timing = on ? 1 : 0;
+    ctx->timing = on == -1 ? ((1u << BGS_NUM_STAGES) - 1u) : ((uint32_t)on & ((1u << BGS_NUM_STAGES) - 1u));
     ctx->slot = 0;
     for (int i = 0; i < BGS_NUM_STAGES; ++i) {
         for (int r = 0; r < bgs_ctx::kRing; ++r) ctx->pending[r][i] = false;
@@ -556,7 +559,7 @@ int32_t bgs_reproject(bgs_ctx* ctx, const bgs_camera* src, const bgs_camera* dst
     DevStatus* st = at<DevStatus>(ws, L.status);
     HIP_CHECK(launch_reproject(make_warpcam(*src), make_warpcam(*dst), rel_pose(*src, *dst), roi->a_min, rgb_src,
                                depth_raw_src, alpha_src, at<unsigned long long>(ws, L.zbuf), rgb_dst, z_dst, alpha_dst,
-                               hole_mask, depth_range, st, ctx->stream),
+                               hole_mask, depth_range, true, at<uint4>(ws, L.wpart), st, ctx->stream),
               "reproject");
     return BGS_OK;
 }
@@ -575,9 +578,9 @@ int32_t bgs_classify_holes(bgs_ctx* ctx, const bgs_camera* src, const bgs_camera
         return fail(ctx, BGS_ERR_INVALID_ARG, "null buffer or negative box capacity");
     const Layout L = make_layout(0, dst->width, dst->height, 0);
     if (L.total > ws_bytes) return fail(ctx, BGS_ERR_WORKSPACE, "workspace of %zu bytes is too small", ws_bytes);
-    ClassifyBufs b{at<uint8_t>(ws, L.hole), at<uint8_t>(ws, L.hole2), at<uint32_t>(ws, L.flags),
-                   at<int32_t>(ws, L.bbox), at<uint32_t>(ws, L.pix_scan), at<uint8_t>(ws, L.pflag),
-                   at<int4>(ws, L.pbox)};
+    ClassifyBufs b{at<uint8_t>(ws, L.hole), at<uint8_t>(ws, L.hole2), at<uint32_t>(ws, L.bcount),
+                   at<uint32_t>(ws, L.rmask), at<int32_t>(ws, L.bbox), at<uint8_t>(ws, L.pflag),
+                   at<int4>(ws, L.pbox), at<uint4>(ws, L.wpart), at<uint2>(ws, L.gpart)};
     HIP_CHECK(launch_classify(make_warpcam(*src), make_warpcam(*dst), rel_pose(*src, *dst), *roi, raster->bg,
                               depth_range, rgb_dst, z_dst, alpha_dst, cls, labels, boxes, box_capacity, n_boxes,
                               tile_mask, b, at<DevStatus>(ws, L.status), ctx->stream),
@@ -648,18 +651,21 @@ int32_t bgs_render_stereo(bgs_ctx* ctx, const bgs_scene* scene, const bgs_camera
     // Stage 2: reprojection.  The hole mask is written straight into cls.
     const WarpCam wd = make_warpcam(*cam_dom), wa = make_warpcam(*cam_aff);
     const RelPose P = rel_pose(*cam_dom, *cam_aff);
-    float* depth_range = reinterpret_cast<float*>(&st->pad2[0]);
+    // The status block was zeroed at the start of the frame, so the
+    // reprojection needs no reset, and classification reads the depth range
+    // straight from it.
     mark(ctx, BGS_STAGE_REPROJECT, 0);
     HIP_CHECK(launch_reproject(wd, wa, P, roi->a_min, rgb_dom, depth_raw_dom, alpha_dom,
-                               at<unsigned long long>(ws, L.zbuf), rgb_aff, z_aff, alpha_aff, cls_aff, depth_range, st, s),
+                               at<unsigned long long>(ws, L.zbuf), rgb_aff, z_aff, alpha_aff, cls_aff, nullptr, false,
+                               at<uint4>(ws, L.wpart), st, s),
               "reproject");
     mark(ctx, BGS_STAGE_REPROJECT, 1);
     // Stage 3: hole classification and interpolation.
-    ClassifyBufs b{at<uint8_t>(ws, L.hole), at<uint8_t>(ws, L.hole2), at<uint32_t>(ws, L.flags),
-                   at<int32_t>(ws, L.bbox), at<uint32_t>(ws, L.pix_scan), at<uint8_t>(ws, L.pflag),
-                   at<int4>(ws, L.pbox)};
+    ClassifyBufs b{at<uint8_t>(ws, L.hole), at<uint8_t>(ws, L.hole2), at<uint32_t>(ws, L.bcount),
+                   at<uint32_t>(ws, L.rmask), at<int32_t>(ws, L.bbox), at<uint8_t>(ws, L.pflag),
+                   at<int4>(ws, L.pbox), at<uint4>(ws, L.wpart), at<uint2>(ws, L.gpart)};
     mark(ctx, BGS_STAGE_CLASSIFY, 0);
-    HIP_CHECK(launch_classify(wd, wa, P, *roi, raster->bg, depth_range, rgb_aff, z_aff, alpha_aff, cls_aff, labels, boxes,
+    HIP_CHECK(launch_classify(wd, wa, P, *roi, raster->bg, nullptr, rgb_aff, z_aff, alpha_aff, cls_aff, labels, boxes,
                               box_capacity, n_boxes, tile_mask, b, st, s),
               "classify");
     mark(ctx, BGS_STAGE_CLASSIFY, 1);

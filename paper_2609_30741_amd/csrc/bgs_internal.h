@@ -101,7 +101,9 @@ struct DevStatus {
     uint32_t n_keys_roi;
     uint32_t overflow;     // bit 0 key capacity, bit 1 box capacity
     uint32_t n_holes, n_gap, n_center, n_rowfill, n_boxes, n_roi_tiles, n_edge, pad;
-    uint32_t dmin_bits, dmax_bits;  // depth-range reduction (positive fp32 bits)
+    // Depth-range reduction over positive fp32 bits: the complement of the
+    // minimum (so that a zeroed block means "none yet") and the maximum.
+    uint32_t dmin_inv, dmax_bits;
     uint32_t pad2[2];
     uint32_t n_slots, n_items;  // blend continuation of the current pass
     // Counting mode only, dominant then ROI pass, 6 each: evaluated pairs,
@@ -166,19 +168,31 @@ struct RelPose {
 };
 RelPose rel_pose(const bgs_camera& src, const bgs_camera& dst);
 
+// Per-block partials the reprojection leaves in wpart (row-preserving form:
+// one per row; the scatter form reduces with atomics and leaves none).
+int warp_parts(const WarpCam& src, const WarpCam& dst, const RelPose& P);
+// reset: clear the status fields the reprojection and classification
+// accumulate (not needed when the whole status block was zeroed);
+// depth_range (optional): fold the partials into the status block and
+// write the covered depth-proxy range there; without it the classification
+// that follows folds them.
 hipError_t launch_reproject(const WarpCam& src, const WarpCam& dst, const RelPose& P, float a_min,
                             const float* rgb, const float* draw, const float* alpha, unsigned long long* zbuf,
                             float* rgb_dst, float* z_dst, float* alpha_dst, uint8_t* hole, float* depth_range,
-                            DevStatus* st, hipStream_t s);
+                            bool reset, uint4* wpart, DevStatus* st, hipStream_t s);
 struct ClassifyBufs {
     uint8_t* hole;     // interpolation tags
     uint8_t* hole2;    // center-hole mask
-    uint32_t* flags;   // root flags -> slots (exclusive scan), n + 1
-    int32_t* bbox;     // 4 per component
-    uint32_t* scan_tmp;
+    uint32_t* bcount;  // component roots per 256-pixel block, then their exclusive scan
+    uint32_t* rmask;   // per 256-pixel block: bit mask of its component roots (8 words)
+    int32_t* bbox;     // per component: box (4) and root pixel (1), 8 words
     uint8_t* pflag;    // block-local piece roots
     int4* pbox;        // piece boxes, indexed by root pixel
+    uint4* wpart;      // reprojection partials (warp_parts entries)
+    uint2* gpart;      // gap-fill partials, one per gap-fill block
 };
+// depth_range null: take the range from the reprojection just run (its
+// partials in b.wpart and its status fields).
 hipError_t launch_classify(const WarpCam& src, const WarpCam& dst, const RelPose& P, const bgs_roi_params& roi,
                            const float bg[3], const float* depth_range, float* rgb, float* z, float* alpha,
                            uint8_t* cls, int32_t* labels, bgs_box* boxes, int32_t box_cap, int32_t* n_boxes,

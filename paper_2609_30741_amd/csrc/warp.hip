@@ -6,6 +6,7 @@
 // evaluated operation by operation in a fixed order, so that their integer
 // outcomes (target pixels, hole masks, widths, labels, boxes) are exactly
 // reproducible.
+#include <algorithm>
 #include <cfloat>
 #include <climits>
 
@@ -111,7 +112,7 @@ __global__ void k_warp_reset(DevStatus* st) {
     st->n_rowfill = 0;
     st->n_boxes = 0;
     st->n_edge = 0;
-    st->dmin_bits = 0xFFFFFFFFu;
+    st->dmin_inv = 0u;
     st->dmax_bits = 0u;
     st->overflow &= ~2u;
 }
@@ -121,21 +122,21 @@ __global__ __launch_bounds__(256) void k_fill_u64(unsigned long long* p, int64_t
     if (i < n) p[i] = v;
 }
 
-// Where source pixel s lands: the fixed-order fp64 recipe of Eq. 4-5.
-// Returns false when it lands nowhere; *df gets the fp32 depth proxy of a
-// covered source pixel (else stays untouched).
-__device__ inline bool splat_target(const WarpCam& src, const WarpCam& dst, const RelPose& P, float a_min,
-                                    const float* __restrict__ draw, const float* __restrict__ alpha, int i, int j,
-                                    int64_t* fu_out, int64_t* fv_out, unsigned long long* key, float* df_out) {
+// Where source pixel (i, j) with alpha A and raw depth Dr lands: the
+// fixed-order fp64 recipe of Eq. 4-5.  Returns false when it lands nowhere;
+// *df gets the fp32 depth proxy of a covered source pixel (else stays
+// untouched).
+__device__ inline bool splat_target_v(const WarpCam& src, const WarpCam& dst, const RelPose& P, float a_min, float A,
+                                      float Dr, int i, int j, int64_t* fu_out, int64_t* fv_out,
+                                      unsigned long long* key, float* df_out) {
     const int64_t s = (int64_t)j * src.W + i;
     const double xn = ((double)i - src.cx) / src.fx;
     const double yn = ((double)j - src.cy) / src.fy;
-    const float A = alpha[s];
     double Xp[3];
     bool ok;
     float zf;
     if (A >= a_min) {
-        const float df = draw[s] / A;
+        const float df = Dr / A;
         *df_out = df;
         const double d = (double)df;
         map_point(P, true, d * xn, d * yn, d, Xp);
@@ -155,6 +156,12 @@ __device__ inline bool splat_target(const WarpCam& src, const WarpCam& dst, cons
     *fv_out = (int64_t)fv;
     *key = ((unsigned long long)__float_as_uint(zf) << 32) | (unsigned long long)(uint32_t)s;
     return true;
+}
+__device__ inline bool splat_target(const WarpCam& src, const WarpCam& dst, const RelPose& P, float a_min,
+                                    const float* __restrict__ draw, const float* __restrict__ alpha, int i, int j,
+                                    int64_t* fu_out, int64_t* fv_out, unsigned long long* key, float* df_out) {
+    const int64_t s = (int64_t)j * src.W + i;
+    return splat_target_v(src, dst, P, a_min, alpha[s], draw[s], i, j, fu_out, fv_out, key, df_out);
 }
 
 // Forward splat of every source pixel into the destination z-buffer.
@@ -181,7 +188,7 @@ __global__ __launch_bounds__(256) void k_reproject_scatter(WarpCam src, WarpCam 
     dmin = block_min_u32(dmin, s4);
     dmax = block_max_u32(dmax, s4);
     if (threadIdx.x == 0) {
-        if (dmin != 0xFFFFFFFFu) atomicMin(&st->dmin_bits, dmin);
+        if (dmin != 0xFFFFFFFFu) atomicMax(&st->dmin_inv, ~dmin);
         if (dmax != 0u) atomicMax(&st->dmax_bits, dmax);
     }
 }
@@ -214,47 +221,122 @@ __device__ inline uint32_t resolve_pixel(unsigned long long key, int64_t t, int6
 // source row, as for a rig that keeps the orientation and moves along x):
 // one block per row, the row's z-buffer in LDS (64-bit LDS atomicMin), the
 // z-test and the resolve in one kernel.  Same recipe, same result as the
-// scatter/resolve pair.
+// scatter/resolve pair.  Each thread takes kRowPix pixels of a chunk and
+// issues all of their loads before any arithmetic, so the row's memory
+// latency is paid once per chunk rather than once per pixel.
+constexpr int kRowPix = 4;
 __global__ __launch_bounds__(256) void k_reproject_rows(WarpCam src, WarpCam dst, RelPose P, float a_min,
                                                         const float* __restrict__ draw,
                                                         const float* __restrict__ alpha,
                                                         const float* __restrict__ rgb, float* __restrict__ rgb_dst,
                                                         float* __restrict__ z_dst, float* __restrict__ a_dst,
-                                                        uint8_t* __restrict__ hole, DevStatus* st) {
+                                                        uint8_t* __restrict__ hole, uint4* __restrict__ wpart) {
     extern __shared__ unsigned long long zrow[];
     const int j = blockIdx.x;
     for (int t = threadIdx.x; t < dst.W; t += 256) zrow[t] = ~0ull;
     __syncthreads();
     uint32_t dmin = 0xFFFFFFFFu, dmax = 0u, off_row = 0;
-    for (int i = threadIdx.x; i < src.W; i += 256) {
-        int64_t fu, fv;
-        unsigned long long key;
-        float df = -1.f;
-        const bool hit = splat_target(src, dst, P, a_min, draw, alpha, i, j, &fu, &fv, &key, &df);
-        if (df >= 0.f) {
-            dmin = min(dmin, __float_as_uint(df));
-            dmax = max(dmax, __float_as_uint(df));
+    const int64_t srow = (int64_t)j * src.W;
+    for (int base = 0; base < src.W; base += 256 * kRowPix) {
+        float Av[kRowPix], Dv[kRowPix];
+#pragma unroll
+        for (int k = 0; k < kRowPix; ++k) {
+            const int i = base + threadIdx.x + 256 * k;
+            Av[k] = i < src.W ? alpha[srow + i] : 0.f;
+            Dv[k] = i < src.W ? draw[srow + i] : 0.f;
         }
-        if (hit) {
-            if (fv == j) atomicMin(&zrow[fu], key);
-            else off_row = 1;
+#pragma unroll
+        for (int k = 0; k < kRowPix; ++k) {
+            const int i = base + threadIdx.x + 256 * k;
+            if (i >= src.W) continue;
+            int64_t fu, fv;
+            unsigned long long key;
+            float df = -1.f;
+            const bool hit = splat_target_v(src, dst, P, a_min, Av[k], Dv[k], i, j, &fu, &fv, &key, &df);
+            if (df >= 0.f) {
+                dmin = min(dmin, __float_as_uint(df));
+                dmax = max(dmax, __float_as_uint(df));
+            }
+            if (hit) {
+                if (fv == j) atomicMin(&zrow[fu], key);
+                else off_row = 1;
+            }
         }
     }
     __syncthreads();
     const int64_t nd = (int64_t)dst.W * dst.H, ns = (int64_t)src.W * src.H;
+    const int64_t drow = (int64_t)j * dst.W;
     uint32_t holes = 0;
-    for (int t = threadIdx.x; t < dst.W; t += 256)
-        holes += resolve_pixel(zrow[t], (int64_t)j * dst.W + t, nd, ns, rgb, alpha, rgb_dst, z_dst, a_dst, hole);
+    for (int base = 0; base < dst.W; base += 256 * kRowPix) {
+        unsigned long long kv[kRowPix];
+        float c0[kRowPix], c1[kRowPix], c2[kRowPix], av[kRowPix];
+#pragma unroll
+        for (int k = 0; k < kRowPix; ++k) {
+            const int t = base + threadIdx.x + 256 * k;
+            kv[k] = t < dst.W ? zrow[t] : ~0ull;
+            const uint32_t sidx = (uint32_t)(kv[k] & 0xFFFFFFFFull);
+            const bool have = kv[k] != ~0ull;
+            c0[k] = have ? rgb[sidx] : 0.f;
+            c1[k] = have ? rgb[ns + sidx] : 0.f;
+            c2[k] = have ? rgb[2 * ns + sidx] : 0.f;
+            av[k] = have ? alpha[sidx] : 0.f;
+        }
+#pragma unroll
+        for (int k = 0; k < kRowPix; ++k) {
+            const int t = base + threadIdx.x + 256 * k;
+            if (t >= dst.W) continue;
+            const int64_t g = drow + t;
+            const bool have = kv[k] != ~0ull;
+            rgb_dst[g] = c0[k];
+            rgb_dst[nd + g] = c1[k];
+            rgb_dst[2 * nd + g] = c2[k];
+            z_dst[g] = have ? __uint_as_float((uint32_t)(kv[k] >> 32)) : INFINITY;
+            a_dst[g] = av[k];
+            hole[g] = have ? 0 : 1;
+            holes += have ? 0u : 1u;
+        }
+    }
     __shared__ uint32_t s4[4];
     dmin = block_min_u32(dmin, s4);
     dmax = block_max_u32(dmax, s4);
     holes = block_sum_u32(holes, s4);
     off_row = block_max_u32(off_row, s4);
+    // off_row cannot be set when the host's bound holds (overflow bit 2).
+    if (threadIdx.x == 0) wpart[j] = make_uint4(~dmin, dmax, holes, off_row ? 4u : 0u);
+}
+
+// Fold the per-row partials of k_reproject_rows (n of them; none for the
+// scatter form, which reduces with atomics) into the status block, from
+// every thread of a 256-thread block.  Returns the depth-proxy range of the
+// covered pixels, or [z_near, z_far] when none was covered, to every thread.
+__device__ inline void fold_warp_parts(const uint4* __restrict__ wpart, int n, DevStatus* st, float z_near,
+                                       float z_far, float* r0, float* r1) {
+    __shared__ uint32_t s4[4];
+    uint32_t a = 0u, b = 0u, h = 0u, f = 0u;
+    for (int i = threadIdx.x; i < n; i += 256) {
+        const uint4 q = wpart[i];
+        a = max(a, q.x);
+        b = max(b, q.y);
+        h += q.z;
+        f |= q.w;
+    }
+    a = max(block_max_u32(a, s4), st->dmin_inv);
+    b = max(block_max_u32(b, s4), st->dmax_bits);
+    h = block_sum_u32(h, s4);
+    f = block_max_u32(f, s4);
+    __syncthreads();
     if (threadIdx.x == 0) {
-        if (dmin != 0xFFFFFFFFu) atomicMin(&st->dmin_bits, dmin);
-        if (dmax != 0u) atomicMax(&st->dmax_bits, dmax);
-        if (holes) atomicAdd(&st->n_holes, holes);
-        if (off_row) atomicOr(&st->overflow, 4u);  // cannot happen when the host's bound holds
+        st->dmin_inv = a;
+        st->dmax_bits = b;
+        st->n_holes += h;
+        if (f) st->overflow |= f;
+    }
+    if (a == 0u) {
+        *r0 = z_near;
+        *r1 = z_far;
+    } else {
+        *r0 = __uint_as_float(~a);
+        *r1 = __uint_as_float(b);
     }
 }
 
@@ -274,13 +356,14 @@ __global__ __launch_bounds__(256) void k_reproject_resolve(int64_t nd, int64_t n
     if (threadIdx.x == 0 && h) atomicAdd(&st->n_holes, h);
 }
 
-__global__ void k_depth_range(const DevStatus* st, float z_near, float z_far, float* range) {
-    if (st->dmin_bits == 0xFFFFFFFFu) {
-        range[0] = z_near;
-        range[1] = z_far;
-    } else {
-        range[0] = __uint_as_float(st->dmin_bits);
-        range[1] = __uint_as_float(st->dmax_bits);
+// Standalone reprojection: fold the partials and write the depth range.
+__global__ __launch_bounds__(256) void k_warp_finish(const uint4* __restrict__ wpart, int n, DevStatus* st,
+                                                     float z_near, float z_far, float* range) {
+    float r0, r1;
+    fold_warp_parts(wpart, n, st, z_near, z_far, &r0, &r1);
+    if (threadIdx.x == 0) {
+        range[0] = r0;
+        range[1] = r1;
     }
 }
 
@@ -299,11 +382,25 @@ __device__ inline double clampd(double x, double a, double b) { return x < a ? a
 __device__ inline int64_t align_down(int64_t x, int64_t T) { return (x / T) * T; }
 __device__ inline int64_t align_up(int64_t x, int64_t T) { return ((x + T - 1) / T) * T; }
 
+// Also writes the edge boxes' tiles into the ROI tile mask (every tile
+// covered by an edge box is 1, all others 0).  depth_range null: the range
+// comes from the reprojection just run, whose partials (n_wpart, possibly
+// none) it folds into the status block first.
 __global__ __launch_bounds__(256) void k_edge_rois(WarpCam src, WarpCam dst, RelPose P, int N, int margin, int T,
-                                                   const float* __restrict__ depth_range, DevStatus* st,
-                                                   bgs_box* boxes, int box_cap) {
+                                                   const float* __restrict__ depth_range,
+                                                   const uint4* __restrict__ wpart, int n_wpart, DevStatus* st,
+                                                   bgs_box* boxes, int box_cap, uint8_t* __restrict__ tm) {
     __shared__ double red[4][256];
-    const double hyp0 = (double)depth_range[0], hyp1 = (double)depth_range[1];
+    __shared__ int32_t sbx[4][4];
+    __shared__ int snb;
+    float r0, r1;
+    if (depth_range) {
+        r0 = depth_range[0];
+        r1 = depth_range[1];
+    } else {
+        fold_warp_parts(wpart, n_wpart, st, (float)src.z_near, (float)src.z_far, &r0, &r1);
+    }
+    const double hyp0 = (double)r0, hyp1 = (double)r1;
     double xmin = INFINITY, xmax = -INFINITY, ymin = INFINITY, ymax = -INFINITY;
     const int64_t total = 4LL * N;
     for (int64_t q = threadIdx.x; q < total; q += 256) {
@@ -344,52 +441,64 @@ __global__ __launch_bounds__(256) void k_edge_rois(WarpCam src, WarpCam dst, Rel
         }
         __syncthreads();
     }
-    if (threadIdx.x != 0) return;
-    const double W = dst.W, H = dst.H, m = margin;
-    const double hw = floor(W / 2.0), hh = floor(H / 2.0);
-    const double umin = snap(red[0][0]), umax = snap(red[1][0]), vmin = snap(red[2][0]), vmax = snap(red[3][0]);
-    const double lw = umin > 0.0 ? clampd(ceil(umin) + m, 0.0, hw) : 0.0;
-    const double rw = umax < W - 1.0 ? clampd((W - 1.0) - floor(umax) + m, 0.0, hw) : 0.0;
-    const double th = vmin > 0.0 ? clampd(ceil(vmin) + m, 0.0, hh) : 0.0;
-    const double bh = vmax < H - 1.0 ? clampd((H - 1.0) - floor(vmax) + m, 0.0, hh) : 0.0;
-    const int w4[4] = {(int)lw, (int)rw, (int)th, (int)bh};
-    const int64_t Wi = dst.W, Hi = dst.H;
-    int nb = 0;
-    int32_t bx[4][6];
-    if (w4[0] > 0) {
-        int64_t x1 = align_up(w4[0], T);
-        int32_t b[6] = {0, 0, (int32_t)(x1 < Wi ? x1 : Wi), (int32_t)Hi, BGS_BOX_LEFT, -1};
-        for (int q = 0; q < 6; ++q) bx[nb][q] = b[q];
-        ++nb;
-    }
-    if (w4[1] > 0) {
-        int32_t b[6] = {(int32_t)align_down(Wi - w4[1], T), 0, (int32_t)Wi, (int32_t)Hi, BGS_BOX_RIGHT, -1};
-        for (int q = 0; q < 6; ++q) bx[nb][q] = b[q];
-        ++nb;
-    }
-    if (w4[2] > 0) {
-        int64_t y1 = align_up(w4[2], T);
-        int32_t b[6] = {0, 0, (int32_t)Wi, (int32_t)(y1 < Hi ? y1 : Hi), BGS_BOX_TOP, -1};
-        for (int q = 0; q < 6; ++q) bx[nb][q] = b[q];
-        ++nb;
-    }
-    if (w4[3] > 0) {
-        int32_t b[6] = {0, (int32_t)align_down(Hi - w4[3], T), (int32_t)Wi, (int32_t)Hi, BGS_BOX_BOTTOM, -1};
-        for (int q = 0; q < 6; ++q) bx[nb][q] = b[q];
-        ++nb;
-    }
-    for (int q = 0; q < 4; ++q) st->widths[q] = w4[q];
-    st->n_edge = (uint32_t)nb;
-    for (int b = 0; b < nb; ++b) {
-        for (int q = 0; q < 6; ++q) st->edge_boxes[b * 6 + q] = bx[b][q];
-        if (b < box_cap) {
-            boxes[b].x0 = bx[b][0];
-            boxes[b].y0 = bx[b][1];
-            boxes[b].x1 = bx[b][2];
-            boxes[b].y1 = bx[b][3];
-            boxes[b].kind = bx[b][4];
-            boxes[b].label = bx[b][5];
+    if (threadIdx.x == 0) {
+        const double W = dst.W, H = dst.H, m = margin;
+        const double hw = floor(W / 2.0), hh = floor(H / 2.0);
+        const double umin = snap(red[0][0]), umax = snap(red[1][0]), vmin = snap(red[2][0]), vmax = snap(red[3][0]);
+        const double lw = umin > 0.0 ? clampd(ceil(umin) + m, 0.0, hw) : 0.0;
+        const double rw = umax < W - 1.0 ? clampd((W - 1.0) - floor(umax) + m, 0.0, hw) : 0.0;
+        const double th = vmin > 0.0 ? clampd(ceil(vmin) + m, 0.0, hh) : 0.0;
+        const double bh = vmax < H - 1.0 ? clampd((H - 1.0) - floor(vmax) + m, 0.0, hh) : 0.0;
+        const int w4[4] = {(int)lw, (int)rw, (int)th, (int)bh};
+        const int64_t Wi = dst.W, Hi = dst.H;
+        int nb = 0;
+        int32_t bx[4][6];
+        if (w4[0] > 0) {
+            int64_t x1 = align_up(w4[0], T);
+            int32_t b[6] = {0, 0, (int32_t)(x1 < Wi ? x1 : Wi), (int32_t)Hi, BGS_BOX_LEFT, -1};
+            for (int q = 0; q < 6; ++q) bx[nb][q] = b[q];
+            ++nb;
         }
+        if (w4[1] > 0) {
+            int32_t b[6] = {(int32_t)align_down(Wi - w4[1], T), 0, (int32_t)Wi, (int32_t)Hi, BGS_BOX_RIGHT, -1};
+            for (int q = 0; q < 6; ++q) bx[nb][q] = b[q];
+            ++nb;
+        }
+        if (w4[2] > 0) {
+            int64_t y1 = align_up(w4[2], T);
+            int32_t b[6] = {0, 0, (int32_t)Wi, (int32_t)(y1 < Hi ? y1 : Hi), BGS_BOX_TOP, -1};
+            for (int q = 0; q < 6; ++q) bx[nb][q] = b[q];
+            ++nb;
+        }
+        if (w4[3] > 0) {
+            int32_t b[6] = {0, (int32_t)align_down(Hi - w4[3], T), (int32_t)Wi, (int32_t)Hi, BGS_BOX_BOTTOM, -1};
+            for (int q = 0; q < 6; ++q) bx[nb][q] = b[q];
+            ++nb;
+        }
+        for (int q = 0; q < 4; ++q) st->widths[q] = w4[q];
+        st->n_edge = (uint32_t)nb;
+        snb = nb;
+        for (int b = 0; b < nb; ++b) {
+            for (int q = 0; q < 6; ++q) st->edge_boxes[b * 6 + q] = bx[b][q];
+            for (int q = 0; q < 4; ++q) sbx[b][q] = bx[b][q];
+            if (b < box_cap) {
+                boxes[b].x0 = bx[b][0];
+                boxes[b].y0 = bx[b][1];
+                boxes[b].x1 = bx[b][2];
+                boxes[b].y1 = bx[b][3];
+                boxes[b].kind = bx[b][4];
+                boxes[b].label = bx[b][5];
+            }
+        }
+    }
+    __syncthreads();
+    const int tiles_x = (dst.W + T - 1) / T, n_tiles = tiles_x * ((dst.H + T - 1) / T);
+    for (int t = threadIdx.x; t < n_tiles; t += 256) {
+        const int x0 = (t % tiles_x) * T, y0 = (t / tiles_x) * T, x1 = x0 + T, y1 = y0 + T;
+        uint8_t hit = 0;
+        for (int b = 0; b < snb; ++b)
+            if (x0 < sbx[b][2] && sbx[b][0] < x1 && y0 < sbx[b][3] && sbx[b][1] < y1) hit = 1;
+        tm[t] = hit;
     }
 }
 
@@ -466,14 +575,18 @@ __global__ __launch_bounds__(256) void k_gap_pass(int W, int H, int pass, float*
 // passes there (pass j is final for pixels at least j from the halo's
 // edge, which after all passes is the tile), and writes the tile's filled
 // pixels, tags and center mask.  Per pixel it computes exactly what
-// k_tag_init, k_gap_pass and k_center_mask compute.
+// k_tag_init, k_gap_pass and k_center_mask compute.  Its filled and center
+// counts go to gpart (one entry per block) rather than to shared counters,
+// so that hundreds of blocks do not serialise on one cache line; the
+// component-box kernels add them up.
 constexpr int kGapMaxHalo = 4;
 constexpr int kGapRW = 64 + 2 * kGapMaxHalo, kGapRH = kBandRows + 2 * kGapMaxHalo;
 
 __global__ __launch_bounds__(256) void k_gap_fill(int W, int H, int passes, float* __restrict__ rgb,
                                                   float* __restrict__ z, float* __restrict__ alpha,
                                                   uint8_t* __restrict__ tag_out, uint8_t* __restrict__ cls,
-                                                  uint8_t* __restrict__ center, DevStatus* st) {
+                                                  uint8_t* __restrict__ center, const DevStatus* st,
+                                                  uint2* __restrict__ gpart) {
     __shared__ float s_c[3][kGapRH * kGapRW];
     __shared__ float s_a[kGapRH * kGapRW], s_z[kGapRH * kGapRW];
     __shared__ uint8_t s_tag[kGapRH * kGapRW];
@@ -560,10 +673,7 @@ __global__ __launch_bounds__(256) void k_gap_fill(int W, int H, int passes, floa
     }
     filled = block_sum_u32(filled, s4);
     centers = block_sum_u32(centers, s4);
-    if (threadIdx.x == 0) {
-        if (filled) atomicAdd(&st->n_gap, filled);
-        if (centers) atomicAdd(&st->n_center, centers);
-    }
+    if (threadIdx.x == 0) gpart[blockIdx.y * gridDim.x + blockIdx.x] = make_uint2(filled, centers);
 }
 
 // Holes left after interpolation and outside the edge ROIs.
@@ -803,89 +913,181 @@ __global__ __launch_bounds__(256) void k_ccl_flatten(int64_t n, int* labels) {
 }
 
 // ---------------------------------------------------------------------------
-// Center boxes.
+// Center boxes.  Component c (in order of root pixel) gets box slot
+// n_edge + c.  A component's root is its smallest pixel index, so the
+// component roots are the pixels with labels[p] == p; slot_of() ranks a
+// root among them from per-block root counts (scanned) and per-block root
+// masks, so no per-pixel slot map is needed.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_root_flags(int64_t n, const int* __restrict__ labels,
-                                                    uint32_t* __restrict__ flags) {
+constexpr int kBoxWords = 8;  // per component: x0, y0, x1, y1, root pixel, pad
+
+// Flatten every label to its root (as k_ccl_flatten) and record, per
+// 256-pixel block of the flatten grid, the mask of component roots and its
+// population.
+__global__ __launch_bounds__(256) void k_ccl_flatten_roots(int64_t n, int* labels, uint32_t* __restrict__ bcount,
+                                                           uint32_t* __restrict__ rmask) {
+    __shared__ uint32_t cnt[4];
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (p < n) flags[p] = (labels[p] == (int)p) ? 1u : 0u;
+    bool root = false;
+    if (p < n) {
+        const int l = labels[p];
+        if (l >= 0) {
+            root = l == (int)p;
+            if (!root) labels[p] = find_root_g(labels, l);
+        }
+    }
+    const unsigned long long m = __ballot(root);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        rmask[(size_t)blockIdx.x * 8 + 2 * w] = (uint32_t)m;
+        rmask[(size_t)blockIdx.x * 8 + 2 * w + 1] = (uint32_t)(m >> 32);
+        cnt[w] = (uint32_t)__popcll(m);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) bcount[blockIdx.x] = cnt[0] + cnt[1] + cnt[2] + cnt[3];
 }
 
-__global__ __launch_bounds__(256) void k_bbox_init(int64_t n, const int* __restrict__ labels,
-                                                   const uint32_t* __restrict__ slots, int32_t* __restrict__ bbox) {
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (p >= n || labels[p] != (int)p) return;
-    const uint32_t s = slots[p];
-    bbox[4 * s + 0] = INT_MAX;
-    bbox[4 * s + 1] = INT_MAX;
-    bbox[4 * s + 2] = -1;
-    bbox[4 * s + 3] = -1;
+// One workgroup: the gap-fill counts, an exclusive scan of the nb block
+// counts in place (bcount[nb] gets the component count), the box count and
+// capacity flag, and the initial (empty) box of every component.
+// Adds the gap-fill block counts (n_gpart entries) to the status block.
+__device__ inline void fold_gap_parts(const uint2* __restrict__ gpart, int n_gpart, DevStatus* st) {
+    __shared__ uint32_t s_g[2];
+    if (threadIdx.x == 0) s_g[0] = s_g[1] = 0u;
+    __syncthreads();
+    uint32_t f = 0u, c = 0u;
+    for (int i = threadIdx.x; i < n_gpart; i += blockDim.x) {
+        const uint2 q = gpart[i];
+        f += q.x;
+        c += q.y;
+    }
+    f = wave_sum_u32(f);
+    c = wave_sum_u32(c);
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&s_g[0], f);
+        atomicAdd(&s_g[1], c);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        st->n_gap += s_g[0];
+        st->n_center += s_g[1];
+    }
 }
 
-// Component boxes from the block-local pieces: 4 atomics per piece.
+__global__ __launch_bounds__(1024) void k_root_scan(int64_t nb, uint32_t* bcount, int32_t* __restrict__ bbox,
+                                                    int box_cap, int32_t* __restrict__ n_boxes,
+                                                    const uint2* __restrict__ gpart, int n_gpart, DevStatus* st) {
+    __shared__ uint32_t part[1024];
+    fold_gap_parts(gpart, n_gpart, st);
+    const int64_t per = (nb + 1023) / 1024;
+    const int64_t b0 = min(nb, (int64_t)threadIdx.x * per), b1 = min(nb, b0 + per);
+    uint32_t sum = 0;
+    for (int64_t b = b0; b < b1; ++b) sum += bcount[b];
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[threadIdx.x] - sum;
+    for (int64_t b = b0; b < b1; ++b) {
+        const uint32_t c = bcount[b];
+        bcount[b] = run;
+        run += c;
+    }
+    const uint32_t total = part[1023];
+    if (threadIdx.x == 0) {
+        bcount[nb] = total;
+        const uint32_t tot = st->n_edge + total;
+        st->n_boxes = tot;
+        if ((int64_t)tot > box_cap) atomicOr(&st->overflow, 2u);
+        *n_boxes = (int32_t)tot;
+    }
+    for (uint32_t c = threadIdx.x; c < total; c += 1024) {
+        int32_t* e = bbox + (size_t)c * kBoxWords;
+        e[0] = INT_MAX;
+        e[1] = INT_MAX;
+        e[2] = -1;
+        e[3] = -1;
+        e[4] = -1;
+    }
+}
+
+// Rank of component root r among all roots, in pixel order.
+__device__ inline uint32_t slot_of(int r, const uint32_t* __restrict__ boff, const uint32_t* __restrict__ rmask) {
+    const uint32_t blk = (uint32_t)r >> 8, bit = (uint32_t)r & 255u;
+    const uint32_t* m = rmask + (size_t)blk * 8;
+    uint32_t rank = boff[blk];
+    for (uint32_t q = 0; q < (bit >> 5); ++q) rank += __popc(m[q]);
+    const uint32_t low = bit & 31u;
+    if (low) rank += __popc(m[bit >> 5] & ((1u << low) - 1u));
+    return rank;
+}
+
+// Component boxes from the block-local pieces: 4 atomics per piece; the
+// piece that holds the component root records it.
 __global__ __launch_bounds__(256) void k_bbox_acc(int64_t n, const int* __restrict__ labels,
                                                   const uint8_t* __restrict__ pflag, const int4* __restrict__ pbox,
-                                                  const uint32_t* __restrict__ slots, int32_t* bbox) {
+                                                  const uint32_t* __restrict__ boff, const uint32_t* __restrict__ rmask,
+                                                  int32_t* bbox) {
     const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= n || !pflag[p]) return;
-    const uint32_t s = slots[labels[p]];
+    const int r = labels[p];
+    int32_t* e = bbox + (size_t)slot_of(r, boff, rmask) * kBoxWords;
     const int4 b = pbox[p];
-    atomicMin(&bbox[4 * s + 0], b.x);
-    atomicMin(&bbox[4 * s + 1], b.y);
-    atomicMax(&bbox[4 * s + 2], b.z);
-    atomicMax(&bbox[4 * s + 3], b.w);
+    atomicMin(&e[0], b.x);
+    atomicMin(&e[1], b.y);
+    atomicMax(&e[2], b.z);
+    atomicMax(&e[3], b.w);
+    if (r == (int)p) e[4] = r;
 }
 
-__global__ __launch_bounds__(256) void k_tile_mask_edges(int tiles_x, int tiles_y, int T, const DevStatus* st,
-                                                         uint8_t* __restrict__ tm) {
-    const int t = blockIdx.x * 256 + threadIdx.x;
-    if (t >= tiles_x * tiles_y) return;
-    const int x0 = (t % tiles_x) * T, y0 = (t / tiles_x) * T, x1 = x0 + T, y1 = y0 + T;
-    uint8_t hit = 0;
-    for (int b = 0; b < (int)st->n_edge; ++b) {
-        const int32_t* e = st->edge_boxes + b * 6;
-        if (x0 < e[2] && e[0] < x1 && y0 < e[3] && e[1] < y1) hit = 1;
-    }
-    tm[t] = hit;
-}
-
-__global__ __launch_bounds__(256) void k_center_boxes(int W, int H, int64_t n, int margin, int T, int tiles_x,
-                                                      const int* __restrict__ labels,
-                                                      const uint32_t* __restrict__ slots,
+// One workgroup per component (grid-stride over the component count):
+// margin, clip, tile alignment, the box record, and its tiles in the mask.
+__global__ __launch_bounds__(256) void k_center_boxes(int W, int H, int margin, int T, int tiles_x,
+                                                      const uint32_t* __restrict__ ncomp,
                                                       const int32_t* __restrict__ bbox, bgs_box* __restrict__ boxes,
-                                                      int box_cap, uint8_t* tm, DevStatus* st) {
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (p >= n || labels[p] != (int)p) return;
-    const uint32_t s = slots[p];
-    int64_t x0 = bbox[4 * s + 0] - margin, y0 = bbox[4 * s + 1] - margin;
-    int64_t x1 = bbox[4 * s + 2] + margin, y1 = bbox[4 * s + 3] + margin;
-    if (x0 < 0) x0 = 0;
-    if (y0 < 0) y0 = 0;
-    if (x1 > W) x1 = W;
-    if (y1 > H) y1 = H;
-    x0 = align_down(x0, T);
-    y0 = align_down(y0, T);
-    x1 = align_up(x1, T);
-    y1 = align_up(y1, T);
-    if (x1 > W) x1 = W;
-    if (y1 > H) y1 = H;
-    const int64_t slot = (int64_t)st->n_edge + s;
-    if (slot < box_cap) {
-        boxes[slot].x0 = (int32_t)x0;
-        boxes[slot].y0 = (int32_t)y0;
-        boxes[slot].x1 = (int32_t)x1;
-        boxes[slot].y1 = (int32_t)y1;
-        boxes[slot].kind = BGS_BOX_CENTER;
-        boxes[slot].label = (int32_t)p;
+                                                      int box_cap, uint8_t* tm, const DevStatus* st) {
+    const uint32_t total = *ncomp;
+    for (uint32_t c = blockIdx.x; c < total; c += gridDim.x) {
+        const int32_t* e = bbox + (size_t)c * kBoxWords;
+        int64_t x0 = e[0] - margin, y0 = e[1] - margin;
+        int64_t x1 = e[2] + margin, y1 = e[3] + margin;
+        if (x0 < 0) x0 = 0;
+        if (y0 < 0) y0 = 0;
+        if (x1 > W) x1 = W;
+        if (y1 > H) y1 = H;
+        x0 = align_down(x0, T);
+        y0 = align_down(y0, T);
+        x1 = align_up(x1, T);
+        y1 = align_up(y1, T);
+        if (x1 > W) x1 = W;
+        if (y1 > H) y1 = H;
+        if (threadIdx.x == 0) {
+            const int64_t slot = (int64_t)st->n_edge + c;
+            if (slot < box_cap) {
+                boxes[slot].x0 = (int32_t)x0;
+                boxes[slot].y0 = (int32_t)y0;
+                boxes[slot].x1 = (int32_t)x1;
+                boxes[slot].y1 = (int32_t)y1;
+                boxes[slot].kind = BGS_BOX_CENTER;
+                boxes[slot].label = e[4];
+            }
+        }
+        const int64_t tx0 = x0 / T, ty0 = y0 / T;
+        const int64_t bw = (x1 + T - 1) / T - tx0, bh = (y1 + T - 1) / T - ty0;
+        for (int64_t q = threadIdx.x; q < bw * bh; q += 256) tm[(ty0 + q / bw) * tiles_x + tx0 + q % bw] = 1;
     }
-    for (int64_t ty = y0 / T; ty < (y1 + T - 1) / T; ++ty)
-        for (int64_t tx = x0 / T; tx < (x1 + T - 1) / T; ++tx) tm[ty * tiles_x + tx] = 1;
 }
 
-__global__ void k_box_count(int64_t n, const uint32_t* __restrict__ slots, int box_cap, int32_t* n_boxes,
-                            DevStatus* st, int center) {
-    const uint32_t nc = center ? slots[n] : 0u;
-    const uint32_t tot = st->n_edge + nc;
+// Box count without center ROIs: the edge boxes only.  256 threads.
+__global__ __launch_bounds__(256) void k_box_count(int box_cap, int32_t* n_boxes, const uint2* __restrict__ gpart,
+                                                   int n_gpart, DevStatus* st) {
+    fold_gap_parts(gpart, n_gpart, st);
+    if (threadIdx.x != 0) return;
+    const uint32_t tot = st->n_edge;
     st->n_boxes = tot;
     if ((int64_t)tot > box_cap) st->overflow |= 2u;
     *n_boxes = (int32_t)tot;
@@ -923,15 +1125,19 @@ static bool rows_preserved(const WarpCam& src, const WarpCam& dst, const RelPose
     return bound < 0.25;
 }
 
+int warp_parts(const WarpCam& src, const WarpCam& dst, const RelPose& P) {
+    return rows_preserved(src, dst, P) ? dst.H : 0;
+}
+
 hipError_t launch_reproject(const WarpCam& src, const WarpCam& dst, const RelPose& P, float a_min, const float* rgb,
                             const float* draw, const float* alpha, unsigned long long* zbuf, float* rgb_dst,
-                            float* z_dst, float* alpha_dst, uint8_t* hole, float* depth_range, DevStatus* st,
-                            hipStream_t s) {
+                            float* z_dst, float* alpha_dst, uint8_t* hole, float* depth_range, bool reset,
+                            uint4* wpart, DevStatus* st, hipStream_t s) {
     const int64_t ns = (int64_t)src.W * src.H, nd = (int64_t)dst.W * dst.H;
-    hipLaunchKernelGGL(k_warp_reset, dim3(1), dim3(1), 0, s, st);
+    if (reset) hipLaunchKernelGGL(k_warp_reset, dim3(1), dim3(1), 0, s, st);
     if (rows_preserved(src, dst, P)) {
         hipLaunchKernelGGL(k_reproject_rows, dim3(dst.H), dim3(256), sizeof(unsigned long long) * dst.W, s, src, dst, P,
-                           a_min, draw, alpha, rgb, rgb_dst, z_dst, alpha_dst, hole, st);
+                           a_min, draw, alpha, rgb, rgb_dst, z_dst, alpha_dst, hole, wpart);
     } else {
         hipLaunchKernelGGL(k_fill_u64, dim3(grid(nd)), dim3(256), 0, s, zbuf, nd, ~0ull);
         hipLaunchKernelGGL(k_reproject_scatter, band_grid(src.W, src.H), dim3(256), 0, s, src, dst, P, a_min, draw,
@@ -939,7 +1145,9 @@ hipError_t launch_reproject(const WarpCam& src, const WarpCam& dst, const RelPos
         hipLaunchKernelGGL(k_reproject_resolve, dim3((unsigned)((nd + 1023) / 1024)), dim3(256), 0, s, nd, ns, zbuf, rgb,
                            alpha, rgb_dst, z_dst, alpha_dst, hole, st);
     }
-    hipLaunchKernelGGL(k_depth_range, dim3(1), dim3(1), 0, s, st, (float)src.z_near, (float)src.z_far, depth_range);
+    if (depth_range)
+        hipLaunchKernelGGL(k_warp_finish, dim3(1), dim3(256), 0, s, wpart, warp_parts(src, dst, P), st,
+                           (float)src.z_near, (float)src.z_far, depth_range);
     return hipGetLastError();
 }
 
@@ -964,38 +1172,43 @@ hipError_t launch_classify(const WarpCam& src, const WarpCam& dst, const RelPose
                            uint8_t* tile_mask, const ClassifyBufs& b, DevStatus* st, hipStream_t s) {
     const int W = dst.W, H = dst.H, T = roi.tile;
     const int64_t n = (int64_t)W * H;
-    const int tiles_x = (W + T - 1) / T, tiles_y = (H + T - 1) / T;
+    const int tiles_x = (W + T - 1) / T;
     hipLaunchKernelGGL(k_edge_rois, dim3(1), dim3(256), 0, s, src, dst, P, roi.edge_samples, roi.margin, T,
-                       depth_range, st, boxes, box_cap);
+                       depth_range, b.wpart, depth_range ? 0 : warp_parts(src, dst, P), st, boxes, box_cap,
+                       tile_mask);
+    const dim3 gg = band_grid(W, H);
+    int n_gpart = 0;
     uint8_t* tag = b.hole;
     uint8_t* center = b.hole2;
     if (roi.gap_passes <= kGapMaxHalo) {
-        hipLaunchKernelGGL(k_gap_fill, band_grid(W, H), dim3(256), 0, s, W, H, roi.gap_passes, rgb, z, alpha, tag, cls,
-                           center, st);
+        hipLaunchKernelGGL(k_gap_fill, gg, dim3(256), 0, s, W, H, roi.gap_passes, rgb, z, alpha, tag, cls, center, st,
+                           b.gpart);
+        n_gpart = (int)(gg.x * gg.y);
     } else {
         hipLaunchKernelGGL(k_tag_init, dim3(grid(n)), dim3(256), 0, s, n, cls, tag);
         for (int pass = 1; pass <= roi.gap_passes; ++pass)
             hipLaunchKernelGGL(k_gap_pass, band_grid(W, H), dim3(256), 0, s, W, H, pass, rgb, z, alpha, tag, cls, st);
         hipLaunchKernelGGL(k_center_mask, band_grid(W, H), dim3(256), 0, s, W, H, tag, center, st);
     }
-    hipLaunchKernelGGL(k_tile_mask_edges, dim3(grid((int64_t)tiles_x * tiles_y)), dim3(256), 0, s, tiles_x, tiles_y, T,
-                       st, tile_mask);
     if (roi.center_roi) {
-        hipError_t e = label_components(center, W, H, 8, labels, b.pflag, b.pbox, s);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_root_flags, dim3(grid(n)), dim3(256), 0, s, n, labels, b.flags);
-        e = exclusive_scan(b.flags, nullptr, b.flags, nullptr, n, b.scan_tmp, s);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_bbox_init, dim3(grid(n)), dim3(256), 0, s, n, labels, b.flags, b.bbox);
-        hipLaunchKernelGGL(k_bbox_acc, dim3(grid(n)), dim3(256), 0, s, n, labels, b.pflag, b.pbox, b.flags, b.bbox);
-        hipLaunchKernelGGL(k_center_boxes, dim3(grid(n)), dim3(256), 0, s, W, H, n, roi.margin, T, tiles_x, labels,
-                           b.flags, b.bbox, boxes, box_cap, tile_mask, st);
+        const int64_t nb = (n + 255) / 256;
+        dim3 g((W + 15) / 16, (H + 15) / 16);
+        hipLaunchKernelGGL(k_ccl_local, g, dim3(256), 0, s, W, H, 8, center, labels, b.pflag, b.pbox);
+        hipLaunchKernelGGL(k_ccl_border, g, dim3(256), 0, s, W, H, 8, center, labels);
+        hipLaunchKernelGGL(k_ccl_flatten_roots, dim3((unsigned)nb), dim3(256), 0, s, n, labels, b.bcount, b.rmask);
+        hipLaunchKernelGGL(k_root_scan, dim3(1), dim3(1024), 0, s, nb, b.bcount, b.bbox, box_cap, n_boxes, b.gpart,
+                           n_gpart, st);
+        hipLaunchKernelGGL(k_bbox_acc, dim3((unsigned)nb), dim3(256), 0, s, n, labels, b.pflag, b.pbox, b.bcount,
+                           b.rmask, b.bbox);
+        const unsigned gcb = (unsigned)std::min<int64_t>(256, nb);
+        hipLaunchKernelGGL(k_center_boxes, dim3(gcb), dim3(256), 0, s, W, H, roi.margin, T, tiles_x, b.bcount + nb,
+                           b.bbox, boxes, box_cap, tile_mask, st);
     } else {
         hipLaunchKernelGGL(k_fill_i32, dim3(grid(n)), dim3(256), 0, s, n, labels, -1);
         hipLaunchKernelGGL(k_row_fill, dim3(H), dim3(256), 0, s, W, H, tag, center, bg[0], bg[1], bg[2], rgb, z, alpha,
                            cls, st);
+        hipLaunchKernelGGL(k_box_count, dim3(1), dim3(256), 0, s, box_cap, n_boxes, b.gpart, n_gpart, st);
     }
-    hipLaunchKernelGGL(k_box_count, dim3(1), dim3(1), 0, s, n, b.flags, box_cap, n_boxes, st, roi.center_roi);
     return hipGetLastError();
 }
 
