@@ -76,7 +76,9 @@ struct BlendArgs {
 };
 
 // Continuation of long tile lists in the blend (k_blend, k_blend_seg,
-// k_blend_fix in raster.hip).  All arrays live in the workspace.
+// k_blend_chain, k_blend_fix in raster.hip).  All arrays live in the
+// workspace.  A continued tile takes a slot and a run of consecutive items,
+// one per segment of its remaining records.
 struct ContArgs {
     uint32_t cap;          // records a tile composites before its rest is continued; 0: never
     uint32_t seg_len;      // records per continuation segment (at most kContMaxSeg segments)
@@ -84,12 +86,13 @@ struct ContArgs {
     uint32_t min_far;      // continue a tile only if some pixel is expected to composite this many more records
     uint32_t* n_slots;     // counters (DevStatus), cleared before each pass
     uint32_t* n_items;
-    uint4* slot_desc;      // per slot: compact tile id, first continued record, end record, item base | nseg << 27
+    uint4* slot_desc;      // per slot: compact tile id, first continued record, end record, item base | nseg << kContSegShift
     uint32_t* item_slot;   // per item: its slot
     float4* st1;           // per slot: 256 pixels x 2 float4 after the capped walk
     float4* part;          // per item: 256 pixels x 2 float4, the segment's walk from the slot's transmittance
 };
-constexpr uint32_t kContMaxSeg = 16;
+constexpr uint32_t kContMaxSeg = 32;
+constexpr uint32_t kContSegShift = 26;  // item base in the low 26 bits, segment count above
 
 
 // Device status block kept in the workspace.

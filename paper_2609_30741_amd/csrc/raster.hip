@@ -578,6 +578,7 @@ constexpr int kTrip = 4;                // records per trip of the walk
 constexpr int kDummy = kBatch;          // LDS record index of the zero record
 constexpr int kListLen = kBatch + 4;    // per-wave hit list, with padding
 constexpr uint32_t kRoundSeg = 4;       // continuation segments walked in the first round
+constexpr uint32_t kChainBatch = 8;     // earlier segments' parts loaded together when chaining
 
 
 // A pixel's compositing state.  A pixel that has stopped, or that takes no
@@ -885,7 +886,7 @@ __global__ __launch_bounds__(256) void k_blend(const SurfelRec* __restrict__ rec
                 if (slot < ca.max_slots) {
                     const uint32_t nseg = min(kContMaxSeg, max(1u, (rem + ca.seg_len - 1) / ca.seg_len));
                     const uint32_t ibase = atomicAdd(ca.n_items, nseg);
-                    ca.slot_desc[slot] = make_uint4(cid, cap_end, rg.y, ibase | (nseg << 27));
+                    ca.slot_desc[slot] = make_uint4(cid, cap_end, rg.y, ibase | (nseg << kContSegShift));
                     s_slot = slot;
                     s_ibase = ibase;
                     s_nseg = nseg;
@@ -929,12 +930,12 @@ __global__ __launch_bounds__(256) void k_blend(const SurfelRec* __restrict__ rec
 // chains exactly while no pixel would stop inside the segment, and a pixel
 // that stops in this walk stops at or before the same record in the true
 // one.
-// k_blend_fix chains the segments before its own for every pixel; a pixel
-// whose transmittance would cross t_min inside its segment (or that stopped
-// in the speculative walk) is composited again over the segment, in order,
-// from its exact state, and written; the last segment also writes the
-// pixels that never stop.  k_blend writes the pixels already done when it
-// hands a tile over, so every pixel is written once.
+// k_blend_chain chains a slot's segments for every pixel and writes the
+// pixels that never stop; a pixel whose transmittance would cross t_min
+// inside a segment (or that stopped in the speculative walk) is composited
+// again over that segment, in order, from its exact state, by k_blend_fix,
+// and written there.  k_blend writes the pixels already done when it hands
+// a tile over, so every pixel is written once.
 // ---------------------------------------------------------------------------
 struct Chain {
     float T, c0, c1, c2, D, A;
@@ -958,7 +959,7 @@ __device__ __forceinline__ bool chain_step(const float4& x0, const float4& x1, f
 }
 
 __device__ __forceinline__ void item_segment(const uint4& d, uint32_t k, uint32_t* sb, uint32_t* se) {
-    const uint32_t nseg = d.w >> 27;
+    const uint32_t nseg = d.w >> kContSegShift;
     const uint64_t rem = d.z - d.y;
     *sb = d.y + (uint32_t)(rem * k / nseg);
     *se = d.y + (uint32_t)(rem * (k + 1) / nseg);
@@ -984,7 +985,7 @@ __global__ __launch_bounds__(256) void k_blend_seg(const SurfelRec* __restrict__
     for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
         const uint32_t slot = ca.item_slot[item];
         const uint4 d = ca.slot_desc[slot];
-        const uint32_t ibase = d.w & 0x07FFFFFFu, nseg = d.w >> 27, k = item - ibase;
+        const uint32_t ibase = d.w & ((1u << kContSegShift) - 1u), nseg = d.w >> kContSegShift, k = item - ibase;
         const uint32_t m = min(nseg, kRoundSeg);
         if ((k < m) != (round == 0)) continue;
         uint32_t sb, se;
@@ -996,10 +997,19 @@ __global__ __launch_bounds__(256) void k_blend_seg(const SurfelRec* __restrict__
         Chain c{s1.y, 0.f, 0.f, 0.f, 0.f, 0.f};
         bool live = s1.z != 0.f;
         if (round != 0) {
-            for (uint32_t j = 0; j < m && live; ++j) {
-                const float4* x = ca.part + (size_t)(ibase + j) * 512 + 2 * tid;
-                live = chain_step(x[0], x[1], a.t_min, c);
+            // The m <= kRoundSeg round-0 parts, loaded together.
+            const float4* xb = ca.part + (size_t)ibase * 512 + 2 * tid;
+            float4 x0[kRoundSeg], x1[kRoundSeg];
+#pragma unroll
+            for (uint32_t j = 0; j < kRoundSeg; ++j) {
+                if (j < m) {
+                    x0[j] = xb[(size_t)j * 512];
+                    x1[j] = xb[(size_t)j * 512 + 1];
+                }
             }
+#pragma unroll
+            for (uint32_t j = 0; j < kRoundSeg; ++j)
+                if (j < m && live) live = chain_step(x0[j], x1[j], a.t_min, c);
         }
         const float ts = c.T;
         PixelState p{live ? ts : 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -1013,6 +1023,74 @@ __global__ __launch_bounds__(256) void k_blend_seg(const SurfelRec* __restrict__
     if (kCount) count_flush(wc, tid & 63, tid >> 6, 0, pair_counts, nullptr);
 }
 
+// After both segment rounds, one workgroup per slot chains the segments of
+// every pixel from the state after the capped walk.  A pixel that never
+// stops is written here, and so is one that stops in a segment walked from
+// its exact transmittance; for one that stops inside any other segment j
+// (or stopped in its speculative walk), the exact state at the start of
+// segment j and j + 1 replace the slot's state after the capped walk, for
+// k_blend_fix.
+template <bool kPatch>
+__global__ __launch_bounds__(256) void k_blend_chain(const uint32_t* __restrict__ tile_list, BlendArgs a, ContArgs ca,
+                                                     float* __restrict__ rgb, float* __restrict__ dz,
+                                                     float* __restrict__ alpha, uint8_t* __restrict__ cls) {
+    const uint32_t n_slots = min(*ca.n_slots, ca.max_slots);
+    const int tid = (int)threadIdx.x;
+    for (uint32_t slot = blockIdx.x; slot < n_slots; slot += gridDim.x) {
+        const uint4 d = ca.slot_desc[slot];
+        const uint32_t ibase = d.w & ((1u << kContSegShift) - 1u), nseg = d.w >> kContSegShift;
+        bool inside;
+        int px, py;
+        (void)tile_geom(tile_list ? tile_list[d.x] : d.x, tid, a, &inside, &px, &py);
+        float4* st = ca.st1 + (size_t)slot * 512 + 2 * tid;
+        const float4 s0 = st[0], s1 = st[1];
+        if (s1.z == 0.f) continue;  // done before the cap and written then
+        Chain c{s1.y, s0.x, s0.y, s0.z, s0.w, s1.x};
+        uint32_t stop = nseg;
+        bool exact = false;
+        const float4* xb = ca.part + (size_t)ibase * 512 + 2 * tid;
+        for (uint32_t j0 = 0; j0 < nseg && stop == nseg; j0 += kChainBatch) {
+            float4 x0[kChainBatch], x1[kChainBatch];
+#pragma unroll
+            for (uint32_t u = 0; u < kChainBatch; ++u) {
+                if (j0 + u < nseg) {
+                    x0[u] = xb[(size_t)(j0 + u) * 512];
+                    x1[u] = xb[(size_t)(j0 + u) * 512 + 1];
+                }
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < kChainBatch; ++u) {
+                const uint32_t j = j0 + u;
+                if (j < nseg && stop == nseg && !chain_step(x0[u], x1[u], a.t_min, c)) {
+                    stop = j;
+                    // Segments 0 and kRoundSeg were walked from the pixel's
+                    // exact transmittance: where the pixel stopped in that
+                    // walk, the walk is the true one and needs no repeat.
+                    if (x1[u].z == 1.f && (j == 0 || j == kRoundSeg)) {
+                        c.c0 = fmaf(c.T, x0[u].x, c.c0);
+                        c.c1 = fmaf(c.T, x0[u].y, c.c1);
+                        c.c2 = fmaf(c.T, x0[u].z, c.c2);
+                        c.D = fmaf(c.T, x0[u].w, c.D);
+                        c.A = fmaf(c.T, x1[u].x, c.A);
+                        c.T = 0.f;
+                        exact = true;
+                    }
+                }
+            }
+        }
+        if (stop == nseg || exact) {
+            if (inside) write_pixel<kPatch>(PixelState{c.T, c.c0, c.c1, c.c2, c.D, c.A}, px, py, a, rgb, dz, alpha, cls);
+            st[1] = make_float4(c.A, c.T, 0.f, 0.f);
+        } else {
+            st[0] = make_float4(c.c0, c.c1, c.c2, c.D);
+            st[1] = make_float4(c.A, c.T, (float)(stop + 1), 0.f);
+        }
+    }
+}
+
+// Item k of a slot composites segment k again, in order, from the exact
+// state k_blend_chain recorded, for the pixels that stop inside it, and
+// writes them.
 template <bool kCount, bool kPatch>
 __global__ __launch_bounds__(256) void k_blend_fix(const SurfelRec* __restrict__ recs,
                                                    const uint32_t* __restrict__ vals,
@@ -1030,34 +1108,18 @@ __global__ __launch_bounds__(256) void k_blend_fix(const SurfelRec* __restrict__
     for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
         const uint32_t slot = ca.item_slot[item];
         const uint4 d = ca.slot_desc[slot];
-        const uint32_t ibase = d.w & 0x07FFFFFFu, nseg = d.w >> 27, k = item - ibase;
+        const uint32_t k = item - (d.w & ((1u << kContSegShift) - 1u));
+        const float4 s0 = ca.st1[(size_t)slot * 512 + 2 * tid], s1 = ca.st1[(size_t)slot * 512 + 2 * tid + 1];
+        const bool need = s1.z == (float)(k + 1);
+        if (!__syncthreads_or(need)) continue;
         uint32_t sb, se;
         item_segment(d, k, &sb, &se);
         bool inside;
         int px, py;
         const TileGeom g = tile_geom(tile_list ? tile_list[d.x] : d.x, tid, a, &inside, &px, &py);
-        const float4 s0 = ca.st1[(size_t)slot * 512 + 2 * tid], s1 = ca.st1[(size_t)slot * 512 + 2 * tid + 1];
-        Chain c{s1.y, s0.x, s0.y, s0.z, s0.w, s1.x};
-        bool reach = s1.z != 0.f;  // the pixel is still compositing when this segment starts
-        for (uint32_t j = 0; j < k && reach; ++j) {
-            const float4* x = ca.part + (size_t)(ibase + j) * 512 + 2 * tid;
-            reach = chain_step(x[0], x[1], a.t_min, c);
-        }
-        bool need = false, done_here = false;
-        if (reach) {
-            const float4* x = ca.part + (size_t)item * 512 + 2 * tid;
-            need = !chain_step(x[0], x[1], a.t_min, c);
-            done_here = !need && k + 1 == nseg;  // never stops: the last segment writes it
-        }
-        // c was left at the segment's start for the pixels that stop in it;
-        // the others take no part in the walk.
-        PixelState q{need ? c.T : 0.f, c.c0, c.c1, c.c2, c.D, c.A};
-        if (__syncthreads_or(need)) {
-            walk_range<kCount>(recs, vals, sb, se, s_rec, s_list + (tid >> 6) * kListLen, g, a, q, wc);
-        }
+        PixelState q{need ? s1.y : 0.f, s0.x, s0.y, s0.z, s0.w, s1.x};
+        walk_range<kCount>(recs, vals, sb, se, s_rec, s_list + (tid >> 6) * kListLen, g, a, q, wc);
         if (inside && need) write_pixel<kPatch>(q, px, py, a, rgb, dz, alpha, cls);
-        if (inside && done_here)
-            write_pixel<kPatch>(PixelState{c.T, c.c0, c.c1, c.c2, c.D, c.A}, px, py, a, rgb, dz, alpha, cls);
     }
     if (kCount) count_flush(wc, tid & 63, tid >> 6, 0, pair_counts, nullptr);
 }
@@ -1104,7 +1166,7 @@ hipError_t launch_blend(const SurfelRec* recs, const uint32_t* vals, const uint2
     if (n_blocks <= 0) return hipSuccess;
     const dim3 g(n_blocks), b(256);
     const bool cont = ca.cap != 0 && ca.max_slots != 0;
-    const dim3 gc(min(ca.max_slots * kContMaxSeg, 4096u));
+    const dim3 gc(min(ca.max_slots * kContMaxSeg, 4096u)), gs(ca.max_slots);
     if (a.patch) {
         if (pair_counts) {
             hipLaunchKernelGGL((k_blend<true, true>), g, b, 0, s, recs, vals, ranges, tile_list, order, n_live, a, ca,
@@ -1113,6 +1175,7 @@ hipError_t launch_blend(const SurfelRec* recs, const uint32_t* vals, const uint2
                 for (int round = 0; round < 2; ++round)
                     hipLaunchKernelGGL((k_blend_seg<true>), gc, b, 0, s, recs, vals, tile_list, a, ca, round,
                                        pair_counts);
+                hipLaunchKernelGGL((k_blend_chain<true>), gs, b, 0, s, tile_list, a, ca, rgb, d_or_z, alpha, cls);
                 hipLaunchKernelGGL((k_blend_fix<true, true>), gc, b, 0, s, recs, vals, tile_list, a, ca, rgb, d_or_z,
                                    alpha, cls, pair_counts);
             }
@@ -1123,6 +1186,7 @@ hipError_t launch_blend(const SurfelRec* recs, const uint32_t* vals, const uint2
                 for (int round = 0; round < 2; ++round)
                     hipLaunchKernelGGL((k_blend_seg<false>), gc, b, 0, s, recs, vals, tile_list, a, ca, round,
                                        pair_counts);
+                hipLaunchKernelGGL((k_blend_chain<true>), gs, b, 0, s, tile_list, a, ca, rgb, d_or_z, alpha, cls);
                 hipLaunchKernelGGL((k_blend_fix<false, true>), gc, b, 0, s, recs, vals, tile_list, a, ca, rgb, d_or_z,
                                    alpha, cls, pair_counts);
             }
@@ -1135,6 +1199,7 @@ hipError_t launch_blend(const SurfelRec* recs, const uint32_t* vals, const uint2
                 for (int round = 0; round < 2; ++round)
                     hipLaunchKernelGGL((k_blend_seg<true>), gc, b, 0, s, recs, vals, tile_list, a, ca, round,
                                        pair_counts);
+                hipLaunchKernelGGL((k_blend_chain<false>), gs, b, 0, s, tile_list, a, ca, rgb, d_or_z, alpha, cls);
                 hipLaunchKernelGGL((k_blend_fix<true, false>), gc, b, 0, s, recs, vals, tile_list, a, ca, rgb, d_or_z,
                                    alpha, cls, pair_counts);
             }
@@ -1145,6 +1210,7 @@ hipError_t launch_blend(const SurfelRec* recs, const uint32_t* vals, const uint2
                 for (int round = 0; round < 2; ++round)
                     hipLaunchKernelGGL((k_blend_seg<false>), gc, b, 0, s, recs, vals, tile_list, a, ca, round,
                                        pair_counts);
+                hipLaunchKernelGGL((k_blend_chain<false>), gs, b, 0, s, tile_list, a, ca, rgb, d_or_z, alpha, cls);
                 hipLaunchKernelGGL((k_blend_fix<false, false>), gc, b, 0, s, recs, vals, tile_list, a, ca, rgb,
                                    d_or_z, alpha, cls, pair_counts);
             }
