@@ -48,6 +48,7 @@ struct Layout {
     size_t zbuf, hole, hole2, bcount, rmask, bbox, pflag, pbox, wpart, gpart;
     size_t ranges, colcum, mprefix, tlist, torder;
     size_t recs, zkeys, rects, counts, dkeys_b, dvals_a, dvals_b, offs, surf_scan;
+    size_t recs2, zkeys2, rects2;  // the affiliated eye's surfels, from the dominant pass of a stereo frame
     size_t tkeys_a, tkeys_b, tvals_a, tvals_b;
     size_t radix;
     size_t trace;  // per-tile blend trace of the last counting-mode dominant pass
@@ -92,6 +93,9 @@ Layout make_layout(int64_t n, int64_t W, int64_t H, int64_t kc) {
     L.dvals_b = take(4 * n);
     L.offs = take(4 * (n + 1));
     L.surf_scan = take(4 * scan_tmp_elems(n));
+    L.recs2 = take(sizeof(SurfelRec) * n);
+    L.zkeys2 = take(4 * n);
+    L.rects2 = take(8 * n);
     L.tkeys_a = take(4 * kc);
     L.tkeys_b = take(4 * kc);
     L.tvals_a = take(4 * kc);
@@ -303,9 +307,14 @@ struct RasterOut {
 // reuse_order: the compositing order of an earlier pass whose centre-depth
 // keys are bit-identical to this camera's (null: sort here).  *order_out
 // receives the order used.
+// cam_next: also preprocess the surfels for this camera (the affiliated eye
+// of a stereo frame) into the second record set; precomputed: this pass's
+// camera is that one, so it takes those records and only counts the keys
+// inside tile_mask.
 int raster_pass(bgs_ctx* ctx, const Layout& L, void* ws, int64_t kc, const bgs_scene& scene, const bgs_camera& cam,
                 const bgs_raster_params& rp, const uint8_t* tile_mask, float a_min, const RasterOut& out, int which,
-                const uint32_t* reuse_order = nullptr, const uint32_t** order_out = nullptr) {
+                const uint32_t* reuse_order = nullptr, const uint32_t** order_out = nullptr,
+                const bgs_camera* cam_next = nullptr, bool precomputed = false) {
     hipStream_t s = ctx->stream;
     const int n = (int)scene.n;
     const PreCam pc = make_precam(cam);
@@ -322,13 +331,23 @@ int raster_pass(bgs_ctx* ctx, const Layout& L, void* ws, int64_t kc, const bgs_s
         mask.colcum = at<uint32_t>(ws, L.colcum);
         mask.enabled = 1;
     }
-    SurfelRec* recs = at<SurfelRec>(ws, L.recs);
-    uint32_t* zkeys = at<uint32_t>(ws, L.zkeys);
-    uint2* rects = at<uint2>(ws, L.rects);
+    SurfelRec* recs = at<SurfelRec>(ws, precomputed ? L.recs2 : L.recs);
+    uint32_t* zkeys = at<uint32_t>(ws, precomputed ? L.zkeys2 : L.zkeys);
+    uint2* rects = at<uint2>(ws, precomputed ? L.rects2 : L.rects);
     uint32_t* counts = at<uint32_t>(ws, L.counts);
     uint32_t* offs = at<uint32_t>(ws, L.offs);
-    const SceneArgs sa{scene.pos, scene.quat, scene.scale, scene.opacity, scene.sh, n, scene.sh_degree};
-    HIP_CHECK(launch_preprocess(sa, pc, rp.alpha_min, rp.lowpass, mask, recs, zkeys, rects, counts, s), "preprocess");
+    if (precomputed) {
+        if (!tile_mask) return fail(ctx, BGS_ERR_INVALID_ARG, "precomputed records need a tile mask");
+        HIP_CHECK(launch_masked_counts(rects, n, mask, counts, s), "masked counts");
+    } else {
+        const SceneArgs sa{scene.pos, scene.quat, scene.scale, scene.opacity, scene.sh, n, scene.sh_degree};
+        PreCam pn{};
+        if (cam_next) pn = make_precam(*cam_next);
+        HIP_CHECK(launch_preprocess(sa, pc, rp.alpha_min, rp.lowpass, mask, recs, zkeys, rects, counts,
+                                    cam_next ? &pn : nullptr, at<SurfelRec>(ws, L.recs2), at<uint32_t>(ws, L.zkeys2),
+                                    at<uint2>(ws, L.rects2), s),
+                  "preprocess");
+    }
     mark(ctx, sb + 0, 1);
     // Compositing order: surfels sorted by (fp32 centre-depth bits, index).
     mark(ctx, sb + 1, 0);
@@ -345,8 +364,14 @@ int raster_pass(bgs_ctx* ctx, const Layout& L, void* ws, int64_t kc, const bgs_s
     if (order_out) *order_out = order;
     mark(ctx, sb + 1, 1);
     mark(ctx, sb + 2, 0);
-    HIP_CHECK(exclusive_scan(counts, order, offs, nullptr, n, at<uint32_t>(ws, L.surf_scan), s), "count scan");
-    HIP_CHECK(launch_status_keys(offs, n, st, (uint32_t)kc, which, s), "key count");
+    hipError_t se = hipSuccess;
+    if (scan_counts(counts, order, offs, n, at<uint32_t>(ws, L.surf_scan), KeyCount{st, (uint32_t)kc, which}, s,
+                    &se)) {
+        HIP_CHECK(se, "count scan");
+    } else {
+        HIP_CHECK(exclusive_scan(counts, order, offs, nullptr, n, at<uint32_t>(ws, L.surf_scan), s), "count scan");
+        HIP_CHECK(launch_status_keys(offs, n, st, (uint32_t)kc, which, s), "key count");
+    }
     uint32_t* tka = at<uint32_t>(ws, L.tkeys_a);
     uint32_t* tva = at<uint32_t>(ws, L.tvals_a);
     uint32_t* tkb = at<uint32_t>(ws, L.tkeys_b);
@@ -640,7 +665,7 @@ int32_t bgs_render_stereo(bgs_ctx* ctx, const bgs_scene* scene, const bgs_camera
     // Stage 1: dominant eye with the depth proxy.
     const uint32_t* dom_order = nullptr;
     rc = raster_pass(ctx, L, ws, kc, *scene, *cam_dom, *raster, nullptr, 0.f,
-                     RasterOut{rgb_dom, depth_raw_dom, alpha_dom, nullptr}, 0, nullptr, &dom_order);
+                     RasterOut{rgb_dom, depth_raw_dom, alpha_dom, nullptr}, 0, nullptr, &dom_order, cam_aff);
     if (rc) return rc;
     // The affiliated eye's compositing order equals the dominant one when
     // their fp32 centre-depth key coefficients and near planes coincide bit
@@ -671,7 +696,8 @@ int32_t bgs_render_stereo(bgs_ctx* ctx, const bgs_scene* scene, const bgs_camera
     mark(ctx, BGS_STAGE_CLASSIFY, 1);
     // Stage 4: ROI re-rasterisation of the affiliated eye.
     rc = raster_pass(ctx, L, ws, kc, *scene, *cam_aff, *raster, tile_mask, roi->a_min,
-                     RasterOut{rgb_aff, z_aff, alpha_aff, cls_aff}, 1, same_keys ? dom_order : nullptr);
+                     RasterOut{rgb_aff, z_aff, alpha_aff, cls_aff}, 1, same_keys ? dom_order : nullptr, nullptr,
+                     nullptr, true);
     if (rc) return rc;
     if (!ctx->sync && !stats) return BGS_OK;
     DevStatus h{};
@@ -752,7 +778,7 @@ int32_t bgs_preprocess_debug(bgs_ctx* ctx, const bgs_scene* scene, const bgs_cam
                        scene->sh_degree};
     const int n = (int)scene->n;
     HIP_CHECK(launch_preprocess(sa, pc, raster->alpha_min, raster->lowpass, MaskArgs{nullptr, 0}, at<SurfelRec>(ws, L.recs),
-                                zkey, at<uint2>(ws, L.rects), counts, ctx->stream),
+                                zkey, at<uint2>(ws, L.rects), counts, nullptr, nullptr, nullptr, nullptr, ctx->stream),
               "preprocess");
     // Unpack the tile rectangles for the caller.
     if (n > 0) {

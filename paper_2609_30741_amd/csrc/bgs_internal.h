@@ -124,6 +124,20 @@ size_t scan_tmp_elems(int64_t n);
 // n_dev is given (at most n_cap), else n_cap.  Elements past n count as 0.
 hipError_t exclusive_scan(const uint32_t* in, const uint32_t* idx, uint32_t* out, const uint32_t* n_dev,
                           int64_t n_cap, uint32_t* tmp, hipStream_t s);
+// Key count of a binning pass, recorded in the status block by the scan of
+// the per-surfel key counts (which: 0 dominant, 1 ROI; cap: key capacity).
+// It also clears the blend-continuation counters of the pass.
+struct KeyCount {
+    DevStatus* st;
+    uint32_t cap;
+    int which;
+};
+// Exclusive scan of n per-surfel counts (gathered through idx) into out[0..n]
+// with the key count recorded, in two launches.  Returns false, launching
+// nothing, when n is beyond its size limit (use exclusive_scan and
+// launch_status_keys then); *err gets the launch status otherwise.
+bool scan_counts(const uint32_t* in, const uint32_t* idx, uint32_t* out, int64_t n, uint32_t* tmp,
+                 const KeyCount& kcnt, hipStream_t s, hipError_t* err);
 size_t radix_tmp_bytes(int64_t n_cap);
 // Stable LSD radix sort of (keys, values) by bits [0, key_bits) with digits
 // of up to 8 bits.  (ka, va) is the input, (kb, vb) the ping-pong buffer (all four
@@ -135,9 +149,14 @@ hipError_t radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, co
                       int64_t n_cap, int key_bits, bool iota, void* tmp, hipStream_t s, bool* in_b);
 
 // ---- rasteriser (raster.hip) --------------------------------------------------
+// cam2 (optional): also the keys, rects and records of a second camera (no
+// key counts: see launch_masked_counts).
 hipError_t launch_preprocess(const SceneArgs& sc, const PreCam& cam, float alpha_min, int lowpass,
                              const MaskArgs& mask, SurfelRec* recs, uint32_t* zkeys, uint2* rects,
-                             uint32_t* counts, hipStream_t s);
+                             uint32_t* counts, const PreCam* cam2, SurfelRec* recs2, uint32_t* zkeys2,
+                             uint2* rects2, hipStream_t s);
+// Key counts within the mask's tiles from precomputed tile rects.
+hipError_t launch_masked_counts(const uint2* rects, int n, const MaskArgs& mask, uint32_t* counts, hipStream_t s);
 hipError_t launch_emit(const uint32_t* order, const uint32_t* offs, const uint2* rects, int n, int tiles_x,
                        const MaskArgs& mask, uint32_t cap, uint32_t* tkeys, uint32_t* tvals, hipStream_t s);
 hipError_t launch_ranges(const uint32_t* tkeys, const uint32_t* n_dev, int64_t cap, uint2* ranges,

@@ -180,40 +180,24 @@ __device__ uint2 strip_band(bool bounded, double c00, double c01, double c02, do
     return make_uint2(nbits, cb | (half_bits_up(w) << 16));
 }
 
-__global__ __launch_bounds__(256) void k_preprocess(SceneArgs sc, PreCam cam, float alpha_min, int lowpass,
-                                                    MaskArgs mask, SurfelRec* __restrict__ recs,
-                                                    uint32_t* __restrict__ zkeys, uint2* __restrict__ rects,
-                                                    uint32_t* __restrict__ counts) {
-    const int k = blockIdx.x * 256 + threadIdx.x;
-    if (k >= sc.n) return;
-    const int n = sc.n;
-    const float px = sc.pos[k], py = sc.pos[n + k], pz = sc.pos[2 * n + k];
-    const float zf = centre_depth_key(cam.zc, px, py, pz);
-    const float op = sc.opacity[k];
-    const uint2 empty = make_uint2(0xFFFFFFFFu, 0u);
-    if (!((double)zf > cam.z_near)) {
-        zkeys[k] = 0xFFFFFFFFu;
-        counts[k] = 0;
-        rects[k] = empty;
-        return;
-    }
-    zkeys[k] = __float_as_uint(zf);
-    if (!(op >= alpha_min)) {  // alpha = min(0.99, o G) <= o can never reach alpha_min
-        counts[k] = 0;
-        rects[k] = empty;
-        return;
-    }
+// A surfel seen from one camera: its tile rect and every record word but
+// the colour (geometry in fp64, Sec. 3.3).  drawn = false: no pixel of this
+// camera can get alpha >= alpha_min from it.
+struct SurfelView {
+    bool drawn;
+    int tx0, ty0, tx1, ty1;
+    SurfelRec rec;  // rec.d.xyz (colour) left for the caller
+};
+
+__device__ __forceinline__ void surfel_view(const PreCam& cam, float px, float py, float pz, float op,
+                                            const double tu[3], const double tv[3], double su, double sv,
+                                            float alpha_min, int lowpass, SurfelView& v) {
+    v.drawn = false;
     // ---- geometry in fp64 ----
     const double d0 = (double)px - cam.t[0], d1 = (double)py - cam.t[1], d2 = (double)pz - cam.t[2];
     double pc[3];
 #pragma unroll
     for (int r = 0; r < 3; ++r) pc[r] = cam.Rt[r * 3 + 0] * d0 + cam.Rt[r * 3 + 1] * d1 + cam.Rt[r * 3 + 2] * d2;
-    double qw = sc.quat[k], qx = sc.quat[n + k], qy = sc.quat[2 * n + k], qz = sc.quat[3 * n + k];
-    const double qn = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
-    qw *= qn; qx *= qn; qy *= qn; qz *= qn;
-    // Columns t_u, t_v of the quaternion's rotation matrix (Sec. 3.3).
-    const double tu[3] = {1.0 - 2.0 * (qy * qy + qz * qz), 2.0 * (qx * qy + qw * qz), 2.0 * (qx * qz - qw * qy)};
-    const double tv[3] = {2.0 * (qx * qy - qw * qz), 1.0 - 2.0 * (qx * qx + qz * qz), 2.0 * (qy * qz + qw * qx)};
     double a[3], b[3];
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
@@ -221,7 +205,6 @@ __global__ __launch_bounds__(256) void k_preprocess(SceneArgs sc, PreCam cam, fl
         b[r] = cam.Rt[r * 3 + 0] * tv[0] + cam.Rt[r * 3 + 1] * tv[1] + cam.Rt[r * 3 + 2] * tv[2];
     }
     const double nv[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
-    const double su = sc.scale[k], sv = sc.scale[n + k];
     const double pzc = pc[2];
     const double mux = cam.fx * pc[0] / pzc + cam.cx;
     const double muy = cam.fy * pc[1] / pzc + cam.cy;
@@ -275,38 +258,15 @@ __global__ __launch_bounds__(256) void k_preprocess(SceneArgs sc, PreCam cam, fl
     const double pady = 0.02 + 1e-7 * (fabs(ymin) + fabs(ymax));
     const double fx0 = fmax(ceil(xmin - padx), 0.0), fx1 = fmin(floor(xmax + padx), (double)(cam.W - 1));
     const double fy0 = fmax(ceil(ymin - pady), 0.0), fy1 = fmin(floor(ymax + pady), (double)(cam.H - 1));
-    if (!(fx0 <= fx1 && fy0 <= fy1)) {
-        counts[k] = 0;
-        rects[k] = empty;
-        return;
-    }
+    if (!(fx0 <= fx1 && fy0 <= fy1)) return;
     const int x0 = (int)fx0, x1 = (int)fx1, y0 = (int)fy0, y1 = (int)fy1;
     const uint2 band = strip_band(bounded, c00, c01, c02, c11, c12, c22, cam, mux, muy,
                                   lowpass ? sqrt(lr) * (1.0 + 1e-5) : 0.0, xmin, xmax, ymin, ymax);
-    const int tx0 = x0 / kTile, tx1 = x1 / kTile, ty0 = y0 / kTile, ty1 = y1 / kTile;
-    const uint32_t cnt = mask.enabled ? masked_count(mask, tx0, ty0, tx1, ty1)
-                                      : (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1));
-    counts[k] = cnt;
-    rects[k] = make_uint2((uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tx1 | ((uint32_t)ty1 << 16));
-    if (cnt == 0) return;
-
-    // ---- colour: SH towards the surfel from this camera's centre ----
-    float col[3];
-    {
-        float dirx = (float)((double)px - cam.t[0]), diry = (float)((double)py - cam.t[1]),
-              dirz = (float)((double)pz - cam.t[2]);
-        const float inv = rsqrtf(dirx * dirx + diry * diry + dirz * dirz);
-        dirx *= inv; diry *= inv; dirz *= inv;
-        float Y[16];
-        sh_basis(sc.sh_degree, dirx, diry, dirz, Y);
-        const int nc = (sc.sh_degree + 1) * (sc.sh_degree + 1);
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            float acc = 0.f;
-            for (int c = 0; c < nc; ++c) acc += Y[c] * sc.sh[(int64_t)(c * 3 + ch) * n + k];
-            col[ch] = fmaxf(acc + 0.5f, 0.f);
-        }
-    }
+    v.tx0 = x0 / kTile;
+    v.tx1 = x1 / kTile;
+    v.ty0 = y0 / kTile;
+    v.ty1 = y1 / kTile;
+    v.drawn = true;
 
     // ---- plane-to-screen homography centred at the projected centre ----
     // With r_c = p/p_z and delta = ((i-mu_x)/fx, (j-mu_y)/fy, 0) the pixel
@@ -338,12 +298,118 @@ __global__ __launch_bounds__(256) void k_preprocess(SceneArgs sc, PreCam cam, fl
             lam_num = (float)pzc;
         }
     }
-    SurfelRec rec;
-    rec.a = make_float4((float)mux, (float)muy, C1, C2);
-    rec.b = make_float4(D1, D2, N1, N2);
-    rec.c = make_float4(lam_num, (float)pzc, op, __uint_as_float(band.x));
-    rec.d = make_float4(col[0], col[1], col[2], __uint_as_float(band.y));
-    recs[k] = rec;
+    v.rec.a = make_float4((float)mux, (float)muy, C1, C2);
+    v.rec.b = make_float4(D1, D2, N1, N2);
+    v.rec.c = make_float4(lam_num, (float)pzc, op, __uint_as_float(band.x));
+    v.rec.d = make_float4(0.f, 0.f, 0.f, __uint_as_float(band.y));
+}
+
+__device__ __forceinline__ void sh_dir(const PreCam& cam, float px, float py, float pz, float* d) {
+    float dirx = (float)((double)px - cam.t[0]), diry = (float)((double)py - cam.t[1]),
+          dirz = (float)((double)pz - cam.t[2]);
+    const float inv = rsqrtf(dirx * dirx + diry * diry + dirz * dirz);
+    d[0] = dirx * inv;
+    d[1] = diry * inv;
+    d[2] = dirz * inv;
+}
+
+// Per surfel: the centre-depth key, tile rect, key count and record for
+// `cam`; with kTwo also the key, rect and record for cam2 (the other eye of
+// a stereo frame, whose key counts depend on a tile mask known only later).
+// The scene is read once; the colours of both eyes come from one pass over
+// the SH coefficients, each toward its own camera centre.
+template <bool kTwo>
+__global__ __launch_bounds__(256) void k_preprocess(SceneArgs sc, PreCam cam, PreCam cam2, float alpha_min,
+                                                    int lowpass, MaskArgs mask, SurfelRec* __restrict__ recs,
+                                                    uint32_t* __restrict__ zkeys, uint2* __restrict__ rects,
+                                                    uint32_t* __restrict__ counts, SurfelRec* __restrict__ recs2,
+                                                    uint32_t* __restrict__ zkeys2, uint2* __restrict__ rects2) {
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= sc.n) return;
+    const int n = sc.n;
+    const float px = sc.pos[k], py = sc.pos[n + k], pz = sc.pos[2 * n + k];
+    const float op = sc.opacity[k];
+    const uint2 empty = make_uint2(0xFFFFFFFFu, 0u);
+    const float zf = centre_depth_key(cam.zc, px, py, pz);
+    const bool in1 = (double)zf > cam.z_near;
+    float zf2 = 0.f;
+    bool in2 = false;
+    if (kTwo) {
+        zf2 = centre_depth_key(cam2.zc, px, py, pz);
+        in2 = (double)zf2 > cam2.z_near;
+        zkeys2[k] = in2 ? __float_as_uint(zf2) : 0xFFFFFFFFu;
+    }
+    zkeys[k] = in1 ? __float_as_uint(zf) : 0xFFFFFFFFu;
+    // alpha = min(0.99, o G) <= o can never reach alpha_min below it.
+    const bool live = op >= alpha_min;
+    SurfelView v1, v2;
+    v1.drawn = v2.drawn = false;
+    if (live && (in1 || in2)) {
+        double qw = sc.quat[k], qx = sc.quat[n + k], qy = sc.quat[2 * n + k], qz = sc.quat[3 * n + k];
+        const double qn = 1.0 / sqrt(qw * qw + qx * qx + qy * qy + qz * qz);
+        qw *= qn; qx *= qn; qy *= qn; qz *= qn;
+        // Columns t_u, t_v of the quaternion's rotation matrix (Sec. 3.3).
+        const double tu[3] = {1.0 - 2.0 * (qy * qy + qz * qz), 2.0 * (qx * qy + qw * qz), 2.0 * (qx * qz - qw * qy)};
+        const double tv[3] = {2.0 * (qx * qy - qw * qz), 1.0 - 2.0 * (qx * qx + qz * qz), 2.0 * (qy * qz + qw * qx)};
+        const double su = sc.scale[k], sv = sc.scale[n + k];
+        if (in1) surfel_view(cam, px, py, pz, op, tu, tv, su, sv, alpha_min, lowpass, v1);
+        if (kTwo && in2) surfel_view(cam2, px, py, pz, op, tu, tv, su, sv, alpha_min, lowpass, v2);
+    }
+    uint32_t cnt = 0;
+    if (v1.drawn) {
+        cnt = mask.enabled ? masked_count(mask, v1.tx0, v1.ty0, v1.tx1, v1.ty1)
+                           : (uint32_t)((v1.tx1 - v1.tx0 + 1) * (v1.ty1 - v1.ty0 + 1));
+        rects[k] = make_uint2((uint32_t)v1.tx0 | ((uint32_t)v1.ty0 << 16), (uint32_t)v1.tx1 | ((uint32_t)v1.ty1 << 16));
+    } else {
+        rects[k] = empty;
+    }
+    counts[k] = cnt;
+    if (kTwo)
+        rects2[k] = v2.drawn ? make_uint2((uint32_t)v2.tx0 | ((uint32_t)v2.ty0 << 16),
+                                          (uint32_t)v2.tx1 | ((uint32_t)v2.ty1 << 16))
+                             : empty;
+    const bool col1 = cnt > 0, col2 = kTwo && v2.drawn;
+    if (!col1 && !col2) return;
+    // ---- colour: SH towards the surfel from each camera's centre ----
+    float d1[3] = {0.f, 0.f, 1.f}, d2[3] = {0.f, 0.f, 1.f};
+    if (col1) sh_dir(cam, px, py, pz, d1);
+    if (col2) sh_dir(cam2, px, py, pz, d2);
+    float Y1[16], Y2[16];
+    sh_basis(sc.sh_degree, d1[0], d1[1], d1[2], Y1);
+    if (kTwo) sh_basis(sc.sh_degree, d2[0], d2[1], d2[2], Y2);
+    const int nc = (sc.sh_degree + 1) * (sc.sh_degree + 1);
+    float acc1[3] = {0.f, 0.f, 0.f}, acc2[3] = {0.f, 0.f, 0.f};
+    for (int c = 0; c < nc; ++c) {
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            const float q = sc.sh[(int64_t)(c * 3 + ch) * n + k];
+            acc1[ch] += Y1[c] * q;
+            if (kTwo) acc2[ch] += Y2[c] * q;
+        }
+    }
+    if (col1) {
+        v1.rec.d.x = fmaxf(acc1[0] + 0.5f, 0.f);
+        v1.rec.d.y = fmaxf(acc1[1] + 0.5f, 0.f);
+        v1.rec.d.z = fmaxf(acc1[2] + 0.5f, 0.f);
+        recs[k] = v1.rec;
+    }
+    if (col2) {
+        v2.rec.d.x = fmaxf(acc2[0] + 0.5f, 0.f);
+        v2.rec.d.y = fmaxf(acc2[1] + 0.5f, 0.f);
+        v2.rec.d.z = fmaxf(acc2[2] + 0.5f, 0.f);
+        recs2[k] = v2.rec;
+    }
+}
+
+// Key counts of surfels whose tile rects were computed earlier, restricted
+// to the tiles of a mask.
+__global__ __launch_bounds__(256) void k_masked_counts(const uint2* __restrict__ rects, int n, MaskArgs mask,
+                                                       uint32_t* __restrict__ counts) {
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= n) return;
+    const uint2 r = rects[k];
+    counts[k] = r.x > r.y ? 0u : masked_count(mask, (int)(r.x & 0xFFFFu), (int)(r.x >> 16), (int)(r.y & 0xFFFFu),
+                                              (int)(r.y >> 16));
 }
 
 // ---------------------------------------------------------------------------
@@ -1128,10 +1194,22 @@ __global__ __launch_bounds__(256) void k_blend_fix(const SurfelRec* __restrict__
 
 hipError_t launch_preprocess(const SceneArgs& sc, const PreCam& cam, float alpha_min, int lowpass,
                              const MaskArgs& mask, SurfelRec* recs, uint32_t* zkeys, uint2* rects,
-                             uint32_t* counts, hipStream_t s) {
+                             uint32_t* counts, const PreCam* cam2, SurfelRec* recs2, uint32_t* zkeys2,
+                             uint2* rects2, hipStream_t s) {
     if (sc.n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_preprocess, dim3((sc.n + 255) / 256), dim3(256), 0, s, sc, cam, alpha_min, lowpass, mask,
-                       recs, zkeys, rects, counts);
+    const dim3 g((sc.n + 255) / 256);
+    if (cam2)
+        hipLaunchKernelGGL(k_preprocess<true>, g, dim3(256), 0, s, sc, cam, *cam2, alpha_min, lowpass, mask, recs, zkeys,
+                           rects, counts, recs2, zkeys2, rects2);
+    else
+        hipLaunchKernelGGL(k_preprocess<false>, g, dim3(256), 0, s, sc, cam, cam, alpha_min, lowpass, mask, recs, zkeys,
+                           rects, counts, nullptr, nullptr, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_masked_counts(const uint2* rects, int n, const MaskArgs& mask, uint32_t* counts, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_masked_counts, dim3((n + 255) / 256), dim3(256), 0, s, rects, n, mask, counts);
     return hipGetLastError();
 }
 

@@ -86,9 +86,63 @@ __global__ __launch_bounds__(256) void k_scan_down(const uint32_t* in, const uin
     }
 }
 
-int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+// Two-launch form for up to kScanFlat blocks: every block adds up the block
+// sums before its own (at most kScanFlat / 256 loads per thread), so no
+// second level is needed.  With status given, the thread that writes out[n]
+// also records the total as the pass's key count (see KeyCount).
+constexpr int64_t kScanFlat = 4096;
+
+__global__ __launch_bounds__(256) void k_scan_down_flat(const uint32_t* in, const uint32_t* __restrict__ idx,
+                                                        const uint32_t* __restrict__ n_dev, int64_t n_cap,
+                                                        const uint32_t* __restrict__ partials, uint32_t* out,
+                                                        KeyCount kcnt) {
+    __shared__ uint32_t lds[4];
+    const int64_t n = n_dev ? (int64_t)*n_dev : n_cap;
+    uint32_t pre = 0;
+    for (uint32_t b = threadIdx.x; b < blockIdx.x; b += 256) pre += partials[b];
+    pre = block_sum(pre, lds);
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint32_t s = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        int64_t i = base + j;
+        v[j] = (i < n) ? in[idx ? idx[i] : i] : 0u;
+        s += v[j];
+    }
+    uint32_t run = block_excl_scan(s, lds, nullptr) + pre;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        int64_t i = base + j;
+        if (i <= n) out[i] = run;
+        if (i == n && kcnt.st) {
+            DevStatus* st = kcnt.st;
+            st->n_slots = 0;
+            st->n_items = 0;
+            st->n_keys = run;
+            st->n_sort = run < kcnt.cap ? run : kcnt.cap;
+            if (run > kcnt.cap) st->overflow |= 1u;
+            if (kcnt.which == 0) st->n_keys_dom = run;
+            else st->n_keys_roi = run;
+        }
+        run += v[j];
+    }
+}
 
 }  // namespace
+
+static inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+bool scan_counts(const uint32_t* in, const uint32_t* idx, uint32_t* out, int64_t n, uint32_t* tmp,
+                 const KeyCount& kcnt, hipStream_t s, hipError_t* err) {
+    const int64_t nb = ceil_div(n + 1, kScanBlock);
+    if (nb > kScanFlat) return false;
+    if (nb > 1)
+        hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(256), 0, s, in, idx, nullptr, n, tmp);
+    hipLaunchKernelGGL(k_scan_down_flat, dim3((unsigned)nb), dim3(256), 0, s, in, idx, nullptr, n, tmp, out, kcnt);
+    *err = hipGetLastError();
+    return true;
+}
 
 size_t scan_tmp_elems(int64_t n) {
     // Level l scans n_l elements (n_0 = n) with ceil((n_l + 1) / block)
