@@ -380,8 +380,9 @@ int raster_pass(bgs_ctx* ctx, const Layout& L, void* ws, int64_t kc, const bgs_s
     mark(ctx, sb + 2, 1);
     // Stable sort by tile: within a tile the emission (= compositing) order stays.
     mark(ctx, sb + 3, 0);
+    // An ROI pass bins a small part of the tiles: a small sort is expected.
     HIP_CHECK(radix_sort(tka, tva, tkb, tvb, &st->n_sort, kc, tile_bits(n_tiles), false, at<void>(ws, L.radix), s,
-                         &in_b),
+                         &in_b, tile_mask ? 1 : 0),
               "tile sort");
     const uint32_t* skeys = in_b ? tkb : tka;
     const uint32_t* svals = in_b ? tvb : tva;

@@ -144,9 +144,12 @@ size_t radix_tmp_bytes(int64_t n_cap);
 // are real buffers); iota = true ignores the input values and uses the
 // input positions instead.  The element count is *n_dev (<= n_cap), or
 // n_cap when n_dev is null.
-// Returns in *in_b whether the result is in (kb, vb).
+// Returns in *in_b whether the result is in (kb, vb).  n_hint (optional):
+// the expected element count when it is far below n_cap; it only chooses
+// the kernels' sub-chunk size, never the result.
 hipError_t radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, const uint32_t* n_dev,
-                      int64_t n_cap, int key_bits, bool iota, void* tmp, hipStream_t s, bool* in_b);
+                      int64_t n_cap, int key_bits, bool iota, void* tmp, hipStream_t s, bool* in_b,
+                      int64_t n_hint = 0);
 
 // ---- rasteriser (raster.hip) --------------------------------------------------
 // cam2 (optional): also the keys, rects and records of a second camera (no

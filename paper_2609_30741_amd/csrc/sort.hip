@@ -179,16 +179,17 @@ hipError_t exclusive_scan(const uint32_t* in, const uint32_t* idx, uint32_t* out
 // ---------------------------------------------------------------------------
 // Radix sort.  Stable LSD with digits of up to 8 bits (a 32-bit key takes four
 // passes, an 11-bit tile id two of 6 and 5 bits).  The grid is fixed by the
-// capacity (at most kRsGrid blocks); block b owns the contiguous chunk
-// [b C, b C + C) of the *n_dev keys, C = n / grid rounded up to 256.  A pass
-// is three launches:
+// capacity (at most kRsGrid blocks; always kRsGrid for small sorts, which
+// use 1024-key sub-chunks instead of 4096); block b owns the contiguous
+// chunk [b C, b C + C) of the *n_dev keys, C = n / grid rounded up to 256.
+// A pass is three launches:
 //   1. k_rs_hist: per-block digit counts (LDS, match-any aggregated), stored
 //      digit-major: counts[d * grid + b].
 //   2. k_rs_scan: one block per digit scans its row over the blocks and
 //      writes the digit total.
 //   3. k_rs_scatter: every block scans the digit totals, then walks its chunk
 //      in sub-chunks of 4096 keys: each wave ranks its 1024 keys in 16 steps
-//      of 64 with match-any ballots and a per-wave LDS count per digit, the
+//      of 64 (a quarter of that for small sorts) with match-any ballots and a per-wave LDS count per digit, the
 //      sub-chunk is reordered by digit in LDS, and each digit's run (16 keys
 //      on average at 8 bits) is written out contiguously.
 // Blocks never wait on each other.
@@ -198,8 +199,10 @@ namespace {
 constexpr int kRsMaxBits = 8;
 constexpr int kRsBins = 1 << kRsMaxBits;
 constexpr int kRsGrid = 1024;
-constexpr int kRsItems = 16;                 // keys per thread per sub-chunk
-constexpr int kRsSub = 256 * kRsItems;       // 4096
+// Keys per thread per sub-chunk: 16 (4096-key sub-chunks, long digit runs)
+// for large sorts; 4 (1024-key sub-chunks) for small ones, where a block
+// holds only a few hundred keys and its latency is the sort's.
+constexpr int kRsItemsBig = 16, kRsItemsSmall = 4;
 
 __device__ inline uint64_t match_digit(uint32_t d, uint64_t valid, int bits) {
     uint64_t peers = valid;
@@ -213,7 +216,11 @@ __device__ inline uint64_t match_digit(uint32_t d, uint64_t valid, int bits) {
     return peers;
 }
 
-__device__ inline void chunk_of(uint32_t n, uint32_t grid, uint32_t b, uint32_t* lo, uint32_t* hi) {
+// Block b's chunk: n / grid keys rounded up to a multiple of 256 (and to at
+// least one key per thread).  sub (the sub-chunk size) is unused here but
+// keeps the chunking tied to the kernel's instance.
+__device__ inline void chunk_of(uint32_t n, uint32_t grid, uint32_t b, uint32_t sub, uint32_t* lo, uint32_t* hi) {
+    (void)sub;
     const uint32_t per = (uint32_t)(((uint64_t)n + grid - 1) / grid);
     const uint64_t c = ((uint64_t)per + 255u) & ~255ull;
     const uint64_t l = min<uint64_t>((uint64_t)b * c, n);
@@ -221,15 +228,17 @@ __device__ inline void chunk_of(uint32_t n, uint32_t grid, uint32_t b, uint32_t*
     *hi = (uint32_t)min<uint64_t>(l + c, n);
 }
 
+template <int kRsItems>
 __global__ __launch_bounds__(256) void k_rs_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_dev,
                                                  uint32_t n_host, int shift, int bits,
                                                  uint32_t* __restrict__ counts) {
+    constexpr int kRsSub = 256 * kRsItems;
     __shared__ uint32_t h[kRsBins];
     const uint32_t n = n_dev ? *n_dev : n_host, bins = 1u << bits, mask = bins - 1u;
     h[threadIdx.x] = 0;
     __syncthreads();
     uint32_t lo, hi;
-    chunk_of(n, gridDim.x, blockIdx.x, &lo, &hi);
+    chunk_of(n, gridDim.x, blockIdx.x, kRsSub, &lo, &hi);
     const uint64_t lt = (1ull << lane_id()) - 1ull;
     for (uint64_t sub = lo; sub < hi; sub += kRsSub) {
         uint32_t k[kRsItems];
@@ -274,11 +283,13 @@ __global__ __launch_bounds__(256) void k_rs_scan(uint32_t* __restrict__ counts, 
     if (threadIdx.x == 0) totals[blockIdx.x] = tot;
 }
 
+template <int kRsItems>
 __global__ __launch_bounds__(256) void k_rs_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                     uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                     const uint32_t* __restrict__ n_dev, uint32_t n_host, int shift,
                                                     int bits, const uint32_t* __restrict__ counts,
                                                     const uint32_t* __restrict__ totals) {
+    constexpr int kRsSub = 256 * kRsItems;
     __shared__ uint32_t s_keys[kRsSub];
     __shared__ uint32_t s_vals[kRsSub];
     __shared__ uint32_t cnt[4][kRsBins];
@@ -288,7 +299,7 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const uint32_t* __restrict__
     __shared__ uint32_t lds[4];
     const uint32_t n = n_dev ? *n_dev : n_host, bins = 1u << bits, mask = bins - 1u;
     uint32_t lo, hi;
-    chunk_of(n, gridDim.x, blockIdx.x, &lo, &hi);
+    chunk_of(n, gridDim.x, blockIdx.x, kRsSub, &lo, &hi);
     if (lo >= hi) return;
     const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
     const uint64_t lt = (1ull << lane) - 1ull;
@@ -365,23 +376,28 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const uint32_t* __restrict__
     }
 }
 
-uint32_t rs_grid(int64_t n_cap) {
-    const int64_t g = ceil_div(n_cap > 0 ? n_cap : 1, kRsSub);
+uint32_t rs_grid(int64_t n_cap, int items) {
+    const int64_t g = ceil_div(n_cap > 0 ? n_cap : 1, 256 * items);
     return (uint32_t)(g < kRsGrid ? g : kRsGrid);
 }
 
 }  // namespace
 
 size_t radix_tmp_bytes(int64_t n_cap) {
-    return ((size_t)kRsBins * rs_grid(n_cap) + kRsBins + 64) * sizeof(uint32_t) + 256;
+    return ((size_t)kRsBins * kRsGrid + kRsBins + 64) * sizeof(uint32_t) + 256;
 }
 
 hipError_t radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, const uint32_t* n_dev,
-                      int64_t n_cap, int key_bits, bool iota, void* tmp, hipStream_t s, bool* in_b) {
+                      int64_t n_cap, int key_bits, bool iota, void* tmp, hipStream_t s, bool* in_b, int64_t n_hint) {
     *in_b = false;
     if (n_cap <= 0 || key_bits <= 0) return hipSuccess;
     if (n_cap > 0xFFFFFFFFll) return hipErrorInvalidValue;
-    const uint32_t grid = rs_grid(n_cap);
+    // Small sorts (expected keys per block of the full grid below 4096):
+    // 1024-key sub-chunks.
+    const int64_t n_exp = n_hint > 0 && n_hint < n_cap ? n_hint : n_cap;
+    const bool small = n_exp <= (int64_t)kRsGrid * 256 * kRsItemsSmall;
+    const int items = small ? kRsItemsSmall : kRsItemsBig;
+    const uint32_t grid = small ? kRsGrid : rs_grid(n_cap, items);
     uint32_t* counts = (uint32_t*)tmp;
     uint32_t* totals = counts + (size_t)kRsBins * grid;
     const int passes = (key_bits + kRsMaxBits - 1) / kRsMaxBits;
@@ -391,10 +407,19 @@ hipError_t radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, co
     bool cur_b = false;
     for (int shift = 0; shift < key_bits; shift += per) {
         const int bits = key_bits - shift < per ? key_bits - shift : per;
-        hipLaunchKernelGGL(k_rs_hist, dim3(grid), dim3(256), 0, s, ki, n_dev, (uint32_t)n_cap, shift, bits, counts);
+        if (small)
+            hipLaunchKernelGGL(k_rs_hist<kRsItemsSmall>, dim3(grid), dim3(256), 0, s, ki, n_dev, (uint32_t)n_cap, shift,
+                               bits, counts);
+        else
+            hipLaunchKernelGGL(k_rs_hist<kRsItemsBig>, dim3(grid), dim3(256), 0, s, ki, n_dev, (uint32_t)n_cap, shift,
+                               bits, counts);
         hipLaunchKernelGGL(k_rs_scan, dim3(1u << bits), dim3(256), 0, s, counts, grid, totals);
-        hipLaunchKernelGGL(k_rs_scatter, dim3(grid), dim3(256), 0, s, ki, vi, ko, vo, n_dev, (uint32_t)n_cap, shift,
-                           bits, counts, totals);
+        if (small)
+            hipLaunchKernelGGL(k_rs_scatter<kRsItemsSmall>, dim3(grid), dim3(256), 0, s, ki, vi, ko, vo, n_dev,
+                               (uint32_t)n_cap, shift, bits, counts, totals);
+        else
+            hipLaunchKernelGGL(k_rs_scatter<kRsItemsBig>, dim3(grid), dim3(256), 0, s, ki, vi, ko, vo, n_dev,
+                               (uint32_t)n_cap, shift, bits, counts, totals);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         cur_b = !cur_b;
