@@ -365,12 +365,14 @@ int raster_pass(bgs_ctx* ctx, const Layout& L, void* ws, int64_t kc, const bgs_s
     mark(ctx, sb + 1, 1);
     mark(ctx, sb + 2, 0);
     hipError_t se = hipSuccess;
-    if (scan_counts(counts, order, offs, n, at<uint32_t>(ws, L.surf_scan), KeyCount{st, (uint32_t)kc, which}, s,
-                    &se)) {
+    uint2* ranges = at<uint2>(ws, L.ranges);
+    if (scan_counts(counts, order, offs, n, at<uint32_t>(ws, L.surf_scan),
+                    KeyCount{st, (uint32_t)kc, which, ranges, (uint32_t)n_tiles}, s, &se)) {
         HIP_CHECK(se, "count scan");
     } else {
         HIP_CHECK(exclusive_scan(counts, order, offs, nullptr, n, at<uint32_t>(ws, L.surf_scan), s), "count scan");
         HIP_CHECK(launch_status_keys(offs, n, st, (uint32_t)kc, which, s), "key count");
+        HIP_CHECK(launch_clear_ranges(ranges, n_tiles, s), "range clear");
     }
     uint32_t* tka = at<uint32_t>(ws, L.tkeys_a);
     uint32_t* tva = at<uint32_t>(ws, L.tvals_a);
@@ -387,7 +389,6 @@ int raster_pass(bgs_ctx* ctx, const Layout& L, void* ws, int64_t kc, const bgs_s
     const uint32_t* skeys = in_b ? tkb : tka;
     const uint32_t* svals = in_b ? tvb : tva;
     mark(ctx, sb + 3, 1);
-    uint2* ranges = at<uint2>(ws, L.ranges);
     mark(ctx, sb + 4, 0);
     HIP_CHECK(launch_ranges(skeys, &st->n_sort, kc, ranges, n_tiles, s), "ranges");
     uint32_t* torder = at<uint32_t>(ws, L.torder);

@@ -131,6 +131,8 @@ struct KeyCount {
     DevStatus* st;
     uint32_t cap;
     int which;
+    uint2* ranges;     // tile ranges to clear to empty (n_tiles of them)
+    uint32_t n_tiles;
 };
 // Exclusive scan of n per-surfel counts (gathered through idx) into out[0..n]
 // with the key count recorded, in two launches.  Returns false, launching
@@ -162,8 +164,11 @@ hipError_t launch_preprocess(const SceneArgs& sc, const PreCam& cam, float alpha
 hipError_t launch_masked_counts(const uint2* rects, int n, const MaskArgs& mask, uint32_t* counts, hipStream_t s);
 hipError_t launch_emit(const uint32_t* order, const uint32_t* offs, const uint2* rects, int n, int tiles_x,
                        const MaskArgs& mask, uint32_t cap, uint32_t* tkeys, uint32_t* tvals, hipStream_t s);
+// Tile ranges of the sorted keys; the ranges must have been cleared (by
+// scan_counts, or launch_clear_ranges).
 hipError_t launch_ranges(const uint32_t* tkeys, const uint32_t* n_dev, int64_t cap, uint2* ranges,
                          int n_tiles, hipStream_t s);
+hipError_t launch_clear_ranges(uint2* ranges, int n_tiles, hipStream_t s);
 // Dispatch order of the (compact) tiles for the blend, heaviest first.
 hipError_t launch_tile_order(const uint2* ranges, const uint32_t* n_live, int n_tiles, uint32_t* order,
                              hipStream_t s);

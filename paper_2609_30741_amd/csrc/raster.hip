@@ -3,6 +3,8 @@
 // the joint depth proxy (Sec. 3.1 Stage 1, Sec. 3.3 Eq. 1-2).
 #include <cmath>
 
+#include <algorithm>
+
 #include "bgs_internal.h"
 
 namespace bgs {
@@ -473,27 +475,38 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order
     }
 }
 
-// [start, end) of every tile in the sorted keys, by binary search (a tile
-// with no key gets an empty range).
+// [start, end) of every tile in the sorted keys: a key that differs from
+// its predecessor starts its tile's range and ends the predecessor's.  The
+// ranges were cleared to empty beforehand (by the count scan), so a tile
+// with no key keeps an empty range.  Grid-stride over the *n_dev keys.
+// Each thread takes four consecutive keys (one 16-byte load; the keys
+// buffer is 16-byte aligned) and the key before them.
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_dev,
                                                 uint2* __restrict__ ranges, uint32_t n_tiles) {
-    const uint32_t t = blockIdx.x * 256 + threadIdx.x;
-    if (t >= n_tiles) return;
     const uint32_t n = *n_dev;
-    uint32_t lo = 0, hi = n;
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (keys[mid] < t) lo = mid + 1;
-        else hi = mid;
+    for (uint64_t q = (uint64_t)blockIdx.x * 256 + threadIdx.x; 4 * q < n; q += (uint64_t)gridDim.x * 256) {
+        const uint32_t i0 = (uint32_t)(4 * q);
+        uint32_t k[4];
+        if (i0 + 3 < n) {
+            const uint4 v = *reinterpret_cast<const uint4*>(keys + i0);
+            k[0] = v.x; k[1] = v.y; k[2] = v.z; k[3] = v.w;
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) k[u] = i0 + u < n ? keys[i0 + u] : 0xFFFFFFFFu;
+        }
+        uint32_t prev = i0 > 0 ? keys[i0 - 1] : 0xFFFFFFFFu;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t i = i0 + u;
+            if (i >= n) break;
+            if (k[u] != prev) {
+                if (k[u] < n_tiles) ranges[k[u]].x = i;
+                if (i > 0 && prev < n_tiles) ranges[prev].y = i;
+            }
+            if (i + 1 == n && k[u] < n_tiles) ranges[k[u]].y = n;
+            prev = k[u];
+        }
     }
-    const uint32_t start = lo;
-    hi = n;
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (keys[mid] <= t) lo = mid + 1;
-        else hi = mid;
-    }
-    ranges[t] = make_uint2(start, lo);
 }
 
 __global__ void k_status_keys(const uint32_t* __restrict__ offs, int n, DevStatus* st, uint32_t cap, int which) {
@@ -643,7 +656,11 @@ constexpr int kBatch = 256;
 constexpr int kTrip = 4;                // records per trip of the walk
 constexpr int kDummy = kBatch;          // LDS record index of the zero record
 constexpr int kListLen = kBatch + 4;    // per-wave hit list, with padding
-constexpr uint32_t kRoundSeg = 4;       // continuation segments walked in the first round
+// Continuation segments are walked in kRounds rounds: round r takes the
+// segments [round_lo(r), round_lo(r + 1)) of every continued tile.
+constexpr int kRounds = 2;
+__host__ __device__ constexpr uint32_t round_lo(int r) { return r <= 0 ? 0u : r == 1 ? 4u : kContMaxSeg; }
+static_assert(round_lo(kRounds) == kContMaxSeg, "the rounds cover every segment");
 constexpr uint32_t kChainBatch = 8;     // earlier segments' parts loaded together when chaining
 
 
@@ -1031,11 +1048,12 @@ __device__ __forceinline__ void item_segment(const uint4& d, uint32_t k, uint32_
     *se = d.y + (uint32_t)(rem * (k + 1) / nseg);
 }
 
-// Round 0 walks the first kRoundSeg segments of every continued tile from
-// the transmittance T1 after the capped walk.  Round 1 walks the others,
-// each pixel from its exact transmittance after the round-0 segments (a
-// tighter bound than T1), and only for the pixels that get through round 0:
-// for tiles whose pixels stop soon after the cap, round 1 has no work.
+// Round 0 walks the first segments of every continued tile from the
+// transmittance T1 after the capped walk.  Each later round walks its
+// segments from every pixel's exact transmittance after the segments of the
+// rounds before (a tighter bound than T1), and only for the pixels that get
+// through them: for tiles whose pixels stop soon after the cap, the later
+// rounds have no work.
 template <bool kCount>
 __global__ __launch_bounds__(256) void k_blend_seg(const SurfelRec* __restrict__ recs,
                                                    const uint32_t* __restrict__ vals,
@@ -1052,8 +1070,8 @@ __global__ __launch_bounds__(256) void k_blend_seg(const SurfelRec* __restrict__
         const uint32_t slot = ca.item_slot[item];
         const uint4 d = ca.slot_desc[slot];
         const uint32_t ibase = d.w & ((1u << kContSegShift) - 1u), nseg = d.w >> kContSegShift, k = item - ibase;
-        const uint32_t m = min(nseg, kRoundSeg);
-        if ((k < m) != (round == 0)) continue;
+        const uint32_t lo = round_lo(round);
+        if (k < lo || k >= round_lo(round + 1)) continue;
         uint32_t sb, se;
         item_segment(d, k, &sb, &se);
         bool inside;
@@ -1062,20 +1080,21 @@ __global__ __launch_bounds__(256) void k_blend_seg(const SurfelRec* __restrict__
         const float4 s1 = ca.st1[(size_t)slot * 512 + 2 * tid + 1];
         Chain c{s1.y, 0.f, 0.f, 0.f, 0.f, 0.f};
         bool live = s1.z != 0.f;
-        if (round != 0) {
-            // The m <= kRoundSeg round-0 parts, loaded together.
-            const float4* xb = ca.part + (size_t)ibase * 512 + 2 * tid;
-            float4 x0[kRoundSeg], x1[kRoundSeg];
+        // Chain the lo segments of the earlier rounds, four parts loaded
+        // together at a time.
+        const float4* xb = ca.part + (size_t)ibase * 512 + 2 * tid;
+        for (uint32_t j0 = 0; j0 < lo && live; j0 += 4) {
+            float4 x0[4], x1[4];
 #pragma unroll
-            for (uint32_t j = 0; j < kRoundSeg; ++j) {
-                if (j < m) {
-                    x0[j] = xb[(size_t)j * 512];
-                    x1[j] = xb[(size_t)j * 512 + 1];
+            for (uint32_t u = 0; u < 4; ++u) {
+                if (j0 + u < lo) {
+                    x0[u] = xb[(size_t)(j0 + u) * 512];
+                    x1[u] = xb[(size_t)(j0 + u) * 512 + 1];
                 }
             }
 #pragma unroll
-            for (uint32_t j = 0; j < kRoundSeg; ++j)
-                if (j < m && live) live = chain_step(x0[j], x1[j], a.t_min, c);
+            for (uint32_t u = 0; u < 4; ++u)
+                if (j0 + u < lo && live) live = chain_step(x0[u], x1[u], a.t_min, c);
         }
         const float ts = c.T;
         PixelState p{live ? ts : 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -1089,7 +1108,7 @@ __global__ __launch_bounds__(256) void k_blend_seg(const SurfelRec* __restrict__
     if (kCount) count_flush(wc, tid & 63, tid >> 6, 0, pair_counts, nullptr);
 }
 
-// After both segment rounds, one workgroup per slot chains the segments of
+// After all segment rounds, one workgroup per slot chains the segments of
 // every pixel from the state after the capped walk.  A pixel that never
 // stops is written here, and so is one that stops in a segment walked from
 // its exact transmittance; for one that stops inside any other segment j
@@ -1129,10 +1148,11 @@ __global__ __launch_bounds__(256) void k_blend_chain(const uint32_t* __restrict_
                 const uint32_t j = j0 + u;
                 if (j < nseg && stop == nseg && !chain_step(x0[u], x1[u], a.t_min, c)) {
                     stop = j;
-                    // Segments 0 and kRoundSeg were walked from the pixel's
-                    // exact transmittance: where the pixel stopped in that
-                    // walk, the walk is the true one and needs no repeat.
-                    if (x1[u].z == 1.f && (j == 0 || j == kRoundSeg)) {
+                    // The first segment of each round was walked from the
+                    // pixel's exact transmittance: where the pixel stopped
+                    // in that walk, the walk is the true one and needs no
+                    // repeat.
+                    if (x1[u].z == 1.f && (j == round_lo(0) || j == round_lo(1))) {
                         c.c0 = fmaf(c.T, x0[u].x, c.c0);
                         c.c1 = fmaf(c.T, x0[u].y, c.c1);
                         c.c2 = fmaf(c.T, x0[u].z, c.c2);
@@ -1223,10 +1243,21 @@ hipError_t launch_emit(const uint32_t* order, const uint32_t* offs, const uint2*
 
 hipError_t launch_ranges(const uint32_t* tkeys, const uint32_t* n_dev, int64_t cap, uint2* ranges, int n_tiles,
                          hipStream_t s) {
-    (void)cap;
     if (n_tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ranges, dim3((unsigned)((n_tiles + 255) / 256)), dim3(256), 0, s, tkeys, n_dev, ranges,
-                       (uint32_t)n_tiles);
+    const int64_t blocks = std::min<int64_t>(4096, std::max<int64_t>(1, (cap + 1023) / 1024));
+    hipLaunchKernelGGL(k_ranges, dim3((unsigned)blocks), dim3(256), 0, s, tkeys, n_dev, ranges, (uint32_t)n_tiles);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_fill_u2(uint2* p, int64_t n, uint2 v) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+hipError_t launch_clear_ranges(uint2* ranges, int n_tiles, hipStream_t s) {
+    if (n_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u2, dim3((unsigned)((n_tiles + 255) / 256)), dim3(256), 0, s, ranges, (int64_t)n_tiles,
+                       make_uint2(0u, 0u));
     return hipGetLastError();
 }
 
@@ -1250,7 +1281,7 @@ hipError_t launch_blend(const SurfelRec* recs, const uint32_t* vals, const uint2
             hipLaunchKernelGGL((k_blend<true, true>), g, b, 0, s, recs, vals, ranges, tile_list, order, n_live, a, ca,
                                rgb, d_or_z, alpha, cls, pair_counts, trace);
             if (cont) {
-                for (int round = 0; round < 2; ++round)
+                for (int round = 0; round < kRounds; ++round)
                     hipLaunchKernelGGL((k_blend_seg<true>), gc, b, 0, s, recs, vals, tile_list, a, ca, round,
                                        pair_counts);
                 hipLaunchKernelGGL((k_blend_chain<true>), gs, b, 0, s, tile_list, a, ca, rgb, d_or_z, alpha, cls);
@@ -1261,7 +1292,7 @@ hipError_t launch_blend(const SurfelRec* recs, const uint32_t* vals, const uint2
             hipLaunchKernelGGL((k_blend<false, true>), g, b, 0, s, recs, vals, ranges, tile_list, order, n_live, a, ca,
                                rgb, d_or_z, alpha, cls, pair_counts, (long long*)nullptr);
             if (cont) {
-                for (int round = 0; round < 2; ++round)
+                for (int round = 0; round < kRounds; ++round)
                     hipLaunchKernelGGL((k_blend_seg<false>), gc, b, 0, s, recs, vals, tile_list, a, ca, round,
                                        pair_counts);
                 hipLaunchKernelGGL((k_blend_chain<true>), gs, b, 0, s, tile_list, a, ca, rgb, d_or_z, alpha, cls);
@@ -1274,7 +1305,7 @@ hipError_t launch_blend(const SurfelRec* recs, const uint32_t* vals, const uint2
             hipLaunchKernelGGL((k_blend<true, false>), g, b, 0, s, recs, vals, ranges, tile_list, order, n_live, a, ca,
                                rgb, d_or_z, alpha, cls, pair_counts, trace);
             if (cont) {
-                for (int round = 0; round < 2; ++round)
+                for (int round = 0; round < kRounds; ++round)
                     hipLaunchKernelGGL((k_blend_seg<true>), gc, b, 0, s, recs, vals, tile_list, a, ca, round,
                                        pair_counts);
                 hipLaunchKernelGGL((k_blend_chain<false>), gs, b, 0, s, tile_list, a, ca, rgb, d_or_z, alpha, cls);
@@ -1285,7 +1316,7 @@ hipError_t launch_blend(const SurfelRec* recs, const uint32_t* vals, const uint2
             hipLaunchKernelGGL((k_blend<false, false>), g, b, 0, s, recs, vals, ranges, tile_list, order, n_live, a,
                                ca, rgb, d_or_z, alpha, cls, pair_counts, (long long*)nullptr);
             if (cont) {
-                for (int round = 0; round < 2; ++round)
+                for (int round = 0; round < kRounds; ++round)
                     hipLaunchKernelGGL((k_blend_seg<false>), gc, b, 0, s, recs, vals, tile_list, a, ca, round,
                                        pair_counts);
                 hipLaunchKernelGGL((k_blend_chain<false>), gs, b, 0, s, tile_list, a, ca, rgb, d_or_z, alpha, cls);

@@ -89,7 +89,8 @@ __global__ __launch_bounds__(256) void k_scan_down(const uint32_t* in, const uin
 // Two-launch form for up to kScanFlat blocks: every block adds up the block
 // sums before its own (at most kScanFlat / 256 loads per thread), so no
 // second level is needed.  With status given, the thread that writes out[n]
-// also records the total as the pass's key count (see KeyCount).
+// also records the total as the pass's key count, and the blocks clear the
+// tile ranges (see KeyCount).
 constexpr int64_t kScanFlat = 4096;
 
 __global__ __launch_bounds__(256) void k_scan_down_flat(const uint32_t* in, const uint32_t* __restrict__ idx,
@@ -98,6 +99,8 @@ __global__ __launch_bounds__(256) void k_scan_down_flat(const uint32_t* in, cons
                                                         KeyCount kcnt) {
     __shared__ uint32_t lds[4];
     const int64_t n = n_dev ? (int64_t)*n_dev : n_cap;
+    for (uint32_t t = blockIdx.x * 256 + threadIdx.x; t < kcnt.n_tiles; t += gridDim.x * 256)
+        kcnt.ranges[t] = make_uint2(0u, 0u);
     uint32_t pre = 0;
     for (uint32_t b = threadIdx.x; b < blockIdx.x; b += 256) pre += partials[b];
     pre = block_sum(pre, lds);
