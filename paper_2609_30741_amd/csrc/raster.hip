@@ -1205,6 +1205,11 @@ __global__ __launch_bounds__(256) void k_blend_fix(const SurfelRec* __restrict__
         const TileGeom g = tile_geom(tile_list ? tile_list[d.x] : d.x, tid, a, &inside, &px, &py);
         PixelState q{need ? s1.y : 0.f, s0.x, s0.y, s0.z, s0.w, s1.x};
         walk_range<kCount>(recs, vals, sb, se, s_rec, s_list + (tid >> 6) * kListLen, g, a, q, wc);
+        // A pixel still compositing at the segment's end (whose crossing of
+        // t_min the chained product placed in this segment by rounding) walks
+        // on, in order, to its stop or the end of the list.
+        if (__syncthreads_or(live(q)))
+            walk_range<kCount>(recs, vals, se, d.z, s_rec, s_list + (tid >> 6) * kListLen, g, a, q, wc);
         if (inside && need) write_pixel<kPatch>(q, px, py, a, rgb, dz, alpha, cls);
     }
     if (kCount) count_flush(wc, tid & 63, tid >> 6, 0, pair_counts, nullptr);

@@ -390,8 +390,8 @@ __global__ __launch_bounds__(256) void k_edge_rois(WarpCam src, WarpCam dst, Rel
                                                    const float* __restrict__ depth_range,
                                                    const uint4* __restrict__ wpart, int n_wpart, DevStatus* st,
                                                    bgs_box* boxes, int box_cap, uint8_t* __restrict__ tm) {
-    __shared__ double red[4][256];
-    __shared__ int32_t sbx[4][4];
+    __shared__ double red[4][4];
+    __shared__ int32_t sbx[4][6];
     __shared__ int snb;
     float r0, r1;
     if (depth_range) {
@@ -427,24 +427,30 @@ __global__ __launch_bounds__(256) void k_edge_rois(WarpCam src, WarpCam dst, Rel
             ymax = fmax(ymax, v);
         }
     }
-    red[0][threadIdx.x] = xmin;
-    red[1][threadIdx.x] = xmax;
-    red[2][threadIdx.x] = ymin;
-    red[3][threadIdx.x] = ymax;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) {
-            red[0][threadIdx.x] = fmin(red[0][threadIdx.x], red[0][threadIdx.x + s]);
-            red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + s]);
-            red[2][threadIdx.x] = fmin(red[2][threadIdx.x], red[2][threadIdx.x + s]);
-            red[3][threadIdx.x] = fmax(red[3][threadIdx.x], red[3][threadIdx.x + s]);
-        }
-        __syncthreads();
+    // min / max are exact in any order: wave shuffles, then the four waves.
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        xmin = fmin(xmin, __shfl_xor(xmin, off, 64));
+        xmax = fmax(xmax, __shfl_xor(xmax, off, 64));
+        ymin = fmin(ymin, __shfl_xor(ymin, off, 64));
+        ymax = fmax(ymax, __shfl_xor(ymax, off, 64));
     }
+    if ((threadIdx.x & 63) == 0) {
+        const int w = threadIdx.x >> 6;
+        red[0][w] = xmin;
+        red[1][w] = xmax;
+        red[2][w] = ymin;
+        red[3][w] = ymax;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
+        const double rx0 = fmin(fmin(red[0][0], red[0][1]), fmin(red[0][2], red[0][3]));
+        const double rx1 = fmax(fmax(red[1][0], red[1][1]), fmax(red[1][2], red[1][3]));
+        const double ry0 = fmin(fmin(red[2][0], red[2][1]), fmin(red[2][2], red[2][3]));
+        const double ry1 = fmax(fmax(red[3][0], red[3][1]), fmax(red[3][2], red[3][3]));
         const double W = dst.W, H = dst.H, m = margin;
         const double hw = floor(W / 2.0), hh = floor(H / 2.0);
-        const double umin = snap(red[0][0]), umax = snap(red[1][0]), vmin = snap(red[2][0]), vmax = snap(red[3][0]);
+        const double umin = snap(rx0), umax = snap(rx1), vmin = snap(ry0), vmax = snap(ry1);
         const double lw = umin > 0.0 ? clampd(ceil(umin) + m, 0.0, hw) : 0.0;
         const double rw = umax < W - 1.0 ? clampd((W - 1.0) - floor(umax) + m, 0.0, hw) : 0.0;
         const double th = vmin > 0.0 ? clampd(ceil(vmin) + m, 0.0, hh) : 0.0;
@@ -452,7 +458,7 @@ __global__ __launch_bounds__(256) void k_edge_rois(WarpCam src, WarpCam dst, Rel
         const int w4[4] = {(int)lw, (int)rw, (int)th, (int)bh};
         const int64_t Wi = dst.W, Hi = dst.H;
         int nb = 0;
-        int32_t bx[4][6];
+        int32_t (*bx)[6] = sbx;  // LDS: indexed by the running box count
         if (w4[0] > 0) {
             int64_t x1 = align_up(w4[0], T);
             int32_t b[6] = {0, 0, (int32_t)(x1 < Wi ? x1 : Wi), (int32_t)Hi, BGS_BOX_LEFT, -1};
@@ -480,7 +486,6 @@ __global__ __launch_bounds__(256) void k_edge_rois(WarpCam src, WarpCam dst, Rel
         snb = nb;
         for (int b = 0; b < nb; ++b) {
             for (int q = 0; q < 6; ++q) st->edge_boxes[b * 6 + q] = bx[b][q];
-            for (int q = 0; q < 4; ++q) sbx[b][q] = bx[b][q];
             if (b < box_cap) {
                 boxes[b].x0 = bx[b][0];
                 boxes[b].y0 = bx[b][1];
@@ -510,6 +515,25 @@ __device__ inline bool in_edge(const DevStatus* st, int x, int y) {
     }
     return false;
 }
+
+// The (at most four) edge boxes, read once into registers.
+struct EdgeBoxes {
+    int n;
+    int b[4][4];  // x0, y0, x1, y1
+    __device__ explicit EdgeBoxes(const DevStatus* st) {
+        n = (int)st->n_edge;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) b[k][q] = st->edge_boxes[k * 6 + q];
+    }
+    __device__ bool contains(int x, int y) const {
+        bool in = false;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) in = in || (k < n && x >= b[k][0] && x < b[k][2] && y >= b[k][1] && y < b[k][3]);
+        return in;
+    }
+};
 
 // ---------------------------------------------------------------------------
 // Gap interpolation, Jacobi passes done in place.  tag[p] = 0 for a pixel
@@ -596,7 +620,55 @@ __global__ __launch_bounds__(256) void k_gap_fill(int W, int H, int passes, floa
     const int h = passes;
     const int rw = 64 + 2 * h, rh = kBandRows + 2 * h;
     const int x0 = blockIdx.x * 64 - h, y0 = blockIdx.y * kBandRows - h;
-    for (int i = threadIdx.x; i < rw * rh; i += 256) {
+    {
+        // Holes are sparse: a tile without one has nothing to fill and no
+        // center pixel, and needs none of its neighbours' values.  (The
+        // loads are issued together: unrolled, none waits on another.)
+        const int cx = blockIdx.x * 64 + (threadIdx.x & 63);
+        uint8_t hv[kBandRows / 4];
+#pragma unroll
+        for (int q = 0; q < kBandRows / 4; ++q) {
+            const int cy = blockIdx.y * kBandRows + (threadIdx.x >> 6) + 4 * q;
+            hv[q] = (cx < W && cy < H) ? cls[(int64_t)cy * W + cx] : 0;
+        }
+        bool any = false;
+#pragma unroll
+        for (int q = 0; q < kBandRows / 4; ++q) any = any || hv[q] != 0;
+        if (!__syncthreads_or(any)) {
+            for (int r = threadIdx.x >> 6; r < kBandRows; r += 4) {
+                const int cy = blockIdx.y * kBandRows + r;
+                if (cx < W && cy < H) {
+                    tag_out[(int64_t)cy * W + cx] = 0;
+                    center[(int64_t)cy * W + cx] = 0;
+                }
+            }
+            if (threadIdx.x == 0) gpart[blockIdx.y * gridDim.x + blockIdx.x] = make_uint2(0u, 0u);
+            return;
+        }
+    }
+    const EdgeBoxes eb(st);
+    // The tile and its halo: all loads first (unrolled, so none waits on
+    // another), then the LDS stores.
+    constexpr int kLoads = (kGapRW * kGapRH + 255) / 256;
+    float lc0[kLoads], lc1[kLoads], lc2[kLoads], la[kLoads], lz[kLoads];
+    uint8_t lh[kLoads];
+#pragma unroll
+    for (int q = 0; q < kLoads; ++q) {
+        const int i = threadIdx.x + 256 * q;
+        const int lx = i % rw, ly = i / rw, x = x0 + lx, y = y0 + ly;
+        const bool ok = i < rw * rh && x >= 0 && y >= 0 && x < W && y < H;
+        const int64_t p = ok ? (int64_t)y * W + x : 0;
+        lh[q] = ok ? cls[p] : 0;
+        lc0[q] = ok ? rgb[p] : 0.f;
+        lc1[q] = ok ? rgb[n + p] : 0.f;
+        lc2[q] = ok ? rgb[2 * n + p] : 0.f;
+        la[q] = ok ? alpha[p] : 0.f;
+        lz[q] = ok ? z[p] : 0.f;
+    }
+#pragma unroll
+    for (int q = 0; q < kLoads; ++q) {
+        const int i = threadIdx.x + 256 * q;
+        if (i >= rw * rh) continue;
         const int lx = i % rw, ly = i / rw, x = x0 + lx, y = y0 + ly;
         const int li = ly * kGapRW + lx;
         if (x < 0 || y < 0 || x >= W || y >= H) {
@@ -604,15 +676,14 @@ __global__ __launch_bounds__(256) void k_gap_fill(int W, int H, int passes, floa
             s_fix[li] = 1;
             continue;
         }
-        const int64_t p = (int64_t)y * W + x;
-        const bool hole = cls[p] != 0;
+        const bool hole = lh[q] != 0;
         s_tag[li] = hole ? 255 : 0;
-        s_fix[li] = (hole && in_edge(st, x, y)) ? 2 : 0;
-        s_c[0][li] = rgb[p];
-        s_c[1][li] = rgb[n + p];
-        s_c[2][li] = rgb[2 * n + p];
-        s_a[li] = alpha[p];
-        s_z[li] = z[p];
+        s_fix[li] = (hole && eb.contains(x, y)) ? 2 : 0;
+        s_c[0][li] = lc0[q];
+        s_c[1][li] = lc1[q];
+        s_c[2][li] = lc2[q];
+        s_a[li] = la[q];
+        s_z[li] = lz[q];
     }
     __syncthreads();
     for (int pass = 1; pass <= passes; ++pass) {
@@ -624,18 +695,30 @@ __global__ __launch_bounds__(256) void k_gap_fill(int W, int H, int passes, floa
             if (s_tag[li] != 255 || s_fix[li] != 0) continue;
             const int NX[8] = {-1, 0, 1, -1, 1, -1, 0, 1};
             const int NY[8] = {-1, -1, -1, 0, 0, 1, 1, 1};
+            // All eight neighbours' values are read together (no read waits
+            // on another), then the valid ones are summed in neighbour order.
+            bool ok[8];
+            float v0[8], v1[8], v2[8], va[8], vz[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int r = (ly + NY[q]) * kGapRW + lx + NX[q];
+                ok[q] = !(s_fix[r] == 1 || (int)s_tag[r] >= pass);  // outside, a hole, or filled in this pass
+                v0[q] = s_c[0][r];
+                v1[q] = s_c[1][r];
+                v2[q] = s_c[2][r];
+                va[q] = s_a[r];
+                vz[q] = s_z[r];
+            }
             int cnt = 0;
             float s0 = 0.f, s1 = 0.f, s2 = 0.f, sa = 0.f, zm = -INFINITY;
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                const int r = (ly + NY[q]) * kGapRW + lx + NX[q];
-                if (s_fix[r] == 1 || (int)s_tag[r] >= pass) continue;  // outside, a hole, or filled in this pass
-                s0 = s0 + s_c[0][r];
-                s1 = s1 + s_c[1][r];
-                s2 = s2 + s_c[2][r];
-                sa = sa + s_a[r];
-                const float zr = s_z[r];
-                if (zr > zm) zm = zr;
+                if (!ok[q]) continue;
+                s0 = s0 + v0[q];
+                s1 = s1 + v1[q];
+                s2 = s2 + v2[q];
+                sa = sa + va[q];
+                if (vz[q] > zm) zm = vz[q];
                 ++cnt;
             }
             if (cnt > 0) {
@@ -839,6 +922,13 @@ __global__ __launch_bounds__(256) void k_ccl_local(int W, int H, int conn, const
     const bool in = x < W && y < H;
     const int li = threadIdx.x;
     const bool set = in && mask[(int64_t)y * W + x];
+    if (!__syncthreads_or(set)) {  // an empty block (the usual case for a sparse mask)
+        if (in) {
+            labels[(int64_t)y * W + x] = -1;
+            if (pflag) pflag[(int64_t)y * W + x] = 0;
+        }
+        return;
+    }
     m[li] = set ? 1 : 0;
     L[li] = li;
     bx0[li] = INT_MAX;
