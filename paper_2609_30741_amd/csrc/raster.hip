@@ -73,13 +73,12 @@ __device__ inline uint32_t masked_count(const MaskArgs& m, int tx0, int ty0, int
 // Strip band of a surfel: a direction n (snorm16 pair) and an interval
 // [n.mu + c - w, n.mu + c + w] (fp16 c, w) of n.x that holds every pixel x
 // the surfel can reach with alpha >= alpha_min.  The blend skips a record
-// for a 16x4 strip that lies outside the band, which is exact: such a
-// record is a no-op on every pixel of the strip.  Tile binning already
-// guarantees overlap in x, so the band only has to separate strips in y;
-// n is the footprint's narrowest direction when that confines the strips of
-// a tile column better than the y extent, else the y axis.  The band is
-// computed for the quantised n the blend decodes, and padded for the fp16
-// rounding and for the blend's fp32 arithmetic.
+// for a wave's 8x8 pixel region that lies outside the band, which is exact:
+// such a record is a no-op on every pixel of the region.  n is the
+// footprint's narrowest direction when that confines the regions of a tile
+// column better than the y extent, else the y axis.  The band is computed
+// for the quantised n the blend decodes, and padded for the fp16 rounding
+// and for the blend's fp32 arithmetic.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float snorm16_value(int q) { return (float)q * (1.0f / 32767.0f); }
 
@@ -147,9 +146,10 @@ __device__ uint2 strip_band(bool bounded, double c00, double c01, double c02, do
             const double nmu = nx * mux + ny * muy, rn = r_lowpass * sqrt(nx * nx + ny * ny);
             lo = fmin(lo, nmu - rn);
             hi = fmax(hi, nmu + rn);
-            // Length of the strip-centre rows of one tile column that pass.
-            const double pass_n = ny > 1e-6 ? (0.5 * (hi - lo) + 7.5 * fabs(nx) + 1.5 * ny) / ny : INFINITY;
-            const double pass_y = 0.5 * (ymax - ymin) + 1.5;
+            // Half-length of the rows of one tile column whose 8x8 regions
+            // pass, along n and along y.
+            const double pass_n = ny > 1e-6 ? (0.5 * (hi - lo) + 3.5 * fabs(nx) + 3.5 * ny) / ny : INFINITY;
+            const double pass_y = 0.5 * (ymax - ymin) + 3.5;
             if (pass_n < pass_y) {
                 qx = cx;
                 qy = cy;
@@ -639,13 +639,14 @@ __global__ __launch_bounds__(1024) void k_tile_order(const uint2* __restrict__ r
 }
 
 // ---------------------------------------------------------------------------
-// Blend.  One 256-thread block per 16x16 tile; wave w owns the 16x4 strip of
-// rows 4w..4w+3.  walk_range composites the records [b, e) of the tile's
-// sorted list into the block's pixels: batches of 256 records are fetched
-// by all threads with vector loads (the next batch while the current one is
-// composited) and put in LDS; each wave tests the whole batch against its
-// strip (the record's strip band) in one vector pass and writes the byte offsets of the records that
-// can touch it, in list order, to its own LDS list, padded with an all-zero
+// Blend.  One 256-thread block per 16x16 tile; wave w owns the 8x8 quadrant
+// (w & 1, w >> 1) of the tile.  walk_range composites the records [b, e)
+// of the tile's sorted list into the block's pixels: batches of 256 records
+// are fetched by all threads with vector loads (the next batch while the
+// current one is composited) and put in LDS; each wave tests the whole
+// batch against its region (the record's strip band) in one vector pass and
+// writes the byte offsets of the records that can touch it, in list order,
+// to its own LDS list, padded with an all-zero
 // record that never contributes.  It then takes kTrip records per trip: their
 // alphas are independent and computed together, and only the short
 // transmittance chain runs in sequence.  The walk ends at the first batch
@@ -682,7 +683,7 @@ struct WalkCounts {
 struct TileGeom {
     int tid, lane;
     float fpx, fpy;
-    float scx, scy;  // centre of the wave's 16x4 strip
+    float scx, scy;  // centre of the wave's 8x8 region
 };
 
 // Alpha of one (pixel, surfel) pair (Eq. 2 with the plane homography of the
@@ -730,7 +731,7 @@ __device__ __forceinline__ void accumulate(float al, float dsel, const float4& r
     p.T = stop ? 0.f : Tn;
 }
 
-// Strip test, compaction and compositing of one staged batch of nb records
+// Region test, compaction and compositing of one staged batch of nb records
 // by one wave (no block barriers).
 template <bool kCount>
 __device__ __forceinline__ void walk_batch(const float4* s_rec, uint32_t nb, uint16_t* s_list, const TileGeom& g,
@@ -747,7 +748,7 @@ __device__ __forceinline__ void walk_batch(const float4* s_rec, uint32_t nb, uin
             const float ny = snorm16_value((int)(int16_t)(nq >> 16));
             const float4 r0 = s_rec[4 * j];
             const float pr = fmaf(nx, g.scx - r0.x, ny * (g.scy - r0.y)) - half_value(bq);
-            h = fabsf(pr) <= half_value(bq >> 16) + fmaf(fabsf(nx), 7.5f, fabsf(ny) * 1.5f);
+            h = fabsf(pr) <= half_value(bq >> 16) + 3.5f * (fabsf(nx) + fabsf(ny));
         }
         const uint64_t m = __ballot(h);
         if (h) {
@@ -834,13 +835,13 @@ __device__ __forceinline__ TileGeom tile_geom(uint32_t tile, int tid, const Blen
     g.tid = tid;
     g.lane = g.tid & 63;
     const int wave = g.tid >> 6;
-    *px = tx * kTile + (g.lane & 15);
-    *py = ty * kTile + wave * 4 + (g.lane >> 4);
+    *px = tx * kTile + (wave & 1) * 8 + (g.lane & 7);
+    *py = ty * kTile + (wave >> 1) * 8 + (g.lane >> 3);
     *inside = *px < a.W && *py < a.H;
     g.fpx = (float)*px;
     g.fpy = (float)*py;
-    g.scx = (float)(tx * kTile) + 7.5f;
-    g.scy = (float)(ty * kTile + wave * 4) + 1.5f;
+    g.scx = (float)(tx * kTile + (wave & 1) * 8) + 3.5f;
+    g.scy = (float)(ty * kTile + (wave >> 1) * 8) + 3.5f;
     return g;
 }
 
