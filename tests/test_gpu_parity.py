@@ -378,3 +378,65 @@ def test_render_stereo_cube_end_to_end(ctx, oracle, center):
     warp_px = same & (cls_g == api.CLS_WARPED)
     frac = (np.abs(rgb_g - rgb_o).max(0)[warp_px] > RGB_TOL).mean()
     assert frac < 2e-3
+
+
+# ---------------------------------------------------------------------------
+# Frames in flight and stage timing
+# ---------------------------------------------------------------------------
+
+def test_frames_in_flight_match_sequential(ctx):
+    """Several contexts, each on its own stream, rendering different stereo
+    frames at once give the same bits as one context rendering them in turn
+    (the kernels share nothing but the read-only scene)."""
+    sc, cams, b = synth.workload_sphere800(0, n=60_000, n_poses=6)
+    affs = [synth.affiliated(c, b) for c in cams]
+    ds = api.DeviceScene(sc)
+    seq = [ctx.render_stereo(ds, cd, ca) for cd, ca in zip(cams, affs)]
+    keys = ("rgb_dom", "depth_raw_dom", "alpha_dom", "rgb_aff", "z_aff", "alpha_aff", "cls_aff", "labels",
+            "tile_mask")
+    seq = [{k: o[k].clone() for k in keys} for o in seq]
+    K = 3
+    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(K - 1)]
+    ctxs, outs = [], []
+    for k in range(K):
+        with torch.cuda.stream(streams[k]):
+            c = api.Context(sync=True)
+            outs.append(c.render_stereo(ds, cams[0], affs[0]))
+            c.set_sync(False)
+            ctxs.append(c)
+    torch.cuda.synchronize()
+    got = [None] * len(cams)
+    for rep in range(2):  # the second round reuses every context's buffers
+        for i, (cd, ca) in enumerate(zip(cams, affs)):
+            k = i % K
+            with torch.cuda.stream(streams[k]):
+                ctxs[k].render_stereo(ds, cd, ca, out=outs[k])
+                # Copy on the same stream, before the context's next frame.
+                got[i] = {key: outs[k][key].clone() for key in keys}
+        torch.cuda.synchronize()
+        for i in range(len(cams)):
+            for key in keys:
+                assert torch.equal(got[i][key], seq[i][key]), f"round {rep} frame {i}: {key} differs"
+    for c in ctxs:
+        assert c.poll_status()["overflow"] == 0
+
+
+def test_timing_stage_mask(ctx):
+    sc, cam = cube_workload(10_000, 256, 256, 300.0, seed=3)
+    aff = synth.affiliated(cam, 0.064)
+    ds = api.DeviceScene(sc)
+    out = ctx.render_stereo(ds, cam, aff)
+    ctx.set_timing(True, stages=["blend_dom", "classify"])
+    for _ in range(3):
+        ctx.render_stereo(ds, cam, aff, out=out)
+    torch.cuda.synchronize()
+    t = ctx.timing_collect()
+    ctx.set_timing(False)
+    assert t["blend_dom"][1] == 3 and t["classify"][1] == 3 and t["blend_dom"][0] > 0
+    assert all(v[1] == 0 for k, v in t.items() if k not in ("blend_dom", "classify"))
+    ctx.set_timing(True)
+    ctx.render_stereo(ds, cam, aff, out=out)
+    torch.cuda.synchronize()
+    t = ctx.timing_collect()
+    ctx.set_timing(False)
+    assert all(v[1] == 1 for v in t.values()), t
