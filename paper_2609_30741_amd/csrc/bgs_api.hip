@@ -338,7 +338,7 @@ int raster_pass(bgs_ctx* ctx, const Layout& L, void* ws, int64_t kc, const bgs_s
     uint32_t* offs = at<uint32_t>(ws, L.offs);
     if (precomputed) {
         if (!tile_mask) return fail(ctx, BGS_ERR_INVALID_ARG, "precomputed records need a tile mask");
-        HIP_CHECK(launch_masked_counts(rects, n, mask, counts, s), "masked counts");
+        HIP_CHECK(launch_masked_counts(rects, recs, n, mask, counts, s), "masked counts");
     } else {
         const SceneArgs sa{scene.pos, scene.quat, scene.scale, scene.opacity, scene.sh, n, scene.sh_degree};
         PreCam pn{};
@@ -378,7 +378,7 @@ int raster_pass(bgs_ctx* ctx, const Layout& L, void* ws, int64_t kc, const bgs_s
     uint32_t* tva = at<uint32_t>(ws, L.tvals_a);
     uint32_t* tkb = at<uint32_t>(ws, L.tkeys_b);
     uint32_t* tvb = at<uint32_t>(ws, L.tvals_b);
-    HIP_CHECK(launch_emit(order, offs, rects, n, pc.tiles_x, mask, (uint32_t)kc, tka, tva, s), "emit");
+    HIP_CHECK(launch_emit(order, offs, rects, recs, n, pc.tiles_x, mask, (uint32_t)kc, tka, tva, s), "emit");
     mark(ctx, sb + 2, 1);
     // Stable sort by tile: within a tile the emission (= compositing) order stays.
     mark(ctx, sb + 3, 0);

@@ -160,10 +160,14 @@ hipError_t launch_preprocess(const SceneArgs& sc, const PreCam& cam, float alpha
                              const MaskArgs& mask, SurfelRec* recs, uint32_t* zkeys, uint2* rects,
                              uint32_t* counts, const PreCam* cam2, SurfelRec* recs2, uint32_t* zkeys2,
                              uint2* rects2, hipStream_t s);
-// Key counts within the mask's tiles from precomputed tile rects.
-hipError_t launch_masked_counts(const uint2* rects, int n, const MaskArgs& mask, uint32_t* counts, hipStream_t s);
-hipError_t launch_emit(const uint32_t* order, const uint32_t* offs, const uint2* rects, int n, int tiles_x,
-                       const MaskArgs& mask, uint32_t cap, uint32_t* tkeys, uint32_t* tvals, hipStream_t s);
+// Key counts within the mask's tiles from precomputed tile rects and records.
+hipError_t launch_masked_counts(const uint2* rects, const SurfelRec* recs, int n, const MaskArgs& mask,
+                                uint32_t* counts, hipStream_t s);
+// Keys of every surfel in compositing order: the tiles of its rect that its
+// strip band meets (and the mask holds, when enabled), row by row.
+hipError_t launch_emit(const uint32_t* order, const uint32_t* offs, const uint2* rects, const SurfelRec* recs, int n,
+                       int tiles_x, const MaskArgs& mask, uint32_t cap, uint32_t* tkeys, uint32_t* tvals,
+                       hipStream_t s);
 // Tile ranges of the sorted keys; the ranges must have been cleared (by
 // scan_counts, or launch_clear_ranges).
 hipError_t launch_ranges(const uint32_t* tkeys, const uint32_t* n_dev, int64_t cap, uint2* ranges,

@@ -182,6 +182,68 @@ __device__ uint2 strip_band(bool bounded, double c00, double c01, double c02, do
     return make_uint2(nbits, cb | (half_bits_up(w) << 16));
 }
 
+
+// ---------------------------------------------------------------------------
+// Tile binning by band: of row ty of a surfel's tile rect, the columns
+// [*a, *b] (empty when *b < *a) whose 16x16 tile meets the record's strip
+// band.  A tile that misses the band is missed by every pixel region in it,
+// so the record is a no-op there and needs no key.  fp64, from the record's
+// own (fp32 centre, snorm16 direction, fp16 interval) values, with half a
+// pixel of margin: the preprocess, the masked counts and the emission call
+// this one function on the same values, so counts and keys agree exactly.
+// ---------------------------------------------------------------------------
+struct BandRows {
+    double k0, k16, r, inv;  // k(ty) = k0 + k16 ty; columns where |16 nx tx + k| <= r
+    bool vertical;           // nx = 0 (or no direction): whole rows in or out
+    __device__ BandRows() : k0(0.0), k16(0.0), r(-1.0), inv(0.0), vertical(true) {}  // no tile
+    __device__ explicit BandRows(const SurfelRec& rec) {
+#pragma clang fp contract(off)
+        const uint32_t nq = __float_as_uint(rec.c.w), bq = __float_as_uint(rec.d.w);
+        const double nx = (double)snorm16_value((int)(int16_t)(nq & 0xFFFFu));
+        const double ny = (double)snorm16_value((int)(int16_t)(nq >> 16));
+        const double c = (double)half_value(bq);
+        r = (double)half_value(bq >> 16) + 7.5 * (fabs(nx) + fabs(ny)) + 0.5;
+        k0 = nx * (7.5 - (double)rec.a.x) + ny * (7.5 - (double)rec.a.y) - c;
+        k16 = 16.0 * ny;
+        vertical = !(fabs(nx) > 1e-9);
+        inv = vertical ? 0.0 : 1.0 / (16.0 * nx);
+    }
+    __device__ void row(int ty, int tx0, int tx1, int* a, int* b) const {
+#pragma clang fp contract(off)
+        const double k = fma(k16, (double)ty, k0);
+        if (vertical) {  // also an infinite band (r = inf): every column
+            const bool in = !(fabs(k) > r);
+            *a = in ? tx0 : 1;
+            *b = in ? tx1 : 0;
+            return;
+        }
+        double lo = (-r - k) * inv, hi = (r - k) * inv;
+        if (lo > hi) {
+            const double t = lo;
+            lo = hi;
+            hi = t;
+        }
+        lo = ceil(lo);
+        hi = floor(hi);
+        *a = lo > (double)tx0 ? (lo > (double)tx1 ? tx1 + 1 : (int)lo) : tx0;
+        *b = hi < (double)tx1 ? (hi < (double)tx0 ? tx0 - 1 : (int)hi) : tx1;
+    }
+};
+
+// Keys of a surfel: the band's tiles of its rect, only masked ones when the
+// mask is enabled.
+__device__ inline uint32_t band_count(const BandRows& br, const MaskArgs& m, int tx0, int ty0, int tx1, int ty1) {
+    uint32_t cnt = 0;
+    for (int ty = ty0; ty <= ty1; ++ty) {
+        int a, b;
+        br.row(ty, tx0, tx1, &a, &b);
+        if (b < a) continue;
+        cnt += m.enabled ? m.prefix[(int64_t)ty * m.tiles_x + b + 1] - m.prefix[(int64_t)ty * m.tiles_x + a]
+                         : (uint32_t)(b - a + 1);
+    }
+    return cnt;
+}
+
 // A surfel seen from one camera: its tile rect and every record word but
 // the colour (geometry in fp64, Sec. 3.3).  drawn = false: no pixel of this
 // camera can get alpha >= alpha_min from it.
@@ -359,8 +421,7 @@ __global__ __launch_bounds__(256) void k_preprocess(SceneArgs sc, PreCam cam, Pr
     }
     uint32_t cnt = 0;
     if (v1.drawn) {
-        cnt = mask.enabled ? masked_count(mask, v1.tx0, v1.ty0, v1.tx1, v1.ty1)
-                           : (uint32_t)((v1.tx1 - v1.tx0 + 1) * (v1.ty1 - v1.ty0 + 1));
+        cnt = band_count(BandRows(v1.rec), mask, v1.tx0, v1.ty0, v1.tx1, v1.ty1);
         rects[k] = make_uint2((uint32_t)v1.tx0 | ((uint32_t)v1.ty0 << 16), (uint32_t)v1.tx1 | ((uint32_t)v1.ty1 << 16));
     } else {
         rects[k] = empty;
@@ -403,15 +464,21 @@ __global__ __launch_bounds__(256) void k_preprocess(SceneArgs sc, PreCam cam, Pr
     }
 }
 
-// Key counts of surfels whose tile rects were computed earlier, restricted
-// to the tiles of a mask.
-__global__ __launch_bounds__(256) void k_masked_counts(const uint2* __restrict__ rects, int n, MaskArgs mask,
+// Key counts of surfels whose tile rects and records were computed
+// earlier, restricted to the tiles of a mask.
+__global__ __launch_bounds__(256) void k_masked_counts(const uint2* __restrict__ rects,
+                                                       const SurfelRec* __restrict__ recs, int n, MaskArgs mask,
                                                        uint32_t* __restrict__ counts) {
     const int k = blockIdx.x * 256 + threadIdx.x;
     if (k >= n) return;
     const uint2 r = rects[k];
-    counts[k] = r.x > r.y ? 0u : masked_count(mask, (int)(r.x & 0xFFFFu), (int)(r.x >> 16), (int)(r.y & 0xFFFFu),
-                                              (int)(r.y >> 16));
+    if (r.x > r.y || masked_count(mask, (int)(r.x & 0xFFFFu), (int)(r.x >> 16), (int)(r.y & 0xFFFFu),
+                                  (int)(r.y >> 16)) == 0) {
+        counts[k] = 0;
+        return;
+    }
+    counts[k] = band_count(BandRows(recs[k]), mask, (int)(r.x & 0xFFFFu), (int)(r.x >> 16), (int)(r.y & 0xFFFFu),
+                           (int)(r.y >> 16));
 }
 
 // ---------------------------------------------------------------------------
@@ -420,57 +487,110 @@ __global__ __launch_bounds__(256) void k_masked_counts(const uint2* __restrict__
 // its surfel by binary search over the block's offsets), so a surfel that
 // covers the whole screen does not serialise one thread.
 // ---------------------------------------------------------------------------
+// Per block of 256 surfels: one thread per surfel lists the non-empty rows
+// of its band within its rect as segments (start of the segment's keys in
+// the block, the first tile's key and the surfel), in LDS.  The block's keys
+// are then taken in windows: each segment marks its keys of the window with
+// its index in an owner table, and each key is written from its owner's
+// segment, with consecutive threads on consecutive keys.  A block with more
+// segments than the table holds takes them in turns of the table's size.
+constexpr int kEmitSegs = 2048;
+constexpr int kEmitWin = 2048;
+
 __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order, const uint32_t* __restrict__ offs,
-                                              const uint2* __restrict__ rects, int n, int tiles_x, MaskArgs mask,
-                                              uint32_t cap, uint32_t* __restrict__ tkeys,
-                                              uint32_t* __restrict__ tvals) {
-    __shared__ uint32_t loc[257];
+                                              const uint2* __restrict__ rects, const SurfelRec* __restrict__ recs,
+                                              int n, int tiles_x, MaskArgs mask, uint32_t cap,
+                                              uint32_t* __restrict__ tkeys, uint32_t* __restrict__ tvals) {
     __shared__ uint32_t sk[256];
-    __shared__ uint2 srect[256];
+    __shared__ uint32_t seg_start[kEmitSegs + 1];
+    __shared__ uint32_t seg_tile[kEmitSegs];  // first tile's key | surfel << 24 (keys < 2^20: sides <= 16384 px)
+    __shared__ uint16_t owner[kEmitWin];
+    __shared__ uint32_t lds[4];
     const int r0 = blockIdx.x * 256;
     const int m = min(256, n - r0);
     const uint32_t base = offs[r0];
-    if ((int)threadIdx.x < m) {
-        const uint32_t k = order[r0 + threadIdx.x];
-        sk[threadIdx.x] = k;
-        srect[threadIdx.x] = rects[k];
-        loc[threadIdx.x] = offs[r0 + threadIdx.x] - base;
+    const int t = threadIdx.x;
+    uint2 rc = make_uint2(0xFFFFFFFFu, 0u);
+    uint32_t cnt = 0, loc = 0;
+    SurfelRec rec;
+    if (t < m) {
+        const uint32_t k = order[r0 + t];
+        loc = offs[r0 + t] - base;
+        cnt = offs[r0 + t + 1] - offs[r0 + t];
+        sk[t] = k;
+        if (cnt) {
+            rc = rects[k];
+            rec = recs[k];
+        }
     }
-    if (threadIdx.x == 0) loc[m] = offs[r0 + m] - base;
+    const int tx0 = rc.x & 0xFFFF, ty0 = rc.x >> 16, tx1 = rc.y & 0xFFFF, ty1 = rc.y >> 16;
+    const BandRows br = cnt ? BandRows(rec) : BandRows();
+    // Segments of this thread's surfel.
+    uint32_t ns = 0;
+    if (cnt) {
+        for (int ty = ty0; ty <= ty1; ++ty) {
+            int a, b;
+            br.row(ty, tx0, tx1, &a, &b);
+            if (b < a) continue;
+            const int64_t rb = (int64_t)ty * tiles_x;
+            const uint32_t c = mask.enabled ? mask.prefix[rb + b + 1] - mask.prefix[rb + a] : (uint32_t)(b - a + 1);
+            ns += c ? 1u : 0u;
+        }
+    }
+    // Exclusive scan of the segment counts over the block.
+    uint32_t v = ns;
+    const int lane = t & 63, w = t >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(v, off, 64);
+        if (lane >= off) v += y;
+    }
+    if (lane == 63) lds[w] = v;
     __syncthreads();
-    const uint32_t total = loc[m];
-    for (uint32_t p = threadIdx.x; p < total; p += 256) {
-        // Last l with loc[l] <= p (that surfel has a non-empty range).
-        int lo = 0, hi = m - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (loc[mid] <= p) lo = mid;
-            else hi = mid - 1;
-        }
-        uint32_t local = p - loc[lo];
-        const uint2 rc = srect[lo];
-        const int tx0 = rc.x & 0xFFFF, ty0 = rc.x >> 16, tx1 = rc.y & 0xFFFF, ty1 = rc.y >> 16;
-        uint32_t tile;
-        if (!mask.enabled) {
-            const uint32_t w = (uint32_t)(tx1 - tx0 + 1);
-            tile = (uint32_t)(ty0 + (int)(local / w)) * (uint32_t)tiles_x + (uint32_t)tx0 + local % w;
-        } else {
-            // The row holding the local-th masked tile of the rect: the first
-            // row whose cumulative masked count exceeds local.
-            int lo = ty0, hi = ty1;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (masked_rows(mask, tx0, ty0, tx1, mid) > local) hi = mid;
-                else lo = mid + 1;
+    uint32_t sbase = v - ns;
+    for (int q = 0; q < w; ++q) sbase += lds[q];
+    const uint32_t tot_seg = lds[0] + lds[1] + lds[2] + lds[3];
+    for (uint32_t w0 = 0; w0 < tot_seg; w0 += kEmitSegs) {
+        const uint32_t w1 = min(tot_seg, w0 + (uint32_t)kEmitSegs);
+        if (ns && sbase < w1 && sbase + ns > w0) {
+            uint32_t si = sbase, kpos = loc;
+            for (int ty = ty0; ty <= ty1 && si < w1; ++ty) {
+                int a, b;
+                br.row(ty, tx0, tx1, &a, &b);
+                if (b < a) continue;
+                const int64_t rb = (int64_t)ty * tiles_x;
+                const uint32_t c =
+                    mask.enabled ? mask.prefix[rb + b + 1] - mask.prefix[rb + a] : (uint32_t)(b - a + 1);
+                if (!c) continue;
+                if (si >= w0) {
+                    seg_start[si - w0] = kpos;
+                    seg_tile[si - w0] = (mask.enabled ? mask.prefix[rb + a] : (uint32_t)(rb + a)) | ((uint32_t)t << 24);
+                    if (si + 1 == w1) seg_start[w1 - w0] = kpos + c;  // end of the turn's keys
+                }
+                kpos += c;
+                ++si;
             }
-            const uint32_t before = lo > ty0 ? masked_rows(mask, tx0, ty0, tx1, lo - 1) : 0u;
-            // Compact id: the masked tiles before it in row-major order.
-            tile = mask.prefix[(int64_t)lo * tiles_x + tx0] + (local - before);
         }
-        const uint32_t g = base + p;
-        if (g < cap) {
-            tkeys[g] = tile;
-            tvals[g] = sk[lo];
+        __syncthreads();
+        const int nw = (int)(w1 - w0);
+        const uint32_t p0 = seg_start[0], p1 = seg_start[nw];
+        for (uint32_t kw = p0; kw < p1; kw += kEmitWin) {
+            const uint32_t ke = min(p1, kw + (uint32_t)kEmitWin);
+            for (int j = t; j < nw; j += 256) {
+                const uint32_t s0 = max(seg_start[j], kw), s1 = min(seg_start[j + 1], ke);
+                for (uint32_t q = s0; q < s1; ++q) owner[q - kw] = (uint16_t)j;
+            }
+            __syncthreads();
+            for (uint32_t p = kw + t; p < ke; p += 256) {
+                const int j = owner[p - kw];
+                const uint32_t st = seg_tile[j];
+                const uint32_t g = base + p;
+                if (g < cap) {
+                    tkeys[g] = (st & 0xFFFFFFu) + (p - seg_start[j]);
+                    tvals[g] = sk[st >> 24];
+                }
+            }
+            __syncthreads();
         }
     }
 }
@@ -1233,17 +1353,19 @@ hipError_t launch_preprocess(const SceneArgs& sc, const PreCam& cam, float alpha
     return hipGetLastError();
 }
 
-hipError_t launch_masked_counts(const uint2* rects, int n, const MaskArgs& mask, uint32_t* counts, hipStream_t s) {
+hipError_t launch_masked_counts(const uint2* rects, const SurfelRec* recs, int n, const MaskArgs& mask,
+                                uint32_t* counts, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_masked_counts, dim3((n + 255) / 256), dim3(256), 0, s, rects, n, mask, counts);
+    hipLaunchKernelGGL(k_masked_counts, dim3((n + 255) / 256), dim3(256), 0, s, rects, recs, n, mask, counts);
     return hipGetLastError();
 }
 
-hipError_t launch_emit(const uint32_t* order, const uint32_t* offs, const uint2* rects, int n, int tiles_x,
-                       const MaskArgs& mask, uint32_t cap, uint32_t* tkeys, uint32_t* tvals, hipStream_t s) {
+hipError_t launch_emit(const uint32_t* order, const uint32_t* offs, const uint2* rects, const SurfelRec* recs, int n,
+                       int tiles_x, const MaskArgs& mask, uint32_t cap, uint32_t* tkeys, uint32_t* tvals,
+                       hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_emit, dim3((n + 255) / 256), dim3(256), 0, s, order, offs, rects, n, tiles_x, mask, cap,
-                       tkeys, tvals);
+    hipLaunchKernelGGL(k_emit, dim3((n + 255) / 256), dim3(256), 0, s, order, offs, rects, recs, n, tiles_x, mask,
+                       cap, tkeys, tvals);
     return hipGetLastError();
 }
 
