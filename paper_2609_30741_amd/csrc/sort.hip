@@ -186,7 +186,7 @@ hipError_t exclusive_scan(const uint32_t* in, const uint32_t* idx, uint32_t* out
 // use 1024-key sub-chunks instead of 4096); block b owns the contiguous
 // chunk [b C, b C + C) of the *n_dev keys, C = n / grid rounded up to 256.
 // A pass is three launches:
-//   1. k_rs_hist: per-block digit counts (LDS, match-any aggregated), stored
+//   1. k_rs_hist: per-block digit counts (LDS atomics), stored
 //      digit-major: counts[d * grid + b].
 //   2. k_rs_scan: one block per digit scans its row over the blocks and
 //      writes the digit total.
@@ -242,7 +242,6 @@ __global__ __launch_bounds__(256) void k_rs_hist(const uint32_t* __restrict__ ke
     __syncthreads();
     uint32_t lo, hi;
     chunk_of(n, gridDim.x, blockIdx.x, kRsSub, &lo, &hi);
-    const uint64_t lt = (1ull << lane_id()) - 1ull;
     for (uint64_t sub = lo; sub < hi; sub += kRsSub) {
         uint32_t k[kRsItems];
 #pragma unroll
@@ -250,12 +249,12 @@ __global__ __launch_bounds__(256) void k_rs_hist(const uint32_t* __restrict__ ke
             const uint64_t i = sub + it * 256 + threadIdx.x;
             k[it] = i < hi ? keys[i] : 0u;
         }
+        // Counts only (no ranks): one LDS add per key; lanes of a wave on
+        // one digit are serialised by the LDS, which costs less than
+        // matching the digits with ballots.
 #pragma unroll
         for (int it = 0; it < kRsItems; ++it) {
-            const bool ok = sub + it * 256 + threadIdx.x < hi;
-            const uint32_t d = (k[it] >> shift) & mask;
-            const uint64_t peers = match_digit(d, __ballot(ok), bits);
-            if (ok && (peers & lt) == 0) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+            if (sub + it * 256 + threadIdx.x < hi) atomicAdd(&h[(k[it] >> shift) & mask], 1u);
         }
     }
     __syncthreads();
