@@ -311,10 +311,16 @@ struct RasterOut {
 // of a stereo frame) into the second record set; precomputed: this pass's
 // camera is that one, so it takes those records and only counts the keys
 // inside tile_mask.
+// The sorted per-tile surfel lists of a pass: surfel = vals[i] & vmask.
+struct SortedVals {
+    const uint32_t* vals;
+    uint32_t vmask;
+};
+
 int raster_pass(bgs_ctx* ctx, const Layout& L, void* ws, int64_t kc, const bgs_scene& scene, const bgs_camera& cam,
                 const bgs_raster_params& rp, const uint8_t* tile_mask, float a_min, const RasterOut& out, int which,
                 const uint32_t* reuse_order = nullptr, const uint32_t** order_out = nullptr,
-                const bgs_camera* cam_next = nullptr, bool precomputed = false) {
+                const bgs_camera* cam_next = nullptr, bool precomputed = false, SortedVals* vals_out = nullptr) {
     hipStream_t s = ctx->stream;
     const int n = (int)scene.n;
     const PreCam pc = make_precam(cam);
@@ -378,19 +384,25 @@ int raster_pass(bgs_ctx* ctx, const Layout& L, void* ws, int64_t kc, const bgs_s
     uint32_t* tva = at<uint32_t>(ws, L.tvals_a);
     uint32_t* tkb = at<uint32_t>(ws, L.tkeys_b);
     uint32_t* tvb = at<uint32_t>(ws, L.tvals_b);
-    HIP_CHECK(launch_emit(order, offs, rects, recs, n, pc.tiles_x, mask, (uint32_t)kc, tka, tva, s), "emit");
+    // A key and its surfel share one word (tile << vbits | surfel) when both
+    // fit in 32 bits: the sort then moves half the bytes.
+    const int tbits = tile_bits(n_tiles), sbits = tile_bits(n);
+    const int vbits = tbits + sbits <= 32 ? sbits : 0;
+    HIP_CHECK(launch_emit(order, offs, rects, recs, n, pc.tiles_x, mask, (uint32_t)kc, vbits, tka, tva, s), "emit");
     mark(ctx, sb + 2, 1);
     // Stable sort by tile: within a tile the emission (= compositing) order stays.
     mark(ctx, sb + 3, 0);
     // An ROI pass bins a small part of the tiles: a small sort is expected.
-    HIP_CHECK(radix_sort(tka, tva, tkb, tvb, &st->n_sort, kc, tile_bits(n_tiles), false, at<void>(ws, L.radix), s,
-                         &in_b, tile_mask ? 1 : 0),
+    HIP_CHECK(radix_sort(tka, vbits ? nullptr : tva, tkb, vbits ? nullptr : tvb, &st->n_sort, kc, tbits, false,
+                         at<void>(ws, L.radix), s, &in_b, tile_mask ? 1 : 0, vbits),
               "tile sort");
     const uint32_t* skeys = in_b ? tkb : tka;
-    const uint32_t* svals = in_b ? tvb : tva;
+    const uint32_t* svals = vbits ? skeys : in_b ? tvb : tva;
+    const uint32_t vmask = vbits ? (1u << vbits) - 1u : 0xFFFFFFFFu;
+    if (vals_out) *vals_out = SortedVals{svals, vmask};
     mark(ctx, sb + 3, 1);
     mark(ctx, sb + 4, 0);
-    HIP_CHECK(launch_ranges(skeys, &st->n_sort, kc, ranges, n_tiles, s), "ranges");
+    HIP_CHECK(launch_ranges(skeys, &st->n_sort, kc, ranges, n_tiles, vbits, s), "ranges");
     uint32_t* torder = at<uint32_t>(ws, L.torder);
     HIP_CHECK(launch_tile_order(ranges, tile_mask ? &st->n_masked : nullptr, n_tiles, torder, s), "tile order");
     mark(ctx, sb + 4, 1);
@@ -408,6 +420,7 @@ int raster_pass(bgs_ctx* ctx, const Layout& L, void* ws, int64_t kc, const bgs_s
     ba.a_min = a_min;
     ba.z_near = (float)cam.z_near;
     ba.patch = tile_mask ? 1 : 0;
+    ba.vmask = vmask;
     const ContArgs ca{which ? ctx->cap_roi : ctx->cap_dom, ctx->seg_len, L.cslots,
                       which ? ctx->far_roi : ctx->far_dom, &st->n_slots,
                       &st->n_items,
@@ -824,8 +837,10 @@ int32_t bgs_tile_lists_debug(bgs_ctx* ctx, const bgs_scene* scene, const bgs_cam
     // Scratch outputs: rgb in the piece-box region (16 B/px), depth and
     // alpha in the z-buffer (8 B/px).
     float* scratch = at<float>(ws, L.pbox);
+    SortedVals sv{};
     rc = raster_pass(ctx, L, ws, kc, *scene, *cam, *raster, nullptr, 0.f,
-                     RasterOut{scratch, at<float>(ws, L.zbuf), at<float>(ws, L.zbuf) + np, nullptr}, 0);
+                     RasterOut{scratch, at<float>(ws, L.zbuf), at<float>(ws, L.zbuf) + np, nullptr}, 0, nullptr,
+                     nullptr, nullptr, false, &sv);
     if (rc) return rc;
     DevStatus h{};
     if ((rc = finish(ctx, ws, L, &h))) return rc;
@@ -834,12 +849,9 @@ int32_t bgs_tile_lists_debug(bgs_ctx* ctx, const bgs_scene* scene, const bgs_cam
     if ((int64_t)h.n_sort > values_capacity) return fail(ctx, BGS_ERR_CAPACITY, "values_capacity too small");
     const PreCam pc = make_precam(*cam);
     const int n_tiles = pc.tiles_x * pc.tiles_y;
-    const int passes = (tile_bits(n_tiles) + 7) / 8;
-    const uint32_t* svals = (passes % 2) ? at<uint32_t>(ws, L.tvals_b) : at<uint32_t>(ws, L.tvals_a);
     HIP_CHECK(hipMemcpyAsync(ranges, at<uint2>(ws, L.ranges), 8 * (size_t)n_tiles, hipMemcpyDeviceToDevice, ctx->stream),
               "copy");
-    if (h.n_sort)
-        HIP_CHECK(hipMemcpyAsync(values, svals, 4 * (size_t)h.n_sort, hipMemcpyDeviceToDevice, ctx->stream), "copy");
+    HIP_CHECK(launch_mask_copy(sv.vals, values, (int64_t)h.n_sort, sv.vmask, ctx->stream), "copy");
     HIP_CHECK(hipStreamSynchronize(ctx->stream), "sync");
     return BGS_OK;
 }

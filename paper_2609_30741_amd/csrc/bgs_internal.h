@@ -73,6 +73,7 @@ struct BlendArgs {
     float a_min;     // patch mode: depth proxy written only when A >= a_min
     float z_near;
     int patch;       // 0: write rgb/depth_raw/alpha; 1: write rgb/z/alpha/cls
+    uint32_t vmask;  // surfel index = sorted value & vmask (values that also carry the tile key)
 };
 
 // Continuation of long tile lists in the blend (k_blend, k_blend_seg,
@@ -141,17 +142,19 @@ struct KeyCount {
 bool scan_counts(const uint32_t* in, const uint32_t* idx, uint32_t* out, int64_t n, uint32_t* tmp,
                  const KeyCount& kcnt, hipStream_t s, hipError_t* err);
 size_t radix_tmp_bytes(int64_t n_cap);
-// Stable LSD radix sort of (keys, values) by bits [0, key_bits) with digits
-// of up to 8 bits.  (ka, va) is the input, (kb, vb) the ping-pong buffer (all four
-// are real buffers); iota = true ignores the input values and uses the
-// input positions instead.  The element count is *n_dev (<= n_cap), or
-// n_cap when n_dev is null.
+// Stable LSD radix sort of (keys, values) by bits [key_shift, key_shift +
+// key_bits) of the keys, with digits of up to 8 bits.  (ka, va) is the
+// input, (kb, vb) the ping-pong buffer; iota = true ignores the input
+// values and uses the input positions instead; va = vb = null (and iota
+// false) sorts the keys alone (keys that carry their value in the bits
+// below key_shift).  The element count is *n_dev (<= n_cap), or n_cap when
+// n_dev is null.
 // Returns in *in_b whether the result is in (kb, vb).  n_hint (optional):
 // the expected element count when it is far below n_cap; it only chooses
 // the kernels' sub-chunk size, never the result.
 hipError_t radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, const uint32_t* n_dev,
                       int64_t n_cap, int key_bits, bool iota, void* tmp, hipStream_t s, bool* in_b,
-                      int64_t n_hint = 0);
+                      int64_t n_hint = 0, int key_shift = 0);
 
 // ---- rasteriser (raster.hip) --------------------------------------------------
 // cam2 (optional): also the keys, rects and records of a second camera (no
@@ -165,13 +168,17 @@ hipError_t launch_masked_counts(const uint2* rects, const SurfelRec* recs, int n
                                 uint32_t* counts, hipStream_t s);
 // Keys of every surfel in compositing order: the tiles of its rect that its
 // strip band meets (and the mask holds, when enabled), row by row.
+// vbits > 0: one word per key, tile << vbits | surfel (tvals unused);
+// vbits = 0: the tile in tkeys and the surfel in tvals.
 hipError_t launch_emit(const uint32_t* order, const uint32_t* offs, const uint2* rects, const SurfelRec* recs, int n,
-                       int tiles_x, const MaskArgs& mask, uint32_t cap, uint32_t* tkeys, uint32_t* tvals,
+                       int tiles_x, const MaskArgs& mask, uint32_t cap, int vbits, uint32_t* tkeys, uint32_t* tvals,
                        hipStream_t s);
-// Tile ranges of the sorted keys; the ranges must have been cleared (by
-// scan_counts, or launch_clear_ranges).
+// Tile ranges of the sorted keys (tile = key >> key_shift); the ranges must
+// have been cleared (by scan_counts, or launch_clear_ranges).
 hipError_t launch_ranges(const uint32_t* tkeys, const uint32_t* n_dev, int64_t cap, uint2* ranges,
-                         int n_tiles, hipStream_t s);
+                         int n_tiles, int key_shift, hipStream_t s);
+// dst[i] = src[i] & mask for i < n.
+hipError_t launch_mask_copy(const uint32_t* src, uint32_t* dst, int64_t n, uint32_t mask, hipStream_t s);
 hipError_t launch_clear_ranges(uint2* ranges, int n_tiles, hipStream_t s);
 // Dispatch order of the (compact) tiles for the blend, heaviest first.
 hipError_t launch_tile_order(const uint2* ranges, const uint32_t* n_live, int n_tiles, uint32_t* order,

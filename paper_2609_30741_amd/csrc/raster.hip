@@ -499,7 +499,7 @@ constexpr int kEmitWin = 2048;
 
 __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order, const uint32_t* __restrict__ offs,
                                               const uint2* __restrict__ rects, const SurfelRec* __restrict__ recs,
-                                              int n, int tiles_x, MaskArgs mask, uint32_t cap,
+                                              int n, int tiles_x, MaskArgs mask, uint32_t cap, int vbits,
                                               uint32_t* __restrict__ tkeys, uint32_t* __restrict__ tvals) {
     __shared__ uint32_t sk[256];
     __shared__ uint32_t seg_start[kEmitSegs + 1];
@@ -586,8 +586,13 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order
                 const uint32_t st = seg_tile[j];
                 const uint32_t g = base + p;
                 if (g < cap) {
-                    tkeys[g] = (st & 0xFFFFFFu) + (p - seg_start[j]);
-                    tvals[g] = sk[st >> 24];
+                    const uint32_t tile = (st & 0xFFFFFFu) + (p - seg_start[j]);
+                    if (vbits) {
+                        tkeys[g] = tile << vbits | sk[st >> 24];
+                    } else {
+                        tkeys[g] = tile;
+                        tvals[g] = sk[st >> 24];
+                    }
                 }
             }
             __syncthreads();
@@ -602,19 +607,19 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order
 // Each thread takes four consecutive keys (one 16-byte load; the keys
 // buffer is 16-byte aligned) and the key before them.
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_dev,
-                                                uint2* __restrict__ ranges, uint32_t n_tiles) {
+                                                uint2* __restrict__ ranges, uint32_t n_tiles, int shift) {
     const uint32_t n = *n_dev;
     for (uint64_t q = (uint64_t)blockIdx.x * 256 + threadIdx.x; 4 * q < n; q += (uint64_t)gridDim.x * 256) {
         const uint32_t i0 = (uint32_t)(4 * q);
         uint32_t k[4];
         if (i0 + 3 < n) {
             const uint4 v = *reinterpret_cast<const uint4*>(keys + i0);
-            k[0] = v.x; k[1] = v.y; k[2] = v.z; k[3] = v.w;
+            k[0] = v.x >> shift; k[1] = v.y >> shift; k[2] = v.z >> shift; k[3] = v.w >> shift;
         } else {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) k[u] = i0 + u < n ? keys[i0 + u] : 0xFFFFFFFFu;
+            for (int u = 0; u < 4; ++u) k[u] = i0 + u < n ? keys[i0 + u] >> shift : 0xFFFFFFFFu;
         }
-        uint32_t prev = i0 > 0 ? keys[i0 - 1] : 0xFFFFFFFFu;
+        uint32_t prev = i0 > 0 ? keys[i0 - 1] >> shift : 0xFFFFFFFFu;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const uint32_t i = i0 + u;
@@ -915,8 +920,9 @@ __device__ __forceinline__ void walk_batch(const float4* s_rec, uint32_t nb, uin
 }
 
 __device__ __forceinline__ void load_rec(const SurfelRec* __restrict__ recs, const uint32_t* __restrict__ vals,
-                                         uint32_t pos, float4& q0, float4& q1, float4& q2, float4& q3) {
-    const SurfelRec* r = recs + vals[pos];
+                                         uint32_t pos, uint32_t vmask, float4& q0, float4& q1, float4& q2,
+                                         float4& q3) {
+    const SurfelRec* r = recs + (vals[pos] & vmask);
     q0 = r->a;
     q1 = r->b;
     q2 = r->c;
@@ -936,13 +942,13 @@ __device__ __forceinline__ void walk_range(const SurfelRec* __restrict__ recs, c
                                            uint32_t b, uint32_t e, float4* s_rec, uint16_t* s_list,
                                            const TileGeom& g, const BlendArgs& a, PixelState& p, WalkCounts& wc) {
     float4 q0, q1, q2, q3;
-    if (b + g.tid < e) load_rec(recs, vals, b + g.tid, q0, q1, q2, q3);
+    if (b + g.tid < e) load_rec(recs, vals, b + g.tid, a.vmask, q0, q1, q2, q3);
     for (uint32_t base = b; base < e; base += kBatch) {
         const uint32_t nb = min((uint32_t)kBatch, e - base);
         __syncthreads();
         if ((uint32_t)g.tid < nb) stage_rec(s_rec, g.tid, q0, q1, q2, q3);
         __syncthreads();
-        if (base + kBatch + g.tid < e) load_rec(recs, vals, base + kBatch + g.tid, q0, q1, q2, q3);
+        if (base + kBatch + g.tid < e) load_rec(recs, vals, base + kBatch + g.tid, a.vmask, q0, q1, q2, q3);
         walk_batch<kCount>(s_rec, nb, s_list, g, a, p, wc);
         if (__syncthreads_count(live(p)) == 0) break;
     }
@@ -1046,14 +1052,14 @@ __global__ __launch_bounds__(256) void k_blend(const SurfelRec* __restrict__ rec
     // tile decides once whether to hand the rest over (then it leaves the
     // loop) or to walk on.
     float4 q0, q1, q2, q3;
-    if (rg.x + g.tid < rg.y) load_rec(recs, vals, rg.x + g.tid, q0, q1, q2, q3);
+    if (rg.x + g.tid < rg.y) load_rec(recs, vals, rg.x + g.tid, a.vmask, q0, q1, q2, q3);
     for (uint32_t base = rg.x; base < rg.y;) {
         const uint32_t lim = base < mid ? mid : base < cap_end ? cap_end : rg.y;
         const uint32_t nb = min((uint32_t)kBatch, lim - base);
         __syncthreads();
         if ((uint32_t)g.tid < nb) stage_rec(s_rec, g.tid, q0, q1, q2, q3);
         __syncthreads();
-        if (base + nb + g.tid < rg.y) load_rec(recs, vals, base + nb + g.tid, q0, q1, q2, q3);
+        if (base + nb + g.tid < rg.y) load_rec(recs, vals, base + nb + g.tid, a.vmask, q0, q1, q2, q3);
         walk_batch<kCount>(s_rec, nb, my_list, g, a, p, wc);
         base += nb;
         if (!half_taken && base >= mid) {
@@ -1361,19 +1367,34 @@ hipError_t launch_masked_counts(const uint2* rects, const SurfelRec* recs, int n
 }
 
 hipError_t launch_emit(const uint32_t* order, const uint32_t* offs, const uint2* rects, const SurfelRec* recs, int n,
-                       int tiles_x, const MaskArgs& mask, uint32_t cap, uint32_t* tkeys, uint32_t* tvals,
+                       int tiles_x, const MaskArgs& mask, uint32_t cap, int vbits, uint32_t* tkeys, uint32_t* tvals,
                        hipStream_t s) {
     if (n <= 0) return hipSuccess;
+    if (vbits < 0 || vbits > 31 || (vbits && (int64_t)n > ((int64_t)1 << vbits))) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_emit, dim3((n + 255) / 256), dim3(256), 0, s, order, offs, rects, recs, n, tiles_x, mask,
-                       cap, tkeys, tvals);
+                       cap, vbits, tkeys, tvals);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_mask_copy(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst,
+                                                   int64_t n, uint32_t mask) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) dst[i] = src[i] & mask;
+}
+
+hipError_t launch_mask_copy(const uint32_t* src, uint32_t* dst, int64_t n, uint32_t mask, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mask_copy, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, n, mask);
     return hipGetLastError();
 }
 
 hipError_t launch_ranges(const uint32_t* tkeys, const uint32_t* n_dev, int64_t cap, uint2* ranges, int n_tiles,
-                         hipStream_t s) {
+                         int key_shift, hipStream_t s) {
+    if (key_shift < 0 || key_shift > 31) return hipErrorInvalidValue;
     if (n_tiles <= 0) return hipSuccess;
     const int64_t blocks = std::min<int64_t>(4096, std::max<int64_t>(1, (cap + 1023) / 1024));
-    hipLaunchKernelGGL(k_ranges, dim3((unsigned)blocks), dim3(256), 0, s, tkeys, n_dev, ranges, (uint32_t)n_tiles);
+    hipLaunchKernelGGL(k_ranges, dim3((unsigned)blocks), dim3(256), 0, s, tkeys, n_dev, ranges, (uint32_t)n_tiles,
+                       key_shift);
     return hipGetLastError();
 }
 

@@ -300,6 +300,7 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const uint32_t* __restrict__
     __shared__ uint32_t run[kRsBins];
     __shared__ uint32_t lds[4];
     const uint32_t n = n_dev ? *n_dev : n_host, bins = 1u << bits, mask = bins - 1u;
+    const bool has_v = vout != nullptr;  // keys only (a key that carries its value) when null
     uint32_t lo, hi;
     chunk_of(n, gridDim.x, blockIdx.x, kRsSub, &lo, &hi);
     if (lo >= hi) return;
@@ -322,7 +323,7 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const uint32_t* __restrict__
             const uint64_t i = sub + wave * (64 * kRsItems) + it * 64 + lane;
             const bool ok = i < hi;
             k[it] = ok ? kin[i] : 0u;
-            v[it] = ok ? (vin ? vin[i] : (uint32_t)i) : 0u;
+            v[it] = (ok && has_v) ? (vin ? vin[i] : (uint32_t)i) : 0u;
         }
 #pragma unroll
         for (int it = 0; it < kRsItems; ++it) {
@@ -357,7 +358,7 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const uint32_t* __restrict__
             if (r[it] != 0xFFFFFFFFu) {
                 const uint32_t lp = cnt[wave][(k[it] >> shift) & mask] + r[it];
                 s_keys[lp] = k[it];
-                s_vals[lp] = v[it];
+                if (has_v) s_vals[lp] = v[it];
             }
         }
         __syncthreads();
@@ -368,7 +369,7 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const uint32_t* __restrict__
             const uint32_t o = gbase[d] + (p - dstart[d]);
             if (o < n) {  // always true for consistent counts; keeps every write in bounds
                 kout[o] = kk;
-                vout[o] = s_vals[p];
+                if (has_v) vout[o] = s_vals[p];
             }
         }
         __syncthreads();
@@ -390,7 +391,8 @@ size_t radix_tmp_bytes(int64_t n_cap) {
 }
 
 hipError_t radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, const uint32_t* n_dev,
-                      int64_t n_cap, int key_bits, bool iota, void* tmp, hipStream_t s, bool* in_b, int64_t n_hint) {
+                      int64_t n_cap, int key_bits, bool iota, void* tmp, hipStream_t s, bool* in_b, int64_t n_hint,
+                      int key_shift) {
     *in_b = false;
     if (n_cap <= 0 || key_bits <= 0) return hipSuccess;
     if (n_cap > 0xFFFFFFFFll) return hipErrorInvalidValue;
@@ -407,8 +409,9 @@ hipError_t radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, co
     uint32_t *ki = ka, *ko = kb, *vo = vb;
     const uint32_t* vi = iota ? nullptr : va;
     bool cur_b = false;
-    for (int shift = 0; shift < key_bits; shift += per) {
-        const int bits = key_bits - shift < per ? key_bits - shift : per;
+    if (key_shift < 0 || key_shift + key_bits > 32) return hipErrorInvalidValue;
+    for (int shift = key_shift; shift < key_shift + key_bits; shift += per) {
+        const int bits = key_shift + key_bits - shift < per ? key_shift + key_bits - shift : per;
         if (small)
             hipLaunchKernelGGL(k_rs_hist<kRsItemsSmall>, dim3(grid), dim3(256), 0, s, ki, n_dev, (uint32_t)n_cap, shift,
                                bits, counts);
