@@ -379,6 +379,153 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const uint32_t* __restrict__
     }
 }
 
+// k_rs_scatter for digits of at most 6 bits and 4096-key sub-chunks, with
+// the ranks taken from per-thread digit counters instead of ballots: thread
+// t holds the sub-chunk's keys [16 t, 16 t + 16) (blocked, so input order is
+// (thread, item) order), counts its digits in a 16-bit LDS counter per
+// (digit, thread), a raking scan of the counters in (digit, thread) order
+// gives every (digit, thread) its first rank, and the thread's own count
+// before each key adds the rest.  Stable, like the ballot ranking, at a
+// fraction of its vector work.  The counter words are padded by one word in
+// 32 so the raking threads hit distinct banks; the same LDS holds the
+// reordered keys and values once the ranks are known.
+constexpr int kRsCntBits = 6;
+constexpr int kRsCntBins = 1 << kRsCntBits;
+constexpr int kRsCntWords = kRsCntBins * 256 / 2;                 // two 16-bit counters a word
+constexpr int kRsCntLds = kRsCntWords + kRsCntWords / 32;         // with the padding
+static_assert(kRsCntLds >= 2 * 256 * kRsItemsBig, "the counter LDS also holds a sub-chunk's keys and values");
+
+__device__ __forceinline__ uint32_t cnt_slot(uint32_t w) { return w + (w >> 5); }
+
+__global__ __launch_bounds__(256) void k_rs_scatter_cnt(const uint32_t* __restrict__ kin,
+                                                        const uint32_t* __restrict__ vin,
+                                                        uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                        const uint32_t* __restrict__ n_dev, uint32_t n_host,
+                                                        int shift, int bits, const uint32_t* __restrict__ counts,
+                                                        const uint32_t* __restrict__ totals) {
+    constexpr int kItems = kRsItemsBig;
+    constexpr int kSub = 256 * kItems;
+    __shared__ uint32_t s_buf[kRsCntLds];
+    __shared__ uint32_t dstart[kRsCntBins + 1];
+    __shared__ uint32_t gbase[kRsCntBins];
+    __shared__ uint32_t run[kRsCntBins];
+    __shared__ uint32_t lds[4];
+    uint32_t* s_keys = s_buf;
+    uint32_t* s_vals = s_buf + kSub;
+    const uint32_t n = n_dev ? *n_dev : n_host, bins = 1u << bits, mask = bins - 1u;
+    const bool has_v = vout != nullptr;
+    uint32_t lo, hi;
+    chunk_of(n, gridDim.x, blockIdx.x, kSub, &lo, &hi);
+    if (lo >= hi) return;
+    const uint32_t t = threadIdx.x;
+    {
+        // run[d] = (keys of smaller digits) + (keys of digit d in earlier blocks).
+        const uint32_t tv = t < bins ? totals[t] : 0u;
+        const uint32_t acc = block_excl_scan(tv, lds, nullptr);
+        if (t < bins) run[t] = acc + counts[(uint64_t)t * gridDim.x + blockIdx.x];
+    }
+    const uint32_t rake = bins / 2;         // counter words per thread (bins * 256 / 2 words over 256 threads)
+    const uint32_t nclear = cnt_slot(bins * 128u);
+    for (uint64_t sub = lo; sub < hi; sub += kSub) {
+        const uint32_t m = (uint32_t)min<uint64_t>((uint64_t)kSub, hi - sub);
+        const uint32_t i0 = t * kItems;
+        uint32_t k[kItems], v[kItems], r[kItems];
+        if (i0 + kItems <= m) {
+            const uint4* kp = reinterpret_cast<const uint4*>(kin + sub + i0);
+#pragma unroll
+            for (int q = 0; q < kItems / 4; ++q) {
+                const uint4 x = kp[q];
+                k[4 * q] = x.x; k[4 * q + 1] = x.y; k[4 * q + 2] = x.z; k[4 * q + 3] = x.w;
+            }
+            if (has_v && vin) {
+                const uint4* vp = reinterpret_cast<const uint4*>(vin + sub + i0);
+#pragma unroll
+                for (int q = 0; q < kItems / 4; ++q) {
+                    const uint4 x = vp[q];
+                    v[4 * q] = x.x; v[4 * q + 1] = x.y; v[4 * q + 2] = x.z; v[4 * q + 3] = x.w;
+                }
+            } else {
+#pragma unroll
+                for (int it = 0; it < kItems; ++it) v[it] = (uint32_t)(sub + i0 + it);
+            }
+        } else {
+#pragma unroll
+            for (int it = 0; it < kItems; ++it) {
+                const bool ok = i0 + it < m;
+                k[it] = ok ? kin[sub + i0 + it] : 0u;
+                v[it] = ok ? (has_v && vin ? vin[sub + i0 + it] : (uint32_t)(sub + i0 + it)) : 0u;
+            }
+        }
+        for (uint32_t w = t; w < nclear; w += 256) s_buf[w] = 0u;
+        __syncthreads();
+        // This thread's count of each digit before each of its keys.
+#pragma unroll
+        for (int it = 0; it < kItems; ++it) {
+            if (i0 + it < m) {
+                const uint32_t d = (k[it] >> shift) & mask;
+                const uint32_t e = d * 256u + t;
+                const uint32_t h = 16u * (e & 1u);
+                const uint32_t old = atomicAdd(&s_buf[cnt_slot(e >> 1)], 1u << h);
+                r[it] = (old >> h) & 0xFFFFu;
+            }
+        }
+        __syncthreads();
+        // Raking exclusive scan of the counters in (digit, thread) order.
+        uint32_t wv[kRsCntBins / 2];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int j = 0; j < kRsCntBins / 2; ++j) {
+            if ((uint32_t)j < rake) {
+                wv[j] = s_buf[cnt_slot(t * rake + j)];
+                sum += (wv[j] & 0xFFFFu) + (wv[j] >> 16);
+            }
+        }
+        uint32_t acc = block_excl_scan(sum, lds, nullptr);
+#pragma unroll
+        for (int j = 0; j < kRsCntBins / 2; ++j) {
+            if ((uint32_t)j < rake) {
+                const uint32_t e0 = acc;
+                acc += wv[j] & 0xFFFFu;
+                s_buf[cnt_slot(t * rake + j)] = e0 | (acc << 16);
+                acc += wv[j] >> 16;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < kItems; ++it) {
+            if (i0 + it < m) {
+                const uint32_t e = ((k[it] >> shift) & mask) * 256u + t;
+                r[it] += (s_buf[cnt_slot(e >> 1)] >> (16u * (e & 1u))) & 0xFFFFu;
+            }
+        }
+        if (t < bins) dstart[t] = s_buf[cnt_slot(t * 128u)] & 0xFFFFu;
+        if (t == 0) dstart[bins] = m;
+        __syncthreads();  // every counter read is done before the keys overwrite them
+        if (t < bins) {
+            gbase[t] = run[t];
+            run[t] += dstart[t + 1] - dstart[t];
+        }
+#pragma unroll
+        for (int it = 0; it < kItems; ++it) {
+            if (i0 + it < m) {
+                s_keys[r[it]] = k[it];
+                if (has_v) s_vals[r[it]] = v[it];
+            }
+        }
+        __syncthreads();
+        for (uint32_t p = t; p < m; p += 256) {
+            const uint32_t kk = s_keys[p];
+            const uint32_t d = (kk >> shift) & mask;
+            const uint32_t o = gbase[d] + (p - dstart[d]);
+            if (o < n) {  // always true for consistent counts; keeps every write in bounds
+                kout[o] = kk;
+                if (has_v) vout[o] = s_vals[p];
+            }
+        }
+        __syncthreads();
+    }
+}
+
 uint32_t rs_grid(int64_t n_cap, int items) {
     const int64_t g = ceil_div(n_cap > 0 ? n_cap : 1, 256 * items);
     return (uint32_t)(g < kRsGrid ? g : kRsGrid);
@@ -406,6 +553,9 @@ hipError_t radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, co
     uint32_t* totals = counts + (size_t)kRsBins * grid;
     const int passes = (key_bits + kRsMaxBits - 1) / kRsMaxBits;
     const int per = (key_bits + passes - 1) / passes;
+    // The counter-ranked scatter loads 16-byte vectors.
+    const auto a16 = [](const void* p) { return ((uintptr_t)p & 15u) == 0; };
+    const bool aligned = a16(ka) && a16(kb) && a16(va) && a16(vb);
     uint32_t *ki = ka, *ko = kb, *vo = vb;
     const uint32_t* vi = iota ? nullptr : va;
     bool cur_b = false;
@@ -421,6 +571,9 @@ hipError_t radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, co
         hipLaunchKernelGGL(k_rs_scan, dim3(1u << bits), dim3(256), 0, s, counts, grid, totals);
         if (small)
             hipLaunchKernelGGL(k_rs_scatter<kRsItemsSmall>, dim3(grid), dim3(256), 0, s, ki, vi, ko, vo, n_dev,
+                               (uint32_t)n_cap, shift, bits, counts, totals);
+        else if (bits <= kRsCntBits && aligned)
+            hipLaunchKernelGGL(k_rs_scatter_cnt, dim3(grid), dim3(256), 0, s, ki, vi, ko, vo, n_dev,
                                (uint32_t)n_cap, shift, bits, counts, totals);
         else
             hipLaunchKernelGGL(k_rs_scatter<kRsItemsBig>, dim3(grid), dim3(256), 0, s, ki, vi, ko, vo, n_dev,

@@ -69,7 +69,10 @@ def check_image(gpu_rgb, gpu_d, gpu_a, ref, where=""):
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("n,bits", [(0, 8), (1, 8), (4095, 8), (4096, 13), (4097, 13), (100_003, 11),
-                                    (1_000_001, 32), (250_000, 1), (70_000, 20)])
+                                    (1_000_001, 32), (250_000, 1), (70_000, 20),
+                                    # above 2^20 elements: 4096-key sub-chunks; digits of at most
+                                    # 6 bits are ranked by per-thread counters
+                                    (1_500_007, 11), (1_048_577, 5), (2_000_003, 12), (1_100_000, 6)])
 def test_sort_pairs_bit_exact(ctx, n, bits):
     log(f"sort n={n} bits={bits}")
     keys, vals = synth.random_sort_keys(n, seed=n + bits, key_bits=32)
@@ -135,16 +138,20 @@ def test_preprocess_keys_and_conservative_bins(ctx, oracle):
     log(f"binning: {int(counts.sum())} keys of {int(area.sum())} rect tiles")
 
 
-def test_tile_lists_are_sorted_and_complete(ctx, oracle):
+@pytest.mark.parametrize("capacity", [None, 3_000_000])
+def test_tile_lists_are_sorted_and_complete(ctx, oracle, capacity):
     """Every tile's list is its rect-binned surfels in compositing order,
     less the ones whose strip band misses the tile; the dropped ones give
     alpha < alpha_min at every pixel of the tile (checked with the oracle's
-    pair evaluation on a sample)."""
+    pair evaluation on a sample).  A key capacity above 2^20 takes the
+    large-sort kernels (a fresh context, so the workspace holds exactly it)."""
     sc, cam = cube_workload(4000, 128, 96, 140.0, seed=3)
     ds = api.DeviceScene(sc)
+    if capacity:
+        ctx = api.Context(sync=True)
     zkey, rects, _ = ctx.preprocess_debug(ds, cam)
     zkey, rects = to_np(zkey).view(np.uint32), to_np(rects)
-    ranges, vals, nk = ctx.tile_lists_debug(ds, cam)
+    ranges, vals, nk = ctx.tile_lists_debug(ds, cam, capacity=capacity)
     ranges, vals = to_np(ranges), to_np(vals)
     tx_n = (cam.width + 15) // 16
     dropped = []
@@ -171,10 +178,14 @@ def test_tile_lists_are_sorted_and_complete(ctx, oracle):
                 assert pr is None or pr["alpha"] < 1.0 / 255.0, f"surfel {k} reaches pixel ({i}, {j}) of tile ({tx}, {ty})"
 
 
-@pytest.mark.parametrize("W,H", [(256, 256), (37, 23), (129, 65)])
-def test_render_dominant_cube(ctx, oracle, W, H):
+@pytest.mark.parametrize("W,H,capacity", [(256, 256, None), (37, 23, None), (129, 65, None), (256, 256, 2_500_000)])
+def test_render_dominant_cube(ctx, oracle, W, H, capacity):
     sc, cam = cube_workload(10_000, W, H, 300.0 * W / 256)
-    log(f"render cube {W}x{H}")
+    log(f"render cube {W}x{H} capacity {capacity}")
+    if capacity:
+        # Large-sort kernels: a fresh context whose workspace holds this many keys.
+        ctx = api.Context(sync=True)
+        ctx.reserve(10_000, W, H, capacity)
     out = ctx.render_dominant(api.DeviceScene(sc), cam)
     ref = oracle.render(sc, cam)
     check_image(to_np(out["rgb"]), to_np(out["depth_raw"]), to_np(out["alpha"]), ref, f"cube {W}x{H}")
