@@ -344,7 +344,7 @@ int raster_pass(bgs_ctx* ctx, const Layout& L, void* ws, int64_t kc, const bgs_s
     uint32_t* offs = at<uint32_t>(ws, L.offs);
     if (precomputed) {
         if (!tile_mask) return fail(ctx, BGS_ERR_INVALID_ARG, "precomputed records need a tile mask");
-        HIP_CHECK(launch_masked_counts(rects, recs, n, mask, counts, s), "masked counts");
+        HIP_CHECK(launch_masked_counts(rects, recs, n, n_tiles, mask, counts, s), "masked counts");
     } else {
         const SceneArgs sa{scene.pos, scene.quat, scene.scale, scene.opacity, scene.sh, n, scene.sh_degree};
         PreCam pn{};
@@ -388,7 +388,7 @@ int raster_pass(bgs_ctx* ctx, const Layout& L, void* ws, int64_t kc, const bgs_s
     // fit in 32 bits: the sort then moves half the bytes.
     const int tbits = tile_bits(n_tiles), sbits = tile_bits(n);
     const int vbits = tbits + sbits <= 32 ? sbits : 0;
-    HIP_CHECK(launch_emit(order, offs, rects, recs, n, pc.tiles_x, mask, (uint32_t)kc, vbits, tka, tva, s), "emit");
+    HIP_CHECK(launch_emit(order, offs, rects, recs, n, pc.tiles_x, n_tiles, mask, (uint32_t)kc, vbits, tka, tva, s), "emit");
     mark(ctx, sb + 2, 1);
     // Stable sort by tile: within a tile the emission (= compositing) order stays.
     mark(ctx, sb + 3, 0);

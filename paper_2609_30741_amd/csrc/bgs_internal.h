@@ -164,15 +164,15 @@ hipError_t launch_preprocess(const SceneArgs& sc, const PreCam& cam, float alpha
                              uint32_t* counts, const PreCam* cam2, SurfelRec* recs2, uint32_t* zkeys2,
                              uint2* rects2, hipStream_t s);
 // Key counts within the mask's tiles from precomputed tile rects and records.
-hipError_t launch_masked_counts(const uint2* rects, const SurfelRec* recs, int n, const MaskArgs& mask,
+hipError_t launch_masked_counts(const uint2* rects, const SurfelRec* recs, int n, int n_tiles, const MaskArgs& mask,
                                 uint32_t* counts, hipStream_t s);
 // Keys of every surfel in compositing order: the tiles of its rect that its
 // strip band meets (and the mask holds, when enabled), row by row.
 // vbits > 0: one word per key, tile << vbits | surfel (tvals unused);
 // vbits = 0: the tile in tkeys and the surfel in tvals.
 hipError_t launch_emit(const uint32_t* order, const uint32_t* offs, const uint2* rects, const SurfelRec* recs, int n,
-                       int tiles_x, const MaskArgs& mask, uint32_t cap, int vbits, uint32_t* tkeys, uint32_t* tvals,
-                       hipStream_t s);
+                       int tiles_x, int n_tiles, const MaskArgs& mask, uint32_t cap, int vbits, uint32_t* tkeys,
+                       uint32_t* tvals, hipStream_t s);
 // Tile ranges of the sorted keys (tile = key >> key_shift); the ranges must
 // have been cleared (by scan_counts, or launch_clear_ranges).
 hipError_t launch_ranges(const uint32_t* tkeys, const uint32_t* n_dev, int64_t cap, uint2* ranges,

@@ -466,9 +466,17 @@ __global__ __launch_bounds__(256) void k_preprocess(SceneArgs sc, PreCam cam, Pr
 
 // Key counts of surfels whose tile rects and records were computed
 // earlier, restricted to the tiles of a mask.
+// The mask prefix is staged in LDS (dynamic shared memory, mask_lds words)
+// when it fits: the band rows read it twice a row.
 __global__ __launch_bounds__(256) void k_masked_counts(const uint2* __restrict__ rects,
                                                        const SurfelRec* __restrict__ recs, int n, MaskArgs mask,
-                                                       uint32_t* __restrict__ counts) {
+                                                       int mask_lds, uint32_t* __restrict__ counts) {
+    extern __shared__ uint32_t s_mpre[];
+    if (mask_lds > 0) {  // uniform over the grid
+        for (int i = threadIdx.x; i < mask_lds; i += 256) s_mpre[i] = mask.prefix[i];
+        __syncthreads();
+        mask.prefix = s_mpre;
+    }
     const int k = blockIdx.x * 256 + threadIdx.x;
     if (k >= n) return;
     const uint2 r = rects[k];
@@ -482,25 +490,27 @@ __global__ __launch_bounds__(256) void k_masked_counts(const uint2* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Key emission: one block per 256 consecutive surfels in compositing order;
-// output positions are spread evenly over the block's threads (each finds
-// its surfel by binary search over the block's offsets), so a surfel that
-// covers the whole screen does not serialise one thread.
+// Key emission, per block of 256 surfels in compositing order: one thread
+// per surfel lists the non-empty rows of its band within its rect as
+// segments (start of the segment's keys in the block, the first tile's key
+// and the surfel), in LDS.  The block's keys are then taken in windows: each
+// segment marks its keys of the window with its index in an owner table,
+// and each key is written from its owner's segment, with consecutive
+// threads on consecutive keys, so a surfel that covers many tiles does not
+// serialise one thread.  A block with more segments than the table holds
+// takes them in turns of the table's size.  With a tile mask, its prefix
+// table is staged in LDS (dynamic shared memory) when it fits.
 // ---------------------------------------------------------------------------
-// Per block of 256 surfels: one thread per surfel lists the non-empty rows
-// of its band within its rect as segments (start of the segment's keys in
-// the block, the first tile's key and the surfel), in LDS.  The block's keys
-// are then taken in windows: each segment marks its keys of the window with
-// its index in an owner table, and each key is written from its owner's
-// segment, with consecutive threads on consecutive keys.  A block with more
-// segments than the table holds takes them in turns of the table's size.
 constexpr int kEmitSegs = 2048;
 constexpr int kEmitWin = 2048;
+constexpr int kEmitMaskLds = 8192;  // mask prefix words staged in LDS at most (32 KiB)
 
 __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order, const uint32_t* __restrict__ offs,
                                               const uint2* __restrict__ rects, const SurfelRec* __restrict__ recs,
-                                              int n, int tiles_x, MaskArgs mask, uint32_t cap, int vbits,
-                                              uint32_t* __restrict__ tkeys, uint32_t* __restrict__ tvals) {
+                                              int n, int tiles_x, MaskArgs mask, int mask_lds, uint32_t cap,
+                                              int vbits, uint32_t* __restrict__ tkeys,
+                                              uint32_t* __restrict__ tvals) {
+    extern __shared__ uint32_t s_mpre[];  // mask_lds words: the mask prefix, when staged
     __shared__ uint32_t sk[256];
     __shared__ uint32_t seg_start[kEmitSegs + 1];
     __shared__ uint32_t seg_tile[kEmitSegs];  // first tile's key | surfel << 24 (keys < 2^20: sides <= 16384 px)
@@ -510,6 +520,12 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order
     const int m = min(256, n - r0);
     const uint32_t base = offs[r0];
     const int t = threadIdx.x;
+    const uint32_t* pref = mask.prefix;
+    if (mask_lds > 0) {  // uniform over the grid
+        for (int i = t; i < mask_lds; i += 256) s_mpre[i] = mask.prefix[i];
+        __syncthreads();
+        pref = s_mpre;
+    }
     uint2 rc = make_uint2(0xFFFFFFFFu, 0u);
     uint32_t cnt = 0, loc = 0;
     SurfelRec rec;
@@ -533,7 +549,7 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order
             br.row(ty, tx0, tx1, &a, &b);
             if (b < a) continue;
             const int64_t rb = (int64_t)ty * tiles_x;
-            const uint32_t c = mask.enabled ? mask.prefix[rb + b + 1] - mask.prefix[rb + a] : (uint32_t)(b - a + 1);
+            const uint32_t c = mask.enabled ? pref[rb + b + 1] - pref[rb + a] : (uint32_t)(b - a + 1);
             ns += c ? 1u : 0u;
         }
     }
@@ -560,11 +576,11 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order
                 if (b < a) continue;
                 const int64_t rb = (int64_t)ty * tiles_x;
                 const uint32_t c =
-                    mask.enabled ? mask.prefix[rb + b + 1] - mask.prefix[rb + a] : (uint32_t)(b - a + 1);
+                    mask.enabled ? pref[rb + b + 1] - pref[rb + a] : (uint32_t)(b - a + 1);
                 if (!c) continue;
                 if (si >= w0) {
                     seg_start[si - w0] = kpos;
-                    seg_tile[si - w0] = (mask.enabled ? mask.prefix[rb + a] : (uint32_t)(rb + a)) | ((uint32_t)t << 24);
+                    seg_tile[si - w0] = (mask.enabled ? pref[rb + a] : (uint32_t)(rb + a)) | ((uint32_t)t << 24);
                     if (si + 1 == w1) seg_start[w1 - w0] = kpos + c;  // end of the turn's keys
                 }
                 kpos += c;
@@ -1359,20 +1375,23 @@ hipError_t launch_preprocess(const SceneArgs& sc, const PreCam& cam, float alpha
     return hipGetLastError();
 }
 
-hipError_t launch_masked_counts(const uint2* rects, const SurfelRec* recs, int n, const MaskArgs& mask,
+hipError_t launch_masked_counts(const uint2* rects, const SurfelRec* recs, int n, int n_tiles, const MaskArgs& mask,
                                 uint32_t* counts, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_masked_counts, dim3((n + 255) / 256), dim3(256), 0, s, rects, recs, n, mask, counts);
+    const int mask_lds = n_tiles + 1 <= kEmitMaskLds ? n_tiles + 1 : 0;
+    hipLaunchKernelGGL(k_masked_counts, dim3((n + 255) / 256), dim3(256), (size_t)mask_lds * sizeof(uint32_t), s,
+                       rects, recs, n, mask, mask_lds, counts);
     return hipGetLastError();
 }
 
 hipError_t launch_emit(const uint32_t* order, const uint32_t* offs, const uint2* rects, const SurfelRec* recs, int n,
-                       int tiles_x, const MaskArgs& mask, uint32_t cap, int vbits, uint32_t* tkeys, uint32_t* tvals,
-                       hipStream_t s) {
+                       int tiles_x, int n_tiles, const MaskArgs& mask, uint32_t cap, int vbits, uint32_t* tkeys,
+                       uint32_t* tvals, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     if (vbits < 0 || vbits > 31 || (vbits && (int64_t)n > ((int64_t)1 << vbits))) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_emit, dim3((n + 255) / 256), dim3(256), 0, s, order, offs, rects, recs, n, tiles_x, mask,
-                       cap, vbits, tkeys, tvals);
+    const int mask_lds = mask.enabled && n_tiles + 1 <= kEmitMaskLds ? n_tiles + 1 : 0;
+    hipLaunchKernelGGL(k_emit, dim3((n + 255) / 256), dim3(256), (size_t)mask_lds * sizeof(uint32_t), s, order, offs,
+                       rects, recs, n, tiles_x, mask, mask_lds, cap, vbits, tkeys, tvals);
     return hipGetLastError();
 }
 

@@ -138,14 +138,23 @@ def test_preprocess_keys_and_conservative_bins(ctx, oracle):
     log(f"binning: {int(counts.sum())} keys of {int(area.sum())} rect tiles")
 
 
-@pytest.mark.parametrize("capacity", [None, 3_000_000])
-def test_tile_lists_are_sorted_and_complete(ctx, oracle, capacity):
+def large_surfel_workload(n=1500, W=320, H=320, f=300.0, seed=5):
+    """Surfels spanning about ten tile rows each: a workgroup of 256 of them
+    has more band-row segments than the emission's LDS table holds."""
+    sc = synth.scene_uniform_cube(seed, n, log_scale=(-0.9, 0.2))
+    cam = synth.look_at((0.0, -4.0, 0.0), (0, 0, 0), (0, 0, 1), W, H, f)
+    return sc, cam
+
+
+@pytest.mark.parametrize("case,capacity", [("cube", None), ("cube", 3_000_000), ("large_surfels", 400_000)])
+def test_tile_lists_are_sorted_and_complete(ctx, oracle, case, capacity):
     """Every tile's list is its rect-binned surfels in compositing order,
     less the ones whose strip band misses the tile; the dropped ones give
     alpha < alpha_min at every pixel of the tile (checked with the oracle's
     pair evaluation on a sample).  A key capacity above 2^20 takes the
-    large-sort kernels (a fresh context, so the workspace holds exactly it)."""
-    sc, cam = cube_workload(4000, 128, 96, 140.0, seed=3)
+    large-sort kernels (a fresh context, so the workspace holds exactly it);
+    large surfels make the emission take its segments in several turns."""
+    sc, cam = cube_workload(4000, 128, 96, 140.0, seed=3) if case == "cube" else large_surfel_workload()
     ds = api.DeviceScene(sc)
     if capacity:
         ctx = api.Context(sync=True)
@@ -176,6 +185,15 @@ def test_tile_lists_are_sorted_and_complete(ctx, oracle, capacity):
             for i in range(16 * tx, min(16 * tx + 16, cam.width)):
                 pr = oracle.pair(sc, cam, k, i, j)
                 assert pr is None or pr["alpha"] < 1.0 / 255.0, f"surfel {k} reaches pixel ({i}, {j}) of tile ({tx}, {ty})"
+
+
+def test_render_dominant_large_surfels(ctx, oracle):
+    """Large surfels (several emission turns per workgroup) render as the oracle does."""
+    sc, cam = large_surfel_workload()
+    log("render large surfels 320x320")
+    out = ctx.render_dominant(api.DeviceScene(sc), cam)
+    ref = oracle.render(sc, cam)
+    check_image(to_np(out["rgb"]), to_np(out["depth_raw"]), to_np(out["alpha"]), ref, "large surfels")
 
 
 @pytest.mark.parametrize("W,H,capacity", [(256, 256, None), (37, 23, None), (129, 65, None), (256, 256, 2_500_000)])
