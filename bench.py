@@ -20,6 +20,11 @@ synchronisations:
   * frames in flight (`value`): --inflight contexts, each with its own
     workspace and default-priority stream, frames assigned round robin, as
     a serving loop runs independent frames; throughput = steps / wall time.
+    Long tile lists are not split into continuation segments here
+    (--inflight-split): the segments shorten one frame's blend by doing
+    speculative extra work, which costs throughput when other frames
+    already fill the GPU.  One frame at a time keeps the library's
+    latency-oriented default split.
 The two-pass comparison (the same full render for both eyes) is timed the
 same two ways.  The per-stage breakdown comes from a separate, fully
 instrumented pass.  Prints one JSON line.
@@ -80,6 +85,9 @@ def main():
     ap.add_argument("--inflight", type=int, default=4,
                     help="frames in flight for the throughput region: one context and one default-priority stream "
                          "each, frames assigned round robin (the two-pass baseline the same way)")
+    ap.add_argument("--inflight-split", default="0,0,128,0,0",
+                    help="blend split (cap_dom, cap_roi, seg_len, far_dom, far_roi) of the in-flight region, "
+                         "both methods; 0,0 never continues a tile list")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="no timing: a 512 MiB copy (counter calibration), then 12 dominant-eye renders of the "
                          "workload, for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs")
@@ -218,6 +226,9 @@ def main():
             fds.append(c.render_dominant(ds, cams[0], raster))
             fos.append(c.render_dominant(ds, affs[0], raster))
             c.set_sync(False)
+    split = tuple(int(x) for x in args.inflight_split.split(","))
+    for c in ctxs:
+        c.set_blend_split(*split)
     torch.cuda.synchronize()
 
     def inflight_ours(n0, n):
@@ -248,6 +259,7 @@ def main():
     for c in ctxs:
         status = c.poll_status()
         assert status["overflow"] == 0, f"capacity overflow during the in-flight timing: {status}"
+    ctx.set_blend_split()  # back to the library's default for the stage breakdown
 
     # ---- per-stage breakdown (every stage timed; not part of the rates) ----
     n_stage = max(20, min(args.steps, 64))
@@ -322,6 +334,7 @@ def main():
         "p50_ms": round(pct(lat, 50), 4),
         "p99_ms": round(pct(lat, 99), 4),
         "inflight": K,
+        "blend_split": {"inflight": list(split), "one_frame_at_a_time": "library default"},
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
