@@ -57,7 +57,7 @@ PEAK_FP32_TFLOPS = 157.3
 # HBM bytes of one sphere800 dominant-eye blend stage (capped walk, two
 # segment rounds, chain, fix-up), FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
 # (factors from a 512 MiB copy), valid for the blend source with this sha1.
-BLEND_TRAFFIC = {"raster_sha1": "d76a717486718d340bcbc4d9d231e7d1b756d8c4", "bytes": 192.8e6}
+BLEND_TRAFFIC = {"raster_sha1": "8c277d5a0c586cbf3ed1931678129651533b4450", "bytes": 111.3e6}
 # fp32 operations of one evaluated (pixel, surfel) pair in the blend and the
 # extra ones of a contributing pair (an FMA counts as two).
 FLOPS_EVAL = 31
