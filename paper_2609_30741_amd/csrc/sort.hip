@@ -183,7 +183,7 @@ hipError_t exclusive_scan(const uint32_t* in, const uint32_t* idx, uint32_t* out
 // Radix sort.  Stable LSD with digits of up to 8 bits (a 32-bit key takes four
 // passes, an 11-bit tile id two of 6 and 5 bits).  The grid is fixed by the
 // capacity (at most kRsGrid blocks; always kRsGrid for small sorts, which
-// use 1024-key sub-chunks instead of 4096); block b owns the contiguous
+// use 1024-key sub-chunks instead of 6144); block b owns the contiguous
 // chunk [b C, b C + C) of the *n_dev keys, C = n / grid rounded up to 256.
 // A pass is three launches:
 //   1. k_rs_hist: per-block digit counts (LDS atomics), stored
@@ -191,10 +191,12 @@ hipError_t exclusive_scan(const uint32_t* in, const uint32_t* idx, uint32_t* out
 //   2. k_rs_scan: one block per digit scans its row over the blocks and
 //      writes the digit total.
 //   3. k_rs_scatter: every block scans the digit totals, then walks its chunk
-//      in sub-chunks of 4096 keys: each wave ranks its 1024 keys in 16 steps
-//      of 64 (a quarter of that for small sorts) with match-any ballots and a per-wave LDS count per digit, the
-//      sub-chunk is reordered by digit in LDS, and each digit's run (16 keys
-//      on average at 8 bits) is written out contiguously.
+//      in sub-chunks of 6144 keys: each wave ranks its 1536 keys in 24 steps
+//      of 64 (1024-key sub-chunks, 4 steps, for small sorts) with match-any
+//      ballots and a per-wave LDS count per digit, the sub-chunk is
+//      reordered by digit in LDS, and each digit's run (24 keys on average
+//      at 8 bits) is written out contiguously.  Large sorts rank digits of
+//      at most 6 bits with per-thread counters instead (k_rs_scatter_cnt).
 // Blocks never wait on each other.
 // ---------------------------------------------------------------------------
 namespace {
@@ -202,10 +204,12 @@ namespace {
 constexpr int kRsMaxBits = 8;
 constexpr int kRsBins = 1 << kRsMaxBits;
 constexpr int kRsGrid = 1024;
-// Keys per thread per sub-chunk: 16 (4096-key sub-chunks, long digit runs)
-// for large sorts; 4 (1024-key sub-chunks) for small ones, where a block
-// holds only a few hundred keys and its latency is the sort's.
-constexpr int kRsItemsBig = 16, kRsItemsSmall = 4;
+// Keys per thread per sub-chunk: 24 (6144-key sub-chunks, long digit runs;
+// a 6M-key tile sort then gives each block one sub-chunk, not a full and a
+// partial one in turn) for large sorts; 4 (1024-key sub-chunks) for small
+// ones, where a block holds only a few hundred keys and its latency is the
+// sort's.
+constexpr int kRsItemsBig = 24, kRsItemsSmall = 4;
 
 __device__ inline uint64_t match_digit(uint32_t d, uint64_t valid, int bits) {
     uint64_t peers = valid;
@@ -379,21 +383,23 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const uint32_t* __restrict__
     }
 }
 
-// k_rs_scatter for digits of at most 6 bits and 4096-key sub-chunks, with
+// k_rs_scatter for digits of at most 6 bits and 6144-key sub-chunks, with
 // the ranks taken from per-thread digit counters instead of ballots: thread
-// t holds the sub-chunk's keys [16 t, 16 t + 16) (blocked, so input order is
+// t holds the sub-chunk's keys [24 t, 24 t + 24) (blocked, so input order is
 // (thread, item) order), counts its digits in a 16-bit LDS counter per
 // (digit, thread), a raking scan of the counters in (digit, thread) order
 // gives every (digit, thread) its first rank, and the thread's own count
 // before each key adds the rest.  Stable, like the ballot ranking, at a
 // fraction of its vector work.  The counter words are padded by one word in
 // 32 so the raking threads hit distinct banks; the same LDS holds the
-// reordered keys and values once the ranks are known.
+// reordered keys and values once the ranks are known.  (At 24 keys per
+// thread a counter reaches 24 and a rank 6143: 16 bits hold both.)
 constexpr int kRsCntBits = 6;
 constexpr int kRsCntBins = 1 << kRsCntBits;
 constexpr int kRsCntWords = kRsCntBins * 256 / 2;                 // two 16-bit counters a word
 constexpr int kRsCntLds = kRsCntWords + kRsCntWords / 32;         // with the padding
-static_assert(kRsCntLds >= 2 * 256 * kRsItemsBig, "the counter LDS also holds a sub-chunk's keys and values");
+constexpr int kRsCntBuf = kRsCntLds > 2 * 256 * kRsItemsBig ? kRsCntLds : 2 * 256 * kRsItemsBig;
+static_assert(kRsItemsBig % 4 == 0, "a thread's keys are loaded as 16-byte vectors");
 
 __device__ __forceinline__ uint32_t cnt_slot(uint32_t w) { return w + (w >> 5); }
 
@@ -405,7 +411,7 @@ __global__ __launch_bounds__(256) void k_rs_scatter_cnt(const uint32_t* __restri
                                                         const uint32_t* __restrict__ totals) {
     constexpr int kItems = kRsItemsBig;
     constexpr int kSub = 256 * kItems;
-    __shared__ uint32_t s_buf[kRsCntLds];
+    __shared__ uint32_t s_buf[kRsCntBuf];  // the counters, then the sub-chunk's keys and values
     __shared__ uint32_t dstart[kRsCntBins + 1];
     __shared__ uint32_t gbase[kRsCntBins];
     __shared__ uint32_t run[kRsCntBins];

@@ -70,9 +70,10 @@ def check_image(gpu_rgb, gpu_d, gpu_a, ref, where=""):
 
 @pytest.mark.parametrize("n,bits", [(0, 8), (1, 8), (4095, 8), (4096, 13), (4097, 13), (100_003, 11),
                                     (1_000_001, 32), (250_000, 1), (70_000, 20),
-                                    # above 2^20 elements: 4096-key sub-chunks; digits of at most
-                                    # 6 bits are ranked by per-thread counters
-                                    (1_500_007, 11), (1_048_577, 5), (2_000_003, 12), (1_100_000, 6)])
+                                    # above 2^20 elements: 6144-key sub-chunks; digits of at most
+                                    # 6 bits are ranked by per-thread counters, 8-bit digits by ballots
+                                    (1_500_007, 11), (1_048_577, 5), (2_000_003, 12), (1_100_000, 6),
+                                    (1_200_001, 16), (1_300_000, 32)])
 def test_sort_pairs_bit_exact(ctx, n, bits):
     log(f"sort n={n} bits={bits}")
     keys, vals = synth.random_sort_keys(n, seed=n + bits, key_bits=32)
