@@ -302,8 +302,9 @@ def main():
 
     # ---- HBM efficiency of the sort and reprojection stages (algorithmic
     # bytes: one read and one write of every key and value for a sort, 4 B
-    # each way when a tile key and its surfel share one word; the 20 B read +
-    # 17 B written per pixel of a forward warp) ----
+    # each way when a tile key and its surfel share one word; the 20 B read
+    # (colour, depth proxy, alpha) + 21 B written (colour, z, alpha, hole
+    # mask) per pixel of a forward warp) ----
     def hbm(stage, nbytes):
         ms = stage_ms[stage]
         gbs = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
@@ -314,7 +315,7 @@ def main():
     bits = lambda x: max(1, int(math.ceil(math.log2(max(x, 2)))))
     key_b = 8.0 if bits(n_tiles) + bits(scene.n) <= 32 else 16.0
     hbm_stages = [hbm("tile_sort_dom", key_b * np.mean(keys_dom)), hbm("depth_sort_dom", 16.0 * scene.n),
-                  hbm("tile_sort_roi", key_b * np.mean(keys_roi)), hbm("reproject", 37.0 * npx)]
+                  hbm("tile_sort_roi", key_b * np.mean(keys_roi)), hbm("reproject", 41.0 * npx)]
 
     # ---- CPU oracle on a bounded sample (a baseline only) ----
     cpu = None

@@ -219,35 +219,38 @@ __device__ inline uint32_t resolve_pixel(unsigned long long key, int64_t t, int6
 
 // Row-preserving form (the host has proven that every splat stays on its
 // source row, as for a rig that keeps the orientation and moves along x):
-// one block per row, the row's z-buffer in LDS (64-bit LDS atomicMin), the
-// z-test and the resolve in one kernel.  Same recipe, same result as the
-// scatter/resolve pair.  Each thread takes kRowPix pixels of a chunk and
-// issues all of their loads before any arithmetic, so the row's memory
-// latency is paid once per chunk rather than once per pixel.
-constexpr int kRowPix = 4;
-__global__ __launch_bounds__(256) void k_reproject_rows(WarpCam src, WarpCam dst, RelPose P, float a_min,
-                                                        const float* __restrict__ draw,
-                                                        const float* __restrict__ alpha,
-                                                        const float* __restrict__ rgb, float* __restrict__ rgb_dst,
-                                                        float* __restrict__ z_dst, float* __restrict__ a_dst,
-                                                        uint8_t* __restrict__ hole, uint4* __restrict__ wpart) {
+// one block of NT threads per row, the row's z-buffer in LDS (64-bit LDS
+// atomicMin), the z-test and the resolve in one kernel.  Same recipe, same
+// result as the scatter/resolve pair.  Each thread takes kRowPix pixels of a
+// chunk of NT * kRowPix and issues all of their loads before any arithmetic,
+// so the row's memory latency is paid once per chunk rather than once per
+// pixel; the row's four counters are reduced in one LDS exchange.
+constexpr int kRowThreads = 512, kRowItems = 2;  // threads per row block, pixels per thread per chunk
+template <int NT, int kRowPix>
+__global__ __launch_bounds__(NT) void k_reproject_rows(WarpCam src, WarpCam dst, RelPose P, float a_min,
+                                                       const float* __restrict__ draw,
+                                                       const float* __restrict__ alpha,
+                                                       const float* __restrict__ rgb, float* __restrict__ rgb_dst,
+                                                       float* __restrict__ z_dst, float* __restrict__ a_dst,
+                                                       uint8_t* __restrict__ hole, uint4* __restrict__ wpart) {
     extern __shared__ unsigned long long zrow[];
+    __shared__ uint4 s_red[NT / 64];
     const int j = blockIdx.x;
-    for (int t = threadIdx.x; t < dst.W; t += 256) zrow[t] = ~0ull;
+    for (int t = threadIdx.x; t < dst.W; t += NT) zrow[t] = ~0ull;
     __syncthreads();
     uint32_t dmin = 0xFFFFFFFFu, dmax = 0u, off_row = 0;
     const int64_t srow = (int64_t)j * src.W;
-    for (int base = 0; base < src.W; base += 256 * kRowPix) {
+    for (int base = 0; base < src.W; base += NT * kRowPix) {
         float Av[kRowPix], Dv[kRowPix];
 #pragma unroll
         for (int k = 0; k < kRowPix; ++k) {
-            const int i = base + threadIdx.x + 256 * k;
+            const int i = base + threadIdx.x + NT * k;
             Av[k] = i < src.W ? alpha[srow + i] : 0.f;
             Dv[k] = i < src.W ? draw[srow + i] : 0.f;
         }
 #pragma unroll
         for (int k = 0; k < kRowPix; ++k) {
-            const int i = base + threadIdx.x + 256 * k;
+            const int i = base + threadIdx.x + NT * k;
             if (i >= src.W) continue;
             int64_t fu, fv;
             unsigned long long key;
@@ -267,12 +270,12 @@ __global__ __launch_bounds__(256) void k_reproject_rows(WarpCam src, WarpCam dst
     const int64_t nd = (int64_t)dst.W * dst.H, ns = (int64_t)src.W * src.H;
     const int64_t drow = (int64_t)j * dst.W;
     uint32_t holes = 0;
-    for (int base = 0; base < dst.W; base += 256 * kRowPix) {
+    for (int base = 0; base < dst.W; base += NT * kRowPix) {
         unsigned long long kv[kRowPix];
         float c0[kRowPix], c1[kRowPix], c2[kRowPix], av[kRowPix];
 #pragma unroll
         for (int k = 0; k < kRowPix; ++k) {
-            const int t = base + threadIdx.x + 256 * k;
+            const int t = base + threadIdx.x + NT * k;
             kv[k] = t < dst.W ? zrow[t] : ~0ull;
             const uint32_t sidx = (uint32_t)(kv[k] & 0xFFFFFFFFull);
             const bool have = kv[k] != ~0ull;
@@ -283,7 +286,7 @@ __global__ __launch_bounds__(256) void k_reproject_rows(WarpCam src, WarpCam dst
         }
 #pragma unroll
         for (int k = 0; k < kRowPix; ++k) {
-            const int t = base + threadIdx.x + 256 * k;
+            const int t = base + threadIdx.x + NT * k;
             if (t >= dst.W) continue;
             const int64_t g = drow + t;
             const bool have = kv[k] != ~0ull;
@@ -296,13 +299,23 @@ __global__ __launch_bounds__(256) void k_reproject_rows(WarpCam src, WarpCam dst
             holes += have ? 0u : 1u;
         }
     }
-    __shared__ uint32_t s4[4];
-    dmin = block_min_u32(dmin, s4);
-    dmax = block_max_u32(dmax, s4);
-    holes = block_sum_u32(holes, s4);
-    off_row = block_max_u32(off_row, s4);
-    // off_row cannot be set when the host's bound holds (overflow bit 2).
-    if (threadIdx.x == 0) wpart[j] = make_uint4(~dmin, dmax, holes, off_row ? 4u : 0u);
+    // The row's partial: max of ~dmin, max of dmax, hole count, off-row flag.
+    uint32_t x = wave_max_u32(~dmin), y = wave_max_u32(dmax), h = wave_sum_u32(holes), f = wave_max_u32(off_row);
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = make_uint4(x, y, h, f);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint4 r = s_red[0];
+#pragma unroll
+        for (int w = 1; w < NT / 64; ++w) {
+            const uint4 q = s_red[w];
+            r.x = max(r.x, q.x);
+            r.y = max(r.y, q.y);
+            r.z += q.z;
+            r.w = max(r.w, q.w);
+        }
+        // off_row cannot be set when the host's bound holds (overflow bit 2).
+        wpart[j] = make_uint4(r.x, r.y, r.z, r.w ? 4u : 0u);
+    }
 }
 
 // Fold the per-row partials of k_reproject_rows (n of them; none for the
@@ -1226,8 +1239,9 @@ hipError_t launch_reproject(const WarpCam& src, const WarpCam& dst, const RelPos
     const int64_t ns = (int64_t)src.W * src.H, nd = (int64_t)dst.W * dst.H;
     if (reset) hipLaunchKernelGGL(k_warp_reset, dim3(1), dim3(1), 0, s, st);
     if (rows_preserved(src, dst, P)) {
-        hipLaunchKernelGGL(k_reproject_rows, dim3(dst.H), dim3(256), sizeof(unsigned long long) * dst.W, s, src, dst, P,
-                           a_min, draw, alpha, rgb, rgb_dst, z_dst, alpha_dst, hole, wpart);
+        hipLaunchKernelGGL((k_reproject_rows<kRowThreads, kRowItems>), dim3(dst.H), dim3(kRowThreads),
+                           sizeof(unsigned long long) * dst.W, s, src, dst, P, a_min, draw, alpha, rgb, rgb_dst, z_dst,
+                           alpha_dst, hole, wpart);
     } else {
         hipLaunchKernelGGL(k_fill_u64, dim3(grid(nd)), dim3(256), 0, s, zbuf, nd, ~0ull);
         hipLaunchKernelGGL(k_reproject_scatter, band_grid(src.W, src.H), dim3(256), 0, s, src, dst, P, a_min, draw,
