@@ -267,14 +267,22 @@ def test_render_edge_cases(ctx, oracle):
     assert np.all(to_np(out["alpha"]) == 0)
 
 
-@pytest.mark.parametrize("name,n_px", [("sphere800", 1500), ("unbounded1600", 600)])
-def test_render_dominant_full_size_sampled(ctx, oracle, name, n_px):
-    """The full-size workloads in the bench's launch configuration, checked on
-    sampled pixels the oracle computes one by one."""
-    log(f"full-size {name}")
+@pytest.mark.parametrize("name,n_px,split", [("sphere800", 1500, None), ("unbounded1600", 600, None),
+                                              ("sphere800", 1500, (0, 0, 128, 0, 0))])
+def test_render_dominant_full_size_sampled(ctx, oracle, name, n_px, split):
+    """The full-size workloads in the bench's launch configurations (the
+    default blend split of one frame at a time; no continuation, as with
+    frames in flight), checked on sampled pixels the oracle computes one by
+    one."""
+    log(f"full-size {name} split {split}")
     sc, cams, _ = synth.WORKLOADS[name](0)
     cam = cams[3]
-    out = ctx.render_dominant(api.DeviceScene(sc), cam)
+    if split:
+        ctx.set_blend_split(*split)
+    try:
+        out = ctx.render_dominant(api.DeviceScene(sc), cam)
+    finally:
+        ctx.set_blend_split()
     rng = np.random.default_rng(7)
     pix = np.stack([rng.integers(0, cam.width, n_px), rng.integers(0, cam.height, n_px)], axis=1).astype(np.int32)
     ref = oracle.render(sc, cam, pixels=pix)
