@@ -56,8 +56,9 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
 # HBM bytes of one sphere800 dominant-eye blend stage (capped walk, two
 # segment rounds, chain, fix-up), FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
-# (factors from a 512 MiB copy), valid for the blend source with this sha1.
-BLEND_TRAFFIC = {"raster_sha1": "8c277d5a0c586cbf3ed1931678129651533b4450", "bytes": 111.3e6}
+# (factors from a 512 MiB copy), valid while raster.hip and bgs_api.hip hash
+# (sha1 over the two files in that order) to this value.
+BLEND_TRAFFIC = {"source_sha1": "a6a87381dce39856f62fab9ee9badb43f5c563bd", "bytes": 120.1e6}
 # fp32 operations of one evaluated (pixel, surfel) pair in the blend and the
 # extra ones of a contributing pair (an FMA counts as two).
 FLOPS_EVAL = 31
@@ -396,13 +397,16 @@ def traffic_probe(args):
 def blend_traffic():
     """HBM bytes per dominant-eye blend stage (all its launches) of the bench
     workload, from calibrated FETCH_SIZE and WRITE_SIZE counter runs of
-    `bench.py --traffic-probe`; None when the blend source has changed since
-    the counters were taken."""
+    `bench.py --traffic-probe`; None when the blend kernels or the default
+    blend schedule (raster.hip, bgs_api.hip) have changed since the counters
+    were taken."""
     import hashlib
-    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2609_30741_amd", "csrc", "raster.hip")
-    with open(src, "rb") as f:
-        h = hashlib.sha1(f.read()).hexdigest()
-    return BLEND_TRAFFIC["bytes"] if h == BLEND_TRAFFIC["raster_sha1"] else None
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2609_30741_amd", "csrc")
+    h = hashlib.sha1()
+    for f in ("raster.hip", "bgs_api.hip"):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return BLEND_TRAFFIC["bytes"] if h.hexdigest() == BLEND_TRAFFIC["source_sha1"] else None
 
 
 def cpu_baseline(args, scene, cam_dom, cam_aff, roi_px):
