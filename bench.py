@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="sphere800", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--center-roi", type=int, default=1)
+    ap.add_argument("--margin", type=int, default=32, help="ROI safety margin m in pixels (the paper fixes 32)")
+    ap.add_argument("--surfels", type=int, default=0, help="surfel count of the workload's scene (0: its default)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="budget of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
@@ -113,16 +115,18 @@ def main():
         return
 
     t0 = time.time()
-    scene, cams, baseline = synth.WORKLOADS[args.workload](args.seed)
+    wl_kw = {"n": args.surfels} if args.surfels > 0 else {}
+    scene, cams, baseline = synth.WORKLOADS[args.workload](args.seed, **wl_kw)
     affs = [synth.affiliated(c, baseline) for c in cams]
     ds = api.DeviceScene(scene)
     ctx = api.Context(sync=True)
-    roi = api.Roi(center_roi=bool(args.center_roi))
+    roi = api.Roi(center_roi=bool(args.center_roi), margin=args.margin)
     raster = api.Raster()
     log(f"scene {args.workload}: n={scene.n} generated+uploaded in {time.time() - t0:.1f}s")
 
     # ---- untimed: size the workspace on every pose, quality and pair counts ----
-    ps, keys_dom, keys_roi, roi_tiles, n_boxes = [], [], [], [], []
+    from paper_2609_30741_amd import metrics
+    ps, ss, keys_dom, keys_roi, roi_tiles, n_boxes = [], [], [], [], [], []
     out = None
     full = None
     for i, (cd, ca) in enumerate(zip(cams, affs)):
@@ -134,6 +138,7 @@ def main():
         n_boxes.append(st["n_boxes"])
         full = ctx.render_dominant(ds, ca, raster, out=full)
         ps.append(api.psnr(out["rgb_aff"], full["rgb"]))
+        ss.append(metrics.ssim(out["rgb_aff"].cpu().numpy(), full["rgb"].cpu().numpy()))
     # Reserve 25% headroom over the largest key count so the timed frames
     # never run out of capacity.
     kmax = max(max(keys_dom), max(keys_roi))
@@ -143,6 +148,7 @@ def main():
     mses = [10 ** (-p / 10) for p in ps]
     delta_db = float(np.mean([10 * math.log10(1 + m / mse_ref) for m in mses]))
     log(f"quality: PSNR(ours, full) mean {np.mean(ps):.2f} dB min {np.min(ps):.2f}; loss {delta_db:.3f} dB; "
+        f"SSIM(ours, full) mean {np.mean(ss):.4f} min {np.min(ss):.4f}; "
         f"keys dom {np.mean(keys_dom):.3g} roi {np.mean(keys_roi):.3g}; roi tiles {np.mean(roi_tiles):.0f}/{n_tiles}")
 
     ctx.set_count_pairs(True)
@@ -342,7 +348,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD_TEXT[args.workload], "surfels": int(scene.n),
+        "config": {"workload": WORKLOAD_TEXT[args.workload] + (f" (surfel count set to {scene.n})" if args.surfels > 0
+                                                               else ""),
+                   "surfels": int(scene.n),
                    "width": int(cams[0].width), "height": int(cams[0].height), "poses": n_poses,
                    "sh_degree": int(scene.sh_degree), "baseline": baseline, "center_roi": bool(args.center_roi),
                    "margin": roi.margin, "tile": 16, "parallelism": "single GPU"},
@@ -355,7 +363,8 @@ def main():
                                 "two_pass_ms_per_step": round(t_two / args.steps * 1e3, 4),
                                 "time_reduction_vs_two_pass": round(1 - t_ours / t_two, 4)},
         "quality": {"psnr_ours_vs_full_db": round(float(np.mean(ps)), 3), "psnr_min_db": round(float(np.min(ps)), 3),
-                    "psnr_loss_db": round(delta_db, 4), "p_ref_db": P_REF[args.workload]},
+                    "psnr_loss_db": round(delta_db, 4), "p_ref_db": P_REF[args.workload],
+                    "ssim_ours_vs_full": round(float(np.mean(ss)), 5), "ssim_min": round(float(np.min(ss)), 5)},
         "frame": {"keys_dom": int(np.mean(keys_dom)), "keys_roi": int(np.mean(keys_roi)),
                   "roi_tile_frac": round(float(np.mean(roi_tiles)) / n_tiles, 4), "boxes": float(np.mean(n_boxes))},
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
