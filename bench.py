@@ -81,6 +81,8 @@ def main():
     ap.add_argument("--workload", default="sphere800", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--center-roi", type=int, default=1)
     ap.add_argument("--margin", type=int, default=32, help="ROI safety margin m in pixels (the paper fixes 32)")
+    ap.add_argument("--edge-bounds", type=int, default=0,
+                    help="edge-ROI bounds: 0 = Eq. 6 over all edge samples, 1 = each side's own edge, worst case")
     ap.add_argument("--surfels", type=int, default=0, help="surfel count of the workload's scene (0: its default)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="budget of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -120,7 +122,7 @@ def main():
     affs = [synth.affiliated(c, baseline) for c in cams]
     ds = api.DeviceScene(scene)
     ctx = api.Context(sync=True)
-    roi = api.Roi(center_roi=bool(args.center_roi), margin=args.margin)
+    roi = api.Roi(center_roi=bool(args.center_roi), margin=args.margin, edge_bounds=args.edge_bounds)
     raster = api.Raster()
     log(f"scene {args.workload}: n={scene.n} generated+uploaded in {time.time() - t0:.1f}s")
 
@@ -353,7 +355,7 @@ def main():
                    "surfels": int(scene.n),
                    "width": int(cams[0].width), "height": int(cams[0].height), "poses": n_poses,
                    "sh_degree": int(scene.sh_degree), "baseline": baseline, "center_roi": bool(args.center_roi),
-                   "margin": roi.margin, "tile": 16, "parallelism": "single GPU"},
+                   "margin": roi.margin, "edge_bounds": roi.edge_bounds, "tile": 16, "parallelism": "single GPU"},
         "two_pass": {"value": round(fps2_k, 2), "unit": "stereo frames/s",
                      "ms_per_step": round(t_two_k / args.steps * 1e3, 4),
                      "p50_ms": round(pct(lat2, 50), 4), "p99_ms": round(pct(lat2, 99), 4)},

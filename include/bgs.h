@@ -107,7 +107,14 @@ typedef struct bgs_raster_params {
  * in [1, 65536] per image edge; gap_passes in [0, 64]; center_roi = 1
  * enables Step 2 (connected center holes), 0 fills the remaining holes
  * along their row instead; a_min in (0, 1] is the accumulated weight A
- * below which a source pixel counts as empty background. */
+ * below which a source pixel counts as empty background.  edge_bounds
+ * selects the valid projection bounds of Eq. 7-8: 0 takes the extrema of
+ * Eq. 6 over all projected edge samples (as the paper writes it); 1 takes,
+ * for each side, the worst case of that side's own edge over both depth
+ * hypotheses (u_min = largest x of the left edge, u_max = smallest x of
+ * the right edge, likewise v for top and bottom), which covers the strip a
+ * border leaves uncovered at any depth in the range; a side whose edge has
+ * no valid projection falls back to Eq. 6. */
 typedef struct bgs_roi_params {
     int32_t margin;
     int32_t tile;
@@ -115,6 +122,7 @@ typedef struct bgs_roi_params {
     int32_t gap_passes;
     int32_t center_roi;
     float a_min;
+    int32_t edge_bounds;
 } bgs_roi_params;
 
 /* Box kinds. */

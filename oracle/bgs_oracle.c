@@ -60,7 +60,8 @@ typedef struct {
 } orc_raster;
 
 typedef struct {
-    int32_t margin, tile, edge_samples, gap_passes, center_roi, pad;
+    int32_t margin, tile, edge_samples, gap_passes, center_roi;
+    int32_t edge_bounds; /* 0: Eq. 6 over all samples; 1: each side from its own edge, worst case */
     double a_min;
 } orc_roi;
 
@@ -679,6 +680,12 @@ ORC_API int orc_edge_rois(const orc_camera* src, const orc_camera* dst, const or
     int64_t N = rp->edge_samples;
     double hyp[2] = {(double)depth_range[0], (double)depth_range[1]};
     double xmin = INFINITY, xmax = -INFINITY, ymin = INFINITY, ymax = -INFINITY;
+    /* The uncovered strip along a side ends where that side's own edge
+       lands: at any depth in the range it is at most as wide as the worst
+       case over the edge's samples and both hypotheses (largest x of the
+       left edge, smallest x of the right edge, largest y of the top edge,
+       smallest y of the bottom edge). */
+    double left_x = -INFINITY, right_x = INFINITY, top_y = -INFINITY, bottom_y = INFINITY;
     int64_t Ws = src->width, Hs = src->height;
     for (int edge = 0; edge < 4; ++edge) {
         for (int64_t k = 0; k < N; ++k) {
@@ -700,8 +707,19 @@ ORC_API int orc_edge_rois(const orc_camera* src, const orc_camera* dst, const or
                 if (u > xmax) xmax = u;
                 if (v < ymin) ymin = v;
                 if (v > ymax) ymax = v;
+                if (edge == 0 && v > top_y) top_y = v;
+                if (edge == 1 && v < bottom_y) bottom_y = v;
+                if (edge == 2 && u > left_x) left_x = u;
+                if (edge == 3 && u < right_x) right_x = u;
             }
         }
+    }
+    if (rp->edge_bounds) {
+        /* A side whose edge has no valid projection keeps Eq. 6. */
+        if (left_x > -INFINITY) xmin = left_x;
+        if (right_x < INFINITY) xmax = right_x;
+        if (top_y > -INFINITY) ymin = top_y;
+        if (bottom_y < INFINITY) ymax = bottom_y;
     }
     double W = dst->width, H = dst->height;
     double m = rp->margin;

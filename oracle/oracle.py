@@ -50,7 +50,7 @@ class _Raster(C.Structure):
 
 class _Roi(C.Structure):
     _fields_ = [("margin", C.c_int32), ("tile", C.c_int32), ("edge_samples", C.c_int32),
-                ("gap_passes", C.c_int32), ("center_roi", C.c_int32), ("pad", C.c_int32),
+                ("gap_passes", C.c_int32), ("center_roi", C.c_int32), ("edge_bounds", C.c_int32),
                 ("a_min", C.c_double)]
 
 
@@ -87,6 +87,7 @@ class Roi:
     gap_passes: int = 2
     center_roi: bool = True
     a_min: float = 0.5
+    edge_bounds: int = 0  # 0: Eq. 6 extrema over all edge samples; 1: per-side worst case of its own edge
 
 
 _lib = None
@@ -148,6 +149,7 @@ def _roi(r: Roi) -> _Roi:
     s = _Roi()
     s.margin, s.tile, s.edge_samples, s.gap_passes = r.margin, r.tile, r.edge_samples, r.gap_passes
     s.center_roi = int(bool(r.center_roi))
+    s.edge_bounds = int(r.edge_bounds)
     s.a_min = r.a_min
     return s
 

@@ -51,12 +51,14 @@ class Roi:
     gap_passes: int = 2
     center_roi: bool = True
     a_min: float = 0.5
+    edge_bounds: int = 0  # 0: Eq. 6 over all edge samples; 1: each side's own edge, worst case
 
     def c(self):
         r = _abi.RoiParams()
         r.margin, r.tile, r.edge_samples, r.gap_passes = self.margin, self.tile, self.edge_samples, self.gap_passes
         r.center_roi = int(bool(self.center_roi))
         r.a_min = self.a_min
+        r.edge_bounds = int(self.edge_bounds)
         return r
 
 

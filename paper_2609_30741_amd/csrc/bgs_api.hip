@@ -200,6 +200,8 @@ int check_roi(bgs_ctx* ctx, const bgs_roi_params* r) {
     if (r->gap_passes < 0 || r->gap_passes > 64)
         return fail(ctx, BGS_ERR_INVALID_ARG, "gap_passes %d out of range", r->gap_passes);
     if (!(r->a_min > 0.f && r->a_min <= 1.f)) return fail(ctx, BGS_ERR_INVALID_ARG, "a_min out of (0, 1]");
+    if (r->edge_bounds != 0 && r->edge_bounds != 1)
+        return fail(ctx, BGS_ERR_INVALID_ARG, "edge_bounds %d is neither 0 nor 1", r->edge_bounds);
     return BGS_OK;
 }
 

@@ -400,10 +400,10 @@ __device__ inline int64_t align_up(int64_t x, int64_t T) { return ((x + T - 1) /
 // comes from the reprojection just run, whose partials (n_wpart, possibly
 // none) it folds into the status block first.
 __global__ __launch_bounds__(256) void k_edge_rois(WarpCam src, WarpCam dst, RelPose P, int N, int margin, int T,
-                                                   const float* __restrict__ depth_range,
+                                                   int edge_bounds, const float* __restrict__ depth_range,
                                                    const uint4* __restrict__ wpart, int n_wpart, DevStatus* st,
                                                    bgs_box* boxes, int box_cap, uint8_t* __restrict__ tm) {
-    __shared__ double red[4][4];
+    __shared__ double red[8][4];
     __shared__ int32_t sbx[4][6];
     __shared__ int snb;
     float r0, r1;
@@ -415,6 +415,10 @@ __global__ __launch_bounds__(256) void k_edge_rois(WarpCam src, WarpCam dst, Rel
     }
     const double hyp0 = (double)r0, hyp1 = (double)r1;
     double xmin = INFINITY, xmax = -INFINITY, ymin = INFINITY, ymax = -INFINITY;
+    // Per side, the worst case of its own edge (edge_bounds = 1): largest x
+    // of the left edge, smallest x of the right, largest y of the top,
+    // smallest y of the bottom.
+    double lmax = -INFINITY, rmin = INFINITY, tmax = -INFINITY, bmin = INFINITY;
     const int64_t total = 4LL * N;
     for (int64_t q = threadIdx.x; q < total; q += 256) {
         const int edge = (int)(q / N);
@@ -438,6 +442,10 @@ __global__ __launch_bounds__(256) void k_edge_rois(WarpCam src, WarpCam dst, Rel
             xmax = fmax(xmax, u);
             ymin = fmin(ymin, v);
             ymax = fmax(ymax, v);
+            if (edge == 0) tmax = fmax(tmax, v);
+            else if (edge == 1) bmin = fmin(bmin, v);
+            else if (edge == 2) lmax = fmax(lmax, u);
+            else rmin = fmin(rmin, u);
         }
     }
     // min / max are exact in any order: wave shuffles, then the four waves.
@@ -447,6 +455,10 @@ __global__ __launch_bounds__(256) void k_edge_rois(WarpCam src, WarpCam dst, Rel
         xmax = fmax(xmax, __shfl_xor(xmax, off, 64));
         ymin = fmin(ymin, __shfl_xor(ymin, off, 64));
         ymax = fmax(ymax, __shfl_xor(ymax, off, 64));
+        lmax = fmax(lmax, __shfl_xor(lmax, off, 64));
+        rmin = fmin(rmin, __shfl_xor(rmin, off, 64));
+        tmax = fmax(tmax, __shfl_xor(tmax, off, 64));
+        bmin = fmin(bmin, __shfl_xor(bmin, off, 64));
     }
     if ((threadIdx.x & 63) == 0) {
         const int w = threadIdx.x >> 6;
@@ -454,6 +466,10 @@ __global__ __launch_bounds__(256) void k_edge_rois(WarpCam src, WarpCam dst, Rel
         red[1][w] = xmax;
         red[2][w] = ymin;
         red[3][w] = ymax;
+        red[4][w] = lmax;
+        red[5][w] = rmin;
+        red[6][w] = tmax;
+        red[7][w] = bmin;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -461,9 +477,16 @@ __global__ __launch_bounds__(256) void k_edge_rois(WarpCam src, WarpCam dst, Rel
         const double rx1 = fmax(fmax(red[1][0], red[1][1]), fmax(red[1][2], red[1][3]));
         const double ry0 = fmin(fmin(red[2][0], red[2][1]), fmin(red[2][2], red[2][3]));
         const double ry1 = fmax(fmax(red[3][0], red[3][1]), fmax(red[3][2], red[3][3]));
+        const double el = fmax(fmax(red[4][0], red[4][1]), fmax(red[4][2], red[4][3]));
+        const double er = fmin(fmin(red[5][0], red[5][1]), fmin(red[5][2], red[5][3]));
+        const double et = fmax(fmax(red[6][0], red[6][1]), fmax(red[6][2], red[6][3]));
+        const double eb = fmin(fmin(red[7][0], red[7][1]), fmin(red[7][2], red[7][3]));
+        const bool pe = edge_bounds != 0;
         const double W = dst.W, H = dst.H, m = margin;
         const double hw = floor(W / 2.0), hh = floor(H / 2.0);
-        const double umin = snap(rx0), umax = snap(rx1), vmin = snap(ry0), vmax = snap(ry1);
+        // A side whose own edge has no valid projection keeps Eq. 6.
+        const double umin = snap(pe && el > -INFINITY ? el : rx0), umax = snap(pe && er < INFINITY ? er : rx1);
+        const double vmin = snap(pe && et > -INFINITY ? et : ry0), vmax = snap(pe && eb < INFINITY ? eb : ry1);
         const double lw = umin > 0.0 ? clampd(ceil(umin) + m, 0.0, hw) : 0.0;
         const double rw = umax < W - 1.0 ? clampd((W - 1.0) - floor(umax) + m, 0.0, hw) : 0.0;
         const double th = vmin > 0.0 ? clampd(ceil(vmin) + m, 0.0, hh) : 0.0;
@@ -1278,7 +1301,7 @@ hipError_t launch_classify(const WarpCam& src, const WarpCam& dst, const RelPose
     const int64_t n = (int64_t)W * H;
     const int tiles_x = (W + T - 1) / T;
     hipLaunchKernelGGL(k_edge_rois, dim3(1), dim3(256), 0, s, src, dst, P, roi.edge_samples, roi.margin, T,
-                       depth_range, b.wpart, depth_range ? 0 : warp_parts(src, dst, P), st, boxes, box_cap,
+                       roi.edge_bounds, depth_range, b.wpart, depth_range ? 0 : warp_parts(src, dst, P), st, boxes, box_cap,
                        tile_mask);
     const dim3 gg = band_grid(W, H);
     int n_gpart = 0;

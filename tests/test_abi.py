@@ -38,7 +38,7 @@ def test_struct_sizes():
     assert C.sizeof(_abi.Camera) == 152
     assert C.sizeof(_abi.Scene) == 56
     assert C.sizeof(_abi.RasterParams) == 32
-    assert C.sizeof(_abi.RoiParams) == 24
+    assert C.sizeof(_abi.RoiParams) == 28
     assert C.sizeof(_abi.Box) == 24
     assert C.sizeof(_abi.Stats) == 144
 
@@ -117,6 +117,10 @@ def test_stage_validation(L, ctx):
                          FAKE, FAKE, FAKE)
     assert rc == _abi.ERR_UNSUPPORTED
     roi = api.Roi(edge_samples=0).c()
+    rc = L.bgs_reproject(ctx, C.byref(cam), C.byref(cam), C.byref(roi), FAKE, FAKE, FAKE, FAKE, 1 << 30, FAKE, FAKE,
+                         FAKE, FAKE, FAKE)
+    assert rc == _abi.ERR_INVALID_ARG
+    roi = api.Roi(edge_bounds=2).c()
     rc = L.bgs_reproject(ctx, C.byref(cam), C.byref(cam), C.byref(roi), FAKE, FAKE, FAKE, FAKE, 1 << 30, FAKE, FAKE,
                          FAKE, FAKE, FAKE)
     assert rc == _abi.ERR_INVALID_ARG

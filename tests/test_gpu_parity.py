@@ -321,17 +321,21 @@ def test_reproject_bit_exact(ctx, oracle, W, H, seed, b, turn):
     assert np.array_equal(to_np(out["depth_range"]), ref["depth_range"])
 
 
-@pytest.mark.parametrize("center", [True, False])
+@pytest.mark.parametrize("center,edge_bounds", [(True, 0), (False, 0), (True, 1)])
 @pytest.mark.parametrize("W,H,seed,b,turn", [(256, 256, 5, 0.064, 0.0), (800, 600, 6, 0.15, 0.0),
                                              (203, 117, 7, 0.3, 0.0), (1600, 1064, 8, 0.064, 0.0),
-                                             (320, 240, 9, 0.1, 0.1)])
-def test_classify_bit_exact(ctx, oracle, center, W, H, seed, b, turn):
+                                             (320, 240, 9, 0.1, 0.1), (320, 240, 10, -0.2, 0.0)])
+def test_classify_bit_exact(ctx, oracle, center, edge_bounds, W, H, seed, b, turn):
     dom, aff = stage_rig(W, H, 1.2 * W, b, turn)
     rgb, dr, a = synth.stage_images(W, H, seed, n_occluders=10)
     rep = oracle.reproject(dom, aff, rgb, dr, a)
-    roi = api.Roi(center_roi=center)
-    ref = oracle.classify(dom, aff, oracle.Roi(center_roi=center), rep["depth_range"], rep["rgb"], rep["z"],
-                          rep["alpha"], rep["hole"], box_cap=4096)
+    roi = api.Roi(center_roi=center, edge_bounds=edge_bounds)
+    ref = oracle.classify(dom, aff, oracle.Roi(center_roi=center, edge_bounds=edge_bounds), rep["depth_range"],
+                          rep["rgb"], rep["z"], rep["alpha"], rep["hole"], box_cap=4096)
+    if edge_bounds:
+        lit, _ = oracle.edge_rois(dom, aff, oracle.Roi(), rep["depth_range"])
+        per, _ = oracle.edge_rois(dom, aff, oracle.Roi(edge_bounds=1), rep["depth_range"])
+        log(f"edge widths: Eq. 6 {list(lit)}, per edge {list(per)}")
     g_rgb = torch.from_numpy(rep["rgb"]).cuda()
     g_z = torch.from_numpy(rep["z"]).cuda()
     g_a = torch.from_numpy(rep["alpha"]).cuda()
@@ -339,7 +343,7 @@ def test_classify_bit_exact(ctx, oracle, center, W, H, seed, b, turn):
     out = ctx.classify_holes(dom, aff, torch.from_numpy(rep["depth_range"]).cuda(), g_rgb, g_z, g_a, g_cls, roi,
                              box_capacity=4096)
     torch.cuda.synchronize()
-    log(f"classify {W}x{H} center={center}: boxes={ref['n_boxes']} stats={ref['stats']}")
+    log(f"classify {W}x{H} center={center} edge_bounds={edge_bounds}: boxes={ref['n_boxes']} stats={ref['stats']}")
     assert np.array_equal(to_np(g_cls), ref["cls"])
     assert np.array_equal(to_np(out["labels"]), ref["labels"])
     nb = int(to_np(out["n_boxes"])[0])
@@ -413,13 +417,13 @@ def test_render_stereo_zero_baseline(ctx):
     assert torch.equal(out["rgb_aff"], out["rgb_dom"])
 
 
-@pytest.mark.parametrize("center", [False, True])
-def test_render_stereo_cube_end_to_end(ctx, oracle, center):
+@pytest.mark.parametrize("center,edge_bounds", [(False, 0), (True, 0), (True, 1)])
+def test_render_stereo_cube_end_to_end(ctx, oracle, center, edge_bounds):
     sc, cam = cube_workload(10_000, 256, 256, 300.0)
     aff = synth.affiliated(cam, 0.064)
-    roi = api.Roi(center_roi=center)
+    roi = api.Roi(center_roi=center, edge_bounds=edge_bounds)
     out = ctx.render_stereo(api.DeviceScene(sc), cam, aff, roi=roi)
-    ref = oracle.render_stereo(sc, cam, aff, roi=oracle.Roi(center_roi=center))
+    ref = oracle.render_stereo(sc, cam, aff, roi=oracle.Roi(center_roi=center, edge_bounds=edge_bounds))
     check_image(to_np(out["rgb_dom"]), to_np(out["depth_raw_dom"]), to_np(out["alpha_dom"]), ref["dom"], "stereo dom")
     cls_g, cls_o = to_np(out["cls_aff"]), ref["aff"]["cls"]
     mism = (cls_g != cls_o).mean()

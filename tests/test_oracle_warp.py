@@ -79,6 +79,34 @@ def test_edge_rois_cube_workload_example(oracle):
     assert widths[1] == 128
 
 
+def test_edge_rois_per_edge_bounds_closed_form(oracle):
+    # Depth range [2, 8] on the 256x256 rig (fx = 300, b = 0.064): the right
+    # edge lands at 255 - fx b / d, i.e. 245.4 at d = 2 and 252.6 at d = 8.
+    # Eq. 6 over all samples takes the far hypothesis for the right side:
+    # width 255 - floor(252.6) + 32 = 35.  The per-edge worst case takes the
+    # near one: 255 - floor(245.4) + 32 = 42, which covers the strip the
+    # border leaves open at any depth in the range.  No other side opens.
+    dom = synth.look_at((0.0, -4.0, 0.0), (0, 0, 0), (0, 0, 1), 256, 256, 300.0)
+    aff = synth.affiliated(dom, 0.064)
+    dr = np.array([2.0, 8.0], np.float32)
+    fb = 300.0 * 0.064
+    literal, _ = oracle.edge_rois(dom, aff, oracle.Roi(), dr)
+    assert list(literal) == [0, 255 - math.floor(255 - fb / 8.0) + 32, 0, 0] == [0, 35, 0, 0]
+    per_edge, boxes = oracle.edge_rois(dom, aff, oracle.Roi(edge_bounds=1), dr)
+    assert list(per_edge) == [0, 255 - math.floor(255 - fb / 2.0) + 32, 0, 0] == [0, 42, 0, 0]
+    assert boxes.tolist() == [[(256 - 42) // 16 * 16, 0, 256, 256, oracle.BOX_RIGHT, -1]]
+    # With one depth both readings agree.
+    one = np.array([4.0, 4.0], np.float32)
+    assert list(oracle.edge_rois(dom, aff, oracle.Roi(edge_bounds=1), one)[0]) == \
+        list(oracle.edge_rois(dom, aff, oracle.Roi(), one)[0])
+    # The left eye seen from the right one (b < 0) opens the left border:
+    # the left edge lands at fx |b| / d, widest at the near depth.
+    left = synth.affiliated(dom, -0.064)
+    lw = oracle.edge_rois(dom, left, oracle.Roi(edge_bounds=1), dr)[0]
+    assert list(lw) == [math.ceil(fb / 2.0) + 32, 0, 0, 0]
+    assert list(oracle.edge_rois(dom, left, oracle.Roi(), dr)[0]) == [math.ceil(fb / 8.0) + 32, 0, 0, 0]
+
+
 def test_ztest_nearest_and_index_tiebreak(oracle):
     # Two source pixels of one row aimed at the same destination column: the
     # nearer one wins; with equal depth the smaller source index wins.
