@@ -1,0 +1,251 @@
+"""Serving loop for stereo-frame requests over resident scenes.
+
+Requests (a scene key, a dominant and an affiliated camera) arrive over time.
+The scheduler admits a request when a slot is free and the memory it needs
+(workspace and output images) fits in what the in-flight requests leave of
+the budget; its frame is then issued at once on the slot's own stream, so
+requests that arrive while others run join the work already on the GPU
+(continuous batching: no batch boundaries, frames overlap on the device).
+Scenes stay resident on the device for the server's lifetime.  Latency is
+completion minus arrival; completion is read from GPU events, so the host's
+polling interval does not enter it.
+
+The scheduler (`serve`) is plain Python over an executor with four calls
+(need_bytes, issue, poll, release), so its admission logic is testable
+without a GPU; `GpuExecutor` runs each frame through the library
+(`Context.render_stereo`, or two `render_dominant` calls for the two-pass
+baseline), one context and one default-priority stream per slot.
+
+    python -m paper_2609_30741_amd.serve [--workload serve2064] [--rate 90]
+        [--requests 300] [--slots 4] [--mode stereo|two_pass]
+
+prints one JSON line with p50/p99 latency, throughput and queueing.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import dataclasses
+import json
+import math
+import sys
+import time
+from typing import Callable, Dict, List, Optional
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    scene: str
+    cam_dom: object
+    cam_aff: object
+    arrival: float  # seconds after the start of the run
+    slot: int = -1
+    admitted: float = math.nan  # host time of issue, seconds after the start
+    done: float = math.nan  # completion on the GPU clock, seconds after the start
+    out: Optional[dict] = None
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+def poisson_arrivals(rate: float, n: int, seed: int = 0) -> np.ndarray:
+    """n arrival times (seconds) of a Poisson process of the given rate."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=n))
+
+
+def serve(requests: List[Request], executor, n_slots: int, mem_budget: float,
+          clock: Callable[[], float] = time.perf_counter, idle: Callable[[], None] = lambda: None) -> List[Request]:
+    """Run the requests (sorted by arrival) to completion and return them with
+    slot, admission and completion times filled in.  First come, first
+    admitted: a request waits for the one ahead of it, so none is starved by
+    later, smaller ones."""
+    pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+    queue: collections.deque = collections.deque()
+    busy: Dict[int, Request] = {}
+    free = list(range(n_slots))
+    used = 0.0
+    executor.start()  # the GPU clock's zero, then the host's
+    t0 = clock()
+    while pending or queue or busy:
+        progressed = False
+        now = clock() - t0
+        while pending and pending[0].arrival <= now:
+            queue.append(pending.popleft())
+            progressed = True
+        for s, r in list(busy.items()):
+            t = executor.poll(s)
+            if t is not None:
+                r.done = t
+                used -= executor.need_bytes(r)
+                executor.release(s, r)
+                del busy[s]
+                free.append(s)
+                progressed = True
+        while queue and free:
+            r = queue[0]
+            need = executor.need_bytes(r)
+            if need > mem_budget:
+                raise ValueError(f"request {r.rid} needs {need:.3g} B, more than the whole budget {mem_budget:.3g} B")
+            if used + need > mem_budget:
+                break  # waits for memory, not only for a slot
+            queue.popleft()
+            s = free.pop(0)
+            r.slot = s
+            r.admitted = clock() - t0
+            used += need
+            executor.issue(s, r)
+            busy[s] = r
+            progressed = True
+        if not progressed:
+            idle()
+    return requests
+
+
+def summary(reqs: List[Request]) -> dict:
+    lat = np.array([r.latency for r in reqs]) * 1e3
+    wait = np.array([r.admitted - r.arrival for r in reqs]) * 1e3
+    span = max(r.done for r in reqs) - min(r.arrival for r in reqs)
+    return {"requests": len(reqs), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3), "mean_ms": round(float(lat.mean()), 3),
+            "max_ms": round(float(lat.max()), 3), "queue_p99_ms": round(float(np.percentile(wait, 99)), 3),
+            "throughput": round(len(reqs) / span, 2), "span_s": round(span, 4)}
+
+
+class GpuExecutor:
+    """Frames through the library: one context, stream and workspace per slot;
+    scenes resident; completion from an event recorded after each frame."""
+
+    def __init__(self, scenes: dict, n_slots: int, raster=None, roi=None, mode: str = "stereo",
+                 key_capacity: int = 0, keep_outputs: bool = False):
+        import torch
+        from . import api
+        self.torch, self.api = torch, api
+        self.mode = mode
+        self.raster = raster or api.Raster()
+        self.roi = roi or api.Roi()
+        self.keep = keep_outputs
+        self.scenes = {k: api.DeviceScene(s) for k, s in scenes.items()}
+        self.key_capacity = key_capacity
+        self.streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(n_slots - 1)]
+        self.ctxs, self.outs, self.events = [], [], [None] * n_slots
+        for s in range(n_slots):
+            with torch.cuda.stream(self.streams[s]):
+                c = api.Context(sync=False)
+                self.ctxs.append(c)
+                self.outs.append(None)
+        self.start_ev = torch.cuda.Event(enable_timing=True)
+
+    def need_bytes(self, r: Request) -> float:
+        sc = self.scenes[r.scene]
+        W = max(r.cam_dom.width, r.cam_aff.width)
+        H = max(r.cam_dom.height, r.cam_aff.height)
+        ws = self.ctxs[0]._ws_bytes(sc.n, W, H, self.key_capacity)
+        images = W * H * (2 * 5 * 4 + 4 + 1 + 4)  # two eyes' rgb/depth/alpha, z, class map, labels
+        return float(ws + images)
+
+    def start(self):
+        torch = self.torch
+        torch.cuda.synchronize()
+        self.start_ev.record(self.streams[0])
+        torch.cuda.synchronize()
+
+    def issue(self, s: int, r: Request):
+        torch = self.torch
+        sc = self.scenes[r.scene]
+        W = max(r.cam_dom.width, r.cam_aff.width)
+        H = max(r.cam_dom.height, r.cam_aff.height)
+        ctx = self.ctxs[s]
+        with torch.cuda.stream(self.streams[s]):
+            ctx.reserve(sc.n, W, H, self.key_capacity)
+            if self.mode == "stereo":
+                o = self.outs[s]
+                if o is not None and tuple(o["rgb_aff"].shape[1:]) != (r.cam_aff.height, r.cam_aff.width):
+                    o = None
+                o = ctx.render_stereo(sc, r.cam_dom, r.cam_aff, self.raster, self.roi, out=o)
+                self.outs[s] = o
+                keys = ("rgb_dom", "depth_raw_dom", "alpha_dom", "rgb_aff", "z_aff", "alpha_aff", "cls_aff")
+            else:
+                o = self.outs[s] or {}
+                a = ctx.render_dominant(sc, r.cam_dom, self.raster, out=o.get("dom"))
+                b = ctx.render_dominant(sc, r.cam_aff, self.raster, out=o.get("aff"))
+                o = {"dom": a, "aff": b}
+                self.outs[s] = o
+                keys = ()
+            if self.keep:
+                # Copied in stream order, before the slot's next frame reuses the buffers.
+                r.out = {k: o[k].clone() for k in keys} if keys else {
+                    "rgb_dom": o["dom"]["rgb"].clone(), "rgb_aff": o["aff"]["rgb"].clone()}
+            ev = torch.cuda.Event(enable_timing=True)
+            ev.record(self.streams[s])
+            self.events[s] = ev
+
+    def poll(self, s: int) -> Optional[float]:
+        ev = self.events[s]
+        if ev is None or not ev.query():
+            return None
+        return self.start_ev.elapsed_time(ev) * 1e-3
+
+    def release(self, s: int, r: Request):
+        st = self.ctxs[s].poll_status()
+        if st["overflow"]:
+            raise RuntimeError(f"request {r.rid}: key capacity {self.key_capacity} exceeded; raise --key-capacity")
+        self.events[s] = None
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--workload", default="serve2064")
+    ap.add_argument("--rate", type=float, default=90.0, help="Poisson arrival rate, stereo frames/s")
+    ap.add_argument("--requests", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=8)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--mem-gb", type=float, default=64.0, help="memory budget of the in-flight requests")
+    ap.add_argument("--mode", choices=("stereo", "two_pass"), default="stereo")
+    ap.add_argument("--key-capacity", type=int, default=0, help="keys per pass (0: sized on the first poses)")
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args(argv)
+
+    import torch
+    from . import api, synth
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        return 3
+    scene, cams, b = synth.WORKLOADS[args.workload](args.seed)
+    affs = [synth.affiliated(c, b) for c in cams]
+    kc = args.key_capacity
+    if kc <= 0:
+        # Size the key capacity on the poses (a synchronous context reads the
+        # key counts back), with headroom.
+        ctx = api.Context(sync=True)
+        ds = api.DeviceScene(scene)
+        out, mx = None, 0
+        for cd, ca in zip(cams, affs):
+            out = ctx.render_stereo(ds, cd, ca, out=out)
+            mx = max(mx, out["stats"]["n_keys_dom"], out["stats"]["n_keys_roi"])
+        kc = int(mx * 1.25) + 4096
+        del ctx, ds, out
+        torch.cuda.synchronize()
+    ex = GpuExecutor({"s": scene}, args.slots, mode=args.mode, key_capacity=kc)
+    n_poses = len(cams)
+
+    def reqs(n, rate, seed):
+        t = poisson_arrivals(rate, n, seed)
+        return [Request(i, "s", cams[i % n_poses], affs[i % n_poses], float(t[i])) for i in range(n)]
+
+    serve(reqs(args.warmup, args.rate, args.seed + 1), ex, args.slots, args.mem_gb * 1e9)
+    done = serve(reqs(args.requests, args.rate, args.seed + 2), ex, args.slots, args.mem_gb * 1e9)
+    s = summary(done)
+    s.update({"workload": args.workload, "mode": args.mode, "rate": args.rate, "slots": args.slots,
+              "width": int(cams[0].width), "height": int(cams[0].height), "surfels": int(scene.n),
+              "key_capacity": kc})
+    print(json.dumps(s), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -274,10 +274,23 @@ def workload_unbounded1600(seed: int = 0, n: int = 1_000_000, n_poses: int = 32)
     return scene, cams, BASELINE_IPD
 
 
+def workload_serve2064(seed: int = 0, n: int = 1_000_000, n_poses: int = 32):
+    """The serving workload: the unbounded 1M-surfel SH3 scene seen at
+    2064x2208 per eye (fx=fy=1700), poses along the forward trajectory."""
+    scene = scene_unbounded(seed, n)
+    cams = []
+    for k in range(n_poses):
+        y = -6.0 + 4.5 * k / max(n_poses - 1, 1)
+        eye = (0.0, y, 0.0)
+        cams.append(look_at(eye, (0.0, y + 1.0, 0.0), (0.0, 0.0, 1.0), 2064, 2208, 1700.0))
+    return scene, cams, BASELINE_IPD
+
+
 WORKLOADS = {
     "cube256": workload_cube256,
     "sphere800": workload_sphere800,
     "unbounded1600": workload_unbounded1600,
+    "serve2064": workload_serve2064,
 }
 
 

@@ -15,6 +15,8 @@ most about alpha_min.
 """
 import sys
 
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -481,6 +483,34 @@ def test_frames_in_flight_match_sequential(ctx):
                 assert torch.equal(got[i][key], seq[i][key]), f"round {rep} frame {i}: {key} differs"
     for c in ctxs:
         assert c.poll_status()["overflow"] == 0
+
+
+def test_serving_results_alone_equal_results_in_the_mix():
+    """The serving loop: the same requests served one at a time (one slot)
+    and overlapped on the device (three slots, all arriving at once, so
+    later ones join work in flight) give the same frames bit for bit."""
+    from paper_2609_30741_amd import serve
+    sc = synth.scene_uniform_cube(11, 10_000)
+    cams = [synth.look_at((4.0 * math.cos(t), 4.0 * math.sin(t), 0.3), (0, 0, 0), (0, 0, 1), 192, 160, 220.0)
+            for t in np.linspace(0.0, 2.0, 8)]
+    affs = [synth.affiliated(c, 0.064) for c in cams]
+
+    def run(slots):
+        ex = serve.GpuExecutor({"s": sc}, slots, key_capacity=1 << 18, keep_outputs=True)
+        reqs = [serve.Request(i, "s", cams[i], affs[i], 0.0) for i in range(len(cams))]
+        serve.serve(reqs, ex, slots, 1e12)
+        torch.cuda.synchronize()
+        return reqs
+
+    alone = run(1)
+    mix = run(3)
+    assert len({r.slot for r in mix}) == 3
+    for a, b in zip(alone, mix):
+        assert a.out.keys() == b.out.keys()
+        for k in a.out:
+            assert torch.equal(a.out[k], b.out[k]), (a.rid, k)
+    s = serve.summary(mix)
+    log(f"serving mix of {s['requests']}: p50 {s['p50_ms']} ms p99 {s['p99_ms']} ms")
 
 
 def test_timing_stage_mask(ctx):
