@@ -25,6 +25,7 @@ struct bgs_ctx {
     hipEvent_t ev[kRing][BGS_NUM_STAGES][2] = {};
     bool pending[kRing][BGS_NUM_STAGES] = {};
     int slot = 0;
+    hipError_t timing_err = hipSuccess;  // first failure of an event call while timing, reported on collect
     double total_ms[BGS_NUM_STAGES] = {};
     int64_t count[BGS_NUM_STAGES] = {};
     std::string err;
@@ -271,9 +272,16 @@ void mark(bgs_ctx* ctx, int stage, int end) {
     if (!((ctx->timing >> stage) & 1u)) return;
     if (!end && ctx->pending[ctx->slot][stage]) {
         ctx->slot = (ctx->slot + 1) % bgs_ctx::kRing;
-        drain_slot(ctx, ctx->slot);
+        const hipError_t e = drain_slot(ctx, ctx->slot);
+        if (e != hipSuccess && ctx->timing_err == hipSuccess) ctx->timing_err = e;
     }
-    hipEventRecord(ctx->ev[ctx->slot][stage][end], ctx->stream);
+    const hipError_t e = hipEventRecord(ctx->ev[ctx->slot][stage][end], ctx->stream);
+    if (e != hipSuccess) {
+        // Leave the stage out of this frame rather than time an unrecorded event.
+        if (ctx->timing_err == hipSuccess) ctx->timing_err = e;
+        ctx->pending[ctx->slot][stage] = false;
+        return;
+    }
     if (end) ctx->pending[ctx->slot][stage] = true;
 }
 
@@ -466,7 +474,7 @@ int32_t bgs_ctx_destroy(bgs_ctx* ctx) {
     for (int r = 0; r < bgs_ctx::kRing; ++r)
         for (int i = 0; i < BGS_NUM_STAGES; ++i)
             for (int j = 0; j < 2; ++j)
-                if (ctx->ev[r][i][j]) hipEventDestroy(ctx->ev[r][i][j]);
+                if (ctx->ev[r][i][j]) (void)hipEventDestroy(ctx->ev[r][i][j]);  // nothing to report on teardown
     delete ctx;
     return BGS_OK;
 }
@@ -527,6 +535,11 @@ int32_t bgs_ctx_set_timing(bgs_ctx* ctx, int32_t on) {
 
 int32_t bgs_timing_collect(bgs_ctx* ctx, double* total_ms, int64_t* counts) {
     if (!ctx) return BGS_ERR_INVALID_ARG;
+    if (ctx->timing_err != hipSuccess) {
+        const hipError_t e = ctx->timing_err;
+        ctx->timing_err = hipSuccess;
+        return hip_fail(ctx, e, "stage timing (event record)");
+    }
     for (int k = 1; k <= bgs_ctx::kRing; ++k) {
         const hipError_t e = drain_slot(ctx, (ctx->slot + k) % bgs_ctx::kRing);
         if (e != hipSuccess) return hip_fail(ctx, e, "stage timing");
@@ -794,8 +807,9 @@ int32_t bgs_preprocess_debug(bgs_ctx* ctx, const bgs_scene* scene, const bgs_cam
     const SceneArgs sa{scene->pos, scene->quat, scene->scale, scene->opacity, scene->sh, (int)scene->n,
                        scene->sh_degree};
     const int n = (int)scene->n;
-    HIP_CHECK(launch_preprocess(sa, pc, raster->alpha_min, raster->lowpass, MaskArgs{nullptr, 0}, at<SurfelRec>(ws, L.recs),
-                                zkey, at<uint2>(ws, L.rects), counts, nullptr, nullptr, nullptr, nullptr, ctx->stream),
+    const MaskArgs no_mask{nullptr, nullptr, pc.tiles_x, 0};
+    HIP_CHECK(launch_preprocess(sa, pc, raster->alpha_min, raster->lowpass, no_mask, at<SurfelRec>(ws, L.recs), zkey,
+                                at<uint2>(ws, L.rects), counts, nullptr, nullptr, nullptr, nullptr, ctx->stream),
               "preprocess");
     // Unpack the tile rectangles for the caller.
     if (n > 0) {

@@ -1212,7 +1212,7 @@ __global__ __launch_bounds__(256) void k_blend_seg(const SurfelRec* __restrict__
     for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
         const uint32_t slot = ca.item_slot[item];
         const uint4 d = ca.slot_desc[slot];
-        const uint32_t ibase = d.w & ((1u << kContSegShift) - 1u), nseg = d.w >> kContSegShift, k = item - ibase;
+        const uint32_t ibase = d.w & ((1u << kContSegShift) - 1u), k = item - ibase;
         const uint32_t lo = round_lo(round);
         if (k < lo || k >= round_lo(round + 1)) continue;
         uint32_t sb, se;

@@ -540,6 +540,7 @@ uint32_t rs_grid(int64_t n_cap, int items) {
 }  // namespace
 
 size_t radix_tmp_bytes(int64_t n_cap) {
+    (void)n_cap;  // the grid, and so the count table, is at most kRsGrid blocks for any size
     return ((size_t)kRsBins * kRsGrid + kRsBins + 64) * sizeof(uint32_t) + 256;
 }
 
