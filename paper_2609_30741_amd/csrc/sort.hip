@@ -182,8 +182,8 @@ hipError_t exclusive_scan(const uint32_t* in, const uint32_t* idx, uint32_t* out
 // ---------------------------------------------------------------------------
 // Radix sort.  Stable LSD with digits of up to 8 bits (a 32-bit key takes four
 // passes, an 11-bit tile id two of 6 and 5 bits).  The grid is fixed by the
-// capacity (at most kRsGrid blocks; always kRsGrid for small sorts, which
-// use 1024-key sub-chunks instead of 6144); block b owns the contiguous
+// capacity (at most kRsGrid blocks; always kRsSmallGrid for small sorts,
+// which use 1024-key sub-chunks instead of 6144); block b owns the contiguous
 // chunk [b C, b C + C) of the *n_dev keys, C = n / grid rounded up to 256.
 // A pass is three launches:
 //   1. k_rs_hist: per-block digit counts (LDS atomics), stored
@@ -204,6 +204,10 @@ namespace {
 constexpr int kRsMaxBits = 8;
 constexpr int kRsBins = 1 << kRsMaxBits;
 constexpr int kRsGrid = 1024;
+// Small sorts use half the grid: a 300k-key depth sort then gives each
+// block about 600 keys, and its count table and per-digit scans shrink by
+// half (61.8 against 69.2 us on sphere800; 256 blocks slowed the ROI sort).
+constexpr int kRsSmallGrid = 512;
 // Keys per thread per sub-chunk: 24 (6144-key sub-chunks, long digit runs;
 // a 6M-key tile sort then gives each block one sub-chunk, not a full and a
 // partial one in turn) for large sorts; 4 (1024-key sub-chunks) for small
@@ -555,7 +559,7 @@ hipError_t radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, co
     const int64_t n_exp = n_hint > 0 && n_hint < n_cap ? n_hint : n_cap;
     const bool small = n_exp <= (int64_t)kRsGrid * 256 * kRsItemsSmall;
     const int items = small ? kRsItemsSmall : kRsItemsBig;
-    const uint32_t grid = small ? kRsGrid : rs_grid(n_cap, items);
+    const uint32_t grid = small ? kRsSmallGrid : rs_grid(n_cap, items);
     uint32_t* counts = (uint32_t*)tmp;
     uint32_t* totals = counts + (size_t)kRsBins * grid;
     const int passes = (key_bits + kRsMaxBits - 1) / kRsMaxBits;
