@@ -93,6 +93,9 @@ def main():
     ap.add_argument("--inflight-split", default="0,0,128,0,0",
                     help="blend split (cap_dom, cap_roi, seg_len, far_dom, far_roi) of the in-flight region, "
                          "both methods; 0,0 never continues a tile list")
+    ap.add_argument("--traffic-probe-stereo", action="store_true",
+                    help="no timing: 48 stereo frames of the workload at the default blend split (16 sizing the "
+                         "workspace, then 32), for per-kernel rocprofv3 counter runs of the sorts and reprojection")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="no timing: a 512 MiB copy (counter calibration), then 12 dominant-eye renders of the "
                          "workload, for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs")
@@ -114,6 +117,9 @@ def main():
 
     if args.traffic_probe:
         traffic_probe(args)
+        return
+    if args.traffic_probe_stereo:
+        traffic_probe_stereo(args)
         return
 
     t0 = time.time()
@@ -403,6 +409,28 @@ def traffic_probe(args):
         ctx.render_dominant(ds, c)
     torch.cuda.synchronize()
     log("traffic probe done")
+
+
+def traffic_probe_stereo(args):
+    """Kernels for per-kernel HBM counter runs over whole stereo frames: 16
+    frames that size the workspace (synchronous), then 32 frames issued back
+    to back, all at the library's default blend split."""
+    import torch
+    from paper_2609_30741_amd import api, synth
+
+    scene, cams, baseline = synth.WORKLOADS[args.workload](args.seed)
+    affs = [synth.affiliated(c, baseline) for c in cams]
+    ds = api.DeviceScene(scene)
+    ctx = api.Context(sync=True)
+    out = None
+    for cd, ca in zip(cams, affs):
+        out = ctx.render_stereo(ds, cd, ca, out=out)
+    ctx.set_sync(False)
+    for _ in range(2):
+        for cd, ca in zip(cams, affs):
+            ctx.render_stereo(ds, cd, ca, out=out)
+    torch.cuda.synchronize()
+    log("stereo traffic probe done")
 
 
 def blend_traffic():
