@@ -407,7 +407,8 @@ static_assert(kRsItemsBig % 4 == 0, "a thread's keys are loaded as 16-byte vecto
 
 __device__ __forceinline__ uint32_t cnt_slot(uint32_t w) { return w + (w >> 5); }
 
-__global__ __launch_bounds__(256) void k_rs_scatter_cnt(const uint32_t* __restrict__ kin,
+template <bool kHasV>
+__global__ __launch_bounds__(256, 4) void k_rs_scatter_cnt(const uint32_t* __restrict__ kin,
                                                         const uint32_t* __restrict__ vin,
                                                         uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                         const uint32_t* __restrict__ n_dev, uint32_t n_host,
@@ -415,15 +416,18 @@ __global__ __launch_bounds__(256) void k_rs_scatter_cnt(const uint32_t* __restri
                                                         const uint32_t* __restrict__ totals) {
     constexpr int kItems = kRsItemsBig;
     constexpr int kSub = 256 * kItems;
-    __shared__ uint32_t s_buf[kRsCntBuf];  // the counters, then the sub-chunk's keys and values
+    // The counters, then the sub-chunk's keys (and values): keys alone need
+    // no more LDS than the counters, so four blocks share a CU instead of three.
+    constexpr int kBuf = kHasV ? kRsCntBuf : (kRsCntLds > kSub ? kRsCntLds : kSub);
+    __shared__ uint32_t s_buf[kBuf];
     __shared__ uint32_t dstart[kRsCntBins + 1];
     __shared__ uint32_t gbase[kRsCntBins];
     __shared__ uint32_t run[kRsCntBins];
     __shared__ uint32_t lds[4];
     uint32_t* s_keys = s_buf;
-    uint32_t* s_vals = s_buf + kSub;
+    uint32_t* s_vals = s_buf + (kHasV ? kSub : 0);  // not touched without values
     const uint32_t n = n_dev ? *n_dev : n_host, bins = 1u << bits, mask = bins - 1u;
-    const bool has_v = vout != nullptr;
+    constexpr bool has_v = kHasV;  // false: keys only (a key that carries its value)
     uint32_t lo, hi;
     chunk_of(n, gridDim.x, blockIdx.x, kSub, &lo, &hi);
     if (lo >= hi) return;
@@ -439,7 +443,7 @@ __global__ __launch_bounds__(256) void k_rs_scatter_cnt(const uint32_t* __restri
     for (uint64_t sub = lo; sub < hi; sub += kSub) {
         const uint32_t m = (uint32_t)min<uint64_t>((uint64_t)kSub, hi - sub);
         const uint32_t i0 = t * kItems;
-        uint32_t k[kItems], v[kItems], r[kItems];
+        uint32_t k[kItems], v[kItems];
         if (i0 + kItems <= m) {
             const uint4* kp = reinterpret_cast<const uint4*>(kin + sub + i0);
 #pragma unroll
@@ -468,7 +472,12 @@ __global__ __launch_bounds__(256) void k_rs_scatter_cnt(const uint32_t* __restri
         }
         for (uint32_t w = t; w < nclear; w += 256) s_buf[w] = 0u;
         __syncthreads();
-        // This thread's count of each digit before each of its keys.
+        // This thread's count of each digit before each of its keys.  Ranks
+        // stay below 2^16 (a sub-chunk holds 6144 keys), so two share a
+        // register: fewer live registers, more waves per SIMD.
+        uint32_t r2[kItems / 2];
+#pragma unroll
+        for (int q = 0; q < kItems / 2; ++q) r2[q] = 0u;
 #pragma unroll
         for (int it = 0; it < kItems; ++it) {
             if (i0 + it < m) {
@@ -476,28 +485,29 @@ __global__ __launch_bounds__(256) void k_rs_scatter_cnt(const uint32_t* __restri
                 const uint32_t e = d * 256u + t;
                 const uint32_t h = 16u * (e & 1u);
                 const uint32_t old = atomicAdd(&s_buf[cnt_slot(e >> 1)], 1u << h);
-                r[it] = (old >> h) & 0xFFFFu;
+                r2[it >> 1] |= ((old >> h) & 0xFFFFu) << (16 * (it & 1));
             }
         }
         __syncthreads();
-        // Raking exclusive scan of the counters in (digit, thread) order.
-        uint32_t wv[kRsCntBins / 2];
+        // Raking exclusive scan of the counters in (digit, thread) order; the
+        // words are read again for the second sweep rather than held.
         uint32_t sum = 0;
 #pragma unroll
         for (int j = 0; j < kRsCntBins / 2; ++j) {
             if ((uint32_t)j < rake) {
-                wv[j] = s_buf[cnt_slot(t * rake + j)];
-                sum += (wv[j] & 0xFFFFu) + (wv[j] >> 16);
+                const uint32_t w = s_buf[cnt_slot(t * rake + j)];
+                sum += (w & 0xFFFFu) + (w >> 16);
             }
         }
         uint32_t acc = block_excl_scan(sum, lds, nullptr);
 #pragma unroll
         for (int j = 0; j < kRsCntBins / 2; ++j) {
             if ((uint32_t)j < rake) {
+                const uint32_t w = s_buf[cnt_slot(t * rake + j)];
                 const uint32_t e0 = acc;
-                acc += wv[j] & 0xFFFFu;
+                acc += w & 0xFFFFu;
                 s_buf[cnt_slot(t * rake + j)] = e0 | (acc << 16);
-                acc += wv[j] >> 16;
+                acc += w >> 16;
             }
         }
         __syncthreads();
@@ -505,7 +515,8 @@ __global__ __launch_bounds__(256) void k_rs_scatter_cnt(const uint32_t* __restri
         for (int it = 0; it < kItems; ++it) {
             if (i0 + it < m) {
                 const uint32_t e = ((k[it] >> shift) & mask) * 256u + t;
-                r[it] += (s_buf[cnt_slot(e >> 1)] >> (16u * (e & 1u))) & 0xFFFFu;
+                const uint32_t first = (s_buf[cnt_slot(e >> 1)] >> (16u * (e & 1u))) & 0xFFFFu;
+                r2[it >> 1] += first << (16 * (it & 1));  // no carry: every rank is below 2^16
             }
         }
         if (t < bins) dstart[t] = s_buf[cnt_slot(t * 128u)] & 0xFFFFu;
@@ -518,8 +529,9 @@ __global__ __launch_bounds__(256) void k_rs_scatter_cnt(const uint32_t* __restri
 #pragma unroll
         for (int it = 0; it < kItems; ++it) {
             if (i0 + it < m) {
-                s_keys[r[it]] = k[it];
-                if (has_v) s_vals[r[it]] = v[it];
+                const uint32_t rk = (r2[it >> 1] >> (16 * (it & 1))) & 0xFFFFu;
+                s_keys[rk] = k[it];
+                if (has_v) s_vals[rk] = v[it];
             }
         }
         __syncthreads();
@@ -583,8 +595,11 @@ hipError_t radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, co
         if (small)
             hipLaunchKernelGGL(k_rs_scatter<kRsItemsSmall>, dim3(grid), dim3(256), 0, s, ki, vi, ko, vo, n_dev,
                                (uint32_t)n_cap, shift, bits, counts, totals);
+        else if (bits <= kRsCntBits && aligned && vo)
+            hipLaunchKernelGGL(k_rs_scatter_cnt<true>, dim3(grid), dim3(256), 0, s, ki, vi, ko, vo, n_dev,
+                               (uint32_t)n_cap, shift, bits, counts, totals);
         else if (bits <= kRsCntBits && aligned)
-            hipLaunchKernelGGL(k_rs_scatter_cnt, dim3(grid), dim3(256), 0, s, ki, vi, ko, vo, n_dev,
+            hipLaunchKernelGGL(k_rs_scatter_cnt<false>, dim3(grid), dim3(256), 0, s, ki, vi, ko, vo, n_dev,
                                (uint32_t)n_cap, shift, bits, counts, totals);
         else
             hipLaunchKernelGGL(k_rs_scatter<kRsItemsBig>, dim3(grid), dim3(256), 0, s, ki, vi, ko, vo, n_dev,
