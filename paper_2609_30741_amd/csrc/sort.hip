@@ -408,7 +408,7 @@ static_assert(kRsItemsBig % 4 == 0, "a thread's keys are loaded as 16-byte vecto
 __device__ __forceinline__ uint32_t cnt_slot(uint32_t w) { return w + (w >> 5); }
 
 template <bool kHasV>
-__global__ __launch_bounds__(256, 4) void k_rs_scatter_cnt(const uint32_t* __restrict__ kin,
+__global__ __launch_bounds__(256, kHasV ? 2 : 4) void k_rs_scatter_cnt(const uint32_t* __restrict__ kin,
                                                         const uint32_t* __restrict__ vin,
                                                         uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                         const uint32_t* __restrict__ n_dev, uint32_t n_host,
