@@ -93,7 +93,9 @@ Layout make_layout(int64_t n, int64_t W, int64_t H, int64_t kc) {
     L.dvals_a = take(4 * n);
     L.dvals_b = take(4 * n);
     L.offs = take(4 * (n + 1));
-    L.surf_scan = take(4 * scan_tmp_elems(n));
+    // Scan scratch: the count scan's block sums, or the per-256 totals of the
+    // ROI pass's ordered counts (ceil(n / 256) words), whichever is larger.
+    L.surf_scan = take(4 * std::max<size_t>(scan_tmp_elems(n), (size_t)((n + 255) / 256) + 64));
     L.recs2 = take(sizeof(SurfelRec) * n);
     L.zkeys2 = take(4 * n);
     L.rects2 = take(8 * n);
@@ -352,9 +354,14 @@ int raster_pass(bgs_ctx* ctx, const Layout& L, void* ws, int64_t kc, const bgs_s
     uint2* rects = at<uint2>(ws, precomputed ? L.rects2 : L.rects);
     uint32_t* counts = at<uint32_t>(ws, L.counts);
     uint32_t* offs = at<uint32_t>(ws, L.offs);
+    // Precomputed records: the masked key counts are taken in compositing
+    // order together with the first step of their scan, once the order is
+    // known (below), when the flat scan covers n.
+    const bool fused_counts = precomputed && scan_is_flat(n);
     if (precomputed) {
         if (!tile_mask) return fail(ctx, BGS_ERR_INVALID_ARG, "precomputed records need a tile mask");
-        HIP_CHECK(launch_masked_counts(rects, recs, n, n_tiles, mask, counts, s), "masked counts");
+        if (!fused_counts)
+            HIP_CHECK(launch_masked_counts(rects, recs, n, n_tiles, mask, counts, s), "masked counts");
     } else {
         const SceneArgs sa{scene.pos, scene.quat, scene.scale, scene.opacity, scene.sh, n, scene.sh_degree};
         PreCam pn{};
@@ -382,8 +389,17 @@ int raster_pass(bgs_ctx* ctx, const Layout& L, void* ws, int64_t kc, const bgs_s
     mark(ctx, sb + 2, 0);
     hipError_t se = hipSuccess;
     uint2* ranges = at<uint2>(ws, L.ranges);
-    if (scan_counts(counts, order, offs, n, at<uint32_t>(ws, L.surf_scan),
-                    KeyCount{st, (uint32_t)kc, which, ranges, (uint32_t)n_tiles}, s, &se)) {
+    uint32_t* surf_scan = at<uint32_t>(ws, L.surf_scan);
+    const KeyCount kcnt{st, (uint32_t)kc, which, ranges, (uint32_t)n_tiles};
+    bool scanned;
+    if (fused_counts) {
+        HIP_CHECK(launch_masked_counts_ordered(rects, recs, order, n, n_tiles, mask, counts, surf_scan, s),
+                  "masked counts");
+        scanned = scan_counts_presummed(counts, offs, n, surf_scan, kcnt, s, &se);  // the flat form covers n
+    } else {
+        scanned = scan_counts(counts, order, offs, n, surf_scan, kcnt, s, &se);
+    }
+    if (scanned) {
         HIP_CHECK(se, "count scan");
     } else {
         HIP_CHECK(exclusive_scan(counts, order, offs, nullptr, n, at<uint32_t>(ws, L.surf_scan), s), "count scan");

@@ -141,6 +141,13 @@ struct KeyCount {
 // launch_status_keys then); *err gets the launch status otherwise.
 bool scan_counts(const uint32_t* in, const uint32_t* idx, uint32_t* out, int64_t n, uint32_t* tmp,
                  const KeyCount& kcnt, hipStream_t s, hipError_t* err);
+// scan_counts' down-sweep alone, over counts in order whose totals per 256
+// consecutive elements are already in partials; false when n needs more
+// than the flat form's blocks.
+bool scan_counts_presummed(const uint32_t* in, uint32_t* out, int64_t n, const uint32_t* partials,
+                           const KeyCount& kcnt, hipStream_t s, hipError_t* err);
+// Whether the flat, two-launch scan covers n elements.
+bool scan_is_flat(int64_t n);
 size_t radix_tmp_bytes(int64_t n_cap);
 // Stable LSD radix sort of (keys, values) by bits [key_shift, key_shift +
 // key_bits) of the keys, with digits of up to 8 bits.  (ka, va) is the
@@ -166,6 +173,12 @@ hipError_t launch_preprocess(const SceneArgs& sc, const PreCam& cam, float alpha
 // Key counts within the mask's tiles from precomputed tile rects and records.
 hipError_t launch_masked_counts(const uint2* rects, const SurfelRec* recs, int n, int n_tiles, const MaskArgs& mask,
                                 uint32_t* counts, hipStream_t s);
+// The same counts in compositing order (counts[i] for surfel order[i]), with
+// the total of every 256 consecutive positions in partials (ceil(n / 256)
+// of them): the scan then needs only its down-sweep (scan_counts_presummed).
+hipError_t launch_masked_counts_ordered(const uint2* rects, const SurfelRec* recs, const uint32_t* order, int n,
+                                        int n_tiles, const MaskArgs& mask, uint32_t* counts, uint32_t* partials,
+                                        hipStream_t s);
 // Keys of every surfel in compositing order: the tiles of its rect that its
 // strip band meets (and the mask holds, when enabled), row by row.
 // vbits > 0: one word per key, tile << vbits | surfel (tvals unused);

@@ -489,6 +489,45 @@ __global__ __launch_bounds__(256) void k_masked_counts(const uint2* __restrict__
                            (int)(r.y >> 16));
 }
 
+// The ROI pass's key counts in compositing order, fused with the first step
+// of their scan: one thread per position i of the order writes the masked
+// key count of surfel order[i] at i, and each block of 256 positions writes
+// its total to partials[block], so only the scan's down-sweep remains (it
+// adds kScanItems of these partials per block of its own).
+__global__ __launch_bounds__(256) void k_masked_counts_ordered(const uint2* __restrict__ rects,
+                                                               const SurfelRec* __restrict__ recs,
+                                                               const uint32_t* __restrict__ order, int n,
+                                                               MaskArgs mask, int mask_lds,
+                                                               uint32_t* __restrict__ counts,
+                                                               uint32_t* __restrict__ partials) {
+    extern __shared__ uint32_t s_mpre[];
+    __shared__ uint32_t s4[4];
+    if (mask_lds > 0) {  // uniform over the grid
+        for (int i = threadIdx.x; i < mask_lds; i += 256) s_mpre[i] = mask.prefix[i];
+        __syncthreads();
+        mask.prefix = s_mpre;
+    }
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    uint32_t c = 0;
+    if (i < n) {
+        const uint32_t k = order[i];
+        const uint2 r = rects[k];
+        if (!(r.x > r.y)) {
+            const int tx0 = (int)(r.x & 0xFFFFu), ty0 = (int)(r.x >> 16), tx1 = (int)(r.y & 0xFFFFu),
+                      ty1 = (int)(r.y >> 16);
+            if (masked_count(mask, tx0, ty0, tx1, ty1) != 0)
+                c = band_count(BandRows(recs[k]), mask, tx0, ty0, tx1, ty1);
+        }
+        counts[i] = c;
+    }
+    uint32_t sum = c;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) sum += (uint32_t)__shfl_xor((int)sum, off, 64);
+    if ((threadIdx.x & 63) == 0) s4[threadIdx.x >> 6] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) partials[blockIdx.x] = s4[0] + s4[1] + s4[2] + s4[3];
+}
+
 // ---------------------------------------------------------------------------
 // Key emission, per block of up to 256 surfels in compositing order: one thread
 // per surfel lists the non-empty rows of its band within its rect as
@@ -1372,6 +1411,17 @@ hipError_t launch_preprocess(const SceneArgs& sc, const PreCam& cam, float alpha
     else
         hipLaunchKernelGGL(k_preprocess<false>, g, dim3(256), 0, s, sc, cam, cam, alpha_min, lowpass, mask, recs, zkeys,
                            rects, counts, nullptr, nullptr, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_masked_counts_ordered(const uint2* rects, const SurfelRec* recs, const uint32_t* order, int n,
+                                        int n_tiles, const MaskArgs& mask, uint32_t* counts, uint32_t* partials,
+                                        hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int mask_lds = n_tiles + 1 <= kEmitMaskLds ? n_tiles + 1 : 0;
+    hipLaunchKernelGGL(k_masked_counts_ordered, dim3((unsigned)((n + 255) / 256)), dim3(256),
+                       (size_t)mask_lds * sizeof(uint32_t), s, rects, recs, order, n, mask, mask_lds, counts,
+                       partials);
     return hipGetLastError();
 }
 

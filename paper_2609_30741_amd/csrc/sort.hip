@@ -93,16 +93,18 @@ __global__ __launch_bounds__(256) void k_scan_down(const uint32_t* in, const uin
 // tile ranges (see KeyCount).
 constexpr int64_t kScanFlat = 4096;
 
+// parts: partials per block of the scan (1: one sum per block of kScanBlock
+// elements; kScanItems: one per 256 elements).
 __global__ __launch_bounds__(256) void k_scan_down_flat(const uint32_t* in, const uint32_t* __restrict__ idx,
                                                         const uint32_t* __restrict__ n_dev, int64_t n_cap,
-                                                        const uint32_t* __restrict__ partials, uint32_t* out,
-                                                        KeyCount kcnt) {
+                                                        const uint32_t* __restrict__ partials, int parts,
+                                                        uint32_t* out, KeyCount kcnt) {
     __shared__ uint32_t lds[4];
     const int64_t n = n_dev ? (int64_t)*n_dev : n_cap;
     for (uint32_t t = blockIdx.x * 256 + threadIdx.x; t < kcnt.n_tiles; t += gridDim.x * 256)
         kcnt.ranges[t] = make_uint2(0u, 0u);
     uint32_t pre = 0;
-    for (uint32_t b = threadIdx.x; b < blockIdx.x; b += 256) pre += partials[b];
+    for (uint32_t b = threadIdx.x; b < blockIdx.x * (uint32_t)parts; b += 256) pre += partials[b];
     pre = block_sum(pre, lds);
     const int64_t base = (int64_t)blockIdx.x * kScanBlock + (int64_t)threadIdx.x * kScanItems;
     uint32_t v[kScanItems];
@@ -142,7 +144,20 @@ bool scan_counts(const uint32_t* in, const uint32_t* idx, uint32_t* out, int64_t
     if (nb > kScanFlat) return false;
     if (nb > 1)
         hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(256), 0, s, in, idx, nullptr, n, tmp);
-    hipLaunchKernelGGL(k_scan_down_flat, dim3((unsigned)nb), dim3(256), 0, s, in, idx, nullptr, n, tmp, out, kcnt);
+    hipLaunchKernelGGL(k_scan_down_flat, dim3((unsigned)nb), dim3(256), 0, s, in, idx, nullptr, n, tmp, 1, out,
+                       kcnt);
+    *err = hipGetLastError();
+    return true;
+}
+
+bool scan_is_flat(int64_t n) { return ceil_div(n + 1, kScanBlock) <= kScanFlat; }
+
+bool scan_counts_presummed(const uint32_t* in, uint32_t* out, int64_t n, const uint32_t* partials,
+                           const KeyCount& kcnt, hipStream_t s, hipError_t* err) {
+    const int64_t nb = ceil_div(n + 1, kScanBlock);
+    if (nb > kScanFlat) return false;
+    hipLaunchKernelGGL(k_scan_down_flat, dim3((unsigned)nb), dim3(256), 0, s, in, nullptr, nullptr, n, partials,
+                       kScanItems, out, kcnt);
     *err = hipGetLastError();
     return true;
 }
