@@ -58,7 +58,7 @@ PEAK_FP32_TFLOPS = 157.3
 # segment rounds, chain, fix-up), FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
 # (factors from a 512 MiB copy), valid while raster.hip and bgs_api.hip hash
 # (sha1 over the two files in that order) to this value.
-BLEND_TRAFFIC = {"source_sha1": "397201011b1a6b882f31db5fc8d5d750aab8800f", "bytes": 120.1e6}
+BLEND_TRAFFIC = {"source_sha1": "d38cf24a846cd3817a9fda718d17bb872d6199f3", "bytes": 120.1e6}
 # fp32 operations of one evaluated (pixel, surfel) pair in the blend and the
 # extra ones of a contributing pair (an FMA counts as two).
 FLOPS_EVAL = 31

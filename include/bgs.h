@@ -181,7 +181,7 @@ BGS_API int32_t bgs_ctx_set_count_pairs(bgs_ctx* ctx, int32_t count);
  * back, and a pixel that stops inside a segment is composited again over
  * that segment, in order, from its exact state (unless the segment's own
  * walk started from that state).  Defaults 1024, 128, 64,
- * 0, 512.  BGS_ERR_INVALID_ARG for a negative cap or far, or seg_len < 1. */
+ * 0, 256.  BGS_ERR_INVALID_ARG for a negative cap or far, or seg_len < 1. */
 BGS_API int32_t bgs_ctx_set_blend_split(bgs_ctx* ctx, int32_t cap_dom, int32_t cap_roi, int32_t seg_len,
                                         int32_t far_dom, int32_t far_roi);
 

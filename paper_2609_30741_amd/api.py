@@ -136,7 +136,7 @@ class Context:
         self._check(self.L.bgs_ctx_set_count_pairs(self.h, int(bool(on))))
 
     def set_blend_split(self, cap_dom: int = 1024, cap_roi: int = 128, seg_len: int = 64, far_dom: int = 0,
-                        far_roi: int = 512):
+                        far_roi: int = 256):
         """Records a tile composites before the rest of its list may be split
         into segments (dominant / full renders, ROI patch; 0 = never), the
         segment length, and the extrapolated walk a pixel must still have for
