@@ -1,0 +1,72 @@
+/* Learned gap/edge repair of the affiliated eye: a small convolutional
+ * network that fills the holes the forward reprojection leaves (the
+ * disocclusions and cracks of Sec. 3.4-3.5), as an alternative to gap
+ * interpolation plus ROI re-rendering.  Inference and training run on the
+ * GPU: 3x3 convolutions as implicit GEMMs on bf16 MFMA with fp32
+ * accumulation, Adam in fp32.
+ *
+ * Network (three-level U-Net, every 3x3 convolution zero-padded, ReLU
+ * after all but the last):
+ *   level 1 (H x W):      e1a 5->16, e1b 16->16
+ *   level 2 (H/2 x W/2):  e2a 16->32, e2b 32->32   input: 2x2 mean pool of e1b
+ *   level 3 (H/4 x W/4):  e3a 32->64, e3b 64->64   input: 2x2 mean pool of e2b
+ *   level 2:              d2 96->32                 input: [nearest 2x upsample of e3b, e2b]
+ *   level 1:              d1 48->16                 input: [upsample of d2, e1b]
+ *   level 1:              out 16->3, no activation
+ * Inputs per pixel: warped RGB (zeroed at holes), hole mask, 1/z (0 at
+ * holes and for infinite depth).  Output: rgb_out = rgb + hole * r, so only
+ * holes change.  Training loss: sum over hole pixels and channels of
+ * (rgb_out - target)^2 / (3 max(1, holes)).
+ *
+ * Parameters: one flat fp32 device array, per layer in the order above
+ * W[cout][cin][3][3] then b[cout] (bgs_repair_num_params elements).
+ * Activations and weights are held in bfloat16 (round to nearest even),
+ * accumulations in fp32.
+ *
+ * Images: rgb and target [B][3][H][W] fp32, z [B][H][W] fp32, hole
+ * [B][H][W] u8 (nonzero = hole), all device pointers, planar and dense.
+ * H and W must be positive multiples of 4.  All calls are asynchronous on
+ * the given HIP stream (null: the default stream); device buffers belong
+ * to the caller.  Errors: BGS_ERR_INVALID_ARG for a bad size or a null
+ * pointer, BGS_ERR_WORKSPACE for a workspace smaller than
+ * bgs_repair_workspace_size, BGS_ERR_HIP for a failed launch; nothing is
+ * launched on an argument error. */
+#ifndef BGS_REPAIR_H
+#define BGS_REPAIR_H
+
+#include "bgs.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+BGS_API int32_t bgs_repair_num_params(int64_t* n);
+
+/* Workspace bytes for a batch of B images of H x W; train = 1 adds the
+ * gradient buffers that bgs_repair_grad needs.  Allocate 256-byte aligned. */
+BGS_API int32_t bgs_repair_workspace_size(int32_t batch, int32_t height, int32_t width, int32_t train,
+                                          size_t* bytes);
+
+/* Inference: rgb_out [B][3][H][W] = rgb + hole * r. */
+BGS_API int32_t bgs_repair_forward(const float* params, int32_t batch, int32_t height, int32_t width,
+                                   const float* rgb, const float* z, const uint8_t* hole, float* rgb_out,
+                                   void* ws, size_t ws_bytes, void* hip_stream);
+
+/* Forward and backward pass: loss (one device float) and the gradient of
+ * the loss in the parameter layout (grad, device, overwritten).  rgb_out
+ * may be null. */
+BGS_API int32_t bgs_repair_grad(const float* params, int32_t batch, int32_t height, int32_t width,
+                                const float* rgb, const float* z, const uint8_t* hole, const float* target,
+                                float* grad, float* loss, float* rgb_out, void* ws, size_t ws_bytes,
+                                void* hip_stream);
+
+/* One Adam step (Kingma and Ba, 2015) over n parameters, step >= 1 the
+ * 1-based step count used for the bias correction; params, m and v are
+ * updated in place (fp32). */
+BGS_API int32_t bgs_repair_adam(float* params, const float* grad, float* m, float* v, int64_t n, int32_t step,
+                                float lr, float beta1, float beta2, float eps, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

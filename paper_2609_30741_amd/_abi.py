@@ -60,6 +60,9 @@ EXPORTS = [
     "bgs_patch_rois", "bgs_render_stereo", "bgs_sort_workspace_size", "bgs_sort_pairs",
     "bgs_label_components", "bgs_preprocess_debug", "bgs_tile_lists_debug", "bgs_ctx_set_count_pairs",
     "bgs_ctx_set_timing", "bgs_timing_collect", "bgs_blend_trace", "bgs_ctx_set_blend_split",
+    # include/bgs_repair.h
+    "bgs_repair_num_params", "bgs_repair_workspace_size", "bgs_repair_forward", "bgs_repair_grad",
+    "bgs_repair_adam",
 ]
 
 _lib = None
@@ -102,6 +105,11 @@ def load():
         "bgs_preprocess_debug": [P, C.POINTER(Scene), C.POINTER(Camera), C.POINTER(RasterParams), P, SZ, P, P, P],
         "bgs_tile_lists_debug": [P, C.POINTER(Scene), C.POINTER(Camera), C.POINTER(RasterParams), P, SZ, P, P, I64,
                                  C.POINTER(I64)],
+        "bgs_repair_num_params": [C.POINTER(I64)],
+        "bgs_repair_workspace_size": [I32, I32, I32, I32, C.POINTER(SZ)],
+        "bgs_repair_forward": [P, I32, I32, I32, P, P, P, P, P, SZ, P],
+        "bgs_repair_grad": [P, I32, I32, I32, P, P, P, P, P, P, P, P, SZ, P],
+        "bgs_repair_adam": [P, P, P, P, I64, I32, C.c_float, C.c_float, C.c_float, C.c_float, P],
     }
     for name, args in sig.items():
         f = getattr(L, name)

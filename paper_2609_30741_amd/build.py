@@ -34,6 +34,7 @@ SOURCES = {
     "raster.hip": [],
     "warp.hip": ["-ffp-contract=off"],
     "bgs_api.hip": ["-ffp-contract=off"],
+    "repair.hip": [],
 }
 
 

@@ -1,0 +1,672 @@
+// Learned gap/edge repair network: inference and training kernels.
+//
+// 3x3 convolutions run as implicit GEMMs on the bf16 matrix cores
+// (v_mfma_f32_16x16x16_bf16, fp32 accumulate).  Forward: rows of the GEMM
+// are output channels (weights, packed [cout16][cin*9 padded to 16]),
+// columns are 16 consecutive pixels of one image row, the reduction runs
+// over (input channel, tap).  The input-gradient pass is the same kernel
+// with the weights transposed and flipped.  The weight gradient is a GEMM
+// over pixels: each block accumulates a slab of rows into per-block
+// partials that a second kernel adds in a fixed order, so results are
+// deterministic.  Activations and gradients between layers are stored as
+// bf16 planes [B][C][H][W]; a layer may read or write a channel slice of a
+// larger tensor (per-image stride), which is how the skip connections land
+// in the decoder's concatenated inputs without copies.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+
+#include "bgs_repair.h"
+
+namespace {
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+struct LayerDef {
+    int cin, cout, relu;
+};
+// e1a e1b e2a e2b e3a e3b d2 d1 out
+constexpr int kLayers = 9;
+constexpr LayerDef kNet[kLayers] = {{5, 16, 1},  {16, 16, 1}, {16, 32, 1}, {32, 32, 1}, {32, 64, 1},
+                                    {64, 64, 1}, {96, 32, 1}, {48, 16, 1}, {16, 3, 0}};
+enum { E1A, E1B, E2A, E2B, E3A, E3B, D2, D1, OUT };
+
+constexpr int pad16(int v) { return (v + 15) & ~15; }
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    // Round to nearest even (values are finite).
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// ---------------------------------------------------------------------------
+// Convolution (forward, or input gradient with transposed weights).
+// ---------------------------------------------------------------------------
+struct ConvArgs {
+    const uint16_t* in;
+    int64_t in_bs;
+    int cin;
+    const uint16_t* w;  // [pad16(cout)][kpad] bf16
+    int kpad;
+    const float* bias;  // may be null
+    int cout;
+    uint16_t* out;      // bf16 output, or
+    float* out_f;       // fp32 output (exactly one is set)
+    int64_t out_bs;
+    const uint16_t* mask;  // may be null: output zero where mask <= 0
+    int64_t mask_bs;
+    int relu;
+    int H, W;
+};
+
+// Block: 4 waves, each 16 pixels of row blockIdx.y, x from
+// blockIdx.x * 64 + 16 * wave; blockIdx.z = image * groups + group, a group
+// being up to 64 output channels (four 16-row tiles).
+__global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int groups = (a.cout + 63) >> 6;
+    const int y = blockIdx.y, b = blockIdx.z / groups, m0 = (blockIdx.z - b * groups) * 4;
+    const int x0 = blockIdx.x * 64 + wave * 16;
+    if (x0 >= a.W) return;  // whole wave: no block-wide synchronisation follows
+    const int HW = a.H * a.W;
+    const int n = lane & 15, kq = (lane >> 4) * 4;
+    const int x = x0 + n;
+    const uint16_t* inb = a.in + (int64_t)b * a.in_bs;
+    const int K = a.cin * 9;
+    const int mt = min(4, ((a.cout + 15) >> 4) - m0);
+    v4f acc[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) acc[m] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int kc = 0; kc < a.kpad; kc += 16) {
+        v4s bv;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = kc + kq + j;
+            uint16_t v = 0;
+            if (k < K) {
+                const int ci = k / 9, t = k - ci * 9;
+                const int ky = t / 3, kx = t - ky * 3;
+                const int yy = y + ky - 1, xx = x + kx - 1;
+                if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W) v = inb[(int64_t)ci * HW + yy * a.W + xx];
+            }
+            bv[j] = (short)v;
+        }
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            if (m < mt) {
+                const uint2 wv =
+                    *reinterpret_cast<const uint2*>(a.w + (size_t)((m0 + m) * 16 + n) * a.kpad + kc + kq);
+                v4s av;
+                av[0] = (short)(wv.x & 0xFFFFu);
+                av[1] = (short)(wv.x >> 16);
+                av[2] = (short)(wv.y & 0xFFFFu);
+                av[3] = (short)(wv.y >> 16);
+                acc[m] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[m], 0, 0, 0);
+            }
+        }
+    }
+    if (x >= a.W) return;
+    // Lane holds output channels (m0 + m) * 16 + kq + j of pixel column n.
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        if (m >= mt) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int co = (m0 + m) * 16 + kq + j;
+            if (co >= a.cout) continue;
+            float v = acc[m][j] + (a.bias ? a.bias[co] : 0.f);
+            if (a.relu) v = fmaxf(v, 0.f);
+            const int64_t p = (int64_t)co * HW + (int64_t)y * a.W + x;
+            if (a.mask && !(bf2f(a.mask[(int64_t)b * a.mask_bs + p]) > 0.f)) v = 0.f;
+            if (a.out_f)
+                a.out_f[(int64_t)b * a.out_bs + p] = v;
+            else
+                a.out[(int64_t)b * a.out_bs + p] = f2bf(v);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient: part[chunk][co][ci * 9 + tap] = sum over the chunk's
+// pixels of g[co, p] * in[ci, p + tap offset].  Block: 4 waves, one
+// 16-column tile of (ci, tap) each; blockIdx.y: chunk of image rows.
+// ---------------------------------------------------------------------------
+struct WgradArgs {
+    const uint16_t* g;
+    int64_t g_bs;
+    int cout;
+    const uint16_t* in;
+    int64_t in_bs;
+    int cin;
+    int B, H, W;
+    int rows;  // image rows (over the whole batch) per chunk
+    float* part;
+};
+
+__global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int K = a.cin * 9;
+    const int nt = blockIdx.x * 4 + wave;
+    if (nt * 16 >= K) return;  // whole wave
+    const int n = lane & 15, kq = (lane >> 4) * 4;
+    const int col = nt * 16 + n;
+    const bool col_ok = col < K;
+    const int ci = col_ok ? col / 9 : 0, t = col - ci * 9;
+    const int ky = t / 3, kx = t - ky * 3;
+    const int HW = a.H * a.W;
+    const int mt = (a.cout + 15) >> 4;
+    v4f acc[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) acc[m] = v4f{0.f, 0.f, 0.f, 0.f};
+    const int r0 = blockIdx.y * a.rows, r1 = min(r0 + a.rows, a.B * a.H);
+    for (int r = r0; r < r1; ++r) {
+        const int b = r / a.H, y = r - b * a.H;
+        const uint16_t* gb = a.g + (int64_t)b * a.g_bs + (int64_t)y * a.W;
+        const uint16_t* ib = a.in + (int64_t)b * a.in_bs + (int64_t)ci * HW;
+        const int yy = y + ky - 1;
+        const bool row_ok = col_ok && yy >= 0 && yy < a.H;
+        for (int xb = 0; xb < a.W; xb += 16) {
+            v4s bv;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int xx = xb + kq + j + kx - 1;
+                const bool ok = row_ok && xb + kq + j < a.W && xx >= 0 && xx < a.W;
+                bv[j] = (short)(ok ? ib[(int64_t)yy * a.W + xx] : (uint16_t)0);
+            }
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                if (m < mt) {
+                    const int co = m * 16 + n;
+                    v4s av;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int xp = xb + kq + j;
+                        av[j] = (short)((co < a.cout && xp < a.W) ? gb[(int64_t)co * HW + xp] : (uint16_t)0);
+                    }
+                    acc[m] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[m], 0, 0, 0);
+                }
+            }
+        }
+    }
+    if (!col_ok) return;
+    float* pb = a.part + (size_t)blockIdx.y * a.cout * K;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        if (m >= mt) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int co = m * 16 + kq + j;
+            if (co < a.cout) pb[(size_t)co * K + col] = acc[m][j];
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ part, int chunks, int64_t n,
+                                                      float* __restrict__ grad) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.f;
+    for (int c = 0; c < chunks; ++c) s += part[(size_t)c * n + i];
+    grad[i] = s;
+}
+
+__device__ __forceinline__ float block_sum(float v, float* red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const float s = (red[0] + red[1]) + (red[2] + red[3]);
+    __syncthreads();
+    return s;
+}
+
+// Bias gradient: one block per output channel.
+__global__ __launch_bounds__(256) void k_bgrad(const uint16_t* __restrict__ g, int64_t g_bs, int B, int HW,
+                                               float* __restrict__ grad) {
+    __shared__ float red[4];
+    const int co = blockIdx.x;
+    float s = 0.f;
+    for (int b = 0; b < B; ++b) {
+        const uint16_t* gb = g + (int64_t)b * g_bs + (int64_t)co * HW;
+        for (int p = threadIdx.x; p < HW; p += 256) s += bf2f(gb[p]);
+    }
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) grad[co] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Weight packing (fp32 master -> bf16 GEMM operands), pooling, upsampling,
+// gradient merges, input assembly, output and loss.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_pack(const float* __restrict__ w, int cin, int cout, int transpose,
+                                              int mpad, int kpad, uint16_t* __restrict__ out) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= mpad * kpad) return;
+    const int m = i / kpad, k = i - m * kpad;
+    float v = 0.f;
+    if (!transpose) {
+        if (m < cout && k < cin * 9) v = w[m * cin * 9 + k];
+    } else {
+        // Row = input channel, column = (output channel, flipped tap).
+        if (m < cin && k < cout * 9) {
+            const int co = k / 9, t = k - co * 9;
+            v = w[(co * cin + m) * 9 + (8 - t)];
+        }
+    }
+    out[i] = f2bf(v);
+}
+
+__global__ __launch_bounds__(256) void k_pool(const uint16_t* __restrict__ in, int64_t in_bs, int C, int H, int W,
+                                              uint16_t* __restrict__ out, int B) {
+    const int h = H / 2, w = W / 2;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)B * C * h * w) return;
+    const int X = (int)(i % w), Y = (int)((i / w) % h);
+    const int64_t bc = i / ((int64_t)w * h);
+    const int c = (int)(bc % C), b = (int)(bc / C);
+    const uint16_t* p = in + (int64_t)b * in_bs + (int64_t)c * H * W + (int64_t)(2 * Y) * W + 2 * X;
+    const float s = ((bf2f(p[0]) + bf2f(p[1])) + bf2f(p[W])) + bf2f(p[W + 1]);
+    out[i] = f2bf(0.25f * s);
+}
+
+// Nearest 2x upsample of [B][C][h][w] into a slice of a larger tensor.
+__global__ __launch_bounds__(256) void k_up(const uint16_t* __restrict__ in, int C, int h, int w,
+                                            uint16_t* __restrict__ out, int64_t out_bs, int B) {
+    const int H = 2 * h, W = 2 * w;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)B * C * H * W) return;
+    const int x = (int)(i % W), y = (int)((i / W) % H);
+    const int64_t bc = i / ((int64_t)W * H);
+    const int c = (int)(bc % C), b = (int)(bc / C);
+    out[(int64_t)b * out_bs + (int64_t)c * H * W + (int64_t)y * W + x] =
+        in[((int64_t)b * C + c) * h * w + (int64_t)(y / 2) * w + x / 2];
+}
+
+// Gradient of the upsample: sum of each 2x2 block of a slice, masked by the
+// activation (ReLU derivative).
+__global__ __launch_bounds__(256) void k_up_grad(const uint16_t* __restrict__ g, int64_t g_bs, int C, int H, int W,
+                                                 const uint16_t* __restrict__ act, uint16_t* __restrict__ out,
+                                                 int B) {
+    const int h = H / 2, w = W / 2;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)B * C * h * w) return;
+    const int X = (int)(i % w), Y = (int)((i / w) % h);
+    const int64_t bc = i / ((int64_t)w * h);
+    const int c = (int)(bc % C), b = (int)(bc / C);
+    const uint16_t* p = g + (int64_t)b * g_bs + (int64_t)c * H * W + (int64_t)(2 * Y) * W + 2 * X;
+    const float s = ((bf2f(p[0]) + bf2f(p[1])) + bf2f(p[W])) + bf2f(p[W + 1]);
+    out[i] = bf2f(act[i]) > 0.f ? f2bf(s) : (uint16_t)0;
+}
+
+// Gradient reaching an encoder activation from its skip connection (a
+// slice of the decoder input's gradient) and from the pool below it,
+// masked by the activation.
+__global__ __launch_bounds__(256) void k_merge(const uint16_t* __restrict__ skip, int64_t skip_bs,
+                                               const uint16_t* __restrict__ pg, const uint16_t* __restrict__ act,
+                                               int64_t act_bs, int C, int H, int W, uint16_t* __restrict__ out,
+                                               int B) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)B * C * H * W) return;
+    const int x = (int)(i % W), y = (int)((i / W) % H);
+    const int64_t bc = i / ((int64_t)W * H);
+    const int c = (int)(bc % C), b = (int)(bc / C);
+    const int64_t off = (int64_t)c * H * W + (int64_t)y * W + x;
+    const float s = bf2f(skip[(int64_t)b * skip_bs + off]) +
+                    0.25f * bf2f(pg[((int64_t)b * C + c) * (H / 2) * (W / 2) + (int64_t)(y / 2) * (W / 2) + x / 2]);
+    out[i] = bf2f(act[(int64_t)b * act_bs + off]) > 0.f ? f2bf(s) : (uint16_t)0;
+}
+
+__global__ __launch_bounds__(256) void k_input(const float* __restrict__ rgb, const float* __restrict__ z,
+                                               const uint8_t* __restrict__ hole, int B, int HW,
+                                               uint16_t* __restrict__ x0) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)B * HW) return;
+    const int64_t b = i / HW, p = i - b * HW;
+    const bool h = hole[i] != 0;
+    const float zz = z[i];
+    uint16_t* o = x0 + b * 5 * HW + p;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) o[(int64_t)c * HW] = h ? (uint16_t)0 : f2bf(rgb[(b * 3 + c) * HW + p]);
+    o[3 * (int64_t)HW] = h ? f2bf(1.f) : (uint16_t)0;
+    o[4 * (int64_t)HW] = (h || !(zz < INFINITY)) ? (uint16_t)0 : f2bf(1.f / zz);
+}
+
+__global__ __launch_bounds__(256) void k_output(const float* __restrict__ rgb, const uint8_t* __restrict__ hole,
+                                                const float* __restrict__ r, int B, int HW,
+                                                float* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)B * 3 * HW) return;
+    const int64_t p = i % HW, b = i / (3 * (int64_t)HW);
+    out[i] = hole[b * HW + p] ? rgb[i] + r[i] : rgb[i];
+}
+
+// Per-block hole counts.
+__global__ __launch_bounds__(256) void k_count(const uint8_t* __restrict__ hole, int64_t n, float* __restrict__ part) {
+    __shared__ float red[4];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const float c = (i < n && hole[i]) ? 1.f : 0.f;
+    const float s = block_sum(c, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// One block: out[0] = scale * sum of part[0, n) (fixed order per thread,
+// then the block tree).
+__global__ __launch_bounds__(256) void k_sum(const float* __restrict__ part, int n, const float* __restrict__ div,
+                                             float* __restrict__ out) {
+    __shared__ float red[4];
+    float s = 0.f;
+    for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) out[0] = div ? s / (3.f * fmaxf(div[0], 1.f)) : s;
+}
+
+// Masked squared error: per-block partial sums of (pred - target)^2 over
+// hole pixels, and the gradient with respect to r (bf16).
+__global__ __launch_bounds__(256) void k_loss(const float* __restrict__ rgb, const uint8_t* __restrict__ hole,
+                                              const float* __restrict__ r, const float* __restrict__ target,
+                                              const float* __restrict__ n_hole, int B, int HW,
+                                              float* __restrict__ rgb_out, uint16_t* __restrict__ g_r,
+                                              float* __restrict__ part) {
+    __shared__ float red[4];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    float e = 0.f;
+    if (i < (int64_t)B * 3 * HW) {
+        const int64_t p = i % HW, b = i / (3 * (int64_t)HW);
+        const bool h = hole[b * HW + p] != 0;
+        const float pred = h ? rgb[i] + r[i] : rgb[i];
+        const float d = h ? pred - target[i] : 0.f;
+        e = d * d;
+        g_r[i] = f2bf(2.f * d / (3.f * fmaxf(n_hole[0], 1.f)));
+        if (rgb_out) rgb_out[i] = pred;
+    }
+    const float s = block_sum(e, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_adam(float* __restrict__ w, const float* __restrict__ g,
+                                              float* __restrict__ m, float* __restrict__ v, int64_t n, float lr,
+                                              float b1, float b2, float eps, float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// ---------------------------------------------------------------------------
+// Host side: parameter offsets, workspace layout, launch sequences.
+// ---------------------------------------------------------------------------
+int64_t param_offset(int l) {
+    int64_t o = 0;
+    for (int i = 0; i < l; ++i) o += (int64_t)kNet[i].cout * kNet[i].cin * 9 + kNet[i].cout;
+    return o;
+}
+
+struct Layout {
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) & ~(size_t)255;
+        return o;
+    }
+};
+
+struct Bufs {
+    uint16_t *x0, *e1a, *cat1, *p1, *e2a, *cat2, *p2, *e3a, *e3b, *d2, *d1;
+    float* r;
+    uint16_t* wf[kLayers];
+    uint16_t* wb[kLayers];
+    // training
+    uint16_t *g_r, *g_d1, *g_cat1, *g_d2, *g_cat2, *g_e3b, *g_e3a, *g_p2, *g_e2b, *g_e2a, *g_p1, *g_e1b, *g_e1a;
+    float *part, *cnt_part, *loss_part, *n_hole;
+    int chunks1, chunks2, chunks3;
+    size_t bytes;
+};
+
+int chunk_rows(int rows) { return std::max(1, (rows + 127) / 128); }
+
+Bufs layout(int B, int H, int W, bool train, char* base) {
+    Layout L;
+    Bufs f{};
+    const size_t h1 = (size_t)H * W, h2 = h1 / 4, h3 = h1 / 16;
+    auto bf = [&](size_t elems) { return (uint16_t*)(base + L.take(elems * 2)); };
+    auto fl = [&](size_t elems) { return (float*)(base + L.take(elems * 4)); };
+    f.x0 = bf(B * 5 * h1);
+    f.e1a = bf(B * 16 * h1);
+    f.cat1 = bf(B * 48 * h1);
+    f.p1 = bf(B * 16 * h2);
+    f.e2a = bf(B * 32 * h2);
+    f.cat2 = bf(B * 96 * h2);
+    f.p2 = bf(B * 32 * h3);
+    f.e3a = bf(B * 64 * h3);
+    f.e3b = bf(B * 64 * h3);
+    f.d2 = bf(B * 32 * h2);
+    f.d1 = bf(B * 16 * h1);
+    f.r = fl(B * 3 * h1);
+    for (int l = 0; l < kLayers; ++l) {
+        f.wf[l] = bf((size_t)pad16(kNet[l].cout) * pad16(kNet[l].cin * 9));
+        f.wb[l] = bf((size_t)pad16(kNet[l].cin) * pad16(kNet[l].cout * 9));
+    }
+    const int64_t n3 = (int64_t)B * 3 * h1;
+    f.cnt_part = fl((B * h1 + 255) / 256);
+    f.loss_part = fl((n3 + 255) / 256);
+    f.n_hole = fl(1);
+    if (train) {
+        f.g_r = bf(B * 3 * h1);
+        f.g_d1 = bf(B * 16 * h1);
+        f.g_cat1 = bf(B * 48 * h1);
+        f.g_d2 = bf(B * 32 * h2);
+        f.g_cat2 = bf(B * 96 * h2);
+        f.g_e3b = bf(B * 64 * h3);
+        f.g_e3a = bf(B * 64 * h3);
+        f.g_p2 = bf(B * 32 * h3);
+        f.g_e2b = bf(B * 32 * h2);
+        f.g_e2a = bf(B * 32 * h2);
+        f.g_p1 = bf(B * 16 * h2);
+        f.g_e1b = bf(B * 16 * h1);
+        f.g_e1a = bf(B * 16 * h1);
+        const int rows1 = B * H, rows2 = B * H / 2, rows3 = B * H / 4;
+        f.chunks1 = (rows1 + chunk_rows(rows1) - 1) / chunk_rows(rows1);
+        f.chunks2 = (rows2 + chunk_rows(rows2) - 1) / chunk_rows(rows2);
+        f.chunks3 = (rows3 + chunk_rows(rows3) - 1) / chunk_rows(rows3);
+        size_t mx = 0;
+        const int lvl[kLayers] = {1, 1, 2, 2, 3, 3, 2, 1, 1};
+        for (int l = 0; l < kLayers; ++l) {
+            const int ch = lvl[l] == 1 ? f.chunks1 : lvl[l] == 2 ? f.chunks2 : f.chunks3;
+            mx = std::max(mx, (size_t)ch * kNet[l].cout * kNet[l].cin * 9);
+        }
+        f.part = fl(mx);
+    }
+    f.bytes = L.off;
+    return f;
+}
+
+inline unsigned blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+void conv(hipStream_t s, int B, int H, int W, int l, bool transpose, const Bufs& f, const uint16_t* in,
+          int64_t in_bs, const float* params, uint16_t* out, float* out_f, int64_t out_bs, const uint16_t* mask,
+          int64_t mask_bs) {
+    ConvArgs a{};
+    a.in = in;
+    a.in_bs = in_bs;
+    a.cin = transpose ? kNet[l].cout : kNet[l].cin;
+    a.cout = transpose ? kNet[l].cin : kNet[l].cout;
+    a.w = transpose ? f.wb[l] : f.wf[l];
+    a.kpad = pad16(a.cin * 9);
+    a.bias = transpose ? nullptr : params + param_offset(l) + (int64_t)kNet[l].cout * kNet[l].cin * 9;
+    a.out = out;
+    a.out_f = out_f;
+    a.out_bs = out_bs;
+    a.mask = mask;
+    a.mask_bs = mask_bs;
+    a.relu = transpose ? 0 : kNet[l].relu;
+    a.H = H;
+    a.W = W;
+    hipLaunchKernelGGL(k_conv3x3, dim3((W + 63) / 64, H, B * ((a.cout + 63) / 64)), dim3(256), 0, s, a);
+}
+
+void wgrad(hipStream_t s, int B, int H, int W, int l, const Bufs& f, const uint16_t* g, int64_t g_bs,
+           const uint16_t* in, int64_t in_bs, int chunks, float* grad) {
+    WgradArgs a{};
+    a.g = g;
+    a.g_bs = g_bs;
+    a.cout = kNet[l].cout;
+    a.in = in;
+    a.in_bs = in_bs;
+    a.cin = kNet[l].cin;
+    a.B = B;
+    a.H = H;
+    a.W = W;
+    a.rows = chunk_rows(B * H);
+    a.part = f.part;
+    const int nt = (a.cin * 9 + 15) / 16;
+    hipLaunchKernelGGL(k_wgrad, dim3((nt + 3) / 4, chunks), dim3(256), 0, s, a);
+    const int64_t nw = (int64_t)a.cout * a.cin * 9;
+    float* gl = grad + param_offset(l);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(nw)), dim3(256), 0, s, (const float*)f.part, chunks, nw, gl);
+    hipLaunchKernelGGL(k_bgrad, dim3(a.cout), dim3(256), 0, s, g, g_bs, B, H * W, gl + nw);
+}
+
+void forward(hipStream_t s, int B, int H, int W, const float* params, const float* rgb, const float* z,
+             const uint8_t* hole, const Bufs& f) {
+    for (int l = 0; l < kLayers; ++l) {
+        const float* w = params + param_offset(l);
+        const int ci = kNet[l].cin, co = kNet[l].cout;
+        hipLaunchKernelGGL(k_pack, dim3(blocks((int64_t)pad16(co) * pad16(ci * 9))), dim3(256), 0, s, w, ci, co, 0,
+                           pad16(co), pad16(ci * 9), f.wf[l]);
+        hipLaunchKernelGGL(k_pack, dim3(blocks((int64_t)pad16(ci) * pad16(co * 9))), dim3(256), 0, s, w, ci, co, 1,
+                           pad16(ci), pad16(co * 9), f.wb[l]);
+    }
+    const int64_t h1 = (int64_t)H * W, h2 = h1 / 4, h3 = h1 / 16;
+    const int H2 = H / 2, W2 = W / 2, H3 = H / 4, W3 = W / 4;
+    hipLaunchKernelGGL(k_input, dim3(blocks(B * h1)), dim3(256), 0, s, rgb, z, hole, B, (int)h1, f.x0);
+    conv(s, B, H, W, E1A, false, f, f.x0, 5 * h1, params, f.e1a, nullptr, 16 * h1, nullptr, 0);
+    uint16_t* e1b = f.cat1 + 32 * h1;
+    conv(s, B, H, W, E1B, false, f, f.e1a, 16 * h1, params, e1b, nullptr, 48 * h1, nullptr, 0);
+    hipLaunchKernelGGL(k_pool, dim3(blocks(B * 16 * h2)), dim3(256), 0, s, e1b, 48 * h1, 16, H, W, f.p1, B);
+    conv(s, B, H2, W2, E2A, false, f, f.p1, 16 * h2, params, f.e2a, nullptr, 32 * h2, nullptr, 0);
+    uint16_t* e2b = f.cat2 + 64 * h2;
+    conv(s, B, H2, W2, E2B, false, f, f.e2a, 32 * h2, params, e2b, nullptr, 96 * h2, nullptr, 0);
+    hipLaunchKernelGGL(k_pool, dim3(blocks(B * 32 * h3)), dim3(256), 0, s, e2b, 96 * h2, 32, H2, W2, f.p2, B);
+    conv(s, B, H3, W3, E3A, false, f, f.p2, 32 * h3, params, f.e3a, nullptr, 64 * h3, nullptr, 0);
+    conv(s, B, H3, W3, E3B, false, f, f.e3a, 64 * h3, params, f.e3b, nullptr, 64 * h3, nullptr, 0);
+    hipLaunchKernelGGL(k_up, dim3(blocks(B * 64 * h2)), dim3(256), 0, s, f.e3b, 64, H3, W3, f.cat2, 96 * h2, B);
+    conv(s, B, H2, W2, D2, false, f, f.cat2, 96 * h2, params, f.d2, nullptr, 32 * h2, nullptr, 0);
+    hipLaunchKernelGGL(k_up, dim3(blocks(B * 32 * h1)), dim3(256), 0, s, f.d2, 32, H2, W2, f.cat1, 48 * h1, B);
+    conv(s, B, H, W, D1, false, f, f.cat1, 48 * h1, params, f.d1, nullptr, 16 * h1, nullptr, 0);
+    conv(s, B, H, W, OUT, false, f, f.d1, 16 * h1, params, nullptr, f.r, 3 * h1, nullptr, 0);
+}
+
+void backward(hipStream_t s, int B, int H, int W, const float* params, const Bufs& f, float* grad) {
+    const int64_t h1 = (int64_t)H * W, h2 = h1 / 4, h3 = h1 / 16;
+    const int H2 = H / 2, W2 = W / 2, H3 = H / 4, W3 = W / 4;
+    uint16_t* e1b = f.cat1 + 32 * h1;
+    uint16_t* e2b = f.cat2 + 64 * h2;
+    wgrad(s, B, H, W, OUT, f, f.g_r, 3 * h1, f.d1, 16 * h1, f.chunks1, grad);
+    conv(s, B, H, W, OUT, true, f, f.g_r, 3 * h1, params, f.g_d1, nullptr, 16 * h1, f.d1, 16 * h1);
+    wgrad(s, B, H, W, D1, f, f.g_d1, 16 * h1, f.cat1, 48 * h1, f.chunks1, grad);
+    conv(s, B, H, W, D1, true, f, f.g_d1, 16 * h1, params, f.g_cat1, nullptr, 48 * h1, nullptr, 0);
+    hipLaunchKernelGGL(k_up_grad, dim3(blocks(B * 32 * h2)), dim3(256), 0, s, f.g_cat1, 48 * h1, 32, H, W, f.d2,
+                       f.g_d2, B);
+    wgrad(s, B, H2, W2, D2, f, f.g_d2, 32 * h2, f.cat2, 96 * h2, f.chunks2, grad);
+    conv(s, B, H2, W2, D2, true, f, f.g_d2, 32 * h2, params, f.g_cat2, nullptr, 96 * h2, nullptr, 0);
+    hipLaunchKernelGGL(k_up_grad, dim3(blocks(B * 64 * h3)), dim3(256), 0, s, f.g_cat2, 96 * h2, 64, H2, W2, f.e3b,
+                       f.g_e3b, B);
+    wgrad(s, B, H3, W3, E3B, f, f.g_e3b, 64 * h3, f.e3a, 64 * h3, f.chunks3, grad);
+    conv(s, B, H3, W3, E3B, true, f, f.g_e3b, 64 * h3, params, f.g_e3a, nullptr, 64 * h3, f.e3a, 64 * h3);
+    wgrad(s, B, H3, W3, E3A, f, f.g_e3a, 64 * h3, f.p2, 32 * h3, f.chunks3, grad);
+    conv(s, B, H3, W3, E3A, true, f, f.g_e3a, 64 * h3, params, f.g_p2, nullptr, 32 * h3, nullptr, 0);
+    hipLaunchKernelGGL(k_merge, dim3(blocks(B * 32 * h2)), dim3(256), 0, s, f.g_cat2 + 64 * h2, 96 * h2, f.g_p2, e2b,
+                       96 * h2, 32, H2, W2, f.g_e2b, B);
+    wgrad(s, B, H2, W2, E2B, f, f.g_e2b, 32 * h2, f.e2a, 32 * h2, f.chunks2, grad);
+    conv(s, B, H2, W2, E2B, true, f, f.g_e2b, 32 * h2, params, f.g_e2a, nullptr, 32 * h2, f.e2a, 32 * h2);
+    wgrad(s, B, H2, W2, E2A, f, f.g_e2a, 32 * h2, f.p1, 16 * h2, f.chunks2, grad);
+    conv(s, B, H2, W2, E2A, true, f, f.g_e2a, 32 * h2, params, f.g_p1, nullptr, 16 * h2, nullptr, 0);
+    hipLaunchKernelGGL(k_merge, dim3(blocks(B * 16 * h1)), dim3(256), 0, s, f.g_cat1 + 32 * h1, 48 * h1, f.g_p1, e1b,
+                       48 * h1, 16, H, W, f.g_e1b, B);
+    wgrad(s, B, H, W, E1B, f, f.g_e1b, 16 * h1, f.e1a, 16 * h1, f.chunks1, grad);
+    conv(s, B, H, W, E1B, true, f, f.g_e1b, 16 * h1, params, f.g_e1a, nullptr, 16 * h1, f.e1a, 16 * h1);
+    wgrad(s, B, H, W, E1A, f, f.g_e1a, 16 * h1, f.x0, 5 * h1, f.chunks1, grad);
+}
+
+bool sizes_ok(int B, int H, int W) { return B >= 1 && H >= 4 && W >= 4 && H % 4 == 0 && W % 4 == 0 && H <= 8192 && W <= 8192; }
+
+int32_t launched() { return hipGetLastError() == hipSuccess ? BGS_OK : BGS_ERR_HIP; }
+
+}  // namespace
+
+extern "C" {
+
+BGS_API int32_t bgs_repair_num_params(int64_t* n) {
+    if (!n) return BGS_ERR_INVALID_ARG;
+    *n = param_offset(kLayers);
+    return BGS_OK;
+}
+
+BGS_API int32_t bgs_repair_workspace_size(int32_t batch, int32_t height, int32_t width, int32_t train, size_t* bytes) {
+    if (!bytes || !sizes_ok(batch, height, width) || (train != 0 && train != 1)) return BGS_ERR_INVALID_ARG;
+    *bytes = layout(batch, height, width, train != 0, nullptr).bytes;
+    return BGS_OK;
+}
+
+BGS_API int32_t bgs_repair_forward(const float* params, int32_t batch, int32_t height, int32_t width,
+                                   const float* rgb, const float* z, const uint8_t* hole, float* rgb_out, void* ws,
+                                   size_t ws_bytes, void* hip_stream) {
+    if (!params || !rgb || !z || !hole || !rgb_out || !ws || !sizes_ok(batch, height, width))
+        return BGS_ERR_INVALID_ARG;
+    const Bufs f = layout(batch, height, width, false, (char*)ws);
+    if (ws_bytes < f.bytes) return BGS_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)hip_stream;
+    (void)hipGetLastError();
+    forward(s, batch, height, width, params, rgb, z, hole, f);
+    const int64_t n3 = (int64_t)batch * 3 * height * width;
+    hipLaunchKernelGGL(k_output, dim3(blocks(n3)), dim3(256), 0, s, rgb, hole, (const float*)f.r, batch,
+                       height * width, rgb_out);
+    return launched();
+}
+
+BGS_API int32_t bgs_repair_grad(const float* params, int32_t batch, int32_t height, int32_t width, const float* rgb,
+                                const float* z, const uint8_t* hole, const float* target, float* grad, float* loss,
+                                float* rgb_out, void* ws, size_t ws_bytes, void* hip_stream) {
+    if (!params || !rgb || !z || !hole || !target || !grad || !loss || !ws || !sizes_ok(batch, height, width))
+        return BGS_ERR_INVALID_ARG;
+    const Bufs f = layout(batch, height, width, true, (char*)ws);
+    if (ws_bytes < f.bytes) return BGS_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)hip_stream;
+    (void)hipGetLastError();
+    forward(s, batch, height, width, params, rgb, z, hole, f);
+    const int HW = height * width;
+    const int64_t np = (int64_t)batch * HW, n3 = 3 * np;
+    hipLaunchKernelGGL(k_count, dim3(blocks(np)), dim3(256), 0, s, hole, np, f.cnt_part);
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, (const float*)f.cnt_part, (int)blocks(np), (const float*)nullptr,
+                       f.n_hole);
+    hipLaunchKernelGGL(k_loss, dim3(blocks(n3)), dim3(256), 0, s, rgb, hole, (const float*)f.r, target,
+                       (const float*)f.n_hole, batch, HW, rgb_out, f.g_r, f.loss_part);
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, (const float*)f.loss_part, (int)blocks(n3),
+                       (const float*)f.n_hole, loss);
+    backward(s, batch, height, width, params, f, grad);
+    return launched();
+}
+
+BGS_API int32_t bgs_repair_adam(float* params, const float* grad, float* m, float* v, int64_t n, int32_t step,
+                                float lr, float beta1, float beta2, float eps, void* hip_stream) {
+    if (!params || !grad || !m || !v || n < 1 || step < 1 || !(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) ||
+        !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+        return BGS_ERR_INVALID_ARG;
+    const float c1 = (float)(1.0 - std::pow((double)beta1, step));
+    const float c2 = (float)(1.0 - std::pow((double)beta2, step));
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_adam, dim3(blocks(n)), dim3(256), 0, (hipStream_t)hip_stream, params, grad, m, v, n, lr,
+                       beta1, beta2, eps, c1, c2);
+    return launched();
+}
+
+}  // extern "C"

@@ -1,4 +1,4 @@
-"""The C ABI on the CPU: every symbol include/bgs.h declares is exported,
+"""The C ABI on the CPU: every symbol include/*.h declares is exported,
 and argument validation returns the documented status codes before any
 GPU work is launched (no device is touched by these calls)."""
 import ctypes as C
@@ -22,8 +22,12 @@ def L():
 
 
 def declared():
-    text = open(os.path.join(ROOT, "include", "bgs.h")).read()
-    return sorted(set(re.findall(r"BGS_API\s+[\w\s\*]+?\b(bgs_\w+)\s*\(", text)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", h)).read()
+            names |= set(re.findall(r"BGS_API\s+[\w\s\*]+?\b(bgs_\w+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_symbols_exported(L):

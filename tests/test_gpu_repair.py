@@ -1,0 +1,124 @@
+"""GPU parity of the repair network (include/bgs_repair.h) against its CPU
+oracle, through the C ABI, and what training on the GPU buys.
+
+Both sides use the same bf16-rounded weights and inputs and round the
+stored activations and gradients to bf16 at the same points; they differ
+only in the order and precision of accumulation (fp32 matrix cores against
+fp64).  That difference, about K 2^-24 relative for K <= 864 products,
+flips an occasional bf16 rounding (one ulp, 2^-8 relative) that the later
+layers carry on, so whole-network results are compared at 1e-2 of the
+largest magnitude per element and 3e-3 (output) or 2e-2 (gradient, per
+layer) relative in L2, not bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import repair_oracle as R
+from paper_2609_30741_amd import repair
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(seed, B, H, W, hole_frac=0.3):
+    rng = np.random.default_rng(seed)
+    hole = (rng.uniform(size=(B, H, W)) < hole_frac).astype(np.uint8)
+    rgb = (rng.uniform(size=(B, 3, H, W)) * (1 - hole[:, None])).astype(np.float32)
+    z = np.where(hole > 0, np.inf, rng.uniform(1.5, 4.0, size=(B, H, W))).astype(np.float32)
+    z[:, 0, :3] = np.inf  # background pixels that are not holes
+    target = rng.uniform(size=(B, 3, H, W)).astype(np.float32)
+    p = repair.init_params(seed)
+    # A last layer at full scale, so the residual is not tiny.
+    p[-(3 * 16 * 9 + 3):] *= 10.0
+    p += np.float32(0.01) * rng.normal(size=p.size).astype(np.float32) * (np.abs(p) > 0)
+    return p, rgb, z, hole, target
+
+
+def _dev(*xs):
+    return [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in xs]
+
+
+@pytest.mark.parametrize("B,H,W", [(2, 16, 72), (1, 12, 20), (3, 8, 132)])
+def test_forward_matches_oracle(B, H, W):
+    p, rgb, z, hole, target = _problem(1, B, H, W)
+    net = repair.Repair(params=p)
+    g_rgb, g_z, g_hole = _dev(rgb, z, hole)
+    out = net.forward(g_rgb, g_z, g_hole)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    a = R.forward(p.astype(np.float64), rgb, z, hole, q=R.bf16)
+    want = a["pred"]
+    # Non-hole pixels pass through untouched.
+    np.testing.assert_array_equal(got[np.repeat(hole[:, None] == 0, 3, 1)], rgb[np.repeat(hole[:, None] == 0, 3, 1)])
+    r_got = (got - rgb) * hole[:, None]
+    r_want = a["r"] * hole[:, None]
+    scale = np.abs(r_want).max()
+    assert scale > 1e-2
+    assert np.abs(r_got - r_want).max() <= 1e-2 * scale
+    assert np.linalg.norm(r_got - r_want) <= 3e-3 * np.linalg.norm(r_want)
+    np.testing.assert_allclose(got, want, atol=1e-2 * scale)
+
+
+@pytest.mark.parametrize("B,H,W", [(2, 16, 72), (1, 8, 12)])
+def test_gradient_matches_oracle(B, H, W):
+    p, rgb, z, hole, target = _problem(2, B, H, W)
+    net = repair.Repair(params=p)
+    g_rgb, g_z, g_hole, g_t = _dev(rgb, z, hole, target)
+    loss = net.grad_step(g_rgb, g_z, g_hole, g_t)
+    torch.cuda.synchronize()
+    loss_o, grad_o = R.loss_and_grad(p.astype(np.float64), rgb, z, hole, target, q=R.bf16)
+    assert float(loss.item()) == pytest.approx(loss_o, rel=1e-4)
+    g = net.grad.cpu().numpy().astype(np.float64)
+    o = 0
+    for name, ci, co, _ in R.LAYERS:
+        n = co * ci * 9 + co
+        a, b = g[o:o + n], grad_o[o:o + n]
+        o += n
+        assert np.linalg.norm(a - b) <= 2e-2 * np.linalg.norm(b) + 1e-12, name
+        assert np.abs(a - b).max() <= 2e-2 * np.abs(b).max() + 1e-12, name
+
+
+def test_gradient_of_an_all_hole_free_batch_is_zero():
+    # No holes: the loss and every gradient are exactly zero.
+    p, rgb, z, hole, target = _problem(3, 1, 8, 16)
+    hole[:] = 0
+    net = repair.Repair(params=p)
+    g = _dev(rgb, z, hole, target)
+    loss = net.grad_step(*g)
+    torch.cuda.synchronize()
+    assert float(loss.item()) == 0.0
+    assert float(net.grad.abs().max().item()) == 0.0
+
+
+def test_adam_matches_oracle():
+    rng = np.random.default_rng(4)
+    n = repair.num_params()
+    p = rng.normal(size=n).astype(np.float32)
+    net = repair.Repair(params=p)
+    pw, m, v = p.astype(np.float64), np.zeros(n), np.zeros(n)
+    gsum = np.zeros(n)
+    for step in range(1, 4):
+        g = rng.normal(size=n).astype(np.float32) * 10.0 ** rng.integers(-4, 1, size=n).astype(np.float32)
+        net.grad.copy_(torch.from_numpy(g))
+        net.adam(lr=1e-2)
+        # The library takes its hyper-parameters as fp32 (0.999 becomes
+        # 0.99900001, which moves 1 - beta2 by 1.3e-5 relative).
+        f = lambda x: float(np.float32(x))  # noqa: E731
+        pw, m, v = R.adam(pw, g.astype(np.float64), m, v, step, lr=f(1e-2), beta1=f(0.9), beta2=f(0.999),
+                          eps=f(1e-8))
+        gsum += np.abs(g)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(net.params.cpu().numpy(), pw, rtol=1e-5, atol=1e-6)
+    # The first moment may nearly cancel (0.9 m against 0.1 g of the other
+    # sign): its fp32 error is bounded by the terms' size, not the result's.
+    assert np.all(np.abs(net.m.cpu().numpy() - m) <= 1e-6 * gsum + 1e-12)
+    np.testing.assert_allclose(net.v.cpu().numpy(), v, rtol=1e-5, atol=1e-12)
+
+
+def test_rejects_bad_sizes():
+    net = repair.Repair()
+    x = torch.zeros((1, 3, 10, 16), device="cuda")
+    z = torch.zeros((1, 10, 16), device="cuda")
+    h = torch.zeros((1, 10, 16), dtype=torch.uint8, device="cuda")
+    with pytest.raises(Exception):
+        net.forward(x, z, h)  # H not a multiple of 4
