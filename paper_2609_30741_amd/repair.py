@@ -44,6 +44,15 @@ def num_params() -> int:
     return int(n.value)
 
 
+# Pixel count of each layer's level relative to the full image.
+LEVEL_SCALE = [1.0, 1.0, 0.25, 0.25, 1.0 / 16, 1.0 / 16, 0.25, 1.0, 1.0]
+
+
+def flops_per_pixel() -> float:
+    """Multiply-adds (x2) of the nine 3x3 convolutions per full-size pixel."""
+    return sum(2.0 * 9 * ci * co * s for (ci, co), s in zip(LAYERS, LEVEL_SCALE))
+
+
 def init_params(seed: int = 0) -> np.ndarray:
     """He-normal weights (std sqrt(2 / (9 cin))), zero biases; the last
     layer starts at a tenth of that so the first residuals are small."""
@@ -253,9 +262,14 @@ def main(argv=None):
     e1.record()
     torch.cuda.synchronize()
     H, W = p["hole"].shape
+    ms = e0.elapsed_time(e1) / 50
+    tflops = flops_per_pixel() * H * W / (ms * 1e-3) / 1e12
     print(json.dumps({"workload": "sphere800", "width": int(W), "height": int(H), "train_steps": args.steps,
                       "batch": args.batch, "crop": args.crop, "train_s": round(t_train, 2), "losses": losses,
-                      "held_out": res, "infer_ms": round(e0.elapsed_time(e1) / 50, 4)}), flush=True)
+                      "held_out": res, "infer_ms": round(ms, 4),
+                      "roofline": {"bound": "mfma", "achieved": round(tflops, 2), "peak": 2500.0, "unit": "TFLOP/s",
+                                   "frac": round(tflops / 2500.0, 5),
+                                   "flops_per_pixel": flops_per_pixel()}}), flush=True)
     return 0
 
 

@@ -122,3 +122,30 @@ def test_rejects_bad_sizes():
     h = torch.zeros((1, 10, 16), dtype=torch.uint8, device="cuda")
     with pytest.raises(Exception):
         net.forward(x, z, h)  # H not a multiple of 4
+
+
+def test_training_gains_over_interpolation():
+    # Train on pairs the method produces (sphere scene, 300k surfels,
+    # 800x600), then compare on held-out poses, on the holes that the
+    # method's plain fill covers (gap interpolation, row fill with Step 2
+    # off): the trained network must beat that fill by at least 3 dB.
+    from paper_2609_30741_amd import _abi, synth
+    scene, cams, b = synth.WORKLOADS["sphere800"](0)
+    affs = [synth.affiliated(c, b) for c in cams]
+    held = [0, 8]
+    tr = [i for i in range(len(cams)) if i not in held]
+    pairs = repair.make_pairs(scene, [cams[i] for i in tr], [affs[i] for i in tr])
+    test = repair.make_pairs(scene, [cams[i] for i in held], [affs[i] for i in held])
+    net = repair.Repair(seed=0)
+    losses = repair.train(net, pairs, 200, batch=8, size=128, lr=2e-3, seed=0, log=50)
+    assert losses[-1][1] < 0.25 * losses[0][1], losses
+    for i, p in zip(held, test):
+        x = net.forward(p["rgb"][None].contiguous(), p["z"][None].contiguous(), p["hole"][None].contiguous())[0]
+        interp, cls = repair.interpolation_fill(p, cams[i], affs[i])
+        filled = (p["hole"] > 0) & ((cls == _abi.CLS_GAP) | (cls == _abi.CLS_ROWFILL))
+        assert int(filled.sum()) > 1000
+        gain = repair.hole_psnr(x, p["target"], filled) - repair.hole_psnr(interp, p["target"], filled)
+        assert gain >= 3.0, (i, gain)
+        # Pixels outside the holes are the warped image, untouched.
+        keep = p["hole"] == 0
+        assert torch.equal(x[:, keep], p["rgb"][:, keep])
