@@ -25,9 +25,9 @@
  *
  * Images: rgb and target [B][3][H][W] fp32, z [B][H][W] fp32, hole
  * [B][H][W] u8 (nonzero = hole), all device pointers, planar and dense.
- * H and W must be positive multiples of 4.  All calls are asynchronous on
- * the given HIP stream (null: the default stream); device buffers belong
- * to the caller.  Errors: BGS_ERR_INVALID_ARG for a bad size or a null
+ * H and W must be multiples of 4 in [4, 8192], the batch in [1, 1000].
+ * All calls are asynchronous on the given HIP stream (null: the default
+ * stream); device buffers belong to the caller.  Errors: BGS_ERR_INVALID_ARG for a bad size or a null
  * pointer, BGS_ERR_WORKSPACE for a workspace smaller than
  * bgs_repair_workspace_size, BGS_ERR_HIP for a failed launch; nothing is
  * launched on an argument error. */

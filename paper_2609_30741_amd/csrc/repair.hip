@@ -2,9 +2,9 @@
 //
 // 3x3 convolutions run as implicit GEMMs on the bf16 matrix cores
 // (v_mfma_f32_16x16x16_bf16, fp32 accumulate).  Forward: rows of the GEMM
-// are output channels (weights, packed [cout16][cin*9 padded to 16]),
-// columns are 16 consecutive pixels of one image row, the reduction runs
-// over (input channel, tap).  The input-gradient pass is the same kernel
+// are output channels (weights packed [cout padded to 16][9][cin padded to
+// 16]), columns are 16 consecutive pixels of one image row, the reduction
+// runs over (tap, input channel).  The input-gradient pass is the same kernel
 // with the weights transposed and flipped.  The weight gradient is a GEMM
 // over pixels: each block accumulates a slab of rows into per-block
 // partials that a second kernel adds in a fixed order, so results are
@@ -51,8 +51,9 @@ struct ConvArgs {
     const uint16_t* in;
     int64_t in_bs;
     int cin;
-    const uint16_t* w;  // [pad16(cout)][kpad] bf16
+    const uint16_t* w;  // [pad16(cout)][kpad = 9 * cpad] bf16, k = tap * cpad + ci
     int kpad;
+    int cpad;  // pad16(cin)
     const float* bias;  // may be null
     int cout;
     uint16_t* out;      // bf16 output, or
@@ -64,77 +65,126 @@ struct ConvArgs {
     int H, W;
 };
 
-// Block: 4 waves, each 16 pixels of row blockIdx.y, x from
-// blockIdx.x * 64 + 16 * wave; blockIdx.z = image * groups + group, a group
-// being up to 64 output channels (four 16-row tiles).
+// Block: 4 waves, each 16 pixels of rows 2 blockIdx.y and 2 blockIdx.y + 1,
+// x from blockIdx.x * 64 + 16 * wave; blockIdx.z = image * groups + group,
+// a group being up to 64 output channels (four 16-row tiles).  The block
+// first stages input rows 2 blockIdx.y - 1 .. + 2 of every input channel
+// (channels padded to cpad, a multiple of 16, with zeros), x from
+// blockIdx.x * 64 - 1 to + 64 (zero outside the image), in LDS:
+// [cpad][4][66] bf16.  The reduction index is k = tap * cpad + ci, so each
+// 16-deep slice is one tap and 16 channels, a lane's four operands sit at
+// a fixed LDS stride, and one weight operand serves both rows.
+constexpr int kConvCols = 66, kConvRowsOut = 2, kConvRowsIn = kConvRowsOut + 2;
+constexpr int kConvPlane = kConvRowsIn * kConvCols;
+
 __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
+    extern __shared__ uint16_t s_in[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int groups = (a.cout + 63) >> 6;
-    const int y = blockIdx.y, b = blockIdx.z / groups, m0 = (blockIdx.z - b * groups) * 4;
-    const int x0 = blockIdx.x * 64 + wave * 16;
-    if (x0 >= a.W) return;  // whole wave: no block-wide synchronisation follows
+    const int y0 = blockIdx.y * kConvRowsOut, b = blockIdx.z / groups, m0 = (blockIdx.z - b * groups) * 4;
+    const int xb = blockIdx.x * 64;
     const int HW = a.H * a.W;
+    const int cpad = a.cpad;
+    const uint16_t* inb = a.in + (int64_t)b * a.in_bs;
+    // Fill: wave w takes (channel, row) pairs w, w + 4, ...; eight pairs'
+    // loads in flight before their stores.  Lanes cover columns lane and
+    // lane + 64.
+    const int pairs = cpad * kConvRowsIn;
+    const int xa = xb + lane - 1, xc = xb + lane + 63;
+    const bool oka = xa >= 0 && xa < a.W, okc = lane < kConvCols - 64 && xc < a.W;
+    for (int p0 = wave; p0 < pairs; p0 += 32) {
+        uint16_t va[8], vc[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int pr = p0 + 4 * u;
+            const int ci = pr / kConvRowsIn, ry = pr - ci * kConvRowsIn;
+            const int yy = y0 + ry - 1;
+            const bool ok = pr < pairs && ci < a.cin && yy >= 0 && yy < a.H;
+            const uint16_t* src = inb + (int64_t)ci * HW + (int64_t)yy * a.W;
+            va[u] = (ok && oka) ? src[xa] : (uint16_t)0;
+            vc[u] = (ok && okc) ? src[xc] : (uint16_t)0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int pr = p0 + 4 * u;
+            if (pr < pairs) {
+                s_in[pr * kConvCols + lane] = va[u];
+                if (lane < kConvCols - 64) s_in[pr * kConvCols + 64 + lane] = vc[u];
+            }
+        }
+    }
+    __syncthreads();
+    const int x0 = xb + wave * 16;
+    if (x0 >= a.W) return;  // whole wave, after the block's only barrier
     const int n = lane & 15, kq = (lane >> 4) * 4;
     const int x = x0 + n;
-    const uint16_t* inb = a.in + (int64_t)b * a.in_bs;
-    const int K = a.cin * 9;
     const int mt = min(4, ((a.cout + 15) >> 4) - m0);
-    v4f acc[4];
+    const int col = wave * 16 + n;
+    const uint16_t* wl = a.w + (size_t)(m0 * 16 + n) * a.kpad + kq;
+    v4f acc[4][kConvRowsOut];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) acc[m] = v4f{0.f, 0.f, 0.f, 0.f};
-    for (int kc = 0; kc < a.kpad; kc += 16) {
-        v4s bv;
+    for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int k = kc + kq + j;
-            uint16_t v = 0;
-            if (k < K) {
-                const int ci = k / 9, t = k - ci * 9;
-                const int ky = t / 3, kx = t - ky * 3;
-                const int yy = y + ky - 1, xx = x + kx - 1;
-                if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W) v = inb[(int64_t)ci * HW + yy * a.W + xx];
+        for (int r = 0; r < kConvRowsOut; ++r) acc[m][r] = v4f{0.f, 0.f, 0.f, 0.f};
+    int kk = 0;
+    for (int t = 0; t < 9; ++t) {
+        const int ty = t / 3;
+        const uint16_t* sp = s_in + kq * kConvPlane + ty * kConvCols + (t - 3 * ty) + col;
+#pragma unroll 2
+        for (int c0 = 0; c0 < cpad; c0 += 16) {
+            v4s bv[kConvRowsOut];
+#pragma unroll
+            for (int r = 0; r < kConvRowsOut; ++r)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) bv[r][j] = (short)sp[(c0 + j) * kConvPlane + r * kConvCols];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                if (m < mt) {
+                    const uint2 wv = *reinterpret_cast<const uint2*>(wl + (size_t)m * 16 * a.kpad + kk + c0);
+                    v4s av;
+                    av[0] = (short)(wv.x & 0xFFFFu);
+                    av[1] = (short)(wv.x >> 16);
+                    av[2] = (short)(wv.y & 0xFFFFu);
+                    av[3] = (short)(wv.y >> 16);
+#pragma unroll
+                    for (int r = 0; r < kConvRowsOut; ++r)
+                        acc[m][r] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv[r], acc[m][r], 0, 0, 0);
+                }
             }
-            bv[j] = (short)v;
         }
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            if (m < mt) {
-                const uint2 wv =
-                    *reinterpret_cast<const uint2*>(a.w + (size_t)((m0 + m) * 16 + n) * a.kpad + kc + kq);
-                v4s av;
-                av[0] = (short)(wv.x & 0xFFFFu);
-                av[1] = (short)(wv.x >> 16);
-                av[2] = (short)(wv.y & 0xFFFFu);
-                av[3] = (short)(wv.y >> 16);
-                acc[m] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[m], 0, 0, 0);
-            }
-        }
+        kk += cpad;
     }
     if (x >= a.W) return;
     // Lane holds output channels (m0 + m) * 16 + kq + j of pixel column n.
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        if (m >= mt) continue;
+    for (int r = 0; r < kConvRowsOut; ++r) {
+        const int y = y0 + r;
+        if (y >= a.H) continue;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int co = (m0 + m) * 16 + kq + j;
-            if (co >= a.cout) continue;
-            float v = acc[m][j] + (a.bias ? a.bias[co] : 0.f);
-            if (a.relu) v = fmaxf(v, 0.f);
-            const int64_t p = (int64_t)co * HW + (int64_t)y * a.W + x;
-            if (a.mask && !(bf2f(a.mask[(int64_t)b * a.mask_bs + p]) > 0.f)) v = 0.f;
-            if (a.out_f)
-                a.out_f[(int64_t)b * a.out_bs + p] = v;
-            else
-                a.out[(int64_t)b * a.out_bs + p] = f2bf(v);
+        for (int m = 0; m < 4; ++m) {
+            if (m >= mt) continue;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int co = (m0 + m) * 16 + kq + j;
+                if (co >= a.cout) continue;
+                float v = acc[m][r][j] + (a.bias ? a.bias[co] : 0.f);
+                if (a.relu) v = fmaxf(v, 0.f);
+                const int64_t p = (int64_t)co * HW + (int64_t)y * a.W + x;
+                if (a.mask && !(bf2f(a.mask[(int64_t)b * a.mask_bs + p]) > 0.f)) v = 0.f;
+                if (a.out_f)
+                    a.out_f[(int64_t)b * a.out_bs + p] = v;
+                else
+                    a.out[(int64_t)b * a.out_bs + p] = f2bf(v);
+            }
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Weight gradient: part[chunk][co][ci * 9 + tap] = sum over the chunk's
-// pixels of g[co, p] * in[ci, p + tap offset].  Block: 4 waves, one
-// 16-column tile of (ci, tap) each; blockIdx.y: chunk of image rows.
+// Weight and bias gradient: part[chunk][co][col] = sum over the chunk's
+// pixels of g[co, p] * in[ci, p + tap offset] for col = ci * 9 + tap < K,
+// and of g[co, p] (a column of ones) for col = K, the bias.  Block: 4
+// waves, one 16-column tile each; blockIdx.y: chunk of image rows.
 // ---------------------------------------------------------------------------
 struct WgradArgs {
     const uint16_t* g;
@@ -150,13 +200,13 @@ struct WgradArgs {
 
 __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int K = a.cin * 9;
+    const int K = a.cin * 9, KC = K + 1;
     const int nt = blockIdx.x * 4 + wave;
-    if (nt * 16 >= K) return;  // whole wave
+    if (nt * 16 >= KC) return;  // whole wave
     const int n = lane & 15, kq = (lane >> 4) * 4;
     const int col = nt * 16 + n;
-    const bool col_ok = col < K;
-    const int ci = col_ok ? col / 9 : 0, t = col - ci * 9;
+    const bool col_ok = col < K, is_bias = col == K;
+    const int ci = col_ok ? col / 9 : 0, t = col_ok ? col - ci * 9 : 4;
     const int ky = t / 3, kx = t - ky * 3;
     const int HW = a.H * a.W;
     const int mt = (a.cout + 15) >> 4;
@@ -170,13 +220,14 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
         const uint16_t* ib = a.in + (int64_t)b * a.in_bs + (int64_t)ci * HW;
         const int yy = y + ky - 1;
         const bool row_ok = col_ok && yy >= 0 && yy < a.H;
+#pragma unroll 2
         for (int xb = 0; xb < a.W; xb += 16) {
             v4s bv;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int xx = xb + kq + j + kx - 1;
-                const bool ok = row_ok && xb + kq + j < a.W && xx >= 0 && xx < a.W;
-                bv[j] = (short)(ok ? ib[(int64_t)yy * a.W + xx] : (uint16_t)0);
+                const int xp = xb + kq + j, xx = xp + kx - 1;
+                const bool ok = row_ok && xp < a.W && xx >= 0 && xx < a.W;
+                bv[j] = (short)(ok ? ib[(int64_t)yy * a.W + xx] : (is_bias && xp < a.W) ? (uint16_t)0x3F80u : (uint16_t)0);
             }
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
@@ -193,26 +244,30 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
             }
         }
     }
-    if (!col_ok) return;
-    float* pb = a.part + (size_t)blockIdx.y * a.cout * K;
+    if (col >= KC) return;
+    float* pb = a.part + (size_t)blockIdx.y * a.cout * KC;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
         if (m >= mt) continue;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int co = m * 16 + kq + j;
-            if (co < a.cout) pb[(size_t)co * K + col] = acc[m][j];
+            if (co < a.cout) pb[(size_t)co * KC + col] = acc[m][j];
         }
     }
 }
 
-__global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ part, int chunks, int64_t n,
+// grad (the layer's W[cout][K] then b[cout]) from the partials in a fixed
+// chunk order.
+__global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ part, int chunks, int cout, int K,
                                                       float* __restrict__ grad) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
+    const int KC = K + 1;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= cout * KC) return;
     float s = 0.f;
-    for (int c = 0; c < chunks; ++c) s += part[(size_t)c * n + i];
-    grad[i] = s;
+    for (int c = 0; c < chunks; ++c) s += part[(size_t)c * cout * KC + i];
+    const int co = i / KC, col = i - co * KC;
+    grad[col < K ? co * K + col : cout * K + co] = s;
 }
 
 __device__ __forceinline__ float block_sum(float v, float* red) {
@@ -225,82 +280,68 @@ __device__ __forceinline__ float block_sum(float v, float* red) {
     return s;
 }
 
-// Bias gradient: one block per output channel.
-__global__ __launch_bounds__(256) void k_bgrad(const uint16_t* __restrict__ g, int64_t g_bs, int B, int HW,
-                                               float* __restrict__ grad) {
-    __shared__ float red[4];
-    const int co = blockIdx.x;
-    float s = 0.f;
-    for (int b = 0; b < B; ++b) {
-        const uint16_t* gb = g + (int64_t)b * g_bs + (int64_t)co * HW;
-        for (int p = threadIdx.x; p < HW; p += 256) s += bf2f(gb[p]);
-    }
-    s = block_sum(s, red);
-    if (threadIdx.x == 0) grad[co] = s;
-}
-
 // ---------------------------------------------------------------------------
 // Weight packing (fp32 master -> bf16 GEMM operands), pooling, upsampling,
 // gradient merges, input assembly, output and loss.
 // ---------------------------------------------------------------------------
+// Column k = tap * cpad + c of a packed row.  Forward: row = output
+// channel, c = input channel, W[row][c][tap].  Transposed (input gradient):
+// row = input channel, c = output channel, W[c][row][8 - tap] (the kernel
+// flipped).
 __global__ __launch_bounds__(256) void k_pack(const float* __restrict__ w, int cin, int cout, int transpose,
-                                              int mpad, int kpad, uint16_t* __restrict__ out) {
+                                              int mpad, int cpad, uint16_t* __restrict__ out) {
+    const int kpad = 9 * cpad;
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= mpad * kpad) return;
     const int m = i / kpad, k = i - m * kpad;
+    const int t = k / cpad, c = k - t * cpad;
     float v = 0.f;
     if (!transpose) {
-        if (m < cout && k < cin * 9) v = w[m * cin * 9 + k];
+        if (m < cout && c < cin) v = w[(m * cin + c) * 9 + t];
     } else {
-        // Row = input channel, column = (output channel, flipped tap).
-        if (m < cin && k < cout * 9) {
-            const int co = k / 9, t = k - co * 9;
-            v = w[(co * cin + m) * 9 + (8 - t)];
-        }
+        if (m < cin && c < cout) v = w[(c * cin + m) * 9 + (8 - t)];
     }
     out[i] = f2bf(v);
 }
 
+// The elementwise kernels below run on a 2-D grid: blockIdx.y = image *
+// C + channel, x over the pixels of the output plane.
 __global__ __launch_bounds__(256) void k_pool(const uint16_t* __restrict__ in, int64_t in_bs, int C, int H, int W,
-                                              uint16_t* __restrict__ out, int B) {
+                                              uint16_t* __restrict__ out) {
     const int h = H / 2, w = W / 2;
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= (int64_t)B * C * h * w) return;
-    const int X = (int)(i % w), Y = (int)((i / w) % h);
-    const int64_t bc = i / ((int64_t)w * h);
-    const int c = (int)(bc % C), b = (int)(bc / C);
-    const uint16_t* p = in + (int64_t)b * in_bs + (int64_t)c * H * W + (int64_t)(2 * Y) * W + 2 * X;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= h * w) return;
+    const int bc = blockIdx.y, b = bc / C, c = bc - b * C;
+    const int Y = i / w, X = i - Y * w;
+    const uint16_t* p = in + (int64_t)b * in_bs + (int64_t)c * H * W + (2 * Y) * W + 2 * X;
     const float s = ((bf2f(p[0]) + bf2f(p[1])) + bf2f(p[W])) + bf2f(p[W + 1]);
-    out[i] = f2bf(0.25f * s);
+    out[(int64_t)bc * h * w + i] = f2bf(0.25f * s);
 }
 
 // Nearest 2x upsample of [B][C][h][w] into a slice of a larger tensor.
 __global__ __launch_bounds__(256) void k_up(const uint16_t* __restrict__ in, int C, int h, int w,
-                                            uint16_t* __restrict__ out, int64_t out_bs, int B) {
+                                            uint16_t* __restrict__ out, int64_t out_bs) {
     const int H = 2 * h, W = 2 * w;
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= (int64_t)B * C * H * W) return;
-    const int x = (int)(i % W), y = (int)((i / W) % H);
-    const int64_t bc = i / ((int64_t)W * H);
-    const int c = (int)(bc % C), b = (int)(bc / C);
-    out[(int64_t)b * out_bs + (int64_t)c * H * W + (int64_t)y * W + x] =
-        in[((int64_t)b * C + c) * h * w + (int64_t)(y / 2) * w + x / 2];
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= H * W) return;
+    const int bc = blockIdx.y, b = bc / C, c = bc - b * C;
+    const int y = i / W, x = i - y * W;
+    out[(int64_t)b * out_bs + (int64_t)c * H * W + i] = in[(int64_t)bc * h * w + (y >> 1) * w + (x >> 1)];
 }
 
 // Gradient of the upsample: sum of each 2x2 block of a slice, masked by the
 // activation (ReLU derivative).
 __global__ __launch_bounds__(256) void k_up_grad(const uint16_t* __restrict__ g, int64_t g_bs, int C, int H, int W,
-                                                 const uint16_t* __restrict__ act, uint16_t* __restrict__ out,
-                                                 int B) {
+                                                 const uint16_t* __restrict__ act, uint16_t* __restrict__ out) {
     const int h = H / 2, w = W / 2;
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= (int64_t)B * C * h * w) return;
-    const int X = (int)(i % w), Y = (int)((i / w) % h);
-    const int64_t bc = i / ((int64_t)w * h);
-    const int c = (int)(bc % C), b = (int)(bc / C);
-    const uint16_t* p = g + (int64_t)b * g_bs + (int64_t)c * H * W + (int64_t)(2 * Y) * W + 2 * X;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= h * w) return;
+    const int bc = blockIdx.y, b = bc / C, c = bc - b * C;
+    const int Y = i / w, X = i - Y * w;
+    const uint16_t* p = g + (int64_t)b * g_bs + (int64_t)c * H * W + (2 * Y) * W + 2 * X;
     const float s = ((bf2f(p[0]) + bf2f(p[1])) + bf2f(p[W])) + bf2f(p[W + 1]);
-    out[i] = bf2f(act[i]) > 0.f ? f2bf(s) : (uint16_t)0;
+    const int64_t o = (int64_t)bc * h * w + i;
+    out[o] = bf2f(act[o]) > 0.f ? f2bf(s) : (uint16_t)0;
 }
 
 // Gradient reaching an encoder activation from its skip connection (a
@@ -308,17 +349,15 @@ __global__ __launch_bounds__(256) void k_up_grad(const uint16_t* __restrict__ g,
 // masked by the activation.
 __global__ __launch_bounds__(256) void k_merge(const uint16_t* __restrict__ skip, int64_t skip_bs,
                                                const uint16_t* __restrict__ pg, const uint16_t* __restrict__ act,
-                                               int64_t act_bs, int C, int H, int W, uint16_t* __restrict__ out,
-                                               int B) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= (int64_t)B * C * H * W) return;
-    const int x = (int)(i % W), y = (int)((i / W) % H);
-    const int64_t bc = i / ((int64_t)W * H);
-    const int c = (int)(bc % C), b = (int)(bc / C);
-    const int64_t off = (int64_t)c * H * W + (int64_t)y * W + x;
+                                               int64_t act_bs, int C, int H, int W, uint16_t* __restrict__ out) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= H * W) return;
+    const int bc = blockIdx.y, b = bc / C, c = bc - b * C;
+    const int y = i / W, x = i - y * W;
+    const int64_t off = (int64_t)c * H * W + i;
     const float s = bf2f(skip[(int64_t)b * skip_bs + off]) +
-                    0.25f * bf2f(pg[((int64_t)b * C + c) * (H / 2) * (W / 2) + (int64_t)(y / 2) * (W / 2) + x / 2]);
-    out[i] = bf2f(act[(int64_t)b * act_bs + off]) > 0.f ? f2bf(s) : (uint16_t)0;
+                    0.25f * bf2f(pg[(int64_t)bc * (H / 2) * (W / 2) + (y >> 1) * (W / 2) + (x >> 1)]);
+    out[(int64_t)bc * H * W + i] = bf2f(act[(int64_t)b * act_bs + off]) > 0.f ? f2bf(s) : (uint16_t)0;
 }
 
 __global__ __launch_bounds__(256) void k_input(const float* __restrict__ rgb, const float* __restrict__ z,
@@ -452,8 +491,8 @@ Bufs layout(int B, int H, int W, bool train, char* base) {
     f.d1 = bf(B * 16 * h1);
     f.r = fl(B * 3 * h1);
     for (int l = 0; l < kLayers; ++l) {
-        f.wf[l] = bf((size_t)pad16(kNet[l].cout) * pad16(kNet[l].cin * 9));
-        f.wb[l] = bf((size_t)pad16(kNet[l].cin) * pad16(kNet[l].cout * 9));
+        f.wf[l] = bf((size_t)pad16(kNet[l].cout) * 9 * pad16(kNet[l].cin));
+        f.wb[l] = bf((size_t)pad16(kNet[l].cin) * 9 * pad16(kNet[l].cout));
     }
     const int64_t n3 = (int64_t)B * 3 * h1;
     f.cnt_part = fl((B * h1 + 255) / 256);
@@ -481,7 +520,7 @@ Bufs layout(int B, int H, int W, bool train, char* base) {
         const int lvl[kLayers] = {1, 1, 2, 2, 3, 3, 2, 1, 1};
         for (int l = 0; l < kLayers; ++l) {
             const int ch = lvl[l] == 1 ? f.chunks1 : lvl[l] == 2 ? f.chunks2 : f.chunks3;
-            mx = std::max(mx, (size_t)ch * kNet[l].cout * kNet[l].cin * 9);
+            mx = std::max(mx, (size_t)ch * kNet[l].cout * (kNet[l].cin * 9 + 1));
         }
         f.part = fl(mx);
     }
@@ -500,7 +539,8 @@ void conv(hipStream_t s, int B, int H, int W, int l, bool transpose, const Bufs&
     a.cin = transpose ? kNet[l].cout : kNet[l].cin;
     a.cout = transpose ? kNet[l].cin : kNet[l].cout;
     a.w = transpose ? f.wb[l] : f.wf[l];
-    a.kpad = pad16(a.cin * 9);
+    a.cpad = pad16(a.cin);
+    a.kpad = 9 * a.cpad;
     a.bias = transpose ? nullptr : params + param_offset(l) + (int64_t)kNet[l].cout * kNet[l].cin * 9;
     a.out = out;
     a.out_f = out_f;
@@ -510,7 +550,8 @@ void conv(hipStream_t s, int B, int H, int W, int l, bool transpose, const Bufs&
     a.relu = transpose ? 0 : kNet[l].relu;
     a.H = H;
     a.W = W;
-    hipLaunchKernelGGL(k_conv3x3, dim3((W + 63) / 64, H, B * ((a.cout + 63) / 64)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_conv3x3, dim3((W + 63) / 64, (H + kConvRowsOut - 1) / kConvRowsOut, B * ((a.cout + 63) / 64)),
+                       dim3(256), (size_t)a.cpad * kConvPlane * sizeof(uint16_t), s, a);
 }
 
 void wgrad(hipStream_t s, int B, int H, int W, int l, const Bufs& f, const uint16_t* g, int64_t g_bs,
@@ -527,12 +568,11 @@ void wgrad(hipStream_t s, int B, int H, int W, int l, const Bufs& f, const uint1
     a.W = W;
     a.rows = chunk_rows(B * H);
     a.part = f.part;
-    const int nt = (a.cin * 9 + 15) / 16;
+    const int K = a.cin * 9;
+    const int nt = (K + 1 + 15) / 16;
     hipLaunchKernelGGL(k_wgrad, dim3((nt + 3) / 4, chunks), dim3(256), 0, s, a);
-    const int64_t nw = (int64_t)a.cout * a.cin * 9;
-    float* gl = grad + param_offset(l);
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(nw)), dim3(256), 0, s, (const float*)f.part, chunks, nw, gl);
-    hipLaunchKernelGGL(k_bgrad, dim3(a.cout), dim3(256), 0, s, g, g_bs, B, H * W, gl + nw);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks((int64_t)a.cout * (K + 1))), dim3(256), 0, s, (const float*)f.part,
+                       chunks, a.cout, K, grad + param_offset(l));
 }
 
 void forward(hipStream_t s, int B, int H, int W, const float* params, const float* rgb, const float* z,
@@ -540,10 +580,10 @@ void forward(hipStream_t s, int B, int H, int W, const float* params, const floa
     for (int l = 0; l < kLayers; ++l) {
         const float* w = params + param_offset(l);
         const int ci = kNet[l].cin, co = kNet[l].cout;
-        hipLaunchKernelGGL(k_pack, dim3(blocks((int64_t)pad16(co) * pad16(ci * 9))), dim3(256), 0, s, w, ci, co, 0,
-                           pad16(co), pad16(ci * 9), f.wf[l]);
-        hipLaunchKernelGGL(k_pack, dim3(blocks((int64_t)pad16(ci) * pad16(co * 9))), dim3(256), 0, s, w, ci, co, 1,
-                           pad16(ci), pad16(co * 9), f.wb[l]);
+        hipLaunchKernelGGL(k_pack, dim3(blocks((int64_t)pad16(co) * 9 * pad16(ci))), dim3(256), 0, s, w, ci, co, 0,
+                           pad16(co), pad16(ci), f.wf[l]);
+        hipLaunchKernelGGL(k_pack, dim3(blocks((int64_t)pad16(ci) * 9 * pad16(co))), dim3(256), 0, s, w, ci, co, 1,
+                           pad16(ci), pad16(co), f.wb[l]);
     }
     const int64_t h1 = (int64_t)H * W, h2 = h1 / 4, h3 = h1 / 16;
     const int H2 = H / 2, W2 = W / 2, H3 = H / 4, W3 = W / 4;
@@ -551,16 +591,16 @@ void forward(hipStream_t s, int B, int H, int W, const float* params, const floa
     conv(s, B, H, W, E1A, false, f, f.x0, 5 * h1, params, f.e1a, nullptr, 16 * h1, nullptr, 0);
     uint16_t* e1b = f.cat1 + 32 * h1;
     conv(s, B, H, W, E1B, false, f, f.e1a, 16 * h1, params, e1b, nullptr, 48 * h1, nullptr, 0);
-    hipLaunchKernelGGL(k_pool, dim3(blocks(B * 16 * h2)), dim3(256), 0, s, e1b, 48 * h1, 16, H, W, f.p1, B);
+    hipLaunchKernelGGL(k_pool, dim3(blocks(h2), B * 16), dim3(256), 0, s, e1b, 48 * h1, 16, H, W, f.p1);
     conv(s, B, H2, W2, E2A, false, f, f.p1, 16 * h2, params, f.e2a, nullptr, 32 * h2, nullptr, 0);
     uint16_t* e2b = f.cat2 + 64 * h2;
     conv(s, B, H2, W2, E2B, false, f, f.e2a, 32 * h2, params, e2b, nullptr, 96 * h2, nullptr, 0);
-    hipLaunchKernelGGL(k_pool, dim3(blocks(B * 32 * h3)), dim3(256), 0, s, e2b, 96 * h2, 32, H2, W2, f.p2, B);
+    hipLaunchKernelGGL(k_pool, dim3(blocks(h3), B * 32), dim3(256), 0, s, e2b, 96 * h2, 32, H2, W2, f.p2);
     conv(s, B, H3, W3, E3A, false, f, f.p2, 32 * h3, params, f.e3a, nullptr, 64 * h3, nullptr, 0);
     conv(s, B, H3, W3, E3B, false, f, f.e3a, 64 * h3, params, f.e3b, nullptr, 64 * h3, nullptr, 0);
-    hipLaunchKernelGGL(k_up, dim3(blocks(B * 64 * h2)), dim3(256), 0, s, f.e3b, 64, H3, W3, f.cat2, 96 * h2, B);
+    hipLaunchKernelGGL(k_up, dim3(blocks(h2), B * 64), dim3(256), 0, s, f.e3b, 64, H3, W3, f.cat2, 96 * h2);
     conv(s, B, H2, W2, D2, false, f, f.cat2, 96 * h2, params, f.d2, nullptr, 32 * h2, nullptr, 0);
-    hipLaunchKernelGGL(k_up, dim3(blocks(B * 32 * h1)), dim3(256), 0, s, f.d2, 32, H2, W2, f.cat1, 48 * h1, B);
+    hipLaunchKernelGGL(k_up, dim3(blocks(h1), B * 32), dim3(256), 0, s, f.d2, 32, H2, W2, f.cat1, 48 * h1);
     conv(s, B, H, W, D1, false, f, f.cat1, 48 * h1, params, f.d1, nullptr, 16 * h1, nullptr, 0);
     conv(s, B, H, W, OUT, false, f, f.d1, 16 * h1, params, nullptr, f.r, 3 * h1, nullptr, 0);
 }
@@ -574,30 +614,30 @@ void backward(hipStream_t s, int B, int H, int W, const float* params, const Buf
     conv(s, B, H, W, OUT, true, f, f.g_r, 3 * h1, params, f.g_d1, nullptr, 16 * h1, f.d1, 16 * h1);
     wgrad(s, B, H, W, D1, f, f.g_d1, 16 * h1, f.cat1, 48 * h1, f.chunks1, grad);
     conv(s, B, H, W, D1, true, f, f.g_d1, 16 * h1, params, f.g_cat1, nullptr, 48 * h1, nullptr, 0);
-    hipLaunchKernelGGL(k_up_grad, dim3(blocks(B * 32 * h2)), dim3(256), 0, s, f.g_cat1, 48 * h1, 32, H, W, f.d2,
-                       f.g_d2, B);
+    hipLaunchKernelGGL(k_up_grad, dim3(blocks(h2), B * 32), dim3(256), 0, s, f.g_cat1, 48 * h1, 32, H, W, f.d2,
+                       f.g_d2);
     wgrad(s, B, H2, W2, D2, f, f.g_d2, 32 * h2, f.cat2, 96 * h2, f.chunks2, grad);
     conv(s, B, H2, W2, D2, true, f, f.g_d2, 32 * h2, params, f.g_cat2, nullptr, 96 * h2, nullptr, 0);
-    hipLaunchKernelGGL(k_up_grad, dim3(blocks(B * 64 * h3)), dim3(256), 0, s, f.g_cat2, 96 * h2, 64, H2, W2, f.e3b,
-                       f.g_e3b, B);
+    hipLaunchKernelGGL(k_up_grad, dim3(blocks(h3), B * 64), dim3(256), 0, s, f.g_cat2, 96 * h2, 64, H2, W2, f.e3b,
+                       f.g_e3b);
     wgrad(s, B, H3, W3, E3B, f, f.g_e3b, 64 * h3, f.e3a, 64 * h3, f.chunks3, grad);
     conv(s, B, H3, W3, E3B, true, f, f.g_e3b, 64 * h3, params, f.g_e3a, nullptr, 64 * h3, f.e3a, 64 * h3);
     wgrad(s, B, H3, W3, E3A, f, f.g_e3a, 64 * h3, f.p2, 32 * h3, f.chunks3, grad);
     conv(s, B, H3, W3, E3A, true, f, f.g_e3a, 64 * h3, params, f.g_p2, nullptr, 32 * h3, nullptr, 0);
-    hipLaunchKernelGGL(k_merge, dim3(blocks(B * 32 * h2)), dim3(256), 0, s, f.g_cat2 + 64 * h2, 96 * h2, f.g_p2, e2b,
-                       96 * h2, 32, H2, W2, f.g_e2b, B);
+    hipLaunchKernelGGL(k_merge, dim3(blocks(h2), B * 32), dim3(256), 0, s, f.g_cat2 + 64 * h2, 96 * h2, f.g_p2, e2b,
+                       96 * h2, 32, H2, W2, f.g_e2b);
     wgrad(s, B, H2, W2, E2B, f, f.g_e2b, 32 * h2, f.e2a, 32 * h2, f.chunks2, grad);
     conv(s, B, H2, W2, E2B, true, f, f.g_e2b, 32 * h2, params, f.g_e2a, nullptr, 32 * h2, f.e2a, 32 * h2);
     wgrad(s, B, H2, W2, E2A, f, f.g_e2a, 32 * h2, f.p1, 16 * h2, f.chunks2, grad);
     conv(s, B, H2, W2, E2A, true, f, f.g_e2a, 32 * h2, params, f.g_p1, nullptr, 16 * h2, nullptr, 0);
-    hipLaunchKernelGGL(k_merge, dim3(blocks(B * 16 * h1)), dim3(256), 0, s, f.g_cat1 + 32 * h1, 48 * h1, f.g_p1, e1b,
-                       48 * h1, 16, H, W, f.g_e1b, B);
+    hipLaunchKernelGGL(k_merge, dim3(blocks(h1), B * 16), dim3(256), 0, s, f.g_cat1 + 32 * h1, 48 * h1, f.g_p1, e1b,
+                       48 * h1, 16, H, W, f.g_e1b);
     wgrad(s, B, H, W, E1B, f, f.g_e1b, 16 * h1, f.e1a, 16 * h1, f.chunks1, grad);
     conv(s, B, H, W, E1B, true, f, f.g_e1b, 16 * h1, params, f.g_e1a, nullptr, 16 * h1, f.e1a, 16 * h1);
     wgrad(s, B, H, W, E1A, f, f.g_e1a, 16 * h1, f.x0, 5 * h1, f.chunks1, grad);
 }
 
-bool sizes_ok(int B, int H, int W) { return B >= 1 && H >= 4 && W >= 4 && H % 4 == 0 && W % 4 == 0 && H <= 8192 && W <= 8192; }
+bool sizes_ok(int B, int H, int W) { return B >= 1 && B <= 1000 && H >= 4 && W >= 4 && H % 4 == 0 && W % 4 == 0 && H <= 8192 && W <= 8192; }
 
 int32_t launched() { return hipGetLastError() == hipSuccess ? BGS_OK : BGS_ERR_HIP; }
 
