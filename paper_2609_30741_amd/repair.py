@@ -11,8 +11,9 @@ allocates tensors and marshals arguments.
     python -m paper_2609_30741_amd.repair [--steps 600] [--batch 8] [--crop 128]
 
 trains on sphere800 poses, then reports, on held-out poses at full frame
-size, the hole pixels' PSNR for the network and for the method's gap
-interpolation with row fill, and the time of one inference pass.
+size, the hole pixels' PSNR for the network, for the method's gap
+interpolation with row fill, and for the full method (interpolation plus
+ROI re-rendering), and the time of one inference pass.
 """
 from __future__ import annotations
 
@@ -240,14 +241,19 @@ def main(argv=None):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     res = []
+    ctx = api.Context()
+    ds = api.DeviceScene(scene)
     for i, p in zip(held, test):
         x = net.forward(p["rgb"][None].contiguous(), p["z"][None].contiguous(), p["hole"][None].contiguous())[0]
         interp, cls = interpolation_fill(p, cams[i], affs[i])
         filled = (p["hole"] > 0) & ((cls == _abi.CLS_GAP) | (cls == _abi.CLS_ROWFILL))
+        # The full method: interpolation plus ROI re-rendering (render_stereo).
+        full = ctx.render_stereo(ds, cams[i], affs[i])["rgb_aff"]
         res.append(dict(pose=i, holes=int(p["hole"].sum()), compared=int(filled.sum()),
                         psnr_net=round(hole_psnr(x, p["target"], filled), 3),
                         psnr_interp=round(hole_psnr(interp, p["target"], filled), 3),
-                        psnr_net_all_holes=round(hole_psnr(x, p["target"], p["hole"]), 3)))
+                        psnr_net_all_holes=round(hole_psnr(x, p["target"], p["hole"]), 3),
+                        psnr_method_all_holes=round(hole_psnr(full, p["target"], p["hole"]), 3)))
     # Inference time at full frame size.
     p = test[0]
     args_t = (p["rgb"][None].contiguous(), p["z"][None].contiguous(), p["hole"][None].contiguous())
