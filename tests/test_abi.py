@@ -152,3 +152,27 @@ def test_sort_and_label_validation(L, ctx):
     assert L.bgs_label_components(ctx, FAKE, 10, 10, 6, FAKE) == _abi.ERR_INVALID_ARG
     assert L.bgs_label_components(ctx, FAKE, 0, 10, 8, FAKE) == _abi.ERR_INVALID_ARG
     assert L.bgs_ctx_set_sync(None, 1) == _abi.ERR_INVALID_ARG
+
+
+def test_repair_parameter_count_and_argument_checks(L):
+    # bgs_repair_* validate on the host before any launch.
+    from oracle import repair_oracle as R
+    n = C.c_int64()
+    assert L.bgs_repair_num_params(C.byref(n)) == 0
+    assert n.value == R.num_params()
+    b = C.c_size_t()
+    assert L.bgs_repair_workspace_size(2, 16, 24, 1, C.byref(b)) == 0
+    train = b.value
+    assert L.bgs_repair_workspace_size(2, 16, 24, 0, C.byref(b)) == 0
+    assert 0 < b.value < train
+    for B, H, W in ((0, 16, 16), (1, 10, 16), (1, 16, 18), (1001, 16, 16), (1, 8200, 16)):
+        assert L.bgs_repair_workspace_size(B, H, W, 0, C.byref(b)) == _abi.ERR_INVALID_ARG
+    assert L.bgs_repair_workspace_size(1, 16, 16, 2, C.byref(b)) == _abi.ERR_INVALID_ARG
+    fake = C.c_void_p(0x100000)
+    assert L.bgs_repair_forward(None, 1, 16, 16, fake, fake, fake, fake, fake, 1 << 30, None) == _abi.ERR_INVALID_ARG
+    assert L.bgs_repair_forward(fake, 1, 16, 16, fake, fake, fake, fake, fake, 16, None) == _abi.ERR_WORKSPACE
+    assert L.bgs_repair_grad(fake, 1, 16, 16, fake, fake, fake, fake, fake, fake, None, fake, 16,
+                             None) == _abi.ERR_WORKSPACE
+    assert L.bgs_repair_adam(fake, fake, fake, fake, 0, 1, 1e-3, 0.9, 0.999, 1e-8, None) == _abi.ERR_INVALID_ARG
+    assert L.bgs_repair_adam(fake, fake, fake, fake, 10, 0, 1e-3, 0.9, 0.999, 1e-8, None) == _abi.ERR_INVALID_ARG
+    assert L.bgs_repair_adam(fake, fake, fake, fake, 10, 1, 1e-3, 1.0, 0.999, 1e-8, None) == _abi.ERR_INVALID_ARG

@@ -38,8 +38,11 @@ def _dev(*xs):
     return [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in xs]
 
 
-@pytest.mark.parametrize("B,H,W", [(2, 16, 72), (1, 12, 20), (3, 8, 132)])
+@pytest.mark.parametrize("B,H,W", [(2, 16, 72), (1, 12, 20), (3, 8, 132), (1, 304, 400)])
 def test_forward_matches_oracle(B, H, W):
+    # (1, 12, 20) has an odd row count (3) at the coarsest level, which the
+    # two-row convolution blocks must cut short; (1, 304, 400) spans seven
+    # 64-pixel blocks with a 16-pixel tail at full resolution.
     p, rgb, z, hole, target = _problem(1, B, H, W)
     net = repair.Repair(params=p)
     g_rgb, g_z, g_hole = _dev(rgb, z, hole)
