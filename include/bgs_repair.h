@@ -12,11 +12,13 @@
  *   level 3 (H/4 x W/4):  e3a 32->64, e3b 64->64   input: 2x2 mean pool of e2b
  *   level 2:              d2 96->32                 input: [nearest 2x upsample of e3b, e2b]
  *   level 1:              d1 48->16                 input: [upsample of d2, e1b]
- *   level 1:              out 16->3, no activation
+ *   level 1:              out 16->4, no activation
  * Inputs per pixel: warped RGB (zeroed at holes), hole mask, 1/z (0 at
- * holes and for infinite depth).  Output: rgb_out = rgb + hole * r, so only
- * holes change.  Training loss: sum over hole pixels and channels of
- * (rgb_out - target)^2 / (3 max(1, holes)).
+ * holes and for infinite depth).  Output channels 0-2 are a residual r:
+ * rgb_out = rgb + hole * r, so only holes change; channel 3, e, predicts
+ * the pixel's squared error s = mean over channels of (rgb_out - target)^2.
+ * Training loss over hole pixels: sum_c (rgb_out_c - target_c)^2 / (3 N) +
+ * sum (e - s)^2 / N, N = max(1, holes), s held constant in the gradient.
  *
  * Parameters: one flat fp32 device array, per layer in the order above
  * W[cout][cin][3][3] then b[cout] (bgs_repair_num_params elements).
@@ -47,10 +49,11 @@ BGS_API int32_t bgs_repair_num_params(int64_t* n);
 BGS_API int32_t bgs_repair_workspace_size(int32_t batch, int32_t height, int32_t width, int32_t train,
                                           size_t* bytes);
 
-/* Inference: rgb_out [B][3][H][W] = rgb + hole * r. */
+/* Inference: rgb_out [B][3][H][W] = rgb + hole * r; err_out [B][H][W]
+ * (may be null) = e at holes, 0 elsewhere. */
 BGS_API int32_t bgs_repair_forward(const float* params, int32_t batch, int32_t height, int32_t width,
                                    const float* rgb, const float* z, const uint8_t* hole, float* rgb_out,
-                                   void* ws, size_t ws_bytes, void* hip_stream);
+                                   float* err_out, void* ws, size_t ws_bytes, void* hip_stream);
 
 /* Forward and backward pass: loss (one device float) and the gradient of
  * the loss in the parameter layout (grad, device, overwritten).  rgb_out

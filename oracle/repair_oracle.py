@@ -11,14 +11,18 @@ is a three-level convolutional U-Net:
     level 3 (H/4 x W/4):  e3a 32->64, e3b 64->64   (input: 2x2 mean pool of e2b)
     level 2:              d2 (64+32)->32            (input: [nearest 2x upsample of e3b, e2b])
     level 1:              d1 (32+16)->16            (input: [upsample of d2, e1b])
-    level 1:              out 16->3, no activation
+    level 1:              out 16->4, no activation
     every other 3x3 convolution (zero padding, stride 1) is followed by ReLU.
 
 Inputs per pixel: the warped RGB (0 at holes), the hole mask, and inverse
-depth 1/z (0 at holes and for background).  The output r is a residual on
-the holes only: pred = rgb + hole * r.  The loss is the mean squared error
-over hole pixels and channels, sum((pred - target)^2) / (3 max(1, holes)).
-Training uses Adam (Kingma and Ba, 2015) with bias correction.
+depth 1/z (0 at holes and for background).  Output channels 0-2 are a
+residual on the holes only: pred = rgb + hole * r.  Channel 3, e, predicts
+the pixel's squared error s = mean over channels of (pred - target)^2.  The
+loss over hole pixels is
+    sum_c (pred_c - target_c)^2 / (3 N) + sum (e - s)^2 / N,  N = max(1, holes),
+with s held constant in the gradient (it is the error channel's target, not
+a path back into the residual).  Training uses Adam (Kingma and Ba, 2015)
+with bias correction.
 
 Everything is computed in fp64.  The GPU stores activations, gradients
 that feed matrix products, and weights in bfloat16; passing q=bf16 rounds
@@ -40,7 +44,7 @@ LAYERS = [
     ("e2a", 16, 32, True), ("e2b", 32, 32, True),
     ("e3a", 32, 64, True), ("e3b", 64, 64, True),
     ("d2", 96, 32, True), ("d1", 48, 16, True),
-    ("out", 16, 3, False),
+    ("out", 16, 4, False),
 ]
 
 
@@ -175,20 +179,26 @@ def forward(params: np.ndarray, rgb, z, hole, q=None) -> dict:
     a["r"] = np.asarray((conv3x3(a["d1"], w) + b[None, :, None, None]).astype(np.float32), np.float64) \
         if q is not _ident else conv3x3(a["d1"], w) + b[None, :, None, None]
     h = np.asarray(hole, np.float64)[:, None]
-    a["pred"] = np.asarray(rgb, np.float64) + h * a["r"]
+    a["pred"] = np.asarray(rgb, np.float64) + h * a["r"][:, :3]
+    a["e"] = a["r"][:, 3]
     return a
 
 
-def loss_and_grad(params: np.ndarray, rgb, z, hole, target, q=None):
-    """Loss and gradient (flat, in the parameter layout) of the masked MSE."""
+def loss_and_grad(params: np.ndarray, rgb, z, hole, target, q=None, err_target=None):
+    """Loss and gradient (flat, in the parameter layout).  err_target, if
+    given, replaces the error channel's target s (finite differences hold
+    it fixed, as the gradient does)."""
     qq = q or _ident
     a = forward(params, rgb, z, hole, q)
     P = unpack(np.asarray(params, np.float64))
     Wq = {n: qq(P[n][0]) for n in P}
-    h = np.asarray(hole, np.float64)[:, None]
+    hp = np.asarray(hole, np.float64)
+    h = hp[:, None]
     nh = max(1.0, float(np.sum(hole)))
     diff = (a["pred"] - np.asarray(target, np.float64)) * h
-    loss = float(np.sum(diff * diff) / (3.0 * nh))
+    s = np.mean(diff * diff, axis=1) if err_target is None else np.asarray(err_target, np.float64)
+    de = (a["e"] - s) * hp
+    loss = float(np.sum(diff * diff) / (3.0 * nh) + np.sum(de * de) / nh)
     g = {}
 
     def back(name, g_pre, x_in):
@@ -197,7 +207,7 @@ def loss_and_grad(params: np.ndarray, rgb, z, hole, target, q=None):
     def relu_mask(v, act):
         return v * (act > 0)
 
-    g_r = qq(2.0 * diff / (3.0 * nh))
+    g_r = qq(np.concatenate([2.0 * diff / (3.0 * nh), (2.0 * de / nh)[:, None]], axis=1))
     back("out", g_r, a["d1"])
     g_d1 = relu_mask(qq(conv3x3_grad_input(g_r, Wq["out"])), a["d1"])
     back("d1", g_d1, a["cat1"])

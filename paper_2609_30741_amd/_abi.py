@@ -107,7 +107,7 @@ def load():
                                  C.POINTER(I64)],
         "bgs_repair_num_params": [C.POINTER(I64)],
         "bgs_repair_workspace_size": [I32, I32, I32, I32, C.POINTER(SZ)],
-        "bgs_repair_forward": [P, I32, I32, I32, P, P, P, P, P, SZ, P],
+        "bgs_repair_forward": [P, I32, I32, I32, P, P, P, P, P, P, SZ, P],
         "bgs_repair_grad": [P, I32, I32, I32, P, P, P, P, P, P, P, P, SZ, P],
         "bgs_repair_adam": [P, P, P, P, I64, I32, C.c_float, C.c_float, C.c_float, C.c_float, P],
     }

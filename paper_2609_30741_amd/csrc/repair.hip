@@ -31,7 +31,7 @@ struct LayerDef {
 // e1a e1b e2a e2b e3a e3b d2 d1 out
 constexpr int kLayers = 9;
 constexpr LayerDef kNet[kLayers] = {{5, 16, 1},  {16, 16, 1}, {16, 32, 1}, {32, 32, 1}, {32, 64, 1},
-                                    {64, 64, 1}, {96, 32, 1}, {48, 16, 1}, {16, 3, 0}};
+                                    {64, 64, 1}, {96, 32, 1}, {48, 16, 1}, {16, 4, 0}};
 enum { E1A, E1B, E2A, E2B, E3A, E3B, D2, D1, OUT };
 
 constexpr int pad16(int v) { return (v + 15) & ~15; }
@@ -375,13 +375,21 @@ __global__ __launch_bounds__(256) void k_input(const float* __restrict__ rgb, co
     o[4 * (int64_t)HW] = (h || !(zz < INFINITY)) ? (uint16_t)0 : f2bf(1.f / zz);
 }
 
+// r: [B][4][HW], channels 0-2 the residual, 3 the predicted squared error.
 __global__ __launch_bounds__(256) void k_output(const float* __restrict__ rgb, const uint8_t* __restrict__ hole,
                                                 const float* __restrict__ r, int B, int HW,
-                                                float* __restrict__ out) {
+                                                float* __restrict__ out, float* __restrict__ err) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= (int64_t)B * 3 * HW) return;
-    const int64_t p = i % HW, b = i / (3 * (int64_t)HW);
-    out[i] = hole[b * HW + p] ? rgb[i] + r[i] : rgb[i];
+    if (i >= (int64_t)B * HW) return;
+    const int64_t b = i / HW, p = i - b * HW;
+    const bool h = hole[i] != 0;
+    const float* rb = r + b * 4 * HW + p;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int64_t q = (b * 3 + c) * HW + p;
+        out[q] = h ? rgb[q] + rb[(int64_t)c * HW] : rgb[q];
+    }
+    if (err) err[i] = h ? rb[3 * (int64_t)HW] : 0.f;
 }
 
 // Per-block hole counts.
@@ -404,8 +412,10 @@ __global__ __launch_bounds__(256) void k_sum(const float* __restrict__ part, int
     if (threadIdx.x == 0) out[0] = div ? s / (3.f * fmaxf(div[0], 1.f)) : s;
 }
 
-// Masked squared error: per-block partial sums of (pred - target)^2 over
-// hole pixels, and the gradient with respect to r (bf16).
+// Loss terms per hole pixel: sum over channels of (pred - target)^2 plus
+// 3 (e - s)^2, s the pixel's mean squared error (held constant); per-block
+// partial sums (k_sum divides by 3 holes).  Gradient with respect to the
+// output layer (bf16): 2 d_c / (3 N) for the residual, 2 (e - s) / N for e.
 __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ rgb, const uint8_t* __restrict__ hole,
                                               const float* __restrict__ r, const float* __restrict__ target,
                                               const float* __restrict__ n_hole, int B, int HW,
@@ -414,17 +424,29 @@ __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ rgb, con
     __shared__ float red[4];
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     float e = 0.f;
-    if (i < (int64_t)B * 3 * HW) {
-        const int64_t p = i % HW, b = i / (3 * (int64_t)HW);
-        const bool h = hole[b * HW + p] != 0;
-        const float pred = h ? rgb[i] + r[i] : rgb[i];
-        const float d = h ? pred - target[i] : 0.f;
-        e = d * d;
-        g_r[i] = f2bf(2.f * d / (3.f * fmaxf(n_hole[0], 1.f)));
-        if (rgb_out) rgb_out[i] = pred;
+    if (i < (int64_t)B * HW) {
+        const int64_t b = i / HW, p = i - b * HW;
+        const bool h = hole[i] != 0;
+        const float nh = fmaxf(n_hole[0], 1.f);
+        const float* rb = r + b * 4 * HW + p;
+        uint16_t* gb = g_r + b * 4 * HW + p;
+        float d[3], s2 = 0.f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int64_t q = (b * 3 + c) * HW + p;
+            const float pred = h ? rgb[q] + rb[(int64_t)c * HW] : rgb[q];
+            d[c] = h ? pred - target[q] : 0.f;
+            s2 += d[c] * d[c];
+            if (rgb_out) rgb_out[q] = pred;
+        }
+        const float de = h ? rb[3 * (int64_t)HW] - s2 / 3.f : 0.f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) gb[(int64_t)c * HW] = f2bf(2.f * d[c] / (3.f * nh));
+        gb[3 * (int64_t)HW] = f2bf(2.f * de / nh);
+        e = s2 + 3.f * de * de;
     }
-    const float s = block_sum(e, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
+    const float sum = block_sum(e, red);
+    if (threadIdx.x == 0) part[blockIdx.x] = sum;
 }
 
 __global__ __launch_bounds__(256) void k_adam(float* __restrict__ w, const float* __restrict__ g,
@@ -489,17 +511,16 @@ Bufs layout(int B, int H, int W, bool train, char* base) {
     f.e3b = bf(B * 64 * h3);
     f.d2 = bf(B * 32 * h2);
     f.d1 = bf(B * 16 * h1);
-    f.r = fl(B * 3 * h1);
+    f.r = fl(B * 4 * h1);
     for (int l = 0; l < kLayers; ++l) {
         f.wf[l] = bf((size_t)pad16(kNet[l].cout) * 9 * pad16(kNet[l].cin));
         f.wb[l] = bf((size_t)pad16(kNet[l].cin) * 9 * pad16(kNet[l].cout));
     }
-    const int64_t n3 = (int64_t)B * 3 * h1;
     f.cnt_part = fl((B * h1 + 255) / 256);
-    f.loss_part = fl((n3 + 255) / 256);
+    f.loss_part = fl((B * h1 + 255) / 256);
     f.n_hole = fl(1);
     if (train) {
-        f.g_r = bf(B * 3 * h1);
+        f.g_r = bf(B * 4 * h1);
         f.g_d1 = bf(B * 16 * h1);
         f.g_cat1 = bf(B * 48 * h1);
         f.g_d2 = bf(B * 32 * h2);
@@ -602,7 +623,7 @@ void forward(hipStream_t s, int B, int H, int W, const float* params, const floa
     conv(s, B, H2, W2, D2, false, f, f.cat2, 96 * h2, params, f.d2, nullptr, 32 * h2, nullptr, 0);
     hipLaunchKernelGGL(k_up, dim3(blocks(h1), B * 32), dim3(256), 0, s, f.d2, 32, H2, W2, f.cat1, 48 * h1);
     conv(s, B, H, W, D1, false, f, f.cat1, 48 * h1, params, f.d1, nullptr, 16 * h1, nullptr, 0);
-    conv(s, B, H, W, OUT, false, f, f.d1, 16 * h1, params, nullptr, f.r, 3 * h1, nullptr, 0);
+    conv(s, B, H, W, OUT, false, f, f.d1, 16 * h1, params, nullptr, f.r, 4 * h1, nullptr, 0);
 }
 
 void backward(hipStream_t s, int B, int H, int W, const float* params, const Bufs& f, float* grad) {
@@ -610,8 +631,8 @@ void backward(hipStream_t s, int B, int H, int W, const float* params, const Buf
     const int H2 = H / 2, W2 = W / 2, H3 = H / 4, W3 = W / 4;
     uint16_t* e1b = f.cat1 + 32 * h1;
     uint16_t* e2b = f.cat2 + 64 * h2;
-    wgrad(s, B, H, W, OUT, f, f.g_r, 3 * h1, f.d1, 16 * h1, f.chunks1, grad);
-    conv(s, B, H, W, OUT, true, f, f.g_r, 3 * h1, params, f.g_d1, nullptr, 16 * h1, f.d1, 16 * h1);
+    wgrad(s, B, H, W, OUT, f, f.g_r, 4 * h1, f.d1, 16 * h1, f.chunks1, grad);
+    conv(s, B, H, W, OUT, true, f, f.g_r, 4 * h1, params, f.g_d1, nullptr, 16 * h1, f.d1, 16 * h1);
     wgrad(s, B, H, W, D1, f, f.g_d1, 16 * h1, f.cat1, 48 * h1, f.chunks1, grad);
     conv(s, B, H, W, D1, true, f, f.g_d1, 16 * h1, params, f.g_cat1, nullptr, 48 * h1, nullptr, 0);
     hipLaunchKernelGGL(k_up_grad, dim3(blocks(h2), B * 32), dim3(256), 0, s, f.g_cat1, 48 * h1, 32, H, W, f.d2,
@@ -658,8 +679,8 @@ BGS_API int32_t bgs_repair_workspace_size(int32_t batch, int32_t height, int32_t
 }
 
 BGS_API int32_t bgs_repair_forward(const float* params, int32_t batch, int32_t height, int32_t width,
-                                   const float* rgb, const float* z, const uint8_t* hole, float* rgb_out, void* ws,
-                                   size_t ws_bytes, void* hip_stream) {
+                                   const float* rgb, const float* z, const uint8_t* hole, float* rgb_out,
+                                   float* err_out, void* ws, size_t ws_bytes, void* hip_stream) {
     if (!params || !rgb || !z || !hole || !rgb_out || !ws || !sizes_ok(batch, height, width))
         return BGS_ERR_INVALID_ARG;
     const Bufs f = layout(batch, height, width, false, (char*)ws);
@@ -667,9 +688,9 @@ BGS_API int32_t bgs_repair_forward(const float* params, int32_t batch, int32_t h
     hipStream_t s = (hipStream_t)hip_stream;
     (void)hipGetLastError();
     forward(s, batch, height, width, params, rgb, z, hole, f);
-    const int64_t n3 = (int64_t)batch * 3 * height * width;
-    hipLaunchKernelGGL(k_output, dim3(blocks(n3)), dim3(256), 0, s, rgb, hole, (const float*)f.r, batch,
-                       height * width, rgb_out);
+    const int64_t np = (int64_t)batch * height * width;
+    hipLaunchKernelGGL(k_output, dim3(blocks(np)), dim3(256), 0, s, rgb, hole, (const float*)f.r, batch,
+                       height * width, rgb_out, err_out);
     return launched();
 }
 
@@ -684,13 +705,13 @@ BGS_API int32_t bgs_repair_grad(const float* params, int32_t batch, int32_t heig
     (void)hipGetLastError();
     forward(s, batch, height, width, params, rgb, z, hole, f);
     const int HW = height * width;
-    const int64_t np = (int64_t)batch * HW, n3 = 3 * np;
+    const int64_t np = (int64_t)batch * HW;
     hipLaunchKernelGGL(k_count, dim3(blocks(np)), dim3(256), 0, s, hole, np, f.cnt_part);
     hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, (const float*)f.cnt_part, (int)blocks(np), (const float*)nullptr,
                        f.n_hole);
-    hipLaunchKernelGGL(k_loss, dim3(blocks(n3)), dim3(256), 0, s, rgb, hole, (const float*)f.r, target,
+    hipLaunchKernelGGL(k_loss, dim3(blocks(np)), dim3(256), 0, s, rgb, hole, (const float*)f.r, target,
                        (const float*)f.n_hole, batch, HW, rgb_out, f.g_r, f.loss_part);
-    hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, (const float*)f.loss_part, (int)blocks(n3),
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, (const float*)f.loss_part, (int)blocks(np),
                        (const float*)f.n_hole, loss);
     backward(s, batch, height, width, params, f, grad);
     return launched();

@@ -30,7 +30,7 @@ import torch
 from . import _abi, api
 
 # (cin, cout) per layer, in the parameter layout's order.
-LAYERS = [(5, 16), (16, 16), (16, 32), (32, 32), (32, 64), (64, 64), (96, 32), (48, 16), (16, 3)]
+LAYERS = [(5, 16), (16, 16), (16, 32), (32, 32), (32, 64), (64, 64), (96, 32), (48, 16), (16, 4)]
 
 
 def _check(rc, what):
@@ -97,13 +97,15 @@ class Repair:
             raise ValueError("rgb must be [B, 3, H, W]")
         return int(rgb.shape[0]), int(rgb.shape[2]), int(rgb.shape[3])
 
-    def forward(self, rgb, z, hole, out=None):
+    def forward(self, rgb, z, hole, out=None, err=None):
+        """Repaired rgb [B,3,H,W]; err ([B,H,W], optional) receives the
+        predicted squared error at holes."""
         B, H, W = self._shape(rgb)
         out = torch.empty_like(rgb) if out is None else out
         ws = self._workspace(B, H, W, False)
         P = _abi_ptr
-        _check(self.L.bgs_repair_forward(P(self.params), B, H, W, P(rgb), P(z), P(hole), P(out), P(ws), ws.numel(),
-                                         api._stream()), "bgs_repair_forward")
+        _check(self.L.bgs_repair_forward(P(self.params), B, H, W, P(rgb), P(z), P(hole), P(out), P(err), P(ws),
+                                         ws.numel(), api._stream()), "bgs_repair_forward")
         return out
 
     def grad_step(self, rgb, z, hole, target, rgb_out=None):
@@ -208,6 +210,17 @@ def interpolation_fill(pair, cam_dom, cam_aff, roi: api.Roi = api.Roi(center_roi
     return rgb, cls
 
 
+def error_correlation(x, target, hole, err):
+    """Pearson correlation, over hole pixels, of the predicted squared error
+    with the actual one (mean over channels of (x - target)^2)."""
+    m = hole.bool()
+    actual = ((x.clamp(0, 1) - target.clamp(0, 1)) ** 2).mean(0)[m].double()
+    pred = err[m].double()
+    if actual.numel() < 2:
+        return float("nan")
+    return float(torch.corrcoef(torch.stack([pred, actual]))[0, 1])
+
+
 def hole_psnr(a, b, mask):
     m = mask.bool()
     if int(m.sum()) == 0:
@@ -244,7 +257,9 @@ def main(argv=None):
     ctx = api.Context()
     ds = api.DeviceScene(scene)
     for i, p in zip(held, test):
-        x = net.forward(p["rgb"][None].contiguous(), p["z"][None].contiguous(), p["hole"][None].contiguous())[0]
+        err = torch.empty((1,) + tuple(p["hole"].shape), device=p["rgb"].device)
+        x = net.forward(p["rgb"][None].contiguous(), p["z"][None].contiguous(), p["hole"][None].contiguous(),
+                        err=err)[0]
         interp, cls = interpolation_fill(p, cams[i], affs[i])
         filled = (p["hole"] > 0) & ((cls == _abi.CLS_GAP) | (cls == _abi.CLS_ROWFILL))
         # The full method: interpolation plus ROI re-rendering (render_stereo).
@@ -253,7 +268,8 @@ def main(argv=None):
                         psnr_net=round(hole_psnr(x, p["target"], filled), 3),
                         psnr_interp=round(hole_psnr(interp, p["target"], filled), 3),
                         psnr_net_all_holes=round(hole_psnr(x, p["target"], p["hole"]), 3),
-                        psnr_method_all_holes=round(hole_psnr(full, p["target"], p["hole"]), 3)))
+                        psnr_method_all_holes=round(hole_psnr(full, p["target"], p["hole"]), 3),
+                        err_corr=round(error_correlation(x, p["target"], p["hole"], err[0]), 3)))
     # Inference time at full frame size.
     p = test[0]
     args_t = (p["rgb"][None].contiguous(), p["z"][None].contiguous(), p["hole"][None].contiguous())

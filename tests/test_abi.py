@@ -169,8 +169,9 @@ def test_repair_parameter_count_and_argument_checks(L):
         assert L.bgs_repair_workspace_size(B, H, W, 0, C.byref(b)) == _abi.ERR_INVALID_ARG
     assert L.bgs_repair_workspace_size(1, 16, 16, 2, C.byref(b)) == _abi.ERR_INVALID_ARG
     fake = C.c_void_p(0x100000)
-    assert L.bgs_repair_forward(None, 1, 16, 16, fake, fake, fake, fake, fake, 1 << 30, None) == _abi.ERR_INVALID_ARG
-    assert L.bgs_repair_forward(fake, 1, 16, 16, fake, fake, fake, fake, fake, 16, None) == _abi.ERR_WORKSPACE
+    assert L.bgs_repair_forward(None, 1, 16, 16, fake, fake, fake, fake, None, fake, 1 << 30,
+                                None) == _abi.ERR_INVALID_ARG
+    assert L.bgs_repair_forward(fake, 1, 16, 16, fake, fake, fake, fake, None, fake, 16, None) == _abi.ERR_WORKSPACE
     assert L.bgs_repair_grad(fake, 1, 16, 16, fake, fake, fake, fake, fake, fake, None, fake, 16,
                              None) == _abi.ERR_WORKSPACE
     assert L.bgs_repair_adam(fake, fake, fake, fake, 0, 1, 1e-3, 0.9, 0.999, 1e-8, None) == _abi.ERR_INVALID_ARG

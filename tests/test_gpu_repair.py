@@ -29,7 +29,7 @@ def _problem(seed, B, H, W, hole_frac=0.3):
     target = rng.uniform(size=(B, 3, H, W)).astype(np.float32)
     p = repair.init_params(seed)
     # A last layer at full scale, so the residual is not tiny.
-    p[-(3 * 16 * 9 + 3):] *= 10.0
+    p[-(4 * 16 * 9 + 4):] *= 10.0
     p += np.float32(0.01) * rng.normal(size=p.size).astype(np.float32) * (np.abs(p) > 0)
     return p, rgb, z, hole, target
 
@@ -46,7 +46,8 @@ def test_forward_matches_oracle(B, H, W):
     p, rgb, z, hole, target = _problem(1, B, H, W)
     net = repair.Repair(params=p)
     g_rgb, g_z, g_hole = _dev(rgb, z, hole)
-    out = net.forward(g_rgb, g_z, g_hole)
+    err = torch.empty((B, H, W), device="cuda")
+    out = net.forward(g_rgb, g_z, g_hole, err=err)
     torch.cuda.synchronize()
     got = out.cpu().numpy().astype(np.float64)
     a = R.forward(p.astype(np.float64), rgb, z, hole, q=R.bf16)
@@ -54,12 +55,17 @@ def test_forward_matches_oracle(B, H, W):
     # Non-hole pixels pass through untouched.
     np.testing.assert_array_equal(got[np.repeat(hole[:, None] == 0, 3, 1)], rgb[np.repeat(hole[:, None] == 0, 3, 1)])
     r_got = (got - rgb) * hole[:, None]
-    r_want = a["r"] * hole[:, None]
+    r_want = a["r"][:, :3] * hole[:, None]
     scale = np.abs(r_want).max()
     assert scale > 1e-2
     assert np.abs(r_got - r_want).max() <= 1e-2 * scale
     assert np.linalg.norm(r_got - r_want) <= 3e-3 * np.linalg.norm(r_want)
     np.testing.assert_allclose(got, want, atol=1e-2 * scale)
+    # The predicted-error channel, at holes only.
+    e_got = err.cpu().numpy().astype(np.float64)
+    e_want = a["e"] * hole
+    np.testing.assert_array_equal(e_got[hole == 0], 0.0)
+    assert np.abs(e_got - e_want).max() <= 1e-2 * np.abs(e_want).max()
 
 
 @pytest.mark.parametrize("B,H,W", [(2, 16, 72), (1, 8, 12)])
@@ -149,6 +155,10 @@ def test_training_gains_over_interpolation():
         assert int(filled.sum()) > 1000
         gain = repair.hole_psnr(x, p["target"], filled) - repair.hole_psnr(interp, p["target"], filled)
         assert gain >= 3.0, (i, gain)
+        # The predicted-error channel tracks the actual error.
+        err = torch.empty((1,) + tuple(p["hole"].shape), device="cuda")
+        net.forward(p["rgb"][None].contiguous(), p["z"][None].contiguous(), p["hole"][None].contiguous(), err=err)
+        assert repair.error_correlation(x, p["target"], p["hole"], err[0]) > 0.2
         # Pixels outside the holes are the warped image, untouched.
         keep = p["hole"] == 0
         assert torch.equal(x[:, keep], p["rgb"][:, keep])

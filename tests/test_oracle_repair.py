@@ -56,7 +56,10 @@ def _problem(seed, B=2, H=8, W=12):
 
 def test_gradient_matches_finite_differences():
     params, rgb, z, hole, target = _problem(3)
-    loss, g = R.loss_and_grad(params, rgb, z, hole, target)
+    # The error channel's target is held fixed, as in the gradient.
+    s = np.mean(((R.forward(params, rgb, z, hole)["pred"] - target) * hole[:, None]) ** 2, axis=1)
+    loss, g = R.loss_and_grad(params, rgb, z, hole, target, err_target=s)
+    assert loss == R.loss_and_grad(params, rgb, z, hole, target)[0]
     assert loss > 0
     rng = np.random.default_rng(4)
     # A few coordinates of every layer (weights and bias).
@@ -71,13 +74,15 @@ def test_gradient_matches_finite_differences():
         p1[i] += h
         p0 = params.copy()
         p0[i] -= h
-        fd = (R.loss_and_grad(p1, rgb, z, hole, target)[0] - R.loss_and_grad(p0, rgb, z, hole, target)[0]) / (2 * h)
+        fd = (R.loss_and_grad(p1, rgb, z, hole, target, err_target=s)[0]
+              - R.loss_and_grad(p0, rgb, z, hole, target, err_target=s)[0]) / (2 * h)
         assert g[i] == pytest.approx(fd, rel=1e-5, abs=1e-9), i
 
 
 def test_zero_output_layer_gives_the_warped_image():
-    # With the last layer zeroed, r = 0, pred = the warped image, and the
-    # loss is the hole pixels' squared error over 3 x holes.
+    # With the last layer zeroed, r = 0 and e = 0: pred = the warped image,
+    # and the loss is the hole pixels' squared error over 3 x holes plus the
+    # squared per-pixel mean squared error over holes.
     params, rgb, z, hole, target = _problem(5)
     P = R.unpack(params)
     P["out"][0][...] = 0
@@ -86,8 +91,10 @@ def test_zero_output_layer_gives_the_warped_image():
     np.testing.assert_array_equal(a["pred"], rgb)
     loss, _ = R.loss_and_grad(params, rgb, z, hole, target)
     h = hole[:, None] > 0
-    want = np.sum(((rgb - target) * h) ** 2) / (3 * hole.sum())
+    d2 = ((rgb - target) * h) ** 2
+    want = np.sum(d2) / (3 * hole.sum()) + np.sum(np.mean(d2, axis=1) ** 2) / hole.sum()
     assert loss == pytest.approx(want, rel=1e-12)
+    np.testing.assert_array_equal(a["e"], 0.0)
 
 
 def test_input_channels():
@@ -121,4 +128,4 @@ def test_param_layout():
     assert n == sum(co * ci * 9 + co for _, ci, co, _ in R.LAYERS)
     v = np.arange(n, dtype=np.float64)
     np.testing.assert_array_equal(R.pack({k: v_ for k, v_ in R.unpack(v).items()}), v)
-    assert R.unpack(v)["e1a"][0].shape == (16, 5, 3, 3) and R.unpack(v)["out"][1].shape == (3,)
+    assert R.unpack(v)["e1a"][0].shape == (16, 5, 3, 3) and R.unpack(v)["out"][1].shape == (4,)
