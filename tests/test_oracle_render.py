@@ -303,3 +303,58 @@ def test_brute_force_tiny_scene(oracle, lowpass):
     np.testing.assert_allclose(out["rgb"], rgb, atol=1e-9)
     np.testing.assert_allclose(out["depth_raw"], D, atol=1e-9)
     np.testing.assert_allclose(out["alpha"], A, atol=1e-9)
+
+
+@pytest.mark.parametrize("lowpass", [False, True])
+def test_coverage_boxes_match_pixel_loop(oracle, lowpass):
+    """The per-surfel coverage boxes (the checker of conservative binning)
+    equal the bounding boxes of the pixels where an independent evaluation
+    (a batched 3x3 ray-plane solve per pixel, Eq. 1-2, and the low-pass
+    term) reaches alpha >= alpha_min, and a pixel loop over the oracle's own
+    pair evaluation agrees on a sample of surfels."""
+    sc = synth.scene_uniform_cube(21, 30, half=0.7, log_scale=(-2.2, 0.4))
+    cam = synth.look_at((0.2, -2.6, 0.3), (0, 0, 0), (0, 0, 1), 40, 32, 30.0)
+    r = oracle.Raster(lowpass=lowpass)
+    boxes = oracle.coverage_boxes(sc, cam, r)
+    H, W = cam.height, cam.width
+    jj, ii = np.mgrid[0:H, 0:W].astype(np.float64)
+    ray_w = (cam.R @ np.stack([(ii.ravel() - cam.cx) / cam.fx, (jj.ravel() - cam.cy) / cam.fy,
+                                np.ones(H * W)])).T
+    zkey = oracle.center_zkeys(sc, cam)
+    nonempty = 0
+    for k in range(sc.n):
+        if not zkey[k] > cam.z_near:
+            assert list(boxes[k]) == [-1, -1, -1, -1]
+            continue
+        tu, tv = _frame_from_quat(sc.quat[:, k].astype(np.float64))
+        p = sc.pos[:, k].astype(np.float64)
+        su, sv = sc.scale[:, k].astype(np.float64)
+        M = np.stack([np.broadcast_to(su * tu, ray_w.shape), np.broadcast_to(sv * tv, ray_w.shape), -ray_w], axis=2)
+        det = np.linalg.det(M)
+        ok = np.abs(det) > 1e-12
+        sol = np.zeros((H * W, 3))
+        sol[ok] = np.linalg.solve(M[ok], np.broadcast_to(cam.t - p, (int(ok.sum()), 3))[..., None])[..., 0]
+        g3 = np.where(ok & (sol[:, 2] > cam.z_near), np.exp(-0.5 * (sol[:, 0] ** 2 + sol[:, 1] ** 2)), 0.0)
+        g2 = 0.0
+        if lowpass:
+            pc = cam.R.T @ (p - cam.t)
+            mu = (cam.fx * pc[0] / pc[2] + cam.cx, cam.fy * pc[1] / pc[2] + cam.cy)
+            g2 = np.exp(-((ii.ravel() - mu[0]) ** 2 + (jj.ravel() - mu[1]) ** 2))
+        a = np.minimum(0.99, float(sc.opacity[k]) * np.maximum(g3, g2))
+        hit = (a >= 1.0 / 255.0).reshape(H, W)
+        if not hit.any():
+            assert list(boxes[k]) == [-1, -1, -1, -1], k
+            continue
+        nonempty += 1
+        ys, xs = np.nonzero(hit)
+        assert list(boxes[k]) == [xs.min(), ys.min(), xs.max(), ys.max()], k
+    assert nonempty >= 10
+    # The oracle's own pair evaluation, pixel by pixel, on three surfels.
+    for k in [q for q in range(sc.n) if boxes[q, 0] >= 0][:3]:
+        hit = np.zeros((H, W), bool)
+        for j in range(H):
+            for i in range(W):
+                e = oracle.pair(sc, cam, k, i, j, r)
+                hit[j, i] = e is not None and e["alpha"] >= 1.0 / 255.0
+        ys, xs = np.nonzero(hit)
+        assert list(boxes[k]) == [xs.min(), ys.min(), xs.max(), ys.max()]

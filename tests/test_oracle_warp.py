@@ -165,7 +165,22 @@ def test_gap_isolated_hole_is_neighbour_mean(oracle):
             acc = np.float32(acc + rgb[c, 10 + dy, 20 + dx])
         assert out["rgb"][c, 10, 20] == np.float32(acc / np.float32(8))
     assert out["z"][10, 20] == max(z[10 + dy, 20 + dx] for dx, dy in nb)
+    # The weight A is interpolated like a colour channel.
+    acc = np.float32(0)
+    for dx, dy in nb:
+        acc = np.float32(acc + a[10 + dy, 20 + dx])
+    assert out["alpha"][10, 20] == np.float32(acc / np.float32(8))
     assert out["cls"][10, 20] == oracle.CLS_GAP
+    # A hole on the image border averages only its neighbours inside.
+    hole2 = np.zeros((H, W), np.uint8)
+    hole2[0, 0] = 1
+    out2 = _classify(oracle, rgb, z, a, hole2)
+    inside = [(1, 0), (0, 1), (1, 1)]
+    for ch, arr in ((out2["rgb"][1], rgb[1]), (out2["alpha"], a)):
+        acc = np.float32(0)
+        for dx, dy in inside:
+            acc = np.float32(acc + arr[dy, dx])
+        assert ch[0, 0] == np.float32(acc / np.float32(3))
     assert out["n_boxes"] == 0 and out["tile_mask"].sum() == 0
 
 
@@ -218,14 +233,38 @@ def test_row_fill_takes_farther_side(oracle):
     rgb[1, :, 40:] = 1.0   # far side on the right
     z = np.full((H, W), 1.0, np.float32)
     z[:, 40:] = 5.0
-    a = np.ones((H, W), np.float32)
+    a = np.full((H, W), 0.9, np.float32)
+    a[:, 40:] = 0.6
     hole = np.zeros((H, W), np.uint8)
     hole[:, 20:40] = 1
     out = _classify(oracle, rgb, z, a, hole, center=False)
     mid = out["cls"][:, 25:35]
     assert np.all(mid == oracle.CLS_ROWFILL)
     assert np.all(out["rgb"][1, :, 25:35] == 1.0) and np.all(out["z"][:, 25:35] == 5.0)
+    # The fill copies the nearest non-hole pixel after interpolation (the
+    # gap-filled column 38 on the right): colour, depth and weight A alike.
+    assert np.all(out["cls"][:, 38] == oracle.CLS_GAP)
+    for arr in (out["alpha"], out["z"], out["rgb"][0], out["rgb"][1]):
+        assert np.all(arr[:, 25:35] == arr[:, 38:39])
+    assert np.all(np.abs(out["alpha"][:, 25:35] - 0.6) < 1e-6)
     assert out["n_boxes"] == 0
+    # Equal depths on both sides: the left one is kept (right only if
+    # strictly farther); rows too far from any valid pixel for the gap
+    # passes, with no valid pixel on the row, take the background.
+    z2 = np.full((H, W), 2.0, np.float32)
+    hole2 = hole.copy()
+    hole2[10:17, :] = 1
+    bg = (0.25, 0.5, 0.75)
+    dom, _ = rig(W=W, H=H)
+    out2 = oracle.classify(dom, dom, oracle.Roi(center_roi=False), np.array([4.0, 4.0], np.float32), rgb, z2, a,
+                           hole2, bg=bg)
+    for arr in (out2["alpha"], out2["z"], out2["rgb"][0], out2["rgb"][1]):
+        assert np.all(arr[4, 25:35] == arr[4, 21])
+    assert np.all(np.abs(out2["alpha"][4, 25:35] - 0.9) < 1e-6)
+    assert np.all(out2["cls"][13] == oracle.CLS_ROWFILL)
+    for c in range(3):
+        assert np.all(out2["rgb"][c, 13] == np.float32(bg[c]))
+    assert np.all(out2["alpha"][13] == 0) and np.all(np.isinf(out2["z"][13]))
 
 
 def _partition_equal(lab, ref_lab):
@@ -306,3 +345,162 @@ def test_stereo_cube_workload_small(oracle):
     assert np.array_equal(out["aff"]["rgb"][:, roi], full["rgb"][:, roi].astype(np.float32))
     # Edge ROI on the right for a rightward baseline.
     assert out["cls"]["boxes"][0][4] == oracle.BOX_RIGHT
+
+
+# ---------------------------------------------------------------------------
+# Reprojection under rotated relative poses (Eq. 4-5 through world space)
+# ---------------------------------------------------------------------------
+
+def _rot(axis, ang):
+    """Right-handed rotation matrix about a unit axis (Rodrigues)."""
+    k = np.asarray(axis, np.float64)
+    k = k / np.linalg.norm(k)
+    K = np.array([[0, -k[2], k[1]], [k[2], 0, -k[0]], [-k[1], k[0], 0]])
+    return np.eye(3) + math.sin(ang) * K + (1 - math.cos(ang)) * (K @ K)
+
+
+def rotated_rigs():
+    """Affiliated eyes that are turned, not only moved: toed in about the
+    camera's y axis, rolled about its optical axis, pitched about x, and a
+    general turn about an oblique axis, each with a baseline along x."""
+    dom = synth.look_at((0.3, -4.0, 0.2), (0.0, 0.0, 0.1), (0, 0, 1), 120, 90, 140.0, cy=40.0)
+    out = []
+    for axis, ang in (((0, 1, 0), 0.06), ((0, 0, 1), 0.12), ((1, 0, 0), -0.05), ((1, 2, 3), 0.09)):
+        aff = synth.affiliated(dom, 0.064)
+        aff.R = dom.R @ _rot(axis, ang)  # turn about an axis given in the dominant camera frame
+        aff.cx, aff.fx = 58.0, 150.0     # and different intrinsics on the destination side
+        out.append((dom, aff))
+    return out
+
+
+def _world_route(src, dst, i, j, d):
+    """Eq. 4 then Eq. 5 literally: P_w = R_src pi^-1(u, d) + t_src, then
+    X = R_dst^T (P_w - t_dst) and its pinhole projection (Eq. 3)."""
+    X_src = np.stack([d * (i - src.cx) / src.fx, d * (j - src.cy) / src.fy, d], axis=0)
+    P_w = np.asarray(src.R) @ X_src.reshape(3, -1) + np.asarray(src.t).reshape(3, 1)
+    X = np.asarray(dst.R).T @ (P_w - np.asarray(dst.t).reshape(3, 1))
+    u = dst.fx * X[0] / X[2] + dst.cx
+    v = dst.fy * X[1] / X[2] + dst.cy
+    return u, v, X[2]
+
+
+@pytest.mark.parametrize("which", range(4))
+def test_reproject_rotated_rig_matches_world_route(oracle, which):
+    """Every source pixel goes where the world-space route of Eq. 4-5 sends
+    it, with its destination depth, and each destination pixel keeps the
+    nearest arrival (a brute-force z-buffer over that route).  A transposed
+    relative rotation or a translation taken in the wrong frame moves the
+    targets of a turned eye and fails here."""
+    dom, aff = rotated_rigs()[which]
+    W, H = dom.width, dom.height
+    rgb, dr, a = synth.stage_images(W, H, 20 + which)
+    out = oracle.reproject(dom, aff, rgb, dr, a)
+    jj, ii = np.mgrid[0:H, 0:W].astype(np.float64)
+    fg = a >= np.float32(0.5)
+    d = np.where(fg, (dr / np.where(fg, a, 1)).astype(np.float32), 0).astype(np.float64)
+    u, v, Z = _world_route(dom, aff, ii.ravel(), jj.ravel(), d.ravel())
+    # Background pixels: the direction alone turned into the destination
+    # frame (a point at infinity), R_dst^T R_src r.
+    Rrel = np.asarray(aff.R).T @ np.asarray(dom.R)
+    Xb = Rrel @ np.stack([(ii.ravel() - dom.cx) / dom.fx, (jj.ravel() - dom.cy) / dom.fy, np.ones(H * W)])
+    ub = aff.fx * Xb[0] / Xb[2] + aff.cx
+    vb = aff.fy * Xb[1] / Xb[2] + aff.cy
+    f = fg.ravel()
+    uu, vv = np.where(f, u, ub), np.where(f, v, vb)
+    valid = np.where(f, Z > aff.z_near, Xb[2] > 0)
+    tx, ty = np.floor(uu + 0.5), np.floor(vv + 0.5)
+    inside = valid & (tx >= 0) & (tx <= W - 1) & (ty >= 0) & (ty <= H - 1)
+    # Rounding decisions within 1e-9 of a half pixel may go either way
+    # between two exact fp64 routes; such sources are left out below.
+    frac = lambda x: np.abs((x + 0.5) - np.round(x + 0.5))
+    sure = (frac(uu) > 1e-9) & (frac(vv) > 1e-9)
+    zkey = np.where(f, Z.astype(np.float32), np.float32(np.inf))
+    # Brute-force z-buffer over the world route.
+    best = {}
+    for s in np.flatnonzero(inside):
+        t = int(ty[s]) * W + int(tx[s])
+        k = (float(zkey[s]), int(s))
+        if t not in best or k < best[t]:
+            best[t] = k
+    zb = out["zbuf"].ravel()
+    win = (zb & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    hole = out["hole"].ravel()
+    checked = 0
+    for t in range(W * H):
+        if t not in best:
+            assert hole[t] == 1, f"pixel {t} should be a hole"
+            continue
+        s_exp = best[t][1]
+        if not sure[s_exp] or not sure[win[t]]:
+            continue
+        assert hole[t] == 0
+        assert win[t] == s_exp, f"destination {t}: source {win[t]} won, the world route says {s_exp}"
+        z_got = out["z"].ravel()[t]
+        if f[s_exp]:
+            assert abs(float(z_got) - Z[s_exp]) <= 2 * np.spacing(np.float32(Z[s_exp])), (t, z_got, Z[s_exp])
+        else:
+            assert np.isinf(z_got)
+        checked += 1
+    assert checked > 0.5 * W * H
+    # The turn is real: many pixels move by more than a pixel against the
+    # unrotated rig.
+    plain = oracle.reproject(dom, synth.affiliated(dom, 0.064), rgb, dr, a)
+    assert (plain["hole"] != out["hole"]).mean() > 0.01 or not np.array_equal(plain["zbuf"], out["zbuf"])
+
+
+def test_pure_rotation_moves_principal_ray_closed_form(oracle):
+    """Zero baseline, destination turned by theta about its y axis: the
+    source principal ray lands at u = cx' - fx' tan(theta) on the
+    destination's centre row, at any depth (Eq. 5 with R_dst = R_src Ry)."""
+    dom = synth.look_at((0.0, -4.0, 0.0), (0, 0, 0), (0, 0, 1), 101, 81, 120.0)
+    for th in (0.05, -0.11, 0.2):
+        aff = dom.copy()
+        aff.R = dom.R @ _rot((0, 1, 0), th)
+        rgb, dr, a = plane_images(101, 81, 3.0, seed=3)
+        out = oracle.reproject(dom, aff, rgb, dr, a)
+        src = 40 * 101 + 50  # the principal point (50, 40)
+        u = aff.cx - aff.fx * math.tan(th)
+        t = 40 * 101 + math.floor(u + 0.5)
+        assert int(out["zbuf"].ravel()[t] & np.uint64(0xFFFFFFFF)) == src
+        # Its depth is the source depth times cos(theta) (Z' = R_y^T X along the ray).
+        assert out["z"].ravel()[t] == np.float32(3.0 * math.cos(th))
+
+
+@pytest.mark.parametrize("which", range(4))
+@pytest.mark.parametrize("edge_bounds", [0, 1])
+def test_edge_rois_rotated_rig_match_world_route(oracle, which, edge_bounds):
+    """Eq. 6 extrema of the edge samples at both depth hypotheses, taken
+    through the world-space route, give the oracle's border widths (Eq.
+    7-8) on turned eyes."""
+    dom, aff = rotated_rigs()[which]
+    roi = oracle.Roi(edge_bounds=edge_bounds, margin=8)
+    dr = np.array([1.5, 6.0], np.float32)
+    widths, _ = oracle.edge_rois(dom, aff, roi, dr)
+    N, Ws, Hs = roi.edge_samples, dom.width, dom.height
+    pos = lambda L: [int(math.floor(k * (L - 1) / (N - 1) + 0.5)) for k in range(N)]
+    edges = [[(i, 0) for i in pos(Ws)], [(i, Hs - 1) for i in pos(Ws)], [(0, j) for j in pos(Hs)],
+             [(Ws - 1, j) for j in pos(Hs)]]
+    ext = dict(x=[], y=[])
+    per = [[], [], [], []]
+    for e, pts in enumerate(edges):
+        for (i, j) in pts:
+            for d in (float(dr[0]), float(dr[1])):
+                u, v, Z = _world_route(dom, aff, np.float64(i), np.float64(j), np.float64(d))
+                if Z[0] > aff.z_near:
+                    ext["x"].append(u[0])
+                    ext["y"].append(v[0])
+                    per[e].append((u[0], v[0]))
+    xmin, xmax, ymin, ymax = min(ext["x"]), max(ext["x"]), min(ext["y"]), max(ext["y"])
+    if edge_bounds:
+        if per[2]: xmin = max(p[0] for p in per[2])
+        if per[3]: xmax = min(p[0] for p in per[3])
+        if per[0]: ymin = max(p[1] for p in per[0])
+        if per[1]: ymax = min(p[1] for p in per[1])
+    W, H, m = aff.width, aff.height, roi.margin
+    for x in (xmin, xmax, ymin, ymax):
+        assert abs(x - round(x)) > 1e-7, "an extremum sits on an integer: widths would hinge on rounding"
+    exp = [min(max(math.ceil(xmin) + m, 0), W // 2) if xmin > 0 else 0,
+           min(max((W - 1) - math.floor(xmax) + m, 0), W // 2) if xmax < W - 1 else 0,
+           min(max(math.ceil(ymin) + m, 0), H // 2) if ymin > 0 else 0,
+           min(max((H - 1) - math.floor(ymax) + m, 0), H // 2) if ymax < H - 1 else 0]
+    assert list(widths) == exp
