@@ -213,8 +213,12 @@ BGS_API int32_t bgs_workspace_size(int64_t n, int32_t width, int32_t height, int
                                    size_t* bytes);
 
 /* Status of the last asynchronous render on this context: number of keys
- * of the last dominant and ROI passes and the overflow flags.  Waits for
- * the context's stream. */
+ * of the last dominant and ROI passes and the overflow flags.  The
+ * overflow bits are those of ANY frame rendered with this workspace since
+ * the previous poll (each frame's reset folds the last frame's bits into a
+ * sticky word that only this call clears), so one poll after a run of
+ * asynchronous frames tells whether any of them ran out of capacity.
+ * Waits for the context's stream. */
 BGS_API int32_t bgs_poll_status(bgs_ctx* ctx, void* ws, size_t ws_bytes, bgs_stats* stats);
 
 /* Stage 1 (Sec. 3.1, Sec. 3.3): full tile rasterisation of one eye.

@@ -87,6 +87,68 @@ def _ptr(t):
     return C.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def check_tensor(name, t, shape, dtype, device=None):
+    """Raise ValueError unless t is a contiguous tensor of exactly this
+    shape and dtype (and on this device, when given): the library writes
+    through raw pointers sized from the camera, so a smaller or differently
+    typed buffer would be overrun."""
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a tensor, got {type(t).__name__}")
+    if tuple(t.shape) != tuple(int(x) for x in shape):
+        raise ValueError(f"{name}: shape {tuple(t.shape)}, expected {tuple(int(x) for x in shape)}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if device is not None:
+        dev = torch.device(device)
+        if t.device.type != dev.type or (dev.index is not None and t.device.index != dev.index):
+            raise ValueError(f"{name}: on {t.device}, expected {dev}")
+
+
+def check_boxes(boxes, box_capacity, device):
+    """A box list with room for at least box_capacity boxes of 6 int32."""
+    if box_capacity < 0:
+        raise ValueError("box_capacity must be >= 0")
+    rows = boxes.shape[0] if isinstance(boxes, torch.Tensor) and boxes.dim() == 2 else -1
+    check_tensor("boxes", boxes, (max(rows, 0), 6), torch.int32, device)
+    if rows < max(box_capacity, 1):
+        raise ValueError(f"boxes: room for {rows} boxes, box_capacity is {box_capacity}")
+
+
+def _dev(device):
+    """The concrete device the library's calls run on."""
+    d = torch.device(device)
+    if d.type == "cuda" and d.index is None:
+        return torch.device("cuda", torch.cuda.current_device())
+    return d
+
+
+def check_render_out(out, H, W, device):
+    """Outputs of a full render of an H x W camera."""
+    check_tensor("rgb", out["rgb"], (3, H, W), torch.float32, device)
+    check_tensor("depth_raw", out["depth_raw"], (H, W), torch.float32, device)
+    check_tensor("alpha", out["alpha"], (H, W), torch.float32, device)
+
+
+def check_stereo_out(out, cam_dom, cam_aff, box_capacity, tile, device):
+    """Outputs of a stereo frame: dominant-eye images at its size, the
+    affiliated eye's images and class maps at its own size."""
+    Hd, Wd, Ha, Wa = int(cam_dom.height), int(cam_dom.width), int(cam_aff.height), int(cam_aff.width)
+    f32, u8, i32 = torch.float32, torch.uint8, torch.int32
+    check_tensor("rgb_dom", out["rgb_dom"], (3, Hd, Wd), f32, device)
+    check_tensor("depth_raw_dom", out["depth_raw_dom"], (Hd, Wd), f32, device)
+    check_tensor("alpha_dom", out["alpha_dom"], (Hd, Wd), f32, device)
+    check_tensor("rgb_aff", out["rgb_aff"], (3, Ha, Wa), f32, device)
+    check_tensor("z_aff", out["z_aff"], (Ha, Wa), f32, device)
+    check_tensor("alpha_aff", out["alpha_aff"], (Ha, Wa), f32, device)
+    check_tensor("cls_aff", out["cls_aff"], (Ha, Wa), u8, device)
+    check_tensor("labels", out["labels"], (Ha, Wa), i32, device)
+    check_boxes(out["boxes"], box_capacity, device)
+    check_tensor("n_boxes", out["n_boxes"], (1,), i32, device)
+    check_tensor("tile_mask", out["tile_mask"], ((Ha + tile - 1) // tile, (Wa + tile - 1) // tile), u8, device)
+
+
 def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
@@ -202,6 +264,7 @@ class Context:
         if out is None:
             out = dict(rgb=torch.empty((3, H, W), device=self.device), depth_raw=torch.empty((H, W), device=self.device),
                        alpha=torch.empty((H, W), device=self.device))
+        check_render_out(out, H, W, _dev(self.device))
         if self.ws is None:
             self.workspace(scene.n, W, H, max(1 << 16, 8 * scene.n))
         nk = C.c_int64(0)
@@ -225,6 +288,16 @@ class Context:
                        alpha=torch.empty((H, W), device=self.device),
                        hole=torch.empty((H, W), dtype=torch.uint8, device=self.device),
                        depth_range=torch.empty(2, device=self.device))
+        dev = _dev(self.device)
+        Hs, Ws = int(src.height), int(src.width)
+        check_tensor("rgb_src", rgb, (3, Hs, Ws), torch.float32, dev)
+        check_tensor("depth_raw_src", depth_raw, (Hs, Ws), torch.float32, dev)
+        check_tensor("alpha_src", alpha, (Hs, Ws), torch.float32, dev)
+        check_tensor("rgb", out["rgb"], (3, H, W), torch.float32, dev)
+        check_tensor("z", out["z"], (H, W), torch.float32, dev)
+        check_tensor("alpha", out["alpha"], (H, W), torch.float32, dev)
+        check_tensor("hole", out["hole"], (H, W), torch.uint8, dev)
+        check_tensor("depth_range", out["depth_range"], (2,), torch.float32, dev)
         ws = self.ws if self.ws is not None else self.workspace(0, W, H, 0)
         if ws.numel() < self._ws_bytes(0, W, H, 0):
             ws = self.workspace(0, W, H, 0)
@@ -252,6 +325,16 @@ class Context:
                        n_boxes=torch.empty(1, dtype=torch.int32, device=self.device),
                        tile_mask=torch.empty(((H + T - 1) // T, (W + T - 1) // T), dtype=torch.uint8,
                                              device=self.device))
+        dev = _dev(self.device)
+        check_tensor("depth_range", depth_range, (2,), torch.float32, dev)
+        check_tensor("rgb", rgb, (3, H, W), torch.float32, dev)
+        check_tensor("z", z, (H, W), torch.float32, dev)
+        check_tensor("alpha", alpha, (H, W), torch.float32, dev)
+        check_tensor("cls", cls, (H, W), torch.uint8, dev)
+        check_tensor("labels", out["labels"], (H, W), torch.int32, dev)
+        check_boxes(out["boxes"], box_capacity, dev)
+        check_tensor("n_boxes", out["n_boxes"], (1,), torch.int32, dev)
+        check_tensor("tile_mask", out["tile_mask"], ((H + T - 1) // T, (W + T - 1) // T), torch.uint8, dev)
         ws = self.ws if self.ws is not None else self.workspace(0, W, H, 0)
         if ws.numel() < self._ws_bytes(0, W, H, 0):
             ws = self.workspace(0, W, H, 0)
@@ -267,6 +350,13 @@ class Context:
                    roi: Roi = Roi()):
         self.bind_stream()
         W, H = int(dst.width), int(dst.height)
+        T = roi.tile
+        dev = _dev(self.device)
+        check_tensor("tile_mask", tile_mask, ((H + T - 1) // T, (W + T - 1) // T), torch.uint8, dev)
+        check_tensor("rgb", rgb, (3, H, W), torch.float32, dev)
+        check_tensor("z", z, (H, W), torch.float32, dev)
+        check_tensor("alpha", alpha, (H, W), torch.float32, dev)
+        check_tensor("cls", cls, (H, W), torch.uint8, dev)
         if self.ws is None:
             self.workspace(scene.n, W, H, max(1 << 16, 4 * scene.n))
         nk = C.c_int64(0)
@@ -301,6 +391,7 @@ class Context:
                 n_boxes=torch.empty(1, dtype=torch.int32, device=d),
                 tile_mask=torch.empty(((cam_aff.height + T - 1) // T, (cam_aff.width + T - 1) // T),
                                       dtype=torch.uint8, device=d))
+        check_stereo_out(out, cam_dom, cam_aff, box_capacity, T, _dev(d))
         if self.ws is None:
             self.workspace(scene.n, W, H, max(1 << 16, 8 * scene.n))
         st = _abi.Stats()
@@ -327,6 +418,8 @@ class Context:
         """Stable in-place radix sort of uint32 (as int32 tensors) pairs."""
         self.bind_stream()
         n = keys.numel()
+        check_tensor("keys", keys, (n,), torch.int32, _dev(self.device))
+        check_tensor("values", values, (n,), torch.int32, _dev(self.device))
         need = C.c_size_t()
         self._check(self.L.bgs_sort_workspace_size(n, C.byref(need)))
         ws = torch.empty(max(int(need.value), 1), dtype=torch.uint8, device=self.device)
@@ -336,6 +429,7 @@ class Context:
     def label_components(self, mask, conn=8):
         self.bind_stream()
         H, W = mask.shape
+        check_tensor("mask", mask, (H, W), torch.uint8, _dev(self.device))
         labels = torch.empty((H, W), dtype=torch.int32, device=self.device)
         self._check(self.L.bgs_label_components(self.h, _ptr(mask), int(W), int(H), int(conn), _ptr(labels)))
         return labels

@@ -29,6 +29,9 @@ struct bgs_ctx {
     double total_ms[BGS_NUM_STAGES] = {};
     int64_t count[BGS_NUM_STAGES] = {};
     std::string err;
+    // The workspace whose status block this context last reset: a new one is
+    // zeroed completely (its sticky overflow word included) before first use.
+    const void* ws_seen = nullptr;
 };
 
 namespace bgs {
@@ -462,6 +465,14 @@ int raster_pass(bgs_ctx* ctx, const Layout& L, void* ws, int64_t kc, const bgs_s
     return BGS_OK;
 }
 
+// Start-of-frame status reset: zero the block, keeping the overflow bits of
+// earlier frames (sticky until polled) once this context has used the workspace.
+hipError_t reset_status(bgs_ctx* ctx, void* ws, DevStatus* st) {
+    const int full = ws != ctx->ws_seen;
+    ctx->ws_seen = ws;
+    return launch_status_reset(st, full, ctx->stream);
+}
+
 int finish(bgs_ctx* ctx, void* ws, const Layout& L, DevStatus* host) {
     HIP_CHECK(hipMemcpyAsync(host, at<DevStatus>(ws, L.status), sizeof(DevStatus), hipMemcpyDeviceToHost, ctx->stream),
               "status readback");
@@ -584,6 +595,12 @@ int32_t bgs_poll_status(bgs_ctx* ctx, void* ws, size_t ws_bytes, bgs_stats* stat
     int rc = finish(ctx, ws, L, &h);
     if (rc) return rc;
     fill_stats(h, stats);
+    // Overflow of any frame since the last poll, not only of the last one.
+    stats->overflow = (int32_t)(h.overflow | h.sticky);
+    if (ws == ctx->ws_seen) {
+        HIP_CHECK(launch_fill_u32(&at<DevStatus>(ws, 0)->sticky, 1, 0u, ctx->stream), "sticky clear");
+        HIP_CHECK(hipStreamSynchronize(ctx->stream), "stream sync");
+    }
     return BGS_OK;
 }
 
@@ -599,7 +616,7 @@ int32_t bgs_render_dominant(bgs_ctx* ctx, const bgs_scene* scene, const bgs_came
     if (kc < 0) return fail(ctx, BGS_ERR_WORKSPACE, "workspace of %zu bytes is too small", ws_bytes);
     const Layout L = make_layout(scene->n, cam->width, cam->height, kc);
     DevStatus* st = at<DevStatus>(ws, L.status);
-    HIP_CHECK(hipMemsetAsync(st, 0, sizeof(DevStatus), ctx->stream), "status reset");
+    HIP_CHECK(reset_status(ctx, ws, st), "status reset");
     rc = raster_pass(ctx, L, ws, kc, *scene, *cam, *raster, nullptr, 0.f, RasterOut{rgb, depth_raw, alpha, nullptr}, 0);
     if (rc) return rc;
     if (!ctx->sync) return BGS_OK;
@@ -672,7 +689,7 @@ int32_t bgs_patch_rois(bgs_ctx* ctx, const bgs_scene* scene, const bgs_camera* d
     if (kc < 0) return fail(ctx, BGS_ERR_WORKSPACE, "workspace of %zu bytes is too small", ws_bytes);
     const Layout L = make_layout(scene->n, dst->width, dst->height, kc);
     DevStatus* st = at<DevStatus>(ws, L.status);
-    HIP_CHECK(hipMemsetAsync(st, 0, sizeof(DevStatus), ctx->stream), "status reset");
+    HIP_CHECK(reset_status(ctx, ws, st), "status reset");
     rc = raster_pass(ctx, L, ws, kc, *scene, *dst, *raster, tile_mask, roi->a_min, RasterOut{rgb_dst, z_dst, alpha_dst, cls},
                      1);
     if (rc) return rc;
@@ -707,7 +724,7 @@ int32_t bgs_render_stereo(bgs_ctx* ctx, const bgs_scene* scene, const bgs_camera
     const Layout L = make_layout(scene->n, W, H, kc);
     hipStream_t s = ctx->stream;
     DevStatus* st = at<DevStatus>(ws, L.status);
-    HIP_CHECK(hipMemsetAsync(st, 0, sizeof(DevStatus), s), "status reset");
+    HIP_CHECK(reset_status(ctx, ws, st), "status reset");
     // Stage 1: dominant eye with the depth proxy.
     const uint32_t* dom_order = nullptr;
     rc = raster_pass(ctx, L, ws, kc, *scene, *cam_dom, *raster, nullptr, 0.f,
@@ -862,7 +879,7 @@ int32_t bgs_tile_lists_debug(bgs_ctx* ctx, const bgs_scene* scene, const bgs_cam
     if (kc < 0) return fail(ctx, BGS_ERR_WORKSPACE, "workspace too small");
     const Layout L = make_layout(scene->n, cam->width, cam->height, kc);
     DevStatus* st = at<DevStatus>(ws, L.status);
-    HIP_CHECK(hipMemsetAsync(st, 0, sizeof(DevStatus), ctx->stream), "status reset");
+    HIP_CHECK(reset_status(ctx, ws, st), "status reset");
     // A render whose outputs go to scratch pixel buffers; the binning it
     // leaves in the workspace is what is copied out.
     const int64_t np = (int64_t)cam->width * cam->height;

@@ -104,7 +104,11 @@ struct DevStatus {
     uint32_t n_keys_dom;
     uint32_t n_keys_roi;
     uint32_t overflow;     // bit 0 key capacity, bit 1 box capacity
-    uint32_t n_holes, n_gap, n_center, n_rowfill, n_boxes, n_roi_tiles, n_edge, pad;
+    uint32_t n_holes, n_gap, n_center, n_rowfill, n_boxes, n_roi_tiles, n_edge;
+    // Overflow bits of every earlier frame since the last bgs_poll_status:
+    // the per-frame reset folds the previous frame's overflow into it, and
+    // only the poll clears it.
+    uint32_t sticky;
     // Depth-range reduction over positive fp32 bits: the complement of the
     // minimum (so that a zeroed block means "none yet") and the maximum.
     uint32_t dmin_inv, dmax_bits;
@@ -118,6 +122,15 @@ struct DevStatus {
     int32_t edge_boxes[4 * 6];
     int32_t widths[4];
 };
+
+// ---- status and fills (sort.hip) --------------------------------------------
+// Start-of-frame reset of the status block by a kernel (no memset node, so a
+// frame can be captured in a graph): full = 1 zeroes every word; full = 0
+// keeps the sticky overflow word and ORs the previous frame's overflow bits
+// into it.
+hipError_t launch_status_reset(DevStatus* st, int full, hipStream_t s);
+// dst[i] = value for i < n, by a kernel.
+hipError_t launch_fill_u32(uint32_t* dst, int64_t n, uint32_t value, hipStream_t s);
 
 // ---- scan / sort (sort.hip) -------------------------------------------------
 size_t scan_tmp_elems(int64_t n);

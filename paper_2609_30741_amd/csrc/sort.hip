@@ -176,6 +176,34 @@ size_t scan_tmp_elems(int64_t n) {
     return tot;
 }
 
+__global__ void k_status_reset(DevStatus* st, int full) {
+    constexpr int kWords = (int)(sizeof(DevStatus) / 4);
+    constexpr int kSticky = (int)(offsetof(DevStatus, sticky) / 4);
+    __shared__ uint32_t keep;
+    if (threadIdx.x == 0) keep = full ? 0u : (st->sticky | st->overflow);
+    __syncthreads();
+    uint32_t* w = reinterpret_cast<uint32_t*>(st);
+    for (int i = threadIdx.x; i < kWords; i += blockDim.x) w[i] = i == kSticky ? keep : 0u;
+}
+
+hipError_t launch_status_reset(DevStatus* st, int full, hipStream_t s) {
+    static_assert(sizeof(DevStatus) % 4 == 0, "status block is made of 32-bit words");
+    hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(128), 0, s, st, full);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_u32(uint32_t* dst, int64_t n, uint32_t value) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = value;
+}
+
+hipError_t launch_fill_u32(uint32_t* dst, int64_t n, uint32_t value, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>(ceil_div(n, 256), 2048);
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, dst, n, value);
+    return hipGetLastError();
+}
+
 hipError_t exclusive_scan(const uint32_t* in, const uint32_t* idx, uint32_t* out, const uint32_t* n_dev,
                           int64_t n_cap, uint32_t* tmp, hipStream_t s) {
     const int64_t nb = ceil_div(n_cap + 1, kScanBlock);
@@ -187,7 +215,7 @@ hipError_t exclusive_scan(const uint32_t* in, const uint32_t* idx, uint32_t* out
         hipError_t e = exclusive_scan(partials, nullptr, partials, nullptr, nb, tmp + nb + 64, s);
         if (e != hipSuccess) return e;
     } else {
-        hipError_t e = hipMemsetAsync(partials, 0, sizeof(uint32_t), s);
+        hipError_t e = launch_fill_u32(partials, 1, 0u, s);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(256), 0, s, in, idx, n_dev, n_cap, partials, out);

@@ -93,15 +93,33 @@ class Repair:
 
     @staticmethod
     def _shape(rgb):
-        if rgb.dim() != 4 or rgb.shape[1] != 3:
+        if not isinstance(rgb, torch.Tensor) or rgb.dim() != 4 or rgb.shape[1] != 3:
             raise ValueError("rgb must be [B, 3, H, W]")
         return int(rgb.shape[0]), int(rgb.shape[2]), int(rgb.shape[3])
+
+    @staticmethod
+    def check_images(rgb, z, hole, out=None, err=None, target=None, device=None):
+        """Every image buffer against the batch's shape: rgb, out and target
+        [B,3,H,W] fp32, z and err [B,H,W] fp32, hole [B,H,W] uint8, all
+        contiguous on rgb's device (the kernels write err and out through
+        raw pointers sized from rgb).  Returns (B, H, W)."""
+        B, H, W = Repair._shape(rgb)
+        dev = rgb.device if device is None else device
+        api.check_tensor("rgb", rgb, (B, 3, H, W), torch.float32, dev)
+        api.check_tensor("z", z, (B, H, W), torch.float32, dev)
+        api.check_tensor("hole", hole, (B, H, W), torch.uint8, dev)
+        for name, t in (("out", out), ("target", target)):
+            if t is not None:
+                api.check_tensor(name, t, (B, 3, H, W), torch.float32, dev)
+        if err is not None:
+            api.check_tensor("err", err, (B, H, W), torch.float32, dev)
+        return B, H, W
 
     def forward(self, rgb, z, hole, out=None, err=None):
         """Repaired rgb [B,3,H,W]; err ([B,H,W], optional) receives the
         predicted squared error at holes."""
-        B, H, W = self._shape(rgb)
         out = torch.empty_like(rgb) if out is None else out
+        B, H, W = self.check_images(rgb, z, hole, out=out, err=err)
         ws = self._workspace(B, H, W, False)
         P = _abi_ptr
         _check(self.L.bgs_repair_forward(P(self.params), B, H, W, P(rgb), P(z), P(hole), P(out), P(err), P(ws),
@@ -110,7 +128,7 @@ class Repair:
 
     def grad_step(self, rgb, z, hole, target, rgb_out=None):
         """Loss and gradient into self.loss / self.grad (asynchronous)."""
-        B, H, W = self._shape(rgb)
+        B, H, W = self.check_images(rgb, z, hole, out=rgb_out, target=target)
         ws = self._workspace(B, H, W, True)
         P = _abi_ptr
         _check(self.L.bgs_repair_grad(P(self.params), B, H, W, P(rgb), P(z), P(hole), P(target), P(self.grad),

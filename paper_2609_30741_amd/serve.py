@@ -10,11 +10,20 @@ Scenes stay resident on the device for the server's lifetime.  Latency is
 completion minus arrival; completion is read from GPU events, so the host's
 polling interval does not enter it.
 
-The scheduler (`serve`) is plain Python over an executor with four calls
-(need_bytes, issue, poll, release), so its admission logic is testable
-without a GPU; `GpuExecutor` runs each frame through the library
-(`Context.render_stereo`, or two `render_dominant` calls for the two-pass
-baseline), one context and one default-priority stream per slot.
+The scheduler (`serve`) is plain Python over an executor with six calls
+(need_bytes, held_bytes, trim, issue, poll, release), so its admission
+logic is testable without a GPU; `GpuExecutor` runs each frame through the
+library (`Context.render_stereo`, or two `render_dominant` calls for the
+two-pass baseline), one context and one default-priority stream per slot.
+
+Memory is accounted by what the slots actually hold, not by what the
+requests in flight asked for: a slot keeps its workspace and output images
+after its frame (so the next frame of the same size allocates nothing),
+and those bytes stay charged to the budget until the slot is trimmed.  A
+request is admitted into a free slot when the bytes every other slot holds
+plus its own need fit in the budget; idle slots are trimmed (their buffers
+freed) to make room before the request waits.  The bytes held by all slots
+together therefore never exceed the budget.
 
     python -m paper_2609_30741_amd.serve [--workload serve2064] [--rate 90]
         [--requests 300] [--slots 4] [--mode stereo|two_pass]
@@ -68,7 +77,6 @@ def serve(requests: List[Request], executor, n_slots: int, mem_budget: float,
     queue: collections.deque = collections.deque()
     busy: Dict[int, Request] = {}
     free = list(range(n_slots))
-    used = 0.0
     executor.start()  # the GPU clock's zero, then the host's
     t0 = clock()
     while pending or queue or busy:
@@ -81,7 +89,6 @@ def serve(requests: List[Request], executor, n_slots: int, mem_budget: float,
             t = executor.poll(s)
             if t is not None:
                 r.done = t
-                used -= executor.need_bytes(r)
                 executor.release(s, r)
                 del busy[s]
                 free.append(s)
@@ -91,13 +98,21 @@ def serve(requests: List[Request], executor, n_slots: int, mem_budget: float,
             need = executor.need_bytes(r)
             if need > mem_budget:
                 raise ValueError(f"request {r.rid} needs {need:.3g} B, more than the whole budget {mem_budget:.3g} B")
-            if used + need > mem_budget:
-                break  # waits for memory, not only for a slot
+            # Prefer a free slot that already holds buffers of this size.
+            s = next((q for q in free if executor.held_bytes(q) == need), free[0])
+            others = sum(executor.held_bytes(q) for q in range(n_slots) if q != s)
+            for q in free:
+                if others + need <= mem_budget:
+                    break
+                if q != s and executor.held_bytes(q) > 0:
+                    others -= executor.held_bytes(q)
+                    executor.trim(q)
+            if others + need > mem_budget:
+                break  # waits for memory held by running frames, not only for a slot
             queue.popleft()
-            s = free.pop(0)
+            free.remove(s)
             r.slot = s
             r.admitted = clock() - t0
-            used += need
             executor.issue(s, r)
             busy[s] = r
             progressed = True
@@ -129,6 +144,7 @@ class GpuExecutor:
         self.raster = raster or api.Raster()
         self.roi = roi or api.Roi()
         self.keep = keep_outputs
+        self.box_capacity = 4096
         self.scenes = {k: api.DeviceScene(s) for k, s in scenes.items()}
         self.key_capacity = key_capacity
         self.streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(n_slots - 1)]
@@ -140,13 +156,41 @@ class GpuExecutor:
                 self.outs.append(None)
         self.start_ev = torch.cuda.Event(enable_timing=True)
 
-    def need_bytes(self, r: Request) -> float:
+    def _sizes(self, r: Request):
         sc = self.scenes[r.scene]
         W = max(r.cam_dom.width, r.cam_aff.width)
         H = max(r.cam_dom.height, r.cam_aff.height)
-        ws = self.ctxs[0]._ws_bytes(sc.n, W, H, self.key_capacity)
-        images = W * H * (2 * 5 * 4 + 4 + 1 + 4)  # two eyes' rgb/depth/alpha, z, class map, labels
-        return float(ws + images)
+        return sc.n, W, H
+
+    def _out_bytes(self, r: Request) -> int:
+        """Bytes of the output images a frame of this request writes."""
+        pd = int(r.cam_dom.width) * int(r.cam_dom.height)
+        pa = int(r.cam_aff.width) * int(r.cam_aff.height)
+        if self.mode != "stereo":
+            return 20 * (pd + pa)  # rgb, depth, alpha per eye
+        T = self.roi.tile
+        tiles = ((int(r.cam_aff.width) + T - 1) // T) * ((int(r.cam_aff.height) + T - 1) // T)
+        # dominant rgb/depth/alpha; affiliated rgb/z/alpha, class map, labels; boxes, count, tile mask
+        return 20 * pd + 25 * pa + 6 * 4 * self.box_capacity + 4 + tiles
+
+    def need_bytes(self, r: Request) -> float:
+        n, W, H = self._sizes(r)
+        return float(self.ctxs[0]._ws_bytes(n, W, H, self.key_capacity) + self._out_bytes(r))
+
+    def held_bytes(self, s: int) -> float:
+        ws = self.ctxs[s].ws
+        held = 0 if ws is None else ws.numel()
+        o = self.outs[s]
+        if o is not None:
+            ts = [t for d in ((o["dom"], o["aff"]) if "dom" in o else (o,)) for t in d.values()
+                  if isinstance(t, self.torch.Tensor)]
+            held += sum(t.numel() * t.element_size() for t in ts)
+        return float(held)
+
+    def trim(self, s: int):
+        """Free an idle slot's workspace and output images."""
+        self.ctxs[s].ws = None
+        self.outs[s] = None
 
     def start(self):
         torch = self.torch
@@ -157,22 +201,32 @@ class GpuExecutor:
     def issue(self, s: int, r: Request):
         torch = self.torch
         sc = self.scenes[r.scene]
-        W = max(r.cam_dom.width, r.cam_aff.width)
-        H = max(r.cam_dom.height, r.cam_aff.height)
+        n, W, H = self._sizes(r)
         ctx = self.ctxs[s]
         with torch.cuda.stream(self.streams[s]):
-            ctx.reserve(sc.n, W, H, self.key_capacity)
+            # The slot's buffers are replaced unless they are exactly this
+            # request's: it then holds what need_bytes charged for it.
+            ws_need = ctx._ws_bytes(n, W, H, self.key_capacity)
+            if ctx.ws is not None and ctx.ws.numel() != ws_need:
+                ctx.ws = None
+            ctx.reserve(n, W, H, self.key_capacity)
+            o = self.outs[s]
+            if o is not None and self.held_bytes(s) != self.need_bytes(r):
+                o = None
             if self.mode == "stereo":
-                o = self.outs[s]
-                if o is not None and tuple(o["rgb_aff"].shape[1:]) != (r.cam_aff.height, r.cam_aff.width):
+                if o is not None and not self._stereo_fits(o, r):
                     o = None
-                o = ctx.render_stereo(sc, r.cam_dom, r.cam_aff, self.raster, self.roi, out=o)
+                o = ctx.render_stereo(sc, r.cam_dom, r.cam_aff, self.raster, self.roi,
+                                      box_capacity=self.box_capacity, out=o)
                 self.outs[s] = o
                 keys = ("rgb_dom", "depth_raw_dom", "alpha_dom", "rgb_aff", "z_aff", "alpha_aff", "cls_aff")
             else:
-                o = self.outs[s] or {}
-                a = ctx.render_dominant(sc, r.cam_dom, self.raster, out=o.get("dom"))
-                b = ctx.render_dominant(sc, r.cam_aff, self.raster, out=o.get("aff"))
+                o = o or {}
+                fits = lambda d, c: d is not None and tuple(d["rgb"].shape[1:]) == (c.height, c.width)
+                a = ctx.render_dominant(sc, r.cam_dom, self.raster,
+                                        out=o.get("dom") if fits(o.get("dom"), r.cam_dom) else None)
+                b = ctx.render_dominant(sc, r.cam_aff, self.raster,
+                                        out=o.get("aff") if fits(o.get("aff"), r.cam_aff) else None)
                 o = {"dom": a, "aff": b}
                 self.outs[s] = o
                 keys = ()
@@ -183,6 +237,16 @@ class GpuExecutor:
             ev = torch.cuda.Event(enable_timing=True)
             ev.record(self.streams[s])
             self.events[s] = ev
+
+    def _stereo_fits(self, o, r: Request) -> bool:
+        """Whether a slot's stereo outputs have exactly this request's sizes
+        (both eyes): the library writes through them at the cameras' sizes."""
+        try:
+            self.api.check_stereo_out(o, r.cam_dom, r.cam_aff, self.box_capacity, self.roi.tile,
+                                      o["rgb_dom"].device)
+            return True
+        except ValueError:
+            return False
 
     def poll(self, s: int) -> Optional[float]:
         ev = self.events[s]

@@ -7,11 +7,16 @@ scale: |D_raw(GPU) - D_raw| <= 1e-4 * (D/A) + 1e-7 for the accumulated
 D = sum d w, and the depth proxy D/A within 1e-4 relative wherever
 A >= 0.5 (where reprojection uses it); sort orders, hole masks, labels,
 boxes and tile masks bit-exact.  Pixels where the oracle flags a threshold
-decision that fp32 may take differently (alpha within 5e-5 of alpha_min,
-transmittance within 1e-4 of T_min, the G3/G2 depth choice, rays grazing
-a surfel plane) are counted, must stay below 0.5% of the pixels, and are
-held to a loose bound of 1e-2 instead: one such flip moves a pixel by at
-most about alpha_min.
+decision that fp32 may take differently (alpha within 5e-5 relative of
+alpha_min, transmittance within 1e-4 relative of T_min, the G3/G2 depth
+choice within 1e-5, rays grazing a surfel plane) are counted and held to a
+loose bound of 1e-2 instead: one such flip moves a pixel by at most about
+alpha_min.  Their share is a property of the oracle's flags alone (it is
+the same whatever the GPU computes); on the parity cases here it measures
+4e-4 to 3.1e-3 of the pixels (most on the large-surfel scene, where more
+footprints end inside each tile), and the check requires it to stay below
+0.35%.  How many flagged pixels the GPU actually resolves differently is
+logged for each case.
 """
 import sys
 
@@ -27,7 +32,7 @@ pytestmark = pytest.mark.gpu
 
 RGB_TOL = 1e-4
 DEPTH_RTOL = 1e-4
-MAX_AMBIGUOUS_FRAC = 0.005
+MAX_AMBIGUOUS_FRAC = 0.0035
 AMBIGUOUS_TOL = 1e-2
 
 
@@ -58,7 +63,8 @@ def check_image(gpu_rgb, gpu_d, gpu_a, ref, where=""):
     e_p[fg] = np.abs(gpu_d[fg] / gpu_a[fg] - zhat[fg]) / zhat[fg]
     bad = ((e_rgb > RGB_TOL) | (e_a > RGB_TOL) | (e_d > DEPTH_RTOL + 1e-7) | (e_p > DEPTH_RTOL)) & ~amb
     loose = (e_rgb > AMBIGUOUS_TOL) | (e_a > AMBIGUOUS_TOL) | (e_p > AMBIGUOUS_TOL)
-    log(f"[{where}] px={amb.size} ambiguous={int(amb.sum())} max_rgb_err(non-amb)="
+    flipped = int((((e_rgb > RGB_TOL) | (e_a > RGB_TOL) | (e_p > DEPTH_RTOL)) & amb).sum())
+    log(f"[{where}] px={amb.size} ambiguous={int(amb.sum())} ({amb.mean():.2e}) flipped={flipped} max_rgb_err(non-amb)="
         f"{float(e_rgb[~amb].max()) if (~amb).any() else 0:.2e} max_depth_err(non-amb)="
         f"{float(np.maximum(e_d, e_p)[~amb].max()) if (~amb).any() else 0:.2e} bad={int(bad.sum())}")
     assert amb.mean() <= MAX_AMBIGUOUS_FRAC, f"{where}: too many ambiguous pixels {amb.mean():.4f}"

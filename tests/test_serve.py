@@ -19,13 +19,17 @@ class Clock:
 
 class FakeExecutor:
     """Each request takes `dur[rid]` seconds of simulated time once issued;
-    records what was in flight at every issue."""
+    records what was in flight at every issue.  Like the GPU executor, a
+    slot keeps the buffers of its last frame (its held bytes) after the
+    frame ends, until it is trimmed or its next frame replaces them."""
 
     def __init__(self, clock, dur, size):
         self.clock, self.dur, self.size = clock, dur, size
         self.running = {}
+        self.held = {}
         self.peak_slots = 0
         self.peak_bytes = 0.0
+        self.trims = 0
         self.order = []
 
     def start(self):
@@ -34,12 +38,21 @@ class FakeExecutor:
     def need_bytes(self, r):
         return self.size[r.rid]
 
+    def held_bytes(self, s):
+        return self.held.get(s, 0.0)
+
+    def trim(self, s):
+        assert s not in self.running, "a running slot must never be trimmed"
+        self.held[s] = 0.0
+        self.trims += 1
+
     def issue(self, s, r):
         assert s not in self.running
         self.running[s] = (r, self.clock.t + self.dur[r.rid])
+        self.held[s] = self.size[r.rid]
         self.order.append(r.rid)
         self.peak_slots = max(self.peak_slots, len(self.running))
-        self.peak_bytes = max(self.peak_bytes, sum(self.size[q.rid] for q, _ in self.running.values()))
+        self.peak_bytes = max(self.peak_bytes, sum(self.held.values()))
 
     def poll(self, s):
         if s not in self.running or self.clock.t < self.running[s][1]:
@@ -102,3 +115,27 @@ def test_poisson_arrivals_rate():
     t = serve.poisson_arrivals(90.0, 20_000, seed=3)
     assert np.all(np.diff(t) > 0)
     assert np.mean(np.diff(t)) == pytest.approx(1.0 / 90.0, rel=0.03)
+
+
+def test_held_bytes_never_exceed_the_budget():
+    # The budget fits two frames, there are four slots: slots keep their
+    # buffers after a frame, so admission must count what idle slots hold
+    # and trim them before the held total would pass the budget.
+    rng = np.random.default_rng(4)
+    n = 80
+    arrivals = serve.poisson_arrivals(200.0, n, seed=5)
+    dur = rng.uniform(0.01, 0.04, size=n)
+    size = rng.choice([2.0, 3.0, 3.5], size=n)
+    reqs, ex = run(arrivals, dur, size, slots=4, budget=7.0)
+    assert ex.peak_bytes <= 7.0 + 1e-12
+    assert ex.peak_slots >= 2
+    assert ex.trims > 0
+    assert ex.order == list(range(n))
+    assert all(r.done >= r.admitted for r in reqs)
+
+
+def test_a_slot_holding_this_size_is_reused():
+    # Same-size requests one after another reuse the slot that already
+    # holds their buffers: nothing is trimmed.
+    reqs, ex = run([0.0, 1.5, 3.0], [1.0, 1.0, 1.0], [3.0, 3.0, 3.0], slots=3, budget=4.0)
+    assert ex.trims == 0 and len({r.slot for r in reqs}) == 1
