@@ -249,6 +249,26 @@ BGS_API int32_t bgs_reproject(bgs_ctx* ctx, const bgs_camera* src, const bgs_cam
                               const float* alpha_src, void* ws, size_t ws_bytes, float* rgb_dst, float* z_dst,
                               float* alpha_dst, uint8_t* hole_mask, float* depth_range);
 
+/* bgs_reproject for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  Same arguments, semantics and outputs as bgs_reproject,
+ * without the workspace: its scratch (status words, the per-row partials
+ * and, for rigs that do not keep rows, the 64-bit z-buffer) lives in a
+ * static device array of BGS_REPROJECT_NOALLOC_SCRATCH_BYTES that each GPU
+ * the library runs on holds until the process ends.  The destination image
+ * may have at most BGS_REPROJECT_NOALLOC_MAX_PIXELS pixels
+ * (BGS_ERR_INVALID_ARG beyond, nothing launched).  Every call on one GPU
+ * uses that GPU's single array: calls that overlap in time on one GPU
+ * (several streams or host threads) race and must be serialised by the
+ * caller.  Each call clears what it accumulates, so consecutive calls of
+ * any sizes are independent.  Calls no allocator.  Asynchronous. */
+#define BGS_REPROJECT_NOALLOC_MAX_PIXELS (1 << 23)
+#define BGS_REPROJECT_NOALLOC_SCRATCH_BYTES (512 + 16 * 16384 + 8 * (size_t)BGS_REPROJECT_NOALLOC_MAX_PIXELS)
+BGS_API int32_t bgs_reproject_noalloc(bgs_ctx* ctx, const bgs_camera* src, const bgs_camera* dst,
+                                      const bgs_roi_params* roi, const float* rgb_src, const float* depth_raw_src,
+                                      const float* alpha_src, float* rgb_dst, float* z_dst, float* alpha_dst,
+                                      uint8_t* hole_mask, float* depth_range);
+
 /* Stage 3 and the interpolation part of Stage 4 (Sec. 3.1, Sec. 3.5).
  * Step 1: N samples per source-image edge reprojected at the two depths of
  * depth_range give the extrema of Eq. 6, border widths by Eq. 7-8

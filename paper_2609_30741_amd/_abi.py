@@ -11,6 +11,7 @@ LIB_PATH = os.path.join(HERE, "libbgs.so")
 OK, ERR_INVALID_ARG, ERR_WORKSPACE, ERR_CAPACITY, ERR_HIP, ERR_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 BOX_LEFT, BOX_RIGHT, BOX_TOP, BOX_BOTTOM, BOX_CENTER = 0, 1, 2, 3, 4
 CLS_WARPED, CLS_HOLE, CLS_GAP, CLS_ROI, CLS_ROWFILL = 0, 1, 2, 3, 4
+REPROJECT_NOALLOC_MAX_PIXELS = 1 << 23
 
 
 class Camera(C.Structure):
@@ -56,7 +57,8 @@ STAGES = ["preprocess_dom", "depth_sort_dom", "emit_dom", "tile_sort_dom", "rang
 
 EXPORTS = [
     "bgs_ctx_create", "bgs_ctx_destroy", "bgs_ctx_set_stream", "bgs_ctx_set_sync", "bgs_last_error",
-    "bgs_workspace_size", "bgs_poll_status", "bgs_render_dominant", "bgs_reproject", "bgs_classify_holes",
+    "bgs_workspace_size", "bgs_poll_status", "bgs_render_dominant", "bgs_reproject", "bgs_reproject_noalloc",
+    "bgs_classify_holes",
     "bgs_patch_rois", "bgs_render_stereo", "bgs_sort_workspace_size", "bgs_sort_pairs",
     "bgs_label_components", "bgs_preprocess_debug", "bgs_tile_lists_debug", "bgs_ctx_set_count_pairs",
     "bgs_ctx_set_timing", "bgs_timing_collect", "bgs_blend_trace", "bgs_ctx_set_blend_split",
@@ -92,6 +94,8 @@ def load():
                                 C.POINTER(I64)],
         "bgs_reproject": [P, C.POINTER(Camera), C.POINTER(Camera), C.POINTER(RoiParams), P, P, P, P, SZ, P, P, P, P,
                           P],
+        "bgs_reproject_noalloc": [P, C.POINTER(Camera), C.POINTER(Camera), C.POINTER(RoiParams), P, P, P, P, P, P,
+                                  P, P],
         "bgs_classify_holes": [P, C.POINTER(Camera), C.POINTER(Camera), C.POINTER(RoiParams),
                                C.POINTER(RasterParams), P, P, SZ, P, P, P, P, P, P, I32, P, P],
         "bgs_patch_rois": [P, C.POINTER(Scene), C.POINTER(Camera), C.POINTER(RasterParams), C.POINTER(RoiParams), P,

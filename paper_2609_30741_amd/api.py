@@ -307,6 +307,33 @@ class Context:
                                          _ptr(out["depth_range"])))
         return out
 
+    def reproject_noalloc(self, src, dst, rgb, depth_raw, alpha, roi: Roi = Roi(), out=None):
+        """Stage 2 through bgs_reproject_noalloc: the library's static scratch
+        instead of a workspace (nothing allocated by the call itself; pass
+        `out` to allocate nothing here either)."""
+        self.bind_stream()
+        W, H = int(dst.width), int(dst.height)
+        if out is None:
+            out = dict(rgb=torch.empty((3, H, W), device=self.device), z=torch.empty((H, W), device=self.device),
+                       alpha=torch.empty((H, W), device=self.device),
+                       hole=torch.empty((H, W), dtype=torch.uint8, device=self.device),
+                       depth_range=torch.empty(2, device=self.device))
+        dev = _dev(self.device)
+        Hs, Ws = int(src.height), int(src.width)
+        check_tensor("rgb_src", rgb, (3, Hs, Ws), torch.float32, dev)
+        check_tensor("depth_raw_src", depth_raw, (Hs, Ws), torch.float32, dev)
+        check_tensor("alpha_src", alpha, (Hs, Ws), torch.float32, dev)
+        check_tensor("rgb", out["rgb"], (3, H, W), torch.float32, dev)
+        check_tensor("z", out["z"], (H, W), torch.float32, dev)
+        check_tensor("alpha", out["alpha"], (H, W), torch.float32, dev)
+        check_tensor("hole", out["hole"], (H, W), torch.uint8, dev)
+        check_tensor("depth_range", out["depth_range"], (2,), torch.float32, dev)
+        self._check(self.L.bgs_reproject_noalloc(self.h, C.byref(camera(src)), C.byref(camera(dst)),
+                                                 C.byref(roi.c()), _ptr(rgb), _ptr(depth_raw), _ptr(alpha),
+                                                 _ptr(out["rgb"]), _ptr(out["z"]), _ptr(out["alpha"]),
+                                                 _ptr(out["hole"]), _ptr(out["depth_range"])))
+        return out
+
     def _ws_bytes(self, n, W, H, k):
         need = C.c_size_t()
         self._check(self.L.bgs_workspace_size(int(n), int(W), int(H), int(k), C.byref(need)))

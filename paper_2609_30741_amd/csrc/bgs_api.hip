@@ -4,11 +4,19 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
 
 #include "bgs_internal.h"
+
+// Scratch of bgs_reproject_noalloc: one copy per GPU, allocated with the
+// code object and held until the process ends.  Layout: the status block
+// (512 bytes), one uint4 partial per destination row (16384 rows at most),
+// then the 64-bit z-buffer.  In host code this name is only a stand-in for
+// the symbol; its device address comes from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[BGS_REPROJECT_NOALLOC_SCRATCH_BYTES];
 
 struct bgs_ctx {
     hipStream_t stream = nullptr;
@@ -485,6 +493,32 @@ int finish(bgs_ctx* ctx, void* ws, const Layout& L, DevStatus* host) {
 
 using namespace bgs;
 
+namespace {
+
+// Device address of `scratch` on each GPU, looked up once per device with
+// that device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_for_current_device(void** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
 extern "C" {
 
 int32_t bgs_ctx_create(bgs_ctx** out, void* stream) {
@@ -648,6 +682,38 @@ int32_t bgs_reproject(bgs_ctx* ctx, const bgs_camera* src, const bgs_camera* dst
     HIP_CHECK(launch_reproject(make_warpcam(*src), make_warpcam(*dst), rel_pose(*src, *dst), roi->a_min, rgb_src,
                                depth_raw_src, alpha_src, at<unsigned long long>(ws, L.zbuf), rgb_dst, z_dst, alpha_dst,
                                hole_mask, depth_range, true, at<uint4>(ws, L.wpart), st, ctx->stream),
+              "reproject");
+    return BGS_OK;
+}
+
+int32_t bgs_reproject_noalloc(bgs_ctx* ctx, const bgs_camera* src, const bgs_camera* dst, const bgs_roi_params* roi,
+                              const float* rgb_src, const float* depth_raw_src, const float* alpha_src, float* rgb_dst,
+                              float* z_dst, float* alpha_dst, uint8_t* hole_mask, float* depth_range) {
+    if (!ctx) return BGS_ERR_INVALID_ARG;
+    int rc;
+    if ((rc = check_camera(ctx, src, "src")) || (rc = check_camera(ctx, dst, "dst")) || (rc = check_roi(ctx, roi)))
+        return rc;
+    if (!rgb_src || !depth_raw_src || !alpha_src || !rgb_dst || !z_dst || !alpha_dst || !hole_mask || !depth_range)
+        return fail(ctx, BGS_ERR_INVALID_ARG, "null buffer");
+    if ((int64_t)src->width * src->height > ((int64_t)1 << 32))
+        return fail(ctx, BGS_ERR_INVALID_ARG, "source image too large");
+    const int64_t nd = (int64_t)dst->width * dst->height;
+    if (nd > (int64_t)BGS_REPROJECT_NOALLOC_MAX_PIXELS)
+        return fail(ctx, BGS_ERR_INVALID_ARG,
+                    "destination of %dx%d pixels exceeds the %d pixels of the static scratch; use bgs_reproject",
+                    dst->width, dst->height, (int)BGS_REPROJECT_NOALLOC_MAX_PIXELS);
+    static_assert(sizeof(DevStatus) <= 512, "status block fits its scratch slot");
+    void* base = nullptr;
+    HIP_CHECK(scratch_for_current_device(&base), "scratch address");
+    char* sp = static_cast<char*>(base);
+    DevStatus* st = reinterpret_cast<DevStatus*>(sp);
+    uint4* wpart = reinterpret_cast<uint4*>(sp + 512);
+    unsigned long long* zbuf = reinterpret_cast<unsigned long long*>(sp + 512 + 16 * 16384);
+    // reset = true clears the status fields the reprojection accumulates; the
+    // z-buffer is refilled and every row partial rewritten by each call.
+    HIP_CHECK(launch_reproject(make_warpcam(*src), make_warpcam(*dst), rel_pose(*src, *dst), roi->a_min, rgb_src,
+                               depth_raw_src, alpha_src, zbuf, rgb_dst, z_dst, alpha_dst, hole_mask, depth_range, true,
+                               wpart, st, ctx->stream),
               "reproject");
     return BGS_OK;
 }
