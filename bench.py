@@ -2,32 +2,28 @@
 """Binocular 2DGS frame path on one MI355X: stereo frames/s and p99 ms per
 stereo frame of the reprojection-and-patch pipeline, next to the sequential
 two-pass render (the same full render run for both eyes), with the
-affiliated-eye PSNR of the pipeline against the full render.
+affiliated-eye PSNR loss of the pipeline against the full render.
 
-    python bench.py [--gpus 1] [--steps 200] [--warmup 20] [--workload sphere800]
+    python bench.py [--gpus 1] [--steps 200] [--warmup 20] [--workload unbounded1600]
 
 One step = one stereo frame: dominant render with the depth proxy,
 reprojection, hole classification and interpolation, ROI re-rendering of
 the affiliated eye.  Frames cycle through the workload's poses; inputs are
 resident in HBM before the timed regions.
 
-Two timed regions per method, each of exactly --steps frames between
-synchronisations:
-  * one frame at a time: frames issued back to back on one stream; p50/p99
-    are per-frame GPU times from events recorded around each frame; only
-    the dominant-eye blend carries the library's stage events (for the
-    roofline's live average).
-  * frames in flight (`value`): --inflight contexts, each with its own
-    workspace and default-priority stream, frames assigned round robin, as
-    a serving loop runs independent frames; throughput = steps / wall time.
-    Long tile lists are not split into continuation segments here
-    (--inflight-split): the segments shorten one frame's blend by doing
-    speculative extra work, which costs throughput when other frames
-    already fill the GPU.  One frame at a time keeps the library's
-    latency-oriented default split.
-The two-pass comparison (the same full render for both eyes) is timed the
-same two ways.  The per-stage breakdown comes from a separate, fully
-instrumented pass.  Prints one JSON line.
+Protocol (the paper's Sec. 4.3): both strategies run their stages in
+sequence on ONE stream, one frame after another, with no batched multiview
+rendering and no concurrent streams.  `value` is that rate for the
+pipeline; `two_pass` the same for the sequential two-pass render; p50/p99
+are per-frame GPU times from events recorded around each frame in the same
+timed region.  The headline workload is the unbounded 1M-surfel scene at
+1600x1064 (the largest single-GPU configuration); the object-centric 300k
+scene at 800x600 and the 10k cube at 256x256 (Step 2 off) are measured the
+same way under `configs`.  Secondary figures, outside the paper's protocol
+and never `value`: frames in flight on several streams (`inflight`), and
+the per-stage breakdown from a separate, fully instrumented pass.  Peak
+device memory of each strategy comes from fresh contexts (`memory`).
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -40,29 +36,38 @@ import time
 
 import numpy as np
 
-# Paper's two-pass affiliated-eye PSNR against captured images, used as the
-# reference noise level of the PSNR-loss stand-in (object-centric / DTU-like
-# scenes; unbounded / MipNeRF-360-like scenes).
+# Paper's two-pass affiliated-eye PSNR against captured images (Table 2),
+# used as the reference noise level of the PSNR-loss stand-in: DTU for the
+# object-centric scenes, MipNeRF-360 for the unbounded one.
 P_REF = {"cube256": 28.83, "sphere800": 28.83, "unbounded1600": 26.14}
 WORKLOAD_TEXT = {
-    "cube256": "cube256: 10k surfels uniform in [-1,1]^3, SH0, 256x256 per eye, fx=fy=300, 1 pose, baseline 0.064",
+    "cube256": "cube256: 10k surfels uniform in [-1,1]^3, SH0, 256x256 per eye, fx=fy=300, 1 pose, baseline 0.064, "
+               "Step 2 off",
     "sphere800": "sphere800: 300k surfels on a noisy unit sphere shell, SH3, 800x600 per eye, fx=fy=1100, "
                  "16 poses on an orbit of radius 3, baseline 0.064",
     "unbounded1600": "unbounded1600: 1M surfels (70% unit ball, 30% log-uniform shell r=1-20), SH3, 1600x1064 per "
                      "eye, fx=fy=1300, 32 poses on a forward path, baseline 0.064",
 }
+# Step 2 (center ROIs) per workload: off for the far, small-disparity cube
+# scene, on for the others.
+CENTER_ROI = {"cube256": False, "sphere800": True, "unbounded1600": True}
 # Published MI355X peaks.
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
+# Plain (unpacked) fp32 VALU issue of the chip: 256 CUs x 4 SIMDs x 16 lanes
+# x 2.4 GHz lane-operations per second.
+PEAK_VALU_TLANEOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# fp32 arithmetic of one evaluated (pixel, surfel) pair in the blend (an FMA
+# counts as two, rcp and exp as one each, min/max as one): the plane
+# homography, the two Gaussian exponents, alpha, and the compositing step
+# with its colour, depth and weight accumulation, which the blend runs for
+# every evaluated pair.
+FLOPS_PER_PAIR = 38
 # HBM bytes of one sphere800 dominant-eye blend stage (capped walk, two
 # segment rounds, chain, fix-up), FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
 # (factors from a 512 MiB copy), valid while raster.hip and bgs_api.hip hash
 # (sha1 over the two files in that order) to this value.
 BLEND_TRAFFIC = {"source_sha1": "d38cf24a846cd3817a9fda718d17bb872d6199f3", "bytes": 120.1e6}
-# fp32 operations of one evaluated (pixel, surfel) pair in the blend and the
-# extra ones of a contributing pair (an FMA counts as two).
-FLOPS_EVAL = 31
-FLOPS_USED = 12
 
 
 def log(*a):
@@ -73,47 +78,337 @@ def pct(a, q):
     return float(np.percentile(np.asarray(a), q))
 
 
+class Workload:
+    """A workload's scene on the device, its stereo rigs and one context
+    sized for both strategies."""
+
+    def __init__(self, name, seed, surfels=0, margin=32, edge_bounds=0, center_roi=None):
+        from paper_2609_30741_amd import api, synth
+        self.name = name
+        kw = {"n": surfels} if surfels > 0 else {}
+        t0 = time.time()
+        self.scene, self.cams, self.baseline = synth.WORKLOADS[name](seed, **kw)
+        self.affs = [synth.affiliated(c, self.baseline) for c in self.cams]
+        self.ds = api.DeviceScene(self.scene)
+        self.roi = api.Roi(center_roi=CENTER_ROI[name] if center_roi is None else bool(center_roi), margin=margin,
+                           edge_bounds=edge_bounds)
+        self.raster = api.Raster()
+        self.W, self.H = self.cams[0].width, self.cams[0].height
+        self.n_tiles = ((self.W + 15) // 16) * ((self.H + 15) // 16)
+        log(f"scene {name}: n={self.scene.n} generated+uploaded in {time.time() - t0:.1f}s")
+
+
+def frames_ours(ctx, wl, i0, n, out):
+    k = len(wl.cams)
+    for i in range(i0, i0 + n):
+        ctx.render_stereo(wl.ds, wl.cams[i % k], wl.affs[i % k], wl.raster, wl.roi, out=out)
+
+
+def frames_two(ctx, wl, i0, n, fd, fo):
+    k = len(wl.cams)
+    for i in range(i0, i0 + n):
+        ctx.render_dominant(wl.ds, wl.cams[i % k], wl.raster, out=fd)
+        ctx.render_dominant(wl.ds, wl.affs[i % k], wl.raster, out=fo)
+
+
+def timed(run, steps, warmup):
+    """Warm up, then time exactly `steps` frames issued back to back on the
+    current stream: wall time between synchronisations, and each frame's
+    GPU time from events recorded around it."""
+    import torch
+    run(0, warmup)
+    torch.cuda.synchronize()
+    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for i in range(steps):
+        ev0[i].record()
+        run(i, 1)
+        ev1[i].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    return wall, [a.elapsed_time(b) for a, b in zip(ev0, ev1)]
+
+
+def quality(ctx, wl, n_ssim=8):
+    """Affiliated eye of the pipeline against the full render of that eye,
+    per pose: PSNR, the PSNR-loss stand-in, SSIM on up to n_ssim poses, and
+    the squared error split by the pixel's class (warped, gap-filled,
+    row-filled, ROI re-rendered).  Also sizes the workspace: the largest key
+    counts of both passes."""
+    import torch
+    from paper_2609_30741_amd import api, metrics
+    ps, ss, kd, kr, tiles, boxes = [], [], [], [], [], []
+    share = {c: [] for c in ("warped", "gap", "rowfill", "roi")}
+    frac = {c: [] for c in share}
+    cls_id = {"warped": api.CLS_WARPED, "gap": api.CLS_GAP, "rowfill": api.CLS_ROWFILL, "roi": api.CLS_ROI}
+    out = full = None
+    for i, (cd, ca) in enumerate(zip(wl.cams, wl.affs)):
+        out = ctx.render_stereo(wl.ds, cd, ca, wl.raster, wl.roi, out=out)
+        st = out["stats"]
+        kd.append(st["n_keys_dom"])
+        kr.append(st["n_keys_roi"])
+        tiles.append(st["n_roi_tiles"])
+        boxes.append(st["n_boxes"])
+        full = ctx.render_dominant(wl.ds, ca, wl.raster, out=full)
+        e2 = ((out["rgb_aff"].clamp(0, 1).double() - full["rgb"].clamp(0, 1).double()) ** 2).sum(0)
+        npx = 3 * e2.numel()
+        mse = float(e2.sum()) / npx
+        ps.append(float("inf") if mse == 0 else 10 * math.log10(1 / mse))
+        for c, v in cls_id.items():
+            m = out["cls_aff"] == v
+            share[c].append(float(e2[m].sum()) / npx)
+            frac[c].append(float(m.float().mean()))
+        if i < n_ssim:
+            ss.append(metrics.ssim(out["rgb_aff"].cpu().numpy(), full["rgb"].cpu().numpy()))
+    torch.cuda.synchronize()
+    mse_ref = 10 ** (-P_REF[wl.name] / 10)
+    mses = [10 ** (-p / 10) for p in ps]
+    q = {"psnr_ours_vs_full_db": round(float(np.mean(ps)), 3), "psnr_min_db": round(float(np.min(ps)), 3),
+         "psnr_loss_db": round(float(np.mean([10 * math.log10(1 + m / mse_ref) for m in mses])), 4),
+         "p_ref_db": P_REF[wl.name], "within_1p3_db": None,
+         "ssim_ours_vs_full": round(float(np.mean(ss)), 5), "ssim_min": round(float(np.min(ss)), 5),
+         "ssim_poses": len(ss),
+         "mse": float(np.mean(mses)),
+         "mse_share_by_class": {c: float(np.mean(v)) for c, v in share.items()},
+         "pixel_frac_by_class": {c: round(float(np.mean(v)), 5) for c, v in frac.items()}}
+    q["within_1p3_db"] = q["psnr_loss_db"] <= 1.3
+    frame = {"keys_dom": int(np.mean(kd)), "keys_roi": int(np.mean(kr)),
+             "roi_tile_frac": round(float(np.mean(tiles)) / wl.n_tiles, 4), "boxes": float(np.mean(boxes))}
+    return q, frame, max(max(kd), max(kr))
+
+
+def view_independent_loss(wl, seed):
+    """The same scene with its colours made view-independent (SH degree 0:
+    the DC coefficients only): the PSNR loss that remains when no surfel
+    changes colour between the eyes."""
+    from paper_2609_30741_amd import api, synth
+    sc = wl.scene
+    sc0 = synth.Scene(sc.n, 0, sc.pos, sc.quat, sc.scale, sc.opacity, np.ascontiguousarray(sc.sh[:3]))
+    ds0 = api.DeviceScene(sc0)
+    ctx = api.Context(sync=True)
+    out = full = None
+    mses = []
+    for cd, ca in zip(wl.cams, wl.affs):
+        out = ctx.render_stereo(ds0, cd, ca, wl.raster, wl.roi, out=out)
+        full = ctx.render_dominant(ds0, ca, wl.raster, out=full)
+        mses.append(float(((out["rgb_aff"].clamp(0, 1).double() - full["rgb"].clamp(0, 1).double()) ** 2).mean()))
+    mse_ref = 10 ** (-P_REF[wl.name] / 10)
+    return {"sh_degree": 0, "psnr_ours_vs_full_db": round(float(np.mean([10 * math.log10(1 / m) for m in mses])), 3),
+            "psnr_loss_db": round(float(np.mean([10 * math.log10(1 + m / mse_ref) for m in mses])), 4)}
+
+
+def peak_memory(wl, kmax):
+    """Peak device bytes each strategy allocates for its frames, from a fresh
+    context with the same 25% key headroom: workspace plus output images
+    (the resident scene, shared by both, is reported separately)."""
+    import torch
+    from paper_2609_30741_amd import api
+    kc = int(kmax * 1.25) + 4096
+    res = {}
+    for strat in ("ours", "two_pass"):
+        torch.cuda.synchronize()
+        base = torch.cuda.memory_allocated()
+        torch.cuda.reset_peak_memory_stats()
+        ctx = api.Context(sync=True)
+        ctx.reserve(wl.scene.n, wl.W, wl.H, kc)
+        if strat == "ours":
+            out = None
+            for cd, ca in zip(wl.cams[:4], wl.affs[:4]):
+                out = ctx.render_stereo(wl.ds, cd, ca, wl.raster, wl.roi, out=out)
+        else:
+            fd = fo = None
+            for cd, ca in zip(wl.cams[:4], wl.affs[:4]):
+                fd = ctx.render_dominant(wl.ds, cd, wl.raster, out=fd)
+                fo = ctx.render_dominant(wl.ds, ca, wl.raster, out=fo)
+        torch.cuda.synchronize()
+        res[strat] = torch.cuda.max_memory_allocated() - base
+        del ctx
+        if strat == "ours":
+            del out
+        else:
+            del fd, fo
+    scene_b = sum(t.numel() * t.element_size() for t in wl.ds.t.values())
+    return {"ours_mb": round(res["ours"] / 2 ** 20, 1), "two_pass_mb": round(res["two_pass"] / 2 ** 20, 1),
+            "scene_mb": round(scene_b / 2 ** 20, 1),
+            "reduction": round(1 - res["ours"] / res["two_pass"], 4),
+            "reduction_with_scene": round(1 - (res["ours"] + scene_b) / (res["two_pass"] + scene_b), 4)}
+
+
+def measure(wl, args, headline):
+    """Everything for one workload; the headline adds the in-flight figure,
+    the stage breakdown, the blend's pair counts, the view-independent
+    quality and the CPU baseline."""
+    import torch
+    from paper_2609_30741_amd import api
+    ctx = api.Context(sync=True)
+    q, frame, kmax = quality(ctx, wl, n_ssim=8 if headline else 4)
+    ctx.reserve(wl.scene.n, wl.W, wl.H, int(kmax * 1.25) + 4096)
+    log(f"[{wl.name}] quality: PSNR(ours, full) {q['psnr_ours_vs_full_db']:.2f} dB, loss {q['psnr_loss_db']:.3f} dB, "
+        f"SSIM {q['ssim_ours_vs_full']:.4f}; keys dom {frame['keys_dom']:.3g} roi {frame['keys_roi']:.3g}; "
+        f"roi tiles {frame['roi_tile_frac']:.3f}; MSE by class {q['mse_share_by_class']}")
+    res = {"workload": WORKLOAD_TEXT[wl.name], "quality": q, "frame": frame}
+
+    pe = wd = None
+    if headline:
+        # Blend work counts (a counting pass, before the timed regions).
+        ctx.set_count_pairs(True)
+        out = None
+        pe, pu, wk = [], [], []
+        for cd, ca in zip(wl.cams, wl.affs):
+            out = ctx.render_stereo(wl.ds, cd, ca, wl.raster, wl.roi, out=out)
+            pe.append(out["stats"]["pairs_eval_dom"])
+            pu.append(out["stats"]["pairs_used_dom"])
+            wk.append(out["stats"]["blend_work_dom"])
+        ctx.set_count_pairs(False)
+        wd = np.mean(wk, axis=0)
+        log(f"[{wl.name}] blend work dom: evaluated {np.mean(pe):.3g} pairs, walked {wd[0]:.3g} tested {wd[1]:.3g} "
+            f"lane-eff {np.mean(pe) / max(wd[1], 1) / 64:.3f} longest wave walk {wd[2]:.0f} list {wd[3]:.0f}")
+        pe = (float(np.mean(pe)), float(np.mean(pu)))
+
+    # ---- timed, the paper's protocol: one stream, frames in sequence ----
+    ctx.set_sync(False)
+    out = ctx.render_stereo(wl.ds, wl.cams[0], wl.affs[0], wl.raster, wl.roi)
+    if headline:
+        ctx.set_timing(True, stages=["blend_dom"])  # two event records per frame: the roofline's live average
+    t_ours, lat = timed(lambda i0, n: frames_ours(ctx, wl, i0, n, out), args.steps, args.warmup)
+    blend_live = ctx.timing_collect()["blend_dom"] if headline else None
+    ctx.set_timing(False)
+    st = ctx.poll_status()  # overflow bits of every frame since the last poll
+    assert st["overflow"] == 0, f"capacity overflow during the timed frames: {st}"
+    fd = ctx.render_dominant(wl.ds, wl.cams[0], wl.raster)
+    fo = ctx.render_dominant(wl.ds, wl.affs[0], wl.raster)
+    t_two, lat2 = timed(lambda i0, n: frames_two(ctx, wl, i0, n, fd, fo), args.steps, args.warmup)
+    st = ctx.poll_status()
+    assert st["overflow"] == 0, f"capacity overflow during the two-pass timed frames: {st}"
+    fps, fps2 = args.steps / t_ours, args.steps / t_two
+    log(f"[{wl.name}] one stream: ours {fps:.1f} fps p50 {pct(lat, 50):.3f} p99 {pct(lat, 99):.3f} ms; two-pass "
+        f"{fps2:.1f} fps p99 {pct(lat2, 99):.3f} ms; reduction {1 - t_ours / t_two:.4f}")
+    res.update({"value": round(fps, 2), "ms_per_step": round(t_ours / args.steps * 1e3, 4),
+                "p50_ms": round(pct(lat, 50), 4), "p99_ms": round(pct(lat, 99), 4),
+                "two_pass": {"value": round(fps2, 2), "ms_per_step": round(t_two / args.steps * 1e3, 4),
+                             "p50_ms": round(pct(lat2, 50), 4), "p99_ms": round(pct(lat2, 99), 4)},
+                "time_reduction_vs_two_pass": round(1 - t_ours / t_two, 4)})
+    res["memory"] = None
+    if headline:
+        res["_blend_live"] = blend_live
+        res["_pairs"] = pe
+        res["_work"] = wd
+        res["_ctx"] = (ctx, out, fd, fo, kmax)
+    return res
+
+
+def inflight(wl, args, kmax):
+    """Frames in flight on K contexts and default-priority streams, frames
+    assigned round robin, both strategies; outside the paper's protocol."""
+    import torch
+    from paper_2609_30741_amd import api
+    K = max(1, args.inflight)
+    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(K - 1)]
+    ctxs, outs, fds, fos = [], [], [], []
+    split = tuple(int(x) for x in args.inflight_split.split(","))
+    for k in range(K):
+        with torch.cuda.stream(streams[k]):
+            c = api.Context(sync=True)
+            c.reserve(wl.scene.n, wl.W, wl.H, int(kmax * 1.25) + 4096)
+            outs.append(c.render_stereo(wl.ds, wl.cams[0], wl.affs[0], wl.raster, wl.roi))
+            fds.append(c.render_dominant(wl.ds, wl.cams[0], wl.raster))
+            fos.append(c.render_dominant(wl.ds, wl.affs[0], wl.raster))
+            c.set_sync(False)
+            c.set_blend_split(*split)
+            ctxs.append(c)
+    torch.cuda.synchronize()
+    n_poses = len(wl.cams)
+
+    def ours(n0, n):
+        for i in range(n0, n0 + n):
+            k = i % K
+            with torch.cuda.stream(streams[k]):
+                ctxs[k].render_stereo(wl.ds, wl.cams[i % n_poses], wl.affs[i % n_poses], wl.raster, wl.roi,
+                                      out=outs[k])
+
+    def two(n0, n):
+        for i in range(n0, n0 + n):
+            k = i % K
+            with torch.cuda.stream(streams[k]):
+                ctxs[k].render_dominant(wl.ds, wl.cams[i % n_poses], wl.raster, out=fds[k])
+                ctxs[k].render_dominant(wl.ds, wl.affs[i % n_poses], wl.raster, out=fos[k])
+
+    res = {}
+    for name, fn in (("ours", ours), ("two_pass", two)):
+        fn(0, args.warmup)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        fn(0, args.steps)
+        torch.cuda.synchronize()
+        res[name] = time.perf_counter() - t
+        for c in ctxs:
+            st = c.poll_status()
+            assert st["overflow"] == 0, f"capacity overflow during the in-flight frames: {st}"
+    return {"streams": K, "blend_split": list(split), "value": round(args.steps / res["ours"], 2),
+            "two_pass_value": round(args.steps / res["two_pass"], 2),
+            "time_reduction_vs_two_pass": round(1 - res["ours"] / res["two_pass"], 4),
+            "note": "several frames on several streams at once: outside the paper's one-stream protocol"}
+
+
+def stage_breakdown(ctx, wl, out, fd, fo, n):
+    import torch
+    ctx.set_timing(True)
+    frames_ours(ctx, wl, 0, n, out)
+    torch.cuda.synchronize()
+    s1 = ctx.timing_collect()
+    ctx.set_timing(True)
+    frames_two(ctx, wl, 0, n, fd, fo)
+    torch.cuda.synchronize()
+    s2 = ctx.timing_collect()
+    ctx.set_timing(False)
+    ours = {k: round(v[0] / v[1], 4) if v[1] else 0.0 for k, v in s1.items()}
+    two = {k: round(v[0] / v[1], 4) for k, v in s2.items() if v[1]}
+    return ours, two
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--workload", default="sphere800", choices=sorted(WORKLOAD_TEXT))
-    ap.add_argument("--center-roi", type=int, default=1)
+    ap.add_argument("--workload", default="unbounded1600", choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--configs", default="sphere800,cube256",
+                    help="further workloads measured with the same protocol (comma-separated, '' for none)")
+    ap.add_argument("--center-roi", type=int, default=-1, help="Step 2 on (1) or off (0) for the headline; "
+                                                                 "-1: the workload's default")
     ap.add_argument("--margin", type=int, default=32, help="ROI safety margin m in pixels (the paper fixes 32)")
     ap.add_argument("--edge-bounds", type=int, default=0,
                     help="edge-ROI bounds: 0 = Eq. 6 over all edge samples, 1 = each side's own edge, worst case")
-    ap.add_argument("--surfels", type=int, default=0, help="surfel count of the workload's scene (0: its default)")
+    ap.add_argument("--surfels", type=int, default=0, help="surfel count of the headline scene (0: its default)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="budget of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--inflight", type=int, default=4,
-                    help="frames in flight for the throughput region: one context and one default-priority stream "
-                         "each, frames assigned round robin (the two-pass baseline the same way)")
+                    help="frames in flight of the secondary throughput figure (0: skip it)")
     ap.add_argument("--inflight-split", default="0,0,128,0,0",
                     help="blend split (cap_dom, cap_roi, seg_len, far_dom, far_roi) of the in-flight region, "
                          "both methods; 0,0 never continues a tile list")
     ap.add_argument("--traffic-probe-stereo", action="store_true",
                     help="no timing: 48 stereo frames of the workload at the default blend split (16 sizing the "
-                         "workspace, then 32), for per-kernel rocprofv3 counter runs of the sorts and reprojection")
+                         "workspace, then 32), for per-kernel rocprofv3 counter runs")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="no timing: a 512 MiB copy (counter calibration), then 12 dominant-eye renders of the "
                          "workload, for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1 (the frame path shards "
-                                   "by frame, see the design notes)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this build measures one GPU only: run with --gpus 1. Stereo frames are "
+                                   "independent, so several GPUs would each render their own frames with the "
+                                   "scene replicated (see the design notes).", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
-    from paper_2609_30741_amd import api, synth
-
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(3)
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
+    torch.cuda.set_device(0)
 
     if args.traffic_probe:
         traffic_probe(args)
@@ -122,261 +417,98 @@ def main():
         traffic_probe_stereo(args)
         return
 
-    t0 = time.time()
-    wl_kw = {"n": args.surfels} if args.surfels > 0 else {}
-    scene, cams, baseline = synth.WORKLOADS[args.workload](args.seed, **wl_kw)
-    affs = [synth.affiliated(c, baseline) for c in cams]
-    ds = api.DeviceScene(scene)
-    ctx = api.Context(sync=True)
-    roi = api.Roi(center_roi=bool(args.center_roi), margin=args.margin, edge_bounds=args.edge_bounds)
-    raster = api.Raster()
-    log(f"scene {args.workload}: n={scene.n} generated+uploaded in {time.time() - t0:.1f}s")
-
-    # ---- untimed: size the workspace on every pose, quality and pair counts ----
-    from paper_2609_30741_amd import metrics
-    ps, ss, keys_dom, keys_roi, roi_tiles, n_boxes = [], [], [], [], [], []
-    out = None
-    full = None
-    for i, (cd, ca) in enumerate(zip(cams, affs)):
-        out = ctx.render_stereo(ds, cd, ca, raster, roi, out=out)
-        st = out["stats"]
-        keys_dom.append(st["n_keys_dom"])
-        keys_roi.append(st["n_keys_roi"])
-        roi_tiles.append(st["n_roi_tiles"])
-        n_boxes.append(st["n_boxes"])
-        full = ctx.render_dominant(ds, ca, raster, out=full)
-        ps.append(api.psnr(out["rgb_aff"], full["rgb"]))
-        ss.append(metrics.ssim(out["rgb_aff"].cpu().numpy(), full["rgb"].cpu().numpy()))
-    # Reserve 25% headroom over the largest key count so the timed frames
-    # never run out of capacity.
-    kmax = max(max(keys_dom), max(keys_roi))
-    ctx.reserve(scene.n, cams[0].width, cams[0].height, int(kmax * 1.25) + 4096)
-    n_tiles = ((cams[0].width + 15) // 16) * ((cams[0].height + 15) // 16)
-    mse_ref = 10 ** (-P_REF[args.workload] / 10)
-    mses = [10 ** (-p / 10) for p in ps]
-    delta_db = float(np.mean([10 * math.log10(1 + m / mse_ref) for m in mses]))
-    log(f"quality: PSNR(ours, full) mean {np.mean(ps):.2f} dB min {np.min(ps):.2f}; loss {delta_db:.3f} dB; "
-        f"SSIM(ours, full) mean {np.mean(ss):.4f} min {np.min(ss):.4f}; "
-        f"keys dom {np.mean(keys_dom):.3g} roi {np.mean(keys_roi):.3g}; roi tiles {np.mean(roi_tiles):.0f}/{n_tiles}")
-
-    ctx.set_count_pairs(True)
-    pe_dom, pu_dom, pe_roi, pu_roi, work_dom, work_roi = [], [], [], [], [], []
-    for cd, ca in zip(cams, affs):
-        out = ctx.render_stereo(ds, cd, ca, raster, roi, out=out)
-        st = out["stats"]
-        pe_dom.append(st["pairs_eval_dom"])
-        pu_dom.append(st["pairs_used_dom"])
-        pe_roi.append(st["pairs_eval_roi"])
-        pu_roi.append(st["pairs_used_roi"])
-        work_dom.append(st["blend_work_dom"])
-        work_roi.append(st["blend_work_roi"])
-    ctx.set_count_pairs(False)
-    wd, wr = np.mean(work_dom, axis=0), np.mean(work_roi, axis=0)
-    log(f"blend work dom: walked {wd[0]:.3g} tested {wd[1]:.3g} lane-eff {np.mean(pe_dom) / max(wd[1], 1) / 64:.3f} "
-        f"max wave walk {wd[2]:.0f} max list {wd[3]:.0f}; roi: walked {wr[0]:.3g} tested {wr[1]:.3g} "
-        f"max wave walk {wr[2]:.0f} max list {wr[3]:.0f}")
-
-    # ---- timed: ours ----
-    ctx.set_sync(False)
-    n_poses = len(cams)
-    for i in range(args.warmup):
-        ctx.render_stereo(ds, cams[i % n_poses], affs[i % n_poses], raster, roi, out=out)
-    torch.cuda.synchronize()
-    # Frames are issued back to back (they are independent): throughput is
-    # steps / wall time with the host never waiting on the GPU; each frame's
-    # latency is its GPU time between events recorded on its stream around it.
-    # Only the dominant-eye blend is timed by the library's stage events here
-    # (two event records per frame); the per-stage breakdown comes from a
-    # separate pass below, so its events do not slow the timed frames.
-    ctx.set_timing(True, stages=["blend_dom"])
-    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for i in range(args.steps):
-        ev0[i].record()
-        ctx.render_stereo(ds, cams[i % n_poses], affs[i % n_poses], raster, roi, out=out)
-        ev1[i].record()
-    torch.cuda.synchronize()
-    t_ours = time.perf_counter() - t_start
-    lat = [a.elapsed_time(b) for a, b in zip(ev0, ev1)]
-    blend_live = ctx.timing_collect()["blend_dom"]
-    ctx.set_timing(False)
-    status = ctx.poll_status()
-    assert status["overflow"] == 0, f"capacity overflow during timing: {status}"
-
-    # ---- timed: sequential two-pass render (no stage events at all) ----
-    fo = full
-    fd = ctx.render_dominant(ds, cams[0], raster)
-    for i in range(args.warmup):
-        ctx.render_dominant(ds, cams[i % n_poses], raster, out=fd)
-        ctx.render_dominant(ds, affs[i % n_poses], raster, out=fo)
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for i in range(args.steps):
-        ev0[i].record()
-        ctx.render_dominant(ds, cams[i % n_poses], raster, out=fd)
-        ctx.render_dominant(ds, affs[i % n_poses], raster, out=fo)
-        ev1[i].record()
-    torch.cuda.synchronize()
-    t_two = time.perf_counter() - t_start
-    lat2 = [a.elapsed_time(b) for a, b in zip(ev0, ev1)]
-    status = ctx.poll_status()
-    assert status["overflow"] == 0, f"capacity overflow during two-pass timing: {status}"
-
-    # ---- timed: throughput with frames in flight on several streams ----
-    # Frames are independent, so a serving loop keeps several in flight: K
-    # contexts (own workspace, own default-priority stream), frame i on
-    # context i mod K.  The two-pass baseline is run the same way.
-    K = max(1, args.inflight)
-    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(K - 1)]
-    ctxs, outs, fds, fos = [ctx], [out], [fd], [fo]
-    for k in range(1, K):
-        with torch.cuda.stream(streams[k]):
-            c = api.Context(sync=True)
-            c.reserve(scene.n, cams[0].width, cams[0].height, int(kmax * 1.25) + 4096)
-            o = c.render_stereo(ds, cams[0], affs[0], raster, roi)
-            ctxs.append(c)
-            outs.append(o)
-            fds.append(c.render_dominant(ds, cams[0], raster))
-            fos.append(c.render_dominant(ds, affs[0], raster))
-            c.set_sync(False)
-    split = tuple(int(x) for x in args.inflight_split.split(","))
-    for c in ctxs:
-        c.set_blend_split(*split)
-    torch.cuda.synchronize()
-
-    def inflight_ours(n0, n):
-        for i in range(n0, n0 + n):
-            k = i % K
-            with torch.cuda.stream(streams[k]):
-                ctxs[k].render_stereo(ds, cams[i % n_poses], affs[i % n_poses], raster, roi, out=outs[k])
-
-    def inflight_two(n0, n):
-        for i in range(n0, n0 + n):
-            k = i % K
-            with torch.cuda.stream(streams[k]):
-                ctxs[k].render_dominant(ds, cams[i % n_poses], raster, out=fds[k])
-                ctxs[k].render_dominant(ds, affs[i % n_poses], raster, out=fos[k])
-
-    inflight_ours(0, args.warmup)
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    inflight_ours(0, args.steps)
-    torch.cuda.synchronize()
-    t_ours_k = time.perf_counter() - t_start
-    inflight_two(0, args.warmup)
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    inflight_two(0, args.steps)
-    torch.cuda.synchronize()
-    t_two_k = time.perf_counter() - t_start
-    for c in ctxs:
-        status = c.poll_status()
-        assert status["overflow"] == 0, f"capacity overflow during the in-flight timing: {status}"
-    ctx.set_blend_split()  # back to the library's default for the stage breakdown
-
-    # ---- per-stage breakdown (every stage timed; not part of the rates) ----
-    n_stage = max(20, min(args.steps, 64))
-    ctx.set_timing(True)
-    for i in range(n_stage):
-        ctx.render_stereo(ds, cams[i % n_poses], affs[i % n_poses], raster, roi, out=out)
-    torch.cuda.synchronize()
-    stages = ctx.timing_collect()
-    ctx.set_timing(True)
-    for i in range(n_stage):
-        ctx.render_dominant(ds, cams[i % n_poses], raster, out=fd)
-        ctx.render_dominant(ds, affs[i % n_poses], raster, out=fo)
-    torch.cuda.synchronize()
-    stages2 = ctx.timing_collect()
-    ctx.set_timing(False)
-
-    fps = args.steps / t_ours
-    fps2 = args.steps / t_two
-    fps_k = args.steps / t_ours_k
-    fps2_k = args.steps / t_two_k
-    stage_ms = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in stages.items()}
+    wl = Workload(args.workload, args.seed, args.surfels, args.margin, args.edge_bounds,
+                  None if args.center_roi < 0 else args.center_roi)
+    head = measure(wl, args, headline=True)
+    ctx, out, fd, fo, kmax = head.pop("_ctx")
+    blend_live, (pe_dom, pu_dom), wd = head.pop("_blend_live"), head.pop("_pairs"), head.pop("_work")
+    stage_ms, stage_ms2 = stage_breakdown(ctx, wl, out, fd, fo, max(20, min(args.steps, 64)))
     log("stage ms/frame (ours): " + ", ".join(f"{k}={v:.3f}" for k, v in stage_ms.items()))
-    log(f"one frame at a time: ours {fps:.1f} fps p50 {pct(lat, 50):.3f} p99 {pct(lat, 99):.3f} ms; two-pass "
-        f"{fps2:.1f} fps p99 {pct(lat2, 99):.3f} ms; reduction {1 - t_ours / t_two:.3f}")
-    log(f"{K} frames in flight: ours {fps_k:.1f} fps; two-pass {fps2_k:.1f} fps; reduction {1 - t_ours_k / t_two_k:.3f}")
+    del ctx, out, fd, fo
+    head["memory"] = peak_memory(wl, kmax)
+    log(f"[{wl.name}] peak memory: {head['memory']}")
+    inf = inflight(wl, args, kmax) if args.inflight > 0 else None
+    if inf:
+        log(f"[{wl.name}] {inf['streams']} frames in flight: ours {inf['value']} two-pass {inf['two_pass_value']}")
+    head["quality"]["view_independent"] = view_independent_loss(wl, args.seed)
+    log(f"[{wl.name}] view-independent colours: {head['quality']['view_independent']}")
 
     # ---- roofline of the dominant kernel (the dominant-eye blend) ----
     blend_ms = blend_live[0] / max(blend_live[1], 1)
-    flops = float(np.mean(pe_dom)) * FLOPS_EVAL + float(np.mean(pu_dom)) * FLOPS_USED
-    achieved = flops / (blend_ms * 1e-3) / 1e12
-    dominant = max(stage_ms, key=lambda k: stage_ms[k])
+    achieved = pe_dom * FLOPS_PER_PAIR / (blend_ms * 1e-3) / 1e12
     roofline = {"kernel": "k_blend (dominant eye)", "bound": "alu", "achieved": round(achieved, 3),
                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                "traffic": blend_traffic() if args.workload == "sphere800" else None, "avg_launch_ms": round(blend_ms, 4),
-                "pairs_evaluated_per_launch": int(np.mean(pe_dom)),
-                "pairs_contributing_per_launch": int(np.mean(pu_dom)),
+                "traffic": blend_traffic() if wl.name == "sphere800" else None,
+                "flops_per_pair": FLOPS_PER_PAIR, "avg_launch_ms": round(blend_ms, 4),
+                "pairs_evaluated_per_launch": int(pe_dom), "pairs_contributing_per_launch": int(pu_dom),
+                "pair_evals_per_s": round(pe_dom / (blend_ms * 1e-3), 1),
+                "frac_of_unpacked_fp32": round(achieved / (PEAK_FP32_TFLOPS / 2), 4),
                 "records_walked_per_launch": int(wd[0]), "records_tested_per_launch": int(wd[1]),
+                "lane_efficiency": round(pe_dom / max(wd[1], 1) / 64, 4),
                 "longest_wave_walk": int(wd[2]), "longest_tile_list": int(wd[3]),
-                "largest_stage": dominant}
+                "largest_stage": max(stage_ms, key=lambda k: stage_ms[k])}
 
-    # ---- HBM efficiency of the sort and reprojection stages (algorithmic
-    # bytes: one read and one write of every key and value for a sort, 4 B
-    # each way when a tile key and its surfel share one word; the 20 B read
-    # (colour, depth proxy, alpha) + 21 B written (colour, z, alpha, hole
-    # mask) per pixel of a forward warp) ----
+    # ---- HBM efficiency of the sorts and the reprojection by algorithmic
+    # bytes: one read and one write of every key (and value) per sort, 4 B
+    # each way when a tile key and its surfel share one word; 20 B read
+    # (colour, depth, alpha) + 21 B written (colour, z, alpha, hole mask) per
+    # pixel of the forward warp ----
     def hbm(stage, nbytes):
         ms = stage_ms[stage]
         gbs = nbytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
         return {"stage": stage, "bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(gbs / PEAK_HBM_GBS, 4), "bytes_per_launch": int(nbytes), "avg_ms": round(ms, 4)}
 
-    npx = cams[0].width * cams[0].height
     bits = lambda x: max(1, int(math.ceil(math.log2(max(x, 2)))))
-    key_b = 8.0 if bits(n_tiles) + bits(scene.n) <= 32 else 16.0
-    hbm_stages = [hbm("tile_sort_dom", key_b * np.mean(keys_dom)), hbm("depth_sort_dom", 16.0 * scene.n),
-                  hbm("tile_sort_roi", key_b * np.mean(keys_roi)), hbm("reproject", 41.0 * npx)]
+    key_b = 8.0 if bits(wl.n_tiles) + bits(wl.scene.n) <= 32 else 16.0
+    hbm_stages = [hbm("tile_sort_dom", key_b * head["frame"]["keys_dom"]), hbm("depth_sort_dom", 16.0 * wl.scene.n),
+                  hbm("tile_sort_roi", key_b * head["frame"]["keys_roi"]), hbm("reproject", 41.0 * wl.W * wl.H)]
 
-    # ---- CPU oracle on a bounded sample (a baseline only) ----
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args, scene, cams[0], affs[0], float(np.mean(roi_tiles)) * 256.0)
+        cpu = cpu_baseline(args, wl.scene, wl.cams[0], wl.affs[0], head["frame"]["roi_tile_frac"] * wl.n_tiles * 256.0,
+                           wl.roi.center_roi)
+
+    extra = []
+    for name in [c for c in args.configs.split(",") if c and c != args.workload]:
+        w2 = Workload(name, args.seed)
+        r = measure(w2, args, headline=False)
+        r["memory"] = peak_memory(w2, max(r["frame"]["keys_dom"], r["frame"]["keys_roi"]) * 1.1)
+        r["center_roi"] = bool(w2.roi.center_roi)
+        extra.append(r)
+        del w2
 
     result = {
         "metric": "stereo frames/sec + p99 ms/frame on 1 MI355X vs two-pass render at <=1.3dB PSNR loss",
-        "value": round(fps_k, 2),
+        "value": head["value"],
         "unit": "stereo frames/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(t_ours_k / args.steps * 1e3, 4),
-        # Latency of one frame: GPU time between events around it, frames
-        # issued one stream at a time.
-        "p50_ms": round(pct(lat, 50), 4),
-        "p99_ms": round(pct(lat, 99), 4),
-        "inflight": K,
-        "blend_split": {"inflight": list(split), "one_frame_at_a_time": "library default"},
+        "ms_per_step": head["ms_per_step"],
+        "p50_ms": head["p50_ms"],
+        "p99_ms": head["p99_ms"],
+        "protocol": "one stream, frames in sequence, both strategies (paper Sec. 4.3)",
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": WORKLOAD_TEXT[args.workload] + (f" (surfel count set to {scene.n})" if args.surfels > 0
-                                                               else ""),
-                   "surfels": int(scene.n),
-                   "width": int(cams[0].width), "height": int(cams[0].height), "poses": n_poses,
-                   "sh_degree": int(scene.sh_degree), "baseline": baseline, "center_roi": bool(args.center_roi),
-                   "margin": roi.margin, "edge_bounds": roi.edge_bounds, "tile": 16, "parallelism": "single GPU"},
-        "two_pass": {"value": round(fps2_k, 2), "unit": "stereo frames/s",
-                     "ms_per_step": round(t_two_k / args.steps * 1e3, 4),
-                     "p50_ms": round(pct(lat2, 50), 4), "p99_ms": round(pct(lat2, 99), 4)},
-        "time_reduction_vs_two_pass": round(1 - t_ours_k / t_two_k, 4),
-        "one_frame_at_a_time": {"value": round(fps, 2), "two_pass_value": round(fps2, 2),
-                                "ms_per_step": round(t_ours / args.steps * 1e3, 4),
-                                "two_pass_ms_per_step": round(t_two / args.steps * 1e3, 4),
-                                "time_reduction_vs_two_pass": round(1 - t_ours / t_two, 4)},
-        "quality": {"psnr_ours_vs_full_db": round(float(np.mean(ps)), 3), "psnr_min_db": round(float(np.min(ps)), 3),
-                    "psnr_loss_db": round(delta_db, 4), "p_ref_db": P_REF[args.workload],
-                    "ssim_ours_vs_full": round(float(np.mean(ss)), 5), "ssim_min": round(float(np.min(ss)), 5)},
-        "frame": {"keys_dom": int(np.mean(keys_dom)), "keys_roi": int(np.mean(keys_roi)),
-                  "roi_tile_frac": round(float(np.mean(roi_tiles)) / n_tiles, 4), "boxes": float(np.mean(n_boxes))},
-        "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
-        "stage_ms_two_pass": {k: round(v[0] / v[1], 4) for k, v in stages2.items() if v[1]},
+        "config": {"workload": WORKLOAD_TEXT[args.workload] + (f" (surfel count set to {wl.scene.n})"
+                                                               if args.surfels > 0 else ""),
+                   "surfels": int(wl.scene.n), "width": int(wl.W), "height": int(wl.H), "poses": len(wl.cams),
+                   "sh_degree": int(wl.scene.sh_degree), "baseline": wl.baseline,
+                   "center_roi": bool(wl.roi.center_roi), "margin": wl.roi.margin, "edge_bounds": wl.roi.edge_bounds,
+                   "tile": 16, "parallelism": "single GPU"},
+        "two_pass": head["two_pass"],
+        "time_reduction_vs_two_pass": head["time_reduction_vs_two_pass"],
+        "quality": head["quality"],
+        "frame": head["frame"],
+        "memory": head["memory"],
+        "inflight": inf,
+        "configs": extra,
+        "stage_ms": stage_ms,
+        "stage_ms_two_pass": stage_ms2,
         "roofline": roofline,
         "hbm_stages": hbm_stages,
         "cpu_baseline": cpu,
@@ -422,23 +554,24 @@ def traffic_probe_stereo(args):
     affs = [synth.affiliated(c, baseline) for c in cams]
     ds = api.DeviceScene(scene)
     ctx = api.Context(sync=True)
+    roi = api.Roi(center_roi=CENTER_ROI[args.workload])
     out = None
-    for cd, ca in zip(cams, affs):
-        out = ctx.render_stereo(ds, cd, ca, out=out)
+    for cd, ca in list(zip(cams, affs))[:16]:
+        out = ctx.render_stereo(ds, cd, ca, roi=roi, out=out)
     ctx.set_sync(False)
     for _ in range(2):
-        for cd, ca in zip(cams, affs):
-            ctx.render_stereo(ds, cd, ca, out=out)
+        for cd, ca in list(zip(cams, affs))[:16]:
+            ctx.render_stereo(ds, cd, ca, roi=roi, out=out)
     torch.cuda.synchronize()
     log("stereo traffic probe done")
 
 
 def blend_traffic():
-    """HBM bytes per dominant-eye blend stage (all its launches) of the bench
-    workload, from calibrated FETCH_SIZE and WRITE_SIZE counter runs of
-    `bench.py --traffic-probe`; None when the blend kernels or the default
-    blend schedule (raster.hip, bgs_api.hip) have changed since the counters
-    were taken."""
+    """HBM bytes per dominant-eye blend stage (all its launches) of the
+    sphere800 workload, from calibrated FETCH_SIZE and WRITE_SIZE counter
+    runs of `bench.py --traffic-probe`; None when the blend kernels or the
+    default blend schedule (raster.hip, bgs_api.hip) have changed since the
+    counters were taken."""
     import hashlib
     csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2609_30741_amd", "csrc")
     h = hashlib.sha1()
@@ -448,7 +581,7 @@ def blend_traffic():
     return BLEND_TRAFFIC["bytes"] if h.hexdigest() == BLEND_TRAFFIC["source_sha1"] else None
 
 
-def cpu_baseline(args, scene, cam_dom, cam_aff, roi_px):
+def cpu_baseline(args, scene, cam_dom, cam_aff, roi_px, center_roi):
     """Time the CPU oracle on a bounded sample of the workload and scale it to
     stereo frames/s: per-pixel rendering rate from a random sample of
     dominant-eye pixels, plus the oracle's reprojection and classification
@@ -474,7 +607,7 @@ def cpu_baseline(args, scene, cam_dom, cam_aff, roi_px):
     rgb, dr, a = synth.stage_images(W, H, 0)
     t = time.perf_counter()
     rep = O.reproject(cam_dom, cam_aff, rgb, dr, a)
-    O.classify(cam_dom, cam_aff, O.Roi(center_roi=bool(args.center_roi)), rep["depth_range"], rep["rgb"], rep["z"],
+    O.classify(cam_dom, cam_aff, O.Roi(center_roi=bool(center_roi)), rep["depth_range"], rep["rgb"], rep["z"],
                rep["alpha"], rep["hole"])
     t_rc = time.perf_counter() - t
     s_frame = (W * H + roi_px) / rate + t_rc

@@ -62,7 +62,10 @@ def check_pixels(rgb, a, z_or_d, ref, where, proxy):
     loose = ((e_rgb > AMBIGUOUS_TOL) | (e_a > AMBIGUOUS_TOL)) & amb
     log(f"[{where}] px={amb.size} ambiguous={int(amb.sum())} max_rgb_err={float(e_rgb[~amb].max()):.2e} "
         f"max_depth_err={float(e_d[~amb].max()):.2e} bad={int(bad.sum())}")
-    assert amb.mean() <= 0.0035
+    # The flagged share of the whole image stays below 0.35%; on a sample of
+    # n pixels allow three binomial standard deviations above that.
+    n = amb.size
+    assert amb.sum() <= 0.0035 * n + 3.0 * np.sqrt(0.0035 * n), f"{where}: {int(amb.sum())} of {n} ambiguous"
     assert not bad.any(), f"{where}: {int(bad.sum())} pixels outside tolerance"
     assert not loose.any()
 
