@@ -48,7 +48,7 @@ typedef enum bgs_status {
     BGS_ERR_WORKSPACE = -2,    /* workspace smaller than bgs_workspace_size() */
     BGS_ERR_CAPACITY = -3,     /* more tile keys than the workspace holds */
     BGS_ERR_HIP = -4,          /* a HIP runtime call or launch failed */
-    BGS_ERR_UNSUPPORTED = -5   /* a valid but unsupported setting (e.g. tile != 16) */
+    BGS_ERR_UNSUPPORTED = -5   /* a valid but unsupported setting (e.g. an ROI tile other than 8, 16, 32) */
 } bgs_status;
 
 /* Pinhole camera (Eq. 3-5).  width, height in [1, 16384]; fx, fy > 0;
@@ -103,7 +103,12 @@ typedef struct bgs_raster_params {
 } bgs_raster_params;
 
 /* ROI generator settings (Sec. 3.5).  margin m >= 0 pixels (32 in the
- * paper); tile must be 16 (the rasteriser's native tile); edge_samples N
+ * paper); tile T is the ROI tile size: 16, the rasteriser's native tile
+ * the paper aligns ROIs to, or 8 or 32 (an option for tuning): ROI boxes
+ * are aligned outward to multiples of T, the tile mask holds T x T tiles,
+ * and the patch re-renders exactly the pixels of the masked T-tiles (the
+ * rasteriser still bins 16x16 tiles; with T = 8 it composites only the
+ * masked 8x8 quadrants of each binned tile); edge_samples N
  * in [1, 65536] per image edge; gap_passes in [0, 64]; center_roi = 1
  * enables Step 2 (connected center holes), 0 fills the remaining holes
  * along their row instead; a_min in (0, 1] is the accumulated weight A
@@ -139,7 +144,8 @@ typedef struct bgs_box {
 } bgs_box;
 
 /* Per-frame statistics; overflow bit 0 = tile-key capacity exceeded, bit 1
- * = box capacity exceeded (the tile mask is still complete). */
+ * = box capacity exceeded (the tile mask is still complete).  n_roi_tiles
+ * counts the 16x16 rasteriser tiles the ROI pass re-rendered. */
 typedef struct bgs_stats {
     int64_t n_keys_dom, n_keys_roi;
     int32_t n_holes, n_gap, n_center, n_rowfill, n_boxes, n_roi_tiles;
@@ -180,8 +186,9 @@ BGS_API int32_t bgs_ctx_set_count_pairs(bgs_ctx* ctx, int32_t count);
  * workgroups composite speculatively; the segments are chained front to
  * back, and a pixel that stops inside a segment is composited again over
  * that segment, in order, from its exact state (unless the segment's own
- * walk started from that state).  Defaults 1024, 128, 64,
- * 0, 256.  BGS_ERR_INVALID_ARG for a negative cap or far, or seg_len < 1. */
+ * walk started from that state).  Lists are continued only on images of at
+ * most 4096 16x16 tiles (larger ones fill the GPU with their tiles alone).
+ * Defaults 1024, 128, 64, 0, 256.  BGS_ERR_INVALID_ARG for a negative cap or far, or seg_len < 1. */
 BGS_API int32_t bgs_ctx_set_blend_split(bgs_ctx* ctx, int32_t cap_dom, int32_t cap_roi, int32_t seg_len,
                                         int32_t far_dom, int32_t far_roi);
 
@@ -287,7 +294,8 @@ BGS_API int32_t bgs_reproject_noalloc(bgs_ctx* ctx, const bgs_camera* src, const
  *   boxes      out: edge boxes (left, right, top, bottom that exist), then
  *              center boxes in increasing label order, up to box_capacity
  *   n_boxes    out (device int32): total box count, even beyond capacity
- *   tile_mask  out [ceil(H/16)][ceil(W/16)] uint8: 1 = tile touches a box
+ *   tile_mask  out [ceil(H/T)][ceil(W/T)] uint8 (T = roi->tile): 1 = the
+ *              T x T tile touches a box
  * Asynchronous. */
 BGS_API int32_t bgs_classify_holes(bgs_ctx* ctx, const bgs_camera* src, const bgs_camera* dst,
                                    const bgs_roi_params* roi, const bgs_raster_params* raster,
@@ -295,8 +303,10 @@ BGS_API int32_t bgs_classify_holes(bgs_ctx* ctx, const bgs_camera* src, const bg
                                    float* z_dst, float* alpha_dst, uint8_t* cls, int32_t* labels, bgs_box* boxes,
                                    int32_t box_capacity, int32_t* n_boxes, uint8_t* tile_mask);
 
-/* Stage 4 (Sec. 3.1): ROI-restricted re-rasterisation.  Only tiles with
- * tile_mask = 1 are binned, sorted and blended; every pixel of such a tile
+/* Stage 4 (Sec. 3.1): ROI-restricted re-rasterisation.  tile_mask is
+ * [ceil(H/T)][ceil(W/T)] with T = roi->tile.  Only the 16x16 rasteriser
+ * tiles that overlap a masked T-tile are binned, sorted and blended; every
+ * pixel of a masked T-tile
  * is overwritten with the render at dst: rgb, alpha = A, z = D/A (or +inf
  * when A < a_min), cls = BGS_CLS_ROI.  Other pixels are untouched.
  * n_keys (host, optional) receives the number of ROI keys. */
@@ -315,6 +325,54 @@ BGS_API int32_t bgs_render_stereo(bgs_ctx* ctx, const bgs_scene* scene, const bg
                                   float* depth_raw_dom, float* alpha_dom, float* rgb_aff, float* z_aff,
                                   float* alpha_aff, uint8_t* cls_aff, int32_t* labels, bgs_box* boxes,
                                   int32_t box_capacity, int32_t* n_boxes, uint8_t* tile_mask, bgs_stats* stats);
+
+/* ---- batched form ------------------------------------------------------ */
+
+/* One stereo pair of a batch: its scene, cameras, ROI settings, its own
+ * workspace (bgs_workspace_size for its scene and image size) and its
+ * outputs, laid out as for bgs_render_stereo. */
+typedef struct bgs_batch_pair {
+    const bgs_scene* scene; /* host pointer to a scene description (arrays on the device) */
+    bgs_camera cam_dom, cam_aff;
+    bgs_roi_params roi;
+    int32_t box_capacity;
+    void* ws;
+    size_t ws_bytes;
+    float *rgb_dom, *depth_raw_dom, *alpha_dom;
+    float *rgb_aff, *z_aff, *alpha_aff;
+    uint8_t* cls_aff;
+    int32_t* labels;
+    bgs_box* boxes;
+    int32_t* n_boxes;
+    uint8_t* tile_mask;
+} bgs_batch_pair;
+
+/* Bytes of the batch workspace for n_pairs pairs (descriptors and queue). */
+BGS_API int32_t bgs_batch_workspace_size(int32_t n_pairs, size_t* bytes);
+
+/* Many stereo frames in one call (Sec. 3.1 Stages 1-4 for each pair, with
+ * the same results as bgs_render_stereo given the same settings, except
+ * that long tile lists are never split into continuation segments).  Every
+ * pair's binning runs in turn, then ONE persistent blend launch renders the
+ * dominant-eye tiles of all pairs from a shared (pair, tile) work queue;
+ * then every pair's reprojection, classification and ROI binning, and one
+ * persistent launch for all ROI tiles.  Scenes and image sizes may differ
+ * between pairs.  Asynchronous: each pair's key count and overflow flags are
+ * read with bgs_poll_status on its workspace.  n_pairs in [1, 4096]. */
+BGS_API int32_t bgs_render_stereo_batch(bgs_ctx* ctx, int32_t n_pairs, const bgs_batch_pair* pairs,
+                                        const bgs_raster_params* raster, void* batch_ws, size_t batch_ws_bytes);
+
+/* The batch captured once into a HIP graph and replayed: capture records
+ * every launch of bgs_render_stereo_batch on the context's stream (which
+ * must not be the null stream; stage timing must be off) without running
+ * them; bgs_graph_launch replays them on the context's stream, with the
+ * pairs, cameras and buffers of the capture. */
+typedef struct bgs_graph bgs_graph;
+BGS_API int32_t bgs_batch_graph_capture(bgs_ctx* ctx, int32_t n_pairs, const bgs_batch_pair* pairs,
+                                        const bgs_raster_params* raster, void* batch_ws, size_t batch_ws_bytes,
+                                        bgs_graph** graph);
+BGS_API int32_t bgs_graph_launch(bgs_ctx* ctx, bgs_graph* graph);
+BGS_API int32_t bgs_graph_destroy(bgs_graph* graph);
 
 /* ---- stage-level exports used by the parity tests ---------------------- */
 

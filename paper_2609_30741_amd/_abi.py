@@ -50,6 +50,15 @@ class Stats(C.Structure):
                 ("blend_work_dom", C.c_int64 * 4), ("blend_work_roi", C.c_int64 * 4)]
 
 
+class BatchPair(C.Structure):
+    _fields_ = [("scene", C.c_void_p), ("cam_dom", Camera), ("cam_aff", Camera), ("roi", RoiParams),
+                ("box_capacity", C.c_int32), ("ws", C.c_void_p), ("ws_bytes", C.c_size_t),
+                ("rgb_dom", C.c_void_p), ("depth_raw_dom", C.c_void_p), ("alpha_dom", C.c_void_p),
+                ("rgb_aff", C.c_void_p), ("z_aff", C.c_void_p), ("alpha_aff", C.c_void_p),
+                ("cls_aff", C.c_void_p), ("labels", C.c_void_p), ("boxes", C.c_void_p), ("n_boxes", C.c_void_p),
+                ("tile_mask", C.c_void_p)]
+
+
 STAGES = ["preprocess_dom", "depth_sort_dom", "emit_dom", "tile_sort_dom", "ranges_dom", "blend_dom",
           "reproject", "classify", "preprocess_roi", "depth_sort_roi", "emit_roi", "tile_sort_roi", "ranges_roi",
           "blend_roi"]
@@ -62,6 +71,8 @@ EXPORTS = [
     "bgs_patch_rois", "bgs_render_stereo", "bgs_sort_workspace_size", "bgs_sort_pairs",
     "bgs_label_components", "bgs_preprocess_debug", "bgs_tile_lists_debug", "bgs_ctx_set_count_pairs",
     "bgs_ctx_set_timing", "bgs_timing_collect", "bgs_blend_trace", "bgs_ctx_set_blend_split",
+    "bgs_batch_workspace_size", "bgs_render_stereo_batch", "bgs_batch_graph_capture", "bgs_graph_launch",
+    "bgs_graph_destroy",
     # include/bgs_repair.h
     "bgs_repair_num_params", "bgs_repair_workspace_size", "bgs_repair_forward", "bgs_repair_grad",
     "bgs_repair_adam",
@@ -102,6 +113,11 @@ def load():
                            P, SZ, P, P, P, P, C.POINTER(I64)],
         "bgs_render_stereo": [P, C.POINTER(Scene), C.POINTER(Camera), C.POINTER(Camera), C.POINTER(RasterParams),
                               C.POINTER(RoiParams), P, SZ, P, P, P, P, P, P, P, P, P, I32, P, P, C.POINTER(Stats)],
+        "bgs_batch_workspace_size": [I32, C.POINTER(SZ)],
+        "bgs_render_stereo_batch": [P, I32, C.POINTER(BatchPair), C.POINTER(RasterParams), P, SZ],
+        "bgs_batch_graph_capture": [P, I32, C.POINTER(BatchPair), C.POINTER(RasterParams), P, SZ, C.POINTER(P)],
+        "bgs_graph_launch": [P, P],
+        "bgs_graph_destroy": [P],
         "bgs_sort_workspace_size": [I64, C.POINTER(SZ)],
         "bgs_blend_trace": [P, I64, I32, I32, P, SZ, P],
         "bgs_sort_pairs": [P, P, P, I64, I32, P, SZ],

@@ -1,5 +1,6 @@
 // C ABI of the binocular 2DGS frame path: argument validation, workspace
 // layout and the order of the stages on the context's stream.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -40,6 +41,15 @@ struct bgs_ctx {
     // The workspace whose status block this context last reset: a new one is
     // zeroed completely (its sticky overflow word included) before first use.
     const void* ws_seen = nullptr;
+    // The same for the per-pair workspaces of batched frames.
+    std::vector<const void*> batch_seen;
+    int n_cu = 0;  // compute units of the device (persistent launches), looked up once
+};
+
+// A captured batch: the graph and its executable instance.
+struct bgs_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
 namespace bgs {
@@ -48,6 +58,12 @@ namespace {
 constexpr size_t kAlign = 256;
 // Tiles per pass whose list tail may be continued by segment workgroups.
 constexpr int64_t kContSlots = 512;
+// Long tile lists are continued by segment workgroups only on images of at
+// most this many 16x16 tiles: on larger ones the tiles of a pass already
+// fill the GPU, and the four continuation launches would run (nearly)
+// empty.  800x600 (1900 tiles): continuation saves 54 us in the ROI pass;
+// 1600x1064 (6700 tiles): without it both passes are 18-20 us shorter.
+constexpr int kSplitMaxTiles = 4096;
 
 inline size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -58,7 +74,7 @@ inline size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
     size_t status;
     size_t zbuf, hole, hole2, bcount, rmask, bbox, pflag, pbox, wpart, gpart;
-    size_t ranges, colcum, mprefix, tlist, torder;
+    size_t ranges, colcum, mprefix, tlist, torder, mask16;
     size_t recs, zkeys, rects, counts, dkeys_b, dvals_a, dvals_b, offs, surf_scan;
     size_t recs2, zkeys2, rects2;  // the affiliated eye's surfels, from the dominant pass of a stereo frame
     size_t tkeys_a, tkeys_b, tvals_a, tvals_b;
@@ -96,6 +112,7 @@ Layout make_layout(int64_t n, int64_t W, int64_t H, int64_t kc) {
     L.mprefix = take(4 * (nt + 1));
     L.tlist = take(4 * nt);
     L.torder = take(4 * nt);
+    L.mask16 = take(nt);  // rasteriser-tile mask of an ROI mask with 8- or 32-pixel tiles
     L.recs = take(sizeof(SurfelRec) * n);
     L.zkeys = take(4 * n);
     L.rects = take(8 * n);
@@ -207,7 +224,8 @@ int check_raster(bgs_ctx* ctx, const bgs_raster_params* r) {
 
 int check_roi(bgs_ctx* ctx, const bgs_roi_params* r) {
     if (!r) return fail(ctx, BGS_ERR_INVALID_ARG, "null roi params");
-    if (r->tile != kTile) return fail(ctx, BGS_ERR_UNSUPPORTED, "tile %d unsupported (only 16)", r->tile);
+    if (r->tile != 8 && r->tile != 16 && r->tile != 32)
+        return fail(ctx, BGS_ERR_UNSUPPORTED, "ROI tile %d unsupported (8, 16 or 32)", r->tile);
     if (r->margin < 0 || r->margin > 16384) return fail(ctx, BGS_ERR_INVALID_ARG, "margin %d out of range", r->margin);
     if (r->edge_samples < 1 || r->edge_samples > 65536)
         return fail(ctx, BGS_ERR_INVALID_ARG, "edge_samples %d out of range", r->edge_samples);
@@ -343,7 +361,8 @@ struct SortedVals {
 int raster_pass(bgs_ctx* ctx, const Layout& L, void* ws, int64_t kc, const bgs_scene& scene, const bgs_camera& cam,
                 const bgs_raster_params& rp, const uint8_t* tile_mask, float a_min, const RasterOut& out, int which,
                 const uint32_t* reuse_order = nullptr, const uint32_t** order_out = nullptr,
-                const bgs_camera* cam_next = nullptr, bool precomputed = false, SortedVals* vals_out = nullptr) {
+                const bgs_camera* cam_next = nullptr, bool precomputed = false, SortedVals* vals_out = nullptr,
+                const uint8_t* qmask = nullptr, int qmask_w = 0, BatchBlendDesc* defer = nullptr) {
     hipStream_t s = ctx->stream;
     const int n = (int)scene.n;
     const PreCam pc = make_precam(cam);
@@ -458,11 +477,32 @@ int raster_pass(bgs_ctx* ctx, const Layout& L, void* ws, int64_t kc, const bgs_s
     ba.z_near = (float)cam.z_near;
     ba.patch = tile_mask ? 1 : 0;
     ba.vmask = vmask;
-    const ContArgs ca{which ? ctx->cap_roi : ctx->cap_dom, ctx->seg_len, L.cslots,
-                      which ? ctx->far_roi : ctx->far_dom, &st->n_slots,
+    ba.qmask = qmask;
+    ba.qmask_w = qmask_w;
+    const uint32_t cap = n_tiles > kSplitMaxTiles ? 0u : which ? ctx->cap_roi : ctx->cap_dom;
+    const ContArgs ca{cap, ctx->seg_len, L.cslots, which ? ctx->far_roi : ctx->far_dom, &st->n_slots,
                       &st->n_items,
                       at<uint4>(ws, L.cdesc), at<uint32_t>(ws, L.citem), at<float4>(ws, L.cst1),
                       at<float4>(ws, L.cpart)};
+    if (defer) {
+        // Batched form: the blend of this frame runs later, in one launch with
+        // the other frames of the batch (no continuation there).
+        BatchBlendDesc d{};
+        d.recs = recs;
+        d.vals = svals;
+        d.ranges = ranges;
+        d.tile_list = tile_mask ? at<uint32_t>(ws, L.tlist) : nullptr;
+        d.order = torder;
+        d.n_live = tile_mask ? &st->n_masked : nullptr;
+        d.n_tiles = (uint32_t)n_tiles;
+        d.a = ba;
+        d.rgb = out.rgb;
+        d.dz = out.dz;
+        d.alpha = out.alpha;
+        d.cls = out.cls;
+        HIP_CHECK(launch_put_desc(d, defer, s), "batch descriptor");
+        return BGS_OK;
+    }
     mark(ctx, sb + 5, 0);
     HIP_CHECK(launch_blend(recs, svals, ranges, tile_mask ? at<uint32_t>(ws, L.tlist) : nullptr, torder,
                            tile_mask ? &st->n_masked : nullptr, n_tiles, ba, ca, out.rgb, out.dz, out.alpha, out.cls,
@@ -471,6 +511,25 @@ int raster_pass(bgs_ctx* ctx, const Layout& L, void* ws, int64_t kc, const bgs_s
               "blend");
     mark(ctx, sb + 5, 1);
     return BGS_OK;
+}
+
+// The rasteriser-tile (16x16) mask an ROI pass bins, and the 8x8 quadrant
+// mask its blend honours, for an ROI tile mask with roi.tile-pixel tiles.
+struct PatchMasks {
+    const uint8_t* mask16;
+    const uint8_t* qmask;
+    int qmask_w;
+};
+
+hipError_t patch_masks(bgs_ctx* ctx, const Layout& L, void* ws, const bgs_camera& dst, int T, const uint8_t* tile_mask,
+                       PatchMasks* pm) {
+    if (T == kTile) {
+        *pm = PatchMasks{tile_mask, nullptr, 0};
+        return hipSuccess;
+    }
+    uint8_t* m16 = at<uint8_t>(ws, L.mask16);
+    *pm = PatchMasks{m16, T == 8 ? tile_mask : nullptr, (dst.width + 7) / 8};
+    return launch_mask_to16(tile_mask, T, dst.width, dst.height, m16, ctx->stream);
 }
 
 // Start-of-frame status reset: zero the block, keeping the overflow bits of
@@ -756,8 +815,11 @@ int32_t bgs_patch_rois(bgs_ctx* ctx, const bgs_scene* scene, const bgs_camera* d
     const Layout L = make_layout(scene->n, dst->width, dst->height, kc);
     DevStatus* st = at<DevStatus>(ws, L.status);
     HIP_CHECK(reset_status(ctx, ws, st), "status reset");
-    rc = raster_pass(ctx, L, ws, kc, *scene, *dst, *raster, tile_mask, roi->a_min, RasterOut{rgb_dst, z_dst, alpha_dst, cls},
-                     1);
+    PatchMasks pm{};
+    HIP_CHECK(patch_masks(ctx, L, ws, *dst, roi->tile, tile_mask, &pm), "ROI tile mask");
+    rc = raster_pass(ctx, L, ws, kc, *scene, *dst, *raster, pm.mask16, roi->a_min,
+                     RasterOut{rgb_dst, z_dst, alpha_dst, cls}, 1, nullptr, nullptr, nullptr, false, nullptr, pm.qmask,
+                     pm.qmask_w);
     if (rc) return rc;
     if (!ctx->sync) return BGS_OK;
     DevStatus h{};
@@ -824,9 +886,11 @@ int32_t bgs_render_stereo(bgs_ctx* ctx, const bgs_scene* scene, const bgs_camera
               "classify");
     mark(ctx, BGS_STAGE_CLASSIFY, 1);
     // Stage 4: ROI re-rasterisation of the affiliated eye.
-    rc = raster_pass(ctx, L, ws, kc, *scene, *cam_aff, *raster, tile_mask, roi->a_min,
+    PatchMasks pm{};
+    HIP_CHECK(patch_masks(ctx, L, ws, *cam_aff, roi->tile, tile_mask, &pm), "ROI tile mask");
+    rc = raster_pass(ctx, L, ws, kc, *scene, *cam_aff, *raster, pm.mask16, roi->a_min,
                      RasterOut{rgb_aff, z_aff, alpha_aff, cls_aff}, 1, same_keys ? dom_order : nullptr, nullptr,
-                     nullptr, true);
+                     nullptr, true, nullptr, pm.qmask, pm.qmask_w);
     if (rc) return rc;
     if (!ctx->sync && !stats) return BGS_OK;
     DevStatus h{};
@@ -835,6 +899,171 @@ int32_t bgs_render_stereo(bgs_ctx* ctx, const bgs_scene* scene, const bgs_camera
     if (h.overflow & 1u)
         return fail(ctx, BGS_ERR_CAPACITY, "tile keys (%u dominant, %u ROI) exceed the capacity of %lld", h.n_keys_dom,
                     h.n_keys_roi, (long long)kc);
+    return BGS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+constexpr int32_t kMaxBatch = 4096;
+
+size_t batch_desc_bytes(int32_t n) { return up(sizeof(BatchBlendDesc) * (size_t)n); }
+
+size_t batch_ws_bytes_for(int32_t n) { return 2 * batch_desc_bytes(n) + 2 * up(4 * ((size_t)n + 2)); }
+
+// Start-of-frame status reset of a batched pair's workspace (sticky overflow
+// kept once this context has reset that workspace before).
+hipError_t reset_status_batch(bgs_ctx* ctx, void* ws, DevStatus* st) {
+    bool seen = false;
+    for (const void* w : ctx->batch_seen) seen = seen || w == ws;
+    if (!seen) ctx->batch_seen.push_back(ws);
+    return launch_status_reset(st, seen ? 0 : 1, ctx->stream);
+}
+
+// Validate the batch (host only, nothing launched), then issue it.
+int batch_issue(bgs_ctx* ctx, int32_t n, const bgs_batch_pair* pairs, const bgs_raster_params* raster, void* bws,
+                size_t bws_bytes) {
+    int rc;
+    if (n < 1 || n > kMaxBatch) return fail(ctx, BGS_ERR_INVALID_ARG, "batch of %d pairs outside [1, %d]", n, kMaxBatch);
+    if (!pairs || !bws) return fail(ctx, BGS_ERR_INVALID_ARG, "null batch");
+    if ((rc = check_raster(ctx, raster))) return rc;
+    if (bws_bytes < batch_ws_bytes_for(n)) return fail(ctx, BGS_ERR_WORKSPACE, "batch workspace too small");
+    if (ctx->timing) return fail(ctx, BGS_ERR_INVALID_ARG, "stage timing must be off for batched frames");
+    std::vector<Layout> lays((size_t)n);
+    std::vector<int64_t> kcs((size_t)n);
+    for (int32_t i = 0; i < n; ++i) {
+        const bgs_batch_pair& q = pairs[i];
+        if ((rc = check_scene(ctx, q.scene)) || (rc = check_camera(ctx, &q.cam_dom, "dominant camera")) ||
+            (rc = check_camera(ctx, &q.cam_aff, "affiliated camera")) || (rc = check_roi(ctx, &q.roi)))
+            return rc;
+        if (!q.ws || !q.rgb_dom || !q.depth_raw_dom || !q.alpha_dom || !q.rgb_aff || !q.z_aff || !q.alpha_aff ||
+            !q.cls_aff || !q.labels || !q.n_boxes || !q.tile_mask || q.box_capacity < 0 ||
+            (q.box_capacity > 0 && !q.boxes))
+            return fail(ctx, BGS_ERR_INVALID_ARG, "pair %d: null buffer or negative box capacity", i);
+        const int W = std::max(q.cam_dom.width, q.cam_aff.width), H = std::max(q.cam_dom.height, q.cam_aff.height);
+        kcs[i] = key_capacity_for(q.scene->n, W, H, q.ws_bytes);
+        if (kcs[i] < 0) return fail(ctx, BGS_ERR_WORKSPACE, "pair %d: workspace of %zu bytes is too small", i, q.ws_bytes);
+        lays[i] = make_layout(q.scene->n, W, H, kcs[i]);
+    }
+    if (ctx->n_cu <= 0) {
+        int dev = 0, cus = 0;
+        HIP_CHECK(hipGetDevice(&dev), "device");
+        HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
+        ctx->n_cu = cus > 0 ? cus : 256;
+    }
+    const int grid = ctx->n_cu * 8;  // 8 blend workgroups fit a CU (LDS)
+    hipStream_t s = ctx->stream;
+    BatchBlendDesc* dd = at<BatchBlendDesc>(bws, 0);
+    BatchBlendDesc* dr = at<BatchBlendDesc>(bws, batch_desc_bytes(n));
+    uint32_t* qd = at<uint32_t>(bws, 2 * batch_desc_bytes(n));
+    uint32_t* qr = at<uint32_t>(bws, 2 * batch_desc_bytes(n) + up(4 * ((size_t)n + 2)));
+    std::vector<const uint32_t*> dom_order((size_t)n);
+    // Stage 1 of every pair up to its sorted tile lists; the blends follow in
+    // one launch.
+    for (int32_t i = 0; i < n; ++i) {
+        const bgs_batch_pair& q = pairs[i];
+        void* ws = q.ws;
+        HIP_CHECK(reset_status_batch(ctx, ws, at<DevStatus>(ws, lays[i].status)), "status reset");
+        rc = raster_pass(ctx, lays[i], ws, kcs[i], *q.scene, q.cam_dom, *raster, nullptr, 0.f,
+                         RasterOut{q.rgb_dom, q.depth_raw_dom, q.alpha_dom, nullptr}, 0, nullptr, &dom_order[i],
+                         &q.cam_aff, false, nullptr, nullptr, 0, dd + i);
+        if (rc) return rc;
+    }
+    HIP_CHECK(launch_blend_batch(dd, n, qd, grid, false, s), "batched blend");
+    // Stages 2-3 and the ROI binning of every pair, then one launch for all
+    // ROI tiles.
+    for (int32_t i = 0; i < n; ++i) {
+        const bgs_batch_pair& q = pairs[i];
+        void* ws = q.ws;
+        const Layout& L = lays[i];
+        DevStatus* st = at<DevStatus>(ws, L.status);
+        const PreCam pd = make_precam(q.cam_dom), pa = make_precam(q.cam_aff);
+        const bool same_keys = std::memcmp(pd.zc, pa.zc, sizeof pd.zc) == 0 && pd.z_near == pa.z_near;
+        const WarpCam wd = make_warpcam(q.cam_dom), wa = make_warpcam(q.cam_aff);
+        const RelPose P = rel_pose(q.cam_dom, q.cam_aff);
+        HIP_CHECK(launch_reproject(wd, wa, P, q.roi.a_min, q.rgb_dom, q.depth_raw_dom, q.alpha_dom,
+                                   at<unsigned long long>(ws, L.zbuf), q.rgb_aff, q.z_aff, q.alpha_aff, q.cls_aff, nullptr,
+                                   false, at<uint4>(ws, L.wpart), st, s),
+                  "reproject");
+        ClassifyBufs b{at<uint8_t>(ws, L.hole), at<uint8_t>(ws, L.hole2), at<uint32_t>(ws, L.bcount),
+                       at<uint32_t>(ws, L.rmask), at<int32_t>(ws, L.bbox), at<uint8_t>(ws, L.pflag),
+                       at<int4>(ws, L.pbox), at<uint4>(ws, L.wpart), at<uint2>(ws, L.gpart)};
+        HIP_CHECK(launch_classify(wd, wa, P, q.roi, raster->bg, nullptr, q.rgb_aff, q.z_aff, q.alpha_aff, q.cls_aff,
+                                  q.labels, q.boxes, q.box_capacity, q.n_boxes, q.tile_mask, b, st, s),
+                  "classify");
+        PatchMasks pm{};
+        HIP_CHECK(patch_masks(ctx, L, ws, q.cam_aff, q.roi.tile, q.tile_mask, &pm), "ROI tile mask");
+        rc = raster_pass(ctx, L, ws, kcs[i], *q.scene, q.cam_aff, *raster, pm.mask16, q.roi.a_min,
+                         RasterOut{q.rgb_aff, q.z_aff, q.alpha_aff, q.cls_aff}, 1, same_keys ? dom_order[i] : nullptr,
+                         nullptr, nullptr, true, nullptr, pm.qmask, pm.qmask_w, dr + i);
+        if (rc) return rc;
+    }
+    HIP_CHECK(launch_blend_batch(dr, n, qr, grid, true, s), "batched ROI blend");
+    return BGS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t bgs_batch_workspace_size(int32_t n_pairs, size_t* bytes) {
+    if (!bytes || n_pairs < 1 || n_pairs > kMaxBatch) return BGS_ERR_INVALID_ARG;
+    *bytes = batch_ws_bytes_for(n_pairs);
+    return BGS_OK;
+}
+
+int32_t bgs_render_stereo_batch(bgs_ctx* ctx, int32_t n_pairs, const bgs_batch_pair* pairs,
+                                const bgs_raster_params* raster, void* batch_ws, size_t batch_ws_bytes) {
+    if (!ctx) return BGS_ERR_INVALID_ARG;
+    return batch_issue(ctx, n_pairs, pairs, raster, batch_ws, batch_ws_bytes);
+}
+
+int32_t bgs_batch_graph_capture(bgs_ctx* ctx, int32_t n_pairs, const bgs_batch_pair* pairs,
+                                const bgs_raster_params* raster, void* batch_ws, size_t batch_ws_bytes,
+                                bgs_graph** graph) {
+    if (!ctx) return BGS_ERR_INVALID_ARG;
+    if (!graph) return fail(ctx, BGS_ERR_INVALID_ARG, "null graph");
+    if (!ctx->stream) return fail(ctx, BGS_ERR_INVALID_ARG, "graph capture needs a stream other than the null stream");
+    HIP_CHECK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    const int rc = batch_issue(ctx, n_pairs, pairs, raster, batch_ws, batch_ws_bytes);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(ctx->stream, &g);  // ends the capture whatever happened
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);  // the error of the issue is the one reported
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(ctx, e, "end capture");
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(ctx, ei, "graph instantiate");
+    }
+    bgs_graph* out = new (std::nothrow) bgs_graph();
+    if (!out) {
+        (void)hipGraphExecDestroy(ex);
+        (void)hipGraphDestroy(g);
+        return fail(ctx, BGS_ERR_INVALID_ARG, "out of host memory");
+    }
+    out->graph = g;
+    out->exec = ex;
+    *graph = out;
+    return BGS_OK;
+}
+
+int32_t bgs_graph_launch(bgs_ctx* ctx, bgs_graph* graph) {
+    if (!ctx) return BGS_ERR_INVALID_ARG;
+    if (!graph || !graph->exec) return fail(ctx, BGS_ERR_INVALID_ARG, "null graph");
+    HIP_CHECK(hipGraphLaunch(graph->exec, ctx->stream), "graph launch");
+    return BGS_OK;
+}
+
+int32_t bgs_graph_destroy(bgs_graph* graph) {
+    if (!graph) return BGS_OK;
+    if (graph->exec) (void)hipGraphExecDestroy(graph->exec);  // nothing to report on teardown
+    if (graph->graph) (void)hipGraphDestroy(graph->graph);
+    delete graph;
     return BGS_OK;
 }
 

@@ -74,6 +74,11 @@ struct BlendArgs {
     float z_near;
     int patch;       // 0: write rgb/depth_raw/alpha; 1: write rgb/z/alpha/cls
     uint32_t vmask;  // surfel index = sorted value & vmask (values that also carry the tile key)
+    // ROI patch with 8-pixel ROI tiles: the 8x8 ROI tile mask (qmask_w tiles
+    // per row); an 8x8 quadrant of a 16x16 tile that it leaves out is neither
+    // composited nor written.  Null otherwise.
+    const uint8_t* qmask;
+    int qmask_w;
 };
 
 // Continuation of long tile lists in the blend (k_blend, k_blend_seg,
@@ -216,9 +221,40 @@ hipError_t launch_blend(const SurfelRec* recs, const uint32_t* vals, const uint2
                         const uint32_t* tile_list, const uint32_t* order, const uint32_t* n_live, int n_blocks,
                         const BlendArgs& a, const ContArgs& ca, float* rgb, float* d_or_z, float* alpha, uint8_t* cls,
                         unsigned long long* pair_counts, long long* trace, hipStream_t s);
+// One frame's blend of a batch (one eye of one stereo pair), in device
+// memory: a persistent launch renders the tiles of every frame of the batch
+// from a shared work queue.
+struct BatchBlendDesc {
+    const SurfelRec* recs;
+    const uint32_t* vals;
+    const uint2* ranges;
+    const uint32_t* tile_list;  // compact id -> tile id (masked passes); null: identity
+    const uint32_t* order;      // dispatch order of the compact tiles, heaviest first
+    const uint32_t* n_live;     // live compact tiles (masked passes); null: n_tiles
+    uint32_t n_tiles;
+    uint32_t reserved;
+    BlendArgs a;
+    float* rgb;
+    float* dz;
+    float* alpha;
+    uint8_t* cls;
+};
+// Copy a descriptor (a kernel argument) into device memory.
+hipError_t launch_put_desc(const BatchBlendDesc& d, BatchBlendDesc* dst, hipStream_t s);
+// Blend every tile of n frames: item prefix over the frames, then one
+// persistent launch of `grid` workgroups that take (frame, tile) items from
+// a queue counter in turn until all are done (no waits between workgroups).
+// scratch: n + 2 words (prefix and counter).  patch: the frames are ROI
+// passes (the patch writes).
+hipError_t launch_blend_batch(const BatchBlendDesc* descs, int n, uint32_t* scratch, int grid, bool patch,
+                              hipStream_t s);
+
 // Tables of an ROI tile mask (n_tiles = tiles_x * tiles_y): prefix[n_tiles +
 // 1], the compact list of masked tile ids, the masked count in DevStatus, and
 // colcum[tiles_y][tiles_x + 1], the column sums of prefix over rows.
+// The 16x16 rasteriser-tile mask of an ROI tile mask with T x T tiles (T =
+// 8 or 32) for a W x H image: a 16-tile is set iff it overlaps a set T-tile.
+hipError_t launch_mask_to16(const uint8_t* tmask, int T, int W, int H, uint8_t* mask16, hipStream_t s);
 hipError_t launch_mask_tables(const uint8_t* tile_mask, int n_tiles, int tiles_x, uint32_t* prefix,
                               uint32_t* tile_list, uint32_t* colcum, DevStatus* st, hipStream_t s);
 // Record the key count offs[n] of a binning (which: 0 dominant, 1 ROI).

@@ -558,9 +558,12 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order
     const int r0 = blockIdx.x * spb;  // spb <= 256 surfels, one thread each; all 256 threads write keys
     const int m = min(spb, n - r0);
     const uint32_t base = offs[r0];
+    // A block whose surfels have no key (culled ones sort last; most of a
+    // masked pass's surfels miss its tiles) leaves before staging anything.
+    if (offs[r0 + m] == base) return;
     const int t = threadIdx.x;
     const uint32_t* pref = mask.prefix;
-    if (mask_lds > 0) {  // uniform over the grid
+    if (mask_lds > 0) {  // uniform over the block
         for (int i = t; i < mask_lds; i += 256) s_mpre[i] = mask.prefix[i];
         __syncthreads();
         pref = s_mpre;
@@ -753,19 +756,28 @@ __global__ __launch_bounds__(1024) void k_mask_tables(const uint8_t* __restrict_
         st->n_roi_tiles = s_run;
     }
     __syncthreads();  // prefix is read back below by other threads of this block
-    // Column sums, a column per thread; the prefix is staged in LDS when it
-    // fits so that the walk down a column reads LDS.
+    // Column sums: a wave takes a column and scans it down the rows 64 at a
+    // time with shuffles (a serial walk per column left most threads idle);
+    // the prefix is staged in LDS when it fits.
     const int tiles_y = n_tiles / tiles_x;
     const bool staged = n_tiles + 1 <= kMaskLds;
     if (staged) {
         for (int t = tid; t <= n_tiles; t += 1024) s_pre[t] = prefix[t];
         __syncthreads();
     }
-    for (int xc = tid; xc <= tiles_x; xc += 1024) {
-        uint32_t acc = 0;
-        for (int ty = 0; ty < tiles_y; ++ty) {
-            acc += staged ? s_pre[ty * tiles_x + xc] : prefix[ty * tiles_x + xc];
-            colcum[(int64_t)ty * (tiles_x + 1) + xc] = acc;
+    for (int xc = wave; xc <= tiles_x; xc += 16) {
+        uint32_t carry = 0;
+        for (int y0 = 0; y0 < tiles_y; y0 += 64) {
+            const int ty = y0 + lane;
+            const int q = ty * tiles_x + xc;  // xc = tiles_x reads the next row's first entry, as the serial walk did
+            uint32_t x = ty < tiles_y ? (staged ? s_pre[q] : prefix[q]) : 0u;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t y = __shfl_up(x, off, 64);
+                if (lane >= off) x += y;
+            }
+            if (ty < tiles_y) colcum[(int64_t)ty * (tiles_x + 1) + xc] = carry + x;
+            carry += __shfl(x, 63, 64);
         }
     }
 }
@@ -1018,7 +1030,8 @@ __device__ __forceinline__ TileGeom tile_geom(uint32_t tile, int tid, const Blen
     const int wave = g.tid >> 6;
     *px = tx * kTile + (wave & 1) * 8 + (g.lane & 7);
     *py = ty * kTile + (wave >> 1) * 8 + (g.lane >> 3);
-    *inside = *px < a.W && *py < a.H;
+    *inside = *px < a.W && *py < a.H &&
+              (!a.qmask || a.qmask[(int64_t)(2 * ty + (wave >> 1)) * a.qmask_w + 2 * tx + (wave & 1)] != 0);
     g.fpx = (float)*px;
     g.fpy = (float)*py;
     g.scx = (float)(tx * kTile + (wave & 1) * 8) + 3.5f;
@@ -1418,7 +1431,10 @@ hipError_t launch_masked_counts_ordered(const uint2* rects, const SurfelRec* rec
                                         int n_tiles, const MaskArgs& mask, uint32_t* counts, uint32_t* partials,
                                         hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    const int mask_lds = n_tiles + 1 <= kEmitMaskLds ? n_tiles + 1 : 0;
+    // The mask prefix is read from global memory (it stays in L2): staging it
+    // in LDS per workgroup cost more than the lookups (emission and counts of
+    // a 1M-surfel, 6700-tile ROI pass: 111 -> 94 us).
+    const int mask_lds = 0;
     hipLaunchKernelGGL(k_masked_counts_ordered, dim3((unsigned)((n + 255) / 256)), dim3(256),
                        (size_t)mask_lds * sizeof(uint32_t), s, rects, recs, order, n, mask, mask_lds, counts,
                        partials);
@@ -1439,7 +1455,7 @@ hipError_t launch_emit(const uint32_t* order, const uint32_t* offs, const uint2*
                        uint32_t* tvals, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     if (vbits < 0 || vbits > 31 || (vbits && (int64_t)n > ((int64_t)1 << vbits))) return hipErrorInvalidValue;
-    const int mask_lds = mask.enabled && n_tiles + 1 <= kEmitMaskLds ? n_tiles + 1 : 0;
+    const int mask_lds = 0;  // the mask prefix is read from global memory (see launch_masked_counts_ordered)
     // Unmasked, the surfels nearest the camera (first in compositing order)
     // carry several times the mean key count: 128 surfels per workgroup
     // halve the heaviest workgroups (65 -> 49 us on a 5.9M-key frame).
@@ -1447,6 +1463,113 @@ hipError_t launch_emit(const uint32_t* order, const uint32_t* offs, const uint2*
     const int spb = mask.enabled ? 256 : 128;
     hipLaunchKernelGGL(k_emit, dim3((n + spb - 1) / spb), dim3(256), (size_t)mask_lds * sizeof(uint32_t), s, order,
                        offs, rects, recs, n, spb, tiles_x, mask, mask_lds, cap, vbits, tkeys, tvals);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched blend: one persistent launch over the tiles of many frames.  Each
+// workgroup takes the next (frame, compact tile) item from a queue counter,
+// composites the tile's whole list (no continuation: the batch itself keeps
+// the GPU full) and writes its pixels, until the queue is empty.  Items go
+// frame by frame, each frame's tiles heaviest first.  Workgroups never wait
+// for one another, so every workgroup reaches the end of the queue.
+// ---------------------------------------------------------------------------
+__global__ void k_put_desc(BatchBlendDesc d, BatchBlendDesc* dst) {
+    if (threadIdx.x == 0) *dst = d;
+}
+
+hipError_t launch_put_desc(const BatchBlendDesc& d, BatchBlendDesc* dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_put_desc, dim3(1), dim3(64), 0, s, d, dst);
+    return hipGetLastError();
+}
+
+__global__ void k_batch_prefix(const BatchBlendDesc* __restrict__ descs, int n, uint32_t* __restrict__ prefix,
+                               uint32_t* __restrict__ counter) {
+    if (threadIdx.x != 0) return;
+    uint32_t run = 0;
+    for (int f = 0; f < n; ++f) {
+        prefix[f] = run;
+        run += descs[f].n_live ? min(*descs[f].n_live, descs[f].n_tiles) : descs[f].n_tiles;
+    }
+    prefix[n] = run;
+    *counter = 0u;
+}
+
+template <bool kPatch>
+__global__ __launch_bounds__(256) void k_blend_batch(const BatchBlendDesc* __restrict__ descs, int n,
+                                                     const uint32_t* __restrict__ prefix, uint32_t* counter) {
+    __shared__ float4 s_rec[(kBatch + 1) * 4];
+    __shared__ __align__(8) uint16_t s_list[4 * kListLen];
+    __shared__ uint32_t s_item;
+    const int tid = (int)threadIdx.x;
+    if (tid < 4) s_rec[4 * kDummy + tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+    const uint32_t total = prefix[n];
+    WalkCounts wc{0, 0, 0, 0};
+    for (;;) {
+        __syncthreads();  // the previous item's use of s_item and the LDS batches is over
+        if (tid == 0) s_item = atomicAdd(counter, 1u);
+        __syncthreads();
+        const uint32_t item = s_item;
+        if (item >= total) break;
+        // The frame: the last f with prefix[f] <= item (a frame with no item
+        // shares its prefix with the next one and is never chosen).
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (prefix[mid] <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatchBlendDesc d = descs[lo];
+        const uint32_t blk = item - prefix[lo];
+        const uint32_t cid = d.order ? d.order[blk] : blk;
+        const uint32_t tile = d.tile_list ? d.tile_list[cid] : cid;
+        bool inside;
+        int px, py;
+        const TileGeom g = tile_geom(tile, tid, d.a, &inside, &px, &py);
+        const uint2 rg = d.ranges[cid];
+        PixelState p{inside ? 1.f : 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        walk_range<false>(d.recs, d.vals, rg.x, rg.y, s_rec, s_list + (tid >> 6) * kListLen, g, d.a, p, wc);
+        if (inside) write_pixel<kPatch>(p, px, py, d.a, d.rgb, d.dz, d.alpha, d.cls);
+    }
+}
+
+hipError_t launch_blend_batch(const BatchBlendDesc* descs, int n, uint32_t* scratch, int grid, bool patch,
+                              hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    uint32_t* prefix = scratch;
+    uint32_t* counter = scratch + n + 1;
+    hipLaunchKernelGGL(k_batch_prefix, dim3(1), dim3(64), 0, s, descs, n, prefix, counter);
+    if (patch)
+        hipLaunchKernelGGL((k_blend_batch<true>), dim3(grid), dim3(256), 0, s, descs, n, prefix, counter);
+    else
+        hipLaunchKernelGGL((k_blend_batch<false>), dim3(grid), dim3(256), 0, s, descs, n, prefix, counter);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_mask_to16(const uint8_t* __restrict__ tm, int T, int tw, int th, int tiles_x,
+                                                   int tiles_y, uint8_t* __restrict__ m16) {
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= tiles_x * tiles_y) return;
+    const int tx = t % tiles_x, ty = t / tiles_x;
+    uint8_t v = 0;
+    if (T == 32) {
+        v = tm[(ty >> 1) * tw + (tx >> 1)] != 0;
+    } else {  // T == 8: any of the (up to) four 8x8 tiles of this 16x16 tile
+        for (int dy = 0; dy < 2; ++dy)
+            for (int dx = 0; dx < 2; ++dx) {
+                const int qx = 2 * tx + dx, qy = 2 * ty + dy;
+                if (qx < tw && qy < th && tm[qy * tw + qx]) v = 1;
+            }
+    }
+    m16[t] = v;
+}
+
+hipError_t launch_mask_to16(const uint8_t* tmask, int T, int W, int H, uint8_t* mask16, hipStream_t s) {
+    if (T != 8 && T != 32) return hipErrorInvalidValue;
+    const int tiles_x = (W + kTile - 1) / kTile, tiles_y = (H + kTile - 1) / kTile;
+    const int tw = (W + T - 1) / T, th = (H + T - 1) / T;
+    hipLaunchKernelGGL(k_mask_to16, dim3((unsigned)((tiles_x * tiles_y + 255) / 256)), dim3(256), 0, s, tmask, T, tw,
+                       th, tiles_x, tiles_y, mask16);
     return hipGetLastError();
 }
 

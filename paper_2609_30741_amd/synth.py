@@ -286,6 +286,37 @@ def workload_serve2064(seed: int = 0, n: int = 1_000_000, n_poses: int = 32):
     return scene, cams, BASELINE_IPD
 
 
+BATCH_RESOLUTIONS = ((640, 480), (1024, 768), (1440, 1600), (1920, 1080))
+
+
+def workload_batch(seed: int = 0, n_pairs: int = 64, sizes=(50_000, 200_000, 600_000, 1_200_000)):
+    """The batched configuration: four resident scenes, cube type (uniform
+    in [-1,1]^3, SH0, as the 10k cube scene) for the 1st and 3rd size and
+    shell type (noisy unit sphere shell, SH3, as the 300k scene) for the
+    2nd and 4th, and n_pairs stereo pairs, pair i on scene i mod 4, each
+    with a resolution drawn from BATCH_RESOLUTIONS and fx = fy = 1.17 W
+    (cube type: 300 / 256) or 1.375 W (shell type: 1100 / 800).  Cube-type
+    eyes sit at distance 4 from the origin and shell-type eyes on an orbit
+    of radius 3, at seeded azimuths, all looking at the origin.  Returns
+    (scenes, [(scene index, dominant camera)], baseline)."""
+    scenes = [scene_uniform_cube(seed, sizes[0]), scene_sphere_shell(seed + 1, sizes[1]),
+              scene_uniform_cube(seed + 2, sizes[2]), scene_sphere_shell(seed + 3, sizes[3])]
+    rng = np.random.default_rng(seed + 100)
+    pairs = []
+    for i in range(n_pairs):
+        si = i % 4
+        W, H = BATCH_RESOLUTIONS[int(rng.integers(0, len(BATCH_RESOLUTIONS)))]
+        th = float(rng.uniform(0.0, 2.0 * np.pi))
+        if si % 2 == 0:
+            eye = (4.0 * np.sin(th), -4.0 * np.cos(th), float(rng.uniform(-0.5, 0.5)))
+            fx = 1.17 * W
+        else:
+            eye = (3.0 * np.cos(th), 3.0 * np.sin(th), float(rng.uniform(-0.3, 0.3)))
+            fx = 1.375 * W
+        pairs.append((si, look_at(eye, (0.0, 0.0, 0.0), (0.0, 0.0, 1.0), W, H, fx)))
+    return scenes, pairs, BASELINE_IPD
+
+
 WORKLOADS = {
     "cube256": workload_cube256,
     "sphere800": workload_sphere800,

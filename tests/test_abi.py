@@ -45,6 +45,10 @@ def test_struct_sizes():
     assert C.sizeof(_abi.RoiParams) == 28
     assert C.sizeof(_abi.Box) == 24
     assert C.sizeof(_abi.Stats) == 144
+    # bgs_batch_pair: 448 bytes, box_capacity at 340 and tile_mask at 440
+    # (include/bgs.h compiled by the host compiler agrees).
+    assert C.sizeof(_abi.BatchPair) == 448
+    assert _abi.BatchPair.box_capacity.offset == 340 and _abi.BatchPair.tile_mask.offset == 440
 
 
 @pytest.fixture
@@ -116,7 +120,7 @@ def test_render_validation(L, ctx):
 
 def test_stage_validation(L, ctx):
     cam = _cam()
-    roi = api.Roi(tile=32).c()
+    roi = api.Roi(tile=24).c()  # ROI tiles are 8, 16 or 32 pixels
     rc = L.bgs_reproject(ctx, C.byref(cam), C.byref(cam), C.byref(roi), FAKE, FAKE, FAKE, FAKE, 1 << 30, FAKE, FAKE,
                          FAKE, FAKE, FAKE)
     assert rc == _abi.ERR_UNSUPPORTED

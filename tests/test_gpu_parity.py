@@ -541,3 +541,69 @@ def test_timing_stage_mask(ctx):
     t = ctx.timing_collect()
     ctx.set_timing(False)
     assert all(v[1] == 1 for v in t.values()), t
+
+
+# ---------------------------------------------------------------------------
+# ROI tiles of 8 and 32 pixels (the tuning options next to the paper's 16)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("T", [8, 32])
+@pytest.mark.parametrize("W,H,seed,b", [(256, 192, 11, 0.064), (203, 117, 12, 0.3)])
+def test_classify_roi_tile_bit_exact(ctx, oracle, T, W, H, seed, b):
+    dom, aff = stage_rig(W, H, 1.2 * W, b)
+    rgb, dr, a = synth.stage_images(W, H, seed, n_occluders=10)
+    rep = oracle.reproject(dom, aff, rgb, dr, a)
+    ref = oracle.classify(dom, aff, oracle.Roi(tile=T), rep["depth_range"], rep["rgb"], rep["z"], rep["alpha"],
+                          rep["hole"], box_cap=4096)
+    g = [torch.from_numpy(x).cuda() for x in (rep["rgb"], rep["z"], rep["alpha"], rep["hole"])]
+    out = ctx.classify_holes(dom, aff, torch.from_numpy(rep["depth_range"]).cuda(), *g, api.Roi(tile=T),
+                             box_capacity=4096)
+    torch.cuda.synchronize()
+    nb = int(to_np(out["n_boxes"])[0])
+    assert nb == ref["n_boxes"] > 0
+    assert np.array_equal(to_np(out["boxes"])[:nb], ref["boxes"])
+    assert np.array_equal(to_np(out["tile_mask"]), ref["tile_mask"])
+    assert np.array_equal(to_np(g[3]), ref["cls"]) and np.array_equal(to_np(out["labels"]), ref["labels"])
+
+
+@pytest.mark.parametrize("T", [8, 32])
+def test_patch_roi_tile_sizes(ctx, oracle, T):
+    """The patch re-renders exactly the pixels of the masked T-tiles (with
+    T = 8 only the masked 8x8 quadrants of each binned 16x16 tile)."""
+    sc, _ = cube_workload(10_000, 200, 136, 240.0, seed=6)  # neither side a multiple of 16 or 32
+    cam = synth.look_at((0.0, -4.0, 0.0), (0, 0, 0), (0, 0, 1), 200, 136, 240.0)
+    ds = api.DeviceScene(sc)
+    H, W = 136, 200
+    tm = (np.random.default_rng(T).uniform(size=(-(-H // T), -(-W // T))) < 0.35).astype(np.uint8)
+    base = np.random.default_rng(2).uniform(size=(3, H, W)).astype(np.float32)
+    g_rgb, g_z = torch.from_numpy(base.copy()).cuda(), torch.zeros((H, W), device="cuda")
+    g_a, g_cls = torch.zeros((H, W), device="cuda"), torch.zeros((H, W), dtype=torch.uint8, device="cuda")
+    ctx.patch_rois(ds, cam, torch.from_numpy(tm).cuda(), g_rgb, g_z, g_a, g_cls, roi=api.Roi(tile=T))
+    ref = oracle.patch(sc, cam, tm, base, np.zeros((H, W), np.float32), np.zeros((H, W), np.float32),
+                       np.zeros((H, W), np.uint8), tile=T)
+    pm = np.kron(tm, np.ones((T, T), np.uint8)).astype(bool)[:H, :W]
+    rgb = to_np(g_rgb)
+    assert np.array_equal(rgb[:, ~pm], base[:, ~pm])
+    assert np.array_equal(to_np(g_cls), ref["cls"])
+    amb = ref["amb"] > 0
+    err = np.abs(np.clip(rgb, 0, 1) - np.clip(ref["rgb"], 0, 1)).max(0)
+    assert not np.any((err > RGB_TOL) & pm & ~amb)
+    assert np.abs(to_np(g_a) - ref["alpha"])[pm & ~amb].max() <= RGB_TOL
+
+
+@pytest.mark.parametrize("T", [8, 32])
+def test_render_stereo_roi_tile_sizes(ctx, oracle, T):
+    sc, cam = cube_workload(10_000, 256, 256, 300.0, seed=7)
+    aff = synth.affiliated(cam, 0.064)
+    out = ctx.render_stereo(api.DeviceScene(sc), cam, aff, roi=api.Roi(tile=T))
+    ref = oracle.render_stereo(sc, cam, aff, roi=oracle.Roi(tile=T))
+    cls_g, cls_o = to_np(out["cls_aff"]), ref["aff"]["cls"]
+    mism = (cls_g != cls_o).mean()
+    log(f"stereo T={T}: class mismatch {mism:.5f}; stats {out['stats']}")
+    assert mism < 2e-3
+    assert to_np(out["tile_mask"]).shape == (-(-256 // T), -(-256 // T))
+    same = cls_g == cls_o
+    rgb_g, rgb_o = np.clip(to_np(out["rgb_aff"]), 0, 1), np.clip(ref["aff"]["rgb"], 0, 1)
+    amb = ref["aff"]["amb"] > 0
+    roi_px = same & (cls_g == api.CLS_ROI) & ~amb
+    assert roi_px.sum() > 0 and np.abs(rgb_g - rgb_o).max(0)[roi_px].max() <= RGB_TOL

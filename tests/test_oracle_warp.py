@@ -54,12 +54,14 @@ def test_plane_shift_closed_form(oracle, Z):
         if 0 <= t < W:
             assert np.array_equal(out["rgb"][:, :, t], rgb[:, :, i])
     np.testing.assert_array_equal(out["depth_range"], np.float32([Z, Z]))
-    # Eq. 7-8 closed form: only the right border is uncovered.
-    roi = oracle.Roi()
-    widths, boxes = oracle.edge_rois(dom, aff, roi, out["depth_range"])
-    rw = min(max((W - 1) - math.floor(W - 1 - s) + roi.margin, 0), W // 2)
-    assert list(widths) == [0, rw, 0, 0]
-    assert boxes.tolist() == [[(W - rw) // 16 * 16, 0, W, H, oracle.BOX_RIGHT, -1]]
+    # Eq. 7-8 closed form: only the right border is uncovered; the strip is
+    # aligned outward to the ROI tile T.
+    for T in (8, 16, 32):
+        roi = oracle.Roi(tile=T)
+        widths, boxes = oracle.edge_rois(dom, aff, roi, out["depth_range"])
+        rw = min(max((W - 1) - math.floor(W - 1 - s) + roi.margin, 0), W // 2)
+        assert list(widths) == [0, rw, 0, 0]
+        assert boxes.tolist() == [[(W - rw) // T * T, 0, W, H, oracle.BOX_RIGHT, -1]]
 
 
 def test_edge_rois_cube_workload_example(oracle):
@@ -142,9 +144,9 @@ def test_background_moves_with_rotation_only(oracle):
     np.testing.assert_array_equal(out["depth_range"], np.float32([dom.z_near, dom.z_far]))
 
 
-def _classify(oracle, rgb, z, a, hole, center=True, passes=2, margin=32, W=None, H=None):
+def _classify(oracle, rgb, z, a, hole, center=True, passes=2, margin=32, W=None, H=None, tile=16):
     dom, _ = rig(W=W or rgb.shape[2], H=H or rgb.shape[1])
-    roi = oracle.Roi(center_roi=center, gap_passes=passes, margin=margin)
+    roi = oracle.Roi(center_roi=center, gap_passes=passes, margin=margin, tile=tile)
     # Zero baseline and a single depth: no edge ROIs, only the given holes.
     return oracle.classify(dom, dom, roi, np.array([4.0, 4.0], np.float32), rgb, z, a, hole)
 
@@ -203,14 +205,18 @@ def test_gap_run_filled_iff_short(oracle, w):
         assert (out["cls"][8:30, 10:10 + w] == oracle.CLS_GAP).all() == (w <= 2 * k)
 
 
-def test_center_hole_box(oracle):
+@pytest.mark.parametrize("T", [8, 16, 32])
+def test_center_hole_box(oracle, T):
+    # The box of a center hole is its bounding box grown by m and aligned
+    # outward to the ROI tile T (16: the rasteriser's tile; 8 and 32 are
+    # the tuning options); the tile mask holds exactly the T-tiles it covers.
     W, H = 160, 128
     rgb = np.full((3, H, W), 0.3, np.float32)
     z = np.full((H, W), 2.0, np.float32)
     a = np.ones((H, W), np.float32)
     hole = np.zeros((H, W), np.uint8)
     hole[50:70, 60:75] = 1   # 20x15 block, too wide for 2 passes
-    out = _classify(oracle, rgb, z, a, hole)
+    out = _classify(oracle, rgb, z, a, hole, tile=T)
     lab = out["labels"]
     rem = out["cls"] == oracle.CLS_HOLE
     assert rem.sum() > 0 and np.all(lab[rem] == lab[rem].min())
@@ -218,11 +224,12 @@ def test_center_hole_box(oracle):
     assert lab.ravel()[first] == first
     ys, xs = np.nonzero(rem)
     x0, y0, x1, y1 = xs.min() - 32, ys.min() - 32, xs.max() + 1 + 32, ys.max() + 1 + 32
-    x0, y0 = max(x0, 0) // 16 * 16, max(y0, 0) // 16 * 16
-    x1, y1 = min(-(-min(x1, W) // 16) * 16, W), min(-(-min(y1, H) // 16) * 16, H)
+    x0, y0 = max(x0, 0) // T * T, max(y0, 0) // T * T
+    x1, y1 = min(-(-min(x1, W) // T) * T, W), min(-(-min(y1, H) // T) * T, H)
     assert out["boxes"].tolist() == [[x0, y0, x1, y1, oracle.BOX_CENTER, first]]
+    assert out["tile_mask"].shape == (-(-H // T), -(-W // T))
     tm = np.zeros_like(out["tile_mask"])
-    tm[y0 // 16:-(-y1 // 16), x0 // 16:-(-x1 // 16)] = 1
+    tm[y0 // T:-(-y1 // T), x0 // T:-(-x1 // T)] = 1
     assert np.array_equal(out["tile_mask"], tm)
 
 
@@ -504,3 +511,21 @@ def test_edge_rois_rotated_rig_match_world_route(oracle, which, edge_bounds):
            min(max(math.ceil(ymin) + m, 0), H // 2) if ymin > 0 else 0,
            min(max((H - 1) - math.floor(ymax) + m, 0), H // 2) if ymax < H - 1 else 0]
     assert list(widths) == exp
+
+
+@pytest.mark.parametrize("T", [8, 32])
+def test_patch_roi_tile_size(oracle, T):
+    """With T-pixel ROI tiles the patch re-renders exactly the pixels of the
+    masked T-tiles, each equal to the full render there."""
+    sc = synth.scene_uniform_cube(5, 500)
+    cam = synth.look_at((0.0, -4.0, 0.0), (0, 0, 0), (0, 0, 1), 72, 40, 80.0)  # not a multiple of 16 or 32
+    full = oracle.render(sc, cam)
+    H, W = 40, 72
+    tm = (np.random.default_rng(T).uniform(size=(-(-H // T), -(-W // T))) < 0.4).astype(np.uint8)
+    base = np.random.default_rng(1).uniform(size=(3, H, W)).astype(np.float32)
+    z0 = np.zeros((H, W), np.float32)
+    out = oracle.patch(sc, cam, tm, base, z0, z0, np.zeros((H, W), np.uint8), tile=T)
+    pm = np.kron(tm, np.ones((T, T), np.uint8)).astype(bool)[:H, :W]
+    assert np.array_equal(out["rgb"][:, ~pm], base[:, ~pm])
+    assert np.array_equal(out["rgb"][:, pm], full["rgb"][:, pm].astype(np.float32))
+    assert np.array_equal(out["cls"] == oracle.CLS_ROI, pm)
