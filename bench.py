@@ -352,6 +352,123 @@ def inflight(wl, args, kmax):
             "note": "several frames on several streams at once: outside the paper's one-stream protocol"}
 
 
+def batched(args):
+    """The batched form: args.batch_pairs stereo pairs over four resident
+    scenes (50k / 600k cube-type, 200k / 1.2M shell-type surfels) at mixed
+    resolutions.  The autotuner picks the ROI tile and margin per (scene,
+    resolution) group on two calibration pairs of the group; the batch is
+    then one call (persistent blends over a shared (pair, tile) queue),
+    captured once in a HIP graph and replayed.  Next to it, on the same
+    pairs: the plain form (bgs_render_stereo per pair, one stream, the
+    paper's ROI settings) and the sequential two-pass render.  Quality: the
+    affiliated eye of both forms against its full render."""
+    import torch
+    from paper_2609_30741_amd import api, autotune, batch, synth
+    t0 = time.time()
+    scenes, pairs, b = synth.workload_batch(args.seed, args.batch_pairs)
+    ds = [api.DeviceScene(sc) for sc in scenes]
+    items = [(si, cd, synth.affiliated(cd, b)) for si, cd in pairs]
+    groups = {}
+    for si, cd, ca in items:
+        groups.setdefault((si, cd.width, cd.height), []).append((ds[si], cd, ca))
+    log(f"[batch] {len(items)} pairs over {len(scenes)} scenes ({', '.join(str(sc.n) for sc in scenes)} surfels), "
+        f"{len(groups)} (scene, resolution) groups; generated in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    tuned = autotune.tune({k: v[:2] for k, v in groups.items()})
+    log(f"[batch] autotuned in {time.time() - t0:.1f}s: " +
+        ", ".join(f"{k}: T{v['tile']} m{v['margin']}" for k, v in tuned.items()))
+    bpairs = []
+    for si, cd, ca in items:
+        tv = tuned[(si, cd.width, cd.height)]
+        bpairs.append((ds[si], cd, ca, api.Roi(tile=tv["tile"], margin=tv["margin"])))
+    n = len(bpairs)
+    R = args.batch_reps
+    # Full renders of the affiliated eyes (the quality reference).
+    ref = api.Context(sync=True)
+    full = [ref.render_dominant(ds_, ca)["rgb"].clone() for ds_, _, ca, _ in bpairs]
+    del ref
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ctx = api.Context(sync=False)
+        sb = batch.StereoBatch(ctx, bpairs)
+        ws_gb = (sum(w.numel() for w in sb.ws) + sb.bws.numel()) / 1e9
+        sb.capture()
+        for _ in range(2):
+            sb.replay()
+        stream.synchronize()
+        t = time.perf_counter()
+        for _ in range(R):
+            sb.replay()
+        stream.synchronize()
+        t_graph = time.perf_counter() - t
+        t = time.perf_counter()
+        for _ in range(R):
+            sb.render()
+        stream.synchronize()
+        t_eager = time.perf_counter() - t
+        over = [st["overflow"] for st in sb.poll()]
+        assert not any(over), f"capacity overflow in the batch: {over}"
+        ps_b = [10 * math.log10(1 / max(float(((o["rgb_aff"].clamp(0, 1).double() - f.clamp(0, 1).double()) ** 2)
+                                               .mean()), 1e-30)) for o, f in zip(sb.outs, full)]
+        sb.close()
+        del sb
+    torch.cuda.synchronize()
+    # The plain form and the two-pass render, one stream, frames in sequence.
+    ctx = api.Context(sync=True)
+    outs, fds, fos, ps_p = [], [], [], []
+    for (ds_, cd, ca, _), f in zip(bpairs, full):
+        o = ctx.render_stereo(ds_, cd, ca, box_capacity=1024)
+        ps_p.append(10 * math.log10(1 / max(float(((o["rgb_aff"].clamp(0, 1).double() - f.clamp(0, 1).double()) ** 2)
+                                                  .mean()), 1e-30)))
+        o.pop("stats")
+        outs.append(o)
+        fds.append(ctx.render_dominant(ds_, cd))
+        fos.append(ctx.render_dominant(ds_, ca))
+    ctx.set_sync(False)
+
+    def plain(i0, k):
+        for _ in range(k):
+            for (ds_, cd, ca, _), o in zip(bpairs, outs):
+                ctx.render_stereo(ds_, cd, ca, box_capacity=1024, out=o)
+
+    def two(i0, k):
+        for _ in range(k):
+            for (ds_, cd, ca, _), fd, fo in zip(bpairs, fds, fos):
+                ctx.render_dominant(ds_, cd, out=fd)
+                ctx.render_dominant(ds_, ca, out=fo)
+
+    res = {}
+    for name, fn in (("plain", plain), ("two_pass", two)):
+        fn(0, 1)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        fn(0, R)
+        torch.cuda.synchronize()
+        res[name] = time.perf_counter() - t
+    assert ctx.poll_status()["overflow"] == 0
+    mse_ref = 10 ** (-28.83 / 10)
+    loss = lambda ps: float(np.mean([10 * math.log10(1 + 10 ** (-p / 10) / mse_ref) for p in ps]))
+    out = {"workload": "64 stereo pairs over 4 resident scenes (50k/600k cube-type SH0, 200k/1.2M shell-type SH3), "
+                       "resolutions drawn from 640x480, 1024x768, 1440x1600, 1920x1080",
+           "pairs": n, "batches_timed": R,
+           "value": round(n * R / t_graph, 2), "unit": "stereo frames/s",
+           "graph_ms_per_batch": round(t_graph / R * 1e3, 3),
+           "eager_value": round(n * R / t_eager, 2),
+           "plain_value": round(n * R / res["plain"], 2),
+           "two_pass_value": round(n * R / res["two_pass"], 2),
+           "time_reduction_vs_plain": round(1 - t_graph / res["plain"], 4),
+           "time_reduction_vs_two_pass": round(1 - t_graph / res["two_pass"], 4),
+           "psnr_batched_db": round(float(np.mean(ps_b)), 3), "psnr_plain_db": round(float(np.mean(ps_p)), 3),
+           "psnr_loss_batched_db": round(loss(ps_b), 4), "psnr_loss_plain_db": round(loss(ps_p), 4),
+           "workspace_gb": round(ws_gb, 2),
+           "tuned": {f"scene{k[0]}_{k[1]}x{k[2]}": {"tile": v["tile"], "margin": v["margin"], "ms": v["ms"],
+                                                    "plain_ms": v["plain_ms"], "psnr": v["psnr"],
+                                                    "plain_psnr": v["plain_psnr"]} for k, v in tuned.items()}}
+    log(f"[batch] graph {out['value']} fps (eager {out['eager_value']}), plain {out['plain_value']}, two-pass "
+        f"{out['two_pass_value']}; PSNR batched {out['psnr_batched_db']} dB, plain {out['psnr_plain_db']} dB")
+    return out
+
+
 def stage_breakdown(ctx, wl, out, fd, fo, n):
     import torch
     ctx.set_timing(True)
@@ -390,6 +507,9 @@ def main():
     ap.add_argument("--inflight-split", default="0,0,128,0,0",
                     help="blend split (cap_dom, cap_roi, seg_len, far_dom, far_roi) of the in-flight region, "
                          "both methods; 0,0 never continues a tile list")
+    ap.add_argument("--batch-pairs", type=int, default=64,
+                    help="stereo pairs of the batched form's measurement (0: skip it)")
+    ap.add_argument("--batch-reps", type=int, default=5, help="timed batches of the batched form")
     ap.add_argument("--traffic-probe-stereo", action="store_true",
                     help="no timing: 48 stereo frames of the workload at the default blend split (16 sizing the "
                          "workspace, then 32), for per-kernel rocprofv3 counter runs")
@@ -469,6 +589,8 @@ def main():
         cpu = cpu_baseline(args, wl.scene, wl.cams[0], wl.affs[0], head["frame"]["roi_tile_frac"] * wl.n_tiles * 256.0,
                            wl.roi.center_roi)
 
+    bat = batched(args) if args.batch_pairs > 0 else None
+
     extra = []
     for name in [c for c in args.configs.split(",") if c and c != args.workload]:
         w2 = Workload(name, args.seed)
@@ -507,6 +629,7 @@ def main():
         "memory": head["memory"],
         "inflight": inf,
         "configs": extra,
+        "batched": bat,
         "stage_ms": stage_ms,
         "stage_ms_two_pass": stage_ms2,
         "roofline": roofline,
