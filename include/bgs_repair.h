@@ -55,6 +55,15 @@ BGS_API int32_t bgs_repair_forward(const float* params, int32_t batch, int32_t h
                                    const float* rgb, const float* z, const uint8_t* hole, float* rgb_out,
                                    float* err_out, void* ws, size_t ws_bytes, void* hip_stream);
 
+/* Mean predicted squared error over the holes of each image, the fallback
+ * policy's measure: out[b] (device, batch floats) = sum of err_out[b] over
+ * hole pixels / max(1, holes), with err_out as bgs_repair_forward writes it.
+ * scratch: device, BGS_REPAIR_HOLE_ERROR_SCRATCH(batch) floats.  Summation
+ * order is fixed (deterministic).  batch in [1, 1000], sides in [1, 16384]. */
+#define BGS_REPAIR_HOLE_ERROR_SCRATCH(batch) (512 * (size_t)(batch))
+BGS_API int32_t bgs_repair_hole_error(const float* err, const uint8_t* hole, int32_t batch, int32_t height,
+                                      int32_t width, float* out, float* scratch, void* hip_stream);
+
 /* Forward and backward pass: loss (one device float) and the gradient of
  * the loss in the parameter layout (grad, device, overwritten).  rgb_out
  * may be null. */

@@ -50,6 +50,7 @@ def measure(ctx, pairs, T, m, raster, reps=3, full=None):
         torch.cuda.synchronize()
         times.append(float(np.median([e0.elapsed_time(e1) for e0, e1 in ev])))
     st = ctx.poll_status()
+    ctx.set_sync(True)  # later renders size the workspace again (a synchronous call grows it on overflow)
     if st["overflow"]:
         raise RuntimeError("key capacity exceeded while tuning")
     return float(np.mean(times)), float(np.mean(ps))
@@ -63,6 +64,9 @@ def tune(groups, raster: api.Raster = api.Raster(), reps: int = 3, tol_db: float
     ctx.set_blend_split(0, 0, 64, 0, 0)
     res = {}
     for key, pairs in groups.items():
+        # Synchronous: the full renders grow the workspace to this group's
+        # scene and image size if they need more keys than it holds.
+        ctx.set_sync(True)
         full = [ctx.render_dominant(ds, ca, raster)["rgb"].clone() for ds, _, ca in pairs]
         table = {}
         for T, m in candidates:

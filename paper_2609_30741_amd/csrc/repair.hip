@@ -401,6 +401,41 @@ __global__ __launch_bounds__(256) void k_count(const uint8_t* __restrict__ hole,
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
+// Predicted error of each image over its holes, first step: block b of
+// image y sums err and counts holes over its grid-stride pixels, into
+// part[2 (y * kErrParts + b) + {0, 1}].
+constexpr int kErrParts = 256;
+__global__ __launch_bounds__(256) void k_err_part(const float* __restrict__ err, const uint8_t* __restrict__ hole,
+                                                  int64_t HW, float* __restrict__ part) {
+    __shared__ float red[4];
+    const int64_t img = blockIdx.y;
+    float e = 0.f, c = 0.f;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < HW; p += (int64_t)kErrParts * 256) {
+        if (hole[img * HW + p]) {
+            e += err[img * HW + p];
+            c += 1.f;
+        }
+    }
+    e = block_sum(e, red);
+    __syncthreads();
+    c = block_sum(c, red);
+    if (threadIdx.x == 0) {
+        part[2 * (img * kErrParts + blockIdx.x)] = e;
+        part[2 * (img * kErrParts + blockIdx.x) + 1] = c;
+    }
+}
+
+// Second step, one block per image: out[y] = sum e / max(1, holes).
+__global__ __launch_bounds__(256) void k_err_mean(const float* __restrict__ part, float* __restrict__ out) {
+    __shared__ float red[4];
+    const int64_t img = blockIdx.x;
+    const float* q = part + 2 * img * kErrParts;
+    float e = block_sum(q[2 * threadIdx.x], red);
+    __syncthreads();
+    const float c = block_sum(q[2 * threadIdx.x + 1], red);
+    if (threadIdx.x == 0) out[img] = e / fmaxf(c, 1.f);
+}
+
 // One block: out[0] = scale * sum of part[0, n) (fixed order per thread,
 // then the block tree).
 __global__ __launch_bounds__(256) void k_sum(const float* __restrict__ part, int n, const float* __restrict__ div,
@@ -691,6 +726,20 @@ BGS_API int32_t bgs_repair_forward(const float* params, int32_t batch, int32_t h
     const int64_t np = (int64_t)batch * height * width;
     hipLaunchKernelGGL(k_output, dim3(blocks(np)), dim3(256), 0, s, rgb, hole, (const float*)f.r, batch,
                        height * width, rgb_out, err_out);
+    return launched();
+}
+
+BGS_API int32_t bgs_repair_hole_error(const float* err, const uint8_t* hole, int32_t batch, int32_t height,
+                                      int32_t width, float* out, float* scratch, void* hip_stream) {
+    static_assert(kErrParts == 256, "one part per thread of the second step");
+    if (!err || !hole || !out || !scratch || batch < 1 || batch > 1000 || height < 1 || width < 1 || height > 16384 ||
+        width > 16384)
+        return BGS_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)hip_stream;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_err_part, dim3(kErrParts, batch), dim3(256), 0, s, err, hole, (int64_t)height * width,
+                       scratch);
+    hipLaunchKernelGGL(k_err_mean, dim3(batch), dim3(256), 0, s, (const float*)scratch, out);
     return launched();
 }
 

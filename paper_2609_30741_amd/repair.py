@@ -126,6 +126,21 @@ class Repair:
                                          ws.numel(), api._stream()), "bgs_repair_forward")
         return out
 
+    def hole_error(self, err, hole, out=None, scratch=None):
+        """Mean predicted squared error over each image's holes ([B]
+        device floats), the fallback policy's measure."""
+        B, H, W = (int(x) for x in hole.shape)
+        api.check_tensor("err", err, (B, H, W), torch.float32, err.device)
+        api.check_tensor("hole", hole, (B, H, W), torch.uint8, err.device)
+        out = torch.empty(B, device=err.device) if out is None else out
+        api.check_tensor("out", out, (B,), torch.float32, err.device)
+        scratch = torch.empty(512 * B, device=err.device) if scratch is None else scratch
+        api.check_tensor("scratch", scratch, (512 * B,), torch.float32, err.device)
+        P = _abi_ptr
+        _check(self.L.bgs_repair_hole_error(P(err), P(hole), B, H, W, P(out), P(scratch), api._stream()),
+               "bgs_repair_hole_error")
+        return out
+
     def grad_step(self, rgb, z, hole, target, rgb_out=None):
         """Loss and gradient into self.loss / self.grad (asynchronous)."""
         B, H, W = self.check_images(rgb, z, hole, out=rgb_out, target=target)
@@ -170,6 +185,34 @@ def make_pairs(scene, cams_dom, cams_aff, roi: api.Roi = api.Roi()):
                         depth_range=w["depth_range"].clone(), target=t["rgb"].clone()))
     torch.cuda.synchronize()
     return out
+
+
+def config_pairs(seed=0):
+    """Training and held-out pairs from the three plain configurations'
+    scenes: the 10k cube seen from 12 azimuths at distance 4 (256x256), the
+    300k shell's 16 orbit poses (800x600) and the 1M unbounded scene's 32
+    forward poses (1600x1064); every fourth pose (and the cube's last three)
+    is held out.  Returns {config: (train, test, cams_dom_test, cams_aff_test,
+    scene)}."""
+    from . import synth
+    out = {}
+    sc = synth.scene_uniform_cube(seed, 10_000)
+    cams = [synth.look_at((4.0 * math.sin(t), -4.0 * math.cos(t), 0.8), (0, 0, 0), (0, 0, 1), 256, 256, 300.0)
+            for t in np.linspace(0.0, 2.0 * np.pi, 12, endpoint=False)]
+    held = [9, 10, 11]
+    out["cube256"] = (sc, cams, held, synth.BASELINE_IPD)
+    sc, cams, b = synth.WORKLOADS["sphere800"](seed)
+    out["sphere800"] = (sc, cams, [0, 5, 10, 15], b)
+    sc, cams, b = synth.WORKLOADS["unbounded1600"](seed)
+    out["unbounded1600"] = (sc, cams, list(range(3, 32, 4)), b)
+    res = {}
+    for name, (sc, cams, held, b) in out.items():
+        affs = [synth.affiliated(c, b) for c in cams]
+        tr = [i for i in range(len(cams)) if i not in held]
+        res[name] = (make_pairs(sc, [cams[i] for i in tr], [affs[i] for i in tr]),
+                     make_pairs(sc, [cams[i] for i in held], [affs[i] for i in held]),
+                     [cams[i] for i in held], [affs[i] for i in held], sc)
+    return res
 
 
 def crops(pairs, batch, size, rng, min_holes=16):
@@ -248,8 +291,76 @@ def hole_psnr(a, b, mask):
     return 10.0 * math.log10(1.0 / max(mse, 1e-12))
 
 
+def evaluate(net, ctx, name, test, cams_dom, cams_aff, scene, reps=20):
+    """Held-out poses of one configuration: hole-pixel PSNR of the network,
+    of the plain interpolation fill and of the full method (interpolation
+    plus ROI re-rendering), the error channel's correlation, and the time of
+    the network's pass against the full method's affiliated-eye work."""
+    ds = api.DeviceScene(scene)
+    rows = []
+    for p, cd, ca in zip(test, cams_dom, cams_aff):
+        err = torch.empty((1,) + tuple(p["hole"].shape), device=p["rgb"].device)
+        x = net.forward(p["rgb"][None].contiguous(), p["z"][None].contiguous(), p["hole"][None].contiguous(),
+                        err=err)[0]
+        interp, cls = interpolation_fill(p, cd, ca)
+        filled = (p["hole"] > 0) & ((cls == _abi.CLS_GAP) | (cls == _abi.CLS_ROWFILL))
+        full = ctx.render_stereo(ds, cd, ca)["rgb_aff"]
+        rows.append(dict(psnr_net=hole_psnr(x, p["target"], filled), psnr_interp=hole_psnr(interp, p["target"], filled),
+                         psnr_net_all=hole_psnr(x, p["target"], p["hole"]),
+                         psnr_method_all=hole_psnr(full, p["target"], p["hole"]),
+                         corr=error_correlation(x, p["target"], p["hole"], err[0]),
+                         pred_err=float(net.hole_error(err, p["hole"][None])[0])))
+    # Times at this configuration's frame size: the network's pass, and the
+    # method's affiliated-eye work after reprojection (classification and
+    # ROI patch).
+    p, cd, ca = test[0], cams_dom[0], cams_aff[0]
+    a = (p["rgb"][None].contiguous(), p["z"][None].contiguous(), p["hole"][None].contiguous())
+    o = torch.empty_like(a[0])
+
+    def timeit(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    net_ms = timeit(lambda: net.forward(*a, out=o))
+    rgb, z, al, hole = p["rgb"].clone(), p["z"].clone(), p["alpha"].clone(), p["hole"].clone()
+    roi = api.Roi()
+
+    def method():
+        rgb.copy_(p["rgb"])
+        z.copy_(p["z"])
+        al.copy_(p["alpha"])
+        hole.copy_(p["hole"])
+        c = ctx.classify_holes(cd, ca, p["depth_range"], rgb, z, al, hole, roi)
+        ctx.patch_rois(ds, ca, c["tile_mask"], rgb, z, al, hole)
+
+    ctx.set_sync(True)
+    method()  # sizes the workspace
+    ctx.set_sync(False)
+    method_ms = timeit(method)
+    ctx.set_sync(True)
+    m = lambda k: round(float(np.mean([r[k] for r in rows])), 3)
+    H, W = p["hole"].shape
+    return {"config": name, "width": int(W), "height": int(H), "held_out_poses": len(rows),
+            "hole_psnr_net": m("psnr_net"), "hole_psnr_interp": m("psnr_interp"),
+            "hole_psnr_net_all_holes": m("psnr_net_all"), "hole_psnr_method_all_holes": m("psnr_method_all"),
+            "err_corr": m("corr"), "pred_err_mean": float(np.mean([r["pred_err"] for r in rows])),
+            "net_ms": round(net_ms, 4), "method_aff_ms": round(method_ms, 4)}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--configs", action="store_true",
+                    help="train on crops from the three configurations' scenes (cube, shell, unbounded) and report "
+                         "each configuration's held-out poses")
+    ap.add_argument("--save", default="", help="write the trained parameters here (.npy)")
     ap.add_argument("--steps", type=int, default=600)
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--crop", type=int, default=128)
@@ -260,6 +371,24 @@ def main(argv=None):
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
         return 3
+    if args.configs:
+        t0 = time.perf_counter()
+        sets = config_pairs(args.seed)
+        pairs = [q for tr, *_ in sets.values() for q in tr]
+        t_data = time.perf_counter() - t0
+        net = Repair(seed=args.seed)
+        t0 = time.perf_counter()
+        losses = train(net, pairs, args.steps, args.batch, args.crop, args.lr, args.seed, log=250)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        if args.save:
+            np.save(args.save, net.params.cpu().numpy())
+        ctx = api.Context()
+        rows = [evaluate(net, ctx, name, te, cd, ca, sc) for name, (_, te, cd, ca, sc) in sets.items()]
+        print(json.dumps({"train_pairs": args.steps * args.batch, "crop": args.crop, "source_frames": len(pairs),
+                          "data_s": round(t_data, 2), "train_s": round(t_train, 2), "losses": losses,
+                          "configs": rows}), flush=True)
+        return 0
     scene, cams, b = synth.WORKLOADS["sphere800"](args.seed)
     affs = [synth.affiliated(c, b) for c in cams]
     held = [0, 5, 10, 15]

@@ -55,6 +55,9 @@ class Request:
     admitted: float = math.nan  # host time of issue, seconds after the start
     done: float = math.nan  # completion on the GPU clock, seconds after the start
     out: Optional[dict] = None
+    phase: int = 0  # learned mode: 1 after the network pass, 2 after a fallback pass
+    pred_err: float = math.nan  # learned mode: the network's mean predicted squared error at the holes
+    fallback: Optional[bool] = None  # learned mode: interpolation + ROI re-rendering replaced the network
 
     @property
     def latency(self) -> float:
@@ -86,7 +89,7 @@ def serve(requests: List[Request], executor, n_slots: int, mem_budget: float,
             queue.append(pending.popleft())
             progressed = True
         for s, r in list(busy.items()):
-            t = executor.poll(s)
+            t = executor.poll(s, r)
             if t is not None:
                 r.done = t
                 executor.release(s, r)
@@ -136,11 +139,22 @@ class GpuExecutor:
     scenes resident; completion from an event recorded after each frame."""
 
     def __init__(self, scenes: dict, n_slots: int, raster=None, roi=None, mode: str = "stereo",
-                 key_capacity: int = 0, keep_outputs: bool = False):
+                 key_capacity: int = 0, keep_outputs: bool = False, repair_params=None, threshold: float = math.inf):
         import torch
         from . import api
         self.torch, self.api = torch, api
+        if mode not in ("stereo", "two_pass", "learned"):
+            raise ValueError(f"unknown mode {mode}")
         self.mode = mode
+        self.threshold = float(threshold)
+        self.nets = []
+        if mode == "learned":
+            from . import repair
+            if repair_params is None:
+                raise ValueError("the learned mode needs the repair network's parameters")
+            # One network object per slot: the parameters are copied, and each
+            # slot's forward passes get a workspace of their own.
+            self.nets = [repair.Repair(params=repair_params) for _ in range(n_slots)]
         self.raster = raster or api.Raster()
         self.roi = roi or api.Roi()
         self.keep = keep_outputs
@@ -166,8 +180,18 @@ class GpuExecutor:
         """Bytes of the output images a frame of this request writes."""
         pd = int(r.cam_dom.width) * int(r.cam_dom.height)
         pa = int(r.cam_aff.width) * int(r.cam_aff.height)
-        if self.mode != "stereo":
+        if self.mode == "two_pass":
             return 20 * (pd + pa)  # rgb, depth, alpha per eye
+        if self.mode == "learned":
+            import ctypes as C
+            rw = C.c_size_t()
+            self.nets[0].L.bgs_repair_workspace_size(1, int(r.cam_aff.height), int(r.cam_aff.width), 0, C.byref(rw))
+            T = self.roi.tile
+            tiles = ((int(r.cam_aff.width) + T - 1) // T) * ((int(r.cam_aff.height) + T - 1) // T)
+            # dominant rgb/depth/alpha; warped rgb/z/alpha, class map, labels,
+            # network rgb and error; boxes, counts, tile mask, the network's
+            # workspace and the error reduction's scratch
+            return (20 * pd + 41 * pa + 6 * 4 * self.box_capacity + tiles + 4 + 8 + 4 + 4 * 512 + int(rw.value))
         T = self.roi.tile
         tiles = ((int(r.cam_aff.width) + T - 1) // T) * ((int(r.cam_aff.height) + T - 1) // T)
         # dominant rgb/depth/alpha; affiliated rgb/z/alpha, class map, labels; boxes, count, tile mask
@@ -182,15 +206,23 @@ class GpuExecutor:
         held = 0 if ws is None else ws.numel()
         o = self.outs[s]
         if o is not None:
-            ts = [t for d in ((o["dom"], o["aff"]) if "dom" in o else (o,)) for t in d.values()
-                  if isinstance(t, self.torch.Tensor)]
+            ts = []
+            for v in o.values():
+                if isinstance(v, dict):
+                    ts += [t for t in v.values() if isinstance(t, self.torch.Tensor)]
+                elif isinstance(v, self.torch.Tensor) and not v.is_pinned():
+                    ts.append(v)
             held += sum(t.numel() * t.element_size() for t in ts)
+        if self.nets:
+            held += sum(w.numel() for w in self.nets[s]._ws.values())
         return float(held)
 
     def trim(self, s: int):
         """Free an idle slot's workspace and output images."""
         self.ctxs[s].ws = None
         self.outs[s] = None
+        if self.nets:
+            self.nets[s]._ws.clear()
 
     def start(self):
         torch = self.torch
@@ -213,6 +245,9 @@ class GpuExecutor:
             o = self.outs[s]
             if o is not None and self.held_bytes(s) != self.need_bytes(r):
                 o = None
+            if self.mode == "learned":
+                self._issue_learned(s, r, ctx, sc, o)
+                return
             if self.mode == "stereo":
                 if o is not None and not self._stereo_fits(o, r):
                     o = None
@@ -238,6 +273,73 @@ class GpuExecutor:
             ev.record(self.streams[s])
             self.events[s] = ev
 
+    def _issue_learned(self, s: int, r: Request, ctx, sc, o):
+        """First phase of a learned-mode frame on slot s's stream: dominant
+        render, reprojection into the affiliated buffers, the repair network
+        over the warped image, and its mean predicted error at the holes,
+        copied to pinned host memory for the fallback decision."""
+        torch = self.torch
+        cd, ca = r.cam_dom, r.cam_aff
+        Hd, Wd, H, W = int(cd.height), int(cd.width), int(ca.height), int(ca.width)
+        if o is None or tuple(o["dom"]["rgb"].shape[1:]) != (Hd, Wd) or tuple(o["warp"]["rgb"].shape[1:]) != (H, W):
+            dev = "cuda"
+            T = self.roi.tile
+            o = {"dom": None,
+                 "warp": dict(rgb=torch.empty((3, H, W), device=dev), z=torch.empty((H, W), device=dev),
+                              alpha=torch.empty((H, W), device=dev),
+                              hole=torch.empty((H, W), dtype=torch.uint8, device=dev),
+                              depth_range=torch.empty(2, device=dev)),
+                 "cls": dict(labels=torch.empty((H, W), dtype=torch.int32, device=dev),
+                             boxes=torch.empty((self.box_capacity, 6), dtype=torch.int32, device=dev),
+                             n_boxes=torch.empty(1, dtype=torch.int32, device=dev),
+                             tile_mask=torch.empty(((H + T - 1) // T, (W + T - 1) // T), dtype=torch.uint8,
+                                                   device=dev)),
+                 "net": torch.empty((1, 3, H, W), device=dev), "err": torch.empty((1, H, W), device=dev),
+                 "stat": torch.empty(1, device=dev), "scratch": torch.empty(512, device=dev),
+                 "stat_host": torch.empty(1, pin_memory=True)}
+        o["dom"] = ctx.render_dominant(sc, cd, self.raster, out=o["dom"])
+        d, w = o["dom"], o["warp"]
+        ctx.reproject(cd, ca, d["rgb"], d["depth_raw"], d["alpha"], self.roi, out=w)
+        net = self.nets[s]
+        net.forward(w["rgb"][None], w["z"][None], w["hole"][None], out=o["net"], err=o["err"])
+        net.hole_error(o["err"], w["hole"][None], out=o["stat"], scratch=o["scratch"])
+        o["stat_host"].copy_(o["stat"], non_blocking=True)
+        self.outs[s] = o
+        r.phase = 1
+        ev = torch.cuda.Event(enable_timing=True)
+        ev.record(self.streams[s])
+        self.events[s] = ev
+
+    def _finish_learned(self, s: int, r: Request) -> bool:
+        """After the first phase: decide from the predicted error; above the
+        threshold, issue the fallback (gap interpolation, Step 2 and ROI
+        re-rendering over the warped image) and return False (not done)."""
+        torch = self.torch
+        o = self.outs[s]
+        r.pred_err = float(o["stat_host"][0])
+        sc = self.scenes[r.scene]
+        if r.phase == 1 and r.pred_err > self.threshold:
+            r.fallback = True
+            ctx = self.ctxs[s]
+            w, c = o["warp"], o["cls"]
+            with torch.cuda.stream(self.streams[s]):
+                ctx.classify_holes(r.cam_dom, r.cam_aff, w["depth_range"], w["rgb"], w["z"], w["alpha"], w["hole"],
+                                   self.roi, self.raster, box_capacity=self.box_capacity, out=c)
+                ctx.patch_rois(sc, r.cam_aff, c["tile_mask"], w["rgb"], w["z"], w["alpha"], w["hole"], self.raster,
+                               self.roi)
+                r.phase = 2
+                ev = torch.cuda.Event(enable_timing=True)
+                ev.record(self.streams[s])
+                self.events[s] = ev
+            return False
+        if r.fallback is None:
+            r.fallback = False
+        if self.keep:
+            with torch.cuda.stream(self.streams[s]):
+                r.out = {"rgb_dom": o["dom"]["rgb"].clone(),
+                         "rgb_aff": (o["warp"]["rgb"] if r.fallback else o["net"][0]).clone()}
+        return True
+
     def _stereo_fits(self, o, r: Request) -> bool:
         """Whether a slot's stereo outputs have exactly this request's sizes
         (both eyes): the library writes through them at the cameras' sizes."""
@@ -248,11 +350,13 @@ class GpuExecutor:
         except ValueError:
             return False
 
-    def poll(self, s: int) -> Optional[float]:
+    def poll(self, s: int, r: Optional[Request] = None) -> Optional[float]:
         ev = self.events[s]
         if ev is None or not ev.query():
             return None
-        return self.start_ev.elapsed_time(ev) * 1e-3
+        if self.mode == "learned" and r is not None and not self._finish_learned(s, r):
+            return None  # the fallback pass is running
+        return self.start_ev.elapsed_time(self.events[s]) * 1e-3
 
     def release(self, s: int, r: Request):
         st = self.ctxs[s].poll_status()
@@ -269,7 +373,15 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=8)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--mem-gb", type=float, default=64.0, help="memory budget of the in-flight requests")
-    ap.add_argument("--mode", choices=("stereo", "two_pass"), default="stereo")
+    ap.add_argument("--mode", choices=("stereo", "two_pass", "learned"), default="stereo",
+                    help="stereo: the method (interpolation + ROI re-rendering); two_pass: two full renders; "
+                         "learned: the repair network, with the method as fallback above --threshold")
+    ap.add_argument("--params", default="", help="learned mode: trained repair parameters (.npy)")
+    ap.add_argument("--threshold", type=float, default=0.01,
+                    help="learned mode: fall back when the network's mean predicted squared error at the holes "
+                         "exceeds this")
+    ap.add_argument("--quality", type=int, default=8,
+                    help="affiliated-eye PSNR against the full render over this many poses (after the run)")
     ap.add_argument("--key-capacity", type=int, default=0, help="keys per pass (0: sized on the first poses)")
     ap.add_argument("--seed", type=int, default=0)
     args = ap.parse_args(argv)
@@ -294,7 +406,9 @@ def main(argv=None):
         kc = int(mx * 1.25) + 4096
         del ctx, ds, out
         torch.cuda.synchronize()
-    ex = GpuExecutor({"s": scene}, args.slots, mode=args.mode, key_capacity=kc)
+    params = np.load(args.params) if args.params else None
+    ex = GpuExecutor({"s": scene}, args.slots, mode=args.mode, key_capacity=kc, repair_params=params,
+                     threshold=args.threshold)
     n_poses = len(cams)
 
     def reqs(n, rate, seed):
@@ -307,6 +421,28 @@ def main(argv=None):
     s.update({"workload": args.workload, "mode": args.mode, "rate": args.rate, "slots": args.slots,
               "width": int(cams[0].width), "height": int(cams[0].height), "surfels": int(scene.n),
               "key_capacity": kc})
+    if args.mode == "learned":
+        s["threshold"] = args.threshold
+        s["fallback_frac"] = round(float(np.mean([bool(r.fallback) for r in done])), 4)
+        s["pred_err_p50"] = float(np.percentile([r.pred_err for r in done], 50))
+    if args.quality > 0:
+        # Quality on a few poses, each request alone through the same
+        # executor (outputs kept), against the full render of its eye.
+        ex.keep = True
+        q = [Request(i, "s", cams[i % n_poses], affs[i % n_poses], 0.0) for i in range(min(args.quality, n_poses))]
+        serve(q, ex, 1, args.mem_gb * 1e9)
+        torch.cuda.synchronize()
+        ref = api.Context(sync=True)
+        ds = ex.scenes["s"]
+        ps = []
+        for r in q:
+            f = ref.render_dominant(ds, r.cam_aff)["rgb"]
+            mse = float(((r.out["rgb_aff"].clamp(0, 1).double() - f.clamp(0, 1).double()) ** 2).mean())
+            ps.append(10 * math.log10(1 / max(mse, 1e-30)))
+        s["psnr_aff_vs_full_db"] = round(float(np.mean(ps)), 3)
+        s["psnr_poses"] = len(ps)
+        if args.mode == "learned":
+            s["quality_fallback_frac"] = round(float(np.mean([bool(r.fallback) for r in q])), 4)
     print(json.dumps(s), flush=True)
     return 0
 

@@ -68,8 +68,10 @@ def test_forward_matches_oracle(B, H, W):
     assert np.abs(e_got - e_want).max() <= 1e-2 * np.abs(e_want).max()
 
 
-@pytest.mark.parametrize("B,H,W", [(2, 16, 72), (1, 8, 12)])
+@pytest.mark.parametrize("B,H,W", [(2, 16, 72), (1, 8, 12), (8, 128, 128)])
 def test_gradient_matches_oracle(B, H, W):
+    # 8 x 128 x 128 is the training batch: far more weight-gradient partial
+    # chunks per layer than the small shapes.
     p, rgb, z, hole, target = _problem(2, B, H, W)
     net = repair.Repair(params=p)
     g_rgb, g_z, g_hole, g_t = _dev(rgb, z, hole, target)

@@ -54,7 +54,7 @@ class FakeExecutor:
         self.peak_slots = max(self.peak_slots, len(self.running))
         self.peak_bytes = max(self.peak_bytes, sum(self.held.values()))
 
-    def poll(self, s):
+    def poll(self, s, r=None):
         if s not in self.running or self.clock.t < self.running[s][1]:
             return None
         return self.running[s][1]
