@@ -63,11 +63,11 @@ PEAK_VALU_TLANEOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # with its colour, depth and weight accumulation, which the blend runs for
 # every evaluated pair.
 FLOPS_PER_PAIR = 38
-# HBM bytes of one sphere800 dominant-eye blend stage (capped walk, two
-# segment rounds, chain, fix-up), FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
-# (factors from a 512 MiB copy), valid while raster.hip and bgs_api.hip hash
-# (sha1 over the two files in that order) to this value.
-BLEND_TRAFFIC = {"source_sha1": "d38cf24a846cd3817a9fda718d17bb872d6199f3", "bytes": 120.1e6}
+# HBM bytes of one dominant-eye blend stage (capped walk, two segment
+# rounds, chain, fix-up) per workload, FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
+# (factors from a 512 MiB copy), each valid while raster.hip and bgs_api.hip
+# hash (sha1 over the two files in that order) to its value.
+BLEND_TRAFFIC = {"sphere800": {"source_sha1": "d38cf24a846cd3817a9fda718d17bb872d6199f3", "bytes": 120.1e6}}
 
 
 def log(*a):
@@ -558,7 +558,7 @@ def main():
     achieved = pe_dom * FLOPS_PER_PAIR / (blend_ms * 1e-3) / 1e12
     roofline = {"kernel": "k_blend (dominant eye)", "bound": "alu", "achieved": round(achieved, 3),
                 "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                "traffic": blend_traffic() if wl.name == "sphere800" else None,
+                "traffic": blend_traffic(wl.name),
                 "flops_per_pair": FLOPS_PER_PAIR, "avg_launch_ms": round(blend_ms, 4),
                 "pairs_evaluated_per_launch": int(pe_dom), "pairs_contributing_per_launch": int(pu_dom),
                 "pair_evals_per_s": round(pe_dom / (blend_ms * 1e-3), 1),
@@ -639,6 +639,19 @@ def main():
     print(json.dumps(result), flush=True)
 
 
+def copy_calibration():
+    """Three copies of a 512 MiB fp32 tensor: reads and writes of known size,
+    to calibrate the FETCH_SIZE and WRITE_SIZE counters."""
+    import torch
+    a = torch.empty(128 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+
+
 def traffic_probe(args):
     """Kernels for HBM counter runs: three copies of a 512 MiB fp32 tensor
     (reads and writes of known size, to calibrate FETCH_SIZE/WRITE_SIZE), then
@@ -647,13 +660,7 @@ def traffic_probe(args):
     import torch
     from paper_2609_30741_amd import api, synth
 
-    a = torch.empty(128 * 1024 * 1024, dtype=torch.float32, device="cuda").fill_(1.0)
-    b = torch.empty_like(a)
-    torch.cuda.synchronize()
-    for _ in range(3):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    del a, b
+    copy_calibration()
     scene, cams, _ = synth.WORKLOADS[args.workload](args.seed)
     ds = api.DeviceScene(scene)
     ctx = api.Context(sync=True)
@@ -667,12 +674,14 @@ def traffic_probe(args):
 
 
 def traffic_probe_stereo(args):
-    """Kernels for per-kernel HBM counter runs over whole stereo frames: 16
-    frames that size the workspace (synchronous), then 32 frames issued back
-    to back, all at the library's default blend split."""
+    """Kernels for per-kernel HBM counter runs over whole stereo frames: the
+    copy calibration, 16 frames that size the workspace (synchronous), then
+    32 frames issued back to back, all at the library's default blend
+    split."""
     import torch
     from paper_2609_30741_amd import api, synth
 
+    copy_calibration()
     scene, cams, baseline = synth.WORKLOADS[args.workload](args.seed)
     affs = [synth.affiliated(c, baseline) for c in cams]
     ds = api.DeviceScene(scene)
@@ -689,19 +698,22 @@ def traffic_probe_stereo(args):
     log("stereo traffic probe done")
 
 
-def blend_traffic():
-    """HBM bytes per dominant-eye blend stage (all its launches) of the
-    sphere800 workload, from calibrated FETCH_SIZE and WRITE_SIZE counter
-    runs of `bench.py --traffic-probe`; None when the blend kernels or the
-    default blend schedule (raster.hip, bgs_api.hip) have changed since the
-    counters were taken."""
+def blend_traffic(workload):
+    """HBM bytes per dominant-eye blend stage (all its launches) of a
+    workload, from calibrated FETCH_SIZE and WRITE_SIZE counter runs of
+    `bench.py --traffic-probe-stereo`; None when there is no figure for the
+    workload or the blend kernels or the default blend schedule (raster.hip,
+    bgs_api.hip) have changed since the counters were taken."""
+    if workload not in BLEND_TRAFFIC:
+        return None
     import hashlib
     csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2609_30741_amd", "csrc")
     h = hashlib.sha1()
     for f in ("raster.hip", "bgs_api.hip"):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
-    return BLEND_TRAFFIC["bytes"] if h.hexdigest() == BLEND_TRAFFIC["source_sha1"] else None
+    t = BLEND_TRAFFIC[workload]
+    return t["bytes"] if h.hexdigest() == t["source_sha1"] else None
 
 
 def cpu_baseline(args, scene, cam_dom, cam_aff, roi_px, center_roi):
