@@ -128,6 +128,17 @@ typedef struct bgs_roi_params {
     int32_t center_roi;
     float a_min;
     int32_t edge_bounds;
+    /* 1: view-colour transfer, an option outside the paper's method (which
+     * reprojects the dominant image's colours, 0, the default).  The
+     * dominant pass of bgs_render_stereo also composites every surfel's
+     * colour seen from the affiliated eye's centre (its SH evaluated
+     * towards the surfel from there) with the dominant eye's weights, and
+     * the reprojection moves that colour instead, so warped pixels keep the
+     * affiliated view's view-dependent colour.  The dominant outputs are
+     * unchanged.  A no-op for degree-0 scenes (nothing is added then); the
+     * dominant pass then never splits long lists into continuation
+     * segments.  bgs_render_stereo only: the batched form rejects it. */
+    int32_t view_colour;
 } bgs_roi_params;
 
 /* Box kinds. */

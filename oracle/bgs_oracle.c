@@ -222,8 +222,10 @@ static void quat_frame(const double q0[4], double tu[3], double tv[3], double tw
     }
 }
 
-static int prepare(const oscene* sc, const orc_camera* cam, const orc_raster* rp, osurf** out_list,
-                   int64_t* out_n) {
+/* eye: the point the colours are seen from (NULL: the camera's own centre). */
+static int prepare_eye(const oscene* sc, const orc_camera* cam, const double* eye, const orc_raster* rp,
+                       osurf** out_list, int64_t* out_n) {
+    if (!eye) eye = cam->t;
     int64_t n = sc->n;
     osurf* L = (osurf*)malloc(sizeof(osurf) * (size_t)(n > 0 ? n : 1));
     if (!L) return -1;
@@ -255,8 +257,9 @@ static int prepare(const oscene* sc, const orc_camera* cam, const orc_raster* rp
         s->mu[0] = cam->fx * s->pc[0] / s->pc[2] + cam->cx;
         s->mu[1] = cam->fy * s->pc[1] / s->pc[2] + cam->cy;
         /* Colour: degree-(deg) real SH evaluated towards the surfel from this
-         * camera's centre, plus 0.5, clamped at 0 (the 2DGS/3DGS colour model). */
-        double dir[3] = {px - cam->t[0], py - cam->t[1], pz - cam->t[2]};
+         * camera's centre (or the given eye), plus 0.5, clamped at 0 (the
+         * 2DGS/3DGS colour model). */
+        double dir[3] = {px - eye[0], py - eye[1], pz - eye[2]};
         double Y[16];
         orc_sh_basis(sc->sh_degree, dir, 1, Y);
         for (int ch = 0; ch < 3; ++ch) {
@@ -279,6 +282,11 @@ static int prepare(const oscene* sc, const orc_camera* cam, const orc_raster* rp
     *out_list = L;
     *out_n = m;
     return 0;
+}
+
+static int prepare(const oscene* sc, const orc_camera* cam, const orc_raster* rp, osurf** out_list,
+                   int64_t* out_n) {
+    return prepare_eye(sc, cam, NULL, rp, out_list, out_n);
 }
 
 /* One (surfel, pixel) evaluation: exact ray-plane intersection (Sec. 3.3),
@@ -391,13 +399,15 @@ static void render_pixel(const osurf* L, int64_t m, const orc_camera* cam, const
 
 /* Render a list of pixels (pix = NULL: every pixel, row-major).  Outputs
  * are planar per channel over the npx pixels: rgb[3][npx], depth_raw[npx]
- * (D = sum d_i w_i), alpha[npx] (A = sum w_i), amb[npx]. */
-ORC_API int orc_render(const oscene* sc, const orc_camera* cam, const orc_raster* rp, const int32_t* pix,
-                       int64_t npx, int32_t prefilter, int32_t nthreads, double* rgb, double* depth_raw,
-                       double* alpha, uint8_t* amb) {
+ * (D = sum d_i w_i), alpha[npx] (A = sum w_i), amb[npx].  eye (NULL: the
+ * camera's centre) is the point every surfel's colour is seen from; the
+ * weights, depth and alpha are always the camera's own. */
+ORC_API int orc_render_eye(const oscene* sc, const orc_camera* cam, const double* eye, const orc_raster* rp,
+                           const int32_t* pix, int64_t npx, int32_t prefilter, int32_t nthreads, double* rgb,
+                           double* depth_raw, double* alpha, uint8_t* amb) {
     osurf* L = NULL;
     int64_t m = 0;
-    if (prepare(sc, cam, rp, &L, &m)) return -1;
+    if (prepare_eye(sc, cam, eye, rp, &L, &m)) return -1;
     int64_t total = pix ? npx : (int64_t)cam->width * cam->height;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -424,6 +434,12 @@ ORC_API int orc_render(const oscene* sc, const orc_camera* cam, const orc_raster
     }
     free(L);
     return 0;
+}
+
+ORC_API int orc_render(const oscene* sc, const orc_camera* cam, const orc_raster* rp, const int32_t* pix,
+                       int64_t npx, int32_t prefilter, int32_t nthreads, double* rgb, double* depth_raw,
+                       double* alpha, uint8_t* amb) {
+    return orc_render_eye(sc, cam, NULL, rp, pix, npx, prefilter, nthreads, rgb, depth_raw, alpha, amb);
 }
 
 /* Order in which surfels are composited: the surviving surfel indices

@@ -100,6 +100,8 @@ def lib():
         P = C.c_void_p
         _lib.orc_render.argtypes = [P, P, P, P, C.c_int64, C.c_int32, C.c_int32, P, P, P, P]
         _lib.orc_render.restype = C.c_int
+        _lib.orc_render_eye.argtypes = [P, P, P, P, P, C.c_int64, C.c_int32, C.c_int32, P, P, P, P]
+        _lib.orc_render_eye.restype = C.c_int
         _lib.orc_composite_order.argtypes = [P, P, P, P]
         _lib.orc_composite_order.restype = C.c_int64
         _lib.orc_pair.argtypes = [P, P, P, C.c_int64, C.c_double, C.c_double, P]
@@ -167,10 +169,13 @@ class _SceneRef:
             a.ctypes.data if a.size else None for a in self.arrs]
 
 
-def render(scene, cam, raster: Raster = Raster(), pixels=None, prefilter=True, nthreads=0):
+def render(scene, cam, raster: Raster = Raster(), pixels=None, prefilter=True, nthreads=0, eye=None):
     """Per-pixel exact render (fp64).  pixels: None (full image) or an
     (npx, 2) int array of (i, j).  Returns rgb (3, H, W) or (3, npx),
-    depth_raw, alpha and the per-pixel ambiguity flags."""
+    depth_raw, alpha and the per-pixel ambiguity flags.  eye (a world
+    point, default the camera's centre) is where every surfel's colour is
+    seen from: with another eye's centre, rgb composites that eye's colours
+    with this camera's weights (depth and alpha are unchanged)."""
     L = lib()
     sr = _SceneRef(scene)
     cs, rs = _cam(cam), _raster(raster)
@@ -186,8 +191,10 @@ def render(scene, cam, raster: Raster = Raster(), pixels=None, prefilter=True, n
     dr = np.zeros(npx)
     al = np.zeros(npx)
     amb = np.zeros(npx, np.uint8)
-    rc = L.orc_render(C.byref(sr.s), C.byref(cs), C.byref(rs), _ptr(pix) if pix is not None else None,
-                      npx, int(bool(prefilter)), int(nthreads), _ptr(rgb), _ptr(dr), _ptr(al), _ptr(amb))
+    eye_arr = None if eye is None else np.ascontiguousarray(np.asarray(eye, np.float64).reshape(3))
+    rc = L.orc_render_eye(C.byref(sr.s), C.byref(cs), _ptr(eye_arr) if eye_arr is not None else None, C.byref(rs),
+                          _ptr(pix) if pix is not None else None, npx, int(bool(prefilter)), int(nthreads),
+                          _ptr(rgb), _ptr(dr), _ptr(al), _ptr(amb))
     if rc != 0:
         raise RuntimeError("oracle render failed")
     return dict(rgb=rgb.reshape((3,) + shape), depth_raw=dr.reshape(shape), alpha=al.reshape(shape),
@@ -315,13 +322,20 @@ def patch(scene, cam, tile_mask, rgb, z, alpha, cls, raster: Raster = Raster(), 
     return dict(rgb=rgb, z=z, alpha=alpha, cls=cls, amb=amb)
 
 
-def render_stereo(scene, cam_dom, cam_aff, raster: Raster = Raster(), roi: Roi = Roi(), nthreads=0):
+def render_stereo(scene, cam_dom, cam_aff, raster: Raster = Raster(), roi: Roi = Roi(), nthreads=0,
+                  view_colour=False):
     """The full binocular frame (Sec. 3.1): dominant render with depth proxy
     -> reprojection -> classification and interpolation -> ROI patch.  The
     dominant render is rounded to fp32 before it is reprojected, as a
-    renderer that stores fp32 images would."""
+    renderer that stores fp32 images would.  view_colour (not part of the
+    paper's method): the colour that is reprojected composites every
+    surfel's colour seen from the affiliated eye's centre with the dominant
+    eye's weights, instead of the dominant image itself."""
     dom = render(scene, cam_dom, raster, nthreads=nthreads)
     rgb32 = dom["rgb"].astype(np.float32)
+    if view_colour:
+        dom["rgb_view"] = render(scene, cam_dom, raster, nthreads=nthreads, eye=np.asarray(cam_aff.t))["rgb"]
+        rgb32 = dom["rgb_view"].astype(np.float32)
     dr32 = dom["depth_raw"].astype(np.float32)
     a32 = dom["alpha"].astype(np.float32)
     rep = reproject(cam_dom, cam_aff, rgb32, dr32, a32, roi.a_min)

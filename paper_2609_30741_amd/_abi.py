@@ -33,7 +33,7 @@ class RasterParams(C.Structure):
 class RoiParams(C.Structure):
     _fields_ = [("margin", C.c_int32), ("tile", C.c_int32), ("edge_samples", C.c_int32),
                 ("gap_passes", C.c_int32), ("center_roi", C.c_int32), ("a_min", C.c_float),
-                ("edge_bounds", C.c_int32)]
+                ("edge_bounds", C.c_int32), ("view_colour", C.c_int32)]
 
 
 class Box(C.Structure):

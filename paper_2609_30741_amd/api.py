@@ -52,6 +52,7 @@ class Roi:
     center_roi: bool = True
     a_min: float = 0.5
     edge_bounds: int = 0  # 0: Eq. 6 over all edge samples; 1: each side's own edge, worst case
+    view_colour: int = 0  # 1: reproject the colours seen from the affiliated eye (outside the paper's method)
 
     def c(self):
         r = _abi.RoiParams()
@@ -59,6 +60,7 @@ class Roi:
         r.center_roi = int(bool(self.center_roi))
         r.a_min = self.a_min
         r.edge_bounds = int(self.edge_bounds)
+        r.view_colour = int(self.view_colour)
         return r
 
 

@@ -75,6 +75,7 @@ struct Layout {
     size_t status;
     size_t zbuf, hole, hole2, bcount, rmask, bbox, pflag, pbox, wpart, gpart;
     size_t ranges, colcum, mprefix, tlist, torder, mask16;
+    size_t xrgb;  // view-colour transfer: the dominant pass's affiliated-view colours [3][H][W]
     size_t recs, zkeys, rects, counts, dkeys_b, dvals_a, dvals_b, offs, surf_scan;
     size_t recs2, zkeys2, rects2;  // the affiliated eye's surfels, from the dominant pass of a stereo frame
     size_t tkeys_a, tkeys_b, tvals_a, tvals_b;
@@ -113,6 +114,7 @@ Layout make_layout(int64_t n, int64_t W, int64_t H, int64_t kc) {
     L.tlist = take(4 * nt);
     L.torder = take(4 * nt);
     L.mask16 = take(nt);  // rasteriser-tile mask of an ROI mask with 8- or 32-pixel tiles
+    L.xrgb = take(12 * np);
     L.recs = take(sizeof(SurfelRec) * n);
     L.zkeys = take(4 * n);
     L.rects = take(8 * n);
@@ -234,6 +236,8 @@ int check_roi(bgs_ctx* ctx, const bgs_roi_params* r) {
     if (!(r->a_min > 0.f && r->a_min <= 1.f)) return fail(ctx, BGS_ERR_INVALID_ARG, "a_min out of (0, 1]");
     if (r->edge_bounds != 0 && r->edge_bounds != 1)
         return fail(ctx, BGS_ERR_INVALID_ARG, "edge_bounds %d is neither 0 nor 1", r->edge_bounds);
+    if (r->view_colour != 0 && r->view_colour != 1)
+        return fail(ctx, BGS_ERR_INVALID_ARG, "view_colour %d is neither 0 nor 1", r->view_colour);
     return BGS_OK;
 }
 
@@ -362,7 +366,8 @@ int raster_pass(bgs_ctx* ctx, const Layout& L, void* ws, int64_t kc, const bgs_s
                 const bgs_raster_params& rp, const uint8_t* tile_mask, float a_min, const RasterOut& out, int which,
                 const uint32_t* reuse_order = nullptr, const uint32_t** order_out = nullptr,
                 const bgs_camera* cam_next = nullptr, bool precomputed = false, SortedVals* vals_out = nullptr,
-                const uint8_t* qmask = nullptr, int qmask_w = 0, BatchBlendDesc* defer = nullptr) {
+                const uint8_t* qmask = nullptr, int qmask_w = 0, BatchBlendDesc* defer = nullptr,
+                bool xfer = false) {
     hipStream_t s = ctx->stream;
     const int n = (int)scene.n;
     const PreCam pc = make_precam(cam);
@@ -448,7 +453,9 @@ int raster_pass(bgs_ctx* ctx, const Layout& L, void* ws, int64_t kc, const bgs_s
     mark(ctx, sb + 2, 1);
     // Stable sort by tile: within a tile the emission (= compositing) order stays.
     mark(ctx, sb + 3, 0);
-    // An ROI pass bins a small part of the tiles: a small sort is expected.
+    // An ROI pass bins a small part of the tiles: a small sort is expected
+    // (1024-key sub-chunks; at 2.8M keys with values they still beat the
+    // 6144-key sub-chunks: 74 against 87 us).
     HIP_CHECK(radix_sort(tka, vbits ? nullptr : tva, tkb, vbits ? nullptr : tvb, &st->n_sort, kc, tbits, false,
                          at<void>(ws, L.radix), s, &in_b, tile_mask ? 1 : 0, vbits),
               "tile sort");
@@ -479,7 +486,13 @@ int raster_pass(bgs_ctx* ctx, const Layout& L, void* ws, int64_t kc, const bgs_s
     ba.vmask = vmask;
     ba.qmask = qmask;
     ba.qmask_w = qmask_w;
-    const uint32_t cap = n_tiles > kSplitMaxTiles ? 0u : which ? ctx->cap_roi : ctx->cap_dom;
+    if (xfer) {
+        // The affiliated eye's records hold every binned surfel's colour seen
+        // from that eye (written by the two-eye preprocess of this pass).
+        ba.xrecs = at<SurfelRec>(ws, L.recs2);
+        ba.xrgb = at<float>(ws, L.xrgb);
+    }
+    const uint32_t cap = n_tiles > kSplitMaxTiles || xfer ? 0u : which ? ctx->cap_roi : ctx->cap_dom;
     const ContArgs ca{cap, ctx->seg_len, L.cslots, which ? ctx->far_roi : ctx->far_dom, &st->n_slots,
                       &st->n_items,
                       at<uint4>(ws, L.cdesc), at<uint32_t>(ws, L.citem), at<float4>(ws, L.cst1),
@@ -853,11 +866,16 @@ int32_t bgs_render_stereo(bgs_ctx* ctx, const bgs_scene* scene, const bgs_camera
     hipStream_t s = ctx->stream;
     DevStatus* st = at<DevStatus>(ws, L.status);
     HIP_CHECK(reset_status(ctx, ws, st), "status reset");
-    // Stage 1: dominant eye with the depth proxy.
+    // Stage 1: dominant eye with the depth proxy (and, with the view-colour
+    // transfer on a scene whose colours depend on the view, the affiliated
+    // view's colours under the same weights).
     const uint32_t* dom_order = nullptr;
+    const bool xfer = roi->view_colour != 0 && scene->sh_degree > 0;
     rc = raster_pass(ctx, L, ws, kc, *scene, *cam_dom, *raster, nullptr, 0.f,
-                     RasterOut{rgb_dom, depth_raw_dom, alpha_dom, nullptr}, 0, nullptr, &dom_order, cam_aff);
+                     RasterOut{rgb_dom, depth_raw_dom, alpha_dom, nullptr}, 0, nullptr, &dom_order, cam_aff, false,
+                     nullptr, nullptr, 0, nullptr, xfer);
     if (rc) return rc;
+    const float* rgb_src = xfer ? at<float>(ws, L.xrgb) : rgb_dom;
     // The affiliated eye's compositing order equals the dominant one when
     // their fp32 centre-depth key coefficients and near planes coincide bit
     // for bit (same orientation, offset perpendicular to the optical axis):
@@ -871,7 +889,7 @@ int32_t bgs_render_stereo(bgs_ctx* ctx, const bgs_scene* scene, const bgs_camera
     // reprojection needs no reset, and classification reads the depth range
     // straight from it.
     mark(ctx, BGS_STAGE_REPROJECT, 0);
-    HIP_CHECK(launch_reproject(wd, wa, P, roi->a_min, rgb_dom, depth_raw_dom, alpha_dom,
+    HIP_CHECK(launch_reproject(wd, wa, P, roi->a_min, rgb_src, depth_raw_dom, alpha_dom,
                                at<unsigned long long>(ws, L.zbuf), rgb_aff, z_aff, alpha_aff, cls_aff, nullptr, false,
                                at<uint4>(ws, L.wpart), st, s),
               "reproject");
@@ -937,6 +955,8 @@ int batch_issue(bgs_ctx* ctx, int32_t n, const bgs_batch_pair* pairs, const bgs_
         if ((rc = check_scene(ctx, q.scene)) || (rc = check_camera(ctx, &q.cam_dom, "dominant camera")) ||
             (rc = check_camera(ctx, &q.cam_aff, "affiliated camera")) || (rc = check_roi(ctx, &q.roi)))
             return rc;
+        if (q.roi.view_colour)
+            return fail(ctx, BGS_ERR_UNSUPPORTED, "pair %d: the view-colour transfer is not supported in batches", i);
         if (!q.ws || !q.rgb_dom || !q.depth_raw_dom || !q.alpha_dom || !q.rgb_aff || !q.z_aff || !q.alpha_aff ||
             !q.cls_aff || !q.labels || !q.n_boxes || !q.tile_mask || q.box_capacity < 0 ||
             (q.box_capacity > 0 && !q.boxes))

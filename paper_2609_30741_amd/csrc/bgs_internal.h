@@ -79,6 +79,13 @@ struct BlendArgs {
     // composited nor written.  Null otherwise.
     const uint8_t* qmask;
     int qmask_w;
+    // View-colour transfer (dominant eye of a stereo frame only; an option
+    // outside the paper's method): xrecs are the records of the affiliated
+    // eye, whose last float4 holds each surfel's colour seen from that eye;
+    // the blend composites them with the dominant eye's weights into
+    // xrgb[3][H][W] (plus T bg).  Null otherwise.
+    const SurfelRec* xrecs;
+    float* xrgb;
 };
 
 // Continuation of long tile lists in the blend (k_blend, k_blend_seg,

@@ -434,9 +434,12 @@ __global__ __launch_bounds__(256) void k_preprocess(SceneArgs sc, PreCam cam, Pr
     const bool col1 = cnt > 0, col2 = kTwo && v2.drawn;
     if (!col1 && !col2) return;
     // ---- colour: SH towards the surfel from each camera's centre ----
+    // (With two eyes, the second eye's colour is also kept for every surfel
+    // the first eye bins, drawn in the second eye or not: the view-colour
+    // transfer composites it with the first eye's weights.)
     float d1[3] = {0.f, 0.f, 1.f}, d2[3] = {0.f, 0.f, 1.f};
     if (col1) sh_dir(cam, px, py, pz, d1);
-    if (col2) sh_dir(cam2, px, py, pz, d2);
+    if (kTwo && (col1 || col2)) sh_dir(cam2, px, py, pz, d2);
     float Y1[16], Y2[16];
     sh_basis(sc.sh_degree, d1[0], d1[1], d1[2], Y1);
     if (kTwo) sh_basis(sc.sh_degree, d2[0], d2[1], d2[2], Y2);
@@ -461,6 +464,10 @@ __global__ __launch_bounds__(256) void k_preprocess(SceneArgs sc, PreCam cam, Pr
         v2.rec.d.y = fmaxf(acc2[1] + 0.5f, 0.f);
         v2.rec.d.z = fmaxf(acc2[2] + 0.5f, 0.f);
         recs2[k] = v2.rec;
+    } else if (kTwo && col1) {
+        // Not drawn in the second eye: only the colour part, for the transfer.
+        recs2[k].d = make_float4(fmaxf(acc2[0] + 0.5f, 0.f), fmaxf(acc2[1] + 0.5f, 0.f), fmaxf(acc2[2] + 0.5f, 0.f),
+                                 0.f);
     }
 }
 
@@ -864,6 +871,7 @@ constexpr uint32_t kChainBatch = 8;     // earlier segments' parts loaded togeth
 // weights alpha * T, and each step lowers T by exactly its weight).
 struct PixelState {
     float T, c0, c1, c2, D, A;
+    float x0, x1, x2;  // view-colour transfer only: the affiliated eye's colours, same weights
 };
 
 __device__ __forceinline__ bool live(const PixelState& p) { return p.T > 0.f; }
@@ -905,8 +913,9 @@ __device__ __forceinline__ void pair_alpha(const float4& r0, const float4& r1, c
 // the pixel stops before the surfel that would take T below t_min;
 // otherwise RGB, the depth proxy D and A accumulate with the same weight
 // w = alpha * T, and T drops by w.
-__device__ __forceinline__ void accumulate(float al, float dsel, const float4& r3, const BlendArgs& a, PixelState& p,
-                                           WalkCounts& wc, bool count, bool valid) {
+template <bool kXfer>
+__device__ __forceinline__ void accumulate(float al, float dsel, const float4& r3, const float4& xc, const BlendArgs& a,
+                                           PixelState& p, WalkCounts& wc, bool count, bool valid) {
     float wt = (al >= a.alpha_min ? al : 0.f) * p.T;
     const float Tn = p.T - wt;
     const bool stop = Tn < a.t_min;  // also for a pixel already stopped (T = 0)
@@ -921,13 +930,19 @@ __device__ __forceinline__ void accumulate(float al, float dsel, const float4& r
     p.D = fmaf(wt, dsel, p.D);
     p.A += wt;
     p.T = stop ? 0.f : Tn;
+    if (kXfer) {
+        p.x0 = fmaf(wt, xc.x, p.x0);
+        p.x1 = fmaf(wt, xc.y, p.x1);
+        p.x2 = fmaf(wt, xc.z, p.x2);
+    }
 }
 
 // Region test, compaction and compositing of one staged batch of nb records
 // by one wave (no block barriers).
-template <bool kCount>
+template <bool kCount, bool kXfer = false>
 __device__ __forceinline__ void walk_batch(const float4* s_rec, uint32_t nb, uint16_t* s_list, const TileGeom& g,
-                                           const BlendArgs& a, PixelState& p, WalkCounts& wc) {
+                                           const BlendArgs& a, PixelState& p, WalkCounts& wc,
+                                           const float4* s_xc = nullptr) {
     const char* s_bytes = reinterpret_cast<const char*>(s_rec);
     uint32_t nhit = 0;
 #pragma unroll
@@ -981,7 +996,8 @@ __device__ __forceinline__ void walk_batch(const float4* s_rec, uint32_t nb, uin
 #pragma unroll
         for (int i = 0; i < kTrip; ++i) {
             const float4* r = reinterpret_cast<const float4*>(s_bytes + off[i]);
-            accumulate(al[i], ds[i], r[3], a, p, wc, kCount, k + i < nhit);
+            const float4 xc = kXfer ? s_xc[off[i] >> 6] : make_float4(0.f, 0.f, 0.f, 0.f);
+            accumulate<kXfer>(al[i], ds[i], r[3], xc, a, p, wc, kCount, k + i < nhit);
         }
     }
 }
@@ -994,6 +1010,21 @@ __device__ __forceinline__ void load_rec(const SurfelRec* __restrict__ recs, con
     q1 = r->b;
     q2 = r->c;
     q3 = r->d;
+}
+
+// The same, and with the transfer the surfel's colour seen from the other
+// eye (the last float4 of its record there).
+template <bool kXfer>
+__device__ __forceinline__ void load_rec(const SurfelRec* __restrict__ recs, const uint32_t* __restrict__ vals,
+                                         uint32_t pos, const BlendArgs& a, float4& q0, float4& q1, float4& q2,
+                                         float4& q3, float4& qx) {
+    const uint32_t k = vals[pos] & a.vmask;
+    const SurfelRec* r = recs + k;
+    q0 = r->a;
+    q1 = r->b;
+    q2 = r->c;
+    q3 = r->d;
+    if (kXfer) qx = a.xrecs[k].d;
 }
 
 __device__ __forceinline__ void stage_rec(float4* s_rec, int t, const float4& q0, const float4& q1, const float4& q2,
@@ -1039,7 +1070,7 @@ __device__ __forceinline__ TileGeom tile_geom(uint32_t tile, int tid, const Blen
     return g;
 }
 
-template <bool kPatch>
+template <bool kPatch, bool kXfer = false>
 __device__ __forceinline__ void write_pixel(const PixelState& p, int px, int py, const BlendArgs& a,
                                             float* __restrict__ rgb, float* __restrict__ dz, float* __restrict__ alpha,
                                             uint8_t* __restrict__ cls) {
@@ -1049,6 +1080,11 @@ __device__ __forceinline__ void write_pixel(const PixelState& p, int px, int py,
     rgb[q] = fmaf(tb, a.bg0, p.c0);
     rgb[hw + q] = fmaf(tb, a.bg1, p.c1);
     rgb[2 * hw + q] = fmaf(tb, a.bg2, p.c2);
+    if (kXfer) {
+        a.xrgb[q] = fmaf(tb, a.bg0, p.x0);
+        a.xrgb[hw + q] = fmaf(tb, a.bg1, p.x1);
+        a.xrgb[2 * hw + q] = fmaf(tb, a.bg2, p.x2);
+    }
     alpha[q] = p.A;
     if (!kPatch) {
         dz[q] = p.D;
@@ -1082,7 +1118,7 @@ __device__ __forceinline__ void count_flush(const WalkCounts& wc, int lane, int 
 // One block per tile (compact id blk, taken in the order given, heaviest
 // lists first): composite the whole list, then write the pixels.  kPatch:
 // ROI patch of the affiliated eye (writes the depth proxy and the class).
-template <bool kCount, bool kPatch>
+template <bool kCount, bool kPatch, bool kXfer = false>
 __global__ __launch_bounds__(256) void k_blend(const SurfelRec* __restrict__ recs, const uint32_t* __restrict__ vals,
                                                const uint2* __restrict__ ranges, const uint32_t* __restrict__ tile_list,
                                                const uint32_t* __restrict__ order,
@@ -1092,6 +1128,7 @@ __global__ __launch_bounds__(256) void k_blend(const SurfelRec* __restrict__ rec
                                                unsigned long long* __restrict__ pair_counts,
                                                long long* __restrict__ trace) {
     __shared__ float4 s_rec[(kBatch + 1) * 4];
+    __shared__ float4 s_xc[kXfer ? kBatch + 1 : 1];  // transfer colours, one per staged record
     __shared__ __align__(8) uint16_t s_list[4 * kListLen];
     __shared__ uint32_t s_walk[4];
     __shared__ uint32_t s_slot, s_ibase, s_nseg;
@@ -1108,8 +1145,11 @@ __global__ __launch_bounds__(256) void k_blend(const SurfelRec* __restrict__ rec
     PixelState p{inside ? 1.f : 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     WalkCounts wc{0, 0, 0, 0};
     if (g.tid < 4) s_rec[4 * kDummy + g.tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (kXfer && g.tid == 0) s_xc[kDummy] = make_float4(0.f, 0.f, 0.f, 0.f);
     uint16_t* my_list = s_list + (g.tid >> 6) * kListLen;
-    const uint32_t cap_end = (ca.cap && ca.max_slots && rg.y - rg.x > ca.cap) ? rg.x + ca.cap : rg.y;
+    // The transfer keeps three more sums per pixel, which the continuation
+    // does not carry: such a walk never hands over.
+    const uint32_t cap_end = (!kXfer && ca.cap && ca.max_slots && rg.y - rg.x > ca.cap) ? rg.x + ca.cap : rg.y;
     // A capped walk also breaks its batches at its midpoint, where the
     // transmittance is sampled for the hand-over decision.
     const uint32_t mid = cap_end < rg.y ? rg.x + (cap_end - rg.x) / 2 : rg.y;
@@ -1119,16 +1159,19 @@ __global__ __launch_bounds__(256) void k_blend(const SurfelRec* __restrict__ rec
     // One batch loop over the whole list; batches stop at the cap, where the
     // tile decides once whether to hand the rest over (then it leaves the
     // loop) or to walk on.
-    float4 q0, q1, q2, q3;
-    if (rg.x + g.tid < rg.y) load_rec(recs, vals, rg.x + g.tid, a.vmask, q0, q1, q2, q3);
+    float4 q0, q1, q2, q3, qx;
+    if (rg.x + g.tid < rg.y) load_rec<kXfer>(recs, vals, rg.x + g.tid, a, q0, q1, q2, q3, qx);
     for (uint32_t base = rg.x; base < rg.y;) {
         const uint32_t lim = base < mid ? mid : base < cap_end ? cap_end : rg.y;
         const uint32_t nb = min((uint32_t)kBatch, lim - base);
         __syncthreads();
-        if ((uint32_t)g.tid < nb) stage_rec(s_rec, g.tid, q0, q1, q2, q3);
+        if ((uint32_t)g.tid < nb) {
+            stage_rec(s_rec, g.tid, q0, q1, q2, q3);
+            if (kXfer) s_xc[g.tid] = qx;
+        }
         __syncthreads();
-        if (base + nb + g.tid < rg.y) load_rec(recs, vals, base + nb + g.tid, a.vmask, q0, q1, q2, q3);
-        walk_batch<kCount>(s_rec, nb, my_list, g, a, p, wc);
+        if (base + nb + g.tid < rg.y) load_rec<kXfer>(recs, vals, base + nb + g.tid, a, q0, q1, q2, q3, qx);
+        walk_batch<kCount, kXfer>(s_rec, nb, my_list, g, a, p, wc, s_xc);
         base += nb;
         if (!half_taken && base >= mid) {
             half_taken = true;
@@ -1197,7 +1240,7 @@ __global__ __launch_bounds__(256) void k_blend(const SurfelRec* __restrict__ rec
             t[5] = wall_clock64();
         }
     }
-    if (inside && !handed) write_pixel<kPatch>(p, px, py, a, rgb, dz, alpha, cls);
+    if (inside && !handed) write_pixel<kPatch, kXfer>(p, px, py, a, rgb, dz, alpha, cls);
 }
 
 // ---------------------------------------------------------------------------
@@ -1622,6 +1665,7 @@ hipError_t launch_blend(const SurfelRec* recs, const uint32_t* vals, const uint2
     const dim3 g(n_blocks), b(256);
     const bool cont = ca.cap != 0 && ca.max_slots != 0;
     const dim3 gc(min(ca.max_slots * kContMaxSeg, 4096u)), gs(ca.max_slots);
+    if (a.patch && a.xrecs) return hipErrorInvalidValue;  // the transfer belongs to the dominant eye
     if (a.patch) {
         if (pair_counts) {
             hipLaunchKernelGGL((k_blend<true, true>), g, b, 0, s, recs, vals, ranges, tile_list, order, n_live, a, ca,
@@ -1647,7 +1691,10 @@ hipError_t launch_blend(const SurfelRec* recs, const uint32_t* vals, const uint2
             }
         }
     } else {
-        if (pair_counts) {
+        if (pair_counts && a.xrecs) {
+            hipLaunchKernelGGL((k_blend<true, false, true>), g, b, 0, s, recs, vals, ranges, tile_list, order, n_live,
+                               a, ca, rgb, d_or_z, alpha, cls, pair_counts, trace);
+        } else if (pair_counts) {
             hipLaunchKernelGGL((k_blend<true, false>), g, b, 0, s, recs, vals, ranges, tile_list, order, n_live, a, ca,
                                rgb, d_or_z, alpha, cls, pair_counts, trace);
             if (cont) {
@@ -1658,6 +1705,10 @@ hipError_t launch_blend(const SurfelRec* recs, const uint32_t* vals, const uint2
                 hipLaunchKernelGGL((k_blend_fix<true, false>), gc, b, 0, s, recs, vals, tile_list, a, ca, rgb, d_or_z,
                                    alpha, cls, pair_counts);
             }
+        } else if (a.xrecs) {
+            // View-colour transfer: never continued.
+            hipLaunchKernelGGL((k_blend<false, false, true>), g, b, 0, s, recs, vals, ranges, tile_list, order, n_live,
+                               a, ca, rgb, d_or_z, alpha, cls, pair_counts, (long long*)nullptr);
         } else {
             hipLaunchKernelGGL((k_blend<false, false>), g, b, 0, s, recs, vals, ranges, tile_list, order, n_live, a,
                                ca, rgb, d_or_z, alpha, cls, pair_counts, (long long*)nullptr);

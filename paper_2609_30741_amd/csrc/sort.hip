@@ -239,7 +239,7 @@ hipError_t exclusive_scan(const uint32_t* in, const uint32_t* idx, uint32_t* out
 //      ballots and a per-wave LDS count per digit, the sub-chunk is
 //      reordered by digit in LDS, and each digit's run (24 keys on average
 //      at 8 bits) is written out contiguously.  Large sorts rank digits of
-//      at most 6 bits with per-thread counters instead (k_rs_scatter_cnt).
+//      at most 7 bits with per-thread counters instead (k_rs_scatter_cnt).
 // Blocks never wait on each other.
 // ---------------------------------------------------------------------------
 namespace {
@@ -430,7 +430,7 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const uint32_t* __restrict__
     }
 }
 
-// k_rs_scatter for digits of at most 6 bits and 6144-key sub-chunks, with
+// k_rs_scatter for digits of at most 7 bits and 6144-key sub-chunks, with
 // the ranks taken from per-thread digit counters instead of ballots: thread
 // t holds the sub-chunk's keys [24 t, 24 t + 24) (blocked, so input order is
 // (thread, item) order), counts its digits in a 16-bit LDS counter per
@@ -441,17 +441,20 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const uint32_t* __restrict__
 // 32 so the raking threads hit distinct banks; the same LDS holds the
 // reordered keys and values once the ranks are known.  (At 24 keys per
 // thread a counter reaches 24 and a rank 6143: 16 bits hold both.)
-constexpr int kRsCntBits = 6;
-constexpr int kRsCntBins = 1 << kRsCntBits;
-constexpr int kRsCntWords = kRsCntBins * 256 / 2;                 // two 16-bit counters a word
-constexpr int kRsCntLds = kRsCntWords + kRsCntWords / 32;         // with the padding
-constexpr int kRsCntBuf = kRsCntLds > 2 * 256 * kRsItemsBig ? kRsCntLds : 2 * 256 * kRsItemsBig;
+// Digits of 7 bits need 64 KiB of counters, which gfx950's 160 KiB of LDS
+// per workgroup holds for two workgroups per CU: a 13-bit tile id then
+// takes two counter-ranked passes (7 + 6 bits) instead of a ballot-ranked
+// 7-bit pass and a counter-ranked one.  Digits of at most 6 bits keep the
+// 32 KiB form (four workgroups per CU without values).
+constexpr int kRsCntMaxBits = 7;
+__host__ __device__ constexpr int rs_cnt_words(int bits) { return (1 << bits) * 256 / 2; }  // two 16-bit counters a word
+__host__ __device__ constexpr int rs_cnt_lds(int bits) { return rs_cnt_words(bits) + rs_cnt_words(bits) / 32; }  // padded
 static_assert(kRsItemsBig % 4 == 0, "a thread's keys are loaded as 16-byte vectors");
 
 __device__ __forceinline__ uint32_t cnt_slot(uint32_t w) { return w + (w >> 5); }
 
-template <bool kHasV>
-__global__ __launch_bounds__(256, kHasV ? 2 : 4) void k_rs_scatter_cnt(const uint32_t* __restrict__ kin,
+template <bool kHasV, int kBits>
+__global__ __launch_bounds__(256, (kHasV || kBits > 6) ? 2 : 4) void k_rs_scatter_cnt(const uint32_t* __restrict__ kin,
                                                         const uint32_t* __restrict__ vin,
                                                         uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                         const uint32_t* __restrict__ n_dev, uint32_t n_host,
@@ -459,13 +462,17 @@ __global__ __launch_bounds__(256, kHasV ? 2 : 4) void k_rs_scatter_cnt(const uin
                                                         const uint32_t* __restrict__ totals) {
     constexpr int kItems = kRsItemsBig;
     constexpr int kSub = 256 * kItems;
+    constexpr int kBins = 1 << kBits;
     // The counters, then the sub-chunk's keys (and values): keys alone need
-    // no more LDS than the counters, so four blocks share a CU instead of three.
-    constexpr int kBuf = kHasV ? kRsCntBuf : (kRsCntLds > kSub ? kRsCntLds : kSub);
+    // no more LDS than the 6-bit counters, so four blocks share a CU instead
+    // of three.
+    constexpr int kLds = rs_cnt_lds(kBits);
+    constexpr int kData = (kHasV ? 2 : 1) * kSub;
+    constexpr int kBuf = kLds > kData ? kLds : kData;
     __shared__ uint32_t s_buf[kBuf];
-    __shared__ uint32_t dstart[kRsCntBins + 1];
-    __shared__ uint32_t gbase[kRsCntBins];
-    __shared__ uint32_t run[kRsCntBins];
+    __shared__ uint32_t dstart[kBins + 1];
+    __shared__ uint32_t gbase[kBins];
+    __shared__ uint32_t run[kBins];
     __shared__ uint32_t lds[4];
     uint32_t* s_keys = s_buf;
     uint32_t* s_vals = s_buf + (kHasV ? kSub : 0);  // not touched without values
@@ -536,7 +543,7 @@ __global__ __launch_bounds__(256, kHasV ? 2 : 4) void k_rs_scatter_cnt(const uin
         // words are read again for the second sweep rather than held.
         uint32_t sum = 0;
 #pragma unroll
-        for (int j = 0; j < kRsCntBins / 2; ++j) {
+        for (int j = 0; j < kBins / 2; ++j) {
             if ((uint32_t)j < rake) {
                 const uint32_t w = s_buf[cnt_slot(t * rake + j)];
                 sum += (w & 0xFFFFu) + (w >> 16);
@@ -544,7 +551,7 @@ __global__ __launch_bounds__(256, kHasV ? 2 : 4) void k_rs_scatter_cnt(const uin
         }
         uint32_t acc = block_excl_scan(sum, lds, nullptr);
 #pragma unroll
-        for (int j = 0; j < kRsCntBins / 2; ++j) {
+        for (int j = 0; j < kBins / 2; ++j) {
             if ((uint32_t)j < rake) {
                 const uint32_t w = s_buf[cnt_slot(t * rake + j)];
                 const uint32_t e0 = acc;
@@ -638,11 +645,17 @@ hipError_t radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, co
         if (small)
             hipLaunchKernelGGL(k_rs_scatter<kRsItemsSmall>, dim3(grid), dim3(256), 0, s, ki, vi, ko, vo, n_dev,
                                (uint32_t)n_cap, shift, bits, counts, totals);
-        else if (bits <= kRsCntBits && aligned && vo)
-            hipLaunchKernelGGL(k_rs_scatter_cnt<true>, dim3(grid), dim3(256), 0, s, ki, vi, ko, vo, n_dev,
+        else if (bits <= 6 && aligned && vo)
+            hipLaunchKernelGGL((k_rs_scatter_cnt<true, 6>), dim3(grid), dim3(256), 0, s, ki, vi, ko, vo, n_dev,
                                (uint32_t)n_cap, shift, bits, counts, totals);
-        else if (bits <= kRsCntBits && aligned)
-            hipLaunchKernelGGL(k_rs_scatter_cnt<false>, dim3(grid), dim3(256), 0, s, ki, vi, ko, vo, n_dev,
+        else if (bits <= 6 && aligned)
+            hipLaunchKernelGGL((k_rs_scatter_cnt<false, 6>), dim3(grid), dim3(256), 0, s, ki, vi, ko, vo, n_dev,
+                               (uint32_t)n_cap, shift, bits, counts, totals);
+        else if (bits <= kRsCntMaxBits && aligned && vo)
+            hipLaunchKernelGGL((k_rs_scatter_cnt<true, 7>), dim3(grid), dim3(256), 0, s, ki, vi, ko, vo, n_dev,
+                               (uint32_t)n_cap, shift, bits, counts, totals);
+        else if (bits <= kRsCntMaxBits && aligned)
+            hipLaunchKernelGGL((k_rs_scatter_cnt<false, 7>), dim3(grid), dim3(256), 0, s, ki, vi, ko, vo, n_dev,
                                (uint32_t)n_cap, shift, bits, counts, totals);
         else
             hipLaunchKernelGGL(k_rs_scatter<kRsItemsBig>, dim3(grid), dim3(256), 0, s, ki, vi, ko, vo, n_dev,

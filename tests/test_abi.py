@@ -42,13 +42,13 @@ def test_struct_sizes():
     assert C.sizeof(_abi.Camera) == 152
     assert C.sizeof(_abi.Scene) == 56
     assert C.sizeof(_abi.RasterParams) == 32
-    assert C.sizeof(_abi.RoiParams) == 28
+    assert C.sizeof(_abi.RoiParams) == 32
     assert C.sizeof(_abi.Box) == 24
     assert C.sizeof(_abi.Stats) == 144
-    # bgs_batch_pair: 448 bytes, box_capacity at 340 and tile_mask at 440
+    # bgs_batch_pair: 456 bytes, box_capacity at 344 and tile_mask at 448
     # (include/bgs.h compiled by the host compiler agrees).
-    assert C.sizeof(_abi.BatchPair) == 448
-    assert _abi.BatchPair.box_capacity.offset == 340 and _abi.BatchPair.tile_mask.offset == 440
+    assert C.sizeof(_abi.BatchPair) == 456
+    assert _abi.BatchPair.box_capacity.offset == 344 and _abi.BatchPair.tile_mask.offset == 448
 
 
 @pytest.fixture
@@ -129,6 +129,10 @@ def test_stage_validation(L, ctx):
                          FAKE, FAKE, FAKE)
     assert rc == _abi.ERR_INVALID_ARG
     roi = api.Roi(edge_bounds=2).c()
+    rc = L.bgs_reproject(ctx, C.byref(cam), C.byref(cam), C.byref(roi), FAKE, FAKE, FAKE, FAKE, 1 << 30, FAKE, FAKE,
+                         FAKE, FAKE, FAKE)
+    assert rc == _abi.ERR_INVALID_ARG
+    roi = api.Roi(view_colour=2).c()
     rc = L.bgs_reproject(ctx, C.byref(cam), C.byref(cam), C.byref(roi), FAKE, FAKE, FAKE, FAKE, 1 << 30, FAKE, FAKE,
                          FAKE, FAKE, FAKE)
     assert rc == _abi.ERR_INVALID_ARG

@@ -109,6 +109,10 @@ def test_batch_validation():
     with pytest.raises(api.BgsError, match="ROI tile"):
         b.render()
     b.arr[1].roi.tile = 16
+    b.arr[1].roi.view_colour = 1
+    with pytest.raises(api.BgsError, match="view-colour"):
+        b.render()
+    b.arr[1].roi.view_colour = 0
     b.arr[0].ws_bytes = 100
     with pytest.raises(api.BgsError, match="too small"):
         b.render()

@@ -82,9 +82,10 @@ def check_image(gpu_rgb, gpu_d, gpu_a, ref, where=""):
 @pytest.mark.parametrize("n,bits", [(0, 8), (1, 8), (4095, 8), (4096, 13), (4097, 13), (100_003, 11),
                                     (1_000_001, 32), (250_000, 1), (70_000, 20),
                                     # above 2^20 elements: 6144-key sub-chunks; digits of at most
-                                    # 6 bits are ranked by per-thread counters, 8-bit digits by ballots
+                                    # 7 bits are ranked by per-thread counters, 8-bit digits by ballots
                                     (1_500_007, 11), (1_048_577, 5), (2_000_003, 12), (1_100_000, 6),
-                                    (1_200_001, 16), (1_300_000, 32)])
+                                    (1_200_001, 16), (1_300_000, 32), (1_050_001, 7), (1_400_003, 13),
+                                    (1_600_001, 14), (1_700_000, 20)])
 def test_sort_pairs_bit_exact(ctx, n, bits):
     log(f"sort n={n} bits={bits}")
     keys, vals = synth.random_sort_keys(n, seed=n + bits, key_bits=32)
@@ -158,15 +159,23 @@ def large_surfel_workload(n=1500, W=320, H=320, f=300.0, seed=5):
     return sc, cam
 
 
-@pytest.mark.parametrize("case,capacity", [("cube", None), ("cube", 3_000_000), ("large_surfels", 400_000)])
+@pytest.mark.parametrize("case,capacity", [("cube", None), ("cube", 3_000_000), ("large_surfels", 400_000),
+                                           ("wide", 3_000_000)])
 def test_tile_lists_are_sorted_and_complete(ctx, oracle, case, capacity):
     """Every tile's list is its rect-binned surfels in compositing order,
     less the ones whose strip band misses the tile; the dropped ones give
     alpha < alpha_min at every pixel of the tile (checked with the oracle's
     pair evaluation on a sample).  A key capacity above 2^20 takes the
     large-sort kernels (a fresh context, so the workspace holds exactly it);
-    large surfels make the emission take its segments in several turns."""
-    sc, cam = cube_workload(4000, 128, 96, 140.0, seed=3) if case == "cube" else large_surfel_workload()
+    large surfels make the emission take its segments in several turns; a
+    1600x1064 image has 13 tile bits, sorted in a 7-bit and a 6-bit
+    counter-ranked pass of packed keys."""
+    if case == "cube":
+        sc, cam = cube_workload(4000, 128, 96, 140.0, seed=3)
+    elif case == "wide":
+        sc, cam = cube_workload(4000, 1600, 1064, 1300.0, seed=3)
+    else:
+        sc, cam = large_surfel_workload()
     ds = api.DeviceScene(sc)
     if capacity:
         ctx = api.Context(sync=True)
@@ -451,6 +460,54 @@ def test_render_stereo_cube_end_to_end(ctx, oracle, center, edge_bounds):
     warp_px = same & (cls_g == api.CLS_WARPED)
     frac = (np.abs(rgb_g - rgb_o).max(0)[warp_px] > RGB_TOL).mean()
     assert frac < 2e-3
+
+
+def test_render_stereo_view_colour(ctx, oracle):
+    """The view-colour transfer (an option outside the paper's method) on a
+    scene with degree-3 colours: the dominant outputs are the plain ones, the
+    affiliated eye follows the oracle's transfer route (the colours seen
+    from the affiliated eye composited with the dominant weights, then
+    reprojected), and the warped pixels come closer to the full affiliated
+    render than the dominant colours do.  On a degree-0 scene the option
+    changes nothing, bit for bit."""
+    sc = synth.scene_sphere_shell(5, 20_000, sh_degree=3)
+    cam = synth.look_at((0.0, -2.2, 0.4), (0, 0, 0), (0, 0, 1), 256, 192, 300.0)
+    aff = synth.affiliated(cam, 0.064)
+    ds = api.DeviceScene(sc)
+    plain = ctx.render_stereo(ds, cam, aff, roi=api.Roi())
+    plain = {k: v.clone() for k, v in plain.items() if torch.is_tensor(v)}
+    out = ctx.render_stereo(ds, cam, aff, roi=api.Roi(view_colour=1))
+    for k in ("rgb_dom", "depth_raw_dom", "alpha_dom", "z_aff", "alpha_aff", "cls_aff", "tile_mask"):
+        assert torch.equal(out[k], plain[k]), k
+    ref = oracle.render_stereo(sc, cam, aff, view_colour=True)
+    check_image(to_np(out["rgb_dom"]), to_np(out["depth_raw_dom"]), to_np(out["alpha_dom"]), ref["dom"], "xfer dom")
+    cls_g, cls_o = to_np(out["cls_aff"]), ref["aff"]["cls"]
+    assert (cls_g != cls_o).mean() < 2e-3
+    same = cls_g == cls_o
+    rgb_g = np.clip(to_np(out["rgb_aff"]), 0, 1)
+    rgb_o = np.clip(ref["aff"]["rgb"], 0, 1)
+    warp_px = same & (cls_g == api.CLS_WARPED)
+    assert warp_px.sum() > 10_000
+    frac = (np.abs(rgb_g - rgb_o).max(0)[warp_px] > RGB_TOL).mean()
+    log(f"view colour: warped pixels beyond tolerance {frac:.5f}")
+    assert frac < 2e-3
+    # Closer to the full affiliated render on the warped pixels.
+    full = np.clip(oracle.render(sc, aff)["rgb"], 0, 1)
+    err_x = ((rgb_g - full) ** 2).mean(0)[warp_px].mean()
+    err_p = ((np.clip(to_np(plain["rgb_aff"]), 0, 1) - full) ** 2).mean(0)[warp_px].mean()
+    log(f"view colour: warped-pixel MSE {err_x:.3e} against {err_p:.3e} without")
+    assert err_x < 0.5 * err_p
+    # Degree 0: nothing to transfer.
+    sc0, cam0 = cube_workload(5_000, 128, 96, 150.0)
+    aff0 = synth.affiliated(cam0, 0.064)
+    ds0 = api.DeviceScene(sc0)
+    a = {k: v.clone() for k, v in ctx.render_stereo(ds0, cam0, aff0, roi=api.Roi()).items() if torch.is_tensor(v)}
+    b = ctx.render_stereo(ds0, cam0, aff0, roi=api.Roi(view_colour=1))
+    nb = int(a["n_boxes"].item())
+    assert torch.equal(a["boxes"][:nb], b["boxes"][:nb])  # slots past the count are unspecified
+    for k in a:
+        if k != "boxes":
+            assert torch.equal(a[k], b[k]), k
 
 
 # ---------------------------------------------------------------------------

@@ -358,3 +358,52 @@ def test_coverage_boxes_match_pixel_loop(oracle, lowpass):
                 hit[j, i] = e is not None and e["alpha"] >= 1.0 / 255.0
         ys, xs = np.nonzero(hit)
         assert list(boxes[k]) == [xs.min(), ys.min(), xs.max(), ys.max()]
+
+
+def test_render_seen_from_another_eye_closed_form(oracle):
+    # A fronto-parallel surfel with degree-2 SH coefficients, its colour seen
+    # from another eye's centre: every pixel is alpha * c(eye) (black
+    # background), c(eye) = max(0, sum_lm Y_lm(d) f_lm + 0.5) with d the unit
+    # direction from that eye to the surfel, the Y_lm in their Cartesian
+    # textbook form; alpha and depth are the camera's own.
+    cam = cam_identity()
+    Z, px, py, s, o = 3.0, 0.07, -0.05, 0.04, 0.8
+    sc = synth.explicit_scene([px, py, Z], [1, 0, 0], [0, 1, 0], s, s, o, [0.5, 0.5, 0.5])
+    rng = np.random.default_rng(7)
+    f = rng.normal(0.0, 0.3, size=(9, 3))
+    sc = synth.Scene(1, 2, sc.pos, sc.quat, sc.scale, sc.opacity, f.reshape(27, 1).astype(np.float32))
+    r = oracle.Raster(lowpass=False)
+    eye = np.array([0.6, -0.3, -0.2])
+    base = oracle.render(sc, cam, r, prefilter=False)
+    seen = oracle.render(sc, cam, r, prefilter=False, eye=eye)
+    np.testing.assert_array_equal(seen["alpha"], base["alpha"])
+    np.testing.assert_array_equal(seen["depth_raw"], base["depth_raw"])
+    d = sc.pos[:, 0].astype(np.float64) - eye
+    x, y, z = d / np.linalg.norm(d)
+    pi = math.pi
+    Y = np.array([0.5 / math.sqrt(pi), -math.sqrt(3 / (4 * pi)) * y, math.sqrt(3 / (4 * pi)) * z,
+                  -math.sqrt(3 / (4 * pi)) * x, 0.5 * math.sqrt(15 / pi) * x * y, -0.5 * math.sqrt(15 / pi) * y * z,
+                  0.25 * math.sqrt(5 / pi) * (3 * z * z - 1), -0.5 * math.sqrt(15 / pi) * x * z,
+                  0.25 * math.sqrt(15 / pi) * (x * x - y * y)])
+    c = np.maximum(Y @ sc.sh.astype(np.float64).reshape(9, 3) + 0.5, 0.0)
+    assert np.abs(c - np.maximum(Y[0] * sc.sh[:3, 0] + 0.5, 0)).max() > 0.05  # the view matters here
+    for ch in range(3):
+        np.testing.assert_allclose(seen["rgb"][ch], base["alpha"] * c[ch], rtol=0, atol=1e-12)
+
+
+def test_render_seen_from_another_eye_invariants(oracle):
+    # Degree-0 colours do not depend on the view: any eye gives the camera's
+    # own image bit for bit; the camera's own centre as the eye is the plain
+    # render for any degree.
+    cam = synth.look_at((0.3, -3.0, 0.2), (0, 0, 0), (0, 0, 1), 32, 32, 40.0)
+    sc0 = synth.scene_uniform_cube(2, 300)
+    a = oracle.render(sc0, cam)
+    b = oracle.render(sc0, cam, eye=(1.0, 2.0, -0.5))
+    for k in ("rgb", "depth_raw", "alpha", "amb"):
+        assert np.array_equal(a[k], b[k]), k
+    sc3 = synth.scene_sphere_shell(2, 400, sh_degree=3)
+    a = oracle.render(sc3, cam)
+    b = oracle.render(sc3, cam, eye=np.asarray(cam.t))
+    assert np.array_equal(a["rgb"], b["rgb"])
+    c = oracle.render(sc3, cam, eye=np.asarray(cam.t) + np.array([0.3, 0.0, 0.0]))
+    assert np.array_equal(a["alpha"], c["alpha"]) and np.abs(a["rgb"] - c["rgb"]).max() > 1e-3
