@@ -63,11 +63,14 @@ PEAK_VALU_TLANEOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # with its colour, depth and weight accumulation, which the blend runs for
 # every evaluated pair.
 FLOPS_PER_PAIR = 38
-# HBM bytes of one dominant-eye blend stage (capped walk, two segment
-# rounds, chain, fix-up) per workload, FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
-# (factors from a 512 MiB copy), each valid while raster.hip and bgs_api.hip
-# hash (sha1 over the two files in that order) to its value.
-BLEND_TRAFFIC = {"sphere800": {"source_sha1": "d38cf24a846cd3817a9fda718d17bb872d6199f3", "bytes": 120.1e6}}
+# HBM bytes of one dominant-eye blend stage (all its launches: on
+# unbounded1600 the one k_blend launch, on sphere800 the capped walk, two
+# segment rounds, chain and fix-up) per workload, mean over the workload's
+# poses, FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (factors from a 512 MiB copy),
+# each valid while raster.hip and bgs_api.hip hash (sha1 over the two files
+# in that order) to its value.
+BLEND_TRAFFIC = {"sphere800": {"source_sha1": "d38cf24a846cd3817a9fda718d17bb872d6199f3", "bytes": 120.1e6},
+                 "unbounded1600": {"source_sha1": "3a49e3dbbfa7ad733aa5cd38c98f5dd199dc021b", "bytes": 132.1e6}}
 
 
 def log(*a):
@@ -709,9 +712,10 @@ def traffic_probe(args):
 
 def traffic_probe_stereo(args):
     """Kernels for per-kernel HBM counter runs over whole stereo frames: the
-    copy calibration, 16 frames that size the workspace (synchronous), then
-    32 frames issued back to back, all at the library's default blend
-    split."""
+    copy calibration, one synchronous pass over the workload's poses (it
+    sizes the workspace), then every pose once more, issued back to back, all
+    at the library's default blend split; per-frame means over that last
+    pass cover the same poses as the bench's timed frames."""
     import torch
     from paper_2609_30741_amd import api, synth
 
@@ -722,12 +726,11 @@ def traffic_probe_stereo(args):
     ctx = api.Context(sync=True)
     roi = api.Roi(center_roi=CENTER_ROI[args.workload])
     out = None
-    for cd, ca in list(zip(cams, affs))[:16]:
+    for cd, ca in zip(cams, affs):
         out = ctx.render_stereo(ds, cd, ca, roi=roi, out=out)
     ctx.set_sync(False)
-    for _ in range(2):
-        for cd, ca in list(zip(cams, affs))[:16]:
-            ctx.render_stereo(ds, cd, ca, roi=roi, out=out)
+    for cd, ca in zip(cams, affs):
+        ctx.render_stereo(ds, cd, ca, roi=roi, out=out)
     torch.cuda.synchronize()
     log("stereo traffic probe done")
 
