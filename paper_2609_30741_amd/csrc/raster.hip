@@ -230,17 +230,51 @@ struct BandRows {
     }
 };
 
+// The rows ty0..ty1 of a surfel's rect, in order: for each row whose band
+// interval [a, b] is not empty, f(c, first) gets its key count c (masked
+// tiles of [a, b] with the mask enabled, else b - a + 1) and the key of its
+// first tile (the compact id with the mask, else the tile id); f returns
+// false to stop.  Rows go four at a time, so their mask-prefix loads are in
+// flight together: a surfel across a whole image's rows otherwise waits on
+// two dependent loads per row.
+template <typename F>
+__device__ inline void for_band_rows(const BandRows& br, const MaskArgs& m, const uint32_t* pref, int tx0, int ty0,
+                                     int tx1, int ty1, F&& f) {
+    for (int y0 = ty0; y0 <= ty1; y0 += 4) {
+        int a[4], b[4];
+        uint32_t lo[4], hi[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            a[u] = 1;
+            b[u] = 0;
+            if (y0 + u <= ty1) br.row(y0 + u, tx0, tx1, &a[u], &b[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t rb = (int64_t)(y0 + u) * m.tiles_x;
+            const bool load = m.enabled && b[u] >= a[u];
+            lo[u] = load ? pref[rb + a[u]] : 0u;
+            hi[u] = load ? pref[rb + b[u] + 1] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (b[u] < a[u]) continue;
+            const int64_t rb = (int64_t)(y0 + u) * m.tiles_x;
+            const uint32_t c = m.enabled ? hi[u] - lo[u] : (uint32_t)(b[u] - a[u] + 1);
+            const uint32_t first = m.enabled ? lo[u] : (uint32_t)(rb + a[u]);
+            if (!f(c, first)) return;
+        }
+    }
+}
+
 // Keys of a surfel: the band's tiles of its rect, only masked ones when the
 // mask is enabled.
 __device__ inline uint32_t band_count(const BandRows& br, const MaskArgs& m, int tx0, int ty0, int tx1, int ty1) {
     uint32_t cnt = 0;
-    for (int ty = ty0; ty <= ty1; ++ty) {
-        int a, b;
-        br.row(ty, tx0, tx1, &a, &b);
-        if (b < a) continue;
-        cnt += m.enabled ? m.prefix[(int64_t)ty * m.tiles_x + b + 1] - m.prefix[(int64_t)ty * m.tiles_x + a]
-                         : (uint32_t)(b - a + 1);
-    }
+    for_band_rows(br, m, m.prefix, tx0, ty0, tx1, ty1, [&](uint32_t c, uint32_t) {
+        cnt += c;
+        return true;
+    });
     return cnt;
 }
 
@@ -592,15 +626,13 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order
     const BandRows br = cnt ? BandRows(rec) : BandRows();
     // Segments of this thread's surfel.
     uint32_t ns = 0;
+    MaskArgs mk = mask;
+    mk.tiles_x = tiles_x;
     if (cnt) {
-        for (int ty = ty0; ty <= ty1; ++ty) {
-            int a, b;
-            br.row(ty, tx0, tx1, &a, &b);
-            if (b < a) continue;
-            const int64_t rb = (int64_t)ty * tiles_x;
-            const uint32_t c = mask.enabled ? pref[rb + b + 1] - pref[rb + a] : (uint32_t)(b - a + 1);
+        for_band_rows(br, mk, pref, tx0, ty0, tx1, ty1, [&](uint32_t c, uint32_t) {
             ns += c ? 1u : 0u;
-        }
+            return true;
+        });
     }
     // Exclusive scan of the segment counts over the block.
     uint32_t v = ns;
@@ -619,31 +651,62 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order
         const uint32_t w1 = min(tot_seg, w0 + (uint32_t)kEmitSegs);
         if (ns && sbase < w1 && sbase + ns > w0) {
             uint32_t si = sbase, kpos = loc;
-            for (int ty = ty0; ty <= ty1 && si < w1; ++ty) {
-                int a, b;
-                br.row(ty, tx0, tx1, &a, &b);
-                if (b < a) continue;
-                const int64_t rb = (int64_t)ty * tiles_x;
-                const uint32_t c =
-                    mask.enabled ? pref[rb + b + 1] - pref[rb + a] : (uint32_t)(b - a + 1);
-                if (!c) continue;
+            for_band_rows(br, mk, pref, tx0, ty0, tx1, ty1, [&](uint32_t c, uint32_t first) {
+                if (si >= w1) return false;
+                if (!c) return true;
                 if (si >= w0) {
                     seg_start[si - w0] = kpos;
-                    seg_tile[si - w0] = (mask.enabled ? pref[rb + a] : (uint32_t)(rb + a)) | ((uint32_t)t << 24);
+                    seg_tile[si - w0] = first | ((uint32_t)t << 24);
                     if (si + 1 == w1) seg_start[w1 - w0] = kpos + c;  // end of the turn's keys
                 }
                 kpos += c;
                 ++si;
-            }
+                return true;
+            });
         }
         __syncthreads();
         const int nw = (int)(w1 - w0);
         const uint32_t p0 = seg_start[0], p1 = seg_start[nw];
         for (uint32_t kw = p0; kw < p1; kw += kEmitWin) {
             const uint32_t ke = min(p1, kw + (uint32_t)kEmitWin);
+            // Owner of every key of the window: each segment marks where its
+            // keys start in the window (segment index + 1; the segment that
+            // covers the window's first key marks position 0), and an
+            // inclusive max-scan carries each mark over its segment's keys.
+            // A segment's keys are not filled by one thread in turn: a
+            // surfel across a whole row of tiles would serialise it.
+            static_assert(kEmitWin == 8 * 256, "eight window positions per thread");
+            const uint32_t len = ke - kw;
+            for (uint32_t i = t; i < len; i += 256) owner[i] = 0;
+            __syncthreads();
             for (int j = t; j < nw; j += 256) {
-                const uint32_t s0 = max(seg_start[j], kw), s1 = min(seg_start[j + 1], ke);
-                for (uint32_t q = s0; q < s1; ++q) owner[q - kw] = (uint16_t)j;
+                const uint32_t s0 = seg_start[j], s1 = seg_start[j + 1];
+                if (s0 < ke && s1 > kw) owner[(s0 > kw ? s0 : kw) - kw] = (uint16_t)(j + 1);
+            }
+            __syncthreads();
+            uint32_t run[8], mx = 0;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const uint32_t i = 8u * (uint32_t)t + (uint32_t)e;
+                mx = max(mx, i < len ? (uint32_t)owner[i] : 0u);
+                run[e] = mx;
+            }
+            uint32_t xm = mx;  // inclusive max over the wave's threads, then over the waves before
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t y = __shfl_up(xm, off, 64);
+                if (lane >= off) xm = max(xm, y);
+            }
+            __syncthreads();  // every mark is read before the LDS word below is reused
+            if (lane == 63) lds[w] = xm;
+            __syncthreads();
+            uint32_t before = __shfl_up(xm, 1, 64);
+            if (lane == 0) before = 0;
+            for (int q = 0; q < w; ++q) before = max(before, lds[q]);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const uint32_t i = 8u * (uint32_t)t + (uint32_t)e;
+                if (i < len) owner[i] = (uint16_t)(max(run[e], before) - 1u);
             }
             __syncthreads();
             for (uint32_t p = kw + t; p < ke; p += 256) {
