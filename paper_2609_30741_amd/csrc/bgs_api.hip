@@ -76,7 +76,7 @@ struct Layout {
     size_t zbuf, hole, hole2, bcount, rmask, bbox, pflag, pbox, wpart, gpart;
     size_t ranges, colcum, mprefix, tlist, torder, mask16;
     size_t xrgb;  // view-colour transfer: the dominant pass's affiliated-view colours [3][H][W]
-    size_t recs, zkeys, rects, counts, dkeys_b, dvals_a, dvals_b, offs, surf_scan;
+    size_t recs, zkeys, rects, counts, nseg, dkeys_b, dvals_a, dvals_b, offs, surf_scan;
     size_t recs2, zkeys2, rects2;  // the affiliated eye's surfels, from the dominant pass of a stereo frame
     size_t tkeys_a, tkeys_b, tvals_a, tvals_b;
     size_t radix;
@@ -119,6 +119,7 @@ Layout make_layout(int64_t n, int64_t W, int64_t H, int64_t kc) {
     L.zkeys = take(4 * n);
     L.rects = take(8 * n);
     L.counts = take(4 * n);
+    L.nseg = take(4 * n);
     L.dkeys_b = take(4 * n);
     L.dvals_a = take(4 * n);
     L.dvals_b = take(4 * n);
@@ -388,6 +389,8 @@ int raster_pass(bgs_ctx* ctx, const Layout& L, void* ws, int64_t kc, const bgs_s
     uint32_t* zkeys = at<uint32_t>(ws, precomputed ? L.zkeys2 : L.zkeys);
     uint2* rects = at<uint2>(ws, precomputed ? L.rects2 : L.rects);
     uint32_t* counts = at<uint32_t>(ws, L.counts);
+    uint32_t* nseg = at<uint32_t>(ws, L.nseg);  // rows with keys per surfel, from the counting kernel
+    int nseg_by_pos = 0;
     uint32_t* offs = at<uint32_t>(ws, L.offs);
     // Precomputed records: the masked key counts are taken in compositing
     // order together with the first step of their scan, once the order is
@@ -396,14 +399,14 @@ int raster_pass(bgs_ctx* ctx, const Layout& L, void* ws, int64_t kc, const bgs_s
     if (precomputed) {
         if (!tile_mask) return fail(ctx, BGS_ERR_INVALID_ARG, "precomputed records need a tile mask");
         if (!fused_counts)
-            HIP_CHECK(launch_masked_counts(rects, recs, n, n_tiles, mask, counts, s), "masked counts");
+            HIP_CHECK(launch_masked_counts(rects, recs, n, n_tiles, mask, counts, nseg, s), "masked counts");
     } else {
         const SceneArgs sa{scene.pos, scene.quat, scene.scale, scene.opacity, scene.sh, n, scene.sh_degree};
         PreCam pn{};
         if (cam_next) pn = make_precam(*cam_next);
         HIP_CHECK(launch_preprocess(sa, pc, rp.alpha_min, rp.lowpass, mask, recs, zkeys, rects, counts,
                                     cam_next ? &pn : nullptr, at<SurfelRec>(ws, L.recs2), at<uint32_t>(ws, L.zkeys2),
-                                    at<uint2>(ws, L.rects2), s),
+                                    at<uint2>(ws, L.rects2), nseg, s),
                   "preprocess");
     }
     mark(ctx, sb + 0, 1);
@@ -428,7 +431,8 @@ int raster_pass(bgs_ctx* ctx, const Layout& L, void* ws, int64_t kc, const bgs_s
     const KeyCount kcnt{st, (uint32_t)kc, which, ranges, (uint32_t)n_tiles};
     bool scanned;
     if (fused_counts) {
-        HIP_CHECK(launch_masked_counts_ordered(rects, recs, order, n, n_tiles, mask, counts, surf_scan, s),
+        nseg_by_pos = 1;
+        HIP_CHECK(launch_masked_counts_ordered(rects, recs, order, n, n_tiles, mask, counts, surf_scan, nseg, s),
                   "masked counts");
         scanned = scan_counts_presummed(counts, offs, n, surf_scan, kcnt, s, &se);  // the flat form covers n
     } else {
@@ -449,7 +453,9 @@ int raster_pass(bgs_ctx* ctx, const Layout& L, void* ws, int64_t kc, const bgs_s
     // fit in 32 bits: the sort then moves half the bytes.
     const int tbits = tile_bits(n_tiles), sbits = tile_bits(n);
     const int vbits = tbits + sbits <= 32 ? sbits : 0;
-    HIP_CHECK(launch_emit(order, offs, rects, recs, n, pc.tiles_x, n_tiles, mask, (uint32_t)kc, vbits, tka, tva, s), "emit");
+    HIP_CHECK(launch_emit(order, offs, rects, recs, n, pc.tiles_x, n_tiles, mask, (uint32_t)kc, vbits, tka, tva, nseg,
+                          nseg_by_pos, s),
+              "emit");
     mark(ctx, sb + 2, 1);
     // Stable sort by tile: within a tile the emission (= compositing) order stays.
     mark(ctx, sb + 3, 0);
@@ -1157,7 +1163,8 @@ int32_t bgs_preprocess_debug(bgs_ctx* ctx, const bgs_scene* scene, const bgs_cam
     const int n = (int)scene->n;
     const MaskArgs no_mask{nullptr, nullptr, pc.tiles_x, 0};
     HIP_CHECK(launch_preprocess(sa, pc, raster->alpha_min, raster->lowpass, no_mask, at<SurfelRec>(ws, L.recs), zkey,
-                                at<uint2>(ws, L.rects), counts, nullptr, nullptr, nullptr, nullptr, ctx->stream),
+                                at<uint2>(ws, L.rects), counts, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                ctx->stream),
               "preprocess");
     // Unpack the tile rectangles for the caller.
     if (n > 0) {

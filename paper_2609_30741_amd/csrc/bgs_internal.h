@@ -190,27 +190,33 @@ hipError_t radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, co
 
 // ---- rasteriser (raster.hip) --------------------------------------------------
 // cam2 (optional): also the keys, rects and records of a second camera (no
-// key counts: see launch_masked_counts).
+// key counts: see launch_masked_counts).  nseg (optional, per surfel): the
+// rows of the surfel's band that hold keys, which the emission lists.
 hipError_t launch_preprocess(const SceneArgs& sc, const PreCam& cam, float alpha_min, int lowpass,
                              const MaskArgs& mask, SurfelRec* recs, uint32_t* zkeys, uint2* rects,
                              uint32_t* counts, const PreCam* cam2, SurfelRec* recs2, uint32_t* zkeys2,
-                             uint2* rects2, hipStream_t s);
-// Key counts within the mask's tiles from precomputed tile rects and records.
+                             uint2* rects2, uint32_t* nseg, hipStream_t s);
+// Key counts within the mask's tiles from precomputed tile rects and records,
+// and the rows that hold them (nseg), per surfel.
 hipError_t launch_masked_counts(const uint2* rects, const SurfelRec* recs, int n, int n_tiles, const MaskArgs& mask,
-                                uint32_t* counts, hipStream_t s);
-// The same counts in compositing order (counts[i] for surfel order[i]), with
-// the total of every 256 consecutive positions in partials (ceil(n / 256)
-// of them): the scan then needs only its down-sweep (scan_counts_presummed).
+                                uint32_t* counts, uint32_t* nseg, hipStream_t s);
+// The same counts in compositing order (counts[i] and nseg[i] for surfel
+// order[i]), with the total of every 256 consecutive positions in partials
+// (ceil(n / 256) of them): the scan then needs only its down-sweep
+// (scan_counts_presummed).
 hipError_t launch_masked_counts_ordered(const uint2* rects, const SurfelRec* recs, const uint32_t* order, int n,
                                         int n_tiles, const MaskArgs& mask, uint32_t* counts, uint32_t* partials,
-                                        hipStream_t s);
+                                        uint32_t* nseg, hipStream_t s);
 // Keys of every surfel in compositing order: the tiles of its rect that its
 // strip band meets (and the mask holds, when enabled), row by row.
 // vbits > 0: one word per key, tile << vbits | surfel (tvals unused);
 // vbits = 0: the tile in tkeys and the surfel in tvals.
+// nseg (optional): each surfel's rows with keys as its counting pass left
+// them, indexed by position in the order (nseg_by_pos) or by surfel; null:
+// the emission counts them itself.
 hipError_t launch_emit(const uint32_t* order, const uint32_t* offs, const uint2* rects, const SurfelRec* recs, int n,
                        int tiles_x, int n_tiles, const MaskArgs& mask, uint32_t cap, int vbits, uint32_t* tkeys,
-                       uint32_t* tvals, hipStream_t s);
+                       uint32_t* tvals, const uint32_t* nseg, int nseg_by_pos, hipStream_t s);
 // Tile ranges of the sorted keys (tile = key >> key_shift); the ranges must
 // have been cleared (by scan_counts, or launch_clear_ranges).
 hipError_t launch_ranges(const uint32_t* tkeys, const uint32_t* n_dev, int64_t cap, uint2* ranges,

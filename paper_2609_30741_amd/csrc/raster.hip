@@ -269,12 +269,17 @@ __device__ inline void for_band_rows(const BandRows& br, const MaskArgs& m, cons
 
 // Keys of a surfel: the band's tiles of its rect, only masked ones when the
 // mask is enabled.
-__device__ inline uint32_t band_count(const BandRows& br, const MaskArgs& m, int tx0, int ty0, int tx1, int ty1) {
-    uint32_t cnt = 0;
+// segs (optional) receives the number of rows with keys: the segments the
+// emission lists for this surfel.
+__device__ inline uint32_t band_count(const BandRows& br, const MaskArgs& m, int tx0, int ty0, int tx1, int ty1,
+                                      uint32_t* segs = nullptr) {
+    uint32_t cnt = 0, ns = 0;
     for_band_rows(br, m, m.prefix, tx0, ty0, tx1, ty1, [&](uint32_t c, uint32_t) {
         cnt += c;
+        ns += c ? 1u : 0u;
         return true;
     });
+    if (segs) *segs = ns;
     return cnt;
 }
 
@@ -421,7 +426,8 @@ __global__ __launch_bounds__(256) void k_preprocess(SceneArgs sc, PreCam cam, Pr
                                                     int lowpass, MaskArgs mask, SurfelRec* __restrict__ recs,
                                                     uint32_t* __restrict__ zkeys, uint2* __restrict__ rects,
                                                     uint32_t* __restrict__ counts, SurfelRec* __restrict__ recs2,
-                                                    uint32_t* __restrict__ zkeys2, uint2* __restrict__ rects2) {
+                                                    uint32_t* __restrict__ zkeys2, uint2* __restrict__ rects2,
+                                                    uint32_t* __restrict__ nseg) {
     const int k = blockIdx.x * 256 + threadIdx.x;
     if (k >= sc.n) return;
     const int n = sc.n;
@@ -453,14 +459,15 @@ __global__ __launch_bounds__(256) void k_preprocess(SceneArgs sc, PreCam cam, Pr
         if (in1) surfel_view(cam, px, py, pz, op, tu, tv, su, sv, alpha_min, lowpass, v1);
         if (kTwo && in2) surfel_view(cam2, px, py, pz, op, tu, tv, su, sv, alpha_min, lowpass, v2);
     }
-    uint32_t cnt = 0;
+    uint32_t cnt = 0, segs = 0;
     if (v1.drawn) {
-        cnt = band_count(BandRows(v1.rec), mask, v1.tx0, v1.ty0, v1.tx1, v1.ty1);
+        cnt = band_count(BandRows(v1.rec), mask, v1.tx0, v1.ty0, v1.tx1, v1.ty1, &segs);
         rects[k] = make_uint2((uint32_t)v1.tx0 | ((uint32_t)v1.ty0 << 16), (uint32_t)v1.tx1 | ((uint32_t)v1.ty1 << 16));
     } else {
         rects[k] = empty;
     }
     counts[k] = cnt;
+    if (nseg) nseg[k] = segs;
     if (kTwo)
         rects2[k] = v2.drawn ? make_uint2((uint32_t)v2.tx0 | ((uint32_t)v2.ty0 << 16),
                                           (uint32_t)v2.tx1 | ((uint32_t)v2.ty1 << 16))
@@ -511,7 +518,8 @@ __global__ __launch_bounds__(256) void k_preprocess(SceneArgs sc, PreCam cam, Pr
 // when it fits: the band rows read it twice a row.
 __global__ __launch_bounds__(256) void k_masked_counts(const uint2* __restrict__ rects,
                                                        const SurfelRec* __restrict__ recs, int n, MaskArgs mask,
-                                                       int mask_lds, uint32_t* __restrict__ counts) {
+                                                       int mask_lds, uint32_t* __restrict__ counts,
+                                                       uint32_t* __restrict__ nseg) {
     extern __shared__ uint32_t s_mpre[];
     if (mask_lds > 0) {  // uniform over the grid
         for (int i = threadIdx.x; i < mask_lds; i += 256) s_mpre[i] = mask.prefix[i];
@@ -524,10 +532,13 @@ __global__ __launch_bounds__(256) void k_masked_counts(const uint2* __restrict__
     if (r.x > r.y || masked_count(mask, (int)(r.x & 0xFFFFu), (int)(r.x >> 16), (int)(r.y & 0xFFFFu),
                                   (int)(r.y >> 16)) == 0) {
         counts[k] = 0;
+        nseg[k] = 0;
         return;
     }
+    uint32_t segs = 0;
     counts[k] = band_count(BandRows(recs[k]), mask, (int)(r.x & 0xFFFFu), (int)(r.x >> 16), (int)(r.y & 0xFFFFu),
-                           (int)(r.y >> 16));
+                           (int)(r.y >> 16), &segs);
+    nseg[k] = segs;
 }
 
 // The ROI pass's key counts in compositing order, fused with the first step
@@ -540,7 +551,8 @@ __global__ __launch_bounds__(256) void k_masked_counts_ordered(const uint2* __re
                                                                const uint32_t* __restrict__ order, int n,
                                                                MaskArgs mask, int mask_lds,
                                                                uint32_t* __restrict__ counts,
-                                                               uint32_t* __restrict__ partials) {
+                                                               uint32_t* __restrict__ partials,
+                                                               uint32_t* __restrict__ nseg) {
     extern __shared__ uint32_t s_mpre[];
     __shared__ uint32_t s4[4];
     if (mask_lds > 0) {  // uniform over the grid
@@ -553,13 +565,15 @@ __global__ __launch_bounds__(256) void k_masked_counts_ordered(const uint2* __re
     if (i < n) {
         const uint32_t k = order[i];
         const uint2 r = rects[k];
+        uint32_t segs = 0;
         if (!(r.x > r.y)) {
             const int tx0 = (int)(r.x & 0xFFFFu), ty0 = (int)(r.x >> 16), tx1 = (int)(r.y & 0xFFFFu),
                       ty1 = (int)(r.y >> 16);
             if (masked_count(mask, tx0, ty0, tx1, ty1) != 0)
-                c = band_count(BandRows(recs[k]), mask, tx0, ty0, tx1, ty1);
+                c = band_count(BandRows(recs[k]), mask, tx0, ty0, tx1, ty1, &segs);
         }
         counts[i] = c;
+        nseg[i] = segs;  // by position in the order, as the counts
     }
     uint32_t sum = c;
 #pragma unroll
@@ -589,7 +603,8 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order
                                               const uint2* __restrict__ rects, const SurfelRec* __restrict__ recs,
                                               int n, int spb, int tiles_x, MaskArgs mask, int mask_lds,
                                               uint32_t cap, int vbits, uint32_t* __restrict__ tkeys,
-                                              uint32_t* __restrict__ tvals) {
+                                              uint32_t* __restrict__ tvals, const uint32_t* __restrict__ nseg,
+                                              int nseg_by_pos) {
     extern __shared__ uint32_t s_mpre[];  // mask_lds words: the mask prefix, when staged
     __shared__ uint32_t sk[256];
     __shared__ uint32_t seg_start[kEmitSegs + 1];
@@ -610,7 +625,7 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order
         pref = s_mpre;
     }
     uint2 rc = make_uint2(0xFFFFFFFFu, 0u);
-    uint32_t cnt = 0, loc = 0;
+    uint32_t cnt = 0, loc = 0, ns_given = 0;
     SurfelRec rec;
     if (t < m) {
         const uint32_t k = order[r0 + t];
@@ -620,15 +635,17 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order
         if (cnt) {
             rc = rects[k];
             rec = recs[k];
+            if (nseg) ns_given = nseg[nseg_by_pos ? (uint32_t)(r0 + t) : k];
         }
     }
     const int tx0 = rc.x & 0xFFFF, ty0 = rc.x >> 16, tx1 = rc.y & 0xFFFF, ty1 = rc.y >> 16;
     const BandRows br = cnt ? BandRows(rec) : BandRows();
-    // Segments of this thread's surfel.
-    uint32_t ns = 0;
+    // Segments of this thread's surfel: counted by the pass that counted
+    // its keys, or here.
+    uint32_t ns = ns_given;
     MaskArgs mk = mask;
     mk.tiles_x = tiles_x;
-    if (cnt) {
+    if (cnt && !nseg) {
         for_band_rows(br, mk, pref, tx0, ty0, tx1, ty1, [&](uint32_t c, uint32_t) {
             ns += c ? 1u : 0u;
             return true;
@@ -1521,21 +1538,21 @@ __global__ __launch_bounds__(256) void k_blend_fix(const SurfelRec* __restrict__
 hipError_t launch_preprocess(const SceneArgs& sc, const PreCam& cam, float alpha_min, int lowpass,
                              const MaskArgs& mask, SurfelRec* recs, uint32_t* zkeys, uint2* rects,
                              uint32_t* counts, const PreCam* cam2, SurfelRec* recs2, uint32_t* zkeys2,
-                             uint2* rects2, hipStream_t s) {
+                             uint2* rects2, uint32_t* nseg, hipStream_t s) {
     if (sc.n <= 0) return hipSuccess;
     const dim3 g((sc.n + 255) / 256);
     if (cam2)
         hipLaunchKernelGGL(k_preprocess<true>, g, dim3(256), 0, s, sc, cam, *cam2, alpha_min, lowpass, mask, recs, zkeys,
-                           rects, counts, recs2, zkeys2, rects2);
+                           rects, counts, recs2, zkeys2, rects2, nseg);
     else
         hipLaunchKernelGGL(k_preprocess<false>, g, dim3(256), 0, s, sc, cam, cam, alpha_min, lowpass, mask, recs, zkeys,
-                           rects, counts, nullptr, nullptr, nullptr);
+                           rects, counts, nullptr, nullptr, nullptr, nseg);
     return hipGetLastError();
 }
 
 hipError_t launch_masked_counts_ordered(const uint2* rects, const SurfelRec* recs, const uint32_t* order, int n,
                                         int n_tiles, const MaskArgs& mask, uint32_t* counts, uint32_t* partials,
-                                        hipStream_t s) {
+                                        uint32_t* nseg, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     // The mask prefix is read from global memory (it stays in L2): staging it
     // in LDS per workgroup cost more than the lookups (emission and counts of
@@ -1543,22 +1560,22 @@ hipError_t launch_masked_counts_ordered(const uint2* rects, const SurfelRec* rec
     const int mask_lds = 0;
     hipLaunchKernelGGL(k_masked_counts_ordered, dim3((unsigned)((n + 255) / 256)), dim3(256),
                        (size_t)mask_lds * sizeof(uint32_t), s, rects, recs, order, n, mask, mask_lds, counts,
-                       partials);
+                       partials, nseg);
     return hipGetLastError();
 }
 
 hipError_t launch_masked_counts(const uint2* rects, const SurfelRec* recs, int n, int n_tiles, const MaskArgs& mask,
-                                uint32_t* counts, hipStream_t s) {
+                                uint32_t* counts, uint32_t* nseg, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     const int mask_lds = n_tiles + 1 <= kEmitMaskLds ? n_tiles + 1 : 0;
     hipLaunchKernelGGL(k_masked_counts, dim3((n + 255) / 256), dim3(256), (size_t)mask_lds * sizeof(uint32_t), s,
-                       rects, recs, n, mask, mask_lds, counts);
+                       rects, recs, n, mask, mask_lds, counts, nseg);
     return hipGetLastError();
 }
 
 hipError_t launch_emit(const uint32_t* order, const uint32_t* offs, const uint2* rects, const SurfelRec* recs, int n,
                        int tiles_x, int n_tiles, const MaskArgs& mask, uint32_t cap, int vbits, uint32_t* tkeys,
-                       uint32_t* tvals, hipStream_t s) {
+                       uint32_t* tvals, const uint32_t* nseg, int nseg_by_pos, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     if (vbits < 0 || vbits > 31 || (vbits && (int64_t)n > ((int64_t)1 << vbits))) return hipErrorInvalidValue;
     const int mask_lds = 0;  // the mask prefix is read from global memory (see launch_masked_counts_ordered)
@@ -1568,7 +1585,7 @@ hipError_t launch_emit(const uint32_t* order, const uint32_t* offs, const uint2*
     // Masked, most surfels have no key and 256 per workgroup cost less.
     const int spb = mask.enabled ? 256 : 128;
     hipLaunchKernelGGL(k_emit, dim3((n + spb - 1) / spb), dim3(256), (size_t)mask_lds * sizeof(uint32_t), s, order,
-                       offs, rects, recs, n, spb, tiles_x, mask, mask_lds, cap, vbits, tkeys, tvals);
+                       offs, rects, recs, n, spb, tiles_x, mask, mask_lds, cap, vbits, tkeys, tvals, nseg, nseg_by_pos);
     return hipGetLastError();
 }
 
