@@ -597,6 +597,12 @@ __global__ __launch_bounds__(256) void k_masked_counts_ordered(const uint2* __re
 // ---------------------------------------------------------------------------
 constexpr int kEmitSegs = 2048;
 constexpr int kEmitWin = 2048;
+// Surfels whose rect spans more than kCoopRows tile rows (up to kCoopMax per
+// workgroup) have their segments listed by a whole wave, a row per lane: the
+// nearest surfels span the image's rows, and one thread listing them set the
+// emission's tail.
+constexpr int kCoopRows = 16;
+constexpr int kCoopMax = 32;
 constexpr int kEmitMaskLds = 8192;  // mask prefix words staged in LDS at most (32 KiB)
 
 __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order, const uint32_t* __restrict__ offs,
@@ -611,6 +617,10 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order
     __shared__ uint32_t seg_tile[kEmitSegs];  // first tile's key | surfel << 24 (keys < 2^20: sides <= 16384 px)
     __shared__ uint16_t owner[kEmitWin];
     __shared__ uint32_t lds[4];
+    __shared__ uint32_t s_nh;                // surfels listed by a wave
+    __shared__ float4 s_hrec[kCoopMax];      // their band words: centre x, y and the two packed band words
+    __shared__ uint4 s_hinfo[kCoopMax];      // rect (two packed words), first key in the block, first segment
+    __shared__ uint2 s_howner[kCoopMax];     // owning thread, segment count
     const int r0 = blockIdx.x * spb;  // spb <= 256 surfels, one thread each; all 256 threads write keys
     const int m = min(spb, n - r0);
     const uint32_t base = offs[r0];
@@ -659,14 +669,27 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order
         const uint32_t y = __shfl_up(v, off, 64);
         if (lane >= off) v += y;
     }
+    if (t == 0) s_nh = 0;
     if (lane == 63) lds[w] = v;
     __syncthreads();
     uint32_t sbase = v - ns;
     for (int q = 0; q < w; ++q) sbase += lds[q];
     const uint32_t tot_seg = lds[0] + lds[1] + lds[2] + lds[3];
+    bool coop = false;
+    if (ns && ty1 - ty0 + 1 > kCoopRows) {
+        const uint32_t h = atomicAdd(&s_nh, 1u);
+        if (h < (uint32_t)kCoopMax) {
+            coop = true;
+            s_hrec[h] = make_float4(rec.a.x, rec.a.y, rec.c.w, rec.d.w);
+            s_hinfo[h] = make_uint4(rc.x, rc.y, loc, sbase);
+            s_howner[h] = make_uint2((uint32_t)t, ns);
+        }
+    }
+    __syncthreads();
+    const uint32_t n_coop = min(s_nh, (uint32_t)kCoopMax);
     for (uint32_t w0 = 0; w0 < tot_seg; w0 += kEmitSegs) {
         const uint32_t w1 = min(tot_seg, w0 + (uint32_t)kEmitSegs);
-        if (ns && sbase < w1 && sbase + ns > w0) {
+        if (ns && !coop && sbase < w1 && sbase + ns > w0) {
             uint32_t si = sbase, kpos = loc;
             for_band_rows(br, mk, pref, tx0, ty0, tx1, ty1, [&](uint32_t c, uint32_t first) {
                 if (si >= w1) return false;
@@ -680,6 +703,58 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order
                 ++si;
                 return true;
             });
+        }
+        // The wave-listed surfels: 64 rows at a time, the row's segment slot
+        // from a ballot of the rows with keys and its first key from a
+        // prefix sum of the row counts.
+        for (uint32_t h = (uint32_t)w; h < n_coop; h += 4) {
+            const uint4 hi = s_hinfo[h];
+            const uint2 ho = s_howner[h];
+            if (!(hi.w < w1 && hi.w + ho.y > w0)) continue;  // uniform over the wave
+            const float4 hr = s_hrec[h];
+            SurfelRec q{};
+            q.a.x = hr.x;
+            q.a.y = hr.y;
+            q.c.w = hr.z;
+            q.d.w = hr.w;
+            const BandRows hb(q);
+            const int hx0 = (int)(hi.x & 0xFFFFu), hy0 = (int)(hi.x >> 16), hx1 = (int)(hi.y & 0xFFFFu),
+                      hy1 = (int)(hi.y >> 16);
+            uint32_t seg_carry = 0, key_carry = 0;
+            for (int y0 = hy0; y0 <= hy1 && hi.w + seg_carry < w1; y0 += 64) {
+                const int y = y0 + lane;
+                int a = 1, b = 0;
+                if (y <= hy1) hb.row(y, hx0, hx1, &a, &b);
+                uint32_t c = 0, first = 0;
+                if (b >= a) {
+                    const int64_t rb = (int64_t)y * tiles_x;
+                    if (mask.enabled) {
+                        first = pref[rb + a];
+                        c = pref[rb + b + 1] - first;
+                    } else {
+                        first = (uint32_t)(rb + a);
+                        c = (uint32_t)(b - a + 1);
+                    }
+                }
+                const uint64_t bal = __ballot(c != 0);
+                const uint32_t before = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+                uint32_t kin = c;  // inclusive prefix of the row counts over the wave
+#pragma unroll
+                for (int off = 1; off < 64; off <<= 1) {
+                    const uint32_t yv = __shfl_up(kin, off, 64);
+                    if (lane >= off) kin += yv;
+                }
+                const uint32_t si = hi.w + seg_carry + before;
+                const uint32_t kpos = hi.z + key_carry + kin - c;
+                if (c != 0 && si >= w0 && si < w1) {
+                    seg_start[si - w0] = kpos;
+                    seg_tile[si - w0] = first | (ho.x << 24);
+                    if (si + 1 == w1) seg_start[w1 - w0] = kpos + c;  // end of the turn's keys
+                }
+                seg_carry += (uint32_t)__popcll(bal);
+                key_carry += __shfl(kin, 63, 64);
+            }
         }
         __syncthreads();
         const int nw = (int)(w1 - w0);
