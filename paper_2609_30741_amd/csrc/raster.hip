@@ -512,6 +512,13 @@ __global__ __launch_bounds__(256) void k_preprocess(SceneArgs sc, PreCam cam, Pr
     }
 }
 
+// Surfels whose rect spans more than kCoopRows tile rows are counted (ROI
+// pass) and have their segments listed (emission, up to kCoopMax per
+// workgroup) by a whole wave, a row per lane: the nearest surfels span the
+// image's rows, and one thread walking them set these kernels' tails.
+constexpr int kCoopRows = 16;
+constexpr int kCoopMax = 32;
+
 // Key counts of surfels whose tile rects and records were computed
 // earlier, restricted to the tiles of a mask.
 // The mask prefix is staged in LDS (dynamic shared memory, mask_lds words)
@@ -561,17 +568,53 @@ __global__ __launch_bounds__(256) void k_masked_counts_ordered(const uint2* __re
         mask.prefix = s_mpre;
     }
     const int i = blockIdx.x * 256 + threadIdx.x;
-    uint32_t c = 0;
+    uint32_t c = 0, segs = 0, k = 0;
+    uint2 r = make_uint2(1u, 0u);
+    bool tall = false;
     if (i < n) {
-        const uint32_t k = order[i];
-        const uint2 r = rects[k];
-        uint32_t segs = 0;
+        k = order[i];
+        r = rects[k];
         if (!(r.x > r.y)) {
             const int tx0 = (int)(r.x & 0xFFFFu), ty0 = (int)(r.x >> 16), tx1 = (int)(r.y & 0xFFFFu),
                       ty1 = (int)(r.y >> 16);
-            if (masked_count(mask, tx0, ty0, tx1, ty1) != 0)
-                c = band_count(BandRows(recs[k]), mask, tx0, ty0, tx1, ty1, &segs);
+            if (masked_count(mask, tx0, ty0, tx1, ty1) != 0) {
+                if (ty1 - ty0 + 1 > kCoopRows)
+                    tall = true;  // counted by the whole wave below
+                else
+                    c = band_count(BandRows(recs[k]), mask, tx0, ty0, tx1, ty1, &segs);
+            }
         }
+    }
+    // Surfels across many tile rows (the nearest ones span the image): the
+    // wave counts each one's rows together, a row per lane.
+    const int lane = (int)(threadIdx.x & 63);
+    for (uint64_t tb = __ballot(tall); tb; tb &= tb - 1) {
+        const int src = __ffsll((unsigned long long)tb) - 1;
+        const uint32_t kk = (uint32_t)__shfl((int)k, src, 64);
+        const uint32_t rx = (uint32_t)__shfl((int)r.x, src, 64), ry = (uint32_t)__shfl((int)r.y, src, 64);
+        const int hx0 = (int)(rx & 0xFFFFu), hy0 = (int)(rx >> 16), hx1 = (int)(ry & 0xFFFFu), hy1 = (int)(ry >> 16);
+        const BandRows hb(recs[kk]);
+        uint32_t cc = 0, ss = 0;
+        for (int y = hy0 + lane; y <= hy1; y += 64) {
+            int a, b;
+            hb.row(y, hx0, hx1, &a, &b);
+            if (b < a) continue;
+            const int64_t rb = (int64_t)y * mask.tiles_x;
+            const uint32_t cy = mask.prefix[rb + b + 1] - mask.prefix[rb + a];
+            cc += cy;
+            ss += cy ? 1u : 0u;
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            cc += (uint32_t)__shfl_xor((int)cc, off, 64);
+            ss += (uint32_t)__shfl_xor((int)ss, off, 64);
+        }
+        if (lane == src) {
+            c = cc;
+            segs = ss;
+        }
+    }
+    if (i < n) {
         counts[i] = c;
         nseg[i] = segs;  // by position in the order, as the counts
     }
@@ -597,12 +640,6 @@ __global__ __launch_bounds__(256) void k_masked_counts_ordered(const uint2* __re
 // ---------------------------------------------------------------------------
 constexpr int kEmitSegs = 2048;
 constexpr int kEmitWin = 2048;
-// Surfels whose rect spans more than kCoopRows tile rows (up to kCoopMax per
-// workgroup) have their segments listed by a whole wave, a row per lane: the
-// nearest surfels span the image's rows, and one thread listing them set the
-// emission's tail.
-constexpr int kCoopRows = 16;
-constexpr int kCoopMax = 32;
 constexpr int kEmitMaskLds = 8192;  // mask prefix words staged in LDS at most (32 KiB)
 
 __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ order, const uint32_t* __restrict__ offs,
