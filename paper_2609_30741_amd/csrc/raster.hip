@@ -904,17 +904,106 @@ __global__ void k_status_keys(const uint32_t* __restrict__ offs, int n, DevStatu
 
 constexpr int kMaskLds = 15360;  // tile-mask prefix words staged in LDS (60 KiB)
 
+// Bit j set iff byte j of w is nonzero (j = 0..3).
+__device__ __forceinline__ uint32_t nonzero_bytes(uint32_t w) {
+    const uint32_t h = (((w & 0x7f7f7f7fu) + 0x7f7f7f7fu) | w) & 0x80808080u;
+    return ((h >> 7) & 1u) | ((h >> 14) & 2u) | ((h >> 21) & 4u) | ((h >> 28) & 8u);
+}
+
 // Tables of an ROI tile mask, one workgroup: prefix[t] = masked tiles before
 // tile t (t = 0..n_tiles), the compact list of masked tile ids, their count,
 // and colcum[ty][x] = sum over rows <= ty of prefix[row * tiles_x + x] for
 // x = 0..tiles_x, from which any rect's masked count takes four loads.
+// A mask of fewer than kMaskLds tiles is read in one step (16 tiles a
+// thread, loads issued together), its prefix built in LDS, and the column
+// sums taken by (column, band of rows) pairs: each pair sums its band, the
+// bands before it give its start, and it writes its rows.  Larger masks
+// take 4096 tiles per step and one wave per column.
 __global__ __launch_bounds__(1024) void k_mask_tables(const uint8_t* __restrict__ m, int n_tiles, int tiles_x,
                                                       uint32_t* __restrict__ prefix, uint32_t* __restrict__ list,
                                                       uint32_t* __restrict__ colcum, DevStatus* st) {
     __shared__ uint32_t wsum[16];
     __shared__ uint32_t s_run;
     __shared__ uint32_t s_pre[kMaskLds];
+    __shared__ uint32_t s_band[1024];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tiles_y = n_tiles / tiles_x;
+    const bool staged = n_tiles + 1 <= kMaskLds;
+    static_assert(kMaskLds <= 16 * 1024, "one step of 16 tiles a thread covers a staged mask");
+    if (staged) {
+        const int t0 = 16 * tid;
+        uint32_t bits = 0;  // bit j: tile t0 + j is masked
+        if (t0 + 16 <= n_tiles && ((reinterpret_cast<uintptr_t>(m) & 15u) == 0)) {
+            const uint4 w = *reinterpret_cast<const uint4*>(m + t0);
+            bits = nonzero_bytes(w.x) | (nonzero_bytes(w.y) << 4) | (nonzero_bytes(w.z) << 8) |
+                   (nonzero_bytes(w.w) << 12);
+        } else {
+            uint8_t b[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) b[j] = t0 + j < n_tiles ? m[t0 + j] : 0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) bits |= (b[j] != 0 ? 1u : 0u) << j;
+        }
+        const uint32_t sum = __popc(bits);
+        uint32_t x = sum;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wsum[wave] = x;
+        __syncthreads();
+        uint32_t acc = x - sum, total = 0;
+        for (int w = 0; w < 16; ++w) {
+            const uint32_t ws = wsum[w];
+            if (w < wave) acc += ws;
+            total += ws;
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int t = t0 + j;
+            if (t < n_tiles) {
+                s_pre[t] = acc;
+                if ((bits >> j) & 1u) list[acc] = (uint32_t)t;
+            }
+            acc += (bits >> j) & 1u;
+        }
+        if (tid == 0) {
+            s_pre[n_tiles] = total;
+            st->n_masked = total;
+            st->n_roi_tiles = total;
+        }
+        __syncthreads();
+        for (int t = tid; t <= n_tiles; t += 1024) prefix[t] = s_pre[t];  // coalesced
+        // Column x = tiles_x reads the next row's first entry (the last
+        // row's is the total).
+        const int C = tiles_x + 1;
+        if (C <= 1024) {
+            const int K = max(1, min(tiles_y, 1024 / C)), R = (tiles_y + K - 1) / K;
+            const int k = tid / C, xc = tid - k * C;
+            const bool on = k < K;
+            const int r0 = on ? min(tiles_y, k * R) : 0, r1 = on ? min(tiles_y, r0 + R) : 0;
+            uint32_t bs = 0;
+            for (int r = r0; r < r1; ++r) bs += s_pre[r * tiles_x + xc];
+            s_band[tid] = bs;
+            __syncthreads();
+            uint32_t run = 0;
+            for (int q = 0; q < k && on; ++q) run += s_band[q * C + xc];
+            for (int r = r0; r < r1; ++r) {
+                run += s_pre[r * tiles_x + xc];
+                colcum[(int64_t)r * C + xc] = run;
+            }
+        } else {
+            for (int xc = tid; xc < C; xc += 1024) {
+                uint32_t run = 0;
+                for (int r = 0; r < tiles_y; ++r) {
+                    run += s_pre[r * tiles_x + xc];
+                    colcum[(int64_t)r * C + xc] = run;
+                }
+            }
+        }
+        return;
+    }
     if (tid == 0) s_run = 0;
     __syncthreads();
     for (int base = 0; base < n_tiles; base += 1024 * 4) {
@@ -956,20 +1045,13 @@ __global__ __launch_bounds__(1024) void k_mask_tables(const uint8_t* __restrict_
     }
     __syncthreads();  // prefix is read back below by other threads of this block
     // Column sums: a wave takes a column and scans it down the rows 64 at a
-    // time with shuffles (a serial walk per column left most threads idle);
-    // the prefix is staged in LDS when it fits.
-    const int tiles_y = n_tiles / tiles_x;
-    const bool staged = n_tiles + 1 <= kMaskLds;
-    if (staged) {
-        for (int t = tid; t <= n_tiles; t += 1024) s_pre[t] = prefix[t];
-        __syncthreads();
-    }
+    // time with shuffles.
     for (int xc = wave; xc <= tiles_x; xc += 16) {
         uint32_t carry = 0;
         for (int y0 = 0; y0 < tiles_y; y0 += 64) {
             const int ty = y0 + lane;
-            const int q = ty * tiles_x + xc;  // xc = tiles_x reads the next row's first entry, as the serial walk did
-            uint32_t x = ty < tiles_y ? (staged ? s_pre[q] : prefix[q]) : 0u;
+            const int q = ty * tiles_x + xc;  // xc = tiles_x reads the next row's first entry
+            uint32_t x = ty < tiles_y ? prefix[q] : 0u;
 #pragma unroll
             for (int off = 1; off < 64; off <<= 1) {
                 const uint32_t y = __shfl_up(x, off, 64);
@@ -997,17 +1079,40 @@ __device__ __forceinline__ uint32_t order_bucket(uint32_t len) {
     return (31u - e) * 16u + (15u - m);
 }
 
+// Up to kOrderHeld tiles: each thread loads its ranges at once (bounded by
+// n_tiles, so the loads need not wait for the live count) and keeps their
+// buckets in registers for both passes.
+constexpr uint32_t kOrderRegs = 8, kOrderHeld = 1024 * kOrderRegs;
+
 __global__ __launch_bounds__(1024) void k_tile_order(const uint2* __restrict__ ranges, const uint32_t* n_live,
                                                      uint32_t n_tiles, uint32_t* __restrict__ order) {
     __shared__ uint32_t hist[kOrderBuckets];
     __shared__ uint32_t wsum[16];
-    const uint32_t n = n_live ? min(*n_live, n_tiles) : n_tiles;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const bool held = n_tiles <= kOrderHeld;
+    uint32_t bk[kOrderRegs];
+    if (held) {
+        uint2 r[kOrderRegs];
+#pragma unroll
+        for (uint32_t u = 0; u < kOrderRegs; ++u) {
+            const uint32_t t = tid + 1024u * u;
+            r[u] = t < n_tiles ? ranges[t] : make_uint2(0u, 0u);
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kOrderRegs; ++u) bk[u] = order_bucket(r[u].y - r[u].x);
+    }
+    const uint32_t n = n_live ? min(*n_live, n_tiles) : n_tiles;
     for (int i = tid; i < kOrderBuckets; i += 1024) hist[i] = 0;
     __syncthreads();
-    for (uint32_t t = tid; t < n; t += 1024) {
-        const uint2 r = ranges[t];
-        atomicAdd(&hist[order_bucket(r.y - r.x)], 1u);
+    if (held) {
+#pragma unroll
+        for (uint32_t u = 0; u < kOrderRegs; ++u)
+            if (tid + 1024u * u < n) atomicAdd(&hist[bk[u]], 1u);
+    } else {
+        for (uint32_t t = tid; t < n; t += 1024) {
+            const uint2 r = ranges[t];
+            atomicAdd(&hist[order_bucket(r.y - r.x)], 1u);
+        }
     }
     __syncthreads();
     // Exclusive scan of the buckets (one per thread).
@@ -1023,9 +1128,17 @@ __global__ __launch_bounds__(1024) void k_tile_order(const uint2* __restrict__ r
     for (int w = 0; w < wave; ++w) wbase += wsum[w];
     if (tid < kOrderBuckets) hist[tid] = wbase + x - v;
     __syncthreads();
-    for (uint32_t t = tid; t < n; t += 1024) {
-        const uint2 r = ranges[t];
-        order[atomicAdd(&hist[order_bucket(r.y - r.x)], 1u)] = t;
+    if (held) {
+#pragma unroll
+        for (uint32_t u = 0; u < kOrderRegs; ++u) {
+            const uint32_t t = tid + 1024u * u;
+            if (t < n) order[atomicAdd(&hist[bk[u]], 1u)] = t;
+        }
+    } else {
+        for (uint32_t t = tid; t < n; t += 1024) {
+            const uint2 r = ranges[t];
+            order[atomicAdd(&hist[order_bucket(r.y - r.x)], 1u)] = t;
+        }
     }
 }
 

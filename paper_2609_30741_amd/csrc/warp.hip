@@ -322,27 +322,49 @@ __global__ __launch_bounds__(NT) void k_reproject_rows(WarpCam src, WarpCam dst,
 // scatter form, which reduces with atomics) into the status block, from
 // every thread of a 256-thread block.  Returns the depth-proxy range of the
 // covered pixels, or [z_near, z_far] when none was covered, to every thread.
+// The kernel is a single workgroup on the critical path, so its latency is
+// what counts: the status words and four partials per thread are loaded
+// together, and the four reductions share one barrier.
 __device__ inline void fold_warp_parts(const uint4* __restrict__ wpart, int n, DevStatus* st, float z_near,
                                        float z_far, float* r0, float* r1) {
-    __shared__ uint32_t s4[4];
-    uint32_t a = 0u, b = 0u, h = 0u, f = 0u;
-    for (int i = threadIdx.x; i < n; i += 256) {
-        const uint4 q = wpart[i];
+    __shared__ uint4 s_w[4];
+    const uint32_t a0 = st->dmin_inv, b0 = st->dmax_bits, h0 = st->n_holes, f0 = st->overflow;
+    uint32_t a = 0u, b = 0u, h = 0u, f = 0u;  // 0 is the identity of each fold
+    for (int i0 = threadIdx.x; i0 < n; i0 += 1024) {
+        uint4 q[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) q[u] = i0 + 256 * u < n ? wpart[i0 + 256 * u] : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            a = max(a, q[u].x);
+            b = max(b, q[u].y);
+            h += q[u].z;
+            f |= q[u].w;
+        }
+    }
+    a = wave_max_u32(a);
+    b = wave_max_u32(b);
+    h = wave_sum_u32(h);
+    f = wave_max_u32(f);
+    if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = make_uint4(a, b, h, f);
+    __syncthreads();
+    a = a0;
+    b = b0;
+    h = 0u;
+    f = 0u;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const uint4 q = s_w[w];
         a = max(a, q.x);
         b = max(b, q.y);
         h += q.z;
-        f |= q.w;
+        f = max(f, q.w);
     }
-    a = max(block_max_u32(a, s4), st->dmin_inv);
-    b = max(block_max_u32(b, s4), st->dmax_bits);
-    h = block_sum_u32(h, s4);
-    f = block_max_u32(f, s4);
-    __syncthreads();
     if (threadIdx.x == 0) {
         st->dmin_inv = a;
         st->dmax_bits = b;
-        st->n_holes += h;
-        if (f) st->overflow |= f;
+        st->n_holes = h0 + h;
+        if (f) st->overflow = f0 | f;
     }
     if (a == 0u) {
         *r0 = z_near;
@@ -383,9 +405,18 @@ __global__ __launch_bounds__(256) void k_warp_finish(const uint4* __restrict__ w
 // ---------------------------------------------------------------------------
 // Step 1: edge ROIs (Eq. 6-8).  One block.
 // ---------------------------------------------------------------------------
-__device__ inline int64_t edge_pos(int64_t k, int64_t N, int64_t L) {
+// Sample k of N along an edge of L pixels: the nearest pixel to
+// k (L - 1) / (N - 1), halves rounded down, i.e. floor((2k(L-1) + N-1) /
+// (2(N-1))).  The quotient is taken in double (exact operands below 2^53,
+// so within one of the floor) and corrected in integers, which costs far
+// less than a 64-bit integer division.
+__device__ inline int edge_pos(int k, int N, int L) {
     if (N <= 1) return 0;
-    return (2 * k * (L - 1) + (N - 1)) / (2 * (N - 1));
+    const int64_t a = 2 * (int64_t)k * (L - 1) + (N - 1), b = 2 * (int64_t)(N - 1);
+    int64_t q = (int64_t)((double)a / (double)b);
+    if (q * b > a) --q;
+    else if ((q + 1) * b <= a) ++q;
+    return (int)q;
 }
 __device__ inline double snap(double x) {
     double r = rint(x);
@@ -395,8 +426,9 @@ __device__ inline double clampd(double x, double a, double b) { return x < a ? a
 __device__ inline int64_t align_down(int64_t x, int64_t T) { return (x / T) * T; }
 __device__ inline int64_t align_up(int64_t x, int64_t T) { return ((x + T - 1) / T) * T; }
 
-// Also writes the edge boxes' tiles into the ROI tile mask (every tile
-// covered by an edge box is 1, all others 0).  depth_range null: the range
+// With tm set, also writes the edge boxes' tiles into the ROI tile mask
+// (every tile covered by an edge box is 1, all others 0); k_gap_fill does
+// that instead when it runs, over its many workgroups.  depth_range null: the range
 // comes from the reprojection just run, whose partials (n_wpart, possibly
 // none) it folds into the status block first.
 __global__ __launch_bounds__(256) void k_edge_rois(WarpCam src, WarpCam dst, RelPose P, int N, int margin, int T,
@@ -419,11 +451,11 @@ __global__ __launch_bounds__(256) void k_edge_rois(WarpCam src, WarpCam dst, Rel
     // of the left edge, smallest x of the right, largest y of the top,
     // smallest y of the bottom.
     double lmax = -INFINITY, rmin = INFINITY, tmax = -INFINITY, bmin = INFINITY;
-    const int64_t total = 4LL * N;
-    for (int64_t q = threadIdx.x; q < total; q += 256) {
-        const int edge = (int)(q / N);
-        const int64_t k = q % N;
-        int64_t i, j;
+    const int total = 4 * N;  // N <= 65536
+    for (int q = threadIdx.x; q < total; q += 256) {
+        const int edge = q / N;
+        const int k = q - edge * N;
+        int i, j;
         if (edge == 0) { i = edge_pos(k, N, src.W); j = 0; }
         else if (edge == 1) { i = edge_pos(k, N, src.W); j = src.H - 1; }
         else if (edge == 2) { i = 0; j = edge_pos(k, N, src.H); }
@@ -533,13 +565,39 @@ __global__ __launch_bounds__(256) void k_edge_rois(WarpCam src, WarpCam dst, Rel
         }
     }
     __syncthreads();
+    if (!tm) return;  // the gap fill writes the mask
+    // The mask: box b covers tile columns [x0 / T, ceil(x1 / T)) and rows
+    // [y0 / T, ceil(y1 / T)).  The tile ranges sit in registers (the byte
+    // stores could alias LDS through a generic pointer, which would reload
+    // them per tile), and a thread takes four consecutive tiles per step,
+    // so that one division places them all.
     const int tiles_x = (dst.W + T - 1) / T, n_tiles = tiles_x * ((dst.H + T - 1) / T);
-    for (int t = threadIdx.x; t < n_tiles; t += 256) {
-        const int x0 = (t % tiles_x) * T, y0 = (t / tiles_x) * T, x1 = x0 + T, y1 = y0 + T;
-        uint8_t hit = 0;
-        for (int b = 0; b < snb; ++b)
-            if (x0 < sbx[b][2] && sbx[b][0] < x1 && y0 < sbx[b][3] && sbx[b][1] < y1) hit = 1;
-        tm[t] = hit;
+    const int nbx = snb;
+    int tr[4][4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const bool on = b < nbx;
+        tr[b][0] = on ? sbx[b][0] / T : 0;
+        tr[b][1] = on ? sbx[b][1] / T : 0;
+        tr[b][2] = on ? (sbx[b][2] + T - 1) / T : 0;
+        tr[b][3] = on ? (sbx[b][3] + T - 1) / T : 0;
+    }
+    for (int t0 = 4 * threadIdx.x; t0 < n_tiles; t0 += 4 * 256) {
+        int ty = t0 / tiles_x, tx = t0 - ty * tiles_x;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (t0 + u < n_tiles) {
+                bool hit = false;
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    hit = hit || (tx >= tr[b][0] && tx < tr[b][2] && ty >= tr[b][1] && ty < tr[b][3]);
+                tm[t0 + u] = hit ? 1 : 0;
+            }
+            if (++tx == tiles_x) {
+                tx = 0;
+                ++ty;
+            }
+        }
     }
 }
 
@@ -567,6 +625,14 @@ struct EdgeBoxes {
         bool in = false;
 #pragma unroll
         for (int k = 0; k < 4; ++k) in = in || (k < n && x >= b[k][0] && x < b[k][2] && y >= b[k][1] && y < b[k][3]);
+        return in;
+    }
+    // Does a box overlap the T x T tile whose first pixel is (x0, y0)?
+    __device__ bool overlaps(int x0, int y0, int T) const {
+        bool in = false;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            in = in || (k < n && x0 < b[k][2] && b[k][0] < x0 + T && y0 < b[k][3] && b[k][1] < y0 + T);
         return in;
     }
 };
@@ -635,7 +701,8 @@ __global__ __launch_bounds__(256) void k_gap_pass(int W, int H, int pass, float*
 // passes there (pass j is final for pixels at least j from the halo's
 // edge, which after all passes is the tile), and writes the tile's filled
 // pixels, tags and center mask.  Per pixel it computes exactly what
-// k_tag_init, k_gap_pass and k_center_mask compute.  Its filled and center
+// k_tag_init, k_gap_pass and k_center_mask compute.  It also writes the
+// ROI tile mask's edge-box tiles (the center boxes are added after it).  Its filled and center
 // counts go to gpart (one entry per block) rather than to shared counters,
 // so that hundreds of blocks do not serialise on one cache line; the
 // component-box kernels add them up.
@@ -646,7 +713,8 @@ __global__ __launch_bounds__(256) void k_gap_fill(int W, int H, int passes, floa
                                                   float* __restrict__ z, float* __restrict__ alpha,
                                                   uint8_t* __restrict__ tag_out, uint8_t* __restrict__ cls,
                                                   uint8_t* __restrict__ center, const DevStatus* st,
-                                                  uint2* __restrict__ gpart) {
+                                                  uint2* __restrict__ gpart, int T, int tiles_x, int tiles_y,
+                                                  uint8_t* __restrict__ tm) {
     __shared__ float s_c[3][kGapRH * kGapRW];
     __shared__ float s_a[kGapRH * kGapRW], s_z[kGapRH * kGapRW];
     __shared__ uint8_t s_tag[kGapRH * kGapRW];
@@ -656,6 +724,19 @@ __global__ __launch_bounds__(256) void k_gap_fill(int W, int H, int passes, floa
     const int h = passes;
     const int rw = 64 + 2 * h, rh = kBandRows + 2 * h;
     const int x0 = blockIdx.x * 64 - h, y0 = blockIdx.y * kBandRows - h;
+    const EdgeBoxes eb(st);
+    {
+        // The edge ROIs in the tile mask: the tiles whose first pixel lies
+        // in this block's region (so each tile is written by one block).
+        const int rx = blockIdx.x * 64, ry = blockIdx.y * kBandRows;
+        const int tx0 = (rx + T - 1) / T, tx1 = min(tiles_x, (rx + 64 + T - 1) / T);
+        const int ty0 = (ry + T - 1) / T, ty1 = min(tiles_y, (ry + kBandRows + T - 1) / T);
+        const int ntx = tx1 - tx0, nty = ty1 - ty0;
+        for (int k = threadIdx.x; ntx > 0 && k < ntx * nty; k += 256) {
+            const int ty = ty0 + k / ntx, tx = tx0 + k % ntx;
+            tm[(int64_t)ty * tiles_x + tx] = eb.overlaps(tx * T, ty * T, T) ? 1 : 0;
+        }
+    }
     {
         // Holes are sparse: a tile without one has nothing to fill and no
         // center pixel, and needs none of its neighbours' values.  (The
@@ -682,7 +763,6 @@ __global__ __launch_bounds__(256) void k_gap_fill(int W, int H, int passes, floa
             return;
         }
     }
-    const EdgeBoxes eb(st);
     // The tile and its halo: all loads first (unrolled, so none waits on
     // another), then the LDS stores.
     constexpr int kLoads = (kGapRW * kGapRH + 255) / 256;
@@ -1076,62 +1156,112 @@ __global__ __launch_bounds__(256) void k_ccl_flatten_roots(int64_t n, int* label
 // One workgroup: the gap-fill counts, an exclusive scan of the nb block
 // counts in place (bcount[nb] gets the component count), the box count and
 // capacity flag, and the initial (empty) box of every component.
-// Adds the gap-fill block counts (n_gpart entries) to the status block.
+// Adds the gap-fill block counts (n_gpart entries) to the status block.  The
+// status words are read first and up to four partials per thread are
+// loaded together: this runs on one workgroup, where load latency is most
+// of the time.
 __device__ inline void fold_gap_parts(const uint2* __restrict__ gpart, int n_gpart, DevStatus* st) {
-    __shared__ uint32_t s_g[2];
-    if (threadIdx.x == 0) s_g[0] = s_g[1] = 0u;
-    __syncthreads();
+    __shared__ uint32_t s_g[2][16];
+    const uint32_t g0 = st->n_gap, c0 = st->n_center;
     uint32_t f = 0u, c = 0u;
-    for (int i = threadIdx.x; i < n_gpart; i += blockDim.x) {
-        const uint2 q = gpart[i];
-        f += q.x;
-        c += q.y;
+    const int nt = (int)blockDim.x;
+    for (int i0 = threadIdx.x; i0 < n_gpart; i0 += 4 * nt) {
+        uint2 q[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) q[u] = i0 + u * nt < n_gpart ? gpart[i0 + u * nt] : make_uint2(0u, 0u);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            f += q[u].x;
+            c += q[u].y;
+        }
     }
     f = wave_sum_u32(f);
     c = wave_sum_u32(c);
     if ((threadIdx.x & 63) == 0) {
-        atomicAdd(&s_g[0], f);
-        atomicAdd(&s_g[1], c);
+        s_g[0][threadIdx.x >> 6] = f;
+        s_g[1][threadIdx.x >> 6] = c;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        st->n_gap += s_g[0];
-        st->n_center += s_g[1];
+        uint32_t tf = 0u, tc = 0u;
+        for (int w = 0; w < nt / 64; ++w) {
+            tf += s_g[0][w];
+            tc += s_g[1][w];
+        }
+        st->n_gap = g0 + tf;
+        st->n_center = c0 + tc;
     }
 }
+
+// Block counts up to kRootLds are staged in LDS with coalesced loads (all
+// issued together), scanned there and written back coalesced; larger
+// images walk per-thread chunks in global memory.
+constexpr int kRootLds = 16384;
 
 __global__ __launch_bounds__(1024) void k_root_scan(int64_t nb, uint32_t* bcount, int32_t* __restrict__ bbox,
                                                     int box_cap, int32_t* __restrict__ n_boxes,
                                                     const uint2* __restrict__ gpart, int n_gpart, DevStatus* st) {
-    __shared__ uint32_t part[1024];
-    fold_gap_parts(gpart, n_gpart, st);
+    __shared__ uint32_t s_cnt[kRootLds];
+    __shared__ uint32_t wsum[16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t n_edge = st->n_edge;
+    const bool staged = nb <= kRootLds;
+    if (staged) {
+        constexpr int kU = kRootLds / 1024;
+        uint32_t v[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) v[u] = tid + 1024 * u < nb ? bcount[tid + 1024 * u] : 0u;
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+            if (tid + 1024 * u < nb) s_cnt[tid + 1024 * u] = v[u];
+    }
+    fold_gap_parts(gpart, n_gpart, st);  // its barrier also publishes s_cnt
     const int64_t per = (nb + 1023) / 1024;
-    const int64_t b0 = min(nb, (int64_t)threadIdx.x * per), b1 = min(nb, b0 + per);
+    const int64_t b0 = min(nb, (int64_t)tid * per), b1 = min(nb, b0 + per);
     uint32_t sum = 0;
-    for (int64_t b = b0; b < b1; ++b) sum += bcount[b];
-    part[threadIdx.x] = sum;
+    if (staged)
+        for (int64_t b = b0; b < b1; ++b) sum += s_cnt[b];
+    else
+        for (int64_t b = b0; b < b1; ++b) sum += bcount[b];
+    // Exclusive scan of the 1024 chunk sums: within each wave by shuffles,
+    // then over the 16 wave totals.
+    uint32_t x = sum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
-        __syncthreads();
-        part[threadIdx.x] += v;
-        __syncthreads();
+    uint32_t run = x - sum, total = 0;
+    for (int w = 0; w < 16; ++w) {
+        const uint32_t ws = wsum[w];
+        if (w < wave) run += ws;
+        total += ws;
     }
-    uint32_t run = part[threadIdx.x] - sum;
-    for (int64_t b = b0; b < b1; ++b) {
-        const uint32_t c = bcount[b];
-        bcount[b] = run;
-        run += c;
+    if (staged) {
+        for (int64_t b = b0; b < b1; ++b) {
+            const uint32_t c = s_cnt[b];
+            s_cnt[b] = run;
+            run += c;
+        }
+        __syncthreads();
+        for (int64_t b = tid; b < nb; b += 1024) bcount[b] = s_cnt[b];
+    } else {
+        for (int64_t b = b0; b < b1; ++b) {
+            const uint32_t c = bcount[b];
+            bcount[b] = run;
+            run += c;
+        }
     }
-    const uint32_t total = part[1023];
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         bcount[nb] = total;
-        const uint32_t tot = st->n_edge + total;
+        const uint32_t tot = n_edge + total;
         st->n_boxes = tot;
         if ((int64_t)tot > box_cap) atomicOr(&st->overflow, 2u);
         *n_boxes = (int32_t)tot;
     }
-    for (uint32_t c = threadIdx.x; c < total; c += 1024) {
+    for (uint32_t c = tid; c < total; c += 1024) {
         int32_t* e = bbox + (size_t)c * kBoxWords;
         e[0] = INT_MAX;
         e[1] = INT_MAX;
@@ -1299,17 +1429,18 @@ hipError_t launch_classify(const WarpCam& src, const WarpCam& dst, const RelPose
                            uint8_t* tile_mask, const ClassifyBufs& b, DevStatus* st, hipStream_t s) {
     const int W = dst.W, H = dst.H, T = roi.tile;
     const int64_t n = (int64_t)W * H;
-    const int tiles_x = (W + T - 1) / T;
+    const int tiles_x = (W + T - 1) / T, tiles_y = (H + T - 1) / T;
+    const bool fused = roi.gap_passes <= kGapMaxHalo;  // k_gap_fill writes the edge tiles of the mask
     hipLaunchKernelGGL(k_edge_rois, dim3(1), dim3(256), 0, s, src, dst, P, roi.edge_samples, roi.margin, T,
                        roi.edge_bounds, depth_range, b.wpart, depth_range ? 0 : warp_parts(src, dst, P), st, boxes, box_cap,
-                       tile_mask);
+                       fused ? nullptr : tile_mask);
     const dim3 gg = band_grid(W, H);
     int n_gpart = 0;
     uint8_t* tag = b.hole;
     uint8_t* center = b.hole2;
-    if (roi.gap_passes <= kGapMaxHalo) {
+    if (fused) {
         hipLaunchKernelGGL(k_gap_fill, gg, dim3(256), 0, s, W, H, roi.gap_passes, rgb, z, alpha, tag, cls, center, st,
-                           b.gpart);
+                           b.gpart, T, tiles_x, tiles_y, tile_mask);
         n_gpart = (int)(gg.x * gg.y);
     } else {
         hipLaunchKernelGGL(k_tag_init, dim3(grid(n)), dim3(256), 0, s, n, cls, tag);

@@ -344,7 +344,10 @@ def test_reproject_bit_exact(ctx, oracle, W, H, seed, b, turn):
 @pytest.mark.parametrize("center,edge_bounds", [(True, 0), (False, 0), (True, 1)])
 @pytest.mark.parametrize("W,H,seed,b,turn", [(256, 256, 5, 0.064, 0.0), (800, 600, 6, 0.15, 0.0),
                                              (203, 117, 7, 0.3, 0.0), (1600, 1064, 8, 0.064, 0.0),
-                                             (320, 240, 9, 0.1, 0.1), (320, 240, 10, -0.2, 0.0)])
+                                             (320, 240, 9, 0.1, 0.1), (320, 240, 10, -0.2, 0.0),
+                                             # 16384 and 17200 labelling blocks of 256 pixels: the
+                                             # component scan at and beyond what it stages on chip
+                                             (2048, 2048, 13, 0.1, 0.0), (2752, 1600, 14, 0.064, 0.0)])
 def test_classify_bit_exact(ctx, oracle, center, edge_bounds, W, H, seed, b, turn):
     dom, aff = stage_rig(W, H, 1.2 * W, b, turn)
     rgb, dr, a = synth.stage_images(W, H, seed, n_occluders=10)
@@ -428,6 +431,39 @@ def test_patch_matches_oracle_and_all_tiles_equal_full_render(ctx, oracle):
     finally:
         ctx.set_blend_split()
     assert torch.equal(g_rgb, full["rgb"]) and torch.equal(g_a, full["alpha"])
+
+
+def test_patch_many_tiles_equals_full_render(ctx, oracle):
+    """An image of 128 x 122 tiles, more than the ROI mask tables stage on
+    chip and more than the tile order keeps in registers: every masked tile
+    of the patch equals the full render of the same camera bit for bit (the
+    same continuation caps), every other pixel keeps its value, and the full
+    render matches the oracle on sampled pixels."""
+    W, H = 2048, 1952
+    sc, cam = cube_workload(20_000, W, H, 2400.0, seed=3)
+    ds = api.DeviceScene(sc)
+    tm = (np.random.default_rng(4).uniform(size=(-(-H // 16), W // 16)) < 0.3).astype(np.uint8)
+    base = np.random.default_rng(5).uniform(size=(3, H, W)).astype(np.float32)
+    g_rgb, g_z = torch.from_numpy(base.copy()).cuda(), torch.zeros((H, W), device="cuda")
+    g_a, g_cls = torch.zeros((H, W), device="cuda"), torch.zeros((H, W), dtype=torch.uint8, device="cuda")
+    try:
+        ctx.set_blend_split(256, 256, 256, 0, 0)
+        full = ctx.render_dominant(ds, cam)
+        ctx.patch_rois(ds, cam, torch.from_numpy(tm).cuda(), g_rgb, g_z, g_a, g_cls)
+    finally:
+        ctx.set_blend_split()
+    torch.cuda.synchronize()
+    pm = np.kron(tm, np.ones((16, 16), np.uint8)).astype(bool)[:H, :W]
+    rgb, f_rgb = to_np(g_rgb), to_np(full["rgb"])
+    assert np.array_equal(rgb[:, ~pm], base[:, ~pm])
+    assert np.array_equal(rgb[:, pm], f_rgb[:, pm])
+    assert np.array_equal(to_np(g_a)[pm], to_np(full["alpha"])[pm])
+    rng = np.random.default_rng(8)
+    pix = np.stack([rng.integers(0, W, 800), rng.integers(0, H, 800)], axis=1).astype(np.int32)
+    ref = oracle.render(sc, cam, pixels=pix)
+    d, a = to_np(full["depth_raw"]), to_np(full["alpha"])
+    check_image(f_rgb[:, pix[:, 1], pix[:, 0]], d[pix[:, 1], pix[:, 0]], a[pix[:, 1], pix[:, 0]], ref, "2048x1952")
+    assert float(a.mean()) > 0.1
 
 
 def test_render_stereo_zero_baseline(ctx):
