@@ -702,33 +702,61 @@ __global__ __launch_bounds__(256) void k_gap_pass(int W, int H, int pass, float*
 // edge, which after all passes is the tile), and writes the tile's filled
 // pixels, tags and center mask.  Per pixel it computes exactly what
 // k_tag_init, k_gap_pass and k_center_mask compute.  It also writes the
-// ROI tile mask's edge-box tiles (the center boxes are added after it).  Its filled and center
-// counts go to gpart (one entry per block) rather than to shared counters,
-// so that hundreds of blocks do not serialise on one cache line; the
-// component-box kernels add them up.
+// ROI tile mask's edge-box tiles (the center boxes are added after it).
+// Its filled and center counts go to gpart (one entry per block) rather
+// than to shared counters, so that hundreds of blocks do not serialise on
+// one cache line; the component-box kernels add them up.
 constexpr int kGapMaxHalo = 4;
-constexpr int kGapRW = 64 + 2 * kGapMaxHalo, kGapRH = kBandRows + 2 * kGapMaxHalo;
+constexpr uint8_t kTagEdge = 253, kTagOut = 254;
 
+// Workgroups are dispatched to the 8 XCDs in turn (block b to XCD b % 8),
+// and each XCD has its own L2.  Tile t of an image's gx * gy tiles is
+// given to a block of the XCD that owns its row-major eighth of the tiles,
+// so neighbouring tiles, which read each other's edge pixels as halo, are
+// mostly read through the same L2.  A bijection of [0, gx * gy).
+__device__ inline void xcd_tile(uint32_t b, uint32_t gx, uint32_t gy, int* tx, int* ty) {
+    const uint32_t n = gx * gy, q = n / 8, r = n % 8;
+    const uint32_t xcd = b % 8, k = b / 8;
+    const uint32_t t = xcd * q + min(xcd, r) + k;
+    *tx = (int)(t % gx);
+    *ty = (int)(t / gx);
+}
+
+// kH: the halo the LDS region is sized for (passes <= kH).  1D grid of
+// ceil(W / 64) * ceil(H / kBandRows) blocks.
+template <int kH>
 __global__ __launch_bounds__(256) void k_gap_fill(int W, int H, int passes, float* __restrict__ rgb,
                                                   float* __restrict__ z, float* __restrict__ alpha,
                                                   uint8_t* __restrict__ tag_out, uint8_t* __restrict__ cls,
                                                   uint8_t* __restrict__ center, const DevStatus* st,
                                                   uint2* __restrict__ gpart, int T, int tiles_x, int tiles_y,
                                                   uint8_t* __restrict__ tm) {
-    __shared__ float s_c[3][kGapRH * kGapRW];
-    __shared__ float s_a[kGapRH * kGapRW], s_z[kGapRH * kGapRW];
-    __shared__ uint8_t s_tag[kGapRH * kGapRW];
-    __shared__ uint8_t s_fix[kGapRH * kGapRW];  // 1: outside the image, 2: hole inside an edge ROI
+    constexpr int RW = 64 + 2 * kH, RH = kBandRows + 2 * kH;
+    __shared__ float s_c[3][RH * RW];
+    __shared__ float s_a[RH * RW], s_z[RH * RW];
+    // Tag per pixel: 0 no hole, k a hole filled in pass k, 255 a hole still
+    // open, kTagEdge a hole inside an edge ROI (never filled), kTagOut
+    // outside the image.  In pass k a neighbour is valid iff its tag is
+    // below k.
+    __shared__ uint8_t s_tag[RH * RW];
+    __shared__ uint16_t s_hl[RH * RW];  // the open holes one pixel or more inside the region
+    __shared__ uint32_t s_nh;
     __shared__ uint32_t s4[4];
+    const uint32_t gx = (uint32_t)(W + 63) / 64, gy = (uint32_t)(H + kBandRows - 1) / kBandRows;
+    int bx, by;
+    xcd_tile(blockIdx.x, gx, gy, &bx, &by);
+    const uint32_t gb = (uint32_t)by * gx + (uint32_t)bx;
     const int64_t n = (int64_t)W * H;
-    const int h = passes;
-    const int rw = 64 + 2 * h, rh = kBandRows + 2 * h;
-    const int x0 = blockIdx.x * 64 - h, y0 = blockIdx.y * kBandRows - h;
+    // The halo is kH pixels whatever the number of passes: a wider halo
+    // changes nothing inside the tile (pass j is final for the pixels j or
+    // more from the region's edge).
+    const int x0 = bx * 64 - kH, y0 = by * kBandRows - kH;
     const EdgeBoxes eb(st);
+    if (threadIdx.x == 0) s_nh = 0;
     {
         // The edge ROIs in the tile mask: the tiles whose first pixel lies
         // in this block's region (so each tile is written by one block).
-        const int rx = blockIdx.x * 64, ry = blockIdx.y * kBandRows;
+        const int rx = bx * 64, ry = by * kBandRows;
         const int tx0 = (rx + T - 1) / T, tx1 = min(tiles_x, (rx + 64 + T - 1) / T);
         const int ty0 = (ry + T - 1) / T, ty1 = min(tiles_y, (ry + kBandRows + T - 1) / T);
         const int ntx = tx1 - tx0, nty = ty1 - ty0;
@@ -741,11 +769,11 @@ __global__ __launch_bounds__(256) void k_gap_fill(int W, int H, int passes, floa
         // Holes are sparse: a tile without one has nothing to fill and no
         // center pixel, and needs none of its neighbours' values.  (The
         // loads are issued together: unrolled, none waits on another.)
-        const int cx = blockIdx.x * 64 + (threadIdx.x & 63);
+        const int cx = bx * 64 + (threadIdx.x & 63);
         uint8_t hv[kBandRows / 4];
 #pragma unroll
         for (int q = 0; q < kBandRows / 4; ++q) {
-            const int cy = blockIdx.y * kBandRows + (threadIdx.x >> 6) + 4 * q;
+            const int cy = by * kBandRows + (threadIdx.x >> 6) + 4 * q;
             hv[q] = (cx < W && cy < H) ? cls[(int64_t)cy * W + cx] : 0;
         }
         bool any = false;
@@ -753,26 +781,26 @@ __global__ __launch_bounds__(256) void k_gap_fill(int W, int H, int passes, floa
         for (int q = 0; q < kBandRows / 4; ++q) any = any || hv[q] != 0;
         if (!__syncthreads_or(any)) {
             for (int r = threadIdx.x >> 6; r < kBandRows; r += 4) {
-                const int cy = blockIdx.y * kBandRows + r;
+                const int cy = by * kBandRows + r;
                 if (cx < W && cy < H) {
                     tag_out[(int64_t)cy * W + cx] = 0;
                     center[(int64_t)cy * W + cx] = 0;
                 }
             }
-            if (threadIdx.x == 0) gpart[blockIdx.y * gridDim.x + blockIdx.x] = make_uint2(0u, 0u);
+            if (threadIdx.x == 0) gpart[gb] = make_uint2(0u, 0u);
             return;
         }
     }
     // The tile and its halo: all loads first (unrolled, so none waits on
     // another), then the LDS stores.
-    constexpr int kLoads = (kGapRW * kGapRH + 255) / 256;
+    constexpr int kLoads = (RW * RH + 255) / 256;
     float lc0[kLoads], lc1[kLoads], lc2[kLoads], la[kLoads], lz[kLoads];
     uint8_t lh[kLoads];
 #pragma unroll
     for (int q = 0; q < kLoads; ++q) {
         const int i = threadIdx.x + 256 * q;
-        const int lx = i % rw, ly = i / rw, x = x0 + lx, y = y0 + ly;
-        const bool ok = i < rw * rh && x >= 0 && y >= 0 && x < W && y < H;
+        const int lx = i % RW, ly = i / RW, x = x0 + lx, y = y0 + ly;
+        const bool ok = i < RW * RH && x >= 0 && y >= 0 && x < W && y < H;
         const int64_t p = ok ? (int64_t)y * W + x : 0;
         lh[q] = ok ? cls[p] : 0;
         lc0[q] = ok ? rgb[p] : 0.f;
@@ -784,31 +812,43 @@ __global__ __launch_bounds__(256) void k_gap_fill(int W, int H, int passes, floa
 #pragma unroll
     for (int q = 0; q < kLoads; ++q) {
         const int i = threadIdx.x + 256 * q;
-        if (i >= rw * rh) continue;
-        const int lx = i % rw, ly = i / rw, x = x0 + lx, y = y0 + ly;
-        const int li = ly * kGapRW + lx;
+        if (i >= RW * RH) continue;
+        const int lx = i % RW, ly = i / RW, x = x0 + lx, y = y0 + ly;
         if (x < 0 || y < 0 || x >= W || y >= H) {
-            s_tag[li] = 255;
-            s_fix[li] = 1;
+            s_tag[i] = kTagOut;
             continue;
         }
-        const bool hole = lh[q] != 0;
-        s_tag[li] = hole ? 255 : 0;
-        s_fix[li] = (hole && eb.contains(x, y)) ? 2 : 0;
-        s_c[0][li] = lc0[q];
-        s_c[1][li] = lc1[q];
-        s_c[2][li] = lc2[q];
-        s_a[li] = la[q];
-        s_z[li] = lz[q];
+        s_tag[i] = lh[q] == 0 ? 0 : eb.contains(x, y) ? kTagEdge : 255;
+        s_c[0][i] = lc0[q];
+        s_c[1][i] = lc1[q];
+        s_c[2][i] = lc2[q];
+        s_a[i] = la[q];
+        s_z[i] = lz[q];
     }
     __syncthreads();
+    // The open holes, listed once (in no particular order: a pass reads
+    // only tags below its own number, so its pixels are independent), so
+    // that the passes visit nothing else.
+#pragma unroll
+    for (int q = 0; q < kLoads; ++q) {
+        const int i = threadIdx.x + 256 * q;
+        const int lx = i % RW, ly = i / RW;
+        const bool open = i < RW * RH && lx >= 1 && lx < RW - 1 && ly >= 1 && ly < RH - 1 && s_tag[i] == 255;
+        const unsigned long long bal = __ballot(open);
+        const int lane = threadIdx.x & 63;
+        uint32_t base = 0;
+        if (lane == 0 && bal) base = atomicAdd(&s_nh, (uint32_t)__popcll(bal));
+        base = __shfl(base, 0, 64);
+        if (open) s_hl[base + __popcll(bal & ((1ull << lane) - 1ull))] = (uint16_t)i;
+    }
+    __syncthreads();
+    const int nh = (int)s_nh;
     for (int pass = 1; pass <= passes; ++pass) {
-        const int m = pass;  // pixels at least `pass` from the region's edge
-        const int cw = rw - 2 * m, ch = rh - 2 * m;
-        for (int i = threadIdx.x; i < cw * ch; i += 256) {
-            const int lx = m + i % cw, ly = m + i / cw;
-            const int li = ly * kGapRW + lx;
-            if (s_tag[li] != 255 || s_fix[li] != 0) continue;
+        for (int e = threadIdx.x; e < nh; e += 256) {
+            const int li = s_hl[e];
+            const int ly = li / RW, lx = li - ly * RW;
+            // pixels at least `pass` from the region's edge, not yet filled
+            if (lx < pass || lx >= RW - pass || ly < pass || ly >= RH - pass || s_tag[li] != 255) continue;
             const int NX[8] = {-1, 0, 1, -1, 1, -1, 0, 1};
             const int NY[8] = {-1, -1, -1, 0, 0, 1, 1, 1};
             // All eight neighbours' values are read together (no read waits
@@ -817,8 +857,8 @@ __global__ __launch_bounds__(256) void k_gap_fill(int W, int H, int passes, floa
             float v0[8], v1[8], v2[8], va[8], vz[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-                const int r = (ly + NY[q]) * kGapRW + lx + NX[q];
-                ok[q] = !(s_fix[r] == 1 || (int)s_tag[r] >= pass);  // outside, a hole, or filled in this pass
+                const int r = (ly + NY[q]) * RW + lx + NX[q];
+                ok[q] = (int)s_tag[r] < pass;  // not outside, not a hole, not filled in this pass
                 v0[q] = s_c[0][r];
                 v1[q] = s_c[1][r];
                 v2[q] = s_c[2][r];
@@ -851,13 +891,13 @@ __global__ __launch_bounds__(256) void k_gap_fill(int W, int H, int passes, floa
     }
     uint32_t filled = 0, centers = 0;
     for (int i = threadIdx.x; i < 64 * kBandRows; i += 256) {
-        const int lx = h + (i & 63), ly = h + (i >> 6), x = x0 + lx, y = y0 + ly;
+        const int lx = kH + (i & 63), ly = kH + (i >> 6), x = x0 + lx, y = y0 + ly;
         if (x >= W || y >= H) continue;
-        const int li = ly * kGapRW + lx;
+        const int li = ly * RW + lx;
         const int64_t p = (int64_t)y * W + x;
         const uint8_t t = s_tag[li];
-        tag_out[p] = t;
-        if (t != 0 && t != 255) {
+        tag_out[p] = t >= kTagEdge ? 255 : t;
+        if (t != 0 && t < kTagEdge) {
             rgb[p] = s_c[0][li];
             rgb[n + p] = s_c[1][li];
             rgb[2 * n + p] = s_c[2][li];
@@ -866,13 +906,13 @@ __global__ __launch_bounds__(256) void k_gap_fill(int W, int H, int passes, floa
             cls[p] = (uint8_t)BGS_CLS_GAP;
             ++filled;
         }
-        const uint32_t c = (t == 255 && s_fix[li] == 0) ? 1u : 0u;
+        const uint32_t c = t == 255 ? 1u : 0u;
         center[p] = (uint8_t)c;
         centers += c;
     }
     filled = block_sum_u32(filled, s4);
     centers = block_sum_u32(centers, s4);
-    if (threadIdx.x == 0) gpart[blockIdx.y * gridDim.x + blockIdx.x] = make_uint2(filled, centers);
+    if (threadIdx.x == 0) gpart[gb] = make_uint2(filled, centers);
 }
 
 // Holes left after interpolation and outside the edge ROIs.
@@ -1439,8 +1479,13 @@ hipError_t launch_classify(const WarpCam& src, const WarpCam& dst, const RelPose
     uint8_t* tag = b.hole;
     uint8_t* center = b.hole2;
     if (fused) {
-        hipLaunchKernelGGL(k_gap_fill, gg, dim3(256), 0, s, W, H, roi.gap_passes, rgb, z, alpha, tag, cls, center, st,
-                           b.gpart, T, tiles_x, tiles_y, tile_mask);
+        const dim3 g1(gg.x * gg.y);
+        if (roi.gap_passes <= 2)
+            hipLaunchKernelGGL(k_gap_fill<2>, g1, dim3(256), 0, s, W, H, roi.gap_passes, rgb, z, alpha, tag, cls,
+                               center, st, b.gpart, T, tiles_x, tiles_y, tile_mask);
+        else
+            hipLaunchKernelGGL(k_gap_fill<kGapMaxHalo>, g1, dim3(256), 0, s, W, H, roi.gap_passes, rgb, z, alpha, tag,
+                               cls, center, st, b.gpart, T, tiles_x, tiles_y, tile_mask);
         n_gpart = (int)(gg.x * gg.y);
     } else {
         hipLaunchKernelGGL(k_tag_init, dim3(grid(n)), dim3(256), 0, s, n, cls, tag);
