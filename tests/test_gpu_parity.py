@@ -328,7 +328,10 @@ def stage_rig(W, H, f, b=0.064, turn=0.0):
 @pytest.mark.parametrize("W,H,seed,b,turn", [(256, 256, 0, 0.064, 0.0), (800, 600, 1, 0.064, 0.0),
                                              (203, 117, 2, 0.3, 0.0), (160, 120, 3, 0.0, 0.0),
                                              (96, 64, 4, -0.2, 0.0), (256, 192, 5, 0.064, 0.05),
-                                             (800, 600, 6, 0.1, -0.2)])
+                                             (800, 600, 6, 0.1, -0.2),
+                                             # rows the row kernel stages in LDS, and rows wider
+                                             # than it stages
+                                             (1600, 40, 8, 0.064, 0.0), (2400, 48, 7, 0.064, 0.0)])
 def test_reproject_bit_exact(ctx, oracle, W, H, seed, b, turn):
     dom, aff = stage_rig(W, H, 1.2 * W, b, turn)
     rgb, dr, a = synth.stage_images(W, H, seed)
