@@ -459,11 +459,11 @@ int raster_pass(bgs_ctx* ctx, const Layout& L, void* ws, int64_t kc, const bgs_s
     mark(ctx, sb + 2, 1);
     // Stable sort by tile: within a tile the emission (= compositing) order stays.
     mark(ctx, sb + 3, 0);
-    // An ROI pass bins a small part of the tiles: a small sort is expected
-    // (1024-key sub-chunks; at 2.8M keys with values they still beat the
-    // 6144-key sub-chunks: 74 against 87 us).
+    // An ROI pass's key count is known only on the device and ranges from a
+    // few thousand keys to most of a full pass's: the sort runs both of its
+    // forms, each gated on that count.
     HIP_CHECK(radix_sort(tka, vbits ? nullptr : tva, tkb, vbits ? nullptr : tvb, &st->n_sort, kc, tbits, false,
-                         at<void>(ws, L.radix), s, &in_b, tile_mask ? 1 : 0, vbits),
+                         at<void>(ws, L.radix), s, &in_b, tile_mask ? -1 : 0, vbits),
               "tile sort");
     const uint32_t* skeys = in_b ? tkb : tka;
     const uint32_t* svals = vbits ? skeys : in_b ? tvb : tva;

@@ -182,8 +182,9 @@ size_t radix_tmp_bytes(int64_t n_cap);
 // below key_shift).  The element count is *n_dev (<= n_cap), or n_cap when
 // n_dev is null.
 // Returns in *in_b whether the result is in (kb, vb).  n_hint (optional):
-// the expected element count when it is far below n_cap; it only chooses
-// the kernels' sub-chunk size, never the result.
+// the expected element count when it is far below n_cap, or -1 when only
+// the device knows it (both kernel forms are then launched, each gated on
+// *n_dev); it only chooses the kernels' sub-chunk size, never the result.
 hipError_t radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, const uint32_t* n_dev,
                       int64_t n_cap, int key_bits, bool iota, void* tmp, hipStream_t s, bool* in_b,
                       int64_t n_hint = 0, int key_shift = 0);

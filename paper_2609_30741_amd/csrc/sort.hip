@@ -257,6 +257,15 @@ constexpr int kRsSmallGrid = 512;
 // ones, where a block holds only a few hundred keys and its latency is the
 // sort's.
 constexpr int kRsItemsBig = 24, kRsItemsSmall = 4;
+// A sort whose key count is known only on the device (an ROI pass's) runs
+// both forms and each form's kernels return at once unless the count is
+// in their range: the small form up to kRsSplitKeys keys (2.8M keys: 74 us
+// against 87 us for the large form), the large form above.
+constexpr uint32_t kRsSplitKeys = 4u << 20;
+struct RsGate {
+    uint32_t lo, hi;  // the kernel runs iff lo <= n <= hi
+};
+constexpr RsGate kRsAlways{0u, 0xFFFFFFFFu};
 
 __device__ inline uint64_t match_digit(uint32_t d, uint64_t valid, int bits) {
     uint64_t peers = valid;
@@ -285,10 +294,11 @@ __device__ inline void chunk_of(uint32_t n, uint32_t grid, uint32_t b, uint32_t 
 template <int kRsItems>
 __global__ __launch_bounds__(256) void k_rs_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_dev,
                                                  uint32_t n_host, int shift, int bits,
-                                                 uint32_t* __restrict__ counts) {
+                                                 uint32_t* __restrict__ counts, RsGate gate) {
     constexpr int kRsSub = 256 * kRsItems;
     __shared__ uint32_t h[kRsBins];
     const uint32_t n = n_dev ? *n_dev : n_host, bins = 1u << bits, mask = bins - 1u;
+    if (n < gate.lo || n > gate.hi) return;
     h[threadIdx.x] = 0;
     __syncthreads();
     uint32_t lo, hi;
@@ -314,9 +324,13 @@ __global__ __launch_bounds__(256) void k_rs_hist(const uint32_t* __restrict__ ke
 
 // One block per digit: exclusive scan of counts[d * grid .. + grid) in place;
 // totals[d] = the row's sum.
+// grid_big (with n_dev): the grid of the large form, used when the device
+// key count exceeds kRsSplitKeys.
 __global__ __launch_bounds__(256) void k_rs_scan(uint32_t* __restrict__ counts, uint32_t grid,
-                                                 uint32_t* __restrict__ totals) {
+                                                 uint32_t* __restrict__ totals, uint32_t grid_big,
+                                                 const uint32_t* __restrict__ n_dev) {
     __shared__ uint32_t lds[4];
+    if (n_dev && *n_dev > kRsSplitKeys) grid = grid_big;
     uint32_t* row = counts + (uint64_t)blockIdx.x * grid;
     const uint32_t per = (grid + 255) / 256, b0 = threadIdx.x * per;
     uint32_t v[kRsGrid / 256];
@@ -341,7 +355,7 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const uint32_t* __restrict__
                                                     uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                     const uint32_t* __restrict__ n_dev, uint32_t n_host, int shift,
                                                     int bits, const uint32_t* __restrict__ counts,
-                                                    const uint32_t* __restrict__ totals) {
+                                                    const uint32_t* __restrict__ totals, RsGate gate) {
     constexpr int kRsSub = 256 * kRsItems;
     __shared__ uint32_t s_keys[kRsSub];
     __shared__ uint32_t s_vals[kRsSub];
@@ -351,6 +365,7 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const uint32_t* __restrict__
     __shared__ uint32_t run[kRsBins];
     __shared__ uint32_t lds[4];
     const uint32_t n = n_dev ? *n_dev : n_host, bins = 1u << bits, mask = bins - 1u;
+    if (n < gate.lo || n > gate.hi) return;
     const bool has_v = vout != nullptr;  // keys only (a key that carries its value) when null
     uint32_t lo, hi;
     chunk_of(n, gridDim.x, blockIdx.x, kRsSub, &lo, &hi);
@@ -459,7 +474,7 @@ __global__ __launch_bounds__(256, (kHasV || kBits > 6) ? 2 : 4) void k_rs_scatte
                                                         uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                         const uint32_t* __restrict__ n_dev, uint32_t n_host,
                                                         int shift, int bits, const uint32_t* __restrict__ counts,
-                                                        const uint32_t* __restrict__ totals) {
+                                                        const uint32_t* __restrict__ totals, RsGate gate) {
     constexpr int kItems = kRsItemsBig;
     constexpr int kSub = 256 * kItems;
     constexpr int kBins = 1 << kBits;
@@ -477,6 +492,7 @@ __global__ __launch_bounds__(256, (kHasV || kBits > 6) ? 2 : 4) void k_rs_scatte
     uint32_t* s_keys = s_buf;
     uint32_t* s_vals = s_buf + (kHasV ? kSub : 0);  // not touched without values
     const uint32_t n = n_dev ? *n_dev : n_host, bins = 1u << bits, mask = bins - 1u;
+    if (n < gate.lo || n > gate.hi) return;
     constexpr bool has_v = kHasV;  // false: keys only (a key that carries its value)
     uint32_t lo, hi;
     chunk_of(n, gridDim.x, blockIdx.x, kSub, &lo, &hi);
@@ -617,13 +633,17 @@ hipError_t radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, co
     if (n_cap <= 0 || key_bits <= 0) return hipSuccess;
     if (n_cap > 0xFFFFFFFFll) return hipErrorInvalidValue;
     // Small sorts (expected keys per block of the full grid below 4096):
-    // 1024-key sub-chunks.
-    const int64_t n_exp = n_hint > 0 && n_hint < n_cap ? n_hint : n_cap;
+    // 1024-key sub-chunks.  An unknown count (n_hint < 0) that may exceed
+    // kRsSplitKeys launches both forms, gated on the device count.
+    const bool both = n_hint < 0 && n_dev && n_cap > (int64_t)kRsSplitKeys;
+    const int64_t n_exp = n_hint > 0 && n_hint < n_cap ? n_hint : n_hint < 0 ? 1 : n_cap;
     const bool small = n_exp <= (int64_t)kRsGrid * 256 * kRsItemsSmall;
-    const int items = small ? kRsItemsSmall : kRsItemsBig;
-    const uint32_t grid = small ? kRsSmallGrid : rs_grid(n_cap, items);
+    const bool big = both || !small;
+    const uint32_t grid_small = kRsSmallGrid, grid_big = rs_grid(n_cap, kRsItemsBig);
+    const RsGate g_small = both ? RsGate{0u, kRsSplitKeys} : kRsAlways;
+    const RsGate g_big = both ? RsGate{kRsSplitKeys + 1u, 0xFFFFFFFFu} : kRsAlways;
     uint32_t* counts = (uint32_t*)tmp;
-    uint32_t* totals = counts + (size_t)kRsBins * grid;
+    uint32_t* totals = counts + (size_t)kRsBins * kRsGrid;  // past the largest count table
     const int passes = (key_bits + kRsMaxBits - 1) / kRsMaxBits;
     const int per = (key_bits + passes - 1) / passes;
     // The counter-ranked scatter loads 16-byte vectors.
@@ -636,30 +656,33 @@ hipError_t radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, co
     for (int shift = key_shift; shift < key_shift + key_bits; shift += per) {
         const int bits = key_shift + key_bits - shift < per ? key_shift + key_bits - shift : per;
         if (small)
-            hipLaunchKernelGGL(k_rs_hist<kRsItemsSmall>, dim3(grid), dim3(256), 0, s, ki, n_dev, (uint32_t)n_cap, shift,
-                               bits, counts);
-        else
-            hipLaunchKernelGGL(k_rs_hist<kRsItemsBig>, dim3(grid), dim3(256), 0, s, ki, n_dev, (uint32_t)n_cap, shift,
-                               bits, counts);
-        hipLaunchKernelGGL(k_rs_scan, dim3(1u << bits), dim3(256), 0, s, counts, grid, totals);
+            hipLaunchKernelGGL(k_rs_hist<kRsItemsSmall>, dim3(grid_small), dim3(256), 0, s, ki, n_dev,
+                               (uint32_t)n_cap, shift, bits, counts, g_small);
+        if (big)
+            hipLaunchKernelGGL(k_rs_hist<kRsItemsBig>, dim3(grid_big), dim3(256), 0, s, ki, n_dev, (uint32_t)n_cap,
+                               shift, bits, counts, g_big);
+        hipLaunchKernelGGL(k_rs_scan, dim3(1u << bits), dim3(256), 0, s, counts, small ? grid_small : grid_big, totals,
+                           grid_big, both ? n_dev : nullptr);
         if (small)
-            hipLaunchKernelGGL(k_rs_scatter<kRsItemsSmall>, dim3(grid), dim3(256), 0, s, ki, vi, ko, vo, n_dev,
-                               (uint32_t)n_cap, shift, bits, counts, totals);
-        else if (bits <= 6 && aligned && vo)
-            hipLaunchKernelGGL((k_rs_scatter_cnt<true, 6>), dim3(grid), dim3(256), 0, s, ki, vi, ko, vo, n_dev,
-                               (uint32_t)n_cap, shift, bits, counts, totals);
-        else if (bits <= 6 && aligned)
-            hipLaunchKernelGGL((k_rs_scatter_cnt<false, 6>), dim3(grid), dim3(256), 0, s, ki, vi, ko, vo, n_dev,
-                               (uint32_t)n_cap, shift, bits, counts, totals);
-        else if (bits <= kRsCntMaxBits && aligned && vo)
-            hipLaunchKernelGGL((k_rs_scatter_cnt<true, 7>), dim3(grid), dim3(256), 0, s, ki, vi, ko, vo, n_dev,
-                               (uint32_t)n_cap, shift, bits, counts, totals);
-        else if (bits <= kRsCntMaxBits && aligned)
-            hipLaunchKernelGGL((k_rs_scatter_cnt<false, 7>), dim3(grid), dim3(256), 0, s, ki, vi, ko, vo, n_dev,
-                               (uint32_t)n_cap, shift, bits, counts, totals);
-        else
-            hipLaunchKernelGGL(k_rs_scatter<kRsItemsBig>, dim3(grid), dim3(256), 0, s, ki, vi, ko, vo, n_dev,
-                               (uint32_t)n_cap, shift, bits, counts, totals);
+            hipLaunchKernelGGL(k_rs_scatter<kRsItemsSmall>, dim3(grid_small), dim3(256), 0, s, ki, vi, ko, vo, n_dev,
+                               (uint32_t)n_cap, shift, bits, counts, totals, g_small);
+        if (!big) {
+        } else if (bits <= 6 && aligned && vo) {
+            hipLaunchKernelGGL((k_rs_scatter_cnt<true, 6>), dim3(grid_big), dim3(256), 0, s, ki, vi, ko, vo, n_dev,
+                               (uint32_t)n_cap, shift, bits, counts, totals, g_big);
+        } else if (bits <= 6 && aligned) {
+            hipLaunchKernelGGL((k_rs_scatter_cnt<false, 6>), dim3(grid_big), dim3(256), 0, s, ki, vi, ko, vo, n_dev,
+                               (uint32_t)n_cap, shift, bits, counts, totals, g_big);
+        } else if (bits <= kRsCntMaxBits && aligned && vo) {
+            hipLaunchKernelGGL((k_rs_scatter_cnt<true, 7>), dim3(grid_big), dim3(256), 0, s, ki, vi, ko, vo, n_dev,
+                               (uint32_t)n_cap, shift, bits, counts, totals, g_big);
+        } else if (bits <= kRsCntMaxBits && aligned) {
+            hipLaunchKernelGGL((k_rs_scatter_cnt<false, 7>), dim3(grid_big), dim3(256), 0, s, ki, vi, ko, vo, n_dev,
+                               (uint32_t)n_cap, shift, bits, counts, totals, g_big);
+        } else {
+            hipLaunchKernelGGL(k_rs_scatter<kRsItemsBig>, dim3(grid_big), dim3(256), 0, s, ki, vi, ko, vo, n_dev,
+                               (uint32_t)n_cap, shift, bits, counts, totals, g_big);
+        }
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         cur_b = !cur_b;

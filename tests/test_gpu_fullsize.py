@@ -70,7 +70,10 @@ def check_pixels(rgb, a, z_or_d, ref, where, proxy):
     assert not loose.any()
 
 
-@pytest.mark.parametrize("name,pose,n_dom,n_roi", [("sphere800", 5, 500, 700), ("unbounded1600", 9, 300, 500)])
+# unbounded1600 pose 29: about 27M keys in the ROI pass, whose sort then
+# takes its large form on the device's count.
+@pytest.mark.parametrize("name,pose,n_dom,n_roi", [("sphere800", 5, 500, 700), ("unbounded1600", 9, 300, 500),
+                                                   ("unbounded1600", 29, 300, 500)])
 def test_render_stereo_full_size(ctx, oracle, name, pose, n_dom, n_roi):
     log(f"full-size stereo {name} pose {pose}")
     sc, cams, b = synth.WORKLOADS[name](0)
