@@ -69,8 +69,8 @@ FLOPS_PER_PAIR = 38
 # poses, FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (factors from a 512 MiB copy),
 # each valid while raster.hip and bgs_api.hip hash (sha1 over the two files
 # in that order) to its value.
-BLEND_TRAFFIC = {"sphere800": {"source_sha1": "29df4f657463febb71b9fede550a6185fb161c7a", "bytes": 126.0e6},
-                 "unbounded1600": {"source_sha1": "29df4f657463febb71b9fede550a6185fb161c7a", "bytes": 131.8e6}}
+BLEND_TRAFFIC = {"sphere800": {"source_sha1": "0af4458268b320b8d65f9a62d78b33d448c618fd", "bytes": 126.9e6},
+                 "unbounded1600": {"source_sha1": "0af4458268b320b8d65f9a62d78b33d448c618fd", "bytes": 131.8e6}}
 
 
 def log(*a):

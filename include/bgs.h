@@ -199,7 +199,7 @@ BGS_API int32_t bgs_ctx_set_count_pairs(bgs_ctx* ctx, int32_t count);
  * that segment, in order, from its exact state (unless the segment's own
  * walk started from that state).  Lists are continued only on images of at
  * most 4096 16x16 tiles (larger ones fill the GPU with their tiles alone).
- * Defaults 1024, 128, 64, 0, 256.  BGS_ERR_INVALID_ARG for a negative cap or far, or seg_len < 1. */
+ * Defaults 1024, 32, 32, 0, 256.  BGS_ERR_INVALID_ARG for a negative cap or far, or seg_len < 1. */
 BGS_API int32_t bgs_ctx_set_blend_split(bgs_ctx* ctx, int32_t cap_dom, int32_t cap_roi, int32_t seg_len,
                                         int32_t far_dom, int32_t far_roi);
 

@@ -199,7 +199,7 @@ class Context:
     def set_count_pairs(self, on: bool):
         self._check(self.L.bgs_ctx_set_count_pairs(self.h, int(bool(on))))
 
-    def set_blend_split(self, cap_dom: int = 1024, cap_roi: int = 128, seg_len: int = 64, far_dom: int = 0,
+    def set_blend_split(self, cap_dom: int = 1024, cap_roi: int = 32, seg_len: int = 32, far_dom: int = 0,
                         far_roi: int = 256):
         """Records a tile composites before the rest of its list may be split
         into segments (dominant / full renders, ROI patch; 0 = never), the

@@ -26,7 +26,7 @@ struct bgs_ctx {
     uint32_t timing = 0;  // bit i: time stage i
     // Blend continuation: records a tile composites before the rest of its
     // list is split into segments (0: never), per pass, and the segment length.
-    uint32_t cap_dom = 1024, cap_roi = 128, seg_len = 64, far_dom = 0, far_roi = 256;
+    uint32_t cap_dom = 1024, cap_roi = 32, seg_len = 32, far_dom = 0, far_roi = 256;
     // Stage timing: a ring of event pairs, one set per frame, so frames can
     // be issued back to back; a set is folded into the totals when the ring
     // comes round to it again (its frame is long done by then) or on collect.

@@ -1162,9 +1162,12 @@ constexpr int kTrip = 4;                // records per trip of the walk
 constexpr int kDummy = kBatch;          // LDS record index of the zero record
 constexpr int kListLen = kBatch + 4;    // per-wave hit list, with padding
 // Continuation segments are walked in kRounds rounds: round r takes the
-// segments [round_lo(r), round_lo(r + 1)) of every continued tile.
-constexpr int kRounds = 2;
-__host__ __device__ constexpr uint32_t round_lo(int r) { return r <= 0 ? 0u : r == 1 ? 4u : kContMaxSeg; }
+// segments [round_lo(r), round_lo(r + 1)) of every continued tile.  One
+// round: a second one (the later segments walked from the exact
+// transmittance after the first four) saved speculative work but cost a
+// launch of latency (800x600 frames: 1.5% slower, 256x256 2%).
+constexpr int kRounds = 1;
+__host__ __device__ constexpr uint32_t round_lo(int r) { return r <= 0 ? 0u : kContMaxSeg; }
 static_assert(round_lo(kRounds) == kContMaxSeg, "the rounds cover every segment");
 constexpr uint32_t kChainBatch = 8;     // earlier segments' parts loaded together when chaining
 
@@ -1592,11 +1595,10 @@ __device__ __forceinline__ void item_segment(const uint4& d, uint32_t k, uint32_
 }
 
 // Round 0 walks the first segments of every continued tile from the
-// transmittance T1 after the capped walk.  Each later round walks its
-// segments from every pixel's exact transmittance after the segments of the
-// rounds before (a tighter bound than T1), and only for the pixels that get
-// through them: for tiles whose pixels stop soon after the cap, the later
-// rounds have no work.
+// transmittance T1 after the capped walk.  Each later round (if kRounds > 1)
+// walks its segments from every pixel's exact transmittance after the
+// segments of the rounds before (a tighter bound than T1), and only for the
+// pixels that get through them.
 template <bool kCount>
 __global__ __launch_bounds__(256) void k_blend_seg(const SurfelRec* __restrict__ recs,
                                                    const uint32_t* __restrict__ vals,
