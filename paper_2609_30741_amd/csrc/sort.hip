@@ -291,18 +291,19 @@ __device__ inline void chunk_of(uint32_t n, uint32_t grid, uint32_t b, uint32_t 
     *hi = (uint32_t)min<uint64_t>(l + c, n);
 }
 
+// The kernels' bodies take the grid they partition the keys over (G; the
+// block id is blockIdx.x < G) and their LDS as one array, so that one
+// kernel can run either form on a count known only on the device.
 template <int kRsItems>
-__global__ __launch_bounds__(256) void k_rs_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_dev,
-                                                 uint32_t n_host, int shift, int bits,
-                                                 uint32_t* __restrict__ counts, RsGate gate) {
+__device__ __forceinline__ void rs_hist_body(const uint32_t* __restrict__ keys, uint32_t n, int shift, int bits,
+                                             uint32_t* __restrict__ counts, uint32_t G, uint32_t* smem) {
     constexpr int kRsSub = 256 * kRsItems;
-    __shared__ uint32_t h[kRsBins];
-    const uint32_t n = n_dev ? *n_dev : n_host, bins = 1u << bits, mask = bins - 1u;
-    if (n < gate.lo || n > gate.hi) return;
+    uint32_t* h = smem;  // kRsBins words
+    const uint32_t bins = 1u << bits, mask = bins - 1u;
     h[threadIdx.x] = 0;
     __syncthreads();
     uint32_t lo, hi;
-    chunk_of(n, gridDim.x, blockIdx.x, kRsSub, &lo, &hi);
+    chunk_of(n, G, blockIdx.x, kRsSub, &lo, &hi);
     for (uint64_t sub = lo; sub < hi; sub += kRsSub) {
         uint32_t k[kRsItems];
 #pragma unroll
@@ -319,7 +320,17 @@ __global__ __launch_bounds__(256) void k_rs_hist(const uint32_t* __restrict__ ke
         }
     }
     __syncthreads();
-    if (threadIdx.x < bins) counts[(uint64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
+    if (threadIdx.x < bins) counts[(uint64_t)threadIdx.x * G + blockIdx.x] = h[threadIdx.x];
+}
+
+template <int kRsItems>
+__global__ __launch_bounds__(256) void k_rs_hist(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ n_dev,
+                                                 uint32_t n_host, int shift, int bits,
+                                                 uint32_t* __restrict__ counts, RsGate gate) {
+    __shared__ uint32_t smem[kRsBins];
+    const uint32_t n = n_dev ? *n_dev : n_host;
+    if (n < gate.lo || n > gate.hi) return;
+    rs_hist_body<kRsItems>(keys, n, shift, bits, counts, gridDim.x, smem);
 }
 
 // One block per digit: exclusive scan of counts[d * grid .. + grid) in place;
@@ -351,24 +362,26 @@ __global__ __launch_bounds__(256) void k_rs_scan(uint32_t* __restrict__ counts, 
 }
 
 template <int kRsItems>
-__global__ __launch_bounds__(256) void k_rs_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
-                                                    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                    const uint32_t* __restrict__ n_dev, uint32_t n_host, int shift,
-                                                    int bits, const uint32_t* __restrict__ counts,
-                                                    const uint32_t* __restrict__ totals, RsGate gate) {
+__host__ __device__ constexpr int rs_scatter_lds() { return 2 * 256 * kRsItems + 7 * kRsBins + 4; }
+
+template <int kRsItems>
+__device__ __forceinline__ void rs_scatter_body(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                uint32_t* __restrict__ kout, uint32_t* __restrict__ vout, uint32_t n,
+                                                int shift, int bits, const uint32_t* __restrict__ counts,
+                                                const uint32_t* __restrict__ totals, uint32_t G, uint32_t* smem) {
     constexpr int kRsSub = 256 * kRsItems;
-    __shared__ uint32_t s_keys[kRsSub];
-    __shared__ uint32_t s_vals[kRsSub];
-    __shared__ uint32_t cnt[4][kRsBins];
-    __shared__ uint32_t dstart[kRsBins];
-    __shared__ uint32_t gbase[kRsBins];
-    __shared__ uint32_t run[kRsBins];
-    __shared__ uint32_t lds[4];
-    const uint32_t n = n_dev ? *n_dev : n_host, bins = 1u << bits, mask = bins - 1u;
-    if (n < gate.lo || n > gate.hi) return;
+    uint32_t* s_keys = smem;
+    uint32_t* s_vals = s_keys + kRsSub;
+    uint32_t* cnt0 = s_vals + kRsSub;  // [4][kRsBins]
+    uint32_t* dstart = cnt0 + 4 * kRsBins;
+    uint32_t* gbase = dstart + kRsBins;
+    uint32_t* run = gbase + kRsBins;
+    uint32_t* lds = run + kRsBins;
+    const auto cnt = [&](uint32_t w) { return cnt0 + w * kRsBins; };
+    const uint32_t bins = 1u << bits, mask = bins - 1u;
     const bool has_v = vout != nullptr;  // keys only (a key that carries its value) when null
     uint32_t lo, hi;
-    chunk_of(n, gridDim.x, blockIdx.x, kRsSub, &lo, &hi);
+    chunk_of(n, G, blockIdx.x, kRsSub, &lo, &hi);
     if (lo >= hi) return;
     const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
     const uint64_t lt = (1ull << lane) - 1ull;
@@ -377,9 +390,9 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const uint32_t* __restrict__
         // run[d] = (keys of smaller digits) + (keys of digit d in earlier blocks).
         const uint32_t t = dt < bins ? totals[dt] : 0u;
         const uint32_t acc = block_excl_scan(t, lds, nullptr);
-        if (dt < bins) run[dt] = acc + counts[(uint64_t)dt * gridDim.x + blockIdx.x];
+        if (dt < bins) run[dt] = acc + counts[(uint64_t)dt * G + blockIdx.x];
 #pragma unroll
-        for (int w = 0; w < 4; ++w) cnt[w][dt] = 0;
+        for (int w = 0; w < 4; ++w) cnt(w)[dt] = 0;
     }
     __syncthreads();
     for (uint64_t sub = lo; sub < hi; sub += kRsSub) {
@@ -397,21 +410,21 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const uint32_t* __restrict__
             const bool ok = i < hi;
             const uint32_t d = (k[it] >> shift) & mask;
             const uint64_t peers = match_digit(d, __ballot(ok), bits);
-            const uint32_t c = ok ? cnt[wave][d] : 0u;
+            const uint32_t c = ok ? cnt(wave)[d] : 0u;
             r[it] = ok ? c + (uint32_t)__popcll(peers & lt) : 0xFFFFFFFFu;
             __builtin_amdgcn_wave_barrier();
-            if (ok && (peers & lt) == 0) cnt[wave][d] = c + (uint32_t)__popcll(peers);
+            if (ok && (peers & lt) == 0) cnt(wave)[d] = c + (uint32_t)__popcll(peers);
             __builtin_amdgcn_wave_barrier();
         }
         __syncthreads();
         {
-            const uint32_t c0 = cnt[0][dt], c1 = cnt[1][dt], c2 = cnt[2][dt], c3 = cnt[3][dt];
+            const uint32_t c0 = cnt(0)[dt], c1 = cnt(1)[dt], c2 = cnt(2)[dt], c3 = cnt(3)[dt];
             const uint32_t tot = c0 + c1 + c2 + c3;
             const uint32_t st = block_excl_scan(tot, lds, nullptr);
-            cnt[0][dt] = st;
-            cnt[1][dt] = st + c0;
-            cnt[2][dt] = st + c0 + c1;
-            cnt[3][dt] = st + c0 + c1 + c2;
+            cnt(0)[dt] = st;
+            cnt(1)[dt] = st + c0;
+            cnt(2)[dt] = st + c0 + c1;
+            cnt(3)[dt] = st + c0 + c1 + c2;
             dstart[dt] = st;
             if (dt < bins) {
                 gbase[dt] = run[dt];
@@ -422,7 +435,7 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const uint32_t* __restrict__
 #pragma unroll
         for (int it = 0; it < kRsItems; ++it) {
             if (r[it] != 0xFFFFFFFFu) {
-                const uint32_t lp = cnt[wave][(k[it] >> shift) & mask] + r[it];
+                const uint32_t lp = cnt(wave)[(k[it] >> shift) & mask] + r[it];
                 s_keys[lp] = k[it];
                 if (has_v) s_vals[lp] = v[it];
             }
@@ -440,9 +453,21 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const uint32_t* __restrict__
         }
         __syncthreads();
 #pragma unroll
-        for (int w = 0; w < 4; ++w) cnt[w][dt] = 0;
+        for (int w = 0; w < 4; ++w) cnt(w)[dt] = 0;
         __syncthreads();
     }
+}
+
+template <int kRsItems>
+__global__ __launch_bounds__(256) void k_rs_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                    const uint32_t* __restrict__ n_dev, uint32_t n_host, int shift,
+                                                    int bits, const uint32_t* __restrict__ counts,
+                                                    const uint32_t* __restrict__ totals, RsGate gate) {
+    __shared__ uint32_t smem[rs_scatter_lds<kRsItems>()];
+    const uint32_t n = n_dev ? *n_dev : n_host;
+    if (n < gate.lo || n > gate.hi) return;
+    rs_scatter_body<kRsItems>(kin, vin, kout, vout, n, shift, bits, counts, totals, gridDim.x, smem);
 }
 
 // k_rs_scatter for digits of at most 7 bits and 6144-key sub-chunks, with
@@ -468,41 +493,45 @@ static_assert(kRsItemsBig % 4 == 0, "a thread's keys are loaded as 16-byte vecto
 
 __device__ __forceinline__ uint32_t cnt_slot(uint32_t w) { return w + (w >> 5); }
 
+// The counters, then the sub-chunk's keys (and values): keys alone need no
+// more LDS than the 6-bit counters, so four blocks share a CU instead of
+// three.
 template <bool kHasV, int kBits>
-__global__ __launch_bounds__(256, (kHasV || kBits > 6) ? 2 : 4) void k_rs_scatter_cnt(const uint32_t* __restrict__ kin,
-                                                        const uint32_t* __restrict__ vin,
-                                                        uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                        const uint32_t* __restrict__ n_dev, uint32_t n_host,
-                                                        int shift, int bits, const uint32_t* __restrict__ counts,
-                                                        const uint32_t* __restrict__ totals, RsGate gate) {
+__host__ __device__ constexpr int rs_cnt_buf() {
+    return rs_cnt_lds(kBits) > (kHasV ? 2 : 1) * 256 * kRsItemsBig ? rs_cnt_lds(kBits)
+                                                                   : (kHasV ? 2 : 1) * 256 * kRsItemsBig;
+}
+template <bool kHasV, int kBits>
+__host__ __device__ constexpr int rs_scatter_cnt_lds() { return rs_cnt_buf<kHasV, kBits>() + 3 * (1 << kBits) + 1 + 4; }
+
+template <bool kHasV, int kBits>
+__device__ __forceinline__ void rs_scatter_cnt_body(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                    uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                    uint32_t n, int shift, int bits,
+                                                    const uint32_t* __restrict__ counts,
+                                                    const uint32_t* __restrict__ totals, uint32_t G, uint32_t* smem) {
     constexpr int kItems = kRsItemsBig;
     constexpr int kSub = 256 * kItems;
     constexpr int kBins = 1 << kBits;
-    // The counters, then the sub-chunk's keys (and values): keys alone need
-    // no more LDS than the 6-bit counters, so four blocks share a CU instead
-    // of three.
-    constexpr int kLds = rs_cnt_lds(kBits);
-    constexpr int kData = (kHasV ? 2 : 1) * kSub;
-    constexpr int kBuf = kLds > kData ? kLds : kData;
-    __shared__ uint32_t s_buf[kBuf];
-    __shared__ uint32_t dstart[kBins + 1];
-    __shared__ uint32_t gbase[kBins];
-    __shared__ uint32_t run[kBins];
-    __shared__ uint32_t lds[4];
+    constexpr int kBuf = rs_cnt_buf<kHasV, kBits>();
+    uint32_t* s_buf = smem;
+    uint32_t* dstart = s_buf + kBuf;  // kBins + 1
+    uint32_t* gbase = dstart + kBins + 1;
+    uint32_t* run = gbase + kBins;
+    uint32_t* lds = run + kBins;
     uint32_t* s_keys = s_buf;
     uint32_t* s_vals = s_buf + (kHasV ? kSub : 0);  // not touched without values
-    const uint32_t n = n_dev ? *n_dev : n_host, bins = 1u << bits, mask = bins - 1u;
-    if (n < gate.lo || n > gate.hi) return;
+    const uint32_t bins = 1u << bits, mask = bins - 1u;
     constexpr bool has_v = kHasV;  // false: keys only (a key that carries its value)
     uint32_t lo, hi;
-    chunk_of(n, gridDim.x, blockIdx.x, kSub, &lo, &hi);
+    chunk_of(n, G, blockIdx.x, kSub, &lo, &hi);
     if (lo >= hi) return;
     const uint32_t t = threadIdx.x;
     {
         // run[d] = (keys of smaller digits) + (keys of digit d in earlier blocks).
         const uint32_t tv = t < bins ? totals[t] : 0u;
         const uint32_t acc = block_excl_scan(tv, lds, nullptr);
-        if (t < bins) run[t] = acc + counts[(uint64_t)t * gridDim.x + blockIdx.x];
+        if (t < bins) run[t] = acc + counts[(uint64_t)t * G + blockIdx.x];
     }
     const uint32_t rake = bins / 2;         // counter words per thread (bins * 256 / 2 words over 256 threads)
     const uint32_t nclear = cnt_slot(bins * 128u);
@@ -614,6 +643,52 @@ __global__ __launch_bounds__(256, (kHasV || kBits > 6) ? 2 : 4) void k_rs_scatte
     }
 }
 
+template <bool kHasV, int kBits>
+__global__ __launch_bounds__(256, (kHasV || kBits > 6) ? 2 : 4) void k_rs_scatter_cnt(const uint32_t* __restrict__ kin,
+                                                        const uint32_t* __restrict__ vin,
+                                                        uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                        const uint32_t* __restrict__ n_dev, uint32_t n_host,
+                                                        int shift, int bits, const uint32_t* __restrict__ counts,
+                                                        const uint32_t* __restrict__ totals, RsGate gate) {
+    __shared__ uint32_t smem[rs_scatter_cnt_lds<kHasV, kBits>()];
+    const uint32_t n = n_dev ? *n_dev : n_host;
+    if (n < gate.lo || n > gate.hi) return;
+    rs_scatter_cnt_body<kHasV, kBits>(kin, vin, kout, vout, n, shift, bits, counts, totals, gridDim.x, smem);
+}
+
+// Either form of a pass on the device count: the small form (1024-key
+// sub-chunks, ballot ranks, g_small blocks) up to kRsSplitKeys keys, the
+// counter-ranked form (g_big blocks) above.  One launch of max(g_small,
+// g_big) blocks each; blocks past the chosen form's grid return.
+__global__ __launch_bounds__(256) void k_rs_hist_dual(const uint32_t* __restrict__ keys,
+                                                      const uint32_t* __restrict__ n_dev, int shift, int bits,
+                                                      uint32_t* __restrict__ counts, uint32_t g_small, uint32_t g_big) {
+    __shared__ uint32_t smem[kRsBins];
+    const uint32_t n = *n_dev;
+    if (n <= kRsSplitKeys) {
+        if (blockIdx.x < g_small) rs_hist_body<kRsItemsSmall>(keys, n, shift, bits, counts, g_small, smem);
+    } else if (blockIdx.x < g_big) {
+        rs_hist_body<kRsItemsBig>(keys, n, shift, bits, counts, g_big, smem);
+    }
+}
+
+template <bool kHasV, int kBits>
+__global__ __launch_bounds__(256, (kHasV || kBits > 6) ? 2 : 4) void k_rs_scatter_dual(
+    const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint32_t* __restrict__ kout,
+    uint32_t* __restrict__ vout, const uint32_t* __restrict__ n_dev, int shift, int bits,
+    const uint32_t* __restrict__ counts, const uint32_t* __restrict__ totals, uint32_t g_small, uint32_t g_big) {
+    constexpr int kSmall = rs_scatter_lds<kRsItemsSmall>(), kBig = rs_scatter_cnt_lds<kHasV, kBits>();
+    __shared__ uint32_t smem[kSmall > kBig ? kSmall : kBig];
+    const uint32_t n = *n_dev;
+    if (n <= kRsSplitKeys) {
+        if (blockIdx.x < g_small)
+            rs_scatter_body<kRsItemsSmall>(kin, vin, kout, kHasV ? vout : nullptr, n, shift, bits, counts, totals,
+                                           g_small, smem);
+    } else if (blockIdx.x < g_big) {
+        rs_scatter_cnt_body<kHasV, kBits>(kin, vin, kout, vout, n, shift, bits, counts, totals, g_big, smem);
+    }
+}
+
 uint32_t rs_grid(int64_t n_cap, int items) {
     const int64_t g = ceil_div(n_cap > 0 ? n_cap : 1, 256 * items);
     return (uint32_t)(g < kRsGrid ? g : kRsGrid);
@@ -655,6 +730,36 @@ hipError_t radix_sort(uint32_t* ka, uint32_t* va, uint32_t* kb, uint32_t* vb, co
     if (key_shift < 0 || key_shift + key_bits > 32) return hipErrorInvalidValue;
     for (int shift = key_shift; shift < key_shift + key_bits; shift += per) {
         const int bits = key_shift + key_bits - shift < per ? key_shift + key_bits - shift : per;
+        if (both && bits <= kRsCntMaxBits && aligned) {
+            // One launch per kernel, the form chosen by each block from the
+            // device count.
+            const dim3 gd(grid_small > grid_big ? grid_small : grid_big);
+            hipLaunchKernelGGL(k_rs_hist_dual, gd, dim3(256), 0, s, ki, n_dev, shift, bits, counts, grid_small,
+                               grid_big);
+            hipLaunchKernelGGL(k_rs_scan, dim3(1u << bits), dim3(256), 0, s, counts, grid_small, totals, grid_big,
+                               n_dev);
+            if (vo && bits <= 6)
+                hipLaunchKernelGGL((k_rs_scatter_dual<true, 6>), gd, dim3(256), 0, s, ki, vi, ko, vo, n_dev, shift, bits,
+                                   counts, totals, grid_small, grid_big);
+            else if (vo)
+                hipLaunchKernelGGL((k_rs_scatter_dual<true, 7>), gd, dim3(256), 0, s, ki, vi, ko, vo, n_dev, shift, bits,
+                                   counts, totals, grid_small, grid_big);
+            else if (bits <= 6)
+                hipLaunchKernelGGL((k_rs_scatter_dual<false, 6>), gd, dim3(256), 0, s, ki, vi, ko, vo, n_dev, shift,
+                                   bits, counts, totals, grid_small, grid_big);
+            else
+                hipLaunchKernelGGL((k_rs_scatter_dual<false, 7>), gd, dim3(256), 0, s, ki, vi, ko, vo, n_dev, shift,
+                                   bits, counts, totals, grid_small, grid_big);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            cur_b = !cur_b;
+            if (cur_b) {
+                ki = kb; vi = vb; ko = ka; vo = va;
+            } else {
+                ki = ka; vi = va; ko = kb; vo = vb;
+            }
+            continue;
+        }
         if (small)
             hipLaunchKernelGGL(k_rs_hist<kRsItemsSmall>, dim3(grid_small), dim3(256), 0, s, ki, n_dev,
                                (uint32_t)n_cap, shift, bits, counts, g_small);
