@@ -228,7 +228,8 @@ hipError_t exclusive_scan(const uint32_t* in, const uint32_t* idx, uint32_t* out
 // capacity (at most kRsGrid blocks; always kRsSmallGrid for small sorts,
 // which use 1024-key sub-chunks instead of 6144); block b owns the contiguous
 // chunk [b C, b C + C) of the *n_dev keys, C = n / grid rounded up to 256.
-// A pass is three launches:
+// A pass is three launches (their bodies are device functions taking the
+// grid and the LDS, so one launch can run either form):
 //   1. k_rs_hist: per-block digit counts (LDS atomics), stored
 //      digit-major: counts[d * grid + b].
 //   2. k_rs_scan: one block per digit scans its row over the blocks and
@@ -258,9 +259,12 @@ constexpr int kRsSmallGrid = 512;
 // sort's.
 constexpr int kRsItemsBig = 24, kRsItemsSmall = 4;
 // A sort whose key count is known only on the device (an ROI pass's) runs
-// both forms and each form's kernels return at once unless the count is
-// in their range: the small form up to kRsSplitKeys keys (2.8M keys: 74 us
-// against 87 us for the large form), the large form above.
+// each pass as one histogram and one scatter launch whose blocks take the
+// small form up to kRsSplitKeys keys (2.8M keys: 74 us against 87 us for
+// the large form) and the large form above (k_rs_hist_dual,
+// k_rs_scatter_dual).  Digits of more than 7 bits, or unaligned buffers,
+// launch both forms' kernels instead, each returning at once unless the
+// count is in its range.
 constexpr uint32_t kRsSplitKeys = 4u << 20;
 struct RsGate {
     uint32_t lo, hi;  // the kernel runs iff lo <= n <= hi
