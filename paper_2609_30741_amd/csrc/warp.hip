@@ -725,9 +725,9 @@ __global__ __launch_bounds__(256) void k_gap_pass(int W, int H, int pass, float*
 }
 
 // The same gap passes and the center mask in one kernel: a block loads its
-// 64 x kBandRows tile plus a halo of `passes` pixels into LDS, runs the
+// 64 x kBandRows tile plus a halo of kH >= passes pixels into LDS, runs the
 // passes there (pass j is final for pixels at least j from the halo's
-// edge, which after all passes is the tile), and writes the tile's filled
+// edge, which after all passes includes the tile), and writes the tile's filled
 // pixels, tags and center mask.  Per pixel it computes exactly what
 // k_tag_init, k_gap_pass and k_center_mask compute.  It also writes the
 // ROI tile mask's edge-box tiles (the center boxes are added after it).
