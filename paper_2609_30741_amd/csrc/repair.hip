@@ -1,10 +1,11 @@
 // Learned gap/edge repair network: inference and training kernels.
 //
 // 3x3 convolutions run as implicit GEMMs on the bf16 matrix cores
-// (v_mfma_f32_16x16x16_bf16, fp32 accumulate).  Forward: rows of the GEMM
+// (v_mfma_f32_16x16x32_bf16, fp32 accumulate).  Forward: rows of the GEMM
 // are output channels (weights packed [cout padded to 16][9][cin padded to
-// 16]), columns are 16 consecutive pixels of one image row, the reduction
-// runs over (tap, input channel).  The input-gradient pass is the same kernel
+// 16], each row padded with zeros to a multiple of 32), columns are 16
+// consecutive pixels of one image row, the reduction runs over (tap, input
+// channel).  The input-gradient pass is the same kernel
 // with the weights transposed and flipped.  The weight gradient is a GEMM
 // over pixels: each block accumulates a slab of rows into per-block
 // partials that a second kernel adds in a fixed order, so results are
@@ -23,6 +24,7 @@
 namespace {
 
 typedef short v4s __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 struct LayerDef {
@@ -48,15 +50,20 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 // Convolution (forward, or input gradient with transposed weights).
 // ---------------------------------------------------------------------------
 struct ConvArgs {
-    const uint16_t* in;
+    const uint16_t* in;  // 4-byte aligned, in_bs even (pixel pairs are loaded as one word)
     int64_t in_bs;
     int cin;
-    const uint16_t* w;  // [pad16(cout)][kpad = 9 * cpad] bf16, k = tap * cpad + ci
-    int kpad;
-    int cpad;  // pad16(cin)
+    // Optional half-resolution source of input channels [0, up_c): read at
+    // (y / 2, x / 2), the nearest 2x upsample, so a decoder's concatenated
+    // input needs no upsampled copy.  Channels [up_c, cin) come from in.
+    const uint16_t* up;
+    int64_t up_bs;
+    int up_c;
+    const uint16_t* w;  // [pad16(cout)][kpad] bf16, k = tap * cpad + ci, zero for k >= 9 cpad
+    int kpad;           // pad32(9 cpad)
     const float* bias;  // may be null
     int cout;
-    uint16_t* out;      // bf16 output, or
+    uint16_t* out;
     float* out_f;       // fp32 output (exactly one is set)
     int64_t out_bs;
     const uint16_t* mask;  // may be null: output zero where mask <= 0
@@ -67,105 +74,148 @@ struct ConvArgs {
 
 // Block: 4 waves, each 16 pixels of rows 2 blockIdx.y and 2 blockIdx.y + 1,
 // x from blockIdx.x * 64 + 16 * wave; blockIdx.z = image * groups + group,
-// a group being up to 64 output channels (four 16-row tiles).  The block
-// first stages input rows 2 blockIdx.y - 1 .. + 2 of every input channel
-// (channels padded to cpad, a multiple of 16, with zeros), x from
-// blockIdx.x * 64 - 1 to + 64 (zero outside the image), in LDS:
-// [cpad][4][66] bf16.  The reduction index is k = tap * cpad + ci, so each
-// 16-deep slice is one tap and 16 channels, a lane's four operands sit at
-// a fixed LDS stride, and one weight operand serves both rows.
-constexpr int kConvCols = 66, kConvRowsOut = 2, kConvRowsIn = kConvRowsOut + 2;
-constexpr int kConvPlane = kConvRowsIn * kConvCols;
+// a group being MT <= 4 16-row tiles of output channels (a last group with
+// fewer real tiles repeats its last weight row and stores only its own).  The block
+// first stages input rows 2 blockIdx.y - 1 .. + 2, x from blockIdx.x * 64 - 2
+// to + 65 (zero outside the image), of every input channel (padded to CPAD,
+// a multiple of 16, with zeros) in LDS, channels innermost: [4][68][CPAD + 8]
+// bf16.  The reduction index is k = tap * CPAD + ci in 32-deep slices of
+// v_mfma_f32_16x16x32_bf16; a lane's eight operands of a slice are eight
+// consecutive channels of one tap, one 16-byte LDS read.  The 8 spare
+// channel slots per pixel make the pixel stride an odd multiple of 16 bytes,
+// so the 16 lanes reading one channel group of 16 consecutive pixels touch
+// distinct banks.
+constexpr int kConvCols = 68, kConvRowsOut = 2, kConvRowsIn = kConvRowsOut + 2;
 
+constexpr int pad32(int v) { return (v + 31) & ~31; }
+constexpr size_t conv_lds_bytes(int cpad) { return (size_t)kConvRowsIn * kConvCols * (cpad + 8) * sizeof(uint16_t); }
+
+template <int CPAD, int MT>
 __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
-    extern __shared__ uint16_t s_in[];
+    constexpr int PS = CPAD + 8;          // staged bf16 per pixel
+    constexpr int G = CPAD / 8;           // 16-byte channel groups per pixel
+    constexpr int SL = pad32(9 * CPAD) / 32;  // reduction slices
+    extern __shared__ uint4 s_raw[];
+    uint16_t* s_in = reinterpret_cast<uint16_t*>(s_raw);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int groups = (a.cout + 63) >> 6;
-    const int y0 = blockIdx.y * kConvRowsOut, b = blockIdx.z / groups, m0 = (blockIdx.z - b * groups) * 4;
+    const int groups = (a.cout + 16 * MT - 1) / (16 * MT);
+    const int y0 = blockIdx.y * kConvRowsOut, b = blockIdx.z / groups, m0 = (blockIdx.z - b * groups) * MT;
     const int xb = blockIdx.x * 64;
-    const int HW = a.H * a.W;
-    const int cpad = a.cpad;
+    const int HW = a.H * a.W, W2 = a.W >> 1, HW2 = (a.H >> 1) * W2;
     const uint16_t* inb = a.in + (int64_t)b * a.in_bs;
-    // Fill: wave w takes (channel, row) pairs w, w + 4, ...; eight pairs'
-    // loads in flight before their stores.  Lanes cover columns lane and
-    // lane + 64.
-    const int pairs = cpad * kConvRowsIn;
-    const int xa = xb + lane - 1, xc = xb + lane + 63;
-    const bool oka = xa >= 0 && xa < a.W, okc = lane < kConvCols - 64 && xc < a.W;
-    for (int p0 = wave; p0 < pairs; p0 += 32) {
-        uint16_t va[8], vc[8];
+    const uint16_t* upb = a.up ? a.up + (int64_t)b * a.up_bs : nullptr;
+    // Fill: item = (row, channel group, column pair), pair fastest.  Stage
+    // column c holds x = xb - 2 + c, so a pair starts at an even x.  With W
+    // even, both of its pixels are inside the image or neither is, and one
+    // 4-byte load per channel plane fetches both; an odd W (the coarsest
+    // level of some sizes) takes two 2-byte loads.  The two pixels of an
+    // upsampled channel share one source pixel.  Each item writes two
+    // 16-byte LDS words; four items' loads are in flight before their stores.
+    constexpr int kPairs = kConvCols / 2;
+    constexpr int items = kConvRowsIn * G * kPairs;
+    for (int i0 = threadIdx.x; i0 < items; i0 += 1024) {
+        uint32_t v[4][8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int pr = p0 + 4 * u;
-            const int ci = pr / kConvRowsIn, ry = pr - ci * kConvRowsIn;
-            const int yy = y0 + ry - 1;
-            const bool ok = pr < pairs && ci < a.cin && yy >= 0 && yy < a.H;
-            const uint16_t* src = inb + (int64_t)ci * HW + (int64_t)yy * a.W;
-            va[u] = (ok && oka) ? src[xa] : (uint16_t)0;
-            vc[u] = (ok && okc) ? src[xc] : (uint16_t)0;
+        for (int u = 0; u < 4; ++u) {
+            const int it = i0 + 256 * u;
+            const int pr = it % kPairs, rg = it / kPairs;
+            const int g = rg % G, r = rg / G;
+            const int yy = y0 + r - 1, xx = xb - 2 + 2 * pr, ci = 8 * g;
+            // xx is even and at least -2, so xx + 1 >= 0 exactly when xx >= 0.
+            const bool ok = it < items && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
+            const bool ok1 = ok && xx + 1 < a.W;
+            if (ci < a.up_c) {
+                const uint16_t* src = upb + (ok ? (int64_t)ci * HW2 + (yy >> 1) * W2 + (xx >> 1) : 0);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const uint32_t h = (ok && ci + j < a.cin) ? src[(int64_t)j * HW2] : 0u;
+                    v[u][j] = h | (ok1 ? h << 16 : 0u);
+                }
+            } else if (!(a.W & 1)) {
+                const uint32_t* src =
+                    reinterpret_cast<const uint32_t*>(inb + (ok ? (int64_t)ci * HW + (int64_t)yy * a.W + xx : 0));
+#pragma unroll
+                for (int j = 0; j < 8; ++j) v[u][j] = (ok && ci + j < a.cin) ? src[(int64_t)j * (HW >> 1)] : 0u;
+            } else {
+                const uint16_t* src = inb + (ok ? (int64_t)ci * HW + (int64_t)yy * a.W + xx : 0);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const bool cj = ci + j < a.cin;
+                    const uint32_t h0 = (ok && cj) ? src[(int64_t)j * HW] : 0u;
+                    const uint32_t h1 = (ok1 && cj) ? src[(int64_t)j * HW + 1] : 0u;
+                    v[u][j] = h0 | (h1 << 16);
+                }
+            }
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int pr = p0 + 4 * u;
-            if (pr < pairs) {
-                s_in[pr * kConvCols + lane] = va[u];
-                if (lane < kConvCols - 64) s_in[pr * kConvCols + 64 + lane] = vc[u];
+        for (int u = 0; u < 4; ++u) {
+            const int it = i0 + 256 * u;
+            if (it < items) {
+                const int pr = it % kPairs, rg = it / kPairs;
+                const int g = rg % G, r = rg / G;
+                uint16_t* d = s_in + (r * kConvCols + 2 * pr) * PS + 8 * g;
+                uint32_t lo[4], hi[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    lo[k] = (v[u][2 * k] & 0xFFFFu) | (v[u][2 * k + 1] << 16);
+                    hi[k] = (v[u][2 * k] >> 16) | (v[u][2 * k + 1] & 0xFFFF0000u);
+                }
+                *reinterpret_cast<uint4*>(d) = uint4{lo[0], lo[1], lo[2], lo[3]};
+                *reinterpret_cast<uint4*>(d + PS) = uint4{hi[0], hi[1], hi[2], hi[3]};
             }
         }
     }
     __syncthreads();
     const int x0 = xb + wave * 16;
     if (x0 >= a.W) return;  // whole wave, after the block's only barrier
-    const int n = lane & 15, kq = (lane >> 4) * 4;
+    const int n = lane & 15, kg = lane >> 4;
     const int x = x0 + n;
-    const int mt = min(4, ((a.cout + 15) >> 4) - m0);
+    const int mt = min(MT, ((a.cout + 15) >> 4) - m0);
     const int col = wave * 16 + n;
-    const uint16_t* wl = a.w + (size_t)(m0 * 16 + n) * a.kpad + kq;
-    v4f acc[4][kConvRowsOut];
+    const uint16_t* wl[MT];
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
+    for (int m = 0; m < MT; ++m) wl[m] = a.w + (size_t)((m0 + min(m, mt - 1)) * 16 + n) * a.kpad + 8 * kg;
+    v4f acc[MT][kConvRowsOut];
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
 #pragma unroll
         for (int r = 0; r < kConvRowsOut; ++r) acc[m][r] = v4f{0.f, 0.f, 0.f, 0.f};
-    int kk = 0;
-    for (int t = 0; t < 9; ++t) {
-        const int ty = t / 3;
-        const uint16_t* sp = s_in + kq * kConvPlane + ty * kConvCols + (t - 3 * ty) + col;
-#pragma unroll 2
-        for (int c0 = 0; c0 < cpad; c0 += 16) {
-            v4s bv[kConvRowsOut];
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        // This lane's operands: k = 32 s + 8 kg .. + 7, one tap t and eight
+        // channels from ci.  Past the last tap (the zero padding of the
+        // reduction) the operands are zero.
+        const int k = 32 * s + 8 * kg;
+        const int t = k / CPAD, ci = k - t * CPAD;
+        const int ty = t / 3, tx = t - 3 * ty;
+        v8bf bv[kConvRowsOut];
+#pragma unroll
+        for (int r = 0; r < kConvRowsOut; ++r) {
+            uint4 q = uint4{0u, 0u, 0u, 0u};
+            if (32 * s + 32 <= 9 * CPAD || t < 9)
+                q = *reinterpret_cast<const uint4*>(s_in + ((r + ty) * kConvCols + col + tx + 1) * PS + ci);
+            bv[r] = __builtin_bit_cast(v8bf, q);
+        }
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+            const v8bf av = __builtin_bit_cast(v8bf, *reinterpret_cast<const uint4*>(wl[m] + 32 * s));
 #pragma unroll
             for (int r = 0; r < kConvRowsOut; ++r)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) bv[r][j] = (short)sp[(c0 + j) * kConvPlane + r * kConvCols];
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                if (m < mt) {
-                    const uint2 wv = *reinterpret_cast<const uint2*>(wl + (size_t)m * 16 * a.kpad + kk + c0);
-                    v4s av;
-                    av[0] = (short)(wv.x & 0xFFFFu);
-                    av[1] = (short)(wv.x >> 16);
-                    av[2] = (short)(wv.y & 0xFFFFu);
-                    av[3] = (short)(wv.y >> 16);
-#pragma unroll
-                    for (int r = 0; r < kConvRowsOut; ++r)
-                        acc[m][r] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv[r], acc[m][r], 0, 0, 0);
-                }
-            }
+                acc[m][r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[r], acc[m][r], 0, 0, 0);
         }
-        kk += cpad;
     }
     if (x >= a.W) return;
-    // Lane holds output channels (m0 + m) * 16 + kq + j of pixel column n.
+    // Lane holds output channels (m0 + m) * 16 + 4 kg + j of pixel column n.
 #pragma unroll
     for (int r = 0; r < kConvRowsOut; ++r) {
         const int y = y0 + r;
         if (y >= a.H) continue;
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
+        for (int m = 0; m < MT; ++m) {
             if (m >= mt) continue;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int co = (m0 + m) * 16 + kq + j;
+                const int co = (m0 + m) * 16 + 4 * kg + j;
                 if (co >= a.cout) continue;
                 float v = acc[m][r][j] + (a.bias ? a.bias[co] : 0.f);
                 if (a.relu) v = fmaxf(v, 0.f);
@@ -284,24 +334,43 @@ __device__ __forceinline__ float block_sum(float v, float* red) {
 // Weight packing (fp32 master -> bf16 GEMM operands), pooling, upsampling,
 // gradient merges, input assembly, output and loss.
 // ---------------------------------------------------------------------------
-// Column k = tap * cpad + c of a packed row.  Forward: row = output
-// channel, c = input channel, W[row][c][tap].  Transposed (input gradient):
-// row = input channel, c = output channel, W[c][row][8 - tap] (the kernel
-// flipped).
-__global__ __launch_bounds__(256) void k_pack(const float* __restrict__ w, int cin, int cout, int transpose,
-                                              int mpad, int cpad, uint16_t* __restrict__ out) {
-    const int kpad = 9 * cpad;
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= mpad * kpad) return;
+// Column k = tap * cpad + c of a packed row of kpad columns (zero from
+// 9 cpad on).  Forward: row = output channel, c = input channel,
+// W[row][c][tap].  Transposed (input gradient): row = input channel, c =
+// output channel, W[c][row][8 - tap] (the kernel flipped).  One launch
+// packs every job: job j covers elements [start[j], start[j + 1]) of the
+// grid.
+struct PackJob {
+    const float* w;
+    uint16_t* out;
+    int cin, cout, transpose, cpad, kpad;
+};
+struct PackJobs {
+    PackJob job[2 * kLayers];
+    int start[2 * kLayers + 1];
+    int n;
+};
+
+__global__ __launch_bounds__(256) void k_pack(PackJobs J) {
+    const int g = blockIdx.x * 256 + threadIdx.x;
+    if (g >= J.start[J.n]) return;
+    int jb = 0;
+    while (g >= J.start[jb + 1]) ++jb;
+    const PackJob& P = J.job[jb];
+    const float* __restrict__ w = P.w;
+    const int cin = P.cin, cout = P.cout, transpose = P.transpose, cpad = P.cpad, kpad = P.kpad;
+    const int i = g - J.start[jb];
     const int m = i / kpad, k = i - m * kpad;
     const int t = k / cpad, c = k - t * cpad;
     float v = 0.f;
-    if (!transpose) {
-        if (m < cout && c < cin) v = w[(m * cin + c) * 9 + t];
-    } else {
-        if (m < cin && c < cout) v = w[(c * cin + m) * 9 + (8 - t)];
+    if (t < 9) {
+        if (!transpose) {
+            if (m < cout && c < cin) v = w[(m * cin + c) * 9 + t];
+        } else {
+            if (m < cin && c < cout) v = w[(c * cin + m) * 9 + (8 - t)];
+        }
     }
-    out[i] = f2bf(v);
+    P.out[i] = f2bf(v);
 }
 
 // The elementwise kernels below run on a 2-D grid: blockIdx.y = image *
@@ -548,8 +617,8 @@ Bufs layout(int B, int H, int W, bool train, char* base) {
     f.d1 = bf(B * 16 * h1);
     f.r = fl(B * 4 * h1);
     for (int l = 0; l < kLayers; ++l) {
-        f.wf[l] = bf((size_t)pad16(kNet[l].cout) * 9 * pad16(kNet[l].cin));
-        f.wb[l] = bf((size_t)pad16(kNet[l].cin) * 9 * pad16(kNet[l].cout));
+        f.wf[l] = bf((size_t)pad16(kNet[l].cout) * pad32(9 * pad16(kNet[l].cin)));
+        f.wb[l] = bf((size_t)pad16(kNet[l].cin) * pad32(9 * pad16(kNet[l].cout)));
     }
     f.cnt_part = fl((B * h1 + 255) / 256);
     f.loss_part = fl((B * h1 + 255) / 256);
@@ -586,17 +655,48 @@ Bufs layout(int B, int H, int W, bool train, char* base) {
 
 inline unsigned blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
 
+// The staged channel counts the convolution kernel is built for.
+constexpr bool conv_cpad_ok(int cpad) { return cpad == 16 || cpad == 32 || cpad == 48 || cpad == 64 || cpad == 96; }
+constexpr bool net_cpads_ok() {
+    for (int l = 0; l < kLayers; ++l)
+        if (!conv_cpad_ok(pad16(kNet[l].cin)) || !conv_cpad_ok(pad16(kNet[l].cout))) return false;
+    return true;
+}
+static_assert(net_cpads_ok(), "every layer's input and output width needs a convolution instance");
+
+template <int CPAD, int MT>
+void launch_conv(hipStream_t s, int B, const ConvArgs& a) {
+    const int groups = (a.cout + 16 * MT - 1) / (16 * MT);
+    hipLaunchKernelGGL((k_conv3x3<CPAD, MT>), dim3((a.W + 63) / 64, (a.H + kConvRowsOut - 1) / kConvRowsOut, B * groups),
+                       dim3(256), conv_lds_bytes(CPAD), s, a);
+}
+
+template <int CPAD>
+void launch_conv(hipStream_t s, int B, const ConvArgs& a) {
+    switch (std::min(4, (a.cout + 15) / 16)) {
+        case 1: launch_conv<CPAD, 1>(s, B, a); break;
+        case 2: launch_conv<CPAD, 2>(s, B, a); break;
+        case 3: launch_conv<CPAD, 3>(s, B, a); break;
+        default: launch_conv<CPAD, 4>(s, B, a); break;
+    }
+}
+
+// up (optional, with up_bs and up_c): the half-resolution source of the
+// first up_c input channels, read through the nearest 2x upsample.
 void conv(hipStream_t s, int B, int H, int W, int l, bool transpose, const Bufs& f, const uint16_t* in,
           int64_t in_bs, const float* params, uint16_t* out, float* out_f, int64_t out_bs, const uint16_t* mask,
-          int64_t mask_bs) {
+          int64_t mask_bs, const uint16_t* up = nullptr, int64_t up_bs = 0, int up_c = 0) {
     ConvArgs a{};
     a.in = in;
     a.in_bs = in_bs;
     a.cin = transpose ? kNet[l].cout : kNet[l].cin;
+    a.up = up;
+    a.up_bs = up_bs;
+    a.up_c = up ? up_c : 0;
     a.cout = transpose ? kNet[l].cin : kNet[l].cout;
     a.w = transpose ? f.wb[l] : f.wf[l];
-    a.cpad = pad16(a.cin);
-    a.kpad = 9 * a.cpad;
+    const int cpad = pad16(a.cin);
+    a.kpad = pad32(9 * cpad);
     a.bias = transpose ? nullptr : params + param_offset(l) + (int64_t)kNet[l].cout * kNet[l].cin * 9;
     a.out = out;
     a.out_f = out_f;
@@ -606,8 +706,13 @@ void conv(hipStream_t s, int B, int H, int W, int l, bool transpose, const Bufs&
     a.relu = transpose ? 0 : kNet[l].relu;
     a.H = H;
     a.W = W;
-    hipLaunchKernelGGL(k_conv3x3, dim3((W + 63) / 64, (H + kConvRowsOut - 1) / kConvRowsOut, B * ((a.cout + 63) / 64)),
-                       dim3(256), (size_t)a.cpad * kConvPlane * sizeof(uint16_t), s, a);
+    switch (cpad) {
+        case 16: launch_conv<16>(s, B, a); break;
+        case 32: launch_conv<32>(s, B, a); break;
+        case 48: launch_conv<48>(s, B, a); break;
+        case 64: launch_conv<64>(s, B, a); break;
+        default: launch_conv<96>(s, B, a); break;  // the only other width (static_assert above)
+    }
 }
 
 void wgrad(hipStream_t s, int B, int H, int W, int l, const Bufs& f, const uint16_t* g, int64_t g_bs,
@@ -632,15 +737,26 @@ void wgrad(hipStream_t s, int B, int H, int W, int l, const Bufs& f, const uint1
 }
 
 void forward(hipStream_t s, int B, int H, int W, const float* params, const float* rgb, const float* z,
-             const uint8_t* hole, const Bufs& f) {
-    for (int l = 0; l < kLayers; ++l) {
-        const float* w = params + param_offset(l);
-        const int ci = kNet[l].cin, co = kNet[l].cout;
-        hipLaunchKernelGGL(k_pack, dim3(blocks((int64_t)pad16(co) * 9 * pad16(ci))), dim3(256), 0, s, w, ci, co, 0,
-                           pad16(co), pad16(ci), f.wf[l]);
-        hipLaunchKernelGGL(k_pack, dim3(blocks((int64_t)pad16(ci) * 9 * pad16(co))), dim3(256), 0, s, w, ci, co, 1,
-                           pad16(ci), pad16(co), f.wb[l]);
-    }
+             const uint8_t* hole, const Bufs& f, bool train) {
+    // Forward weights always; the transposed ones only for the input
+    // gradient of training.
+    PackJobs J{};
+    J.start[0] = 0;
+    for (int t = 0; t < (train ? 2 : 1); ++t)
+        for (int l = 0; l < kLayers; ++l) {
+            const int ci = kNet[l].cin, co = kNet[l].cout;
+            PackJob& P = J.job[J.n];
+            P.w = params + param_offset(l);
+            P.out = t ? f.wb[l] : f.wf[l];
+            P.cin = ci;
+            P.cout = co;
+            P.transpose = t;
+            P.cpad = pad16(t ? co : ci);
+            P.kpad = pad32(9 * P.cpad);
+            J.start[J.n + 1] = J.start[J.n] + pad16(t ? ci : co) * P.kpad;
+            ++J.n;
+        }
+    hipLaunchKernelGGL(k_pack, dim3(blocks(J.start[J.n])), dim3(256), 0, s, J);
     const int64_t h1 = (int64_t)H * W, h2 = h1 / 4, h3 = h1 / 16;
     const int H2 = H / 2, W2 = W / 2, H3 = H / 4, W3 = W / 4;
     hipLaunchKernelGGL(k_input, dim3(blocks(B * h1)), dim3(256), 0, s, rgb, z, hole, B, (int)h1, f.x0);
@@ -654,10 +770,15 @@ void forward(hipStream_t s, int B, int H, int W, const float* params, const floa
     hipLaunchKernelGGL(k_pool, dim3(blocks(h3), B * 32), dim3(256), 0, s, e2b, 96 * h2, 32, H2, W2, f.p2);
     conv(s, B, H3, W3, E3A, false, f, f.p2, 32 * h3, params, f.e3a, nullptr, 64 * h3, nullptr, 0);
     conv(s, B, H3, W3, E3B, false, f, f.e3a, 64 * h3, params, f.e3b, nullptr, 64 * h3, nullptr, 0);
-    hipLaunchKernelGGL(k_up, dim3(blocks(h2), B * 64), dim3(256), 0, s, f.e3b, 64, H3, W3, f.cat2, 96 * h2);
-    conv(s, B, H2, W2, D2, false, f, f.cat2, 96 * h2, params, f.d2, nullptr, 32 * h2, nullptr, 0);
-    hipLaunchKernelGGL(k_up, dim3(blocks(h1), B * 32), dim3(256), 0, s, f.d2, 32, H2, W2, f.cat1, 48 * h1);
-    conv(s, B, H, W, D1, false, f, f.cat1, 48 * h1, params, f.d1, nullptr, 16 * h1, nullptr, 0);
+    // The decoders read their upsampled channels straight from the coarser
+    // level; training also stores the upsample, which the weight gradient
+    // reads.
+    if (train)
+        hipLaunchKernelGGL(k_up, dim3(blocks(h2), B * 64), dim3(256), 0, s, f.e3b, 64, H3, W3, f.cat2, 96 * h2);
+    conv(s, B, H2, W2, D2, false, f, f.cat2, 96 * h2, params, f.d2, nullptr, 32 * h2, nullptr, 0, f.e3b, 64 * h3, 64);
+    if (train)
+        hipLaunchKernelGGL(k_up, dim3(blocks(h1), B * 32), dim3(256), 0, s, f.d2, 32, H2, W2, f.cat1, 48 * h1);
+    conv(s, B, H, W, D1, false, f, f.cat1, 48 * h1, params, f.d1, nullptr, 16 * h1, nullptr, 0, f.d2, 32 * h2, 32);
     conv(s, B, H, W, OUT, false, f, f.d1, 16 * h1, params, nullptr, f.r, 4 * h1, nullptr, 0);
 }
 
@@ -722,7 +843,7 @@ BGS_API int32_t bgs_repair_forward(const float* params, int32_t batch, int32_t h
     if (ws_bytes < f.bytes) return BGS_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)hip_stream;
     (void)hipGetLastError();
-    forward(s, batch, height, width, params, rgb, z, hole, f);
+    forward(s, batch, height, width, params, rgb, z, hole, f, false);
     const int64_t np = (int64_t)batch * height * width;
     hipLaunchKernelGGL(k_output, dim3(blocks(np)), dim3(256), 0, s, rgb, hole, (const float*)f.r, batch,
                        height * width, rgb_out, err_out);
@@ -752,7 +873,7 @@ BGS_API int32_t bgs_repair_grad(const float* params, int32_t batch, int32_t heig
     if (ws_bytes < f.bytes) return BGS_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)hip_stream;
     (void)hipGetLastError();
-    forward(s, batch, height, width, params, rgb, z, hole, f);
+    forward(s, batch, height, width, params, rgb, z, hole, f, true);
     const int HW = height * width;
     const int64_t np = (int64_t)batch * HW;
     hipLaunchKernelGGL(k_count, dim3(blocks(np)), dim3(256), 0, s, hole, np, f.cnt_part);
