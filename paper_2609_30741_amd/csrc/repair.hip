@@ -23,7 +23,7 @@
 
 namespace {
 
-typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
@@ -48,120 +48,112 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 
 // ---------------------------------------------------------------------------
 // Convolution (forward, or input gradient with transposed weights).
+// Activations and gradients are bf16 [B][H][W][C] with the channels of a
+// pixel contiguous; a tensor's pixel stride (ps) is a multiple of 8 and may
+// exceed the channels a layer reads or writes (a slice of a concatenation,
+// or zero padding), and every buffer is 16-byte aligned.
 // ---------------------------------------------------------------------------
 struct ConvArgs {
-    const uint16_t* in;  // 4-byte aligned, in_bs even (pixel pairs are loaded as one word)
-    int64_t in_bs;
+    const uint16_t* in;  // channel 0 of the input
+    int64_t in_bs;       // elements per image
+    int in_ps;           // elements per pixel
     int cin;
     // Optional half-resolution source of input channels [0, up_c): read at
     // (y / 2, x / 2), the nearest 2x upsample, so a decoder's concatenated
-    // input needs no upsampled copy.  Channels [up_c, cin) come from in.
+    // input needs no upsampled copy.  Channels [up_c, cin) come from in,
+    // whose first up_c channel slots are then not read.
     const uint16_t* up;
     int64_t up_bs;
+    int up_ps;
     int up_c;
     const uint16_t* w;  // [pad16(cout)][kpad] bf16, k = tap * cpad + ci, zero for k >= 9 cpad
     int kpad;           // pad32(9 cpad)
     const float* bias;  // may be null
-    int cout;
-    uint16_t* out;
-    float* out_f;       // fp32 output (exactly one is set)
+    int cout;           // a multiple of 4
+    uint16_t* out;      // channel 0 of the output (bf16, out_bs, out_ps), or
+    float* out_f;       // fp32 [B][cout][H][W] planes (exactly one is set)
     int64_t out_bs;
-    const uint16_t* mask;  // may be null: output zero where mask <= 0
+    int out_ps;
+    const uint16_t* mask;  // may be null: output zero where mask <= 0 (layout of out)
     int64_t mask_bs;
+    int mask_ps;
     int relu;
     int H, W;
 };
 
-// Block: 4 waves, each 16 pixels of rows 2 blockIdx.y and 2 blockIdx.y + 1,
+// Block: 4 waves, each 16 pixels of R consecutive rows from R blockIdx.y,
 // x from blockIdx.x * 64 + 16 * wave; blockIdx.z = image * groups + group,
 // a group being MT <= 4 16-row tiles of output channels (a last group with
-// fewer real tiles repeats its last weight row and stores only its own).  The block
-// first stages input rows 2 blockIdx.y - 1 .. + 2, x from blockIdx.x * 64 - 2
-// to + 65 (zero outside the image), of every input channel (padded to CPAD,
-// a multiple of 16, with zeros) in LDS, channels innermost: [4][68][CPAD + 8]
-// bf16.  The reduction index is k = tap * CPAD + ci in 32-deep slices of
+// fewer real tiles repeats its last weight row and stores only its own).
+// The block first stages input rows R blockIdx.y - 1 .. + R, x from
+// blockIdx.x * 64 - 1 to + 64 (zero outside the image), of every input
+// channel (padded to CPAD, a multiple of 16, with zeros) in LDS:
+// [R + 2][66][CPAD + 8] bf16, one 16-byte load and store per 8 channels of
+// a pixel.  The reduction index is k = tap * CPAD + ci in 32-deep slices of
 // v_mfma_f32_16x16x32_bf16; a lane's eight operands of a slice are eight
-// consecutive channels of one tap, one 16-byte LDS read.  The 8 spare
-// channel slots per pixel make the pixel stride an odd multiple of 16 bytes,
-// so the 16 lanes reading one channel group of 16 consecutive pixels touch
-// distinct banks.
-constexpr int kConvCols = 68, kConvRowsOut = 2, kConvRowsIn = kConvRowsOut + 2;
+// consecutive channels of one tap, one 16-byte LDS read, and each weight
+// operand serves all R rows.  The 8 spare channel slots per pixel make the
+// pixel stride an odd multiple of 16 bytes, so the 16 lanes reading one
+// channel group of 16 consecutive pixels touch distinct banks.
+constexpr int kConvCols = 66;
 
 constexpr int pad32(int v) { return (v + 31) & ~31; }
-constexpr size_t conv_lds_bytes(int cpad) { return (size_t)kConvRowsIn * kConvCols * (cpad + 8) * sizeof(uint16_t); }
+constexpr size_t conv_lds_bytes(int cpad, int rows) {
+    return (size_t)(rows + 2) * kConvCols * (cpad + 8) * sizeof(uint16_t);
+}
 
-template <int CPAD, int MT>
+template <int CPAD, int MT, int R>
 __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
-    constexpr int PS = CPAD + 8;          // staged bf16 per pixel
-    constexpr int G = CPAD / 8;           // 16-byte channel groups per pixel
+    constexpr int PS = CPAD + 8;              // staged bf16 per pixel
+    constexpr int G = CPAD / 8;               // 16-byte channel groups per pixel
     constexpr int SL = pad32(9 * CPAD) / 32;  // reduction slices
     extern __shared__ uint4 s_raw[];
     uint16_t* s_in = reinterpret_cast<uint16_t*>(s_raw);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int groups = (a.cout + 16 * MT - 1) / (16 * MT);
-    const int y0 = blockIdx.y * kConvRowsOut, b = blockIdx.z / groups, m0 = (blockIdx.z - b * groups) * MT;
+    const int y0 = blockIdx.y * R, b = blockIdx.z / groups, m0 = (blockIdx.z - b * groups) * MT;
     const int xb = blockIdx.x * 64;
-    const int HW = a.H * a.W, W2 = a.W >> 1, HW2 = (a.H >> 1) * W2;
+    const int W2 = a.W >> 1;
     const uint16_t* inb = a.in + (int64_t)b * a.in_bs;
     const uint16_t* upb = a.up ? a.up + (int64_t)b * a.up_bs : nullptr;
-    // Fill: item = (row, channel group, column pair), pair fastest.  Stage
-    // column c holds x = xb - 2 + c, so a pair starts at an even x.  With W
-    // even, both of its pixels are inside the image or neither is, and one
-    // 4-byte load per channel plane fetches both; an odd W (the coarsest
-    // level of some sizes) takes two 2-byte loads.  The two pixels of an
-    // upsampled channel share one source pixel.  Each item writes two
-    // 16-byte LDS words; four items' loads are in flight before their stores.
-    constexpr int kPairs = kConvCols / 2;
-    constexpr int items = kConvRowsIn * G * kPairs;
-    for (int i0 = threadIdx.x; i0 < items; i0 += 1024) {
-        uint32_t v[4][8];
+    // Fill: item = (row, column, channel group), group fastest, so a wave's
+    // loads walk consecutive 16-byte words of consecutive pixels.  Eight
+    // items' loads are in flight before their stores.  Channels at or past
+    // cin read as zero (a group past cin is not loaded: it may lie beyond
+    // the tensor's pixel stride).
+    constexpr int items = (R + 2) * kConvCols * G;
+    for (int i0 = threadIdx.x; i0 < items; i0 += 2048) {
+        uint4 v[8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 8; ++u) {
             const int it = i0 + 256 * u;
-            const int pr = it % kPairs, rg = it / kPairs;
-            const int g = rg % G, r = rg / G;
-            const int yy = y0 + r - 1, xx = xb - 2 + 2 * pr, ci = 8 * g;
-            // xx is even and at least -2, so xx + 1 >= 0 exactly when xx >= 0.
-            const bool ok = it < items && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
-            const bool ok1 = ok && xx + 1 < a.W;
-            if (ci < a.up_c) {
-                const uint16_t* src = upb + (ok ? (int64_t)ci * HW2 + (yy >> 1) * W2 + (xx >> 1) : 0);
+            const int g = it % G, rc = it / G;
+            const int c = rc % kConvCols, r = rc / kConvCols;
+            const int yy = y0 + r - 1, xx = xb + c - 1, ci = 8 * g;
+            const bool ok = it < items && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W && ci < a.cin;
+            v[u] = uint4{0u, 0u, 0u, 0u};
+            if (ok) {
+                const uint16_t* src = ci < a.up_c
+                                          ? upb + ((int64_t)(yy >> 1) * W2 + (xx >> 1)) * a.up_ps + ci
+                                          : inb + ((int64_t)yy * a.W + xx) * a.in_ps + ci;
+                v[u] = *reinterpret_cast<const uint4*>(src);
+                const int left = a.cin - ci;  // channels of this group that exist
+                if (left < 8) {
+                    uint32_t* q = reinterpret_cast<uint32_t*>(&v[u]);
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const uint32_t h = (ok && ci + j < a.cin) ? src[(int64_t)j * HW2] : 0u;
-                    v[u][j] = h | (ok1 ? h << 16 : 0u);
-                }
-            } else if (!(a.W & 1)) {
-                const uint32_t* src =
-                    reinterpret_cast<const uint32_t*>(inb + (ok ? (int64_t)ci * HW + (int64_t)yy * a.W + xx : 0));
-#pragma unroll
-                for (int j = 0; j < 8; ++j) v[u][j] = (ok && ci + j < a.cin) ? src[(int64_t)j * (HW >> 1)] : 0u;
-            } else {
-                const uint16_t* src = inb + (ok ? (int64_t)ci * HW + (int64_t)yy * a.W + xx : 0);
-#pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const bool cj = ci + j < a.cin;
-                    const uint32_t h0 = (ok && cj) ? src[(int64_t)j * HW] : 0u;
-                    const uint32_t h1 = (ok1 && cj) ? src[(int64_t)j * HW + 1] : 0u;
-                    v[u][j] = h0 | (h1 << 16);
+                    for (int k = 0; k < 4; ++k) {
+                        const uint32_t keep = (2 * k + 1 < left ? 0xFFFF0000u : 0u) | (2 * k < left ? 0xFFFFu : 0u);
+                        q[k] &= keep;
+                    }
                 }
             }
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 8; ++u) {
             const int it = i0 + 256 * u;
             if (it < items) {
-                const int pr = it % kPairs, rg = it / kPairs;
-                const int g = rg % G, r = rg / G;
-                uint16_t* d = s_in + (r * kConvCols + 2 * pr) * PS + 8 * g;
-                uint32_t lo[4], hi[4];
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    lo[k] = (v[u][2 * k] & 0xFFFFu) | (v[u][2 * k + 1] << 16);
-                    hi[k] = (v[u][2 * k] >> 16) | (v[u][2 * k + 1] & 0xFFFF0000u);
-                }
-                *reinterpret_cast<uint4*>(d) = uint4{lo[0], lo[1], lo[2], lo[3]};
-                *reinterpret_cast<uint4*>(d + PS) = uint4{hi[0], hi[1], hi[2], hi[3]};
+                const int g = it % G, rc = it / G;
+                *reinterpret_cast<uint4*>(s_in + rc * PS + 8 * g) = v[u];
             }
         }
     }
@@ -175,11 +167,11 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
     const uint16_t* wl[MT];
 #pragma unroll
     for (int m = 0; m < MT; ++m) wl[m] = a.w + (size_t)((m0 + min(m, mt - 1)) * 16 + n) * a.kpad + 8 * kg;
-    v4f acc[MT][kConvRowsOut];
+    v4f acc[MT][R];
 #pragma unroll
     for (int m = 0; m < MT; ++m)
 #pragma unroll
-        for (int r = 0; r < kConvRowsOut; ++r) acc[m][r] = v4f{0.f, 0.f, 0.f, 0.f};
+        for (int r = 0; r < R; ++r) acc[m][r] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int s = 0; s < SL; ++s) {
         // This lane's operands: k = 32 s + 8 kg .. + 7, one tap t and eight
@@ -188,43 +180,57 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
         const int k = 32 * s + 8 * kg;
         const int t = k / CPAD, ci = k - t * CPAD;
         const int ty = t / 3, tx = t - 3 * ty;
-        v8bf bv[kConvRowsOut];
+        v8bf bv[R];
 #pragma unroll
-        for (int r = 0; r < kConvRowsOut; ++r) {
+        for (int r = 0; r < R; ++r) {
             uint4 q = uint4{0u, 0u, 0u, 0u};
             if (32 * s + 32 <= 9 * CPAD || t < 9)
-                q = *reinterpret_cast<const uint4*>(s_in + ((r + ty) * kConvCols + col + tx + 1) * PS + ci);
+                q = *reinterpret_cast<const uint4*>(s_in + ((r + ty) * kConvCols + col + tx) * PS + ci);
             bv[r] = __builtin_bit_cast(v8bf, q);
         }
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
             const v8bf av = __builtin_bit_cast(v8bf, *reinterpret_cast<const uint4*>(wl[m] + 32 * s));
 #pragma unroll
-            for (int r = 0; r < kConvRowsOut; ++r)
+            for (int r = 0; r < R; ++r)
                 acc[m][r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[r], acc[m][r], 0, 0, 0);
         }
     }
     if (x >= a.W) return;
-    // Lane holds output channels (m0 + m) * 16 + 4 kg + j of pixel column n.
+    // Lane holds output channels (m0 + m) * 16 + 4 kg + j, j < 4, of pixel
+    // column n: one 8-byte store per row and tile (cout is a multiple of 4).
 #pragma unroll
-    for (int r = 0; r < kConvRowsOut; ++r) {
+    for (int r = 0; r < R; ++r) {
         const int y = y0 + r;
         if (y >= a.H) continue;
+        const int64_t pix = (int64_t)y * a.W + x;
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
             if (m >= mt) continue;
+            const int co = (m0 + m) * 16 + 4 * kg;
+            if (co >= a.cout) continue;
+            float v[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int co = (m0 + m) * 16 + 4 * kg + j;
-                if (co >= a.cout) continue;
-                float v = acc[m][r][j] + (a.bias ? a.bias[co] : 0.f);
-                if (a.relu) v = fmaxf(v, 0.f);
-                const int64_t p = (int64_t)co * HW + (int64_t)y * a.W + x;
-                if (a.mask && !(bf2f(a.mask[(int64_t)b * a.mask_bs + p]) > 0.f)) v = 0.f;
-                if (a.out_f)
-                    a.out_f[(int64_t)b * a.out_bs + p] = v;
-                else
-                    a.out[(int64_t)b * a.out_bs + p] = f2bf(v);
+                v[j] = acc[m][r][j] + (a.bias ? a.bias[co + j] : 0.f);
+                if (a.relu) v[j] = fmaxf(v[j], 0.f);
+            }
+            if (a.mask) {
+                const uint2 mk =
+                    *reinterpret_cast<const uint2*>(a.mask + (int64_t)b * a.mask_bs + pix * a.mask_ps + co);
+                if (!(bf2f((uint16_t)(mk.x & 0xFFFFu)) > 0.f)) v[0] = 0.f;
+                if (!(bf2f((uint16_t)(mk.x >> 16)) > 0.f)) v[1] = 0.f;
+                if (!(bf2f((uint16_t)(mk.y & 0xFFFFu)) > 0.f)) v[2] = 0.f;
+                if (!(bf2f((uint16_t)(mk.y >> 16)) > 0.f)) v[3] = 0.f;
+            }
+            if (a.out_f) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    a.out_f[(int64_t)b * a.out_bs + (int64_t)(co + j) * a.H * a.W + pix] = v[j];
+            } else {
+                *reinterpret_cast<uint2*>(a.out + (int64_t)b * a.out_bs + pix * a.out_ps + co) =
+                    uint2{(uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16),
+                          (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16)};
             }
         }
     }
@@ -232,16 +238,19 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
 
 // ---------------------------------------------------------------------------
 // Weight and bias gradient: part[chunk][co][col] = sum over the chunk's
-// pixels of g[co, p] * in[ci, p + tap offset] for col = ci * 9 + tap < K,
-// and of g[co, p] (a column of ones) for col = K, the bias.  Block: 4
-// waves, one 16-column tile each; blockIdx.y: chunk of image rows.
+// pixels of g[p, co] * in[p + tap offset, ci] for col = ci * 9 + tap < K,
+// and of g[p, co] (a column of ones) for col = K, the bias.  Block: 4
+// waves, one 16-column tile each; blockIdx.y: chunk of image rows.  The
+// reduction runs over 32 pixels of a row per v_mfma_f32_16x16x32_bf16.
 // ---------------------------------------------------------------------------
 struct WgradArgs {
-    const uint16_t* g;
+    const uint16_t* g;  // layer output gradient, [B][H][W] pixels of g_ps elements
     int64_t g_bs;
+    int g_ps;
     int cout;
-    const uint16_t* in;
+    const uint16_t* in;  // layer input, in_ps elements per pixel
     int64_t in_bs;
+    int in_ps;
     int cin;
     int B, H, W;
     int rows;  // image rows (over the whole batch) per chunk
@@ -253,12 +262,11 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
     const int K = a.cin * 9, KC = K + 1;
     const int nt = blockIdx.x * 4 + wave;
     if (nt * 16 >= KC) return;  // whole wave
-    const int n = lane & 15, kq = (lane >> 4) * 4;
+    const int n = lane & 15, kq = (lane >> 4) * 8;
     const int col = nt * 16 + n;
     const bool col_ok = col < K, is_bias = col == K;
     const int ci = col_ok ? col / 9 : 0, t = col_ok ? col - ci * 9 : 4;
     const int ky = t / 3, kx = t - ky * 3;
-    const int HW = a.H * a.W;
     const int mt = (a.cout + 15) >> 4;
     v4f acc[4];
 #pragma unroll
@@ -266,30 +274,32 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
     const int r0 = blockIdx.y * a.rows, r1 = min(r0 + a.rows, a.B * a.H);
     for (int r = r0; r < r1; ++r) {
         const int b = r / a.H, y = r - b * a.H;
-        const uint16_t* gb = a.g + (int64_t)b * a.g_bs + (int64_t)y * a.W;
-        const uint16_t* ib = a.in + (int64_t)b * a.in_bs + (int64_t)ci * HW;
+        const uint16_t* gb = a.g + (int64_t)b * a.g_bs + (int64_t)y * a.W * a.g_ps;
+        const uint16_t* ib = a.in + (int64_t)b * a.in_bs + ci;
         const int yy = y + ky - 1;
         const bool row_ok = col_ok && yy >= 0 && yy < a.H;
 #pragma unroll 2
-        for (int xb = 0; xb < a.W; xb += 16) {
-            v4s bv;
+        for (int xb = 0; xb < a.W; xb += 32) {
+            v8s bv;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < 8; ++j) {
                 const int xp = xb + kq + j, xx = xp + kx - 1;
                 const bool ok = row_ok && xp < a.W && xx >= 0 && xx < a.W;
-                bv[j] = (short)(ok ? ib[(int64_t)yy * a.W + xx] : (is_bias && xp < a.W) ? (uint16_t)0x3F80u : (uint16_t)0);
+                bv[j] = (short)(ok ? ib[((int64_t)yy * a.W + xx) * a.in_ps]
+                                   : (is_bias && xp < a.W) ? (uint16_t)0x3F80u : (uint16_t)0);
             }
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
                 if (m < mt) {
                     const int co = m * 16 + n;
-                    v4s av;
+                    v8s av;
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
+                    for (int j = 0; j < 8; ++j) {
                         const int xp = xb + kq + j;
-                        av[j] = (short)((co < a.cout && xp < a.W) ? gb[(int64_t)co * HW + xp] : (uint16_t)0);
+                        av[j] = (short)((co < a.cout && xp < a.W) ? gb[(int64_t)xp * a.g_ps + co] : (uint16_t)0);
                     }
-                    acc[m] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[m], 0, 0, 0);
+                    acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, av),
+                                                                    __builtin_bit_cast(v8bf, bv), acc[m], 0, 0, 0);
                 }
             }
         }
@@ -301,7 +311,7 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
         if (m >= mt) continue;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            const int co = m * 16 + kq + j;
+            const int co = m * 16 + (lane >> 4) * 4 + j;
             if (co < a.cout) pb[(size_t)co * KC + col] = acc[m][j];
         }
     }
@@ -373,62 +383,117 @@ __global__ __launch_bounds__(256) void k_pack(PackJobs J) {
     P.out[i] = f2bf(v);
 }
 
-// The elementwise kernels below run on a 2-D grid: blockIdx.y = image *
-// C + channel, x over the pixels of the output plane.
-__global__ __launch_bounds__(256) void k_pool(const uint16_t* __restrict__ in, int64_t in_bs, int C, int H, int W,
-                                              uint16_t* __restrict__ out) {
-    const int h = H / 2, w = W / 2;
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= h * w) return;
-    const int bc = blockIdx.y, b = bc / C, c = bc - b * C;
-    const int Y = i / w, X = i - Y * w;
-    const uint16_t* p = in + (int64_t)b * in_bs + (int64_t)c * H * W + (2 * Y) * W + 2 * X;
-    const float s = ((bf2f(p[0]) + bf2f(p[1])) + bf2f(p[W])) + bf2f(p[W + 1]);
-    out[(int64_t)bc * h * w + i] = f2bf(0.25f * s);
+// The channel kernels below take one pixel's eight channels (one 16-byte
+// word) per thread: grid over B * pixels * C / 8 (C a multiple of 8),
+// channel group fastest.
+__device__ __forceinline__ void unpack8(uint4 q, float* f) {
+    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        f[2 * k] = bf2f((uint16_t)(w[k] & 0xFFFFu));
+        f[2 * k + 1] = bf2f((uint16_t)(w[k] >> 16));
+    }
+}
+__device__ __forceinline__ uint4 pack8(const float* f) {
+    uint32_t w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] = (uint32_t)f2bf(f[2 * k]) | ((uint32_t)f2bf(f[2 * k + 1]) << 16);
+    return uint4{w[0], w[1], w[2], w[3]};
+}
+__device__ __forceinline__ uint4 ld8(const uint16_t* p) { return *reinterpret_cast<const uint4*>(p); }
+__device__ __forceinline__ void st8(uint16_t* p, uint4 v) { *reinterpret_cast<uint4*>(p) = v; }
+
+// Index of this thread's (image, pixel, channel group) over n pixels per
+// image; false past the end.
+__device__ __forceinline__ bool item(int64_t B, int64_t n, int C, int64_t& b, int64_t& p, int& c) {
+    const int G = C >> 3;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= B * n * G) return false;
+    const int64_t bp = i / G;
+    c = (int)(i - bp * G) * 8;
+    b = bp / n;
+    p = bp - b * n;
+    return true;
 }
 
-// Nearest 2x upsample of [B][C][h][w] into a slice of a larger tensor.
-__global__ __launch_bounds__(256) void k_up(const uint16_t* __restrict__ in, int C, int h, int w,
-                                            uint16_t* __restrict__ out, int64_t out_bs) {
+// 2x2 mean of C channels of in (pixel stride in_ps) into out [B][H/2][W/2][C].
+__global__ __launch_bounds__(256) void k_pool(const uint16_t* __restrict__ in, int64_t in_bs, int in_ps, int B, int C,
+                                              int H, int W, uint16_t* __restrict__ out) {
+    const int h = H / 2, w = W / 2;
+    int64_t b, p;
+    int c;
+    if (!item(B, (int64_t)h * w, C, b, p, c)) return;
+    const int Y = (int)(p / w), X = (int)(p - (int64_t)Y * w);
+    const uint16_t* q = in + b * in_bs + ((int64_t)(2 * Y) * W + 2 * X) * in_ps + c;
+    float f0[8], f1[8], f2[8], f3[8], o[8];
+    unpack8(ld8(q), f0);
+    unpack8(ld8(q + in_ps), f1);
+    unpack8(ld8(q + (int64_t)W * in_ps), f2);
+    unpack8(ld8(q + (int64_t)(W + 1) * in_ps), f3);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) o[k] = 0.25f * (((f0[k] + f1[k]) + f2[k]) + f3[k]);
+    st8(out + (b * h * w + p) * C + c, pack8(o));
+}
+
+// Nearest 2x upsample of [B][h][w][C] into the first C channel slots of a
+// larger tensor (out_bs, out_ps).
+__global__ __launch_bounds__(256) void k_up(const uint16_t* __restrict__ in, int B, int C, int h, int w,
+                                            uint16_t* __restrict__ out, int64_t out_bs, int out_ps) {
     const int H = 2 * h, W = 2 * w;
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= H * W) return;
-    const int bc = blockIdx.y, b = bc / C, c = bc - b * C;
-    const int y = i / W, x = i - y * W;
-    out[(int64_t)b * out_bs + (int64_t)c * H * W + i] = in[(int64_t)bc * h * w + (y >> 1) * w + (x >> 1)];
+    int64_t b, p;
+    int c;
+    if (!item(B, (int64_t)H * W, C, b, p, c)) return;
+    const int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
+    st8(out + b * out_bs + p * out_ps + c, ld8(in + (b * h * w + (int64_t)(y >> 1) * w + (x >> 1)) * C + c));
 }
 
-// Gradient of the upsample: sum of each 2x2 block of a slice, masked by the
-// activation (ReLU derivative).
-__global__ __launch_bounds__(256) void k_up_grad(const uint16_t* __restrict__ g, int64_t g_bs, int C, int H, int W,
-                                                 const uint16_t* __restrict__ act, uint16_t* __restrict__ out) {
+// Gradient of the upsample: sum of each 2x2 block of the first C channels
+// of g (g_bs, g_ps), masked by the activation act [B][H/2][W/2][C] (ReLU
+// derivative), into out of that layout.
+__global__ __launch_bounds__(256) void k_up_grad(const uint16_t* __restrict__ g, int64_t g_bs, int g_ps, int B, int C,
+                                                 int H, int W, const uint16_t* __restrict__ act,
+                                                 uint16_t* __restrict__ out) {
     const int h = H / 2, w = W / 2;
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= h * w) return;
-    const int bc = blockIdx.y, b = bc / C, c = bc - b * C;
-    const int Y = i / w, X = i - Y * w;
-    const uint16_t* p = g + (int64_t)b * g_bs + (int64_t)c * H * W + (2 * Y) * W + 2 * X;
-    const float s = ((bf2f(p[0]) + bf2f(p[1])) + bf2f(p[W])) + bf2f(p[W + 1]);
-    const int64_t o = (int64_t)bc * h * w + i;
-    out[o] = bf2f(act[o]) > 0.f ? f2bf(s) : (uint16_t)0;
+    int64_t b, p;
+    int c;
+    if (!item(B, (int64_t)h * w, C, b, p, c)) return;
+    const int Y = (int)(p / w), X = (int)(p - (int64_t)Y * w);
+    const uint16_t* q = g + b * g_bs + ((int64_t)(2 * Y) * W + 2 * X) * g_ps + c;
+    float f0[8], f1[8], f2[8], f3[8], a[8], o[8];
+    unpack8(ld8(q), f0);
+    unpack8(ld8(q + g_ps), f1);
+    unpack8(ld8(q + (int64_t)W * g_ps), f2);
+    unpack8(ld8(q + (int64_t)(W + 1) * g_ps), f3);
+    const int64_t oi = (b * h * w + p) * C + c;
+    unpack8(ld8(act + oi), a);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) o[k] = a[k] > 0.f ? ((f0[k] + f1[k]) + f2[k]) + f3[k] : 0.f;
+    st8(out + oi, pack8(o));
 }
 
-// Gradient reaching an encoder activation from its skip connection (a
-// slice of the decoder input's gradient) and from the pool below it,
-// masked by the activation.
-__global__ __launch_bounds__(256) void k_merge(const uint16_t* __restrict__ skip, int64_t skip_bs,
+// Gradient reaching an encoder activation from its skip connection (C
+// channels of skip, at skip_bs, skip_ps) and from the pool below it (pg,
+// [B][H/2][W/2][C]), masked by the activation (act_bs, act_ps), into out
+// [B][H][W][C].
+__global__ __launch_bounds__(256) void k_merge(const uint16_t* __restrict__ skip, int64_t skip_bs, int skip_ps,
                                                const uint16_t* __restrict__ pg, const uint16_t* __restrict__ act,
-                                               int64_t act_bs, int C, int H, int W, uint16_t* __restrict__ out) {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= H * W) return;
-    const int bc = blockIdx.y, b = bc / C, c = bc - b * C;
-    const int y = i / W, x = i - y * W;
-    const int64_t off = (int64_t)c * H * W + i;
-    const float s = bf2f(skip[(int64_t)b * skip_bs + off]) +
-                    0.25f * bf2f(pg[(int64_t)bc * (H / 2) * (W / 2) + (y >> 1) * (W / 2) + (x >> 1)]);
-    out[(int64_t)bc * H * W + i] = bf2f(act[(int64_t)b * act_bs + off]) > 0.f ? f2bf(s) : (uint16_t)0;
+                                               int64_t act_bs, int act_ps, int B, int C, int H, int W,
+                                               uint16_t* __restrict__ out) {
+    int64_t b, p;
+    int c;
+    if (!item(B, (int64_t)H * W, C, b, p, c)) return;
+    const int y = (int)(p / W), x = (int)(p - (int64_t)y * W);
+    float sk[8], pl[8], a[8], o[8];
+    unpack8(ld8(skip + b * skip_bs + p * skip_ps + c), sk);
+    unpack8(ld8(pg + (b * (H / 2) * (W / 2) + (int64_t)(y >> 1) * (W / 2) + (x >> 1)) * C + c), pl);
+    unpack8(ld8(act + b * act_bs + p * act_ps + c), a);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) o[k] = a[k] > 0.f ? sk[k] + 0.25f * pl[k] : 0.f;
+    st8(out + (b * H * W + p) * C + c, pack8(o));
 }
 
+// Network input x0 [B][H][W][8]: warped rgb (zero at holes), hole flag,
+// 1/z (zero at holes and background), three zero slots.
 __global__ __launch_bounds__(256) void k_input(const float* __restrict__ rgb, const float* __restrict__ z,
                                                const uint8_t* __restrict__ hole, int B, int HW,
                                                uint16_t* __restrict__ x0) {
@@ -437,11 +502,13 @@ __global__ __launch_bounds__(256) void k_input(const float* __restrict__ rgb, co
     const int64_t b = i / HW, p = i - b * HW;
     const bool h = hole[i] != 0;
     const float zz = z[i];
-    uint16_t* o = x0 + b * 5 * HW + p;
+    float f[8];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) o[(int64_t)c * HW] = h ? (uint16_t)0 : f2bf(rgb[(b * 3 + c) * HW + p]);
-    o[3 * (int64_t)HW] = h ? f2bf(1.f) : (uint16_t)0;
-    o[4 * (int64_t)HW] = (h || !(zz < INFINITY)) ? (uint16_t)0 : f2bf(1.f / zz);
+    for (int c = 0; c < 3; ++c) f[c] = h ? 0.f : rgb[(b * 3 + c) * HW + p];
+    f[3] = h ? 1.f : 0.f;
+    f[4] = (h || !(zz < INFINITY)) ? 0.f : 1.f / zz;
+    f[5] = f[6] = f[7] = 0.f;
+    st8(x0 + i * 8, pack8(f));
 }
 
 // r: [B][4][HW], channels 0-2 the residual, 3 the predicted squared error.
@@ -519,7 +586,8 @@ __global__ __launch_bounds__(256) void k_sum(const float* __restrict__ part, int
 // Loss terms per hole pixel: sum over channels of (pred - target)^2 plus
 // 3 (e - s)^2, s the pixel's mean squared error (held constant); per-block
 // partial sums (k_sum divides by 3 holes).  Gradient with respect to the
-// output layer (bf16): 2 d_c / (3 N) for the residual, 2 (e - s) / N for e.
+// output layer (bf16 [B][H][W][8], slots 4-7 zero): 2 d_c / (3 N) for the
+// residual, 2 (e - s) / N for e.
 __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ rgb, const uint8_t* __restrict__ hole,
                                               const float* __restrict__ r, const float* __restrict__ target,
                                               const float* __restrict__ n_hole, int B, int HW,
@@ -533,7 +601,6 @@ __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ rgb, con
         const bool h = hole[i] != 0;
         const float nh = fmaxf(n_hole[0], 1.f);
         const float* rb = r + b * 4 * HW + p;
-        uint16_t* gb = g_r + b * 4 * HW + p;
         float d[3], s2 = 0.f;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -544,9 +611,12 @@ __global__ __launch_bounds__(256) void k_loss(const float* __restrict__ rgb, con
             if (rgb_out) rgb_out[q] = pred;
         }
         const float de = h ? rb[3 * (int64_t)HW] - s2 / 3.f : 0.f;
+        float gr[8];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) gb[(int64_t)c * HW] = f2bf(2.f * d[c] / (3.f * nh));
-        gb[3 * (int64_t)HW] = f2bf(2.f * de / nh);
+        for (int c = 0; c < 3; ++c) gr[c] = 2.f * d[c] / (3.f * nh);
+        gr[3] = 2.f * de / nh;
+        gr[4] = gr[5] = gr[6] = gr[7] = 0.f;
+        st8(g_r + i * 8, pack8(gr));
         e = s2 + 3.f * de * de;
     }
     const float sum = block_sum(e, red);
@@ -604,7 +674,7 @@ Bufs layout(int B, int H, int W, bool train, char* base) {
     const size_t h1 = (size_t)H * W, h2 = h1 / 4, h3 = h1 / 16;
     auto bf = [&](size_t elems) { return (uint16_t*)(base + L.take(elems * 2)); };
     auto fl = [&](size_t elems) { return (float*)(base + L.take(elems * 4)); };
-    f.x0 = bf(B * 5 * h1);
+    f.x0 = bf(B * 8 * h1);
     f.e1a = bf(B * 16 * h1);
     f.cat1 = bf(B * 48 * h1);
     f.p1 = bf(B * 16 * h2);
@@ -624,7 +694,7 @@ Bufs layout(int B, int H, int W, bool train, char* base) {
     f.loss_part = fl((B * h1 + 255) / 256);
     f.n_hole = fl(1);
     if (train) {
-        f.g_r = bf(B * 4 * h1);
+        f.g_r = bf(B * 8 * h1);
         f.g_d1 = bf(B * 16 * h1);
         f.g_cat1 = bf(B * 48 * h1);
         f.g_d2 = bf(B * 32 * h2);
@@ -664,45 +734,79 @@ constexpr bool net_cpads_ok() {
 }
 static_assert(net_cpads_ok(), "every layer's input and output width needs a convolution instance");
 
-template <int CPAD, int MT>
+template <int CPAD, int MT, int R>
 void launch_conv(hipStream_t s, int B, const ConvArgs& a) {
     const int groups = (a.cout + 16 * MT - 1) / (16 * MT);
-    hipLaunchKernelGGL((k_conv3x3<CPAD, MT>), dim3((a.W + 63) / 64, (a.H + kConvRowsOut - 1) / kConvRowsOut, B * groups),
-                       dim3(256), conv_lds_bytes(CPAD), s, a);
+    hipLaunchKernelGGL((k_conv3x3<CPAD, MT, R>), dim3((a.W + 63) / 64, (a.H + R - 1) / R, B * groups), dim3(256),
+                       conv_lds_bytes(CPAD, R), s, a);
 }
 
-template <int CPAD>
-void launch_conv(hipStream_t s, int B, const ConvArgs& a) {
-    switch (std::min(4, (a.cout + 15) / 16)) {
-        case 1: launch_conv<CPAD, 1>(s, B, a); break;
-        case 2: launch_conv<CPAD, 2>(s, B, a); break;
-        case 3: launch_conv<CPAD, 3>(s, B, a); break;
-        default: launch_conv<CPAD, 4>(s, B, a); break;
+template <int CPAD, int R>
+void launch_conv(hipStream_t s, int B, int mt, const ConvArgs& a) {
+    switch (mt) {
+        case 1: launch_conv<CPAD, 1, R>(s, B, a); break;
+        case 2: launch_conv<CPAD, 2, R>(s, B, a); break;
+        case 3: launch_conv<CPAD, 3, R>(s, B, a); break;
+        default: launch_conv<CPAD, 4, R>(s, B, a); break;
     }
 }
 
-// up (optional, with up_bs and up_c): the half-resolution source of the
-// first up_c input channels, read through the nearest 2x upsample.
-void conv(hipStream_t s, int B, int H, int W, int l, bool transpose, const Bufs& f, const uint16_t* in,
-          int64_t in_bs, const float* params, uint16_t* out, float* out_f, int64_t out_bs, const uint16_t* mask,
-          int64_t mask_bs, const uint16_t* up = nullptr, int64_t up_bs = 0, int up_c = 0) {
+// Block shape: four output rows per block where that still leaves at least
+// six blocks per CU (they share the two halo rows and each weight operand),
+// else two; then fewer output tiles per block until there are at least four
+// blocks per CU, since the coarse levels have few pixels.  Four rows of 96
+// staged channels would take 85 KB of LDS; that width keeps two rows.
+template <int CPAD>
+void launch_conv(hipStream_t s, int B, const ConvArgs& a) {
+    const int tiles = (a.cout + 15) / 16;
+    auto nblk = [&](int r, int mt) {
+        return (int64_t)((a.W + 63) / 64) * ((a.H + r - 1) / r) * B * ((tiles + mt - 1) / mt);
+    };
+    int mt = std::min(4, tiles);
+    const int r = (CPAD <= 64 && nblk(4, mt) >= 6 * 256) ? 4 : 2;
+    while (mt > 1 && nblk(r, mt) < 4 * 256) mt = (mt + 1) / 2;
+    if (CPAD <= 64 && r == 4)
+        launch_conv<CPAD, (CPAD <= 64 ? 4 : 2)>(s, B, mt, a);
+    else
+        launch_conv<CPAD, 2>(s, B, mt, a);
+}
+
+// A bf16 activation or gradient tensor [B][H][W] of pixels holding ps
+// elements (bs per image), from channel 0 of a slice.
+struct View {
+    uint16_t* p;
+    int64_t bs;
+    int ps;
+    View at(int channel) const { return View{p + channel, bs, ps}; }
+};
+const View kNone{nullptr, 0, 0};
+
+// up (optional, with up_c): the half-resolution source of the first up_c
+// input channels, read through the nearest 2x upsample.  out_f (fp32
+// planes) replaces out when set.
+void conv(hipStream_t s, int B, int H, int W, int l, bool transpose, const Bufs& f, View in, const float* params,
+          View out, float* out_f, View mask, View up = kNone, int up_c = 0) {
     ConvArgs a{};
-    a.in = in;
-    a.in_bs = in_bs;
+    a.in = in.p;
+    a.in_bs = in.bs;
+    a.in_ps = in.ps;
     a.cin = transpose ? kNet[l].cout : kNet[l].cin;
-    a.up = up;
-    a.up_bs = up_bs;
-    a.up_c = up ? up_c : 0;
+    a.up = up.p;
+    a.up_bs = up.bs;
+    a.up_ps = up.ps;
+    a.up_c = up.p ? up_c : 0;
     a.cout = transpose ? kNet[l].cin : kNet[l].cout;
     a.w = transpose ? f.wb[l] : f.wf[l];
     const int cpad = pad16(a.cin);
     a.kpad = pad32(9 * cpad);
     a.bias = transpose ? nullptr : params + param_offset(l) + (int64_t)kNet[l].cout * kNet[l].cin * 9;
-    a.out = out;
+    a.out = out.p;
+    a.out_bs = out_f ? (int64_t)a.cout * H * W : out.bs;
+    a.out_ps = out.ps;
     a.out_f = out_f;
-    a.out_bs = out_bs;
-    a.mask = mask;
-    a.mask_bs = mask_bs;
+    a.mask = mask.p;
+    a.mask_bs = mask.bs;
+    a.mask_ps = mask.ps;
     a.relu = transpose ? 0 : kNet[l].relu;
     a.H = H;
     a.W = W;
@@ -715,14 +819,15 @@ void conv(hipStream_t s, int B, int H, int W, int l, bool transpose, const Bufs&
     }
 }
 
-void wgrad(hipStream_t s, int B, int H, int W, int l, const Bufs& f, const uint16_t* g, int64_t g_bs,
-           const uint16_t* in, int64_t in_bs, int chunks, float* grad) {
+void wgrad(hipStream_t s, int B, int H, int W, int l, const Bufs& f, View g, View in, int chunks, float* grad) {
     WgradArgs a{};
-    a.g = g;
-    a.g_bs = g_bs;
+    a.g = g.p;
+    a.g_bs = g.bs;
+    a.g_ps = g.ps;
     a.cout = kNet[l].cout;
-    a.in = in;
-    a.in_bs = in_bs;
+    a.in = in.p;
+    a.in_bs = in.bs;
+    a.in_ps = in.ps;
     a.cin = kNet[l].cin;
     a.B = B;
     a.H = H;
@@ -735,6 +840,47 @@ void wgrad(hipStream_t s, int B, int H, int W, int l, const Bufs& f, const uint1
     hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks((int64_t)a.cout * (K + 1))), dim3(256), 0, s, (const float*)f.part,
                        chunks, a.cout, K, grad + param_offset(l));
 }
+
+// The tensors of one pass, as views.
+struct Net {
+    View x0, e1a, cat1, e1b, p1, e2a, cat2, e2b, p2, e3a, e3b, d2, d1;
+    View g_r, g_d1, g_cat1, g_d2, g_cat2, g_e3b, g_e3a, g_p2, g_e2b, g_e2a, g_p1, g_e1b, g_e1a;
+};
+
+Net views(const Bufs& f, int H, int W) {
+    const int64_t h1 = (int64_t)H * W, h2 = h1 / 4, h3 = h1 / 16;
+    auto v = [](uint16_t* p, int c, int64_t hw) { return View{p, c * hw, c}; };
+    Net n;
+    n.x0 = v(f.x0, 8, h1);
+    n.e1a = v(f.e1a, 16, h1);
+    n.cat1 = v(f.cat1, 48, h1);  // up(d2) in channels 0-31, e1b in 32-47
+    n.e1b = n.cat1.at(32);
+    n.p1 = v(f.p1, 16, h2);
+    n.e2a = v(f.e2a, 32, h2);
+    n.cat2 = v(f.cat2, 96, h2);  // up(e3b) in channels 0-63, e2b in 64-95
+    n.e2b = n.cat2.at(64);
+    n.p2 = v(f.p2, 32, h3);
+    n.e3a = v(f.e3a, 64, h3);
+    n.e3b = v(f.e3b, 64, h3);
+    n.d2 = v(f.d2, 32, h2);
+    n.d1 = v(f.d1, 16, h1);
+    n.g_r = v(f.g_r, 8, h1);
+    n.g_d1 = v(f.g_d1, 16, h1);
+    n.g_cat1 = v(f.g_cat1, 48, h1);
+    n.g_d2 = v(f.g_d2, 32, h2);
+    n.g_cat2 = v(f.g_cat2, 96, h2);
+    n.g_e3b = v(f.g_e3b, 64, h3);
+    n.g_e3a = v(f.g_e3a, 64, h3);
+    n.g_p2 = v(f.g_p2, 32, h3);
+    n.g_e2b = v(f.g_e2b, 32, h2);
+    n.g_e2a = v(f.g_e2a, 32, h2);
+    n.g_p1 = v(f.g_p1, 16, h2);
+    n.g_e1b = v(f.g_e1b, 16, h1);
+    n.g_e1a = v(f.g_e1a, 16, h1);
+    return n;
+}
+
+inline unsigned chan_blocks(int B, int64_t pixels, int C) { return blocks((int64_t)B * pixels * (C / 8)); }
 
 void forward(hipStream_t s, int B, int H, int W, const float* params, const float* rgb, const float* z,
              const uint8_t* hole, const Bufs& f, bool train) {
@@ -757,61 +903,64 @@ void forward(hipStream_t s, int B, int H, int W, const float* params, const floa
             ++J.n;
         }
     hipLaunchKernelGGL(k_pack, dim3(blocks(J.start[J.n])), dim3(256), 0, s, J);
+    const Net n = views(f, H, W);
     const int64_t h1 = (int64_t)H * W, h2 = h1 / 4, h3 = h1 / 16;
     const int H2 = H / 2, W2 = W / 2, H3 = H / 4, W3 = W / 4;
     hipLaunchKernelGGL(k_input, dim3(blocks(B * h1)), dim3(256), 0, s, rgb, z, hole, B, (int)h1, f.x0);
-    conv(s, B, H, W, E1A, false, f, f.x0, 5 * h1, params, f.e1a, nullptr, 16 * h1, nullptr, 0);
-    uint16_t* e1b = f.cat1 + 32 * h1;
-    conv(s, B, H, W, E1B, false, f, f.e1a, 16 * h1, params, e1b, nullptr, 48 * h1, nullptr, 0);
-    hipLaunchKernelGGL(k_pool, dim3(blocks(h2), B * 16), dim3(256), 0, s, e1b, 48 * h1, 16, H, W, f.p1);
-    conv(s, B, H2, W2, E2A, false, f, f.p1, 16 * h2, params, f.e2a, nullptr, 32 * h2, nullptr, 0);
-    uint16_t* e2b = f.cat2 + 64 * h2;
-    conv(s, B, H2, W2, E2B, false, f, f.e2a, 32 * h2, params, e2b, nullptr, 96 * h2, nullptr, 0);
-    hipLaunchKernelGGL(k_pool, dim3(blocks(h3), B * 32), dim3(256), 0, s, e2b, 96 * h2, 32, H2, W2, f.p2);
-    conv(s, B, H3, W3, E3A, false, f, f.p2, 32 * h3, params, f.e3a, nullptr, 64 * h3, nullptr, 0);
-    conv(s, B, H3, W3, E3B, false, f, f.e3a, 64 * h3, params, f.e3b, nullptr, 64 * h3, nullptr, 0);
+    conv(s, B, H, W, E1A, false, f, n.x0, params, n.e1a, nullptr, kNone);
+    conv(s, B, H, W, E1B, false, f, n.e1a, params, n.e1b, nullptr, kNone);
+    hipLaunchKernelGGL(k_pool, dim3(chan_blocks(B, h2, 16)), dim3(256), 0, s, n.e1b.p, n.e1b.bs, n.e1b.ps, B, 16, H, W,
+                       f.p1);
+    conv(s, B, H2, W2, E2A, false, f, n.p1, params, n.e2a, nullptr, kNone);
+    conv(s, B, H2, W2, E2B, false, f, n.e2a, params, n.e2b, nullptr, kNone);
+    hipLaunchKernelGGL(k_pool, dim3(chan_blocks(B, h3, 32)), dim3(256), 0, s, n.e2b.p, n.e2b.bs, n.e2b.ps, B, 32, H2,
+                       W2, f.p2);
+    conv(s, B, H3, W3, E3A, false, f, n.p2, params, n.e3a, nullptr, kNone);
+    conv(s, B, H3, W3, E3B, false, f, n.e3a, params, n.e3b, nullptr, kNone);
     // The decoders read their upsampled channels straight from the coarser
     // level; training also stores the upsample, which the weight gradient
     // reads.
     if (train)
-        hipLaunchKernelGGL(k_up, dim3(blocks(h2), B * 64), dim3(256), 0, s, f.e3b, 64, H3, W3, f.cat2, 96 * h2);
-    conv(s, B, H2, W2, D2, false, f, f.cat2, 96 * h2, params, f.d2, nullptr, 32 * h2, nullptr, 0, f.e3b, 64 * h3, 64);
+        hipLaunchKernelGGL(k_up, dim3(chan_blocks(B, h2, 64)), dim3(256), 0, s, f.e3b, B, 64, H3, W3, n.cat2.p,
+                           n.cat2.bs, n.cat2.ps);
+    conv(s, B, H2, W2, D2, false, f, n.cat2, params, n.d2, nullptr, kNone, n.e3b, 64);
     if (train)
-        hipLaunchKernelGGL(k_up, dim3(blocks(h1), B * 32), dim3(256), 0, s, f.d2, 32, H2, W2, f.cat1, 48 * h1);
-    conv(s, B, H, W, D1, false, f, f.cat1, 48 * h1, params, f.d1, nullptr, 16 * h1, nullptr, 0, f.d2, 32 * h2, 32);
-    conv(s, B, H, W, OUT, false, f, f.d1, 16 * h1, params, nullptr, f.r, 4 * h1, nullptr, 0);
+        hipLaunchKernelGGL(k_up, dim3(chan_blocks(B, h1, 32)), dim3(256), 0, s, f.d2, B, 32, H2, W2, n.cat1.p,
+                           n.cat1.bs, n.cat1.ps);
+    conv(s, B, H, W, D1, false, f, n.cat1, params, n.d1, nullptr, kNone, n.d2, 32);
+    conv(s, B, H, W, OUT, false, f, n.d1, params, kNone, f.r, kNone);
 }
 
 void backward(hipStream_t s, int B, int H, int W, const float* params, const Bufs& f, float* grad) {
-    const int64_t h1 = (int64_t)H * W, h2 = h1 / 4, h3 = h1 / 16;
+    const Net n = views(f, H, W);
+    const int64_t h1 = (int64_t)H * W, h2 = h1 / 4;
     const int H2 = H / 2, W2 = W / 2, H3 = H / 4, W3 = W / 4;
-    uint16_t* e1b = f.cat1 + 32 * h1;
-    uint16_t* e2b = f.cat2 + 64 * h2;
-    wgrad(s, B, H, W, OUT, f, f.g_r, 4 * h1, f.d1, 16 * h1, f.chunks1, grad);
-    conv(s, B, H, W, OUT, true, f, f.g_r, 4 * h1, params, f.g_d1, nullptr, 16 * h1, f.d1, 16 * h1);
-    wgrad(s, B, H, W, D1, f, f.g_d1, 16 * h1, f.cat1, 48 * h1, f.chunks1, grad);
-    conv(s, B, H, W, D1, true, f, f.g_d1, 16 * h1, params, f.g_cat1, nullptr, 48 * h1, nullptr, 0);
-    hipLaunchKernelGGL(k_up_grad, dim3(blocks(h2), B * 32), dim3(256), 0, s, f.g_cat1, 48 * h1, 32, H, W, f.d2,
-                       f.g_d2);
-    wgrad(s, B, H2, W2, D2, f, f.g_d2, 32 * h2, f.cat2, 96 * h2, f.chunks2, grad);
-    conv(s, B, H2, W2, D2, true, f, f.g_d2, 32 * h2, params, f.g_cat2, nullptr, 96 * h2, nullptr, 0);
-    hipLaunchKernelGGL(k_up_grad, dim3(blocks(h3), B * 64), dim3(256), 0, s, f.g_cat2, 96 * h2, 64, H2, W2, f.e3b,
-                       f.g_e3b);
-    wgrad(s, B, H3, W3, E3B, f, f.g_e3b, 64 * h3, f.e3a, 64 * h3, f.chunks3, grad);
-    conv(s, B, H3, W3, E3B, true, f, f.g_e3b, 64 * h3, params, f.g_e3a, nullptr, 64 * h3, f.e3a, 64 * h3);
-    wgrad(s, B, H3, W3, E3A, f, f.g_e3a, 64 * h3, f.p2, 32 * h3, f.chunks3, grad);
-    conv(s, B, H3, W3, E3A, true, f, f.g_e3a, 64 * h3, params, f.g_p2, nullptr, 32 * h3, nullptr, 0);
-    hipLaunchKernelGGL(k_merge, dim3(blocks(h2), B * 32), dim3(256), 0, s, f.g_cat2 + 64 * h2, 96 * h2, f.g_p2, e2b,
-                       96 * h2, 32, H2, W2, f.g_e2b);
-    wgrad(s, B, H2, W2, E2B, f, f.g_e2b, 32 * h2, f.e2a, 32 * h2, f.chunks2, grad);
-    conv(s, B, H2, W2, E2B, true, f, f.g_e2b, 32 * h2, params, f.g_e2a, nullptr, 32 * h2, f.e2a, 32 * h2);
-    wgrad(s, B, H2, W2, E2A, f, f.g_e2a, 32 * h2, f.p1, 16 * h2, f.chunks2, grad);
-    conv(s, B, H2, W2, E2A, true, f, f.g_e2a, 32 * h2, params, f.g_p1, nullptr, 16 * h2, nullptr, 0);
-    hipLaunchKernelGGL(k_merge, dim3(blocks(h1), B * 16), dim3(256), 0, s, f.g_cat1 + 32 * h1, 48 * h1, f.g_p1, e1b,
-                       48 * h1, 16, H, W, f.g_e1b);
-    wgrad(s, B, H, W, E1B, f, f.g_e1b, 16 * h1, f.e1a, 16 * h1, f.chunks1, grad);
-    conv(s, B, H, W, E1B, true, f, f.g_e1b, 16 * h1, params, f.g_e1a, nullptr, 16 * h1, f.e1a, 16 * h1);
-    wgrad(s, B, H, W, E1A, f, f.g_e1a, 16 * h1, f.x0, 5 * h1, f.chunks1, grad);
+    wgrad(s, B, H, W, OUT, f, n.g_r, n.d1, f.chunks1, grad);
+    conv(s, B, H, W, OUT, true, f, n.g_r, params, n.g_d1, nullptr, n.d1);
+    wgrad(s, B, H, W, D1, f, n.g_d1, n.cat1, f.chunks1, grad);
+    conv(s, B, H, W, D1, true, f, n.g_d1, params, n.g_cat1, nullptr, kNone);
+    hipLaunchKernelGGL(k_up_grad, dim3(chan_blocks(B, h2, 32)), dim3(256), 0, s, n.g_cat1.p, n.g_cat1.bs, n.g_cat1.ps,
+                       B, 32, H, W, f.d2, f.g_d2);
+    wgrad(s, B, H2, W2, D2, f, n.g_d2, n.cat2, f.chunks2, grad);
+    conv(s, B, H2, W2, D2, true, f, n.g_d2, params, n.g_cat2, nullptr, kNone);
+    hipLaunchKernelGGL(k_up_grad, dim3(chan_blocks(B, h2 / 4, 64)), dim3(256), 0, s, n.g_cat2.p, n.g_cat2.bs,
+                       n.g_cat2.ps, B, 64, H2, W2, f.e3b, f.g_e3b);
+    wgrad(s, B, H3, W3, E3B, f, n.g_e3b, n.e3a, f.chunks3, grad);
+    conv(s, B, H3, W3, E3B, true, f, n.g_e3b, params, n.g_e3a, nullptr, n.e3a);
+    wgrad(s, B, H3, W3, E3A, f, n.g_e3a, n.p2, f.chunks3, grad);
+    conv(s, B, H3, W3, E3A, true, f, n.g_e3a, params, n.g_p2, nullptr, kNone);
+    const View sk2 = n.g_cat2.at(64), sk1 = n.g_cat1.at(32);
+    hipLaunchKernelGGL(k_merge, dim3(chan_blocks(B, h2, 32)), dim3(256), 0, s, sk2.p, sk2.bs, sk2.ps, f.g_p2, n.e2b.p,
+                       n.e2b.bs, n.e2b.ps, B, 32, H2, W2, f.g_e2b);
+    wgrad(s, B, H2, W2, E2B, f, n.g_e2b, n.e2a, f.chunks2, grad);
+    conv(s, B, H2, W2, E2B, true, f, n.g_e2b, params, n.g_e2a, nullptr, n.e2a);
+    wgrad(s, B, H2, W2, E2A, f, n.g_e2a, n.p1, f.chunks2, grad);
+    conv(s, B, H2, W2, E2A, true, f, n.g_e2a, params, n.g_p1, nullptr, kNone);
+    hipLaunchKernelGGL(k_merge, dim3(chan_blocks(B, h1, 16)), dim3(256), 0, s, sk1.p, sk1.bs, sk1.ps, f.g_p1, n.e1b.p,
+                       n.e1b.bs, n.e1b.ps, B, 16, H, W, f.g_e1b);
+    wgrad(s, B, H, W, E1B, f, n.g_e1b, n.e1a, f.chunks1, grad);
+    conv(s, B, H, W, E1B, true, f, n.g_e1b, params, n.g_e1a, nullptr, n.e1a);
+    wgrad(s, B, H, W, E1A, f, n.g_e1a, n.x0, f.chunks1, grad);
 }
 
 bool sizes_ok(int B, int H, int W) { return B >= 1 && B <= 1000 && H >= 4 && W >= 4 && H % 4 == 0 && W % 4 == 0 && H <= 8192 && W <= 8192; }
