@@ -81,10 +81,9 @@ struct ConvArgs {
     int H, W;
 };
 
-// Block: 4 waves, each 16 pixels of R consecutive rows from R blockIdx.y,
-// x from blockIdx.x * 64 + 16 * wave; blockIdx.z = image * groups + group,
-// a group being MT <= 4 16-row tiles of output channels (a last group with
-// fewer real tiles repeats its last weight row and stores only its own).
+// Block: 4 waves over 64 pixels (x from blockIdx.x * 64) of R consecutive
+// rows from R blockIdx.y; blockIdx.z = image * groups + group, a group
+// being MT <= 4 16-row tiles of output channels.
 // The block first stages input rows R blockIdx.y - 1 .. + R, x from
 // blockIdx.x * 64 - 1 to + 64 (zero outside the image), of every input
 // channel (padded to CPAD, a multiple of 16, with zeros) in LDS:
@@ -92,7 +91,7 @@ struct ConvArgs {
 // a pixel.  The reduction index is k = tap * CPAD + ci in 32-deep slices of
 // v_mfma_f32_16x16x32_bf16; a lane's eight operands of a slice are eight
 // consecutive channels of one tap, one 16-byte LDS read, and each weight
-// operand serves all R rows.  The 8 spare channel slots per pixel make the
+// operand serves all R rows and all of a wave's column tiles.  The 8 spare channel slots per pixel make the
 // pixel stride an odd multiple of 16 bytes, so the 16 lanes reading one
 // channel group of 16 consecutive pixels touch distinct banks.
 constexpr int kConvCols = 66;
@@ -116,16 +115,35 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
     const int W2 = a.W >> 1;
     const uint16_t* inb = a.in + (int64_t)b * a.in_bs;
     const uint16_t* upb = a.up ? a.up + (int64_t)b * a.up_bs : nullptr;
+    const int n = lane & 15, kg = lane >> 4;
+    const int mt = min(MT, ((a.cout + 15) >> 4) - m0);
+    // Wave w computes output tile m = w % MT (of the group) for CT = 4 / CW
+    // consecutive 16-pixel column tiles from column tile CT (w / MT), so a
+    // block reads each weight row 4 / MT times instead of 4 (MT = 3: waves
+    // 0-2 take all four column tiles, wave 3 only helps with the fill).
+    constexpr int CW = MT == 1 ? 4 : MT == 2 ? 2 : 1;  // waves per tile
+    constexpr int CT = 4 / CW;
+    const int wm = wave % MT, wc = (wave / MT) * CT;
+    const bool busy = wave < MT * CW;
+    // Weight operands run P slices ahead of their use in a register ring;
+    // the first P are in flight during the fill.
+    constexpr int P = SL < 8 ? SL : 8;
+    const uint16_t* wl = a.w + (size_t)((m0 + min(wm, mt - 1)) * 16 + n) * a.kpad + 8 * kg;
+    uint4 wq[P];
+#pragma unroll
+    for (int s = 0; s < P; ++s) wq[s] = *reinterpret_cast<const uint4*>(wl + 32 * s);
     // Fill: item = (row, column, channel group), group fastest, so a wave's
-    // loads walk consecutive 16-byte words of consecutive pixels.  Eight
-    // items' loads are in flight before their stores.  Channels at or past
+    // loads walk consecutive 16-byte words of consecutive pixels.  Up to 12
+    // items' loads per thread are in flight before their stores (one round
+    // trip for all but the widest input).  Channels at or past
     // cin read as zero (a group past cin is not loaded: it may lie beyond
     // the tensor's pixel stride).
     constexpr int items = (R + 2) * kConvCols * G;
-    for (int i0 = threadIdx.x; i0 < items; i0 += 2048) {
-        uint4 v[8];
+    constexpr int U = (items + 255) / 256 < 12 ? (items + 255) / 256 : 12;
+    for (int i0 = threadIdx.x; i0 < items; i0 += 256 * U) {
+        uint4 v[U];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < U; ++u) {
             const int it = i0 + 256 * u;
             const int g = it % G, rc = it / G;
             const int c = rc % kConvCols, r = rc / kConvCols;
@@ -149,7 +167,7 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
             }
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < U; ++u) {
             const int it = i0 + 256 * u;
             if (it < items) {
                 const int g = it % G, rc = it / G;
@@ -158,20 +176,12 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
         }
     }
     __syncthreads();
-    const int x0 = xb + wave * 16;
-    if (x0 >= a.W) return;  // whole wave, after the block's only barrier
-    const int n = lane & 15, kg = lane >> 4;
-    const int x = x0 + n;
-    const int mt = min(MT, ((a.cout + 15) >> 4) - m0);
-    const int col = wave * 16 + n;
-    const uint16_t* wl[MT];
+    if (!busy || wm >= mt || xb + 16 * wc >= a.W) return;  // whole wave, after the block's only barrier
+    v4f acc[CT][R];
 #pragma unroll
-    for (int m = 0; m < MT; ++m) wl[m] = a.w + (size_t)((m0 + min(m, mt - 1)) * 16 + n) * a.kpad + 8 * kg;
-    v4f acc[MT][R];
+    for (int c = 0; c < CT; ++c)
 #pragma unroll
-    for (int m = 0; m < MT; ++m)
-#pragma unroll
-        for (int r = 0; r < R; ++r) acc[m][r] = v4f{0.f, 0.f, 0.f, 0.f};
+        for (int r = 0; r < R; ++r) acc[c][r] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int s = 0; s < SL; ++s) {
         // This lane's operands: k = 32 s + 8 kg .. + 7, one tap t and eight
@@ -180,39 +190,40 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
         const int k = 32 * s + 8 * kg;
         const int t = k / CPAD, ci = k - t * CPAD;
         const int ty = t / 3, tx = t - 3 * ty;
-        v8bf bv[R];
+        const v8bf av = __builtin_bit_cast(v8bf, wq[s % P]);
+        if (s + P < SL) wq[s % P] = *reinterpret_cast<const uint4*>(wl + 32 * (s + P));
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            uint4 q = uint4{0u, 0u, 0u, 0u};
-            if (32 * s + 32 <= 9 * CPAD || t < 9)
-                q = *reinterpret_cast<const uint4*>(s_in + ((r + ty) * kConvCols + col + tx) * PS + ci);
-            bv[r] = __builtin_bit_cast(v8bf, q);
-        }
+        for (int c = 0; c < CT; ++c) {
+            const int col = 16 * (wc + c) + n;
 #pragma unroll
-        for (int m = 0; m < MT; ++m) {
-            const v8bf av = __builtin_bit_cast(v8bf, *reinterpret_cast<const uint4*>(wl[m] + 32 * s));
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                acc[m][r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[r], acc[m][r], 0, 0, 0);
+            for (int r = 0; r < R; ++r) {
+                uint4 q = uint4{0u, 0u, 0u, 0u};
+                if (32 * s + 32 <= 9 * CPAD || t < 9)
+                    q = *reinterpret_cast<const uint4*>(s_in + ((r + ty) * kConvCols + col + tx) * PS + ci);
+                acc[c][r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(v8bf, q), acc[c][r], 0, 0, 0);
+            }
         }
     }
-    if (x >= a.W) return;
-    // Lane holds output channels (m0 + m) * 16 + 4 kg + j, j < 4, of pixel
-    // column n: one 8-byte store per row and tile (cout is a multiple of 4).
+    // Lane holds output channels co .. co + 3 of pixel column n of each
+    // column tile: one 8-byte store per row and tile (cout is a multiple of 4).
+    const int co = (m0 + wm) * 16 + 4 * kg;
+    if (co >= a.cout) return;
+    float bias[4];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int y = y0 + r;
-        if (y >= a.H) continue;
-        const int64_t pix = (int64_t)y * a.W + x;
+    for (int j = 0; j < 4; ++j) bias[j] = a.bias ? a.bias[co + j] : 0.f;
 #pragma unroll
-        for (int m = 0; m < MT; ++m) {
-            if (m >= mt) continue;
-            const int co = (m0 + m) * 16 + 4 * kg;
-            if (co >= a.cout) continue;
+    for (int c = 0; c < CT; ++c) {
+        const int x = xb + 16 * (wc + c) + n;
+        if (x >= a.W) continue;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int y = y0 + r;
+            if (y >= a.H) continue;
+            const int64_t pix = (int64_t)y * a.W + x;
             float v[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                v[j] = acc[m][r][j] + (a.bias ? a.bias[co + j] : 0.f);
+                v[j] = acc[c][r][j] + bias[j];
                 if (a.relu) v[j] = fmaxf(v[j], 0.f);
             }
             if (a.mask) {
