@@ -77,6 +77,11 @@ struct ConvArgs {
     const uint16_t* mask;  // may be null: output zero where mask <= 0 (layout of out)
     int64_t mask_bs;
     int mask_ps;
+    // May be null: also store the 2x2 mean of the (bf16) output, [H/2][W/2]
+    // pixels of pool_ps elements (H and W even).
+    uint16_t* pool;
+    int64_t pool_bs;
+    int pool_ps;
     int relu;
     int H, W;
 };
@@ -211,14 +216,14 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
     float bias[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) bias[j] = a.bias ? a.bias[co + j] : 0.f;
+    float st[CT][R][4];  // the stored values, for the pool
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
         const int x = xb + 16 * (wc + c) + n;
-        if (x >= a.W) continue;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int y = y0 + r;
-            if (y >= a.H) continue;
+            const bool in = x < a.W && y < a.H;
             const int64_t pix = (int64_t)y * a.W + x;
             float v[4];
 #pragma unroll
@@ -226,7 +231,7 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
                 v[j] = acc[c][r][j] + bias[j];
                 if (a.relu) v[j] = fmaxf(v[j], 0.f);
             }
-            if (a.mask) {
+            if (in && a.mask) {
                 const uint2 mk =
                     *reinterpret_cast<const uint2*>(a.mask + (int64_t)b * a.mask_bs + pix * a.mask_ps + co);
                 if (!(bf2f((uint16_t)(mk.x & 0xFFFFu)) > 0.f)) v[0] = 0.f;
@@ -234,15 +239,47 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
                 if (!(bf2f((uint16_t)(mk.y & 0xFFFFu)) > 0.f)) v[2] = 0.f;
                 if (!(bf2f((uint16_t)(mk.y >> 16)) > 0.f)) v[3] = 0.f;
             }
+            uint16_t h[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                h[j] = f2bf(v[j]);
+                st[c][r][j] = bf2f(h[j]);
+            }
+            if (!in) continue;
             if (a.out_f) {
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     a.out_f[(int64_t)b * a.out_bs + (int64_t)(co + j) * a.H * a.W + pix] = v[j];
             } else {
                 *reinterpret_cast<uint2*>(a.out + (int64_t)b * a.out_bs + pix * a.out_ps + co) =
-                    uint2{(uint32_t)f2bf(v[0]) | ((uint32_t)f2bf(v[1]) << 16),
-                          (uint32_t)f2bf(v[2]) | ((uint32_t)f2bf(v[3]) << 16)};
+                    uint2{(uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16)};
             }
+        }
+    }
+    if (!a.pool) return;
+    // 2x2 mean of the stored values: rows r and r + 1 of the lane (R and the
+    // block's first row are even), columns of lanes n and n ^ 1 (same kg),
+    // summed in the order (x, y), (x + 1, y), (x, y + 1), (x + 1, y + 1).
+    // With W and H even a pair of columns or rows is inside the image or
+    // outside together.
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+        const int x = xb + 16 * (wc + c) + n;
+#pragma unroll
+        for (int r = 0; r < R; r += 2) {
+            const int y = y0 + r;
+            float q[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float s0 = st[c][r][j], s2 = st[c][r + 1][j];
+                const float s1 = __shfl_xor(s0, 1, 64), s3 = __shfl_xor(s2, 1, 64);
+                q[j] = 0.25f * (((s0 + s1) + s2) + s3);
+            }
+            if ((n & 1) || x >= a.W || y >= a.H) continue;
+            const int64_t pp = (int64_t)(y >> 1) * (a.W >> 1) + (x >> 1);
+            *reinterpret_cast<uint2*>(a.pool + (int64_t)b * a.pool_bs + pp * a.pool_ps + co) =
+                uint2{(uint32_t)f2bf(q[0]) | ((uint32_t)f2bf(q[1]) << 16),
+                      (uint32_t)f2bf(q[2]) | ((uint32_t)f2bf(q[3]) << 16)};
         }
     }
 }
@@ -425,25 +462,6 @@ __device__ __forceinline__ bool item(int64_t B, int64_t n, int C, int64_t& b, in
     b = bp / n;
     p = bp - b * n;
     return true;
-}
-
-// 2x2 mean of C channels of in (pixel stride in_ps) into out [B][H/2][W/2][C].
-__global__ __launch_bounds__(256) void k_pool(const uint16_t* __restrict__ in, int64_t in_bs, int in_ps, int B, int C,
-                                              int H, int W, uint16_t* __restrict__ out) {
-    const int h = H / 2, w = W / 2;
-    int64_t b, p;
-    int c;
-    if (!item(B, (int64_t)h * w, C, b, p, c)) return;
-    const int Y = (int)(p / w), X = (int)(p - (int64_t)Y * w);
-    const uint16_t* q = in + b * in_bs + ((int64_t)(2 * Y) * W + 2 * X) * in_ps + c;
-    float f0[8], f1[8], f2[8], f3[8], o[8];
-    unpack8(ld8(q), f0);
-    unpack8(ld8(q + in_ps), f1);
-    unpack8(ld8(q + (int64_t)W * in_ps), f2);
-    unpack8(ld8(q + (int64_t)(W + 1) * in_ps), f3);
-#pragma unroll
-    for (int k = 0; k < 8; ++k) o[k] = 0.25f * (((f0[k] + f1[k]) + f2[k]) + f3[k]);
-    st8(out + (b * h * w + p) * C + c, pack8(o));
 }
 
 // Nearest 2x upsample of [B][h][w][C] into the first C channel slots of a
@@ -796,7 +814,7 @@ const View kNone{nullptr, 0, 0};
 // input channels, read through the nearest 2x upsample.  out_f (fp32
 // planes) replaces out when set.
 void conv(hipStream_t s, int B, int H, int W, int l, bool transpose, const Bufs& f, View in, const float* params,
-          View out, float* out_f, View mask, View up = kNone, int up_c = 0) {
+          View out, float* out_f, View mask, View up = kNone, int up_c = 0, View pool = kNone) {
     ConvArgs a{};
     a.in = in.p;
     a.in_bs = in.bs;
@@ -818,6 +836,9 @@ void conv(hipStream_t s, int B, int H, int W, int l, bool transpose, const Bufs&
     a.mask = mask.p;
     a.mask_bs = mask.bs;
     a.mask_ps = mask.ps;
+    a.pool = pool.p;
+    a.pool_bs = pool.bs;
+    a.pool_ps = pool.ps;
     a.relu = transpose ? 0 : kNet[l].relu;
     a.H = H;
     a.W = W;
@@ -915,17 +936,14 @@ void forward(hipStream_t s, int B, int H, int W, const float* params, const floa
         }
     hipLaunchKernelGGL(k_pack, dim3(blocks(J.start[J.n])), dim3(256), 0, s, J);
     const Net n = views(f, H, W);
-    const int64_t h1 = (int64_t)H * W, h2 = h1 / 4, h3 = h1 / 16;
+    const int64_t h1 = (int64_t)H * W, h2 = h1 / 4;
     const int H2 = H / 2, W2 = W / 2, H3 = H / 4, W3 = W / 4;
     hipLaunchKernelGGL(k_input, dim3(blocks(B * h1)), dim3(256), 0, s, rgb, z, hole, B, (int)h1, f.x0);
     conv(s, B, H, W, E1A, false, f, n.x0, params, n.e1a, nullptr, kNone);
-    conv(s, B, H, W, E1B, false, f, n.e1a, params, n.e1b, nullptr, kNone);
-    hipLaunchKernelGGL(k_pool, dim3(chan_blocks(B, h2, 16)), dim3(256), 0, s, n.e1b.p, n.e1b.bs, n.e1b.ps, B, 16, H, W,
-                       f.p1);
+    // The encoders' second convolutions also store the pooled output.
+    conv(s, B, H, W, E1B, false, f, n.e1a, params, n.e1b, nullptr, kNone, kNone, 0, n.p1);
     conv(s, B, H2, W2, E2A, false, f, n.p1, params, n.e2a, nullptr, kNone);
-    conv(s, B, H2, W2, E2B, false, f, n.e2a, params, n.e2b, nullptr, kNone);
-    hipLaunchKernelGGL(k_pool, dim3(chan_blocks(B, h3, 32)), dim3(256), 0, s, n.e2b.p, n.e2b.bs, n.e2b.ps, B, 32, H2,
-                       W2, f.p2);
+    conv(s, B, H2, W2, E2B, false, f, n.e2a, params, n.e2b, nullptr, kNone, kNone, 0, n.p2);
     conv(s, B, H3, W3, E3A, false, f, n.p2, params, n.e3a, nullptr, kNone);
     conv(s, B, H3, W3, E3B, false, f, n.e3a, params, n.e3b, nullptr, kNone);
     // The decoders read their upsampled channels straight from the coarser
