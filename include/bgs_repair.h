@@ -72,6 +72,16 @@ BGS_API int32_t bgs_repair_grad(const float* params, int32_t batch, int32_t heig
                                 float* grad, float* loss, float* rgb_out, void* ws, size_t ws_bytes,
                                 void* hip_stream);
 
+/* Block shape of the convolution launches, for every later call in the
+ * process: rows = output rows per block (2 or 4; inputs wider than 64
+ * channels always take 2), tiles = 16-channel output tiles per block (1-4,
+ * capped at the layer's).  0 leaves the choice to the library, which picks
+ * from the grid size (the default).  Results do not depend on the shape: a
+ * pixel's sums run in the same order under every shape.  Not synchronised
+ * with calls in flight on other host threads.  BGS_ERR_INVALID_ARG for
+ * other values. */
+BGS_API int32_t bgs_repair_set_block_shape(int32_t rows, int32_t tiles);
+
 /* One Adam step (Kingma and Ba, 2015) over n parameters, step >= 1 the
  * 1-based step count used for the bias correction; params, m and v are
  * updated in place (fp32). */

@@ -75,7 +75,7 @@ EXPORTS = [
     "bgs_graph_destroy",
     # include/bgs_repair.h
     "bgs_repair_num_params", "bgs_repair_workspace_size", "bgs_repair_forward", "bgs_repair_grad",
-    "bgs_repair_adam", "bgs_repair_hole_error",
+    "bgs_repair_adam", "bgs_repair_hole_error", "bgs_repair_set_block_shape",
 ]
 
 _lib = None
@@ -131,6 +131,7 @@ def load():
         "bgs_repair_grad": [P, I32, I32, I32, P, P, P, P, P, P, P, P, SZ, P],
         "bgs_repair_adam": [P, P, P, P, I64, I32, C.c_float, C.c_float, C.c_float, C.c_float, P],
         "bgs_repair_hole_error": [P, P, I32, I32, I32, P, P, P],
+        "bgs_repair_set_block_shape": [I32, I32],
     }
     for name, args in sig.items():
         f = getattr(L, name)

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 
@@ -785,15 +786,22 @@ void launch_conv(hipStream_t s, int B, int mt, const ConvArgs& a) {
 // else two; then fewer output tiles per block until there are at least four
 // blocks per CU, since the coarse levels have few pixels.  Four rows of 96
 // staged channels would take 85 KB of LDS; that width keeps two rows.
+// bgs_repair_set_block_shape may fix either choice (0: automatic).
+std::atomic<int> g_rows{0}, g_tiles{0};
+
 template <int CPAD>
 void launch_conv(hipStream_t s, int B, const ConvArgs& a) {
     const int tiles = (a.cout + 15) / 16;
     auto nblk = [&](int r, int mt) {
         return (int64_t)((a.W + 63) / 64) * ((a.H + r - 1) / r) * B * ((tiles + mt - 1) / mt);
     };
+    const int fr = g_rows.load(), ft = g_tiles.load();
     int mt = std::min(4, tiles);
-    const int r = (CPAD <= 64 && nblk(4, mt) >= 6 * 256) ? 4 : 2;
-    while (mt > 1 && nblk(r, mt) < 4 * 256) mt = (mt + 1) / 2;
+    const int r = CPAD > 64 ? 2 : fr ? fr : nblk(4, mt) >= 6 * 256 ? 4 : 2;
+    if (ft)
+        mt = std::min(ft, tiles);
+    else
+        while (mt > 1 && nblk(r, mt) < 4 * 256) mt = (mt + 1) / 2;
     if (CPAD <= 64 && r == 4)
         launch_conv<CPAD, (CPAD <= 64 ? 4 : 2)>(s, B, mt, a);
     else
@@ -1063,6 +1071,13 @@ BGS_API int32_t bgs_repair_grad(const float* params, int32_t batch, int32_t heig
                        (const float*)f.n_hole, loss);
     backward(s, batch, height, width, params, f, grad);
     return launched();
+}
+
+BGS_API int32_t bgs_repair_set_block_shape(int32_t rows, int32_t tiles) {
+    if (!(rows == 0 || rows == 2 || rows == 4) || tiles < 0 || tiles > 4) return BGS_ERR_INVALID_ARG;
+    g_rows.store(rows);
+    g_tiles.store(tiles);
+    return BGS_OK;
 }
 
 BGS_API int32_t bgs_repair_adam(float* params, const float* grad, float* m, float* v, int64_t n, int32_t step,

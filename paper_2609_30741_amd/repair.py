@@ -45,6 +45,13 @@ def num_params() -> int:
     return int(n.value)
 
 
+def set_block_shape(rows: int = 0, tiles: int = 0) -> None:
+    """Fix the convolutions' output rows (2 or 4) and 16-channel output
+    tiles (1-4) per block for later calls; 0 restores the library's own
+    choice (bgs_repair_set_block_shape)."""
+    _check(_abi.load().bgs_repair_set_block_shape(int(rows), int(tiles)), "bgs_repair_set_block_shape")
+
+
 # Pixel count of each layer's level relative to the full image.
 LEVEL_SCALE = [1.0, 1.0, 0.25, 0.25, 1.0 / 16, 1.0 / 16, 0.25, 1.0, 1.0]
 

@@ -89,6 +89,50 @@ def test_gradient_matches_oracle(B, H, W):
         assert np.abs(a - b).max() <= 2e-2 * np.abs(b).max() + 1e-12, name
 
 
+@pytest.mark.parametrize("B,H,W", [(2, 16, 72), (1, 12, 20)])
+def test_every_block_shape_gives_identical_results(B, H, W):
+    # Output rows and 16-channel output tiles per convolution block are a
+    # launch choice (the library picks them from the grid size; these sizes
+    # take 2 rows).  A pixel's sums run in the same order under every
+    # shape, so the forward output, the error channel and the gradient are
+    # bit-identical across shapes; the 4-row shapes are also checked against
+    # the oracle.  Tiles 3 and 4 split the 48- and 96-channel input
+    # gradients into a full and a partial group; (1, 12, 20) has odd sides
+    # at the coarsest level.
+    p, rgb, z, hole, target = _problem(5, B, H, W)
+    g_rgb, g_z, g_hole, g_t = _dev(rgb, z, hole, target)
+    shapes = [(0, 0), (2, 1), (2, 2), (2, 3), (2, 4), (4, 1), (4, 2), (4, 3), (4, 4)]
+    res = []
+    try:
+        for rows, tiles in shapes:
+            repair.set_block_shape(rows, tiles)
+            net = repair.Repair(params=p)
+            err = torch.empty((B, H, W), device="cuda")
+            out = net.forward(g_rgb, g_z, g_hole, err=err)
+            loss = net.grad_step(g_rgb, g_z, g_hole, g_t)
+            torch.cuda.synchronize()
+            res.append((out.cpu().numpy(), err.cpu().numpy(), net.grad.cpu().numpy().copy(), float(loss.item())))
+    finally:
+        repair.set_block_shape(0, 0)
+    for (rows, tiles), (o, e, g, ls) in zip(shapes[1:], res[1:]):
+        assert np.array_equal(o, res[0][0]), (rows, tiles)
+        assert np.array_equal(e, res[0][1]), (rows, tiles)
+        assert np.array_equal(g, res[0][2]), (rows, tiles)
+        assert ls == res[0][3], (rows, tiles)
+    a = R.forward(p.astype(np.float64), rgb, z, hole, q=R.bf16)
+    r_got = (res[5][0].astype(np.float64) - rgb) * hole[:, None]
+    r_want = a["r"][:, :3] * hole[:, None]
+    scale = np.abs(r_want).max()
+    assert np.abs(r_got - r_want).max() <= 1e-2 * scale
+    assert np.linalg.norm(r_got - r_want) <= 3e-3 * np.linalg.norm(r_want)
+
+
+def test_block_shape_rejects_bad_values():
+    L = repair._abi.load()
+    for rows, tiles in [(1, 0), (3, 0), (8, 0), (0, -1), (0, 5)]:
+        assert L.bgs_repair_set_block_shape(rows, tiles) == repair._abi.ERR_INVALID_ARG
+
+
 def test_gradient_of_an_all_hole_free_batch_is_zero():
     # No holes: the loss and every gradient are exactly zero.
     p, rgb, z, hole, target = _problem(3, 1, 8, 16)
