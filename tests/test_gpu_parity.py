@@ -99,6 +99,33 @@ def test_sort_pairs_bit_exact(ctx, n, bits):
     assert np.array_equal(to_np(vt).view(np.uint32), vals[order])
 
 
+@pytest.mark.parametrize("n,bits", [(5_900_001, 13), (19_600_003, 13), (100_000_000, 32)])
+def test_sort_pairs_bit_exact_large(ctx, n, bits):
+    # The tile sorts' sizes (5.9M keys at 800x600, 19.6M at 1600x1064) and
+    # 10^8 keys.  The values are the input positions, so the stable sort is
+    # the one order in which (masked key, value) strictly increases; with the
+    # values a permutation and every key still paired with its value, that
+    # pins the output bit for bit without a reference sort.
+    log(f"sort n={n} bits={bits}")
+    keys, vals = synth.random_sort_keys(n, seed=n + bits, key_bits=32)
+    kt = torch.from_numpy(keys.view(np.int32).copy()).cuda()
+    vt = torch.from_numpy(vals.view(np.int32).copy()).cuda()
+    ctx.sort_pairs(kt, vt, bits)
+    torch.cuda.synchronize()
+    ko, vo = to_np(kt).view(np.uint32), to_np(vt).view(np.uint32)
+    del kt, vt
+    assert int(vo.max()) < n
+    seen = np.zeros(n, dtype=bool)
+    seen[vo] = True
+    assert seen.all()  # a permutation of the positions
+    assert np.array_equal(ko, keys[vo])
+    mask = np.uint32((1 << bits) - 1) if bits < 32 else np.uint32(0xFFFFFFFF)
+    mk = (ko & mask).astype(np.int64)
+    dk = mk[1:] - mk[:-1]
+    dv = vo[1:].astype(np.int64) - vo[:-1].astype(np.int64)
+    assert np.all((dk > 0) | ((dk == 0) & (dv > 0)))
+
+
 @pytest.mark.parametrize("shape", [(45, 67), (200, 301), (1, 1), (17, 1)])
 @pytest.mark.parametrize("case", ["rand05", "rand30", "rand60", "checker", "serpentine", "empty", "full"])
 @pytest.mark.parametrize("conn", [4, 8])
