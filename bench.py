@@ -547,6 +547,9 @@ def main():
     ap.add_argument("--traffic-probe-stereo", action="store_true",
                     help="no timing: 48 stereo frames of the workload at the default blend split (16 sizing the "
                          "workspace, then 32), for per-kernel rocprofv3 counter runs")
+    ap.add_argument("--sort-probe", action="store_true",
+                    help="the pair sort alone at the tile sorts' sizes and at 10^8 keys: one JSON line per case "
+                         "(best of 5 timed sorts), then the copy calibration for counter runs")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="no timing: a 512 MiB copy (counter calibration), then 12 dominant-eye renders of the "
                          "workload, for rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs")
@@ -564,6 +567,9 @@ def main():
         sys.exit(3)
     torch.cuda.set_device(0)
 
+    if args.sort_probe:
+        sort_probe()
+        return
     if args.traffic_probe:
         traffic_probe(args)
         return
@@ -687,6 +693,46 @@ def copy_calibration():
         b.copy_(a)
     torch.cuda.synchronize()
     del a, b
+
+
+def sort_probe():
+    """bgs_sort_pairs on random 31-bit keys with values: 19.6M keys (the
+    1600x1064 tile sort's size) and 10^8 keys by 13 bits (two passes of 7
+    and 6 bits, the tile sorts' digits), and 10^8 keys by 32 bits (four
+    8-bit passes).  Each case: one untimed sort, then the best of 5 sorts
+    of the same input timed with events on the context's stream.  Then the
+    copy calibration, so counter runs of this command can be scaled."""
+    import torch
+    from paper_2609_30741_amd import api
+
+    ctx = api.Context(sync=False)
+    for n, bits in [(19_600_000, 13), (100_000_000, 13), (100_000_000, 32)]:
+        g = torch.Generator(device="cuda").manual_seed(1)
+        k0 = torch.randint(0, 2**31 - 1, (n,), device="cuda", dtype=torch.int32, generator=g)
+        v0 = torch.arange(n, device="cuda", dtype=torch.int32)
+        k, v = k0.clone(), v0.clone()
+        ctx.sort_pairs(k, v, bits)
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(5):
+            k.copy_(k0)
+            v.copy_(v0)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            ctx.sort_pairs(k, v, bits)
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        passes = 2 if bits <= 14 else (bits + 7) // 8
+        # Algorithmic bytes per pass: the histogram reads the keys (4 B), the
+        # scatter reads and writes keys and values (16 B).
+        gbs = 20.0 * n * passes / (best * 1e-3) / 1e9
+        print(json.dumps({"sort_keys": n, "key_bits": bits, "passes": passes, "ms": round(best, 4),
+                          "GB_per_s": round(gbs, 1), "frac_of_8TBps": round(gbs / 8000.0, 4)}), flush=True)
+        del k, v, k0, v0
+    copy_calibration()
+    log("sort probe done")
 
 
 def traffic_probe(args):
