@@ -367,16 +367,24 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
 }
 
 // grad (the layer's W[cout][K] then b[cout]) from the partials in a fixed
-// chunk order.
+// order: block of 64 outputs; wave q adds the q-th quarter of the chunks in
+// chunk order, then ((q0 + q1) + (q2 + q3)).
 __global__ __launch_bounds__(256) void k_wgrad_reduce(const float* __restrict__ part, int chunks, int cout, int K,
                                                       float* __restrict__ grad) {
+    __shared__ float s_q[4][64];
     const int KC = K + 1;
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= cout * KC) return;
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + lane;
+    const int per = (chunks + 3) / 4, c0 = q * per, c1 = min(chunks, c0 + per);
     float s = 0.f;
-    for (int c = 0; c < chunks; ++c) s += part[(size_t)c * cout * KC + i];
+    if (i < cout * KC)
+        for (int c = c0; c < c1; ++c) s += part[(size_t)c * cout * KC + i];
+    s_q[q][lane] = s;
+    __syncthreads();
+    if (q != 0 || i >= cout * KC) return;
+    const float v = (s_q[0][lane] + s_q[1][lane]) + (s_q[2][lane] + s_q[3][lane]);
     const int co = i / KC, col = i - co * KC;
-    grad[col < K ? co * K + col : cout * K + co] = s;
+    grad[col < K ? co * K + col : cout * K + co] = v;
 }
 
 __device__ __forceinline__ float block_sum(float v, float* red) {
@@ -877,8 +885,8 @@ void wgrad(hipStream_t s, int B, int H, int W, int l, const Bufs& f, View g, Vie
     const int K = a.cin * 9;
     const int nt = (K + 1 + 15) / 16;
     hipLaunchKernelGGL(k_wgrad, dim3((nt + 3) / 4, chunks), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks((int64_t)a.cout * (K + 1))), dim3(256), 0, s, (const float*)f.part,
-                       chunks, a.cout, K, grad + param_offset(l));
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)(((int64_t)a.cout * (K + 1) + 63) / 64)), dim3(256), 0, s,
+                       (const float*)f.part, chunks, a.cout, K, grad + param_offset(l));
 }
 
 // The tensors of one pass, as views.
