@@ -10,9 +10,11 @@
 // over pixels: each block accumulates a slab of rows into per-block
 // partials that a second kernel adds in a fixed order, so results are
 // deterministic.  Activations and gradients between layers are stored as
-// bf16 planes [B][C][H][W]; a layer may read or write a channel slice of a
-// larger tensor (per-image stride), which is how the skip connections land
-// in the decoder's concatenated inputs without copies.
+// bf16 [B][H][W][C], channels innermost; a layer may read or write a
+// channel slice of a larger tensor (the pixel stride exceeds the slice),
+// which is how the skip connections land in the decoder's concatenated
+// inputs without copies.  The images the network reads and writes are
+// planar fp32.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
