@@ -63,8 +63,8 @@ struct ConvArgs {
     int cin;
     // Optional half-resolution source of input channels [0, up_c): read at
     // (y / 2, x / 2), the nearest 2x upsample, so a decoder's concatenated
-    // input needs no upsampled copy.  Channels [up_c, cin) come from in,
-    // whose first up_c channel slots are then not read.
+    // input needs no upsampled copy.  Channel ci >= up_c is channel
+    // ci - up_c of in.
     const uint16_t* up;
     int64_t up_bs;
     int up_ps;
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
             if (ok) {
                 const uint16_t* src = ci < a.up_c
                                           ? upb + ((int64_t)(yy >> 1) * W2 + (xx >> 1)) * a.up_ps + ci
-                                          : inb + ((int64_t)yy * a.W + xx) * a.in_ps + ci;
+                                          : inb + ((int64_t)yy * a.W + xx) * a.in_ps + (ci - a.up_c);
                 v[u] = *reinterpret_cast<const uint4*>(src);
                 const int left = a.cin - ci;  // channels of this group that exist
                 if (left < 8) {
@@ -781,22 +781,34 @@ void launch_conv(hipStream_t s, int B, const ConvArgs& a) {
                        conv_lds_bytes(CPAD, R), s, a);
 }
 
+// mt <= 2 when R is 8 (more tiles would not fit in registers).
 template <int CPAD, int R>
 void launch_conv(hipStream_t s, int B, int mt, const ConvArgs& a) {
-    switch (mt) {
-        case 1: launch_conv<CPAD, 1, R>(s, B, a); break;
-        case 2: launch_conv<CPAD, 2, R>(s, B, a); break;
-        case 3: launch_conv<CPAD, 3, R>(s, B, a); break;
-        default: launch_conv<CPAD, 4, R>(s, B, a); break;
+    if constexpr (R == 8) {
+        if (mt == 1)
+            launch_conv<CPAD, 1, R>(s, B, a);
+        else
+            launch_conv<CPAD, 2, R>(s, B, a);
+    } else {
+        switch (mt) {
+            case 1: launch_conv<CPAD, 1, R>(s, B, a); break;
+            case 2: launch_conv<CPAD, 2, R>(s, B, a); break;
+            case 3: launch_conv<CPAD, 3, R>(s, B, a); break;
+            default: launch_conv<CPAD, 4, R>(s, B, a); break;
+        }
     }
 }
 
 // Block shape: four output rows per block where that still leaves at least
 // six blocks per CU (they share the two halo rows and each weight operand),
-// else two; then fewer output tiles per block until there are at least four
-// blocks per CU, since the coarse levels have few pixels.  Four rows of 96
+// else two; then fewer output tiles per block until there are at least two
+// blocks per CU, since the coarse levels have few pixels (at 200x150, two
+// tiles over 600 blocks beat one tile over 1200: 11.6 against 16.7 us for
+// the 64-channel layer).  Four rows of 96
 // staged channels would take 85 KB of LDS; that width keeps two rows.
-// bgs_repair_set_block_shape may fix either choice (0: automatic).
+// bgs_repair_set_block_shape may fix either choice (0: automatic), and may
+// ask for eight rows, which inputs of up to 32 channels take with up to two
+// output tiles.
 std::atomic<int> g_rows{0}, g_tiles{0};
 
 template <int CPAD>
@@ -807,13 +819,19 @@ void launch_conv(hipStream_t s, int B, const ConvArgs& a) {
     };
     const int fr = g_rows.load(), ft = g_tiles.load();
     int mt = std::min(4, tiles);
-    const int r = CPAD > 64 ? 2 : fr ? fr : nblk(4, mt) >= 6 * 256 ? 4 : 2;
+    // Largest row count this width's LDS allows: 8 rows up to 32 staged
+    // channels, 4 up to 64, else 2.
+    constexpr int kMaxRows = CPAD <= 32 ? 8 : CPAD <= 64 ? 4 : 2;
+    int r = std::min(kMaxRows, fr ? fr : nblk(4, mt) >= 6 * 256 ? 4 : 2);
     if (ft)
         mt = std::min(ft, tiles);
     else
-        while (mt > 1 && nblk(r, mt) < 4 * 256) mt = (mt + 1) / 2;
-    if (CPAD <= 64 && r == 4)
-        launch_conv<CPAD, (CPAD <= 64 ? 4 : 2)>(s, B, mt, a);
+        while (mt > 1 && nblk(r, mt) < 2 * 256) mt = (mt + 1) / 2;
+    if (r == 8 && mt > 2) r = 4;
+    if (r == 8)
+        launch_conv<CPAD, (kMaxRows >= 8 ? 8 : 2)>(s, B, mt, a);
+    else if (r == 4)
+        launch_conv<CPAD, (kMaxRows >= 4 ? 4 : 2)>(s, B, mt, a);
     else
         launch_conv<CPAD, 2>(s, B, mt, a);
 }
@@ -897,18 +915,21 @@ struct Net {
     View g_r, g_d1, g_cat1, g_d2, g_cat2, g_e3b, g_e3a, g_p2, g_e2b, g_e2a, g_p1, g_e1b, g_e1a;
 };
 
-Net views(const Bufs& f, int H, int W) {
+// Training keeps each decoder's concatenated input whole (the weight
+// gradient reads it), the skip connection in its last channels; inference
+// stores the skip tensors dense, in the same memory.
+Net views(const Bufs& f, int H, int W, bool train) {
     const int64_t h1 = (int64_t)H * W, h2 = h1 / 4, h3 = h1 / 16;
     auto v = [](uint16_t* p, int c, int64_t hw) { return View{p, c * hw, c}; };
     Net n;
     n.x0 = v(f.x0, 8, h1);
     n.e1a = v(f.e1a, 16, h1);
     n.cat1 = v(f.cat1, 48, h1);  // up(d2) in channels 0-31, e1b in 32-47
-    n.e1b = n.cat1.at(32);
+    n.e1b = train ? n.cat1.at(32) : v(f.cat1, 16, h1);
     n.p1 = v(f.p1, 16, h2);
     n.e2a = v(f.e2a, 32, h2);
     n.cat2 = v(f.cat2, 96, h2);  // up(e3b) in channels 0-63, e2b in 64-95
-    n.e2b = n.cat2.at(64);
+    n.e2b = train ? n.cat2.at(64) : v(f.cat2, 32, h2);
     n.p2 = v(f.p2, 32, h3);
     n.e3a = v(f.e3a, 64, h3);
     n.e3b = v(f.e3b, 64, h3);
@@ -953,7 +974,7 @@ void forward(hipStream_t s, int B, int H, int W, const float* params, const floa
             ++J.n;
         }
     hipLaunchKernelGGL(k_pack, dim3(blocks(J.start[J.n])), dim3(256), 0, s, J);
-    const Net n = views(f, H, W);
+    const Net n = views(f, H, W, train);
     const int64_t h1 = (int64_t)H * W, h2 = h1 / 4;
     const int H2 = H / 2, W2 = W / 2, H3 = H / 4, W3 = W / 4;
     hipLaunchKernelGGL(k_input, dim3(blocks(B * h1)), dim3(256), 0, s, rgb, z, hole, B, (int)h1, f.x0);
@@ -970,16 +991,16 @@ void forward(hipStream_t s, int B, int H, int W, const float* params, const floa
     if (train)
         hipLaunchKernelGGL(k_up, dim3(chan_blocks(B, h2, 64)), dim3(256), 0, s, f.e3b, B, 64, H3, W3, n.cat2.p,
                            n.cat2.bs, n.cat2.ps);
-    conv(s, B, H2, W2, D2, false, f, n.cat2, params, n.d2, nullptr, kNone, n.e3b, 64);
+    conv(s, B, H2, W2, D2, false, f, n.e2b, params, n.d2, nullptr, kNone, n.e3b, 64);
     if (train)
         hipLaunchKernelGGL(k_up, dim3(chan_blocks(B, h1, 32)), dim3(256), 0, s, f.d2, B, 32, H2, W2, n.cat1.p,
                            n.cat1.bs, n.cat1.ps);
-    conv(s, B, H, W, D1, false, f, n.cat1, params, n.d1, nullptr, kNone, n.d2, 32);
+    conv(s, B, H, W, D1, false, f, n.e1b, params, n.d1, nullptr, kNone, n.d2, 32);
     conv(s, B, H, W, OUT, false, f, n.d1, params, kNone, f.r, kNone);
 }
 
 void backward(hipStream_t s, int B, int H, int W, const float* params, const Bufs& f, float* grad) {
-    const Net n = views(f, H, W);
+    const Net n = views(f, H, W, true);
     const int64_t h1 = (int64_t)H * W, h2 = h1 / 4;
     const int H2 = H / 2, W2 = W / 2, H3 = H / 4, W3 = W / 4;
     wgrad(s, B, H, W, OUT, f, n.g_r, n.d1, f.chunks1, grad);
@@ -1084,7 +1105,7 @@ BGS_API int32_t bgs_repair_grad(const float* params, int32_t batch, int32_t heig
 }
 
 BGS_API int32_t bgs_repair_set_block_shape(int32_t rows, int32_t tiles) {
-    if (!(rows == 0 || rows == 2 || rows == 4) || tiles < 0 || tiles > 4) return BGS_ERR_INVALID_ARG;
+    if (!(rows == 0 || rows == 2 || rows == 4 || rows == 8) || tiles < 0 || tiles > 4) return BGS_ERR_INVALID_ARG;
     g_rows.store(rows);
     g_tiles.store(tiles);
     return BGS_OK;

@@ -46,7 +46,7 @@ def num_params() -> int:
 
 
 def set_block_shape(rows: int = 0, tiles: int = 0) -> None:
-    """Fix the convolutions' output rows (2 or 4) and 16-channel output
+    """Fix the convolutions' output rows (2, 4 or 8) and 16-channel output
     tiles (1-4) per block for later calls; 0 restores the library's own
     choice (bgs_repair_set_block_shape)."""
     _check(_abi.load().bgs_repair_set_block_shape(int(rows), int(tiles)), "bgs_repair_set_block_shape")

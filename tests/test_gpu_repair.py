@@ -93,7 +93,7 @@ def test_gradient_matches_oracle(B, H, W):
 def test_every_block_shape_gives_identical_results(B, H, W):
     # Output rows and 16-channel output tiles per convolution block are a
     # launch choice (the library picks them from the grid size; these sizes
-    # take 2 rows).  A pixel's sums run in the same order under every
+    # take 2 rows; 8 rows apply to inputs of up to 32 channels).  A pixel's sums run in the same order under every
     # shape, so the forward output, the error channel and the gradient are
     # bit-identical across shapes; the 4-row shapes are also checked against
     # the oracle.  Tiles 3 and 4 split the 48- and 96-channel input
@@ -101,7 +101,7 @@ def test_every_block_shape_gives_identical_results(B, H, W):
     # at the coarsest level.
     p, rgb, z, hole, target = _problem(5, B, H, W)
     g_rgb, g_z, g_hole, g_t = _dev(rgb, z, hole, target)
-    shapes = [(0, 0), (2, 1), (2, 2), (2, 3), (2, 4), (4, 1), (4, 2), (4, 3), (4, 4)]
+    shapes = [(0, 0), (2, 1), (2, 2), (2, 3), (2, 4), (4, 1), (4, 2), (4, 3), (4, 4), (8, 1), (8, 2), (8, 4)]
     res = []
     try:
         for rows, tiles in shapes:
@@ -129,7 +129,7 @@ def test_every_block_shape_gives_identical_results(B, H, W):
 
 def test_block_shape_rejects_bad_values():
     L = repair._abi.load()
-    for rows, tiles in [(1, 0), (3, 0), (8, 0), (0, -1), (0, 5)]:
+    for rows, tiles in [(1, 0), (3, 0), (6, 0), (16, 0), (0, -1), (0, 5)]:
         assert L.bgs_repair_set_block_shape(rows, tiles) == repair._abi.ERR_INVALID_ARG
 
 
