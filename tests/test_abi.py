@@ -185,3 +185,12 @@ def test_repair_parameter_count_and_argument_checks(L):
     assert L.bgs_repair_adam(fake, fake, fake, fake, 0, 1, 1e-3, 0.9, 0.999, 1e-8, None) == _abi.ERR_INVALID_ARG
     assert L.bgs_repair_adam(fake, fake, fake, fake, 10, 0, 1e-3, 0.9, 0.999, 1e-8, None) == _abi.ERR_INVALID_ARG
     assert L.bgs_repair_adam(fake, fake, fake, fake, 10, 1, 1e-3, 1.0, 0.999, 1e-8, None) == _abi.ERR_INVALID_ARG
+
+
+def test_repair_block_shape_validation(L):
+    # Rows 0 (automatic), 2, 4 or 8; tiles 0 (automatic) to 4.  The call only
+    # records the choice, so it runs without a device.
+    for rows, tiles in [(1, 0), (3, 0), (6, 0), (16, 0), (-2, 0), (0, -1), (0, 5)]:
+        assert L.bgs_repair_set_block_shape(rows, tiles) == _abi.ERR_INVALID_ARG, (rows, tiles)
+    for rows, tiles in [(2, 1), (4, 3), (8, 2), (0, 4), (0, 0)]:
+        assert L.bgs_repair_set_block_shape(rows, tiles) == _abi.OK, (rows, tiles)

@@ -127,12 +127,6 @@ def test_every_block_shape_gives_identical_results(B, H, W):
     assert np.linalg.norm(r_got - r_want) <= 3e-3 * np.linalg.norm(r_want)
 
 
-def test_block_shape_rejects_bad_values():
-    L = repair._abi.load()
-    for rows, tiles in [(1, 0), (3, 0), (6, 0), (16, 0), (0, -1), (0, 5)]:
-        assert L.bgs_repair_set_block_shape(rows, tiles) == repair._abi.ERR_INVALID_ARG
-
-
 def test_gradient_of_an_all_hole_free_batch_is_zero():
     # No holes: the loss and every gradient are exactly zero.
     p, rgb, z, hole, target = _problem(3, 1, 8, 16)
