@@ -74,9 +74,9 @@ BGS_API int32_t bgs_repair_grad(const float* params, int32_t batch, int32_t heig
 
 /* Block shape of the convolution launches, for every later call in the
  * process: rows = output rows per block (2, 4 or 8; inputs wider than 64
- * channels always take 2, wider than 32 at most 4, and 8 rows take at most
- * two output tiles, else 4 rows), tiles = 16-channel output tiles per block
- * (1-4, capped at the layer's).  0 leaves the choice to the library, which picks
+ * channels take at most 4, and 8 rows, or 4 rows of such inputs, take at
+ * most two output tiles, else fewer rows), tiles = 16-channel output tiles
+ * per block (1-4, capped at the layer's).  0 leaves the choice to the library, which picks
  * from the grid size (the default).  Results do not depend on the shape: a
  * pixel's sums run in the same order under every shape.  Not synchronised
  * with calls in flight on other host threads.  BGS_ERR_INVALID_ARG for

@@ -781,10 +781,13 @@ void launch_conv(hipStream_t s, int B, const ConvArgs& a) {
                        conv_lds_bytes(CPAD, R), s, a);
 }
 
-// mt <= 2 when R is 8 (more tiles would not fit in registers).
+// mt <= 2 for the tall shapes (more tiles would not fit in registers).
+template <int CPAD>
+constexpr bool tall_rows(int r) { return r == 8 || (CPAD > 64 && r == 4); }
+
 template <int CPAD, int R>
 void launch_conv(hipStream_t s, int B, int mt, const ConvArgs& a) {
-    if constexpr (R == 8) {
+    if constexpr (tall_rows<CPAD>(R)) {
         if (mt == 1)
             launch_conv<CPAD, 1, R>(s, B, a);
         else
@@ -804,11 +807,9 @@ void launch_conv(hipStream_t s, int B, int mt, const ConvArgs& a) {
 // else two; then fewer output tiles per block until there are at least two
 // blocks per CU, since the coarse levels have few pixels (at 200x150, two
 // tiles over 600 blocks beat one tile over 1200: 11.6 against 16.7 us for
-// the 64-channel layer).  Four rows of 96
-// staged channels would take 85 KB of LDS; that width keeps two rows.
-// bgs_repair_set_block_shape may fix either choice (0: automatic), and may
-// ask for eight rows, which inputs of up to 32 channels take with up to two
-// output tiles.
+// the 64-channel layer).  bgs_repair_set_block_shape may fix either choice
+// (0: automatic), and may ask for eight rows (inputs of up to 64 channels)
+// or four rows of 96 channels, which take at most two output tiles.
 std::atomic<int> g_rows{0}, g_tiles{0};
 
 template <int CPAD>
@@ -819,15 +820,19 @@ void launch_conv(hipStream_t s, int B, const ConvArgs& a) {
     };
     const int fr = g_rows.load(), ft = g_tiles.load();
     int mt = std::min(4, tiles);
-    // Largest row count this width's LDS allows: 8 rows up to 32 staged
-    // channels, 4 up to 64, else 2.
-    constexpr int kMaxRows = CPAD <= 32 ? 8 : CPAD <= 64 ? 4 : 2;
-    int r = std::min(kMaxRows, fr ? fr : nblk(4, mt) >= 6 * 256 ? 4 : 2);
+    // Largest row count offered for this width (a workgroup may take up to
+    // 160 KB of LDS): 8 rows up to 64 staged channels (95 KB at 64), 4 rows
+    // of 96 (85 KB).
+    constexpr int kMaxRows = CPAD <= 64 ? 8 : 4;
+    // Automatic: 96 staged channels keep two rows (four take 85 KB of LDS,
+    // one block per CU, and measured slower: 211 against 194 us at
+    // 1032x1104); taller blocks than four rows measured no better.
+    int r = std::min(kMaxRows, fr ? fr : (CPAD <= 64 && nblk(4, mt) >= 6 * 256) ? 4 : 2);
     if (ft)
         mt = std::min(ft, tiles);
     else
         while (mt > 1 && nblk(r, mt) < 2 * 256) mt = (mt + 1) / 2;
-    if (r == 8 && mt > 2) r = 4;
+    if (mt > 2 && tall_rows<CPAD>(r)) r = r == 8 && CPAD <= 64 ? 4 : 2;
     if (r == 8)
         launch_conv<CPAD, (kMaxRows >= 8 ? 8 : 2)>(s, B, mt, a);
     else if (r == 4)
