@@ -95,23 +95,29 @@ struct ConvArgs {
 // The block first stages input rows R blockIdx.y - 1 .. + R, x from
 // blockIdx.x * 64 - 1 to + 64 (zero outside the image), of every input
 // channel (padded to CPAD, a multiple of 16, with zeros) in LDS:
-// [R + 2][66][CPAD + 8] bf16, one 16-byte load and store per 8 channels of
-// a pixel.  The reduction index is k = tap * CPAD + ci in 32-deep slices of
-// v_mfma_f32_16x16x32_bf16; a lane's eight operands of a slice are eight
-// consecutive channels of one tap, one 16-byte LDS read, and each weight
-// operand serves all R rows and all of a wave's column tiles.  The 8 spare channel slots per pixel make the
-// pixel stride an odd multiple of 16 bytes, so the 16 lanes reading one
-// channel group of 16 consecutive pixels touch distinct banks.
+// [R + 2][66][CPAD + conv_pad(CPAD)] bf16, one 16-byte load and store per
+// 8 channels of a pixel.  The reduction index is k = tap * CPAD + ci in
+// 32-deep slices of v_mfma_f32_16x16x32_bf16; a lane's eight operands of a
+// slice are eight consecutive channels of one tap, one 16-byte LDS read,
+// and each weight operand serves all R rows and all of a wave's column
+// tiles.
 constexpr int kConvCols = 66;
 
 constexpr int pad32(int v) { return (v + 31) & ~31; }
+// Spare channel slots per staged pixel, by width, chosen by measurement
+// over 0 to 32 spare slots (LDS bank-conflict counter and kernel time): the
+// 16-byte operand reads of 48 and 96 channels are cheapest with none (and
+// the smaller stage fits more blocks per CU: 96 channels at 800x600, 29 ->
+// 23 us), those of 32 and 64 channels with 16, and 16 channels run
+// fastest with 8.
+constexpr int conv_pad(int cpad) { return cpad == 16 ? 8 : cpad == 32 || cpad == 64 ? 16 : 0; }
 constexpr size_t conv_lds_bytes(int cpad, int rows) {
-    return (size_t)(rows + 2) * kConvCols * (cpad + 8) * sizeof(uint16_t);
+    return (size_t)(rows + 2) * kConvCols * (cpad + conv_pad(cpad)) * sizeof(uint16_t);
 }
 
 template <int CPAD, int MT, int R>
 __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
-    constexpr int PS = CPAD + 8;              // staged bf16 per pixel
+    constexpr int PS = CPAD + conv_pad(CPAD);  // staged bf16 per pixel
     constexpr int G = CPAD / 8;               // 16-byte channel groups per pixel
     constexpr int SL = pad32(9 * CPAD) / 32;  // reduction slices
     extern __shared__ uint4 s_raw[];
